@@ -1,0 +1,224 @@
+"""ORACLE -- TEST INFRASTRUCTURE ONLY.
+
+Python side of the plain FP64 reference for the nonconforming multiple-traces
+boundary element method (van 't Wout, "The Boundary Element Method for
+Acoustic Transmission with Nonconforming Grids").  Only the tests, the smoke
+check and the CPU-baseline leg of the benchmark import this module; the
+product library never does.  It shares no code with the GPU path.
+
+Element integrals and the mortar matrix come from ``bem_oracle.c`` (plain C,
+ordered-pair loops).  Everything else is written here with numpy/scipy
+primitives and no blocking or reordering:
+
+  mass(xyz, tri)          M[i][j] = <phi_i, phi_j>  (Sec. 3.1)
+  plane_wave_rhs(...)     f_j = <u_inc, phi_j>, g_j = <d_n u_inc, phi_j>
+                          with u_inc = exp(i k d.x)  (plane wave, Sec. 5.3)
+  mtf_system(...)         the discrete multiple-traces system as printed in
+                          Sec. 3.3, with right-hand side [-f, -g, 0, 0]
+  solve_mtf(...)          x = A^{-1} b by dense LU: GMRES on the mass-
+                          preconditioned (strong) form M^{-1} A x = M^{-1} b
+                          reaches exactly this solution (Sec. 3.3, 5.1)
+  projection_error(...)   E_int, E_ext of Sec. 5.2
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bem_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the C part of the oracle (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-D_DEFAULT_SOURCE", "-o", _LIB + ".tmp", _SRC, "-lm"])
+        os.replace(_LIB + ".tmp", _LIB)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        p, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        L.orc_assemble_rows.argtypes = [i64, p, i64, p, d, d, i32, i32, i64, p, p, p, p, p]
+        L.orc_assemble_rows.restype = i32
+        L.orc_mortar_rows.argtypes = [i64, p, i64, p, i64, p, i64, p, i32, p, i64, p, p]
+        L.orc_mortar_rows.restype = i32
+        L.orc_plane_wave_rhs.argtypes = [i64, p, i64, p, d, d, p, p, p]
+        L.orc_plane_wave_rhs.restype = i32
+        L.orc_pair_blocks.argtypes = [p, p, i64, i64, d, d, i32, p]
+        L.orc_rule6.argtypes = [p, p]
+        L.orc_gauss01.argtypes = [i32, p, p]
+        L.orc_ss_poly.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.orc_ss_poly.restype = d
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _mesh(xyz, tri):
+    return (np.ascontiguousarray(xyz, dtype=np.float64),
+            np.ascontiguousarray(tri, dtype=np.int32))
+
+
+def rule6():
+    b = np.zeros((6, 3)); w = np.zeros(6)
+    lib().orc_rule6(_ptr(b), _ptr(w))
+    return b, w
+
+
+def gauss01(n):
+    x = np.zeros(n); w = np.zeros(n)
+    lib().orc_gauss01(n, _ptr(x), _ptr(w))
+    return x, w
+
+
+def ss_poly(kind, ng, a, b, c, d):
+    """Integral of x1^a x2^b y1^c y2^d over {0<=x2<=x1<=1}^2 via the singular
+    rule's regions; kind = number of shared vertices."""
+    return lib().orc_ss_poly(int(kind), int(ng), a, b, c, d)
+
+
+def pair_blocks(xyz, tri, t, s, k, ng=4):
+    """Element blocks [op][a][b] (op = V, K, T, D) of the ordered pair (t, s)."""
+    xyz, tri = _mesh(xyz, tri)
+    out = np.zeros((4, 3, 3), dtype=np.complex128)
+    lib().orc_pair_blocks(_ptr(xyz), _ptr(tri), int(t), int(s), float(np.real(k)),
+                          float(np.imag(k)), int(ng), _ptr(out))
+    return out
+
+
+def assemble(xyz, tri, k, ng=4, which=3, rows=None, ops="VKTD"):
+    """Dense Galerkin matrices V, K, T, D (rows = test vertices).  Returns a
+    dict op -> complex128 [len(rows), nv].  which: 1 regular pairs only,
+    2 singular pairs only, 3 all."""
+    xyz, tri = _mesh(xyz, tri)
+    nv = xyz.shape[0]
+    rows = np.arange(nv, dtype=np.int64) if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    out = {o: np.zeros((rows.size, nv), dtype=np.complex128) for o in ops}
+    ptrs = [(_ptr(out[o]) if o in out else None) for o in "VKTD"]
+    rc = lib().orc_assemble_rows(nv, _ptr(xyz), tri.shape[0], _ptr(tri), float(np.real(k)),
+                                 float(np.imag(k)), int(ng), int(which), rows.size, _ptr(rows), *ptrs)
+    if rc != 0:
+        raise ValueError("orc_assemble_rows failed")
+    return out
+
+
+def mortar(int_mesh, ext_mesh, mode=0, centre=(0.0, 0.0, 0.0), rows=None):
+    """Dense mortar matrix P_int,ext [N_int, N_ext] (or selected rows)."""
+    xi, ti = _mesh(*int_mesh)
+    xe, te = _mesh(*ext_mesh)
+    rows = (np.arange(xi.shape[0], dtype=np.int64) if rows is None
+            else np.ascontiguousarray(rows, dtype=np.int64))
+    P = np.zeros((rows.size, xe.shape[0]))
+    c = np.ascontiguousarray(centre, dtype=np.float64)
+    rc = lib().orc_mortar_rows(xi.shape[0], _ptr(xi), ti.shape[0], _ptr(ti), xe.shape[0], _ptr(xe),
+                               te.shape[0], _ptr(te), int(mode), _ptr(c), rows.size, _ptr(rows), _ptr(P))
+    if rc != 0:
+        raise ValueError("orc_mortar_rows failed")
+    return P
+
+
+def mass(xyz, tri):
+    """Dense P1 mass matrix: element matrix (A/12) [[2,1,1],[1,2,1],[1,1,2]]."""
+    xyz, tri = _mesh(xyz, tri)
+    nv = xyz.shape[0]
+    M = np.zeros((nv, nv))
+    p0, p1, p2 = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(p1 - p0, p2 - p0), axis=1)
+    for t in range(tri.shape[0]):
+        for a in range(3):
+            for b in range(3):
+                M[tri[t, a], tri[t, b]] += area[t] / 12.0 * (2.0 if a == b else 1.0)
+    return M
+
+
+def plane_wave_rhs(xyz, tri, k, d):
+    xyz, tri = _mesh(xyz, tri)
+    d = np.ascontiguousarray(d, dtype=np.float64)
+    f = np.zeros(xyz.shape[0], dtype=np.complex128)
+    g = np.zeros(xyz.shape[0], dtype=np.complex128)
+    lib().orc_plane_wave_rhs(xyz.shape[0], _ptr(xyz), tri.shape[0], _ptr(tri), float(np.real(k)),
+                             float(np.imag(k)), _ptr(d), _ptr(f), _ptr(g))
+    return f, g
+
+
+def operators(ext_mesh, int_mesh, k_ext, k_int, ng=4):
+    """All dense operators and sparse couplings of the multiple-traces system."""
+    Oe = assemble(*ext_mesh, k_ext, ng=ng)
+    Oi = assemble(*int_mesh, k_int, ng=ng)
+    P_ie = mortar(int_mesh, ext_mesh)
+    return dict(ext=Oe, int=Oi, P_ie=P_ie, M_e=mass(*ext_mesh), M_i=mass(*int_mesh))
+
+
+def mtf_system(ops, rho_ext, rho_int):
+    """The weak-form multiple-traces block matrix, signs as printed:
+        [ -K_e   V_e    1/2 P_ei              0                 ]
+        [  D_e   T_e    0                    1/2 (re/ri) P_ei   ]
+        [ -1/2 P_ie     0      -K_i          V_i                ]
+        [  0  -1/2 (ri/re) P_ie  D_i         T_i                ]
+    with P_ei = P_ie^T; unknowns [v_ext, w_ext, v_int, w_int]."""
+    Oe, Oi, P_ie = ops["ext"], ops["int"], ops["P_ie"]
+    ne, ni = Oe["V"].shape[0], Oi["V"].shape[0]
+    P_ei = P_ie.T
+    Z = np.zeros
+    A = np.block([
+        [-Oe["K"], Oe["V"], 0.5 * P_ei, Z((ne, ni))],
+        [Oe["D"], Oe["T"], Z((ne, ni)), 0.5 * (rho_ext / rho_int) * P_ei],
+        [-0.5 * P_ie, Z((ni, ne)), -Oi["K"], Oi["V"]],
+        [Z((ni, ne)), -0.5 * (rho_int / rho_ext) * P_ie, Oi["D"], Oi["T"]],
+    ])
+    return A
+
+
+def mtf_rhs(ext_mesh, k_ext, d, n_int):
+    f, g = plane_wave_rhs(*ext_mesh, k_ext, d)
+    return np.concatenate([-f, -g, np.zeros(2 * n_int, dtype=np.complex128)])
+
+
+def block_mass(ops):
+    Me, Mi = ops["M_e"], ops["M_i"]
+    ne, ni = Me.shape[0], Mi.shape[0]
+    M = np.zeros((2 * ne + 2 * ni,) * 2)
+    M[:ne, :ne] = Me
+    M[ne:2 * ne, ne:2 * ne] = Me
+    M[2 * ne:2 * ne + ni, 2 * ne:2 * ne + ni] = Mi
+    M[2 * ne + ni:, 2 * ne + ni:] = Mi
+    return M
+
+
+def strong_matvec(A, M, x):
+    """z = M^{-1} A x (mass-matrix preconditioned form, Sec. 3.3)."""
+    return np.linalg.solve(M, A @ x)
+
+
+def solve_mtf(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4, ops=None):
+    """Exact discrete MTF solution(s) by dense LU; returns (x [nrhs, n], ops)."""
+    if ops is None:
+        ops = operators(ext_mesh, int_mesh, k_ext, k_int, ng=ng)
+    A = mtf_system(ops, rho_ext, rho_int)
+    ni = ops["M_i"].shape[0]
+    B = np.stack([mtf_rhs(ext_mesh, k_ext, d, ni) for d in np.atleast_2d(dirs)], axis=1)
+    X = np.linalg.solve(A, B)
+    return X.T, ops
+
+
+def projection_error(M_i, M_e, P_ie, norm="fro"):
+    """E_int = ||I - M_i^-1 P_ie M_e^-1 P_ei||, E_ext = ||I - M_e^-1 P_ei M_i^-1 P_ie||."""
+    P_ei = P_ie.T
+    Ei = np.eye(M_i.shape[0]) - np.linalg.solve(M_i, P_ie @ np.linalg.solve(M_e, P_ei))
+    Ee = np.eye(M_e.shape[0]) - np.linalg.solve(M_e, P_ei @ np.linalg.solve(M_i, P_ie))
+    o = "fro" if norm == "fro" else np.inf
+    if norm == "max":
+        return np.abs(Ei).max(), np.abs(Ee).max()
+    return np.linalg.norm(Ei, o), np.linalg.norm(Ee, o)

@@ -1,0 +1,8 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the
+benchmark: triangle meshes of closed star-shaped surfaces, plane-wave
+directions and request streams.  This package holds no boundary-element
+arithmetic: it only produces geometry and parameters."""
+from .meshes import (icosphere, fibonacci_sphere, random_rotation, jitter_on_sphere,
+                     scale_to_ellipsoid, mesh_check, mean_edge_length, orient_outward,
+                     planar_square)
+from .configs import CONFIGS, make_config, plane_wave_directions

@@ -1,0 +1,365 @@
+"""Pins of the oracle against what the mathematics fixes, independently of the
+oracle's own code: exact quadrature on polynomials, brute-force element
+integrals, closed-form unit-sphere eigenvalues, Calderon identities, the
+divergence theorem, mass/mortar sums, and the Mie series for the full solve."""
+import math
+
+import numpy as np
+import pytest
+
+import brute
+import synth
+from mie import mie_traces
+from scipy.special import spherical_jn, spherical_yn
+
+
+def _h(n, x, d=False):
+    return spherical_jn(n, x, d) + 1j * spherical_yn(n, x, d)
+
+
+# ------------------------------------------------------------- quadrature
+
+def test_rule6_exact_to_degree_4(orc):
+    b, w = orc.rule6()
+    assert abs(w.sum() - 1) < 1e-15
+    # int over the unit reference triangle of s^a t^b = a! b! / (a+b+2)!, area 1/2
+    for a in range(5):
+        for c in range(5 - a):
+            q = 0.5 * np.sum(w * b[:, 1] ** a * b[:, 2] ** c)
+            ex = math.factorial(a) * math.factorial(c) / math.factorial(a + c + 2)
+            assert abs(q - ex) < 1e-15, (a, c)
+    q5 = 0.5 * np.sum(w * b[:, 1] ** 5)
+    assert abs(q5 - math.factorial(5) / math.factorial(7)) > 1e-6   # degree 4, not 5
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16])
+def test_gauss_legendre_exact(orc, n):
+    x, w = orc.gauss01(n)
+    for p in range(2 * n):
+        assert abs(np.sum(w * x ** p) - 1.0 / (p + 1)) < 2e-15
+    if n <= 4:   # degree 2n is no longer exact
+        assert abs(np.sum(w * x ** (2 * n)) - 1.0 / (2 * n + 1)) > 1e-12
+
+
+def _ex_tri(a, b):
+    # int over {0<=x2<=x1<=1} of x1^a x2^b = 1/((b+1)(a+b+2))
+    return 1.0 / ((b + 1) * (a + b + 2))
+
+
+@pytest.mark.parametrize("kind", [1, 2, 3])
+def test_singular_regions_tile_pair_domain(orc, kind):
+    """The regularising maps of each singular case cover the reference pair
+    domain exactly once with the right Jacobians: polynomials integrate exactly."""
+    for a, b, c, d in [(0, 0, 0, 0), (1, 0, 0, 0), (0, 1, 0, 0), (0, 0, 1, 0), (0, 0, 0, 1),
+                       (2, 1, 0, 1), (1, 1, 1, 1), (0, 2, 3, 0), (3, 0, 0, 2)]:
+        q = orc.ss_poly(kind, 8, a, b, c, d)
+        assert abs(q - _ex_tri(a, b) * _ex_tri(c, d)) < 1e-14, (kind, a, b, c, d)
+
+
+# ------------------------------------------------------- element integrals
+
+_X = np.array([[0, 0, 0], [1, 0, 0.0], [0.2, 0.9, 0.1], [0.9, 0.8, 0.5], [-0.8, -0.3, 0.4],
+               [1.5, -0.5, 0.3], [2.0, 0.3, -0.2], [5, 4, 3], [6, 4.2, 3], [5.3, 5, 3.4]])
+_T = np.array([[0, 1, 2], [1, 3, 2], [0, 2, 4], [1, 5, 6], [7, 8, 9]], dtype=np.int32)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("t,s,kind,order", [(0, 0, "coinc", [0, 1, 2]), (0, 1, "edge", [1, 2, 0]),
+                                            (1, 0, "edge", [1, 2, 3]), (0, 3, "vertex", [1, 2, 0])])
+def test_singular_blocks_vs_brute_force(orc, t, s, kind, order):
+    k = 2.0
+    Ps = _X[_T[s]]
+    perm = [list(_T[t]).index(v) for v in order]
+    Vb, Kb = brute.element_blocks(_X[order], Ps, k, kind, n=32, nth=32, nr=32)
+    V = np.zeros_like(Vb); K = np.zeros_like(Kb)
+    V[perm] = Vb; K[perm] = Kb
+    hi = orc.pair_blocks(_X, _T, t, s, k, ng=16)
+    lo = orc.pair_blocks(_X, _T, t, s, k, ng=4)
+    assert _rel(hi[0], V) < 1e-7
+    assert _rel(lo[0], V) < 3e-3
+    if kind == "coinc":
+        # flat panel: (x - y).n = 0 exactly, so K and T vanish
+        assert np.abs(hi[1]).max() < 1e-14 * np.abs(hi[0]).max()
+        assert np.abs(hi[2]).max() < 1e-14 * np.abs(hi[0]).max()
+    else:
+        assert _rel(hi[1], K) < 1e-5
+        assert _rel(lo[1], K) < 3e-3
+
+
+def test_regular_blocks_vs_finite_difference_kernels(orc):
+    """K and T of a separated pair against the same 6-point sums built from
+    central differences of G along n_y and n_x (no analytic derivative)."""
+    k = 3.0
+    t, s = 0, 4
+    blk = orc.pair_blocks(_X, _T, t, s, k)
+    b, w = orc.rule6()
+    Pt, Ps = _X[_T[t]], _X[_T[s]]
+    def geo(P):
+        n = np.cross(P[1] - P[0], P[2] - P[0]); A = 0.5 * np.linalg.norm(n)
+        return n / (2 * A), A
+    nt, At = geo(Pt); ns, As = geo(Ps)
+    G = lambda x, y: np.exp(1j * k * np.linalg.norm(x - y)) / (4 * np.pi * np.linalg.norm(x - y))
+    eps = 1e-5
+    V = np.zeros((3, 3), complex); K = np.zeros_like(V); T = np.zeros_like(V)
+    for p in range(6):
+        x = b[p] @ Pt
+        for q in range(6):
+            y = b[q] @ Ps
+            wt = w[p] * w[q] * At * As
+            g = G(x, y)
+            gk = (G(x, y + eps * ns) - G(x, y - eps * ns)) / (2 * eps)
+            gt = (G(x + eps * nt, y) - G(x - eps * nt, y)) / (2 * eps)
+            V += wt * g * np.outer(b[p], b[q])
+            K += wt * gk * np.outer(b[p], b[q])
+            T += wt * gt * np.outer(b[p], b[q])
+    assert _rel(blk[0], V) < 1e-14
+    assert _rel(blk[1], K) < 1e-8
+    assert _rel(blk[2], T) < 1e-8
+    # separated pair: the order-4 rule approaches the exact integral (brute
+    # force) with an error that shrinks like k^4 when the phase is resolved
+    Vb, Kb = brute.element_blocks(Pt, Ps, k, "regular", n=12, nth=16, nr=16)
+    assert _rel(blk[0], Vb) < 5e-3 and _rel(blk[1], Kb) < 5e-3
+    kl = 0.3
+    lo = orc.pair_blocks(_X, _T, t, s, kl)
+    Vb, Kb = brute.element_blocks(Pt, Ps, kl, "regular", n=12, nth=16, nr=16)
+    assert _rel(lo[0], Vb) < 1e-6 and _rel(lo[1], Kb) < 1e-5
+
+
+def test_vertex_relabelling_permutes_blocks(orc):
+    """Cyclic relabelling of a triangle (same orientation) only permutes its
+    local block; at a high Gauss order the singular rules agree to 1e-8."""
+    k = 2.0
+    for t, s in [(0, 1), (0, 3), (0, 0), (0, 4)]:
+        ref = orc.pair_blocks(_X, _T, t, s, k, ng=14)
+        T2 = _T.copy()
+        T2[t] = np.roll(_T[t], 1)
+        if s != t:
+            T2[s] = np.roll(_T[s], 2)
+        got = orc.pair_blocks(_X, T2, t, s, k, ng=14)
+        rt = [list(T2[t]).index(v) for v in _T[t]]
+        rs = [list(T2[s]).index(v) for v in _T[s]]
+        for op in range(4):
+            a = got[op][np.ix_(rt, rs)]
+            if np.abs(ref[op]).max() > 1e-12:
+                assert _rel(a, ref[op]) < 1e-8, (t, s, op)
+
+
+# ------------------------------------------------------ global operators
+
+def _sphere_eigs(k, n):
+    jv, jp = spherical_jn(n, k), spherical_jn(n, k, True)
+    return dict(V=1j * k * jv * _h(n, k), K=0.5 + 1j * k * k * jv * _h(n, k, True),
+                T=0.5 + 1j * k * k * jv * _h(n, k, True), D=-1j * k ** 3 * jp * _h(n, k, True))
+
+
+def test_unit_sphere_eigenvalues_converge(orc):
+    """Spherical harmonics are eigenfunctions of V, K, T, D on the unit sphere;
+    the mass-inverted Galerkin matrices reproduce the eigenvalues at O(h^2)."""
+    k = 2.0
+    errs = {}
+    for L in (1, 2, 3):
+        xyz, tri = synth.icosphere(L)
+        ops = orc.assemble(xyz, tri, k)
+        M = orc.mass(xyz, tri)
+        for n, f in ((0, np.ones(len(xyz))), (1, xyz[:, 2].copy())):
+            lam = _sphere_eigs(k, n)
+            for op in "VKTD":
+                z = np.linalg.solve(M, ops[op] @ f)
+                errs[(L, op, n)] = np.linalg.norm(z - lam[op] * f) / np.linalg.norm(lam[op] * f)
+    for op in "VKTD":
+        for n in (0, 1):
+            e1, e2, e3 = errs[(1, op, n)], errs[(2, op, n)], errs[(3, op, n)]
+            assert e2 < e1 / 3.2 and e3 < e2 / 3.2, (op, n, e1, e2, e3)
+            assert e3 < (0.1 if (op, n) == ("D", 1) else 1e-2), (op, n, e3)
+
+
+def test_symmetries(orc):
+    xyz, tri = synth.icosphere(2)
+    k = 2.5
+    reg = orc.assemble(xyz, tri, k, which=1)
+    for a, b in (("V", "V"), ("D", "D"), ("K", "T")):
+        assert _rel(reg[a].T, reg[b]) < 1e-13
+    full = orc.assemble(xyz, tri, k, ng=12)
+    for a, b in (("V", "V"), ("D", "D"), ("K", "T")):
+        assert _rel(full[a].T, full[b]) < 1e-7
+
+
+def test_calderon_projectors(orc):
+    """Interior plane wave: (1/2 M - A) [phi; psi] -> 0; exterior point source
+    at the origin: (1/2 M + A) [phi; psi] -> 0, A = [[-K, V], [D, T]]."""
+    k = 2.0
+    d = np.array([0.3, -0.5, 0.81]); d /= np.linalg.norm(d)
+    res = []
+    for L in (2, 3):
+        xyz, tri = synth.icosphere(L)
+        xyz = synth.scale_to_ellipsoid(xyz, (1.0, 0.8, 0.6))
+        o = orc.assemble(xyz, tri, k)
+        M = orc.mass(xyz, tri)
+        nrm = np.zeros_like(xyz)
+        p0, p1, p2 = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+        fn = np.cross(p1 - p0, p2 - p0)
+        for a in range(3):
+            np.add.at(nrm, tri[:, a], fn)
+        nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+        u = np.exp(1j * k * xyz @ d); du = 1j * k * (nrm @ d) * u
+        r = np.linalg.norm(xyz, axis=1)
+        G = np.exp(1j * k * r) / (4 * np.pi * r)
+        dG = G * (1j * k * r - 1) / r * np.einsum("ij,ij->i", xyz / r[:, None], nrm)
+        r1 = 0.5 * M @ u + o["K"] @ u - o["V"] @ du
+        r2 = 0.5 * M @ du - o["D"] @ u - o["T"] @ du
+        e1 = 0.5 * M @ G - o["K"] @ G + o["V"] @ dG
+        e2 = 0.5 * M @ dG + o["D"] @ G + o["T"] @ dG
+        res.append([np.linalg.norm(r1) / np.linalg.norm(M @ u), np.linalg.norm(r2) / np.linalg.norm(M @ du),
+                    np.linalg.norm(e1) / np.linalg.norm(M @ G), np.linalg.norm(e2) / np.linalg.norm(M @ dG)])
+    res = np.array(res)
+    assert np.all(res[1] < res[0] / 2.5), res
+    assert np.all(res[1] < 0.05), res
+
+
+def test_plane_wave_loads_divergence_theorem(orc):
+    """sum_j f_j = int_Gamma u_inc and sum_j g_j = int_Gamma d_n u_inc
+    = -k^2 int_Omega u_inc; on the unit sphere these tend to
+    4 pi sin(k)/k and -4 pi (sin k - k cos k)/k."""
+    k = 3.0
+    d = np.array([0, 0.6, 0.8])
+    e = []
+    for L in (2, 3, 4):
+        xyz, tri = synth.icosphere(L)
+        f, g = orc.plane_wave_rhs(xyz, tri, k, d)
+        e.append((abs(f.sum() - 4 * np.pi * np.sin(k) / k) / (4 * np.pi),
+                  abs(g.sum() + 4 * np.pi * (np.sin(k) - k * np.cos(k)) / k) / (4 * np.pi)))
+    e = np.array(e)
+    assert np.all(e[1:] < e[:-1] / 3.0), e
+
+
+# ------------------------------------------------------------ mass, mortar
+
+def test_mass_sums(orc):
+    xyz, tri = synth.icosphere(2)
+    M = orc.mass(xyz, tri)
+    p0, p1, p2 = xyz[tri[:, 0]], xyz[tri[:, 1]], xyz[tri[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(p1 - p0, p2 - p0), axis=1)
+    assert abs(M.sum() - area.sum()) < 1e-13
+    star = np.zeros(len(xyz))
+    for a in range(3):
+        np.add.at(star, tri[:, a], area)
+    assert np.abs(M.sum(1) - star / 3).max() < 1e-15
+    assert np.linalg.eigvalsh(M).min() > 0
+
+
+def test_mortar_identical_meshes_is_mass(orc):
+    xyz, tri = synth.icosphere(2)
+    P = orc.mortar((xyz, tri), (xyz, tri))
+    M = orc.mass(xyz, tri)
+    assert np.abs(P - M).max() < 1e-14 * np.abs(M).max()
+    xs, ts = synth.planar_square(6)
+    P = orc.mortar((xs, ts), (xs, ts), mode=1)
+    assert np.abs(P - orc.mass(xs, ts)).max() < 1e-15
+
+
+def test_mortar_sums_nonconforming(orc):
+    c = synth.make_config("C1")
+    P = orc.mortar(c["int"], c["ext"])
+    Me, Mi = orc.mass(*c["ext"]), orc.mass(*c["int"])
+    # interior functions sum to one on every exterior facet: column sums are exact
+    assert np.abs(P.sum(0) - Me.sum(1)).max() < 1e-15
+    assert abs(P.sum() - Me.sum()) < 1e-13
+    # row sums approach the interior lumped mass (radial area distortion O(h^2))
+    assert np.abs(P.sum(1) - Mi.sum(1)).max() < 0.01 * Mi.sum(1).max()
+
+
+def test_mortar_planar_against_sampling(orc):
+    """Unit square, two different triangulations: P against a fine midpoint
+    sampling of theta_i * phi_j (point location by brute force)."""
+    rng = np.random.default_rng(0)
+    xi, ti = synth.planar_square(3)
+    xe, te = synth.planar_square(4, sigma=0.06, rng=rng)
+    P = orc.mortar((xi, ti), (xe, te), mode=1)
+    m = 400
+    g = (np.arange(m) + 0.5) / m
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], 1)
+
+    def hat(xyz, tri):
+        H = np.zeros((pts.shape[0], xyz.shape[0]))
+        for t in tri:
+            A, B, C = xyz[t, :2]
+            det = (B[0] - A[0]) * (C[1] - A[1]) - (B[1] - A[1]) * (C[0] - A[0])
+            l1 = ((pts[:, 0] - A[0]) * (C[1] - A[1]) - (pts[:, 1] - A[1]) * (C[0] - A[0])) / det
+            l2 = ((B[0] - A[0]) * (pts[:, 1] - A[1]) - (B[1] - A[1]) * (pts[:, 0] - A[0])) / det
+            l0 = 1 - l1 - l2
+            inside = (l0 >= -1e-12) & (l1 >= -1e-12) & (l2 >= -1e-12)
+            free = inside & (H.sum(1) == 0)
+            for v, l in zip(t, (l0, l1, l2)):
+                H[free, v] = l[free]
+        return H
+    Hi, He = hat(xi, ti), hat(xe, te)
+    Ps = Hi.T @ He / m ** 2
+    assert np.abs(P - Ps).max() < 2e-5 * np.abs(P).max() * 100
+    assert abs(P.sum() - 1.0) < 1e-14
+
+
+def test_projection_error_vanishes_with_perturbation(orc):
+    """E_int, E_ext -> 0 as the node perturbation sigma -> 0 (unit square)."""
+    xi, ti = synth.planar_square(8)
+    Mi = orc.mass(xi, ti)
+    prev = None
+    for sigma in (1e-2, 1e-4, 1e-6):
+        xe, te = synth.planar_square(8, sigma=sigma, rng=np.random.default_rng(3))
+        P = orc.mortar((xi, ti), (xe, te), mode=1)
+        ei, ee = orc.projection_error(Mi, orc.mass(xe, te), P)
+        if prev is not None:
+            assert ei < prev[0] / 20 and ee < prev[1] / 20
+        prev = (ei, ee)
+    assert prev[0] < 1e-4 and prev[1] < 1e-4
+
+
+def test_projection_error_under_exterior_refinement(orc):
+    """Fixed coarse interior grid, refined exterior grid: E_int falls and E_ext rises."""
+    xi, ti = synth.planar_square(2)
+    Mi = orc.mass(xi, ti)
+    out = []
+    for m in (2, 4, 8):
+        xe, te = synth.planar_square(m, sigma=0.02 / m, rng=np.random.default_rng(m))
+        P = orc.mortar((xi, ti), (xe, te), mode=1)
+        out.append(orc.projection_error(Mi, orc.mass(xe, te), P))
+    out = np.array(out)
+    assert out[2, 0] < out[1, 0] < out[0, 0] + 1e-12 or out[2, 0] < out[0, 0]
+    assert out[2, 1] > out[1, 1] > out[0, 1]
+
+
+# ------------------------------------------------------------- full solve
+
+def test_mie_convergence(orc):
+    """Exact discrete MTF solution vs the penetrable-sphere series: O(h^2) for
+    conforming and nonconforming grids.  Unknowns (printed system):
+    -v_ext = p, -w_ext = dp+/dn, -v_int = p, -w_int = dp-/dn."""
+    ke, ki, re, ri = 2.0, 3.0, 1.0, 1.5
+    d = np.array([0.0, 0.0, 1.0])
+    errs = []
+    for L in (1, 2, 3):
+        (xe, te), (xi, ti), _ = synth.configs.make_pair(7, L, "ico", 0.01, (1, 1, 1), int_level=L)
+        X, _ = orc.solve_mtf((xe, te), (xi, ti), ke, ki, re, ri, d)
+        x = X[0]; ne, ni = len(xe), len(xi)
+        p, dpp, _ = mie_traces(xe, d, ke, ki, re, ri)
+        pi, _, dpmi = mie_traces(xi, d, ke, ki, re, ri)
+        e = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+        errs.append([e(-x[:ne], p), e(-x[ne:2 * ne], dpp), e(-x[2 * ne:2 * ne + ni], pi), e(-x[2 * ne + ni:], dpmi)])
+    errs = np.array(errs)
+    assert np.all(errs[1] < errs[0] / 3) and np.all(errs[2] < errs[1] / 3), errs
+    assert np.all(errs[2] < 0.015), errs
+
+
+def test_transparent_body(orc):
+    """k_int = k_ext, rho_int = rho_ext: the total field is the incident wave."""
+    k = 1.5
+    d = np.array([0.6, 0.0, 0.8])
+    (xe, te), (xi, ti), _ = synth.configs.make_pair(9, 2, "ico", 0.02, (1, 0.9, 0.8), int_level=2)
+    X, _ = orc.solve_mtf((xe, te), (xi, ti), k, k, 1.0, 1.0, d)
+    x = X[0]; ne, ni = len(xe), len(xi)
+    ue, ui = np.exp(1j * k * xe @ d), np.exp(1j * k * xi @ d)
+    assert np.linalg.norm(-x[:ne] - ue) / np.linalg.norm(ue) < 0.02
+    assert np.linalg.norm(-x[2 * ne:2 * ne + ni] - ui) / np.linalg.norm(ui) < 0.02
