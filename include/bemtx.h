@@ -1,0 +1,209 @@
+/*
+ * bemtx -- boundary element method for acoustic transmission on two
+ * nonconforming triangle meshes of one closed surface, on one AMD MI355X
+ * (gfx950).  C ABI.
+ *
+ * The problem (van 't Wout, "The Boundary Element Method for Acoustic
+ * Transmission with Nonconforming Grids", J. Comput. Appl. Math. 2024):
+ * a homogeneous body with surface Gamma in free space; time convention
+ * exp(-i omega t); wavenumbers k_ext, k_int; densities rho_ext, rho_int;
+ * Helmholtz equation with the transmission conditions of Sec. 2 (Eq.
+ * "helmholtz").  The interior operators live on the interior mesh, the
+ * exterior operators on the exterior mesh (Sec. 2.1, Sec. 3), and the two
+ * are coupled by the L2 mortar matrix P_int,ext and its transpose (Sec. 3.1).
+ *
+ * Discretisation: continuous P1 Lagrange test and trial functions on both
+ * meshes (Sec. 2.4); dense Galerkin matrices of the single-layer V,
+ * double-layer K, adjoint double-layer T and hypersingular D operators
+ * (Sec. 2.1) with an order-four (6-point) triangle rule on pairs that share
+ * no vertex and Sauter-Schwab regularising transformations on pairs that
+ * share one, two or three vertices (Sec. 5.1).  The multiple-traces system
+ * (Sec. 3.3, Eq. "mtf:discrete"), mass-matrix (strong-form) preconditioning
+ * (Sec. 3.3) and GMRES without restart (Sec. 5.1).
+ *
+ * Conventions common to all entry points
+ *  - Meshes: vertices `double[nv][3]`, triangles `int32_t[nt][3]`, 0-based,
+ *    counter-clockwise seen from outside.  The P1 degree of freedom j is
+ *    vertex j; every matrix and vector crossing this ABI uses the caller's
+ *    vertex numbering.  (The library renumbers internally for locality.)
+ *  - Complex numbers are interleaved (re, im) pairs of doubles: the layout of
+ *    C99 `double complex` and of torch.complex128.
+ *  - Matrices are row-major; row = test function, column = trial function.
+ *  - Memory spaces: BEM_HOST pointers are ordinary host memory; BEM_DEVICE
+ *    pointers are device memory of the context's device (e.g. the
+ *    data_ptr() of a torch tensor on that device).  The library never frees
+ *    caller memory and copies every input it keeps.
+ *  - Streams: all device work is issued on the context's stream.  Entry
+ *    points that write into caller buffers return after that work has
+ *    completed (they synchronise the stream), so the result may be read at
+ *    once from any stream.
+ *  - Errors: a negative bem_status; bem_last_error() gives a message for the
+ *    last failing call on the calling thread.  On error no output is
+ *    written and handles stay valid.
+ *  - Thread safety: one handle must not be used from two threads at once.
+ */
+#ifndef BEMTX_H
+#define BEMTX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bem_status;
+enum {
+    BEM_OK = 0,
+    BEM_W_NOCONV = 1,          /* warning: GMRES reached maxit; best iterate returned */
+    BEM_E_ARG = -1,            /* null pointer, size mismatch, non-positive k/rho/tol, ... */
+    BEM_E_MESH = -2,           /* not a closed, consistently oriented, outward 2-manifold,
+                                  degenerate triangle or unused vertex */
+    BEM_E_MESH_MISMATCH = -3,  /* the two meshes do not cover the same surface */
+    BEM_E_STATE = -4,          /* call order violated (e.g. solve before assembly) */
+    BEM_E_OOM = -5,            /* device allocation failed or over the context budget */
+    BEM_E_DEVICE = -6,         /* HIP runtime error (message carries the HIP error) */
+    BEM_E_UNSUPPORTED = -7     /* option not available in this build */
+};
+
+typedef enum { BEM_HOST = 0, BEM_DEVICE = 1 } bem_memspace;
+
+/* BEM_C128: complex128 operators, mat-vecs and Krylov vectors.
+ * BEM_C64_MIXED: complex64 operators and mat-vecs with FP32 accumulation;
+ * singular integrals, Arnoldi and iterative-refinement residuals in FP64. */
+typedef enum { BEM_C128 = 0, BEM_C64_MIXED = 1 } bem_precision;
+
+typedef struct {
+    int32_t singular_gauss;   /* Gauss-Legendre points per coordinate of the singular rule (1..16; 4) */
+} bem_quad_opts;
+
+typedef struct {
+    double tol;               /* relative residual of the strong form, ||M^-1(b - A x)|| / ||M^-1 b|| */
+    int32_t maxit;            /* Arnoldi steps (no restart, Sec. 5.1), 1..4000 */
+    int32_t ir_max;           /* BEM_C64_MIXED: outer refinement steps */
+    double ir_inner_tol;      /* BEM_C64_MIXED: inner GMRES tolerance */
+} bem_solver_opts;
+
+typedef struct {
+    int32_t iterations;       /* total Arnoldi steps over all right-hand sides */
+    int32_t ir_steps;
+    double rel_residual;      /* worst strong-form relative residual, recomputed in FP64 at exit */
+    double t_geometry_ms, t_regular_ms, t_singular_ms, t_projection_ms;
+    double t_matrix_ms;       /* operators + projection */
+    double t_solve_ms;
+    double t_iter_ms;         /* t_solve / iterations */
+} bem_stats;
+
+typedef struct bem_ctx bem_ctx;
+typedef struct bem_mesh bem_mesh;
+typedef struct bem_problem bem_problem;
+
+/* Message of the last failing call on this thread (never NULL). */
+const char *bem_last_error(void);
+
+/* Context on HIP device `device`, issuing work on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  hbm_budget_bytes caps the device memory the
+ * library allocates for problems of this context (0 = no cap).  Ownership:
+ * *out is owned by the caller and freed with bem_ctx_destroy after every
+ * problem and mesh of the context. */
+bem_status bem_ctx_create(int32_t device, void *hip_stream, size_t hbm_budget_bytes, bem_ctx **out);
+void bem_ctx_destroy(bem_ctx *ctx);
+/* Device bytes currently held by problems of the context. */
+size_t bem_ctx_bytes_in_use(const bem_ctx *ctx);
+
+/* A triangle mesh Gamma_int or Gamma_ext (Sec. 3): checks that it is a closed,
+ * consistently oriented 2-manifold with positive enclosed volume, no
+ * degenerate triangle and no unused vertex (BEM_E_MESH otherwise), and builds
+ * the connectivity tables (adjacent-pair classes, locality blocks).  xyz and
+ * tri are host arrays, copied. */
+bem_status bem_mesh_create(bem_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
+                           bem_mesh **out);
+void bem_mesh_destroy(bem_mesh *mesh);
+int64_t bem_mesh_num_vertices(const bem_mesh *mesh);
+
+/* Transmission problem (Sec. 2, Eq. "helmholtz") on an exterior and an
+ * interior mesh of the same star-shaped surface around the origin (the
+ * meshes are related by central projection from the origin), with real
+ * wavenumbers k_ext, k_int > 0 and densities rho_ext, rho_int > 0.
+ * quad may be NULL (defaults).  The meshes must outlive the problem. */
+bem_status bem_problem_create(bem_ctx *ctx, const bem_mesh *ext, const bem_mesh *inte,
+                              double k_ext, double k_int, double rho_ext, double rho_int,
+                              bem_precision precision, const bem_quad_opts *quad, bem_problem **out);
+void bem_problem_destroy(bem_problem *p);
+
+/* Device bytes the problem needs with `nrhs` right-hand sides and `maxit`
+ * Krylov steps (operators, projections, Krylov bases, scratch); for admission
+ * control.  May be called before assembly. */
+bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t maxit, size_t *bytes);
+
+/* Dense Galerkin matrices V, K, T, D on both meshes (Sec. 2.1, 2.4, 5.1),
+ * device-resident.  parts: bit 0 = contributions of triangle pairs that share
+ * no vertex, bit 1 = pairs that share a vertex (3 = the full operators; other
+ * values exist for testing). */
+bem_status bem_assemble_operators(bem_problem *p, int32_t parts);
+
+/* Mass matrices M_ext, M_int and the mortar matrix P_int,ext (N_int x N_ext)
+ * with P_ext,int = P_int,ext^T (Sec. 3.1), device-resident, plus the dense
+ * inverse mass matrices used by the strong form (Sec. 3.3).
+ * BEM_E_MESH_MISMATCH if the projected interior mesh leaves part of an
+ * exterior facet uncovered (relative area defect above 1e-6). */
+bem_status bem_assemble_projection(bem_problem *p);
+
+/* Apply the discrete multiple-traces matrix of Sec. 3.3 (Eq.
+ * "mtf:discrete") to x: y = A x (strong = 0) or y = blockdiag(M_e, M_e, M_i,
+ * M_i)^-1 A x (strong = 1).  x, y: complex128 [2 N_ext + 2 N_int] in the
+ * unknown order [v_ext, w_ext, v_int, w_int], caller numbering.  Needs both
+ * assemblies. */
+bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space);
+
+/* Right-hand side [-f, -g, 0, 0] of the multiple-traces system for the
+ * plane wave exp(i k_ext d.x) (Sec. 5.3, Eq. "planewave"):
+ * f_j = <u_inc, phi_j>, g_j = <du_inc/dn, phi_j> on the exterior mesh.
+ * dirs: host double[nrhs][3] unit vectors; b: complex128 [nrhs][n]. */
+bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b, bem_memspace space);
+
+/* Solve the multiple-traces system for nrhs plane waves with GMRES without
+ * restart on the mass-preconditioned form, x0 = 0 (Sec. 3.3, 5.1).
+ * traces: complex128 [nrhs][2 N_ext + 2 N_int], the unknowns
+ * [v_ext, w_ext, v_int, w_int] of the printed system; with its signs the
+ * total field satisfies p = -v_ext, dp/dn+ = -w_ext on Gamma_ext and
+ * p = -v_int, dp/dn- = -w_int on Gamma_int.  Returns BEM_W_NOCONV if a
+ * right-hand side did not reach opts->tol within opts->maxit (its best
+ * iterate is written).  stats may be NULL. */
+bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
+                     void *traces, bem_memspace space, bem_stats *stats);
+
+/* Copy one dense operator: mesh 0 = exterior, 1 = interior; op one of 'V',
+ * 'K', 'T', 'D'.  dst: complex128 [N][N] (BEM_C128 problems) in caller
+ * numbering. */
+bem_status bem_copy_operator(const bem_problem *p, int32_t mesh, char op, void *dst, bem_memspace space);
+
+/* Copy the mortar matrix P_int,ext as CSR in caller numbering (host arrays).
+ * With rowptr == NULL only *nnz is returned.  rowptr: int64[N_int + 1],
+ * col: int32[nnz], val: double[nnz]; columns sorted within each row. */
+bem_status bem_copy_projection(const bem_problem *p, int64_t *rowptr, int32_t *col, double *val, int64_t *nnz);
+
+/* ---- host-only entry points (no device needed) ----------------------- */
+
+/* The mesh checks of bem_mesh_create (closed, oriented outward, no
+ * degenerate triangle, no unused vertex) on host arrays. */
+bem_status bem_check_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt);
+
+/* The mortar matrix P_int,ext of bem_assemble_projection computed on host
+ * arrays (Sec. 3.1), in caller numbering, CSR with sorted columns.  With
+ * rowptr == NULL only *nnz is returned; otherwise rowptr: int64[nv_int + 1],
+ * col: int32[*nnz], val: double[*nnz] must hold the size from the first call.
+ * coverage_defect (nullable) receives the largest relative area defect of an
+ * exterior facet.  Meshes are validated as in bem_mesh_create. */
+bem_status bem_host_mortar(const double *xyz_int, int64_t nv_int, const int32_t *tri_int, int64_t nt_int,
+                           const double *xyz_ext, int64_t nv_ext, const int32_t *tri_ext, int64_t nt_ext,
+                           int64_t *rowptr, int32_t *col, double *val, int64_t *nnz, double *coverage_defect);
+
+/* n-point Gauss-Legendre rule on [0,1] used by the singular quadrature
+ * (1 <= n <= 16). */
+bem_status bem_host_gauss_legendre(int32_t n, double *x, double *w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

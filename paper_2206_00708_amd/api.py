@@ -1,0 +1,180 @@
+"""Python face of the bemtx C ABI: same names, argument marshalling only.
+Every step of the method runs in the HIP library; torch provides device
+buffers and the stream."""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+OK, W_NOCONV = 0, 1
+_ERR = {-1: "BEM_E_ARG", -2: "BEM_E_MESH", -3: "BEM_E_MESH_MISMATCH", -4: "BEM_E_STATE",
+        -5: "BEM_E_OOM", -6: "BEM_E_DEVICE", -7: "BEM_E_UNSUPPORTED"}
+HOST, DEVICE = 0, 1
+C128, C64_MIXED = 0, 1
+
+
+class BemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERR.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code < 0:
+        raise BemError(code, N.load().bem_last_error().decode())
+    return code
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """bem_ctx_create / bem_ctx_destroy on a torch device and stream."""
+
+    def __init__(self, device=0, stream=None, hbm_budget_bytes=0):
+        L = N.load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(L.bem_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream), hbm_budget_bytes, ctypes.byref(h)))
+        self._h = h
+
+    def bytes_in_use(self):
+        return N.load().bem_ctx_bytes_in_use(self._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.load().bem_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Mesh:
+    """bem_mesh_create: xyz float64 [nv,3], tri int32 [nt,3] (host arrays)."""
+
+    def __init__(self, ctx, xyz, tri):
+        L = N.load()
+        self.ctx = ctx
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(L.bem_mesh_create(ctx._h, self.xyz.ctypes.data, self.xyz.shape[0], self.tri.ctypes.data,
+                                 self.tri.shape[0], ctypes.byref(h)))
+        self._h = h
+        self.nv = self.xyz.shape[0]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.load().bem_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Problem:
+    """bem_problem_create and the calls on a transmission problem."""
+
+    def __init__(self, ctx, ext, inte, k_ext, k_int, rho_ext=1.0, rho_int=1.0, precision=C128, singular_gauss=4):
+        L = N.load()
+        self.ctx, self.ext, self.inte = ctx, ext, inte
+        q = N.QuadOpts(singular_gauss)
+        h = ctypes.c_void_p()
+        _check(L.bem_problem_create(ctx._h, ext._h, inte._h, k_ext, k_int, rho_ext, rho_int, precision,
+                                    ctypes.byref(q), ctypes.byref(h)))
+        self._h = h
+        self.n = 2 * ext.nv + 2 * inte.nv
+
+    def close(self):
+        if getattr(self, "_h", None):
+            N.load().bem_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def footprint(self, nrhs=1, maxit=500):
+        b = ctypes.c_size_t()
+        _check(N.load().bem_problem_footprint(self._h, nrhs, maxit, ctypes.byref(b)))
+        return b.value
+
+    def assemble_operators(self, parts=3):
+        _check(N.load().bem_assemble_operators(self._h, parts))
+
+    def assemble_projection(self):
+        _check(N.load().bem_assemble_projection(self._h))
+
+    def mtf_matvec(self, x, strong=True):
+        x = x.to(device=self.ctx.device, dtype=torch.complex128).contiguous()
+        y = torch.empty_like(x)
+        _check(N.load().bem_mtf_matvec(self._h, _ptr(x), _ptr(y), int(strong), DEVICE))
+        return y
+
+    def mtf_rhs(self, dirs):
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        b = torch.empty((d.shape[0], self.n), dtype=torch.complex128, device=self.ctx.device)
+        _check(N.load().bem_mtf_rhs(self._h, d.ctypes.data, d.shape[0], _ptr(b), DEVICE))
+        return b
+
+    def solve(self, dirs, tol=1e-6, maxit=1000):
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        out = torch.empty((d.shape[0], self.n), dtype=torch.complex128, device=self.ctx.device)
+        opts = N.SolverOpts(tol, maxit, 0, 0.0)
+        st = N.Stats()
+        code = _check(N.load().bem_solve(self._h, d.ctypes.data, d.shape[0], ctypes.byref(opts), _ptr(out), DEVICE,
+                                         ctypes.byref(st)))
+        return out, st.as_dict(), code
+
+    def operator(self, mesh, op):
+        nv = self.ext.nv if mesh == 0 else self.inte.nv
+        out = torch.empty((nv, nv), dtype=torch.complex128, device=self.ctx.device)
+        _check(N.load().bem_copy_operator(self._h, mesh, op.encode(), _ptr(out), DEVICE))
+        return out
+
+    def projection(self):
+        """P_int,ext as (rowptr int64, col int32, val float64) numpy arrays."""
+        L = N.load()
+        nnz = ctypes.c_int64()
+        _check(L.bem_copy_projection(self._h, None, None, None, ctypes.byref(nnz)))
+        rp = np.zeros(self.inte.nv + 1, dtype=np.int64)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value, dtype=np.float64)
+        _check(L.bem_copy_projection(self._h, rp.ctypes.data, col.ctypes.data, val.ctypes.data, ctypes.byref(nnz)))
+        return rp, col, val
+
+
+# ---------------------------------------------------------- host-only calls
+
+def check_mesh(xyz, tri):
+    """bem_check_mesh: raises BemError(BEM_E_MESH) for an invalid surface mesh."""
+    x = np.ascontiguousarray(xyz, dtype=np.float64)
+    t = np.ascontiguousarray(tri, dtype=np.int32)
+    _check(N.load().bem_check_mesh(x.ctypes.data, x.shape[0], t.ctypes.data, t.shape[0]))
+
+
+def host_mortar(int_mesh, ext_mesh):
+    """bem_host_mortar: P_int,ext as (rowptr, col, val, coverage_defect)."""
+    L = N.load()
+    xi = np.ascontiguousarray(int_mesh[0], dtype=np.float64); ti = np.ascontiguousarray(int_mesh[1], dtype=np.int32)
+    xe = np.ascontiguousarray(ext_mesh[0], dtype=np.float64); te = np.ascontiguousarray(ext_mesh[1], dtype=np.int32)
+    nnz = ctypes.c_int64(); dfc = ctypes.c_double()
+    args = (xi.ctypes.data, xi.shape[0], ti.ctypes.data, ti.shape[0], xe.ctypes.data, xe.shape[0], te.ctypes.data,
+            te.shape[0])
+    _check(L.bem_host_mortar(*args, None, None, None, ctypes.byref(nnz), ctypes.byref(dfc)))
+    rp = np.zeros(xi.shape[0] + 1, dtype=np.int64)
+    col = np.zeros(nnz.value, dtype=np.int32)
+    val = np.zeros(nnz.value, dtype=np.float64)
+    _check(L.bem_host_mortar(*args, rp.ctypes.data, col.ctypes.data, val.ctypes.data, ctypes.byref(nnz),
+                             ctypes.byref(dfc)))
+    return rp, col, val, dfc.value
+
+
+def host_gauss_legendre(n):
+    x = np.zeros(n); w = np.zeros(n)
+    _check(N.load().bem_host_gauss_legendre(n, x.ctypes.data, w.ctypes.data))
+    return x, w

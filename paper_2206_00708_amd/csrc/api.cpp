@@ -1,0 +1,446 @@
+// C-ABI entry points: contexts, meshes, problems, assembly orchestration and
+// copies out.  Kernels live in assemble.hip and solve.hip.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace bemtx {
+
+static thread_local std::string g_last_error = "no error";
+
+bem_status set_error(bem_status code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+bem_status hip_error(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory) return set_error(BEM_E_OOM, std::string("device allocation failed in ") + what);
+    return set_error(BEM_E_DEVICE, std::string(hipGetErrorString(e)) + " in " + what);
+}
+
+void DevMem::release()
+{
+    if (ptr) {
+        (void)hipFree(ptr);
+        if (ctx) ctx->in_use -= bytes;
+    }
+    ptr = nullptr;
+    bytes = 0;
+}
+
+DevMem::~DevMem() { release(); }
+
+bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes)
+{
+    if (m.ptr && m.bytes >= bytes) return BEM_OK;
+    m.release();
+    if (bytes == 0) bytes = 16;
+    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+        return set_error(BEM_E_OOM, "context HBM budget exceeded (" + std::to_string(ctx->in_use + bytes) + " > " +
+                                        std::to_string(ctx->budget) + " bytes)");
+    BEM_HIP(hipSetDevice(ctx->device));
+    hipError_t e = hipMalloc(&m.ptr, bytes);
+    if (e != hipSuccess) {
+        m.ptr = nullptr;
+        return hip_error(e, "hipMalloc");
+    }
+    m.bytes = bytes;
+    m.ctx = ctx;
+    ctx->in_use += bytes;
+    return BEM_OK;
+}
+
+template <class T>
+static bem_status upload(bem_ctx *ctx, DevMem &m, const std::vector<T> &v)
+{
+    bem_status s = dev_alloc(ctx, m, v.size() * sizeof(T));
+    if (s) return s;
+    if (!v.empty()) BEM_HIP(hipMemcpyAsync(m.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    return BEM_OK;
+}
+
+// kernels (assemble.hip, solve.hip)
+bem_status launch_geometry(const bem_mesh *m, hipStream_t st);
+size_t tile_scratch_bytes(const bem_mesh *m);
+bem_status launch_regular(const bem_mesh *m, double k, double2 *scratch, double2 *ops[4], hipStream_t st);
+bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw,
+                           double2 *contrib, double2 *ops[4], hipStream_t st);
+bem_status launch_mass_inverse(bem_problem *p, int mesh);
+bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
+                      bem_memspace space, bem_stats *stats);
+bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space);
+bem_status rhs_impl(bem_problem *p, const double *dirs, int nrhs, void *b, bem_memspace space);
+bem_status permute_matrix_out(const bem_problem *p, int mesh, const double2 *src, double2 *dst);
+
+static double ms_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace bemtx
+
+using namespace bemtx;
+
+extern "C" {
+
+const char *bem_last_error(void) { return g_last_error.c_str(); }
+
+bem_status bem_ctx_create(int32_t device, void *hip_stream, size_t hbm_budget_bytes, bem_ctx **out)
+{
+    if (!out) return set_error(BEM_E_ARG, "out is NULL");
+    int n = 0;
+    BEM_HIP(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return set_error(BEM_E_ARG, "device index out of range");
+    BEM_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    BEM_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
+        return set_error(BEM_E_UNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
+    bem_ctx *c = new bem_ctx;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->budget = hbm_budget_bytes;
+    *out = c;
+    return BEM_OK;
+}
+
+void bem_ctx_destroy(bem_ctx *ctx) { delete ctx; }
+
+size_t bem_ctx_bytes_in_use(const bem_ctx *ctx) { return ctx ? ctx->in_use : 0; }
+
+bem_status bem_mesh_create(bem_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
+                           bem_mesh **out)
+{
+    if (!ctx || !xyz || !tri || !out) return set_error(BEM_E_ARG, "null argument");
+    if (nv <= 0 || nt <= 0) return set_error(BEM_E_ARG, "empty mesh");
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(xyz[i])) return set_error(BEM_E_MESH, "non-finite vertex coordinate");
+    bem_mesh *m = new bem_mesh;
+    m->ctx = ctx;
+    m->h.nv = nv;
+    m->h.nt = nt;
+    m->h.xyz_user.assign(xyz, xyz + 3 * nv);
+    m->h.tri_user.assign(tri, tri + 3 * nt);
+    bem_status s = mesh_prepare(m->h);
+    if (s == BEM_OK) s = upload(ctx, m->d.perm, m->h.int_of_v);
+    if (s == BEM_OK) s = upload(ctx, m->d.xyz, m->h.xyz);
+    if (s == BEM_OK) s = upload(ctx, m->d.tri, m->h.tri);
+    if (s == BEM_OK) s = upload(ctx, m->d.blk_start, m->h.blk_start);
+    if (s == BEM_OK) s = upload(ctx, m->d.blk_nslot, m->h.blk_nslot);
+    if (s == BEM_OK) s = upload(ctx, m->d.slot_cnt, m->h.slot_cnt);
+    if (s == BEM_OK) s = upload(ctx, m->d.slot_ent, m->h.slot_ent);
+    if (s == BEM_OK) s = upload(ctx, m->d.memb_ptr, m->h.memb_ptr);
+    if (s == BEM_OK) s = upload(ctx, m->d.memb, m->h.memb);
+    if (s == BEM_OK) s = upload(ctx, m->d.sing, m->h.sing);
+    if (s == BEM_OK) s = upload(ctx, m->d.near_i, m->h.near_i);
+    if (s == BEM_OK) s = upload(ctx, m->d.near_j, m->h.near_j);
+    if (s == BEM_OK) s = upload(ctx, m->d.near_ptr, m->h.near_ptr);
+    if (s == BEM_OK) s = upload(ctx, m->d.near_src, m->h.near_src);
+    if (s == BEM_OK) s = upload(ctx, m->d.star_ptr, m->h.star_ptr);
+    if (s == BEM_OK) s = upload(ctx, m->d.star_ent, m->h.star_ent);
+    if (s == BEM_OK) s = dev_alloc(ctx, m->d.geo, (size_t)nt * sizeof(TriGeo));
+    if (s == BEM_OK) s = launch_geometry(m, ctx->stream);
+    if (s == BEM_OK) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) s = hip_error(e, "hipStreamSynchronize");
+    }
+    if (s != BEM_OK) {
+        delete m;
+        return s;
+    }
+    *out = m;
+    return BEM_OK;
+}
+
+void bem_mesh_destroy(bem_mesh *mesh) { delete mesh; }
+
+int64_t bem_mesh_num_vertices(const bem_mesh *mesh) { return mesh ? mesh->h.nv : 0; }
+
+bem_status bem_problem_create(bem_ctx *ctx, const bem_mesh *ext, const bem_mesh *inte, double k_ext, double k_int,
+                              double rho_ext, double rho_int, bem_precision precision, const bem_quad_opts *quad,
+                              bem_problem **out)
+{
+    if (!ctx || !ext || !inte || !out) return set_error(BEM_E_ARG, "null argument");
+    if (ext->ctx != ctx || inte->ctx != ctx) return set_error(BEM_E_ARG, "meshes belong to another context");
+    if (!(k_ext > 0) || !(k_int > 0) || !(rho_ext > 0) || !(rho_int > 0) || !std::isfinite(k_ext) ||
+        !std::isfinite(k_int) || !std::isfinite(rho_ext) || !std::isfinite(rho_int))
+        return set_error(BEM_E_ARG, "wavenumbers and densities must be positive and finite");
+    if (precision != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "only BEM_C128 is available in this build");
+    int ng = quad ? quad->singular_gauss : 4;
+    if (ng < 1 || ng > NG_MAX) return set_error(BEM_E_ARG, "singular_gauss must be in 1..16");
+    bem_problem *p = new bem_problem;
+    p->ctx = ctx;
+    p->ext = ext;
+    p->inte = inte;
+    p->k_ext = k_ext;
+    p->k_int = k_int;
+    p->rho_ext = rho_ext;
+    p->rho_int = rho_int;
+    p->prec = precision;
+    p->ng = ng;
+    gauss_legendre01(ng, p->gl_x, p->gl_w);
+    *out = p;
+    return BEM_OK;
+}
+
+void bem_problem_destroy(bem_problem *p) { delete p; }
+
+bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t maxit, size_t *bytes)
+{
+    if (!p || !bytes || nrhs < 1 || maxit < 1) return set_error(BEM_E_ARG, "bad argument");
+    const size_t ne = p->ext->h.nv, ni = p->inte->h.nv, n = 2 * ne + 2 * ni;
+    size_t b = 4 * (ne * ne + ni * ni) * sizeof(double2);          // dense operators
+    b += (ne * ne + ni * ni) * sizeof(double);                     // dense inverse masses
+    size_t scratch = std::max(tile_scratch_bytes(p->ext), tile_scratch_bytes(p->inte));
+    scratch = std::max(scratch, std::max(p->ext->h.sing.size(), p->inte->h.sing.size()) * 36 * sizeof(double2));
+    b += scratch;
+    b += (size_t)nrhs * ((size_t)(maxit + 1) * n + 8 * n) * sizeof(double2);   // Krylov bases + work vectors
+    b += 64 * (ne + ni) * sizeof(double);                          // sparse couplings (bound)
+    *bytes = b;
+    return BEM_OK;
+}
+
+bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
+{
+    if (!p) return set_error(BEM_E_ARG, "null problem");
+    if (parts < 0 || parts > 3) return set_error(BEM_E_ARG, "parts must be 0..3");
+    bem_ctx *ctx = p->ctx;
+    BEM_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const bem_mesh *meshes[2] = {p->ext, p->inte};
+    const double ks[2] = {p->k_ext, p->k_int};
+    size_t scratch_bytes = 16;
+    for (int m = 0; m < 2; ++m) {
+        scratch_bytes = std::max(scratch_bytes, tile_scratch_bytes(meshes[m]));
+        scratch_bytes = std::max(scratch_bytes, meshes[m]->h.sing.size() * 36 * sizeof(double2));
+    }
+    for (int m = 0; m < 2; ++m) {
+        const size_t nv = meshes[m]->h.nv;
+        for (int op = 0; op < 4; ++op) {
+            bem_status s = dev_alloc(ctx, p->ops[m][op], nv * nv * sizeof(double2));
+            if (s) return s;
+        }
+    }
+    DevMem scratch;
+    {
+        bem_status s = dev_alloc(ctx, scratch, scratch_bytes);
+        if (s) return s;
+    }
+    hipEvent_t ev[5];
+    for (auto &e : ev) BEM_HIP(hipEventCreate(&e));
+    BEM_HIP(hipEventRecord(ev[0], st));
+    float t_reg = 0, t_sing = 0;
+    for (int m = 0; m < 2; ++m) {
+        double2 *ops[4];
+        for (int op = 0; op < 4; ++op) ops[op] = p->ops[m][op].as<double2>();
+        const size_t nv = meshes[m]->h.nv;
+        BEM_HIP(hipEventRecord(ev[1], st));
+        if (parts & 1) {
+            bem_status s = launch_regular(meshes[m], ks[m], scratch.as<double2>(), ops, st);
+            if (s) return s;
+        } else {
+            for (int op = 0; op < 4; ++op) BEM_HIP(hipMemsetAsync(ops[op], 0, nv * nv * sizeof(double2), st));
+        }
+        BEM_HIP(hipEventRecord(ev[2], st));
+        if (parts & 2) {
+            bem_status s = launch_singular(meshes[m], ks[m], p->ng, p->gl_x, p->gl_w, scratch.as<double2>(), ops, st);
+            if (s) return s;
+        }
+        BEM_HIP(hipEventRecord(ev[3], st));
+        BEM_HIP(hipEventSynchronize(ev[3]));
+        float a = 0, b = 0;
+        BEM_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
+        BEM_HIP(hipEventElapsedTime(&b, ev[2], ev[3]));
+        t_reg += a;
+        t_sing += b;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    p->t_regular_ms = t_reg;
+    p->t_singular_ms = t_sing;
+    p->ops_ready = true;
+    return BEM_OK;
+}
+
+bem_status bem_assemble_projection(bem_problem *p)
+{
+    if (!p) return set_error(BEM_E_ARG, "null problem");
+    bem_ctx *ctx = p->ctx;
+    BEM_HIP(hipSetDevice(ctx->device));
+    auto t0 = std::chrono::steady_clock::now();
+    mass_csr(p->ext->h, p->M[0]);
+    mass_csr(p->inte->h, p->M[1]);
+    double defect = 0;
+    bem_status s = mortar_csr(p->inte->h, p->ext->h, p->P_ie, &defect);
+    if (s) return s;
+    transpose_csr(p->P_ie, p->P_ei);
+    s = upload(ctx, p->P_ie_ptr, p->P_ie.ptr);
+    if (!s) s = upload(ctx, p->P_ie_col, p->P_ie.col);
+    if (!s) s = upload(ctx, p->P_ie_val, p->P_ie.val);
+    if (!s) s = upload(ctx, p->P_ei_ptr, p->P_ei.ptr);
+    if (!s) s = upload(ctx, p->P_ei_col, p->P_ei.col);
+    if (!s) s = upload(ctx, p->P_ei_val, p->P_ei.val);
+    for (int m = 0; m < 2 && !s; ++m) {
+        s = upload(ctx, p->M_ptr[m], p->M[m].ptr);
+        if (!s) s = upload(ctx, p->M_col[m], p->M[m].col);
+        if (!s) s = upload(ctx, p->M_val[m], p->M[m].val);
+        if (!s) s = launch_mass_inverse(p, m);
+    }
+    if (s) return s;
+    BEM_HIP(hipStreamSynchronize(ctx->stream));
+    p->t_projection_ms = ms_since(t0);
+    p->proj_ready = true;
+    return BEM_OK;
+}
+
+bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space)
+{
+    if (!p || !x || !y) return set_error(BEM_E_ARG, "null argument");
+    if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
+    return matvec_impl(p, x, y, strong, space);
+}
+
+bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b, bem_memspace space)
+{
+    if (!p || !dirs || !b || nrhs < 1) return set_error(BEM_E_ARG, "bad argument");
+    return rhs_impl(p, dirs, nrhs, b, space);
+}
+
+bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts, void *traces,
+                     bem_memspace space, bem_stats *stats)
+{
+    if (!p || !dirs || !opts || !traces || nrhs < 1) return set_error(BEM_E_ARG, "bad argument");
+    if (!(opts->tol > 0) || opts->maxit < 1 || opts->maxit > 4000)
+        return set_error(BEM_E_ARG, "tol must be > 0 and 1 <= maxit <= 4000");
+    if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
+    for (int r = 0; r < nrhs; ++r) {
+        double l = std::sqrt(dirs[3 * r] * dirs[3 * r] + dirs[3 * r + 1] * dirs[3 * r + 1] + dirs[3 * r + 2] * dirs[3 * r + 2]);
+        if (!(std::fabs(l - 1.0) < 1e-6)) return set_error(BEM_E_ARG, "directions must be unit vectors");
+    }
+    return solve_impl(p, dirs, nrhs, opts, traces, space, stats);
+}
+
+bem_status bem_copy_operator(const bem_problem *p, int32_t mesh, char op, void *dst, bem_memspace space)
+{
+    if (!p || !dst) return set_error(BEM_E_ARG, "null argument");
+    if (mesh != 0 && mesh != 1) return set_error(BEM_E_ARG, "mesh must be 0 (exterior) or 1 (interior)");
+    const char *names = "VKTD";
+    const char *f = std::strchr(names, op);
+    if (!f || op == 0) return set_error(BEM_E_ARG, "op must be one of V, K, T, D");
+    if (!p->ops_ready) return set_error(BEM_E_STATE, "operators not assembled");
+    const int o = (int)(f - names);
+    const bem_mesh *m = mesh == 0 ? p->ext : p->inte;
+    const size_t nv = m->h.nv, bytes = nv * nv * sizeof(double2);
+    bem_ctx *ctx = p->ctx;
+    BEM_HIP(hipSetDevice(ctx->device));
+    if (space == BEM_DEVICE) {
+        bem_status s = permute_matrix_out(p, mesh, p->ops[mesh][o].as<double2>(), static_cast<double2 *>(dst));
+        if (s) return s;
+        BEM_HIP(hipStreamSynchronize(ctx->stream));
+        return BEM_OK;
+    }
+    DevMem tmp;
+    bem_status s = dev_alloc(ctx, tmp, bytes);
+    if (s) return s;
+    s = permute_matrix_out(p, mesh, p->ops[mesh][o].as<double2>(), tmp.as<double2>());
+    if (s) return s;
+    BEM_HIP(hipMemcpyAsync(dst, tmp.ptr, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    BEM_HIP(hipStreamSynchronize(ctx->stream));
+    return BEM_OK;
+}
+
+bem_status bem_copy_projection(const bem_problem *p, int64_t *rowptr, int32_t *col, double *val, int64_t *nnz)
+{
+    if (!p || !nnz) return set_error(BEM_E_ARG, "null argument");
+    if (!p->proj_ready) return set_error(BEM_E_STATE, "projection not assembled");
+    const MeshData &mi = p->inte->h, &me = p->ext->h;
+    const Csr &P = p->P_ie;
+    *nnz = (int64_t)P.col.size();
+    if (!rowptr) return BEM_OK;
+    if (!col || !val) return set_error(BEM_E_ARG, "col and val are required with rowptr");
+    // caller numbering: row i_user = v_of_int[i_int], columns mapped and sorted
+    int64_t q = 0;
+    rowptr[0] = 0;
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t iu = 0; iu < mi.nv; ++iu) {
+        const int32_t ii = mi.int_of_v[iu];
+        row.clear();
+        for (int32_t k = P.ptr[ii]; k < P.ptr[ii + 1]; ++k) row.push_back({me.v_of_int[P.col[k]], P.val[k]});
+        std::sort(row.begin(), row.end());
+        for (auto &e : row) {
+            col[q] = e.first;
+            val[q] = e.second;
+            ++q;
+        }
+        rowptr[iu + 1] = q;
+    }
+    return BEM_OK;
+}
+
+bem_status bem_check_mesh(const double *xyz, int64_t nv, const int32_t *tri, int64_t nt)
+{
+    if (!xyz || !tri || nv <= 0 || nt <= 0) return set_error(BEM_E_ARG, "bad argument");
+    for (int64_t i = 0; i < 3 * nv; ++i)
+        if (!std::isfinite(xyz[i])) return set_error(BEM_E_MESH, "non-finite vertex coordinate");
+    MeshData m;
+    m.nv = nv;
+    m.nt = nt;
+    m.xyz_user.assign(xyz, xyz + 3 * nv);
+    m.tri_user.assign(tri, tri + 3 * nt);
+    return mesh_prepare(m);
+}
+
+bem_status bem_host_mortar(const double *xyz_int, int64_t nv_int, const int32_t *tri_int, int64_t nt_int,
+                           const double *xyz_ext, int64_t nv_ext, const int32_t *tri_ext, int64_t nt_ext,
+                           int64_t *rowptr, int32_t *col, double *val, int64_t *nnz, double *coverage_defect)
+{
+    if (!nnz) return set_error(BEM_E_ARG, "nnz is NULL");
+    MeshData mi, me;
+    mi.nv = nv_int; mi.nt = nt_int; me.nv = nv_ext; me.nt = nt_ext;
+    if (!xyz_int || !tri_int || !xyz_ext || !tri_ext) return set_error(BEM_E_ARG, "null mesh array");
+    mi.xyz_user.assign(xyz_int, xyz_int + 3 * nv_int);
+    mi.tri_user.assign(tri_int, tri_int + 3 * nt_int);
+    me.xyz_user.assign(xyz_ext, xyz_ext + 3 * nv_ext);
+    me.tri_user.assign(tri_ext, tri_ext + 3 * nt_ext);
+    bem_status s = mesh_prepare(mi);
+    if (!s) s = mesh_prepare(me);
+    if (s) return s;
+    Csr P;
+    double defect = 0;
+    s = mortar_csr(mi, me, P, &defect);
+    if (coverage_defect) *coverage_defect = defect;
+    if (s) return s;
+    const int64_t total = (int64_t)P.col.size();
+    if (!rowptr) {
+        *nnz = total;
+        return BEM_OK;
+    }
+    if (!col || !val || *nnz < total) return set_error(BEM_E_ARG, "output arrays missing or too small");
+    int64_t q = 0;
+    rowptr[0] = 0;
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t iu = 0; iu < nv_int; ++iu) {
+        const int32_t ii = mi.int_of_v[iu];
+        row.clear();
+        for (int32_t k = P.ptr[ii]; k < P.ptr[ii + 1]; ++k) row.push_back({me.v_of_int[P.col[k]], P.val[k]});
+        std::sort(row.begin(), row.end());
+        for (auto &e : row) { col[q] = e.first; val[q] = e.second; ++q; }
+        rowptr[iu + 1] = q;
+    }
+    *nnz = total;
+    return BEM_OK;
+}
+
+bem_status bem_host_gauss_legendre(int32_t n, double *x, double *w)
+{
+    if (n < 1 || n > NG_MAX || !x || !w) return set_error(BEM_E_ARG, "n must be in 1..16");
+    gauss_legendre01(n, x, w);
+    return BEM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,517 @@
+// Galerkin P1 assembly of the Helmholtz boundary integral operators
+// V (kernel G), K (dG/dn_y), T (dG/dn_x) and D (hypersingular, integrated by
+// parts) on one triangle mesh, G(x,y) = exp(i k |x-y|) / (4 pi |x-y|)
+// (Sec. 2.1, Sec. 2.4), in FP64 on gfx950.
+//
+//   geometry_kernel   per-triangle table: vertices, unit normal, area, the
+//                     six points of the order-four rule, P1 surface curls.
+//   regular_tiles     triangle pairs that share no vertex, order-four rule
+//                     (6 x 6 points, Sec. 5.1).  One workgroup per unordered
+//                     pair of locality blocks (16 x 16 triangles), one
+//                     triangle pair per thread; V, K, T and the scalar sum of
+//                     G are reduced in registers, D follows from them
+//                     (curl.curl S - k^2 n.n V).  The 9 entries of each pair
+//                     are summed per vertex slot through LDS in a fixed order
+//                     and the block-pair tile is written once.  Because the
+//                     regular rule is symmetric in (x, y), the tile of
+//                     (b1, b2) also provides (b2, b1): V, D transpose to
+//                     themselves and K, T into each other.
+//   gather_tiles      dense entry (i, j) = fixed-order sum of the tile
+//                     entries of the blocks containing i and j.
+//   singular_pairs    ordered pairs sharing 3 / 2 / 1 vertices: Sauter-Schwab
+//                     regularising maps of [0,1]^4 with ng^4 Gauss points per
+//                     region (6 / 5 / 2 regions); 16 lanes per pair.
+//   near_scatter      adds the singular contributions of each touched entry
+//                     in a fixed order.
+// Every entry is produced by a fixed sequence of additions, so the result is
+// bitwise reproducible run to run.
+#include <cmath>
+
+#include "internal.h"
+
+namespace bemtx {
+
+namespace {
+
+constexpr double kA1 = 0.445948490915964886318329253883;
+constexpr double kW1 = 0.223381589678011465944827736698;
+constexpr double kA2 = 0.091576213509770743459571463402;
+constexpr double kW2 = 0.109951743655321867388505596635;
+constexpr double kInv4Pi = 0.0795774715459476678844418816863;
+
+// Barycentric coordinate c of point q of the 6-point rule, and its weight
+// (weights sum to one; multiply by the area).
+__host__ __device__ constexpr double r6_bary(int q, int c)
+{
+    return q < 3 ? (c == q ? 1.0 - 2.0 * kA1 : kA1) : (c == q - 3 ? 1.0 - 2.0 * kA2 : kA2);
+}
+__host__ __device__ constexpr double r6_w(int q) { return q < 3 ? kW1 : kW2; }
+
+__device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+}  // namespace
+
+__global__ void geometry_kernel(const double *__restrict__ xyz, const int32_t *__restrict__ tri, int nt,
+                                TriGeo *__restrict__ geo)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    TriGeo g;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) g.p[a][c] = xyz[3 * (int64_t)tri[3 * t + a] + c];
+    double e1[3], e2[3];
+    for (int c = 0; c < 3; ++c) { e1[c] = g.p[1][c] - g.p[0][c]; e2[c] = g.p[2][c] - g.p[0][c]; }
+    double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double len = sqrt(dot3(cr, cr));
+    g.area = 0.5 * len;
+    for (int c = 0; c < 3; ++c) g.n[c] = cr[c] / len;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) g.curl[a][c] = (g.p[(a + 1) % 3][c] - g.p[(a + 2) % 3][c]) / len;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+        for (int c = 0; c < 3; ++c)
+            g.qp[q][c] = r6_bary(q, 0) * g.p[0][c] + r6_bary(q, 1) * g.p[1][c] + r6_bary(q, 2) * g.p[2][c];
+    geo[t] = g;
+}
+
+// ------------------------------------------------------------ regular pairs
+
+struct TileArgs {
+    const TriGeo *geo;
+    const int32_t *tri;
+    const int32_t *blk_start;
+    const int32_t *blk_nslot;
+    const uint8_t *slot_cnt;
+    const uint8_t *slot_ent;
+    int32_t nb;
+    double k;
+    double2 *scratch;      // [tile][op][SMAX*SMAX]
+};
+
+__device__ inline void tile_of(int64_t t, int nb, int &b1, int &b2)
+{
+    // tiles enumerate (b1, b2), b1 <= b2, row by row; offset(b) = b*nb - b*(b-1)/2
+    double B = 2.0 * nb + 1.0;
+    int b = (int)floor(0.5 * (B - sqrt(B * B - 8.0 * (double)t)));
+    if (b < 0) b = 0;
+    if (b > nb - 1) b = nb - 1;
+    while (b > 0 && (int64_t)b * nb - (int64_t)b * (b - 1) / 2 > t) --b;
+    while (b + 1 < nb && (int64_t)(b + 1) * nb - (int64_t)(b + 1) * b / 2 <= t) ++b;
+    b1 = b;
+    b2 = b + (int)(t - ((int64_t)b * nb - (int64_t)b * (b - 1) / 2));
+}
+
+__global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64_t tile0)
+{
+    __shared__ TriGeo gX[BT], gY[BT];
+    __shared__ int32_t vX[BT * 3], vY[BT * 3];
+    __shared__ uint8_t c1[SMAX], c2[SMAX], e1[SMAX * LMAX], e2[SMAX * LMAX];
+    __shared__ double st_re[256 * 9], st_im[256 * 9];
+
+    const int64_t tile = tile0 + blockIdx.x;
+    int b1, b2;
+    tile_of(tile, A.nb, b1, b2);
+    const int s1 = A.blk_start[b1], n1 = A.blk_start[b1 + 1] - s1;
+    const int s2 = A.blk_start[b2], n2 = A.blk_start[b2 + 1] - s2;
+    const int ns1 = A.blk_nslot[b1], ns2 = A.blk_nslot[b2];
+    const int tid = threadIdx.x;
+    {
+        const double *src1 = reinterpret_cast<const double *>(A.geo + s1);
+        const double *src2 = reinterpret_cast<const double *>(A.geo + s2);
+        double *d1 = reinterpret_cast<double *>(gX), *d2 = reinterpret_cast<double *>(gY);
+        const int w = sizeof(TriGeo) / sizeof(double);
+        for (int q = tid; q < n1 * w; q += 256) d1[q] = src1[q];
+        for (int q = tid; q < n2 * w; q += 256) d2[q] = src2[q];
+        if (tid < n1 * 3) vX[tid] = A.tri[3 * s1 + tid];
+        if (tid < n2 * 3) vY[tid] = A.tri[3 * s2 + tid];
+        if (tid < SMAX) { c1[tid] = A.slot_cnt[b1 * SMAX + tid]; c2[tid] = A.slot_cnt[b2 * SMAX + tid]; }
+        for (int q = tid; q < SMAX * LMAX; q += 256) {
+            e1[q] = A.slot_ent[(size_t)b1 * SMAX * LMAX + q];
+            e2[q] = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
+        }
+    }
+    __syncthreads();
+
+    const int t1 = tid >> 4, t2 = tid & 15;
+    bool active = t1 < n1 && t2 < n2;
+    if (active) {
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) active = active && (vX[3 * t1 + a] != vY[3 * t2 + b]);
+    }
+    double vr[9], vi[9], kr[9], ki[9], tr[9], ti[9], sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) { vr[e] = vi[e] = kr[e] = ki[e] = tr[e] = ti[e] = 0.0; }
+    const double k = A.k;
+    if (active) {
+        const TriGeo &X = gX[t1];
+        const TriGeo &Y = gY[t2];
+        const double nx0 = X.n[0], nx1 = X.n[1], nx2 = X.n[2];
+        const double ny0 = Y.n[0], ny1 = Y.n[1], ny2 = Y.n[2];
+#pragma unroll 1
+        for (int p = 0; p < 6; ++p) {
+            const double x0 = X.qp[p][0], x1 = X.qp[p][1], x2 = X.qp[p][2];
+            double hvr[3] = {0, 0, 0}, hvi[3] = {0, 0, 0}, hkr[3] = {0, 0, 0}, hki[3] = {0, 0, 0};
+            double htr[3] = {0, 0, 0}, hti[3] = {0, 0, 0}, hsr = 0.0, hsi = 0.0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const double d0 = x0 - Y.qp[q][0], d1 = x1 - Y.qp[q][1], d2 = x2 - Y.qp[q][2];
+                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const double rinv = rsqrt(r2);
+                const double r = r2 * rinv;
+                const double kr_ = k * r;
+                double sn, cs;
+                sincos(kr_, &sn, &cs);
+                const double gr = cs * rinv, gi = sn * rinv;           // exp(ikr)/r
+                const double rinv2 = rinv * rinv;
+                const double fr = (-gr - gi * kr_) * rinv2;            // exp(ikr)(ikr-1)/r^3
+                const double fi = (gr * kr_ - gi) * rinv2;
+                const double dk = -(d0 * ny0 + d1 * ny1 + d2 * ny2);  // (y-x).n_y
+                const double dt = d0 * nx0 + d1 * nx1 + d2 * nx2;     // (x-y).n_x
+                const double gkr = fr * dk, gki = fi * dk, gtr = fr * dt, gti = fi * dt;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const double W = r6_w(q) * r6_bary(q, b);
+                    hvr[b] += W * gr; hvi[b] += W * gi;
+                    hkr[b] += W * gkr; hki[b] += W * gki;
+                    htr[b] += W * gtr; hti[b] += W * gti;
+                }
+                hsr += r6_w(q) * gr;
+                hsi += r6_w(q) * gi;
+            }
+            const double wp = p < 3 ? kW1 : kW2;
+            const double ap = p < 3 ? kA1 : kA2;
+            const int pc = p < 3 ? p : p - 3;            // corner carrying 1 - 2a
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double W = wp * (a == pc ? 1.0 - 2.0 * ap : ap);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    vr[3 * a + b] += W * hvr[b]; vi[3 * a + b] += W * hvi[b];
+                    kr[3 * a + b] += W * hkr[b]; ki[3 * a + b] += W * hki[b];
+                    tr[3 * a + b] += W * htr[b]; ti[3 * a + b] += W * hti[b];
+                }
+            }
+            sr += wp * hsr;
+            si += wp * hsi;
+        }
+        const double scale = X.area * Y.area * kInv4Pi;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            vr[e] *= scale; vi[e] *= scale; kr[e] *= scale; ki[e] *= scale; tr[e] *= scale; ti[e] *= scale;
+        }
+        sr *= scale;
+        si *= scale;
+    }
+
+    // ---- per-slot reduction through LDS, one operator at a time
+    double2 *out = A.scratch + tile * (4 * SMAX * SMAX);
+#pragma unroll 1
+    for (int op = 0; op < 4; ++op) {
+        if (op == 3 && active) {
+            const TriGeo &X = gX[t1];
+            const TriGeo &Y = gY[t2];
+            const double nn = X.n[0] * Y.n[0] + X.n[1] * Y.n[1] + X.n[2] * Y.n[2];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const double cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
+                    st_re[tid * 9 + 3 * a + b] = cc * sr - k * k * nn * vr[3 * a + b];
+                    st_im[tid * 9 + 3 * a + b] = cc * si - k * k * nn * vi[3 * a + b];
+                }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                double re = op == 0 ? vr[e] : (op == 1 ? kr[e] : (op == 2 ? tr[e] : 0.0));
+                double im = op == 0 ? vi[e] : (op == 1 ? ki[e] : (op == 2 ? ti[e] : 0.0));
+                st_re[tid * 9 + e] = active ? re : 0.0;
+                st_im[tid * 9 + e] = active ? im : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < SMAX * SMAX; e += 256) {
+            const int q1 = e / SMAX, q2 = e - q1 * SMAX;
+            if (q1 >= ns1 || q2 >= ns2) continue;
+            double re = 0.0, im = 0.0;
+            const int m1 = c1[q1], m2 = c2[q2];
+            for (int u = 0; u < m1; ++u) {
+                const int en1 = e1[q1 * LMAX + u];
+                const int tt1 = en1 / 3, a = en1 - 3 * tt1;
+                for (int v = 0; v < m2; ++v) {
+                    const int en2 = e2[q2 * LMAX + v];
+                    const int tt2 = en2 / 3, b = en2 - 3 * tt2;
+                    const int idx = (tt1 * 16 + tt2) * 9 + 3 * a + b;
+                    re += st_re[idx];
+                    im += st_im[idx];
+                }
+            }
+            out[op * SMAX * SMAX + e] = make_double2(re, im);
+        }
+        __syncthreads();
+    }
+}
+
+// dense entry (i, j) from the tiles of the blocks that contain i and j
+__global__ __launch_bounds__(256) void gather_tiles_kernel(int nv, int nb, const int32_t *__restrict__ memb_ptr,
+                                                           const int32_t *__restrict__ memb,
+                                                           const double2 *__restrict__ scratch,
+                                                           double2 *__restrict__ V, double2 *__restrict__ K,
+                                                           double2 *__restrict__ T, double2 *__restrict__ D)
+{
+    const int i = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nv) return;
+    const int pi0 = memb_ptr[i], pi1 = memb_ptr[i + 1];
+    const int pj0 = memb_ptr[j], pj1 = memb_ptr[j + 1];
+    double2 v = make_double2(0, 0), kk = v, t = v, d = v;
+    for (int p = pi0; p < pi1; ++p) {
+        const int mi = memb[p], bi = mi >> 8, si = mi & 255;
+        for (int q = pj0; q < pj1; ++q) {
+            const int mj = memb[q], bj = mj >> 8, sj = mj & 255;
+            const int lo = bi < bj ? bi : bj, hi = bi < bj ? bj : bi;
+            const int64_t tile = (int64_t)lo * nb - (int64_t)lo * (lo - 1) / 2 + (hi - lo);
+            const double2 *tl = scratch + tile * (4 * SMAX * SMAX);
+            if (bi <= bj) {
+                const int e = si * SMAX + sj;
+                const double2 a0 = tl[e], a1 = tl[SMAX * SMAX + e], a2 = tl[2 * SMAX * SMAX + e], a3 = tl[3 * SMAX * SMAX + e];
+                v.x += a0.x; v.y += a0.y; kk.x += a1.x; kk.y += a1.y;
+                t.x += a2.x; t.y += a2.y; d.x += a3.x; d.y += a3.y;
+            } else {
+                // tile of (bj, bi): test side is j; K and T swap under transposition
+                const int e = sj * SMAX + si;
+                const double2 a0 = tl[e], a1 = tl[SMAX * SMAX + e], a2 = tl[2 * SMAX * SMAX + e], a3 = tl[3 * SMAX * SMAX + e];
+                v.x += a0.x; v.y += a0.y; kk.x += a2.x; kk.y += a2.y;
+                t.x += a1.x; t.y += a1.y; d.x += a3.x; d.y += a3.y;
+            }
+        }
+    }
+    const int64_t o = (int64_t)i * nv + j;
+    V[o] = v;
+    K[o] = kk;
+    T[o] = t;
+    D[o] = d;
+}
+
+// ----------------------------------------------------------- singular pairs
+
+struct GLTab {
+    double x[NG_MAX], w[NG_MAX];
+};
+
+// Sauter-Schwab regions on the reference triangle {0 <= s2 <= s1 <= 1}.
+__device__ inline void ss_map(int kind, int reg, double xi, double e1, double e2, double e3, double &x0, double &x1,
+                              double &y0, double &y1, double &jac)
+{
+    const double xi3 = xi * xi * xi;
+    if (kind == 3) {
+        jac = xi3 * e1 * e1 * e2;
+        const double a = xi, b = xi * (1.0 - e1 + e1 * e2), c = xi * (1.0 - e1 * e2 * e3), d = xi * (1.0 - e1);
+        const double f = xi * e1 * (1.0 - e2 + e2 * e3), g = xi * (1.0 - e1 * e2), h = xi * e1 * (1.0 - e2);
+        const double m = xi * e1 * (1.0 - e2 * e3);
+        switch (reg) {
+        case 0: x0 = a; x1 = b; y0 = c; y1 = d; break;
+        case 1: x0 = c; x1 = d; y0 = a; y1 = b; break;
+        case 2: x0 = a; x1 = f; y0 = g; y1 = h; break;
+        case 3: x0 = g; x1 = h; y0 = a; y1 = f; break;
+        case 4: x0 = c; x1 = m; y0 = a; y1 = h; break;
+        default: x0 = a; x1 = h; y0 = c; y1 = m; break;
+        }
+    } else if (kind == 2) {
+        jac = xi3 * e1 * e1 * (reg == 0 ? 1.0 : e2);
+        switch (reg) {
+        case 0: x0 = xi; x1 = xi * e1 * e3; y0 = xi * (1.0 - e1 * e2); y1 = xi * e1 * (1.0 - e2); break;
+        case 1: x0 = xi; x1 = xi * e1; y0 = xi * (1.0 - e1 * e2 * e3); y1 = xi * e1 * e2 * (1.0 - e3); break;
+        case 2: x0 = xi * (1.0 - e1 * e2); x1 = xi * e1 * (1.0 - e2); y0 = xi; y1 = xi * e1 * e2 * e3; break;
+        case 3: x0 = xi * (1.0 - e1 * e2 * e3); x1 = xi * e1 * e2 * (1.0 - e3); y0 = xi; y1 = xi * e1; break;
+        default: x0 = xi * (1.0 - e1 * e2 * e3); x1 = xi * e1 * (1.0 - e2 * e3); y0 = xi; y1 = xi * e1 * e2; break;
+        }
+    } else {
+        jac = xi3 * e2;
+        if (reg == 0) { x0 = xi; x1 = xi * e1; y0 = xi * e2; y1 = xi * e2 * e3; }
+        else { x0 = xi * e2; x1 = xi * e2 * e3; y0 = xi; y1 = xi * e1; }
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__restrict__ geo,
+                                                             const SingPair *__restrict__ pairs, int npairs, int ng,
+                                                             GLTab gl, double k, double2 *__restrict__ out)
+{
+    const int grp = threadIdx.x >> 4, lane = threadIdx.x & 15;
+    const int pid = blockIdx.x * 16 + grp;
+    if (pid >= npairs) return;
+    const SingPair sp = pairs[pid];
+    const TriGeo &X = geo[sp.tau];
+    const TriGeo &Y = geo[sp.sig];
+    int px[3], py[3];
+    for (int r = 0; r < 3; ++r) { px[r] = (sp.perm >> (2 * r)) & 3; py[r] = (sp.perm >> (6 + 2 * r)) & 3; }
+    double Qx[3][3], Qy[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) { Qx[r][c] = X.p[px[r]][c]; Qy[r][c] = Y.p[py[r]][c]; }
+    double ax[2][3], ay[2][3];
+    for (int c = 0; c < 3; ++c) {
+        ax[0][c] = Qx[1][c] - Qx[0][c]; ax[1][c] = Qx[2][c] - Qx[1][c];
+        ay[0][c] = Qy[1][c] - Qy[0][c]; ay[1][c] = Qy[2][c] - Qy[1][c];
+    }
+    const double nx[3] = {X.n[0], X.n[1], X.n[2]}, ny[3] = {Y.n[0], Y.n[1], Y.n[2]};
+    const int kind = sp.kind;
+    const int nreg = kind == 3 ? 6 : (kind == 2 ? 5 : 2);
+    double vr[9], vi[9], kr[9], ki[9], tr[9], ti[9], sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) { vr[e] = vi[e] = kr[e] = ki[e] = tr[e] = ti[e] = 0.0; }
+    const int ng2 = ng * ng;
+    for (int inner = lane; inner < ng2; inner += 16) {
+        const int i2 = inner / ng, i3 = inner - i2 * ng;
+        const double e2 = gl.x[i2], e3 = gl.x[i3], w23 = gl.w[i2] * gl.w[i3];
+        for (int reg = 0; reg < nreg; ++reg)
+            for (int i0 = 0; i0 < ng; ++i0)
+                for (int i1 = 0; i1 < ng; ++i1) {
+                    const double xi = gl.x[i0], e1 = gl.x[i1];
+                    double xs0, xs1, ys0, ys1, jac;
+                    ss_map(kind, reg, xi, e1, e2, e3, xs0, xs1, ys0, ys1, jac);
+                    const double wt = gl.w[i0] * gl.w[i1] * w23 * jac;
+                    double d[3];
+                    for (int c = 0; c < 3; ++c)
+                        d[c] = (Qx[0][c] + xs0 * ax[0][c] + xs1 * ax[1][c]) - (Qy[0][c] + ys0 * ay[0][c] + ys1 * ay[1][c]);
+                    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    const double rinv = rsqrt(r2);
+                    const double r = r2 * rinv, kr_ = k * r;
+                    double sn, cs;
+                    sincos(kr_, &sn, &cs);
+                    const double gr = cs * rinv * wt, gi = sn * rinv * wt;
+                    const double rinv2 = rinv * rinv;
+                    const double fr = (-gr - gi * kr_) * rinv2, fi = (gr * kr_ - gi) * rinv2;
+                    const double dk = -(d[0] * ny[0] + d[1] * ny[1] + d[2] * ny[2]);
+                    const double dt = d[0] * nx[0] + d[1] * nx[1] + d[2] * nx[2];
+                    const double phx[3] = {1.0 - xs0, xs0 - xs1, xs1}, phy[3] = {1.0 - ys0, ys0 - ys1, ys1};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            const double ph = phx[a] * phy[b];
+                            vr[3 * a + b] += ph * gr; vi[3 * a + b] += ph * gi;
+                            kr[3 * a + b] += ph * fr * dk; ki[3 * a + b] += ph * fi * dk;
+                            tr[3 * a + b] += ph * fr * dt; ti[3 * a + b] += ph * fi * dt;
+                        }
+                    sr += gr;
+                    si += gi;
+                }
+    }
+    // reduce over the 16 lanes of the group
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            vr[e] += __shfl_xor(vr[e], off, 16); vi[e] += __shfl_xor(vi[e], off, 16);
+            kr[e] += __shfl_xor(kr[e], off, 16); ki[e] += __shfl_xor(ki[e], off, 16);
+            tr[e] += __shfl_xor(tr[e], off, 16); ti[e] += __shfl_xor(ti[e], off, 16);
+        }
+        sr += __shfl_xor(sr, off, 16);
+        si += __shfl_xor(si, off, 16);
+    }
+    if (lane != 0) return;
+    const double scale = 4.0 * X.area * Y.area * kInv4Pi;
+    const double nn = nx[0] * ny[0] + nx[1] * ny[1] + nx[2] * ny[2];
+    double2 *o = out + (int64_t)pid * 36;
+    for (int ra = 0; ra < 3; ++ra)
+        for (int rb = 0; rb < 3; ++rb) {
+            const int a = px[ra], b = py[rb];        // own corners
+            const int e = 3 * a + b, re = 3 * ra + rb;
+            const double cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
+            const double Vr = vr[re] * scale, Vi = vi[re] * scale;
+            o[e] = make_double2(Vr, Vi);
+            o[9 + e] = make_double2(kr[re] * scale, ki[re] * scale);
+            o[18 + e] = make_double2(tr[re] * scale, ti[re] * scale);
+            o[27 + e] = make_double2(cc * sr * scale - k * k * nn * Vr, cc * si * scale - k * k * nn * Vi);
+        }
+}
+
+// add the singular contributions to their dense entries (fixed order)
+__global__ void near_scatter_kernel(int nv, int nnear, const int32_t *__restrict__ ni, const int32_t *__restrict__ nj,
+                                    const int32_t *__restrict__ nptr, const int32_t *__restrict__ nsrc,
+                                    const SingPair *__restrict__ pairs, const double2 *__restrict__ contrib,
+                                    double2 *__restrict__ V, double2 *__restrict__ K, double2 *__restrict__ T,
+                                    double2 *__restrict__ D)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnear) return;
+    double2 s[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
+    for (int q = nptr[e]; q < nptr[e + 1]; ++q) {
+        const int src = nsrc[q], pid = src / 9, ab = src - 9 * pid;
+        const double2 *c = contrib + (int64_t)pid * 36 + ab;
+        for (int op = 0; op < 4; ++op) { s[op].x += c[9 * op].x; s[op].y += c[9 * op].y; }
+    }
+    const int64_t o = (int64_t)ni[e] * nv + nj[e];
+    double2 *dst[4] = {V, K, T, D};
+    for (int op = 0; op < 4; ++op) {
+        double2 x = dst[op][o];
+        x.x += s[op].x;
+        x.y += s[op].y;
+        dst[op][o] = x;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+bem_status launch_geometry(const bem_mesh *m, hipStream_t st)
+{
+    const int nt = (int)m->h.nt;
+    hipLaunchKernelGGL(geometry_kernel, dim3((nt + 255) / 256), dim3(256), 0, st, m->d.xyz.as<double>(),
+                       m->d.tri.as<int32_t>(), nt, m->d.geo.as<TriGeo>());
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+}
+
+size_t tile_scratch_bytes(const bem_mesh *m)
+{
+    const int64_t nb = m->h.nb;
+    return (size_t)(nb * (nb + 1) / 2) * 4 * SMAX * SMAX * sizeof(double2);
+}
+
+bem_status launch_regular(const bem_mesh *m, double k, double2 *scratch, double2 *ops[4], hipStream_t st)
+{
+    TileArgs A;
+    A.geo = m->d.geo.as<TriGeo>();
+    A.tri = m->d.tri.as<int32_t>();
+    A.blk_start = m->d.blk_start.as<int32_t>();
+    A.blk_nslot = m->d.blk_nslot.as<int32_t>();
+    A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
+    A.slot_ent = m->d.slot_ent.as<uint8_t>();
+    A.nb = m->h.nb;
+    A.k = k;
+    A.scratch = scratch;
+    const int64_t ntiles = (int64_t)A.nb * (A.nb + 1) / 2;
+    const int64_t chunk = 1 << 20;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
+        const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
+        hipLaunchKernelGGL(regular_tiles_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+        BEM_HIP(hipGetLastError());
+    }
+    const int nv = (int)m->h.nv;
+    hipLaunchKernelGGL(gather_tiles_kernel, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, A.nb,
+                       m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(), scratch, ops[0], ops[1], ops[2],
+                       ops[3]);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+}
+
+bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw,
+                           double2 *contrib, double2 *ops[4], hipStream_t st)
+{
+    GLTab gl;
+    for (int i = 0; i < NG_MAX; ++i) { gl.x[i] = i < ng ? glx[i] : 0.0; gl.w[i] = i < ng ? glw[i] : 0.0; }
+    const int np = (int)m->h.sing.size();
+    if (np > 0) {
+        hipLaunchKernelGGL(singular_pairs_kernel, dim3((np + 15) / 16), dim3(256), 0, st, m->d.geo.as<TriGeo>(),
+                           m->d.sing.as<SingPair>(), np, ng, gl, k, contrib);
+        BEM_HIP(hipGetLastError());
+    }
+    const int nn = (int)m->h.near_i.size();
+    if (nn > 0) {
+        hipLaunchKernelGGL(near_scatter_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, (int)m->h.nv, nn,
+                           m->d.near_i.as<int32_t>(), m->d.near_j.as<int32_t>(), m->d.near_ptr.as<int32_t>(),
+                           m->d.near_src.as<int32_t>(), m->d.sing.as<SingPair>(), contrib, ops[0], ops[1], ops[2],
+                           ops[3]);
+        BEM_HIP(hipGetLastError());
+    }
+    return BEM_OK;
+}
+
+}  // namespace bemtx

@@ -1,0 +1,140 @@
+// Private declarations of the bemtx library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bemtx.h"
+
+namespace bemtx {
+
+// ---------------------------------------------------------------- layout
+// Triangles are grouped into locality blocks of at most BT consecutive
+// triangles (Morton order of centroids) touching at most SMAX distinct
+// vertices; a vertex appears in at most LMAX corners of one block.
+constexpr int BT = 16;
+constexpr int SMAX = 24;
+constexpr int LMAX = 12;
+constexpr int NG_MAX = 16;
+
+// Per-triangle geometry table, built on the device (40 doubles, 320 B).
+struct alignas(16) TriGeo {
+    double p[3][3];     // vertices in the triangle's own corner order
+    double qp[6][3];    // points of the 6-point rule
+    double n[3];        // unit normal (right-hand rule, outward)
+    double area;
+    double curl[3][3];  // surface curl of the P1 function of corner a
+};
+
+// Ordered singular pair: x on `tau` (test), y on `sig` (trial); kind = shared
+// vertices (3 coincident, 2 edge, 1 vertex); perms map reference vertex r to
+// the triangle's own corner.
+struct SingPair {
+    int32_t tau, sig;
+    int32_t kind;
+    int32_t perm;   // px0 | px1<<2 | px2<<4 | py0<<6 | py1<<8 | py2<<10
+};
+
+// Device allocation tracked against the context budget.
+struct DevMem {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    bem_ctx *ctx = nullptr;
+    DevMem() = default;
+    DevMem(const DevMem &) = delete;
+    DevMem &operator=(const DevMem &) = delete;
+    ~DevMem();
+    void release();
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Host-side mesh tables (internal numbering) and their device copies.
+struct MeshData {
+    int64_t nv = 0, nt = 0;
+    std::vector<double> xyz_user;      // caller numbering
+    std::vector<int32_t> tri_user;
+    std::vector<int32_t> v_of_int;     // internal vertex -> caller vertex
+    std::vector<int32_t> int_of_v;     // caller vertex -> internal vertex
+    std::vector<double> xyz;           // internal numbering [nv][3]
+    std::vector<int32_t> tri;          // internal triangles, internal vertex ids [nt][3]
+    // blocks
+    int32_t nb = 0;
+    std::vector<int32_t> blk_start;    // [nb+1]
+    std::vector<int32_t> blk_nslot;    // [nb]
+    std::vector<int32_t> blk_slots;    // [nb][SMAX] internal vertex ids
+    std::vector<uint8_t> slot_cnt;     // [nb][SMAX]
+    std::vector<uint8_t> slot_ent;     // [nb][SMAX][LMAX] = tlocal*3 + corner
+    std::vector<int32_t> memb_ptr;     // [nv+1]
+    std::vector<int32_t> memb;         // block<<8 | slot
+    // singular pairs and near-field scatter lists
+    std::vector<SingPair> sing;        // sorted by kind (3, 2, 1)
+    int32_t nsing_kind[4] = {0, 0, 0, 0};
+    std::vector<int32_t> near_i, near_j, near_ptr, near_src;   // src = pair*9 + a*3 + b
+    // vertex star (RHS gather): triangle*3 + corner
+    std::vector<int32_t> star_ptr, star_ent;
+    double area_total = 0.0;
+};
+
+struct MeshDev {
+    DevMem perm;   // caller vertex -> internal vertex (int32)
+    DevMem xyz, tri, blk_start, blk_nslot, slot_cnt, slot_ent, memb_ptr, memb, sing, near_i, near_j,
+        near_ptr, near_src, star_ptr, star_ent, geo;
+};
+
+// CSR in internal numbering
+struct Csr {
+    int64_t nrows = 0, ncols = 0;
+    std::vector<int32_t> ptr, col;
+    std::vector<double> val;
+};
+
+bem_status set_error(bem_status code, const std::string &msg);
+bem_status hip_error(hipError_t e, const char *what);
+#define BEM_HIP(call)                                                     \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) return ::bemtx::hip_error(e_, #call);       \
+    } while (0)
+
+bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes);
+bem_status mesh_prepare(MeshData &m);                    // validation + tables (host)
+void mass_csr(const MeshData &m, Csr &M);
+bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *coverage_defect);
+void transpose_csr(const Csr &A, Csr &At);
+void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue method
+
+}  // namespace bemtx
+
+struct bem_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    size_t in_use = 0;
+};
+
+struct bem_mesh {
+    bem_ctx *ctx = nullptr;
+    bemtx::MeshData h;
+    bemtx::MeshDev d;
+};
+
+struct bem_problem {
+    bem_ctx *ctx = nullptr;
+    const bem_mesh *ext = nullptr, *inte = nullptr;
+    double k_ext = 0, k_int = 0, rho_ext = 1, rho_int = 1;
+    bem_precision prec = BEM_C128;
+    int ng = 4;
+    double gl_x[bemtx::NG_MAX], gl_w[bemtx::NG_MAX];
+    bool ops_ready = false, proj_ready = false;
+    // dense operators, internal numbering: [mesh][op] N x N complex (op order V, K, T, D)
+    bemtx::DevMem ops[2][4];
+    // sparse couplings and masses
+    bemtx::Csr M[2], P_ie, P_ei;
+    bemtx::DevMem P_ie_ptr, P_ie_col, P_ie_val, P_ei_ptr, P_ei_col, P_ei_val;
+    bemtx::DevMem Minv[2];          // dense real inverse mass matrices (FP64)
+    bemtx::DevMem M_ptr[2], M_col[2], M_val[2];
+    double t_geometry_ms = 0, t_regular_ms = 0, t_singular_ms = 0, t_projection_ms = 0;
+};

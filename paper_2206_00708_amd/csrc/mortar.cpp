@@ -1,0 +1,306 @@
+// Mass matrices, the L2 mortar matrix between the two meshes (Sec. 3.1), and
+// the Gauss-Legendre rule of the singular quadrature.  Host code: integer
+// connectivity, clipping and O(N) sparse work that the paper reports at a few
+// percent of the assembly time (Sec. 5.4).
+//
+// Mortar matrix: P_int,ext[i][j] = <theta_i, phi_j>_L2 with theta_i the P1
+// function of interior vertex i and phi_j that of exterior vertex j.  For the
+// curved (star-shaped) surfaces used here the two polyhedra differ; an
+// interior triangle is carried onto the plane of an exterior facet by central
+// projection of its vertices from the origin, theta_i is interpolated
+// linearly on the projected triangle, and the product is integrated exactly
+// over the convex intersection polygon.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "internal.h"
+
+namespace bemtx {
+
+void mass_csr(const MeshData &m, Csr &M)
+{
+    const int64_t nv = m.nv, nt = m.nt;
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(nv);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t *v = &m.tri[3 * t];
+        const double *p0 = &m.xyz[3 * v[0]], *p1 = &m.xyz[3 * v[1]], *p2 = &m.xyz[3 * v[2]];
+        double a[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+        double b[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+        double c[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+        double area = 0.5 * std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) rows[v[i]].push_back({v[j], area * (i == j ? 2.0 : 1.0) / 12.0});
+    }
+    M.nrows = M.ncols = nv;
+    M.ptr.assign(nv + 1, 0);
+    M.col.clear();
+    M.val.clear();
+    for (int64_t i = 0; i < nv; ++i) {
+        auto &r = rows[i];
+        std::stable_sort(r.begin(), r.end(), [](auto &x, auto &y) { return x.first < y.first; });
+        for (size_t q = 0; q < r.size(); ++q) {
+            if (q > 0 && r[q].first == r[q - 1].first) {
+                M.val.back() += r[q].second;
+            } else {
+                M.col.push_back(r[q].first);
+                M.val.push_back(r[q].second);
+            }
+        }
+        M.ptr[i + 1] = (int32_t)M.col.size();
+    }
+}
+
+void transpose_csr(const Csr &A, Csr &At)
+{
+    At.nrows = A.ncols;
+    At.ncols = A.nrows;
+    At.ptr.assign(At.nrows + 1, 0);
+    for (int32_t c : A.col) At.ptr[c + 1]++;
+    for (int64_t i = 0; i < At.nrows; ++i) At.ptr[i + 1] += At.ptr[i];
+    At.col.assign(A.col.size(), 0);
+    At.val.assign(A.val.size(), 0.0);
+    std::vector<int32_t> fill(At.ptr.begin(), At.ptr.end() - 1);
+    for (int64_t r = 0; r < A.nrows; ++r)
+        for (int32_t q = A.ptr[r]; q < A.ptr[r + 1]; ++q) {
+            int32_t d = fill[A.col[q]]++;
+            At.col[d] = (int32_t)r;
+            At.val[d] = A.val[q];
+        }
+}
+
+namespace {
+
+struct V2 { double x, y; };
+inline double orient(V2 a, V2 b, V2 c) { return (b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x); }
+
+// Keep the part of convex polygon `in` on the left of the directed line a->b;
+// boundary points (within tol) are kept.
+int keep_left(const V2 *in, int n, V2 a, V2 b, double tol, V2 *out)
+{
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        V2 cur = in[i], nxt = in[(i + 1) % n];
+        double sc = orient(a, b, cur), sn = orient(a, b, nxt);
+        bool ic = sc >= -tol, inn = sn >= -tol;
+        if (ic) out[m++] = cur;
+        if (ic != inn) {
+            double s = sc / (sc - sn);
+            out[m++] = {cur.x + s * (nxt.x - cur.x), cur.y + s * (nxt.y - cur.y)};
+        }
+    }
+    return m;
+}
+
+struct Facet {
+    double o[3], e1[3], e2[3], n[3];
+    V2 v[3];
+    double area;
+};
+
+inline double dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+Facet make_facet(const double *p0, const double *p1, const double *p2)
+{
+    Facet f;
+    double a[3], b[3];
+    for (int c = 0; c < 3; ++c) { a[c] = p1[c] - p0[c]; b[c] = p2[c] - p0[c]; f.o[c] = p0[c]; }
+    double nn[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    double ln = std::sqrt(dot(nn, nn)), la = std::sqrt(dot(a, a));
+    for (int c = 0; c < 3; ++c) { f.n[c] = nn[c] / ln; f.e1[c] = a[c] / la; }
+    f.e2[0] = f.n[1] * f.e1[2] - f.n[2] * f.e1[1];
+    f.e2[1] = f.n[2] * f.e1[0] - f.n[0] * f.e1[2];
+    f.e2[2] = f.n[0] * f.e1[1] - f.n[1] * f.e1[0];
+    f.area = 0.5 * ln;
+    const double *P[3] = {p0, p1, p2};
+    for (int k = 0; k < 3; ++k) {
+        double d[3] = {P[k][0] - p0[0], P[k][1] - p0[1], P[k][2] - p0[2]};
+        f.v[k] = {dot(d, f.e1), dot(d, f.e2)};
+    }
+    return f;
+}
+
+// barycentric coordinates of q in triangle (a, b, c)
+inline void bary(V2 a, V2 b, V2 c, V2 q, double *l)
+{
+    double det = orient(a, b, c);
+    l[1] = orient(a, q, c) / det;
+    l[2] = orient(a, b, q) / det;
+    l[0] = 1.0 - l[1] - l[2];
+}
+
+}  // namespace
+
+bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *coverage_defect)
+{
+    const int64_t nti = mi.nt, nte = me.nt;
+    // cone of each triangle seen from the origin: centre direction and chord radius
+    auto cones = [](const MeshData &m, std::vector<double> &c, std::vector<double> &r) {
+        c.assign(3 * m.nt, 0.0);
+        r.assign(m.nt, 0.0);
+        for (int64_t t = 0; t < m.nt; ++t) {
+            double u[3][3], s[3] = {0, 0, 0};
+            for (int a = 0; a < 3; ++a) {
+                const double *p = &m.xyz[3 * m.tri[3 * t + a]];
+                double l = std::sqrt(dot(p, p));
+                for (int k = 0; k < 3; ++k) { u[a][k] = p[k] / l; s[k] += u[a][k]; }
+            }
+            double ls = std::sqrt(dot(s, s));
+            for (int k = 0; k < 3; ++k) c[3 * t + k] = s[k] / ls;
+            for (int a = 0; a < 3; ++a) {
+                double d2 = 0;
+                for (int k = 0; k < 3; ++k) d2 += (u[a][k] - c[3 * t + k]) * (u[a][k] - c[3 * t + k]);
+                r[t] = std::max(r[t], std::sqrt(d2));
+            }
+        }
+    };
+    std::vector<double> ci, ri, ce, re;
+    cones(mi, ci, ri);
+    cones(me, ce, re);
+    double rmax_i = *std::max_element(ri.begin(), ri.end()), rmax_e = *std::max_element(re.begin(), re.end());
+    double cell = 1.05 * (rmax_i + rmax_e) + 1e-12;
+    int ncell = std::max(1, std::min(256, (int)std::floor(2.0 / cell)));
+    double h = 2.0 / ncell;
+    auto cidx = [&](double x) { return std::min(ncell - 1, std::max(0, (int)std::floor((x + 1.0) / h))); };
+    std::vector<std::vector<int32_t>> grid((size_t)ncell * ncell * ncell);
+    for (int64_t t = 0; t < nti; ++t)
+        grid[((size_t)cidx(ci[3 * t]) * ncell + cidx(ci[3 * t + 1])) * ncell + cidx(ci[3 * t + 2])].push_back((int32_t)t);
+
+    std::vector<std::map<int32_t, double>> rows(mi.nv);
+    double worst = 0.0;
+    for (int64_t te = 0; te < nte; ++te) {
+        const int32_t *ve = &me.tri[3 * te];
+        Facet F = make_facet(&me.xyz[3 * ve[0]], &me.xyz[3 * ve[1]], &me.xyz[3 * ve[2]]);
+        double scale = std::fabs(F.v[1].x) + std::fabs(F.v[2].x) + std::fabs(F.v[2].y);
+        double tol = 1e-12 * scale * scale;
+        double plane = dot(F.n, F.o);
+        double covered = 0.0;
+        int gx = cidx(ce[3 * te]), gy = cidx(ce[3 * te + 1]), gz = cidx(ce[3 * te + 2]);
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    int x = gx + dx, y = gy + dy, z = gz + dz;
+                    if (x < 0 || y < 0 || z < 0 || x >= ncell || y >= ncell || z >= ncell) continue;
+                    for (int32_t ti : grid[((size_t)x * ncell + y) * ncell + z]) {
+                        double d2 = 0;
+                        for (int k = 0; k < 3; ++k) d2 += (ci[3 * ti + k] - ce[3 * te + k]) * (ci[3 * ti + k] - ce[3 * te + k]);
+                        if (std::sqrt(d2) > (ri[ti] + re[te]) * 1.0001 + 1e-12) continue;
+                        const int32_t *vi = &mi.tri[3 * ti];
+                        V2 S[3];
+                        bool ok = true;
+                        for (int a = 0; a < 3; ++a) {
+                            const double *p = &mi.xyz[3 * vi[a]];
+                            double den = dot(F.n, p);
+                            if (!(den > 0.0)) { ok = false; break; }
+                            double s = plane / den;
+                            double q[3] = {s * p[0] - F.o[0], s * p[1] - F.o[1], s * p[2] - F.o[2]};
+                            S[a] = {dot(q, F.e1), dot(q, F.e2)};
+                        }
+                        if (!ok || orient(S[0], S[1], S[2]) <= 0.0) continue;
+                        // exterior facet clipped by the three edges of the projected interior triangle
+                        V2 poly[12], tmp[12];
+                        int n = 3;
+                        for (int a = 0; a < 3; ++a) poly[a] = F.v[a];
+                        for (int a = 0; a < 3 && n >= 3; ++a) {
+                            n = keep_left(poly, n, S[a], S[(a + 1) % 3], tol, tmp);
+                            std::memcpy(poly, tmp, n * sizeof(V2));
+                        }
+                        if (n < 3) continue;
+                        double apoly = 0.0;
+                        for (int k = 1; k + 1 < n; ++k) apoly += 0.5 * orient(poly[0], poly[k], poly[k + 1]);
+                        if (apoly < 1e-14 * F.area) continue;
+                        covered += apoly;
+                        double blk[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+                        for (int k = 1; k + 1 < n; ++k) {
+                            V2 A = poly[0], B = poly[k], C = poly[k + 1];
+                            double at = 0.5 * orient(A, B, C);
+                            // 3-point interior rule, exact for quadratics
+                            const double w1 = 2.0 / 3.0, w2 = 1.0 / 6.0;
+                            const double L[3][3] = {{w1, w2, w2}, {w2, w1, w2}, {w2, w2, w1}};
+                            for (int g = 0; g < 3; ++g) {
+                                V2 q = {L[g][0] * A.x + L[g][1] * B.x + L[g][2] * C.x,
+                                        L[g][0] * A.y + L[g][1] * B.y + L[g][2] * C.y};
+                                double li[3], le[3];
+                                bary(S[0], S[1], S[2], q, li);
+                                bary(F.v[0], F.v[1], F.v[2], q, le);
+                                for (int a = 0; a < 3; ++a)
+                                    for (int b = 0; b < 3; ++b) blk[a][b] += at / 3.0 * li[a] * le[b];
+                            }
+                        }
+                        for (int a = 0; a < 3; ++a)
+                            for (int b = 0; b < 3; ++b) rows[vi[a]][ve[b]] += blk[a][b];
+                    }
+                }
+        worst = std::max(worst, std::fabs(covered - F.area) / F.area);
+    }
+    if (coverage_defect) *coverage_defect = worst;
+    P.nrows = mi.nv;
+    P.ncols = me.nv;
+    P.ptr.assign(mi.nv + 1, 0);
+    P.col.clear();
+    P.val.clear();
+    for (int64_t i = 0; i < mi.nv; ++i) {
+        for (auto &kv : rows[i]) {
+            P.col.push_back(kv.first);
+            P.val.push_back(kv.second);
+        }
+        P.ptr[i + 1] = (int32_t)P.col.size();
+    }
+    if (worst > 1e-6)
+        return set_error(BEM_E_MESH_MISMATCH, "projected interior mesh leaves an exterior facet uncovered (relative defect " +
+                                                  std::to_string(worst) + ")");
+    return BEM_OK;
+}
+
+// Gauss-Legendre nodes and weights on [0,1] from the eigen-decomposition of
+// the symmetric tridiagonal Jacobi matrix of the Legendre recurrence
+// (Golub-Welsch), computed with cyclic Jacobi rotations.
+void gauss_legendre01(int n, double *x, double *w)
+{
+    std::vector<double> A((size_t)n * n, 0.0), Q((size_t)n * n, 0.0);
+    for (int k = 1; k < n; ++k) {
+        double b = k / std::sqrt(4.0 * k * k - 1.0);
+        A[(size_t)(k - 1) * n + k] = A[(size_t)k * n + k - 1] = b;
+    }
+    for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += A[(size_t)p * n + q] * A[(size_t)p * n + q];
+        if (off < 1e-34) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                double theta = (aqq - app) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - s * akq;
+                    A[(size_t)k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - s * aqk;
+                    A[(size_t)q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double qkp = Q[(size_t)k * n + p], qkq = Q[(size_t)k * n + q];
+                    Q[(size_t)k * n + p] = c * qkp - s * qkq;
+                    Q[(size_t)k * n + q] = s * qkp + c * qkq;
+                }
+            }
+    }
+    std::vector<std::pair<double, double>> nw(n);
+    for (int i = 0; i < n; ++i) nw[i] = {A[(size_t)i * n + i], Q[i] * Q[i]};   // first component of eigenvector i
+    std::sort(nw.begin(), nw.end());
+    for (int i = 0; i < n; ++i) {
+        x[i] = 0.5 * (nw[i].first + 1.0);
+        w[i] = nw[i].second;     // (2 * q0^2) on [-1,1], halved on [0,1]
+    }
+}
+
+}  // namespace bemtx
