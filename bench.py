@@ -1,14 +1,20 @@
 """Benchmark of the nonconforming multiple-traces BEM hot path on one MI355X.
 
-One step = one pass of the whole path on the FP64 workload "sphere-ico4/fib2002"
-(unit sphere; exterior icosphere level 4, 5120 triangles / 2562 nodes;
-interior independent Fibonacci grid 4000 triangles / 2002 nodes, rotated and
-jittered 2 %; k_ext 5, k_int 8, rho_int/rho_ext 1.5; one plane wave; GMRES
-tol 1e-6): mesh tables, dense V/K/T/D on both meshes (regular + singular
-quadrature), mass and mortar matrices, dense inverse masses, load vector,
-unrestarted GMRES on the mass-preconditioned system, traces back to the host
-numbering.  value = dense entries assembled (4 N_e^2 + 4 N_i^2 per step) per
-second of whole-step wall time (Gentries/s).
+One step = one pass of the whole path on the FP64 workload
+"sphere-ico4/fib2002": unit sphere; exterior icosphere level 4 (5120
+triangles, 2562 nodes); interior independent Fibonacci grid (4000 triangles,
+2002 nodes), rotated and jittered 2 %; k_ext 5, k_int 8, rho_int/rho_ext 1.5;
+one plane wave; GMRES tol 1e-6.  The step covers mesh tables, dense
+V/K/T/D on both meshes (regular + singular quadrature), mass and mortar
+matrices and dense inverse masses, the load vector, unrestarted GMRES on the
+mass-preconditioned system and the traces back in the caller's numbering.
+
+value = dense entries assembled (4 N_e^2 + 4 N_i^2 per step) per second of
+whole-step wall time, in Gentries/s.  The line also carries assembly-only
+Gentries/s, solves/s, p50/p99 step latency, a per-phase breakdown, the
+roofline of the dominant kernel (timed with HIP events on the library's
+stream during the timed steps) and the FP64 CPU oracle timed on a bounded
+sample of the same operators.
 """
 import argparse
 import json
@@ -20,8 +26,44 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
-FP64_VEC_TFLOPS = 78.6       # MI355X FP64 vector
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+FP64_VEC_TFLOPS = 78.6       # MI355X FP64 vector, TFLOP/s
+
+# Algorithmic FP64 work per quadrature point pair of the regular kernel,
+# counting a fused multiply-add as two flops (as the vector peak does):
+# difference and squared distance 8, 1/r and r 2, phase k r 1, reduction by
+# pi/2 and the sin/cos polynomials 46, exp(ikr)/r 2, its radial derivative 7,
+# the two normal projections 10 and their products 4, accumulation of the
+# three 3-vectors of partial sums and of sum G 40, and the share of the
+# per-row contraction 19.
+FLOP_PER_POINT_PAIR = 139
+
+
+def cpu_oracle_baseline(c, budget_s=15.0):
+    """FP64 oracle assembly throughput on a bounded row sample of the same
+    operators (both meshes), in Gentries/s; rows grow until ~budget_s."""
+    import numpy as np
+    from oracle import oracle as O
+    O.lib()
+    rng = np.random.default_rng(0)
+    (xe, te), (xi, ti) = c["ext"], c["int"]
+    rows_e, rows_i = 8, 6
+    while True:
+        re_ = rng.choice(len(xe), rows_e, replace=False)
+        ri_ = rng.choice(len(xi), rows_i, replace=False)
+        t0 = time.perf_counter()
+        O.assemble(xe, te, c["k_ext"], rows=re_)
+        O.assemble(xi, ti, c["k_int"], rows=ri_)
+        dt = time.perf_counter() - t0
+        if dt > budget_s / 4 or rows_e > 4000:
+            break
+        scale = max(2.0, min(8.0, budget_s / max(dt, 1e-3) / 2))
+        rows_e, rows_i = int(rows_e * scale), int(rows_i * scale)
+    entries = 4 * (rows_e * len(xe) + rows_i * len(xi))
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(entries / dt / 1e9, 6), "unit": "Gentries/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle V/K/T/D rows: {rows_e} of {len(xe)} exterior + {rows_i} of {len(xi)} interior "
+                      f"({entries} entries, {dt:.1f} s)"}
 
 
 def main():
@@ -33,7 +75,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU row sharding is a design note, not implemented", file=sys.stderr)
+              "multi-GPU sharding of the operators is a design note, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -48,35 +90,60 @@ def main():
     entries = 4 * ne * ne + 4 * ni * ni
     torch.cuda.init()
     ctx = B.Context(0)
-    stream = ctx.stream
 
-    def step():
+    def step(ph):
+        t = time.perf_counter()
         me, mi = B.Mesh(ctx, xe, te), B.Mesh(ctx, xi, ti)
         p = B.Problem(ctx, me, mi, c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
-        t0 = time.perf_counter()
+        t1 = time.perf_counter()
         p.assemble_operators()
-        torch.cuda.synchronize()
-        t_asm = time.perf_counter() - t0
+        t2 = time.perf_counter()
         p.assemble_projection()
-        out, stats, code = p.solve(c["dirs"], tol=c["tol"], maxit=3000)
+        t3 = time.perf_counter()
+        out, stats, code = p.solve(c["dirs"], tol=c["tol"], maxit=2000)
         x = out.cpu().numpy()
-        return p, x, stats, code, t_asm
+        t4 = time.perf_counter()
+        for k, v in (("mesh_problem", t1 - t), ("operators", t2 - t1), ("projection", t3 - t2), ("solve", t4 - t3)):
+            ph.setdefault(k, []).append(v)
+        assert code == B.OK, stats
+        return x, stats
 
     for _ in range(args.warmup):
-        step()
+        step({})
     torch.cuda.synchronize()
-    lat, asm, iters = [], [], []
+    timed = ("regular_tiles", "mtf_dense")
+    ctx.set_kernel_timing(timed)
+    phases, lat, iters = {}, [], []
     t_start = time.perf_counter()
     for _ in range(args.steps):
         t0 = time.perf_counter()
-        p, x, stats, code, t_asm = step()
-        torch.cuda.synchronize()
+        x, stats = step(phases)
         lat.append(time.perf_counter() - t0)
-        asm.append(t_asm)
         iters.append(stats["iterations"])
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
 
+    ktimes = {k: ctx.kernel_time(k) for k in timed}
+    ctx.set_kernel_timing(())
+    dominant = max(ktimes, key=lambda k: ktimes[k][0])
+    # algorithmic work per launch
+    mv_bytes = 64.0 * (ne * ne + ni * ni)                          # V, K, T, D complex128 on both meshes
+    pairs = 0.5 * (len(te) ** 2 + len(ti) ** 2)                    # unordered triangle pairs per step
+    reg_flops = pairs * 36 * FLOP_PER_POINT_PAIR
+    if dominant == "mtf_dense":
+        ms, n = ktimes["mtf_dense"]
+        ach = mv_bytes / (ms / n * 1e-3) / 1e9
+        roof = {"kernel": "mtf_dense", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(1e3 * ms / n, 2), "bytes_per_launch": mv_bytes}
+    else:
+        ms, n = ktimes["regular_tiles"]
+        per_step = ms / args.steps
+        ach = reg_flops / (per_step * 1e-3) / 1e12
+        roof = {"kernel": "regular_tiles", "bound": "alu", "achieved": round(ach, 2), "peak": FP64_VEC_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP64_VEC_TFLOPS, 4), "traffic": None,
+                "avg_launch_us": round(1e3 * ms / n, 2), "flop_per_step": reg_flops}
+    med = {k: round(1e3 * statistics.median(v), 3) for k, v in phases.items()}
     value = entries * args.steps / total / 1e9
     line = {
         "metric": "dense BEM assembly Gentries/s; solves/s vs plain FP64 at 1e-5 err; p99 latency",
@@ -93,19 +160,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sphere-ico4/fib2002 MTF, FP64, 1 plane wave, GMRES tol 1e-6",
                    "n_ext": ne, "n_int": ni, "k_ext": c["k_ext"], "k_int": c["k_int"],
-                   "rho_ratio": c["rho_int"] / c["rho_ext"], "parallelism": "single GPU"},
-        "assembly_gentries_per_s": round(entries / statistics.median(asm) / 1e9, 3),
+                   "rho_ratio": c["rho_int"] / c["rho_ext"]},
+        "roofline": roof,
+        "assembly_gentries_per_s": round(entries / (med["operators"] * 1e-3) / 1e9, 3),
         "solves_per_s": round(args.steps / total, 3),
         "p50_ms": round(1e3 * statistics.median(lat), 3),
         "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3),
+        "phase_ms": med,
         "gmres_iterations": int(statistics.median(iters)),
-        "t_regular_ms": round(stats["t_regular_ms"], 3),
-        "t_singular_ms": round(stats["t_singular_ms"], 3),
-        "t_projection_ms": round(stats["t_projection_ms"], 3),
-        "t_solve_ms": round(stats["t_solve_ms"], 3),
-        "t_iter_ms": round(stats["t_iter_ms"], 4),
         "rel_residual": stats["rel_residual"],
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in ktimes.items()},
     }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_oracle_baseline(c)
     print(json.dumps(line), flush=True)
 
 

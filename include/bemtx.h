@@ -79,7 +79,7 @@ typedef struct {
 
 typedef struct {
     double tol;               /* relative residual of the strong form, ||M^-1(b - A x)|| / ||M^-1 b|| */
-    int32_t maxit;            /* Arnoldi steps (no restart, Sec. 5.1), 1..4000 */
+    int32_t maxit;            /* Arnoldi steps (no restart, Sec. 5.1), 1..3000 */
     int32_t ir_max;           /* BEM_C64_MIXED: outer refinement steps */
     double ir_inner_tol;      /* BEM_C64_MIXED: inner GMRES tolerance */
 } bem_solver_opts;
@@ -110,6 +110,18 @@ bem_status bem_ctx_create(int32_t device, void *hip_stream, size_t hbm_budget_by
 void bem_ctx_destroy(bem_ctx *ctx);
 /* Device bytes currently held by problems of the context. */
 size_t bem_ctx_bytes_in_use(const bem_ctx *ctx);
+
+/* Per-kernel device time.  Kernels, by bit index: 0 "regular_tiles",
+ * 1 "gather_tiles", 2 "singular_pairs", 3 "near_scatter", 4 "mtf_dense",
+ * 5 "mass_apply", 6 "cgs_dots", 7 "cgs_update", 8 "arnoldi_finish",
+ * 9 "mass_inverse".  Every launch of a kernel whose bit is set in
+ * kernel_mask is bracketed by HIP events on the context stream (a few
+ * microseconds of overhead per launch); 0 disables.  Setting the mask resets
+ * the totals.  bem_ctx_kernel_time synchronises the stream and returns the
+ * accumulated milliseconds and launch count of one kernel by name
+ * (BEM_E_ARG for an unknown name). */
+bem_status bem_ctx_set_kernel_timing(bem_ctx *ctx, uint32_t kernel_mask);
+bem_status bem_ctx_kernel_time(bem_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
 
 /* A triangle mesh Gamma_int or Gamma_ext (Sec. 3): checks that it is a closed,
  * consistently oriented 2-manifold with positive enclosed volume, no
@@ -198,6 +210,11 @@ bem_status bem_check_mesh(const double *xyz, int64_t nv, const int32_t *tri, int
 bem_status bem_host_mortar(const double *xyz_int, int64_t nv_int, const int32_t *tri_int, int64_t nt_int,
                            const double *xyz_ext, int64_t nv_ext, const int32_t *tri_ext, int64_t nt_ext,
                            int64_t *rowptr, int32_t *col, double *val, int64_t *nnz, double *coverage_defect);
+
+/* The FP64 sine and cosine the kernels use for the phase k|x-y| (Cody-Waite
+ * reduction by pi/2, Taylor polynomials on [-pi/4, pi/4]), on host arrays of
+ * n values; same arithmetic as the device code. */
+bem_status bem_host_phase_sincos(int64_t n, const double *x, double *s, double *c);
 
 /* n-point Gauss-Legendre rule on [0,1] used by the singular quadrature
  * (1 <= n <= 16). */

@@ -34,6 +34,8 @@ SIGNATURES = {
     "bem_ctx_create": (c_status, [i32, vp, sz, ctypes.POINTER(vp)]),
     "bem_ctx_destroy": (None, [vp]),
     "bem_ctx_bytes_in_use": (sz, [vp]),
+    "bem_ctx_set_kernel_timing": (c_status, [vp, ctypes.c_uint32]),
+    "bem_ctx_kernel_time": (c_status, [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(i64)]),
     "bem_mesh_create": (c_status, [vp, vp, i64, vp, i64, ctypes.POINTER(vp)]),
     "bem_mesh_destroy": (None, [vp]),
     "bem_mesh_num_vertices": (i64, [vp]),
@@ -52,6 +54,7 @@ SIGNATURES = {
     "bem_host_mortar": (c_status, [vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, vp, ctypes.POINTER(i64),
                                    ctypes.POINTER(f64)]),
     "bem_host_gauss_legendre": (c_status, [i32, vp, vp]),
+    "bem_host_phase_sincos": (c_status, [i64, vp, vp, vp]),
 }
 
 _lib = None

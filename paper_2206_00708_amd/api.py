@@ -45,6 +45,22 @@ class Context:
     def bytes_in_use(self):
         return N.load().bem_ctx_bytes_in_use(self._h)
 
+    KERNELS = ("regular_tiles", "gather_tiles", "singular_pairs", "near_scatter", "mtf_dense", "mass_apply",
+               "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse")
+
+    def set_kernel_timing(self, kernels=()):
+        """Time every launch of the named kernels with HIP events (empty: off)."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << self.KERNELS.index(k)
+        _check(N.load().bem_ctx_set_kernel_timing(self._h, mask))
+
+    def kernel_time(self, name):
+        """(total milliseconds, launches) of one kernel since timing was enabled."""
+        ms = ctypes.c_double(); n = ctypes.c_int64()
+        _check(N.load().bem_ctx_kernel_time(self._h, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def close(self):
         if getattr(self, "_h", None):
             N.load().bem_ctx_destroy(self._h)
@@ -178,3 +194,11 @@ def host_gauss_legendre(n):
     x = np.zeros(n); w = np.zeros(n)
     _check(N.load().bem_host_gauss_legendre(n, x.ctypes.data, w.ctypes.data))
     return x, w
+
+
+def host_phase_sincos(x):
+    """bem_host_phase_sincos: the kernels' sin/cos of the phase, on the host."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    s = np.zeros_like(x); c = np.zeros_like(x)
+    _check(N.load().bem_host_phase_sincos(x.size, x.ctypes.data, s.ctypes.data, c.ctypes.data))
+    return s, c

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "internal.h"
+#include "phase.h"
 
 namespace bemtx {
 
@@ -78,6 +79,51 @@ bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_m
 bem_status rhs_impl(bem_problem *p, const double *dirs, int nrhs, void *b, bem_memspace space);
 bem_status permute_matrix_out(const bem_problem *p, int mesh, const double2 *src, double2 *dst);
 
+const char *const kKernelNames[K_COUNT] = {"regular_tiles", "gather_tiles", "singular_pairs", "near_scatter",
+                                           "mtf_dense", "mass_apply", "cgs_dots", "cgs_update", "arnoldi_finish",
+                                           "mass_inverse"};
+
+static hipEvent_t take_event(bem_ctx *c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+KTimer::KTimer(bem_ctx *ctx, int kid) : c(ctx), id(kid)
+{
+    if (!c || !(c->ktiming >> kid & 1u)) return;
+    a = take_event(c);
+    b = take_event(c);
+    if (a && b) (void)hipEventRecord(a, c->stream);
+}
+
+KTimer::~KTimer()
+{
+    if (!a || !b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({id, a, b});
+}
+
+void flush_kernel_timing(bem_ctx *c)
+{
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            c->ktotal_ms[p.id] += ms;
+            c->kcount[p.id] += 1;
+        }
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
+}
+
 static double ms_since(std::chrono::steady_clock::time_point t0)
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -110,7 +156,39 @@ bem_status bem_ctx_create(int32_t device, void *hip_stream, size_t hbm_budget_by
     return BEM_OK;
 }
 
-void bem_ctx_destroy(bem_ctx *ctx) { delete ctx; }
+void bem_ctx_destroy(bem_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    delete ctx;
+}
+
+bem_status bem_ctx_set_kernel_timing(bem_ctx *ctx, uint32_t kernel_mask)
+{
+    if (!ctx) return set_error(BEM_E_ARG, "null context");
+    BEM_HIP(hipStreamSynchronize(ctx->stream));
+    flush_kernel_timing(ctx);
+    ctx->ktiming = kernel_mask & ((1u << K_COUNT) - 1u);
+    for (int k = 0; k < K_COUNT; ++k) { ctx->ktotal_ms[k] = 0.0; ctx->kcount[k] = 0; }
+    return BEM_OK;
+}
+
+bem_status bem_ctx_kernel_time(bem_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches)
+{
+    if (!ctx || !kernel || !total_ms || !launches) return set_error(BEM_E_ARG, "null argument");
+    BEM_HIP(hipStreamSynchronize(ctx->stream));
+    flush_kernel_timing(ctx);
+    for (int k = 0; k < K_COUNT; ++k)
+        if (std::strcmp(kernel, kKernelNames[k]) == 0) {
+            *total_ms = ctx->ktotal_ms[k];
+            *launches = ctx->kcount[k];
+            return BEM_OK;
+        }
+    return set_error(BEM_E_ARG, std::string("unknown kernel name ") + kernel);
+}
 
 size_t bem_ctx_bytes_in_use(const bem_ctx *ctx) { return ctx ? ctx->in_use : 0; }
 
@@ -172,6 +250,17 @@ bem_status bem_problem_create(bem_ctx *ctx, const bem_mesh *ext, const bem_mesh 
         !std::isfinite(k_int) || !std::isfinite(rho_ext) || !std::isfinite(rho_int))
         return set_error(BEM_E_ARG, "wavenumbers and densities must be positive and finite");
     if (precision != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "only BEM_C128 is available in this build");
+    for (int m = 0; m < 2; ++m) {
+        const bemtx::MeshData &h = m == 0 ? ext->h : inte->h;
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int64_t v = 0; v < h.nv; ++v)
+            for (int c = 0; c < 3; ++c) { lo[c] = std::min(lo[c], h.xyz[3 * v + c]); hi[c] = std::max(hi[c], h.xyz[3 * v + c]); }
+        const double diam = std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                      (hi[2] - lo[2]) * (hi[2] - lo[2]));
+        const double k = m == 0 ? k_ext : k_int;
+        if (!(k * diam < 0.5 * kPhaseMax))
+            return set_error(BEM_E_UNSUPPORTED, "k * diameter too large for the FP64 phase reduction (>= 5e4)");
+    }
     int ng = quad ? quad->singular_gauss : 4;
     if (ng < 1 || ng > NG_MAX) return set_error(BEM_E_ARG, "singular_gauss must be in 1..16");
     bem_problem *p = new bem_problem;
@@ -227,11 +316,22 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
             if (s) return s;
         }
     }
-    DevMem scratch;
-    {
-        bem_status s = dev_alloc(ctx, scratch, scratch_bytes);
-        if (s) return s;
+    if (ctx->scratch_bytes < scratch_bytes) {
+        if (ctx->scratch) {
+            BEM_HIP(hipStreamSynchronize(st));
+            (void)hipFree(ctx->scratch);
+            ctx->in_use -= ctx->scratch_bytes;
+            ctx->scratch = nullptr;
+            ctx->scratch_bytes = 0;
+        }
+        if (ctx->budget && ctx->in_use + scratch_bytes > ctx->budget)
+            return set_error(BEM_E_OOM, "context HBM budget exceeded by the assembly scratch");
+        hipError_t e = hipMalloc(&ctx->scratch, scratch_bytes);
+        if (e != hipSuccess) { ctx->scratch = nullptr; return hip_error(e, "hipMalloc(scratch)"); }
+        ctx->scratch_bytes = scratch_bytes;
+        ctx->in_use += scratch_bytes;
     }
+    double2 *scratch = static_cast<double2 *>(ctx->scratch);
     hipEvent_t ev[5];
     for (auto &e : ev) BEM_HIP(hipEventCreate(&e));
     BEM_HIP(hipEventRecord(ev[0], st));
@@ -242,14 +342,14 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
         const size_t nv = meshes[m]->h.nv;
         BEM_HIP(hipEventRecord(ev[1], st));
         if (parts & 1) {
-            bem_status s = launch_regular(meshes[m], ks[m], scratch.as<double2>(), ops, st);
+            bem_status s = launch_regular(meshes[m], ks[m], scratch, ops, st);
             if (s) return s;
         } else {
             for (int op = 0; op < 4; ++op) BEM_HIP(hipMemsetAsync(ops[op], 0, nv * nv * sizeof(double2), st));
         }
         BEM_HIP(hipEventRecord(ev[2], st));
         if (parts & 2) {
-            bem_status s = launch_singular(meshes[m], ks[m], p->ng, p->gl_x, p->gl_w, scratch.as<double2>(), ops, st);
+            bem_status s = launch_singular(meshes[m], ks[m], p->ng, p->gl_x, p->gl_w, scratch, ops, st);
             if (s) return s;
         }
         BEM_HIP(hipEventRecord(ev[3], st));
@@ -261,6 +361,7 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
         t_sing += b;
     }
     for (auto &e : ev) (void)hipEventDestroy(e);
+    flush_kernel_timing(ctx);
     p->t_regular_ms = t_reg;
     p->t_singular_ms = t_sing;
     p->ops_ready = true;
@@ -315,8 +416,8 @@ bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem
                      bem_memspace space, bem_stats *stats)
 {
     if (!p || !dirs || !opts || !traces || nrhs < 1) return set_error(BEM_E_ARG, "bad argument");
-    if (!(opts->tol > 0) || opts->maxit < 1 || opts->maxit > 4000)
-        return set_error(BEM_E_ARG, "tol must be > 0 and 1 <= maxit <= 4000");
+    if (!(opts->tol > 0) || opts->maxit < 1 || opts->maxit > 3000)
+        return set_error(BEM_E_ARG, "tol must be > 0 and 1 <= maxit <= 3000");
     if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
     for (int r = 0; r < nrhs; ++r) {
         double l = std::sqrt(dirs[3 * r] * dirs[3 * r] + dirs[3 * r + 1] * dirs[3 * r + 1] + dirs[3 * r + 2] * dirs[3 * r + 2]);
@@ -433,6 +534,13 @@ bem_status bem_host_mortar(const double *xyz_int, int64_t nv_int, const int32_t 
         rowptr[iu + 1] = q;
     }
     *nnz = total;
+    return BEM_OK;
+}
+
+bem_status bem_host_phase_sincos(int64_t n, const double *x, double *s, double *c)
+{
+    if (n < 0 || (n > 0 && (!x || !s || !c))) return set_error(BEM_E_ARG, "bad argument");
+    for (int64_t i = 0; i < n; ++i) phase_sincos(x[i], s + i, c + i);
     return BEM_OK;
 }
 

@@ -28,6 +28,7 @@
 #include <cmath>
 
 #include "internal.h"
+#include "phase.h"
 
 namespace bemtx {
 
@@ -85,7 +86,7 @@ struct TileArgs {
     const uint8_t *slot_ent;
     int32_t nb;
     double k;
-    double2 *scratch;      // [tile][op][SMAX*SMAX]
+    double2 *scratch;      // [tile][SMAX*SMAX][op]
 };
 
 __device__ inline void tile_of(int64_t t, int nb, int &b1, int &b2)
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
                 const double r = r2 * rinv;
                 const double kr_ = k * r;
                 double sn, cs;
-                sincos(kr_, &sn, &cs);
+                phase_sincos(kr_, &sn, &cs);
                 const double gr = cs * rinv, gi = sn * rinv;           // exp(ikr)/r
                 const double rinv2 = rinv * rinv;
                 const double fr = (-gr - gi * kr_) * rinv2;            // exp(ikr)(ikr-1)/r^3
@@ -243,7 +244,7 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
                     im += st_im[idx];
                 }
             }
-            out[op * SMAX * SMAX + e] = make_double2(re, im);
+            out[4 * e + op] = make_double2(re, im);
         }
         __syncthreads();
     }
@@ -271,13 +272,13 @@ __global__ __launch_bounds__(256) void gather_tiles_kernel(int nv, int nb, const
             const double2 *tl = scratch + tile * (4 * SMAX * SMAX);
             if (bi <= bj) {
                 const int e = si * SMAX + sj;
-                const double2 a0 = tl[e], a1 = tl[SMAX * SMAX + e], a2 = tl[2 * SMAX * SMAX + e], a3 = tl[3 * SMAX * SMAX + e];
+                const double2 a0 = tl[4 * e], a1 = tl[4 * e + 1], a2 = tl[4 * e + 2], a3 = tl[4 * e + 3];
                 v.x += a0.x; v.y += a0.y; kk.x += a1.x; kk.y += a1.y;
                 t.x += a2.x; t.y += a2.y; d.x += a3.x; d.y += a3.y;
             } else {
                 // tile of (bj, bi): test side is j; K and T swap under transposition
                 const int e = sj * SMAX + si;
-                const double2 a0 = tl[e], a1 = tl[SMAX * SMAX + e], a2 = tl[2 * SMAX * SMAX + e], a3 = tl[3 * SMAX * SMAX + e];
+                const double2 a0 = tl[4 * e], a1 = tl[4 * e + 1], a2 = tl[4 * e + 2], a3 = tl[4 * e + 3];
                 v.x += a0.x; v.y += a0.y; kk.x += a2.x; kk.y += a2.y;
                 t.x += a1.x; t.y += a1.y; d.x += a3.x; d.y += a3.y;
             }
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__
                     const double rinv = rsqrt(r2);
                     const double r = r2 * rinv, kr_ = k * r;
                     double sn, cs;
-                    sincos(kr_, &sn, &cs);
+                    phase_sincos(kr_, &sn, &cs);
                     const double gr = cs * rinv * wt, gi = sn * rinv * wt;
                     const double rinv2 = rinv * rinv;
                     const double fr = (-gr - gi * kr_) * rinv2, fi = (gr * kr_ - gi) * rinv2;
@@ -481,10 +482,12 @@ bem_status launch_regular(const bem_mesh *m, double k, double2 *scratch, double2
     const int64_t chunk = 1 << 20;
     for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
         const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
+        KTimer kt(m->ctx, K_REGULAR);
         hipLaunchKernelGGL(regular_tiles_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
         BEM_HIP(hipGetLastError());
     }
     const int nv = (int)m->h.nv;
+    KTimer kt(m->ctx, K_GATHER);
     hipLaunchKernelGGL(gather_tiles_kernel, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, A.nb,
                        m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(), scratch, ops[0], ops[1], ops[2],
                        ops[3]);
@@ -499,12 +502,14 @@ bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *gl
     for (int i = 0; i < NG_MAX; ++i) { gl.x[i] = i < ng ? glx[i] : 0.0; gl.w[i] = i < ng ? glw[i] : 0.0; }
     const int np = (int)m->h.sing.size();
     if (np > 0) {
+        KTimer kt(m->ctx, K_SINGULAR);
         hipLaunchKernelGGL(singular_pairs_kernel, dim3((np + 15) / 16), dim3(256), 0, st, m->d.geo.as<TriGeo>(),
                            m->d.sing.as<SingPair>(), np, ng, gl, k, contrib);
         BEM_HIP(hipGetLastError());
     }
     const int nn = (int)m->h.near_i.size();
     if (nn > 0) {
+        KTimer kt(m->ctx, K_NEAR);
         hipLaunchKernelGGL(near_scatter_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, (int)m->h.nv, nn,
                            m->d.near_i.as<int32_t>(), m->d.near_j.as<int32_t>(), m->d.near_ptr.as<int32_t>(),
                            m->d.near_src.as<int32_t>(), m->d.sing.as<SingPair>(), contrib, ops[0], ops[1], ops[2],

@@ -108,12 +108,42 @@ void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue me
 
 }  // namespace bemtx
 
+namespace bemtx {
+// kernels timed by the optional per-launch HIP-event timer of a context
+enum KernelId { K_REGULAR = 0, K_GATHER, K_SINGULAR, K_NEAR, K_MTF_DENSE, K_MASS_APPLY, K_CGS_DOTS, K_CGS_UPDATE,
+                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_COUNT };
+extern const char *const kKernelNames[K_COUNT];
+}  // namespace bemtx
+
 struct bem_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     size_t budget = 0;
     size_t in_use = 0;
+    // per-kernel timing (HIP events around each launch on `stream`)
+    uint32_t ktiming = 0;   // bit k set: time kernel k
+    struct Pending { int id; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double ktotal_ms[bemtx::K_COUNT] = {};
+    int64_t kcount[bemtx::K_COUNT] = {};
+    // assembly scratch (block-pair tiles, singular contributions), grown on demand
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
 };
+
+namespace bemtx {
+// Brackets one kernel launch with timing events when the context asks for it.
+struct KTimer {
+    bem_ctx *c;
+    int id;
+    hipEvent_t a = nullptr, b = nullptr;
+    KTimer(bem_ctx *ctx, int kid);
+    ~KTimer();
+};
+// Resolve finished timings (call after the stream has been synchronised).
+void flush_kernel_timing(bem_ctx *ctx);
+}  // namespace bemtx
 
 struct bem_mesh {
     bem_ctx *ctx = nullptr;
@@ -135,6 +165,8 @@ struct bem_problem {
     bemtx::Csr M[2], P_ie, P_ei;
     bemtx::DevMem P_ie_ptr, P_ie_col, P_ie_val, P_ei_ptr, P_ei_col, P_ei_val;
     bemtx::DevMem Minv[2];          // dense real inverse mass matrices (FP64)
-    bemtx::DevMem M_ptr[2], M_col[2], M_val[2];
+    std::vector<int32_t> ell_col_h[2];   // host staging of the ELL mass rows (kept for async copies)
+    std::vector<double> ell_val_h[2];
+    bemtx::DevMem M_ptr[2], M_col[2], M_val[2], M_ell_col[2], M_ell_val[2];
     double t_geometry_ms = 0, t_regular_ms = 0, t_singular_ms = 0, t_projection_ms = 0;
 };

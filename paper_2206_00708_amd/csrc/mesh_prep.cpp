@@ -220,25 +220,33 @@ bem_status mesh_prepare(MeshData &m)
     // ---- near entries: unique (i, j) touched by singular pairs, contributions in pair order
     {
         const size_t nc = m.sing.size() * 9;
-        std::vector<std::pair<uint64_t, int32_t>> c(nc);
+        std::vector<int32_t> row_cnt(nv + 1, 0);
         for (size_t p = 0; p < m.sing.size(); ++p)
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) {
-                    uint64_t i = (uint32_t)m.tri[3 * m.sing[p].tau + a], j = (uint32_t)m.tri[3 * m.sing[p].sig + b];
-                    c[p * 9 + a * 3 + b] = {i << 32 | j, (int32_t)(p * 9 + a * 3 + b)};
-                }
-        std::stable_sort(c.begin(), c.end(),
-                         [](const std::pair<uint64_t, int32_t> &x, const std::pair<uint64_t, int32_t> &y) {
-                             return x.first < y.first;
-                         });
-        m.near_i.clear(); m.near_j.clear(); m.near_ptr.clear(); m.near_src.resize(nc);
-        for (size_t q = 0; q < nc; ++q) {
-            if (q == 0 || c[q].first != c[q - 1].first) {
-                m.near_ptr.push_back((int32_t)q);
-                m.near_i.push_back((int32_t)(c[q].first >> 32));
-                m.near_j.push_back((int32_t)(c[q].first & 0xffffffffu));
+            for (int a = 0; a < 3; ++a) row_cnt[m.tri[3 * m.sing[p].tau + a] + 1] += 3;
+        for (int64_t v = 0; v < nv; ++v) row_cnt[v + 1] += row_cnt[v];
+        std::vector<int32_t> fill(row_cnt.begin(), row_cnt.end() - 1);
+        std::vector<std::pair<int32_t, int32_t>> byrow(nc);   // (j, src), grouped by i, src ascending
+        for (size_t p = 0; p < m.sing.size(); ++p)
+            for (int a = 0; a < 3; ++a) {
+                const int32_t i = m.tri[3 * m.sing[p].tau + a];
+                for (int b = 0; b < 3; ++b)
+                    byrow[fill[i]++] = {m.tri[3 * m.sing[p].sig + b], (int32_t)(p * 9 + a * 3 + b)};
             }
-            m.near_src[q] = c[q].second;
+        m.near_i.clear(); m.near_j.clear(); m.near_ptr.clear(); m.near_src.resize(nc);
+        size_t q = 0;
+        for (int64_t i = 0; i < nv; ++i) {
+            auto b0 = byrow.begin() + row_cnt[i], b1 = byrow.begin() + row_cnt[i + 1];
+            std::stable_sort(b0, b1, [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
+                return x.first < y.first;
+            });
+            for (auto it = b0; it != b1; ++it, ++q) {
+                if (it == b0 || it->first != (it - 1)->first) {
+                    m.near_ptr.push_back((int32_t)q);
+                    m.near_i.push_back((int32_t)i);
+                    m.near_j.push_back(it->first);
+                }
+                m.near_src[q] = it->second;
+            }
         }
         m.near_ptr.push_back((int32_t)nc);
     }

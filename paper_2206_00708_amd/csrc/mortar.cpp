@@ -13,7 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <map>
+#include <thread>
 
 #include "internal.h"
 
@@ -167,83 +167,123 @@ bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *co
     for (int64_t t = 0; t < nti; ++t)
         grid[((size_t)cidx(ci[3 * t]) * ncell + cidx(ci[3 * t + 1])) * ncell + cidx(ci[3 * t + 2])].push_back((int32_t)t);
 
-    std::vector<std::map<int32_t, double>> rows(mi.nv);
-    double worst = 0.0;
-    for (int64_t te = 0; te < nte; ++te) {
-        const int32_t *ve = &me.tri[3 * te];
-        Facet F = make_facet(&me.xyz[3 * ve[0]], &me.xyz[3 * ve[1]], &me.xyz[3 * ve[2]]);
-        double scale = std::fabs(F.v[1].x) + std::fabs(F.v[2].x) + std::fabs(F.v[2].y);
-        double tol = 1e-12 * scale * scale;
-        double plane = dot(F.n, F.o);
-        double covered = 0.0;
-        int gx = cidx(ce[3 * te]), gy = cidx(ce[3 * te + 1]), gz = cidx(ce[3 * te + 2]);
-        for (int dx = -1; dx <= 1; ++dx)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dz = -1; dz <= 1; ++dz) {
-                    int x = gx + dx, y = gy + dy, z = gz + dz;
-                    if (x < 0 || y < 0 || z < 0 || x >= ncell || y >= ncell || z >= ncell) continue;
-                    for (int32_t ti : grid[((size_t)x * ncell + y) * ncell + z]) {
-                        double d2 = 0;
-                        for (int k = 0; k < 3; ++k) d2 += (ci[3 * ti + k] - ce[3 * te + k]) * (ci[3 * ti + k] - ce[3 * te + k]);
-                        if (std::sqrt(d2) > (ri[ti] + re[te]) * 1.0001 + 1e-12) continue;
-                        const int32_t *vi = &mi.tri[3 * ti];
-                        V2 S[3];
-                        bool ok = true;
-                        for (int a = 0; a < 3; ++a) {
-                            const double *p = &mi.xyz[3 * vi[a]];
-                            double den = dot(F.n, p);
-                            if (!(den > 0.0)) { ok = false; break; }
-                            double s = plane / den;
-                            double q[3] = {s * p[0] - F.o[0], s * p[1] - F.o[1], s * p[2] - F.o[2]};
-                            S[a] = {dot(q, F.e1), dot(q, F.e2)};
-                        }
-                        if (!ok || orient(S[0], S[1], S[2]) <= 0.0) continue;
-                        // exterior facet clipped by the three edges of the projected interior triangle
-                        V2 poly[12], tmp[12];
-                        int n = 3;
-                        for (int a = 0; a < 3; ++a) poly[a] = F.v[a];
-                        for (int a = 0; a < 3 && n >= 3; ++a) {
-                            n = keep_left(poly, n, S[a], S[(a + 1) % 3], tol, tmp);
-                            std::memcpy(poly, tmp, n * sizeof(V2));
-                        }
-                        if (n < 3) continue;
-                        double apoly = 0.0;
-                        for (int k = 1; k + 1 < n; ++k) apoly += 0.5 * orient(poly[0], poly[k], poly[k + 1]);
-                        if (apoly < 1e-14 * F.area) continue;
-                        covered += apoly;
-                        double blk[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-                        for (int k = 1; k + 1 < n; ++k) {
-                            V2 A = poly[0], B = poly[k], C = poly[k + 1];
-                            double at = 0.5 * orient(A, B, C);
-                            // 3-point interior rule, exact for quadratics
-                            const double w1 = 2.0 / 3.0, w2 = 1.0 / 6.0;
-                            const double L[3][3] = {{w1, w2, w2}, {w2, w1, w2}, {w2, w2, w1}};
-                            for (int g = 0; g < 3; ++g) {
-                                V2 q = {L[g][0] * A.x + L[g][1] * B.x + L[g][2] * C.x,
-                                        L[g][0] * A.y + L[g][1] * B.y + L[g][2] * C.y};
-                                double li[3], le[3];
-                                bary(S[0], S[1], S[2], q, li);
-                                bary(F.v[0], F.v[1], F.v[2], q, le);
-                                for (int a = 0; a < 3; ++a)
-                                    for (int b = 0; b < 3; ++b) blk[a][b] += at / 3.0 * li[a] * le[b];
+    // per exterior facet: (interior triangle, 3x3 block) contributions, facets split over host threads
+    struct Contrib { int32_t ti; double blk[3][3]; };
+    std::vector<std::vector<Contrib>> per_facet(nte);
+    std::vector<double> defect(nte, 0.0);
+    auto work = [&](int64_t te_begin, int64_t te_end) {
+        for (int64_t te = te_begin; te < te_end; ++te) {
+            const int32_t *ve = &me.tri[3 * te];
+            Facet F = make_facet(&me.xyz[3 * ve[0]], &me.xyz[3 * ve[1]], &me.xyz[3 * ve[2]]);
+            double scale = std::fabs(F.v[1].x) + std::fabs(F.v[2].x) + std::fabs(F.v[2].y);
+            double tol = 1e-12 * scale * scale;
+            double plane = dot(F.n, F.o);
+            double covered = 0.0;
+            int gx = cidx(ce[3 * te]), gy = cidx(ce[3 * te + 1]), gz = cidx(ce[3 * te + 2]);
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        int x = gx + dx, y = gy + dy, z = gz + dz;
+                        if (x < 0 || y < 0 || z < 0 || x >= ncell || y >= ncell || z >= ncell) continue;
+                        for (int32_t ti : grid[((size_t)x * ncell + y) * ncell + z]) {
+                            double d2 = 0;
+                            for (int k = 0; k < 3; ++k) d2 += (ci[3 * ti + k] - ce[3 * te + k]) * (ci[3 * ti + k] - ce[3 * te + k]);
+                            if (std::sqrt(d2) > (ri[ti] + re[te]) * 1.0001 + 1e-12) continue;
+                            const int32_t *vi = &mi.tri[3 * ti];
+                            V2 S[3];
+                            bool ok = true;
+                            for (int a = 0; a < 3; ++a) {
+                                const double *p = &mi.xyz[3 * vi[a]];
+                                double den = dot(F.n, p);
+                                if (!(den > 0.0)) { ok = false; break; }
+                                double sc = plane / den;
+                                double q[3] = {sc * p[0] - F.o[0], sc * p[1] - F.o[1], sc * p[2] - F.o[2]};
+                                S[a] = {dot(q, F.e1), dot(q, F.e2)};
                             }
+                            if (!ok || orient(S[0], S[1], S[2]) <= 0.0) continue;
+                            // exterior facet clipped by the three edges of the projected interior triangle
+                            V2 poly[12], tmp[12];
+                            int n = 3;
+                            for (int a = 0; a < 3; ++a) poly[a] = F.v[a];
+                            for (int a = 0; a < 3 && n >= 3; ++a) {
+                                n = keep_left(poly, n, S[a], S[(a + 1) % 3], tol, tmp);
+                                std::memcpy(poly, tmp, n * sizeof(V2));
+                            }
+                            if (n < 3) continue;
+                            double apoly = 0.0;
+                            for (int k = 1; k + 1 < n; ++k) apoly += 0.5 * orient(poly[0], poly[k], poly[k + 1]);
+                            if (apoly < 1e-14 * F.area) continue;
+                            covered += apoly;
+                            Contrib c;
+                            c.ti = ti;
+                            std::memset(c.blk, 0, sizeof c.blk);
+                            for (int k = 1; k + 1 < n; ++k) {
+                                V2 A = poly[0], B = poly[k], C = poly[k + 1];
+                                double at = 0.5 * orient(A, B, C);
+                                // 3-point interior rule, exact for quadratics
+                                const double w1 = 2.0 / 3.0, w2 = 1.0 / 6.0;
+                                const double L[3][3] = {{w1, w2, w2}, {w2, w1, w2}, {w2, w2, w1}};
+                                for (int g = 0; g < 3; ++g) {
+                                    V2 q = {L[g][0] * A.x + L[g][1] * B.x + L[g][2] * C.x,
+                                            L[g][0] * A.y + L[g][1] * B.y + L[g][2] * C.y};
+                                    double li[3], le[3];
+                                    bary(S[0], S[1], S[2], q, li);
+                                    bary(F.v[0], F.v[1], F.v[2], q, le);
+                                    for (int a = 0; a < 3; ++a)
+                                        for (int b = 0; b < 3; ++b) c.blk[a][b] += at / 3.0 * li[a] * le[b];
+                                }
+                            }
+                            per_facet[te].push_back(c);
                         }
-                        for (int a = 0; a < 3; ++a)
-                            for (int b = 0; b < 3; ++b) rows[vi[a]][ve[b]] += blk[a][b];
                     }
-                }
-        worst = std::max(worst, std::fabs(covered - F.area) / F.area);
+            defect[te] = std::fabs(covered - F.area) / F.area;
+        }
+    };
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        int nth = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
+        if (nte < 256) nth = 1;
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nth; ++t)
+            pool.emplace_back(work, nte * t / nth, nte * (t + 1) / nth);
+        for (auto &th : pool) th.join();
     }
+    double worst = 0.0;
+    for (double d : defect) worst = std::max(worst, d);
     if (coverage_defect) *coverage_defect = worst;
+    // COO in facet order -> rows by counting sort -> columns by stable sort, duplicates summed in order
+    std::vector<int32_t> cnt(mi.nv + 1, 0);
+    for (int64_t te = 0; te < nte; ++te)
+        for (const Contrib &c : per_facet[te])
+            for (int a = 0; a < 3; ++a) cnt[mi.tri[3 * c.ti + a] + 1] += 3;
+    for (int64_t i = 0; i < mi.nv; ++i) cnt[i + 1] += cnt[i];
+    std::vector<std::pair<int32_t, double>> ent(cnt[mi.nv]);
+    {
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t te = 0; te < nte; ++te)
+            for (const Contrib &c : per_facet[te])
+                for (int a = 0; a < 3; ++a) {
+                    const int32_t i = mi.tri[3 * c.ti + a];
+                    for (int b = 0; b < 3; ++b) ent[fill[i]++] = {me.tri[3 * te + b], c.blk[a][b]};
+                }
+    }
     P.nrows = mi.nv;
     P.ncols = me.nv;
     P.ptr.assign(mi.nv + 1, 0);
     P.col.clear();
     P.val.clear();
     for (int64_t i = 0; i < mi.nv; ++i) {
-        for (auto &kv : rows[i]) {
-            P.col.push_back(kv.first);
-            P.val.push_back(kv.second);
+        auto b0 = ent.begin() + cnt[i], b1 = ent.begin() + cnt[i + 1];
+        std::stable_sort(b0, b1, [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+            return x.first < y.first;
+        });
+        for (auto it = b0; it != b1; ++it) {
+            if (it != b0 && it->first == (it - 1)->first) {
+                P.val.back() += it->second;
+            } else {
+                P.col.push_back(it->first);
+                P.val.push_back(it->second);
+            }
         }
         P.ptr[i + 1] = (int32_t)P.col.size();
     }

@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "phase.h"
 
 namespace bemtx {
 
@@ -45,6 +46,9 @@ __host__ __device__ constexpr double q6_bary(int q, int c)
     return q < 3 ? (c == q ? 1.0 - 2.0 * kA1 : kA1) : (c == q - 3 ? 1.0 - 2.0 * kA2 : kA2);
 }
 __host__ __device__ constexpr double q6_w(int q) { return q < 3 ? kW1 : kW2; }
+
+// row stride of the dense inverse mass matrices: even, so rows are 16-byte aligned
+__host__ __device__ inline int minv_ld(int nv) { return (nv + 1) & ~1; }
 
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -91,7 +95,7 @@ __global__ void rhs_kernel(int ne, int ni, const int32_t *__restrict__ star_ptr,
         for (int q = 0; q < 6; ++q) {
             const double ph = k * (d0 * g.qp[q][0] + d1 * g.qp[q][1] + d2 * g.qp[q][2]);
             double s, c;
-            sincos(ph, &s, &c);
+            phase_sincos(ph, &s, &c);
             const double w = q6_w(q) * q6_bary(q, a);
             sr += w * c;
             si += w * s;
@@ -111,10 +115,11 @@ __global__ void rhs_kernel(int ne, int ni, const int32_t *__restrict__ star_ptr,
 
 // --------------------------------------------------------- mass inverse
 
+
 // Column c = blockIdx.x of M^-1 (= row c, M is symmetric), blockDim 1024,
 // R rows per thread kept in registers; the search direction lives in LDS.
 template <int R>
-__global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, const int32_t *__restrict__ mp,
+__global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, int ldm, const int32_t *__restrict__ mp,
                                                              const int32_t *__restrict__ mc,
                                                              const double *__restrict__ mv, double *__restrict__ Minv)
 {
@@ -168,7 +173,80 @@ __global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, const int32_
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int row = tid + 1024 * k;
-        if (row < nv) Minv[(int64_t)col * nv + row] = x[k];
+        if (row < nv) Minv[(int64_t)col * ldm + row] = x[k];
+    }
+}
+
+// Same iteration for C columns per workgroup: M in ELL form (width W, layout
+// [q][row] so that loads are coalesced, padding = zero entries on the
+// diagonal) read from L2 once per step for all C columns, and the search
+// directions double-buffered in LDS so that one barrier per step suffices.
+template <int R, int C>
+__global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm, int W, const int32_t *__restrict__ ell_col,
+                                                                 const double *__restrict__ ell_val,
+                                                                 double *__restrict__ Minv)
+{
+    extern __shared__ double dsh[];   // [2][C][nv]
+    const int c0 = blockIdx.x * C;
+    const int tid = threadIdx.x;
+    const double lmin = 0.5, lmax = 2.0;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma1 = theta / delta;
+    double dg[R], x[R][C], r[R][C];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int row = tid + 1024 * k;
+        const bool ok = row < nv;
+        double dsum = 0.0;
+        if (ok)
+            for (int q = 0; q < W; ++q)
+                if (ell_col[(int64_t)q * nv + row] == row) dsum += ell_val[(int64_t)q * nv + row];
+        dg[k] = ok ? 1.0 / dsum : 0.0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            x[k][c] = 0.0;
+            r[k][c] = (ok && row == c0 + c) ? 1.0 : 0.0;
+            if (ok) dsh[c * nv + row] = dg[k] * r[k][c] / theta;
+        }
+    }
+    double rho = 1.0 / sigma1;
+    int cur = 0;
+    __syncthreads();
+    for (int it = 0; it < 40; ++it) {
+        const double rho_new = 1.0 / (2.0 * sigma1 - rho);
+        const double *dold = dsh + cur * C * nv;
+        double *dnew = dsh + (cur ^ 1) * C * nv;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int row = tid + 1024 * k;
+            if (row >= nv) continue;
+            double ad[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) ad[c] = 0.0;
+            for (int q = 0; q < W; ++q) {
+                const int col = ell_col[(int64_t)q * nv + row];
+                const double v = ell_val[(int64_t)q * nv + row];
+#pragma unroll
+                for (int c = 0; c < C; ++c) ad[c] += v * dold[c * nv + col];
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double d = dold[c * nv + row];
+                x[k][c] += d;
+                r[k][c] -= ad[c];
+                dnew[c * nv + row] = rho_new * rho * d + (2.0 * rho_new / delta) * dg[k] * r[k][c];
+            }
+        }
+        rho = rho_new;
+        cur ^= 1;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        const int row = tid + 1024 * k;
+        if (row < nv)
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (c0 + c < nv) Minv[(int64_t)(c0 + c) * ldm + row] = x[k][c];
     }
 }
 
@@ -178,11 +256,37 @@ static bem_status launch_minv_r(bem_problem *p, int nv, int mesh)
     const size_t lds = (size_t)nv * sizeof(double);
     BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_kernel<R>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(mass_inverse_kernel<R>, dim3(nv), dim3(1024), lds, p->ctx->stream, nv,
+    KTimer kt(p->ctx, K_MASS_INVERSE);
+    hipLaunchKernelGGL(mass_inverse_kernel<R>, dim3(nv), dim3(1024), lds, p->ctx->stream, nv, minv_ld(nv),
                        p->M_ptr[mesh].as<int32_t>(), p->M_col[mesh].as<int32_t>(), p->M_val[mesh].as<double>(),
                        p->Minv[mesh].as<double>());
     BEM_HIP(hipGetLastError());
     return BEM_OK;
+}
+
+template <int R, int C>
+static bem_status launch_minv_ell(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev)
+{
+    const size_t lds = (size_t)2 * C * nv * sizeof(double);
+    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_ell_kernel<R, C>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    KTimer kt(p->ctx, K_MASS_INVERSE);
+    hipLaunchKernelGGL((mass_inverse_ell_kernel<R, C>), dim3((nv + C - 1) / C), dim3(1024), lds, p->ctx->stream, nv,
+                       minv_ld(nv), W, ec, ev, p->Minv[mesh].as<double>());
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+}
+
+template <int R>
+static bem_status launch_minv_ell_r(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev)
+{
+    // columns per workgroup: as many double-buffered directions as fit in 160 KiB of LDS
+    const int cfit = (int)(163840 / (2 * (size_t)nv * sizeof(double)));
+    if (cfit >= 8) return launch_minv_ell<R, 8>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 4) return launch_minv_ell<R, 4>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 3) return launch_minv_ell<R, 3>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 2) return launch_minv_ell<R, 2>(p, nv, W, mesh, ec, ev);
+    return launch_minv_ell<R, 1>(p, nv, W, mesh, ec, ev);
 }
 
 bem_status launch_mass_inverse(bem_problem *p, int mesh)
@@ -190,8 +294,45 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh)
     const bem_mesh *m = mesh == 0 ? p->ext : p->inte;
     const int nv = (int)m->h.nv;
     if (nv > 16 * 1024) return set_error(BEM_E_UNSUPPORTED, "mass inverse: more than 16384 vertices on one mesh");
-    bem_status s = dev_alloc(p->ctx, p->Minv[mesh], (size_t)nv * nv * sizeof(double));
+    bem_status s = dev_alloc(p->ctx, p->Minv[mesh], (size_t)nv * minv_ld(nv) * sizeof(double));
     if (s) return s;
+    const Csr &M = p->M[mesh];
+    int W = 0;
+    for (int64_t i = 0; i < M.nrows; ++i) W = std::max(W, M.ptr[i + 1] - M.ptr[i]);
+    if (2 * (size_t)nv * sizeof(double) <= 163840) {
+        // ELL, [q][row], padded with zeros on the diagonal
+        auto &ec = p->ell_col_h[mesh];
+        auto &ev = p->ell_val_h[mesh];
+        ec.assign((size_t)nv * W, 0);
+        ev.assign((size_t)nv * W, 0.0);
+        for (int i = 0; i < nv; ++i) {
+            int q = 0;
+            for (int k = M.ptr[i]; k < M.ptr[i + 1]; ++k, ++q) {
+                ec[(size_t)q * nv + i] = M.col[k];
+                ev[(size_t)q * nv + i] = M.val[k];
+            }
+            for (; q < W; ++q) ec[(size_t)q * nv + i] = i;
+        }
+        s = dev_alloc(p->ctx, p->M_ell_col[mesh], ec.size() * sizeof(int32_t));
+        if (!s) s = dev_alloc(p->ctx, p->M_ell_val[mesh], ev.size() * sizeof(double));
+        if (s) return s;
+        BEM_HIP(hipMemcpyAsync(p->M_ell_col[mesh].ptr, ec.data(), ec.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                               p->ctx->stream));
+        BEM_HIP(hipMemcpyAsync(p->M_ell_val[mesh].ptr, ev.data(), ev.size() * sizeof(double), hipMemcpyHostToDevice,
+                               p->ctx->stream));
+        const int32_t *dc = p->M_ell_col[mesh].as<int32_t>();
+        const double *dv = p->M_ell_val[mesh].as<double>();
+        const int R = (nv + 1023) / 1024;
+        switch (R) {
+        case 1: return launch_minv_ell_r<1>(p, nv, W, mesh, dc, dv);
+        case 2: return launch_minv_ell_r<2>(p, nv, W, mesh, dc, dv);
+        case 3: return launch_minv_ell_r<3>(p, nv, W, mesh, dc, dv);
+        case 4: return launch_minv_ell_r<4>(p, nv, W, mesh, dc, dv);
+        case 5: case 6: return launch_minv_ell_r<6>(p, nv, W, mesh, dc, dv);
+        case 7: case 8: return launch_minv_ell_r<8>(p, nv, W, mesh, dc, dv);
+        default: return launch_minv_ell_r<10>(p, nv, W, mesh, dc, dv);
+        }
+    }
     const int R = (nv + 1023) / 1024;
     switch (R) {
     case 1: return launch_minv_r<1>(p, nv, mesh);
@@ -207,6 +348,14 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh)
 
 // --------------------------------------------------------------- mat-vec
 
+struct KrylovState {
+    int done;       // 1 once the residual estimate met tol (or the step limit was reached)
+    int iters;      // Arnoldi steps taken
+    double resid;   // |g_{j+1}| / beta0
+    double beta0;
+};
+
+
 struct MtfArgs {
     int ne, ni;
     const double2 *Ve, *Ke, *Te, *De, *Vi, *Ki, *Ti, *Di;
@@ -215,45 +364,46 @@ struct MtfArgs {
     double c_ext_v, c_ext_w, c_int_v, c_int_w;   // 1/2, 1/2 re/ri, -1/2, -1/2 ri/re
 };
 
-// y = A x (weak form), one wave per row of [ext rows ; int rows]
-__global__ __launch_bounds__(256) void mtf_dense_kernel(MtfArgs A, const double2 *__restrict__ x, double2 *__restrict__ y)
+// y = A x (weak form).  Each wave owns RPW consecutive rows of one mesh
+// (rows of [ext ; int] are grouped so no wave straddles the two meshes) and
+// streams their four dense rows once (complex128, 16 B per lane, coalesced,
+// non-temporal); each x element loaded serves all RPW rows.  The mortar
+// coupling of each row (CSR) is added before the wave reduction.
+template <int RPW>
+__global__ __launch_bounds__(256) void mtf_dense_kernel(MtfArgs A, const double2 *__restrict__ x, double2 *__restrict__ y,
+                                                        const KrylovState *__restrict__ st)
 {
+    if (st && st->done) return;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (wave >= A.ne + A.ni) return;
-    const bool ext = wave < A.ne;
-    const int i = ext ? wave : wave - A.ne;
+    const int we = (A.ne + RPW - 1) / RPW, wi = (A.ni + RPW - 1) / RPW;
+    if (wave >= we + wi) return;
+    const bool ext = wave < we;
+    const int i0 = (ext ? wave : wave - we) * RPW;
     const int nv = ext ? A.ne : A.ni;
+    const int nr = min(RPW, nv - i0);
     const double2 *Km = ext ? A.Ke : A.Ki, *Vm = ext ? A.Ve : A.Vi, *Dm = ext ? A.De : A.Di, *Tm = ext ? A.Te : A.Ti;
     const double2 *xv = ext ? x : x + 2 * A.ne;
     const double2 *xw = xv + nv;
-    const int64_t o = (int64_t)i * nv;
-    double ar = 0, ai = 0, br = 0, bi = 0;   // row of [-K V] and of [D T]
-    int j = lane;
-    for (; j + 64 < nv; j += 128) {
-        const double2 k0 = ld_stream(&Km[o + j]), k1 = ld_stream(&Km[o + j + 64]);
-        const double2 v0 = ld_stream(&Vm[o + j]), v1 = ld_stream(&Vm[o + j + 64]);
-        const double2 d0 = ld_stream(&Dm[o + j]), d1 = ld_stream(&Dm[o + j + 64]);
-        const double2 t0 = ld_stream(&Tm[o + j]), t1 = ld_stream(&Tm[o + j + 64]);
-        const double2 p0 = xv[j], p1 = xv[j + 64], q0 = xw[j], q1 = xw[j + 64];
-        ar += -(k0.x * p0.x - k0.y * p0.y) + (v0.x * q0.x - v0.y * q0.y);
-        ai += -(k0.x * p0.y + k0.y * p0.x) + (v0.x * q0.y + v0.y * q0.x);
-        br += (d0.x * p0.x - d0.y * p0.y) + (t0.x * q0.x - t0.y * q0.y);
-        bi += (d0.x * p0.y + d0.y * p0.x) + (t0.x * q0.y + t0.y * q0.x);
-        ar += -(k1.x * p1.x - k1.y * p1.y) + (v1.x * q1.x - v1.y * q1.y);
-        ai += -(k1.x * p1.y + k1.y * p1.x) + (v1.x * q1.y + v1.y * q1.x);
-        br += (d1.x * p1.x - d1.y * p1.y) + (t1.x * q1.x - t1.y * q1.y);
-        bi += (d1.x * p1.y + d1.y * p1.x) + (t1.x * q1.y + t1.y * q1.x);
-    }
-    for (; j < nv; j += 64) {
-        const double2 k0 = Km[o + j], v0 = Vm[o + j], d0 = Dm[o + j], t0 = Tm[o + j];
+    double ar[RPW], ai[RPW], br[RPW], bi[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = br[r] = bi[r] = 0.0;
+    for (int j = lane; j < nv; j += 64) {
         const double2 p0 = xv[j], q0 = xw[j];
-        ar += -(k0.x * p0.x - k0.y * p0.y) + (v0.x * q0.x - v0.y * q0.y);
-        ai += -(k0.x * p0.y + k0.y * p0.x) + (v0.x * q0.y + v0.y * q0.x);
-        br += (d0.x * p0.x - d0.y * p0.y) + (t0.x * q0.x - t0.y * q0.y);
-        bi += (d0.x * p0.y + d0.y * p0.x) + (t0.x * q0.y + t0.y * q0.x);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            if (r < nr) {
+                const int64_t o = (int64_t)(i0 + r) * nv + j;
+                const double2 k0 = ld_stream(&Km[o]), v0 = ld_stream(&Vm[o]);
+                const double2 d0 = ld_stream(&Dm[o]), t0 = ld_stream(&Tm[o]);
+                ar[r] += -(k0.x * p0.x - k0.y * p0.y) + (v0.x * q0.x - v0.y * q0.y);
+                ai[r] += -(k0.x * p0.y + k0.y * p0.x) + (v0.x * q0.y + v0.y * q0.x);
+                br[r] += (d0.x * p0.x - d0.y * p0.y) + (t0.x * q0.x - t0.y * q0.y);
+                bi[r] += (d0.x * p0.y + d0.y * p0.x) + (t0.x * q0.y + t0.y * q0.x);
+            }
+        }
     }
-    // mortar coupling of this row
+    // mortar coupling of each row
     const int32_t *pp = ext ? A.pei_ptr : A.pie_ptr;
     const int32_t *pc = ext ? A.pei_col : A.pie_col;
     const double *pv = ext ? A.pei_val : A.pie_val;
@@ -261,115 +411,192 @@ __global__ __launch_bounds__(256) void mtf_dense_kernel(MtfArgs A, const double2
     const int nother = ext ? A.ni : A.ne;
     const double2 *cw = cv + nother;                        // other mesh's w
     const double fv = ext ? A.c_ext_v : A.c_int_v, fw = ext ? A.c_ext_w : A.c_int_w;
-    for (int q = pp[i] + lane; q < pp[i + 1]; q += 64) {
-        const double pvq = pv[q];
-        const int c = pc[q];
-        ar += fv * pvq * cv[c].x;
-        ai += fv * pvq * cv[c].y;
-        br += fw * pvq * cw[c].x;
-        bi += fw * pvq * cw[c].y;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        if (r < nr) {
+            const int i = i0 + r;
+            for (int q = pp[i] + lane; q < pp[i + 1]; q += 64) {
+                const double pvq = pv[q];
+                const int c = pc[q];
+                ar[r] += fv * pvq * cv[c].x;
+                ai[r] += fv * pvq * cv[c].y;
+                br[r] += fw * pvq * cw[c].x;
+                bi[r] += fw * pvq * cw[c].y;
+            }
+        }
+        ar[r] = wave_sum(ar[r]);
+        ai[r] = wave_sum(ai[r]);
+        br[r] = wave_sum(br[r]);
+        bi[r] = wave_sum(bi[r]);
     }
-    ar = wave_sum(ar);
-    ai = wave_sum(ai);
-    br = wave_sum(br);
-    bi = wave_sum(bi);
-    if (lane == 0) {
+    if (lane < nr) {
         double2 *ya = ext ? y : y + 2 * A.ne;
-        ya[i] = make_double2(ar, ai);
-        ya[i + nv] = make_double2(br, bi);
+        double sar = 0, sai = 0, sbr = 0, sbi = 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+            if (r == lane) { sar = ar[r]; sai = ai[r]; sbr = br[r]; sbi = bi[r]; }
+        ya[i0 + lane] = make_double2(sar, sai);
+        ya[i0 + lane + nv] = make_double2(sbr, sbi);
     }
 }
 
-// z = blockdiag(M_e^-1, M_e^-1, M_i^-1, M_i^-1) y; one wave per (mesh row)
+// z = blockdiag(M_e^-1, M_e^-1, M_i^-1, M_i^-1) y; each wave owns RPW rows of
+// one mesh, two columns per lane per step (16-byte loads of the even-strided
+// rows), and applies them to the two vectors of that mesh at once.
+template <int RPW>
 __global__ __launch_bounds__(256) void mass_apply_kernel(int ne, int ni, const double *__restrict__ Me_inv,
                                                          const double *__restrict__ Mi_inv,
-                                                         const double2 *__restrict__ y, double2 *__restrict__ z)
+                                                         const double2 *__restrict__ y, double2 *__restrict__ z,
+                                                         const KrylovState *__restrict__ st)
 {
+    if (st && st->done) return;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (wave >= ne + ni) return;
-    const bool ext = wave < ne;
-    const int i = ext ? wave : wave - ne;
+    const int we = (ne + RPW - 1) / RPW, wi = (ni + RPW - 1) / RPW;
+    if (wave >= we + wi) return;
+    const bool ext = wave < we;
+    const int i0 = (ext ? wave : wave - we) * RPW;
     const int nv = ext ? ne : ni;
-    const double *Mr = (ext ? Me_inv : Mi_inv) + (int64_t)i * nv;
+    const int nr = min(RPW, nv - i0);
+    const int ld = minv_ld(nv);
+    const double *M0 = (ext ? Me_inv : Mi_inv) + (int64_t)i0 * ld;
     const double2 *ya = ext ? y : y + 2 * ne;
     const double2 *yb = ya + nv;
-    double ar = 0, ai = 0, br = 0, bi = 0;
-    for (int j = lane; j < nv; j += 64) {
-        const double m = __builtin_nontemporal_load(&Mr[j]);
-        const double2 a = ya[j], b = yb[j];
-        ar += m * a.x; ai += m * a.y; br += m * b.x; bi += m * b.y;
+    double ar[RPW], ai[RPW], br[RPW], bi[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = br[r] = bi[r] = 0.0;
+    const int npair = nv >> 1;
+    for (int h = lane; h < npair; h += 64) {
+        const double2 a0 = ya[2 * h], a1 = ya[2 * h + 1], b0 = yb[2 * h], b1 = yb[2 * h + 1];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            if (r < nr) {
+                const v2d m = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(M0 + (int64_t)r * ld) + h);
+                ar[r] += m.x * a0.x + m.y * a1.x; ai[r] += m.x * a0.y + m.y * a1.y;
+                br[r] += m.x * b0.x + m.y * b1.x; bi[r] += m.x * b0.y + m.y * b1.y;
+            }
+        }
     }
-    ar = wave_sum(ar); ai = wave_sum(ai); br = wave_sum(br); bi = wave_sum(bi);
-    if (lane == 0) {
+    if ((nv & 1) && lane == 0) {
+        const double2 a = ya[nv - 1], b = yb[nv - 1];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            if (r < nr) {
+                const double m = M0[(int64_t)r * ld + nv - 1];
+                ar[r] += m * a.x; ai[r] += m * a.y; br[r] += m * b.x; bi[r] += m * b.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        ar[r] = wave_sum(ar[r]); ai[r] = wave_sum(ai[r]); br[r] = wave_sum(br[r]); bi[r] = wave_sum(bi[r]);
+    }
+    if (lane < nr) {
         double2 *za = ext ? z : z + 2 * ne;
-        za[i] = make_double2(ar, ai);
-        za[i + nv] = make_double2(br, bi);
+        double sar = 0, sai = 0, sbr = 0, sbi = 0;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+            if (r == lane) { sar = ar[r]; sai = ai[r]; sbr = br[r]; sbi = bi[r]; }
+        za[i0 + lane] = make_double2(sar, sai);
+        za[i0 + lane + nv] = make_double2(sbr, sbi);
     }
+}
+
+constexpr int MV_RPW = 2;     // rows per wave, dense mat-vec
+constexpr int MASS_RPW = 4;   // rows per wave, inverse-mass apply
+
+static inline dim3 rows_grid(int ne, int ni, int rpw)
+{
+    const int waves = (ne + rpw - 1) / rpw + (ni + rpw - 1) / rpw;
+    return dim3((waves + 3) / 4);
 }
 
 // ------------------------------------------------------ Krylov kernels
+//
+// One Arnoldi step j of GMRES on z = M^-1 A v_j, without a host round trip:
+//   dots(pass 0) -> update(pass 0) -> dots(pass 1) -> update(pass 1, partial
+//   norms) -> arnoldi_finish (beta, v_{j+1} = w / beta, and in block 0 the
+//   Givens rotations of the new Hessenberg column and the residual estimate).
+// Every kernel returns at once when the state says the iteration has
+// converged, so steps issued ahead of the host's convergence check cost only
+// their launch.
 
-constexpr int CGS_CHUNK = 4096;   // rows per workgroup of the dot kernel
+constexpr int CGS_CHUNK = 1024;   // rows per partial dot product
+constexpr int MAXIT_CAP = 3000;   // Hessenberg column, rotations and g staged in LDS
 
-// partial[blk][c] = sum over the rows of chunk blk of conj(Vb[c][r]) w[r]
+// partial[chunk][c] = sum over the rows of `chunk` of conj(Vb[c][r]) w[r];
+// one wave per (chunk, c): grid (nchunk, ceil(nvec / 4)), 4 waves per block.
 __global__ __launch_bounds__(256) void cgs_dots_kernel(int n, int nvec, const double2 *__restrict__ Vb,
-                                                       const double2 *__restrict__ w, double2 *__restrict__ partial)
+                                                       const double2 *__restrict__ w, double2 *__restrict__ partial,
+                                                       const KrylovState *__restrict__ st)
 {
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (st->done) return;
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (c >= nvec) return;
     const int r0 = blockIdx.x * CGS_CHUNK, r1 = min(n, r0 + CGS_CHUNK);
-    for (int c = wv; c < nvec; c += 4) {
-        const double2 *vc = Vb + (int64_t)c * n;
-        double sr = 0, si = 0;
-        for (int r = r0 + lane; r < r1; r += 64) {
-            const double2 a = vc[r], b = w[r];
-            sr += a.x * b.x + a.y * b.y;
-            si += a.x * b.y - a.y * b.x;
-        }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        if (lane == 0) partial[(int64_t)blockIdx.x * nvec + c] = make_double2(sr, si);
+    const double2 *vc = Vb + (int64_t)c * n;
+    double sr = 0, si = 0;
+    for (int r = r0 + lane; r < r1; r += 64) {
+        const double2 a = vc[r], b = w[r];
+        sr += a.x * b.x + a.y * b.y;
+        si += a.x * b.y - a.y * b.x;
     }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) partial[(int64_t)blockIdx.x * nvec + c] = make_double2(sr, si);
 }
 
-// h = sum of partials (fixed order); w -= Vb h; hsum += h (block 0)
-__global__ __launch_bounds__(256) void cgs_update_kernel(int n, int nvec, int nblk, const double2 *__restrict__ Vb,
+// h = sum of the partials (fixed order); w -= Vb h; hsum = h (pass 0) or
+// hsum += h (pass 1, which also writes the partial squared norms of w).
+__global__ __launch_bounds__(256) void cgs_update_kernel(int n, int nvec, int nchunk, const double2 *__restrict__ Vb,
                                                          const double2 *__restrict__ partial, double2 *__restrict__ w,
-                                                         double2 *__restrict__ hsum)
+                                                         double2 *__restrict__ hsum, int pass, double *__restrict__ npart,
+                                                         const KrylovState *__restrict__ st)
 {
+    if (st->done) return;
     extern __shared__ double2 hs[];
+    __shared__ double red[4];
     for (int c = threadIdx.x; c < nvec; c += blockDim.x) {
         double2 s = make_double2(0, 0);
-        for (int b = 0; b < nblk; ++b) s = cadd(s, partial[(int64_t)b * nvec + c]);
+        for (int b = 0; b < nchunk; ++b) s = cadd(s, partial[(int64_t)b * nvec + c]);
         hs[c] = s;
-        if (blockIdx.x == 0) hsum[c] = cadd(hsum[c], s);
+        if (blockIdx.x == 0) hsum[c] = pass ? cadd(hsum[c], s) : s;
     }
     __syncthreads();
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    double2 acc = w[r];
-    for (int c = 0; c < nvec; ++c) {
-        const double2 v = Vb[(int64_t)c * n + r], h = hs[c];
-        acc.x -= v.x * h.x - v.y * h.y;
-        acc.y -= v.x * h.y + v.y * h.x;
+    double nrm = 0.0;
+    if (r < n) {
+        double2 acc = w[r];
+        for (int c = 0; c < nvec; ++c) {
+            const double2 v = Vb[(int64_t)c * n + r], h = hs[c];
+            acc.x -= v.x * h.x - v.y * h.y;
+            acc.y -= v.x * h.y + v.y * h.x;
+        }
+        w[r] = acc;
+        nrm = acc.x * acc.x + acc.y * acc.y;
     }
-    w[r] = acc;
+    if (pass) {
+        nrm = wave_sum(nrm);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
+        __syncthreads();
+        if (threadIdx.x == 0) npart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
 }
 
-// partial[blk] = sum |w|^2 over the chunk
+// partial[blk] = sum |w|^2 over 256-row blocks (used for the initial residual)
 __global__ __launch_bounds__(256) void norm_partial_kernel(int n, const double2 *__restrict__ w, double *__restrict__ partial)
 {
     __shared__ double red[4];
-    const int r0 = blockIdx.x * CGS_CHUNK, r1 = min(n, r0 + CGS_CHUNK);
-    double s = 0;
-    for (int r = r0 + threadIdx.x; r < r1; r += 256) s += w[r].x * w[r].x + w[r].y * w[r].y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = r < n ? w[r].x * w[r].x + w[r].y * w[r].y : 0.0;
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// beta = sqrt(sum partial); out = w / beta; beta_out = beta
+// beta = sqrt(sum partial); out = w / beta; beta_out = beta (initial vector)
 __global__ __launch_bounds__(256) void normalize_kernel(int n, int nblk, const double *__restrict__ partial,
                                                         const double2 *__restrict__ w, double2 *__restrict__ out,
                                                         double *__restrict__ beta_out)
@@ -382,6 +609,74 @@ __global__ __launch_bounds__(256) void normalize_kernel(int n, int nblk, const d
     if (r >= n) return;
     const double inv = beta > 0 ? 1.0 / beta : 0.0;
     out[r] = make_double2(w[r].x * inv, w[r].y * inv);
+}
+
+__device__ inline double2 cconj_mul(double2 a, double2 b)   // conj(a) * b
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// v_{j+1} = w / beta; block 0: Hessenberg column j (hsum, beta) through the
+// previous Givens rotations, the new rotation, g and the residual estimate.
+__global__ __launch_bounds__(256) void arnoldi_finish_kernel(int n, int nblk, const double *__restrict__ npart,
+                                                             const double2 *__restrict__ w, double2 *__restrict__ vnext,
+                                                             int j, int m, double tol, const double2 *__restrict__ hsum,
+                                                             double2 *__restrict__ R, double2 *__restrict__ g,
+                                                             double2 *__restrict__ cs, double2 *__restrict__ sn,
+                                                             KrylovState *__restrict__ st)
+{
+    if (st->done) return;
+    double s2 = 0;
+    for (int b = 0; b < nblk; ++b) s2 += npart[b];
+    const double beta = sqrt(s2);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) {
+        const double inv = beta > 0 ? 1.0 / beta : 0.0;
+        vnext[r] = make_double2(w[r].x * inv, w[r].y * inv);
+    }
+    if (blockIdx.x != 0) return;
+    extern __shared__ double2 sh[];   // [h: j+1][cs: j][sn: j]
+    double2 *hl = sh, *csl = sh + (j + 1), *snl = csl + j;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) hl[i] = hsum[i];
+    for (int i = threadIdx.x; i < j; i += blockDim.x) { csl[i] = cs[i]; snl[i] = sn[i]; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double2 *col = R + (int64_t)j * (m + 1);
+    double2 t = hl[0];
+    for (int i = 0; i < j; ++i) {
+        const double2 a = t, b = hl[i + 1], c = csl[i], sv = snl[i];
+        const double2 ca = cconj_mul(c, a), sb = cconj_mul(sv, b);
+        col[i] = make_double2(ca.x + sb.x, ca.y + sb.y);
+        const double2 sa = cmul(sv, a), cb = cmul(c, b);
+        t = make_double2(cb.x - sa.x, cb.y - sa.y);
+    }
+    const double den = sqrt(t.x * t.x + t.y * t.y + beta * beta);
+    double2 c = make_double2(1, 0), sv = make_double2(0, 0);
+    if (den > 0) { c = make_double2(t.x / den, t.y / den); sv = make_double2(beta / den, 0.0); }
+    cs[j] = c;
+    sn[j] = sv;
+    col[j] = make_double2(den, 0.0);
+    const double2 gj = g[j];
+    g[j] = cconj_mul(c, gj);
+    const double2 sg = cmul(sv, gj);
+    g[j + 1] = make_double2(-sg.x, -sg.y);
+    const double res = sqrt(sg.x * sg.x + sg.y * sg.y) / st->beta0;
+    st->resid = res;
+    st->iters = j + 1;
+    if (res <= tol || beta == 0.0 || j + 1 >= m) st->done = 1;
+}
+
+__global__ void krylov_init_kernel(int m, const double *__restrict__ beta0, double2 *__restrict__ g,
+                                   KrylovState *__restrict__ st)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= m) g[i] = make_double2(i == 0 ? *beta0 : 0.0, 0.0);
+    if (i == 0) {
+        st->beta0 = *beta0;
+        st->done = *beta0 == 0.0 ? 1 : 0;
+        st->iters = 0;
+        st->resid = *beta0 == 0.0 ? 0.0 : 1.0;
+    }
 }
 
 // x = sum_c y[c] Vb[c]
@@ -443,7 +738,7 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const double2 *src
 namespace {
 
 struct Work {
-    DevMem xin, y, z, b, r, Vb, partial, hsum, beta, yc, npart;
+    DevMem xin, y, z, b, r, Vb, partial, hsum, beta, yc, npart, R, g, cs, sn, state;
 };
 
 MtfArgs make_args(const bem_problem *p)
@@ -464,15 +759,21 @@ MtfArgs make_args(const bem_problem *p)
     return A;
 }
 
-bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, double2 *y, double2 *z, bool strong)
+bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, double2 *y, double2 *z, bool strong,
+                   const KrylovState *kst = nullptr)
 {
     hipStream_t st = p->ctx->stream;
     const int rows = A.ne + A.ni;
-    hipLaunchKernelGGL(mtf_dense_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, A, x, y);
+    (void)rows;
+    {
+        KTimer kt(p->ctx, K_MTF_DENSE);
+        hipLaunchKernelGGL(mtf_dense_kernel<MV_RPW>, rows_grid(A.ne, A.ni, MV_RPW), dim3(256), 0, st, A, x, y, kst);
+    }
     BEM_HIP(hipGetLastError());
     if (strong) {
-        hipLaunchKernelGGL(mass_apply_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, A.ne, A.ni,
-                           p->Minv[0].as<double>(), p->Minv[1].as<double>(), y, z);
+        KTimer kt(p->ctx, K_MASS_APPLY);
+        hipLaunchKernelGGL(mass_apply_kernel<MASS_RPW>, rows_grid(A.ne, A.ni, MASS_RPW), dim3(256), 0, st, A.ne, A.ni,
+                           p->Minv[0].as<double>(), p->Minv[1].as<double>(), y, z, kst);
         BEM_HIP(hipGetLastError());
     }
     return BEM_OK;
@@ -552,8 +853,10 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     hipStream_t st = ctx->stream;
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne + 2 * ni;
     const int m = opts->maxit;
+    if (m > MAXIT_CAP) return set_error(BEM_E_ARG, "maxit above 3000");
     const size_t vb = (size_t)n * sizeof(double2);
-    const int nblk = (n + CGS_CHUNK - 1) / CGS_CHUNK;
+    const int nchunk = (n + CGS_CHUNK - 1) / CGS_CHUNK;
+    const int nrow_blk = (n + 255) / 256;
     Work W;
     bem_status s = dev_alloc(ctx, W.y, vb);
     if (!s) s = dev_alloc(ctx, W.z, vb);
@@ -561,85 +864,105 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     if (!s) s = dev_alloc(ctx, W.r, vb);
     if (!s) s = dev_alloc(ctx, W.xin, vb);
     if (!s) s = dev_alloc(ctx, W.Vb, (size_t)(m + 1) * vb);
-    if (!s) s = dev_alloc(ctx, W.partial, (size_t)nblk * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.partial, (size_t)nchunk * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.hsum, (size_t)(m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.beta, sizeof(double) * 2);
     if (!s) s = dev_alloc(ctx, W.yc, (size_t)(m + 1) * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.npart, (size_t)nblk * sizeof(double));
+    if (!s) s = dev_alloc(ctx, W.npart, (size_t)nrow_blk * sizeof(double));
+    if (!s) s = dev_alloc(ctx, W.R, (size_t)m * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.g, (size_t)(m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.cs, (size_t)m * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.sn, (size_t)m * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.state, sizeof(KrylovState));
     if (s) return s;
+    KrylovState *hstate = nullptr;   // two pinned slots polled alternately
+    BEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstate), 2 * sizeof(KrylovState), hipHostMallocDefault));
+    struct PinGuard { KrylovState *p; ~PinGuard() { if (p) (void)hipHostFree(p); } } guard{hstate};
+    hipEvent_t ev[2];
+    BEM_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    BEM_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    struct EvGuard { hipEvent_t *e; ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); } } eguard{ev};
     MtfArgs A = make_args(p);
     double2 *Vb = W.Vb.as<double2>();
-    const dim3 gv((n + 255) / 256);
+    KrylovState *dst = W.state.as<KrylovState>();
+    const dim3 gv(nrow_blk);
+    const int BATCH = 8;
+    const size_t finish_lds = (size_t)(3 * m + 1) * sizeof(double2);
+    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&arnoldi_finish_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)finish_lds));
     int total_it = 0;
     double worst_res = 0.0;
     bool all_conv = true;
     auto t0 = std::chrono::steady_clock::now();
-    std::vector<cd> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), h(m + 1);
     for (int rhs = 0; rhs < nrhs; ++rhs) {
         s = rhs_internal(p, dirs + 3 * rhs, W.b.as<double2>());
         if (s) return s;
-        // r0 = M^-1 b (x0 = 0), v0 = r0 / ||r0||
-        hipLaunchKernelGGL(mass_apply_kernel, dim3((ne + ni + 3) / 4), dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
-                           p->Minv[1].as<double>(), W.b.as<double2>(), W.r.as<double2>());
-        hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(256), 0, st, n, W.r.as<double2>(), W.npart.as<double>());
-        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nblk, W.npart.as<double>(), W.r.as<double2>(), Vb,
-                           W.beta.as<double>());
+        // r0 = M^-1 b (x0 = 0), v0 = r0 / ||r0||, g = [beta0, 0, ...]
+        hipLaunchKernelGGL(mass_apply_kernel<MASS_RPW>, rows_grid(ne, ni, MASS_RPW), dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
+                           p->Minv[1].as<double>(), W.b.as<double2>(), W.r.as<double2>(), nullptr);
+        hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, W.r.as<double2>(), W.npart.as<double>());
+        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), W.r.as<double2>(),
+                           Vb, W.beta.as<double>());
+        hipLaunchKernelGGL(krylov_init_kernel, dim3((m + 256) / 256), dim3(256), 0, st, m, W.beta.as<double>(),
+                           W.g.as<double2>(), dst);
         BEM_HIP(hipGetLastError());
-        double beta0 = 0;
-        BEM_HIP(hipMemcpyAsync(&beta0, W.beta.ptr, sizeof(double), hipMemcpyDeviceToHost, st));
-        BEM_HIP(hipStreamSynchronize(st));
-        std::fill(g.begin(), g.end(), cd(0));
-        g[0] = beta0;
-        int j = 0;
-        bool conv = beta0 == 0.0;
-        double res = conv ? 0.0 : 1.0;
-        for (; j < m && !conv; ++j) {
+        int issued = 0, checked_done = 0, slot = 0, pending = -1;
+        for (int j = 0; j < m; ++j) {
             const double2 *vj = Vb + (size_t)j * n;
-            s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true);
+            s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst);
             if (s) return s;
-            BEM_HIP(hipMemsetAsync(W.hsum.ptr, 0, (size_t)(j + 1) * sizeof(double2), st));
             for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(cgs_dots_kernel, dim3(nblk), dim3(256), 0, st, n, j + 1, Vb, W.z.as<double2>(),
-                                   W.partial.as<double2>());
+                {
+                    KTimer kt(ctx, K_CGS_DOTS);
+                    hipLaunchKernelGGL(cgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4), dim3(256), 0, st, n, j + 1, Vb,
+                                       W.z.as<double2>(), W.partial.as<double2>(), dst);
+                }
+                KTimer kt(ctx, K_CGS_UPDATE);
                 hipLaunchKernelGGL(cgs_update_kernel, gv, dim3(256), (size_t)(j + 1) * sizeof(double2), st, n, j + 1,
-                                   nblk, Vb, W.partial.as<double2>(), W.z.as<double2>(), W.hsum.as<double2>());
+                                   nchunk, Vb, W.partial.as<double2>(), W.z.as<double2>(), W.hsum.as<double2>(), pass,
+                                   W.npart.as<double>(), dst);
             }
-            hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(256), 0, st, n, W.z.as<double2>(), W.npart.as<double>());
-            hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nblk, W.npart.as<double>(), W.z.as<double2>(),
-                               Vb + (size_t)(j + 1) * n, W.beta.as<double>());
+            {
+                KTimer kt(ctx, K_ARNOLDI_FINISH);
+                hipLaunchKernelGGL(arnoldi_finish_kernel, gv, dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, n,
+                                   nrow_blk, W.npart.as<double>(), W.z.as<double2>(), Vb + (size_t)(j + 1) * n, j, m,
+                                   opts->tol, W.hsum.as<double2>(), W.R.as<double2>(), W.g.as<double2>(),
+                                   W.cs.as<double2>(), W.sn.as<double2>(), dst);
+            }
             BEM_HIP(hipGetLastError());
-            BEM_HIP(hipMemcpyAsync(h.data(), W.hsum.ptr, (size_t)(j + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
-            double beta = 0;
-            BEM_HIP(hipMemcpyAsync(&beta, W.beta.ptr, sizeof(double), hipMemcpyDeviceToHost, st));
-            BEM_HIP(hipStreamSynchronize(st));
-            // Hessenberg column j, previous rotations, new rotation
-            cd *col = &H[(size_t)j * (m + 1)];
-            for (int i = 0; i <= j; ++i) col[i] = h[i];
-            col[j + 1] = beta;
-            for (int i = 0; i < j; ++i) {
-                cd a = col[i], b = col[i + 1];
-                col[i] = std::conj(cs[i]) * a + std::conj(sn[i]) * b;
-                col[i + 1] = -sn[i] * a + cs[i] * b;
+            issued = j + 1;
+            if (issued % BATCH == 0) {
+                // snapshot this batch's state; test the previous snapshot (already complete or nearly)
+                BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+                BEM_HIP(hipEventRecord(ev[slot], st));
+                if (pending >= 0) {
+                    BEM_HIP(hipEventSynchronize(ev[pending]));
+                    if (hstate[pending].done) { checked_done = 1; break; }
+                }
+                pending = slot;
+                slot ^= 1;
             }
-            double den = std::sqrt(std::norm(col[j]) + std::norm(col[j + 1]));
-            if (den == 0.0) { cs[j] = 1; sn[j] = 0; }
-            else { cs[j] = col[j] / den; sn[j] = col[j + 1] / den; }
-            col[j] = den;
-            col[j + 1] = 0;
-            cd gj = g[j];
-            g[j] = std::conj(cs[j]) * gj;
-            g[j + 1] = -sn[j] * gj;
-            res = std::abs(g[j + 1]) / beta0;
-            if (res <= opts->tol || beta == 0.0) conv = true;
         }
-        const int k = j;
+        (void)checked_done;
+        (void)issued;
+        KrylovState fin;
+        BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+        BEM_HIP(hipStreamSynchronize(st));
+        fin = hstate[slot];
+        const int k = fin.iters;
         total_it += k;
-        // back substitution R y = g
-        std::vector<cd> yv(k);
+        // back substitution R y = g on the host (k x k upper triangular)
+        std::vector<cd> Rh((size_t)std::max(k, 1) * (m + 1)), gh(m + 1);
+        if (k > 0) {
+            BEM_HIP(hipMemcpyAsync(Rh.data(), W.R.ptr, (size_t)k * (m + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipMemcpyAsync(gh.data(), W.g.ptr, (size_t)(m + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipStreamSynchronize(st));
+        }
+        std::vector<cd> yv(std::max(k, 1));
         for (int i = k - 1; i >= 0; --i) {
-            cd sacc = g[i];
-            for (int c = i + 1; c < k; ++c) sacc -= H[(size_t)c * (m + 1) + i] * yv[c];
-            yv[i] = sacc / H[(size_t)i * (m + 1) + i];
+            cd sacc = gh[i];
+            for (int c = i + 1; c < k; ++c) sacc -= Rh[(size_t)c * (m + 1) + i] * yv[c];
+            yv[i] = sacc / Rh[(size_t)i * (m + 1) + i];
         }
         if (k > 0) BEM_HIP(hipMemcpyAsync(W.yc.ptr, yv.data(), (size_t)k * sizeof(double2), hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(combine_kernel, gv, dim3(256), 0, st, n, k, Vb, W.yc.as<double2>(), W.xin.as<double2>());
@@ -648,10 +971,10 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         s = apply_A(p, A, W.xin.as<double2>(), W.y.as<double2>(), W.z.as<double2>(), false);
         if (s) return s;
         hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), W.y.as<double2>(), W.r.as<double2>());
-        hipLaunchKernelGGL(mass_apply_kernel, dim3((ne + ni + 3) / 4), dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
-                           p->Minv[1].as<double>(), W.r.as<double2>(), W.z.as<double2>());
-        hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(256), 0, st, n, W.z.as<double2>(), W.npart.as<double>());
-        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nblk, W.npart.as<double>(), W.z.as<double2>(),
+        hipLaunchKernelGGL(mass_apply_kernel<MASS_RPW>, rows_grid(ne, ni, MASS_RPW), dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
+                           p->Minv[1].as<double>(), W.r.as<double2>(), W.z.as<double2>(), nullptr);
+        hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, W.z.as<double2>(), W.npart.as<double>());
+        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), W.z.as<double2>(),
                            W.r.as<double2>(), W.beta.as<double>() + 1);
         BEM_HIP(hipGetLastError());
         double rn = 0;
@@ -663,9 +986,9 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         BEM_HIP(hipMemcpyAsync(static_cast<double2 *>(traces) + (size_t)rhs * n, W.y.ptr, vb,
                                space == BEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
         BEM_HIP(hipStreamSynchronize(st));
-        const double rel = beta0 > 0 ? rn / beta0 : 0.0;
+        const double rel = fin.beta0 > 0 ? rn / fin.beta0 : 0.0;
         worst_res = std::max(worst_res, rel);
-        if (!(res <= opts->tol)) all_conv = false;
+        if (!(fin.resid <= opts->tol)) all_conv = false;
     }
     const double t_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) {
