@@ -100,13 +100,16 @@ KTimer::KTimer(bem_ctx *ctx, int kid) : c(ctx), id(kid)
     if (!c || !(c->ktiming >> kid & 1u)) return;
     a = take_event(c);
     b = take_event(c);
-    if (a && b) (void)hipEventRecord(a, c->stream);
+    if (!a || !b) {
+        if (a) c->pool.push_back(a);
+        if (b) c->pool.push_back(b);
+        a = b = nullptr;
+    }
 }
 
 KTimer::~KTimer()
 {
     if (!a || !b) return;
-    (void)hipEventRecord(b, c->stream);
     c->pending.push_back({id, a, b});
 }
 

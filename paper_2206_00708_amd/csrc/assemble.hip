@@ -483,12 +483,12 @@ bem_status launch_regular(const bem_mesh *m, double k, double2 *scratch, double2
     for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
         const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
         KTimer kt(m->ctx, K_REGULAR);
-        hipLaunchKernelGGL(regular_tiles_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+        launch_k(kt, regular_tiles_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
         BEM_HIP(hipGetLastError());
     }
     const int nv = (int)m->h.nv;
     KTimer kt(m->ctx, K_GATHER);
-    hipLaunchKernelGGL(gather_tiles_kernel, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, A.nb,
+    launch_k(kt, gather_tiles_kernel, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, A.nb,
                        m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(), scratch, ops[0], ops[1], ops[2],
                        ops[3]);
     BEM_HIP(hipGetLastError());
@@ -503,14 +503,14 @@ bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *gl
     const int np = (int)m->h.sing.size();
     if (np > 0) {
         KTimer kt(m->ctx, K_SINGULAR);
-        hipLaunchKernelGGL(singular_pairs_kernel, dim3((np + 15) / 16), dim3(256), 0, st, m->d.geo.as<TriGeo>(),
+        launch_k(kt, singular_pairs_kernel, dim3((np + 15) / 16), dim3(256), 0, st, m->d.geo.as<TriGeo>(),
                            m->d.sing.as<SingPair>(), np, ng, gl, k, contrib);
         BEM_HIP(hipGetLastError());
     }
     const int nn = (int)m->h.near_i.size();
     if (nn > 0) {
         KTimer kt(m->ctx, K_NEAR);
-        hipLaunchKernelGGL(near_scatter_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, (int)m->h.nv, nn,
+        launch_k(kt, near_scatter_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, (int)m->h.nv, nn,
                            m->d.near_i.as<int32_t>(), m->d.near_j.as<int32_t>(), m->d.near_ptr.as<int32_t>(),
                            m->d.near_src.as<int32_t>(), m->d.sing.as<SingPair>(), contrib, ops[0], ops[1], ops[2],
                            ops[3]);

@@ -1,9 +1,12 @@
 // Private declarations of the bemtx library (not part of the C ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -100,6 +103,11 @@ bem_status hip_error(hipError_t e, const char *what);
     } while (0)
 
 bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes);
+
+// Run f(begin, end) over [0, n) split into contiguous ranges on up to 16 host
+// threads (serial below `grain` items).  Ranges are fixed by n, so results
+// that each range writes to its own slots are independent of scheduling.
+void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &f);
 bem_status mesh_prepare(MeshData &m);                    // validation + tables (host)
 void mass_csr(const MeshData &m, Csr &M);
 bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *coverage_defect);
@@ -133,7 +141,9 @@ struct bem_ctx {
 };
 
 namespace bemtx {
-// Brackets one kernel launch with timing events when the context asks for it.
+// Timing events for one kernel launch when the context asks for it; the
+// events ride on the dispatch itself (hipExtLaunchKernel), so they measure
+// the kernel's execution and nothing queued around it.
 struct KTimer {
     bem_ctx *c;
     int id;
@@ -141,6 +151,18 @@ struct KTimer {
     KTimer(bem_ctx *ctx, int kid);
     ~KTimer();
 };
+
+// Launch `kernel` on `st`, timed by `kt` when it holds events.
+template <typename... KArgs, typename... Args>
+inline void launch_k(const KTimer &kt, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shmem, hipStream_t st,
+                     Args &&...args)
+{
+    if (kt.a && kt.b)
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shmem, st, kt.a, kt.b, 0, std::forward<Args>(args)...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shmem, st, std::forward<Args>(args)...);
+}
+
 // Resolve finished timings (call after the stream has been synchronised).
 void flush_kernel_timing(bem_ctx *ctx);
 }  // namespace bemtx

@@ -15,7 +15,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
-#include <unordered_map>
+#include <thread>
 
 #include "internal.h"
 
@@ -30,6 +30,20 @@ static uint64_t spread3(uint64_t v)
     v = (v | v << 4) & 0x10c30c30c30c30c3ULL;
     v = (v | v << 2) & 0x1249249249249249ULL;
     return v;
+}
+
+void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &f)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    int64_t nth = std::max<int64_t>(1, std::min<int64_t>(16, hw ? hw : 1));
+    nth = std::min<int64_t>(nth, std::max<int64_t>(1, n / std::max<int64_t>(1, grain)));
+    if (nth <= 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    for (int64_t t = 0; t < nth; ++t) pool.emplace_back(f, n * t / nth, n * (t + 1) / nth);
+    for (auto &th : pool) th.join();
 }
 
 bem_status mesh_prepare(MeshData &m)
@@ -181,14 +195,15 @@ bem_status mesh_prepare(MeshData &m)
 
     // ---- ordered singular pairs, kinds 3 / 2 / 1, corner permutations
     std::vector<SingPair> by_kind[4];
+    for (int k = 1; k <= 3; ++k) by_kind[k].reserve(k == 1 ? 10 * nt : (k == 2 ? 3 * nt : nt));
+    std::vector<int64_t> seen_by(nt, -1);
     for (int64_t t = 0; t < nt; ++t) {
-        std::vector<int32_t> seen;
         for (int a = 0; a < 3; ++a) {
             int32_t v = m.tri[3 * t + a];
             for (int32_t e = m.star_ptr[v]; e < m.star_ptr[v + 1]; ++e) {
                 int32_t s = m.star_ent[e] / 3;
-                if (std::find(seen.begin(), seen.end(), s) != seen.end()) continue;
-                seen.push_back(s);
+                if (seen_by[s] == t) continue;
+                seen_by[s] = t;
                 int sx[3], sy[3], ns = 0;
                 for (int i = 0; i < 3; ++i)
                     for (int j = 0; j < 3; ++j)
@@ -232,22 +247,50 @@ bem_status mesh_prepare(MeshData &m)
                 for (int b = 0; b < 3; ++b)
                     byrow[fill[i]++] = {m.tri[3 * m.sing[p].sig + b], (int32_t)(p * 9 + a * 3 + b)};
             }
-        m.near_i.clear(); m.near_j.clear(); m.near_ptr.clear(); m.near_src.resize(nc);
-        size_t q = 0;
-        for (int64_t i = 0; i < nv; ++i) {
-            auto b0 = byrow.begin() + row_cnt[i], b1 = byrow.begin() + row_cnt[i + 1];
-            std::stable_sort(b0, b1, [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
-                return x.first < y.first;
-            });
-            for (auto it = b0; it != b1; ++it, ++q) {
-                if (it == b0 || it->first != (it - 1)->first) {
-                    m.near_ptr.push_back((int32_t)q);
-                    m.near_i.push_back((int32_t)i);
-                    m.near_j.push_back(it->first);
+        // group each row's contributions by column j in order of first appearance
+        // (deterministic; contributions keep their pair order within an entry);
+        // rows in parallel: count distinct columns, prefix, then fill
+        std::vector<int32_t> nuniq(nv + 1, 0);
+        auto group_rows = [&](int64_t r0, int64_t r1, bool fill) {
+            std::vector<int32_t> mark(nv, -1), slot_of(nv, 0), ucol, ucnt, off;
+            for (int64_t i = r0; i < r1; ++i) {
+                ucol.clear();
+                ucnt.clear();
+                for (int32_t e = row_cnt[i]; e < row_cnt[i + 1]; ++e) {
+                    const int32_t j = byrow[e].first;
+                    if (mark[j] != (int32_t)i) {
+                        mark[j] = (int32_t)i;
+                        slot_of[j] = (int32_t)ucol.size();
+                        ucol.push_back(j);
+                        ucnt.push_back(0);
+                    }
+                    ucnt[slot_of[j]]++;
                 }
-                m.near_src[q] = it->second;
+                if (!fill) {
+                    nuniq[i + 1] = (int32_t)ucol.size();
+                    continue;
+                }
+                off.resize(ucol.size());
+                int32_t acc = row_cnt[i];
+                for (size_t u = 0; u < ucol.size(); ++u) {
+                    const size_t k = (size_t)nuniq[i] + u;
+                    m.near_ptr[k] = acc;
+                    m.near_i[k] = (int32_t)i;
+                    m.near_j[k] = ucol[u];
+                    off[u] = acc;
+                    acc += ucnt[u];
+                }
+                for (int32_t e = row_cnt[i]; e < row_cnt[i + 1]; ++e)
+                    m.near_src[off[slot_of[byrow[e].first]]++] = byrow[e].second;
             }
-        }
+        };
+        parallel_for(nv, 256, [&](int64_t a, int64_t b) { group_rows(a, b, false); });
+        for (int64_t i = 0; i < nv; ++i) nuniq[i + 1] += nuniq[i];
+        m.near_i.assign(nuniq[nv], 0);
+        m.near_j.assign(nuniq[nv], 0);
+        m.near_ptr.assign(nuniq[nv], 0);
+        m.near_src.assign(nc, 0);
+        parallel_for(nv, 256, [&](int64_t a, int64_t b) { group_rows(a, b, true); });
         m.near_ptr.push_back((int32_t)nc);
     }
     return BEM_OK;

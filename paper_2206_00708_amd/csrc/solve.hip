@@ -8,20 +8,25 @@
 // with mass-matrix (strong-form) preconditioning blockdiag(M_e, M_e, M_i,
 // M_i)^-1 (Sec. 3.3) and GMRES without restart (Sec. 5.1).
 //
-//   mass_inverse_kernel  dense M^-1 by Chebyshev iteration on Jacobi-scaled M
-//                        (the spectrum of diag(M)^-1 M of P1 triangles lies
-//                        in [1/2, 2], so 40 steps reach rounding level);
-//                        search directions live in LDS, one workgroup per
-//                        group of columns.
-//   mtf_dense_kernel     one wave per row, streams the four dense rows of the
-//                        row's mesh once (complex128, 16 B per lane, coalesced)
-//                        and adds the mortar coupling of that row (CSR).
-//   mass_apply_kernel    z = M^-1 y for the two vectors of one mesh at once.
-//   cgs_dots / cgs_update / norm kernels: classical Gram-Schmidt with one
-//                        re-orthogonalisation in FP64, reductions in a fixed
-//                        order (deterministic).
-//   Givens rotations and the convergence test run on the host from the
-//   (j+2) Hessenberg entries copied back each step.
+//   mass_inverse kernels   dense M^-1 by Chebyshev iteration on Jacobi-scaled
+//                          M (the spectrum of diag(M)^-1 M of P1 triangles
+//                          lies in [1/2, 2], so 40 steps reach rounding
+//                          level); search directions live in LDS, several
+//                          columns per workgroup.
+//   mtf_dense_part         the four dense blocks of each row streamed once
+//                          (complex128, 16 B per lane, coalesced,
+//                          non-temporal) against a column chunk of [v; w]
+//                          staged in LDS; per-chunk partial sums.
+//   mtf_combine            fixed-order sum of the chunk partials plus the
+//                          mortar coupling of the row (CSR).
+//   mass_apply_part/combine  z = M^-1 y, same split-column scheme.
+//   cgs_dots / cgs_update / arnoldi_finish   classical Gram-Schmidt with one
+//                          re-orthogonalisation in FP64 and the Givens
+//                          rotations of the new Hessenberg column on the
+//                          device; reductions in a fixed order
+//                          (deterministic).
+//   The host issues steps ahead and polls a small state record; it learns of
+//   convergence without stalling the device.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -257,7 +262,7 @@ static bem_status launch_minv_r(bem_problem *p, int nv, int mesh)
     BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_kernel<R>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer kt(p->ctx, K_MASS_INVERSE);
-    hipLaunchKernelGGL(mass_inverse_kernel<R>, dim3(nv), dim3(1024), lds, p->ctx->stream, nv, minv_ld(nv),
+    launch_k(kt, mass_inverse_kernel<R>, dim3(nv), dim3(1024), lds, p->ctx->stream, nv, minv_ld(nv),
                        p->M_ptr[mesh].as<int32_t>(), p->M_col[mesh].as<int32_t>(), p->M_val[mesh].as<double>(),
                        p->Minv[mesh].as<double>());
     BEM_HIP(hipGetLastError());
@@ -271,7 +276,7 @@ static bem_status launch_minv_ell(bem_problem *p, int nv, int W, int mesh, const
     BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_ell_kernel<R, C>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer kt(p->ctx, K_MASS_INVERSE);
-    hipLaunchKernelGGL((mass_inverse_ell_kernel<R, C>), dim3((nv + C - 1) / C), dim3(1024), lds, p->ctx->stream, nv,
+    launch_k(kt, mass_inverse_ell_kernel<R, C>, dim3((nv + C - 1) / C), dim3(1024), lds, p->ctx->stream, nv,
                        minv_ld(nv), W, ec, ev, p->Minv[mesh].as<double>());
     BEM_HIP(hipGetLastError());
     return BEM_OK;
@@ -364,151 +369,163 @@ struct MtfArgs {
     double c_ext_v, c_ext_w, c_int_v, c_int_w;   // 1/2, 1/2 re/ri, -1/2, -1/2 ri/re
 };
 
-// y = A x (weak form).  Each wave owns RPW consecutive rows of one mesh
-// (rows of [ext ; int] are grouped so no wave straddles the two meshes) and
-// streams their four dense rows once (complex128, 16 B per lane, coalesced,
-// non-temporal); each x element loaded serves all RPW rows.  The mortar
-// coupling of each row (CSR) is added before the wave reduction.
-template <int RPW>
-__global__ __launch_bounds__(256) void mtf_dense_kernel(MtfArgs A, const double2 *__restrict__ x, double2 *__restrict__ y,
-                                                        const KrylovState *__restrict__ st)
+// ---- split-column forms: x chunk staged in LDS, per-chunk partial sums,
+// fixed-order combine.  Rows of the two meshes form one grid; chunk widths
+// are multiples of 64 chosen per mesh.
+
+constexpr int SPLIT_CW_MAX = 512;   // columns per chunk (upper bound)
+constexpr int SPLIT_ROWS = 4;       // rows per workgroup (one per wave)
+
+__host__ __device__ inline int split_nchunk(int nv) { return (nv + SPLIT_CW_MAX - 1) / SPLIT_CW_MAX; }
+__host__ __device__ inline int split_cw(int nv)
+{
+    const int nc = split_nchunk(nv);
+    return ((nv + nc - 1) / nc + 63) / 64 * 64;
+}
+
+// part[chunk][row] = (sum over the chunk of [-K V] row . [v; w], of [D T] row . [v; w])
+__global__ __launch_bounds__(256) void mtf_dense_part_kernel(MtfArgs A, const double2 *__restrict__ x,
+                                                             double4 *__restrict__ part,
+                                                             const KrylovState *__restrict__ st)
 {
     if (st && st->done) return;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    const int we = (A.ne + RPW - 1) / RPW, wi = (A.ni + RPW - 1) / RPW;
-    if (wave >= we + wi) return;
-    const bool ext = wave < we;
-    const int i0 = (ext ? wave : wave - we) * RPW;
+    __shared__ double2 xs[2 * SPLIT_CW_MAX];
+    const int te = (A.ne + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    const bool ext = (int)blockIdx.x < te;
     const int nv = ext ? A.ne : A.ni;
-    const int nr = min(RPW, nv - i0);
-    const double2 *Km = ext ? A.Ke : A.Ki, *Vm = ext ? A.Ve : A.Vi, *Dm = ext ? A.De : A.Di, *Tm = ext ? A.Te : A.Ti;
+    const int chunk = blockIdx.y;
+    if (chunk >= split_nchunk(nv)) return;
+    const int cw = split_cw(nv);
+    const int c0 = chunk * cw, c1 = min(nv, c0 + cw), ncol = c1 - c0;
     const double2 *xv = ext ? x : x + 2 * A.ne;
     const double2 *xw = xv + nv;
-    double ar[RPW], ai[RPW], br[RPW], bi[RPW];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = br[r] = bi[r] = 0.0;
-    for (int j = lane; j < nv; j += 64) {
-        const double2 p0 = xv[j], q0 = xw[j];
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            if (r < nr) {
-                const int64_t o = (int64_t)(i0 + r) * nv + j;
-                const double2 k0 = ld_stream(&Km[o]), v0 = ld_stream(&Vm[o]);
-                const double2 d0 = ld_stream(&Dm[o]), t0 = ld_stream(&Tm[o]);
-                ar[r] += -(k0.x * p0.x - k0.y * p0.y) + (v0.x * q0.x - v0.y * q0.y);
-                ai[r] += -(k0.x * p0.y + k0.y * p0.x) + (v0.x * q0.y + v0.y * q0.x);
-                br[r] += (d0.x * p0.x - d0.y * p0.y) + (t0.x * q0.x - t0.y * q0.y);
-                bi[r] += (d0.x * p0.y + d0.y * p0.x) + (t0.x * q0.y + t0.y * q0.x);
-            }
-        }
+    for (int t = threadIdx.x; t < ncol; t += blockDim.x) { xs[t] = xv[c0 + t]; xs[SPLIT_CW_MAX + t] = xw[c0 + t]; }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = (ext ? blockIdx.x : blockIdx.x - te) * SPLIT_ROWS + wave;
+    if (i >= nv) return;
+    const double2 *Km = ext ? A.Ke : A.Ki, *Vm = ext ? A.Ve : A.Vi, *Dm = ext ? A.De : A.Di, *Tm = ext ? A.Te : A.Ti;
+    const int64_t o = (int64_t)i * nv + c0;
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    for (int j = lane; j < ncol; j += 64) {
+        const double2 k0 = ld_stream(&Km[o + j]), v0 = ld_stream(&Vm[o + j]);
+        const double2 d0 = ld_stream(&Dm[o + j]), t0 = ld_stream(&Tm[o + j]);
+        const double2 p0 = xs[j], q0 = xs[SPLIT_CW_MAX + j];
+        ar += -(k0.x * p0.x - k0.y * p0.y) + (v0.x * q0.x - v0.y * q0.y);
+        ai += -(k0.x * p0.y + k0.y * p0.x) + (v0.x * q0.y + v0.y * q0.x);
+        br += (d0.x * p0.x - d0.y * p0.y) + (t0.x * q0.x - t0.y * q0.y);
+        bi += (d0.x * p0.y + d0.y * p0.x) + (t0.x * q0.y + t0.y * q0.x);
     }
-    // mortar coupling of each row
+    ar = wave_sum(ar); ai = wave_sum(ai); br = wave_sum(br); bi = wave_sum(bi);
+    if (lane == 0) {
+        const int row = ext ? i : A.ne + i;
+        part[(int64_t)chunk * (A.ne + A.ni) + row] = make_double4(ar, ai, br, bi);
+    }
+}
+
+// y rows = sum of the chunk partials (fixed order) + mortar coupling; one thread per row
+__global__ __launch_bounds__(256) void mtf_combine_kernel(MtfArgs A, const double2 *__restrict__ x,
+                                                          const double4 *__restrict__ part, double2 *__restrict__ y,
+                                                          const KrylovState *__restrict__ st)
+{
+    if (st && st->done) return;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= A.ne + A.ni) return;
+    const bool ext = row < A.ne;
+    const int i = ext ? row : row - A.ne;
+    const int nv = ext ? A.ne : A.ni;
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    const int nch = split_nchunk(nv);
+    for (int c = 0; c < nch; ++c) {
+        const double4 q = part[(int64_t)c * (A.ne + A.ni) + row];
+        ar += q.x; ai += q.y; br += q.z; bi += q.w;
+    }
     const int32_t *pp = ext ? A.pei_ptr : A.pie_ptr;
     const int32_t *pc = ext ? A.pei_col : A.pie_col;
     const double *pv = ext ? A.pei_val : A.pie_val;
-    const double2 *cv = ext ? x + 2 * A.ne : x;           // other mesh's v
+    const double2 *cv = ext ? x + 2 * A.ne : x;
     const int nother = ext ? A.ni : A.ne;
-    const double2 *cw = cv + nother;                        // other mesh's w
+    const double2 *cw = cv + nother;
     const double fv = ext ? A.c_ext_v : A.c_int_v, fw = ext ? A.c_ext_w : A.c_int_w;
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        if (r < nr) {
-            const int i = i0 + r;
-            for (int q = pp[i] + lane; q < pp[i + 1]; q += 64) {
-                const double pvq = pv[q];
-                const int c = pc[q];
-                ar[r] += fv * pvq * cv[c].x;
-                ai[r] += fv * pvq * cv[c].y;
-                br[r] += fw * pvq * cw[c].x;
-                bi[r] += fw * pvq * cw[c].y;
-            }
-        }
-        ar[r] = wave_sum(ar[r]);
-        ai[r] = wave_sum(ai[r]);
-        br[r] = wave_sum(br[r]);
-        bi[r] = wave_sum(bi[r]);
+    double sr = 0, si = 0, tr = 0, ti = 0;
+    for (int q = pp[i]; q < pp[i + 1]; ++q) {
+        const double pvq = pv[q];
+        const double2 a = cv[pc[q]], b = cw[pc[q]];
+        sr += pvq * a.x; si += pvq * a.y; tr += pvq * b.x; ti += pvq * b.y;
     }
-    if (lane < nr) {
-        double2 *ya = ext ? y : y + 2 * A.ne;
-        double sar = 0, sai = 0, sbr = 0, sbi = 0;
-#pragma unroll
-        for (int r = 0; r < RPW; ++r)
-            if (r == lane) { sar = ar[r]; sai = ai[r]; sbr = br[r]; sbi = bi[r]; }
-        ya[i0 + lane] = make_double2(sar, sai);
-        ya[i0 + lane + nv] = make_double2(sbr, sbi);
-    }
+    double2 *ya = ext ? y : y + 2 * A.ne;
+    ya[i] = make_double2(ar + fv * sr, ai + fv * si);
+    ya[i + nv] = make_double2(br + fw * tr, bi + fw * ti);
 }
 
-// z = blockdiag(M_e^-1, M_e^-1, M_i^-1, M_i^-1) y; each wave owns RPW rows of
-// one mesh, two columns per lane per step (16-byte loads of the even-strided
-// rows), and applies them to the two vectors of that mesh at once.
-template <int RPW>
-__global__ __launch_bounds__(256) void mass_apply_kernel(int ne, int ni, const double *__restrict__ Me_inv,
-                                                         const double *__restrict__ Mi_inv,
-                                                         const double2 *__restrict__ y, double2 *__restrict__ z,
-                                                         const KrylovState *__restrict__ st)
+// part[chunk][row] = M^-1 row chunk applied to the mesh's two vectors
+__global__ __launch_bounds__(256) void mass_apply_part_kernel(int ne, int ni, const double *__restrict__ Me_inv,
+                                                              const double *__restrict__ Mi_inv,
+                                                              const double2 *__restrict__ y, double4 *__restrict__ part,
+                                                              const KrylovState *__restrict__ st)
 {
     if (st && st->done) return;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int lane = threadIdx.x & 63;
-    const int we = (ne + RPW - 1) / RPW, wi = (ni + RPW - 1) / RPW;
-    if (wave >= we + wi) return;
-    const bool ext = wave < we;
-    const int i0 = (ext ? wave : wave - we) * RPW;
+    __shared__ double2 ys[2 * SPLIT_CW_MAX];
+    const int te = (ne + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    const bool ext = (int)blockIdx.x < te;
     const int nv = ext ? ne : ni;
-    const int nr = min(RPW, nv - i0);
-    const int ld = minv_ld(nv);
-    const double *M0 = (ext ? Me_inv : Mi_inv) + (int64_t)i0 * ld;
+    const int chunk = blockIdx.y;
+    if (chunk >= split_nchunk(nv)) return;
+    const int cw = split_cw(nv);
+    const int c0 = chunk * cw, c1 = min(nv, c0 + cw), ncol = c1 - c0;
     const double2 *ya = ext ? y : y + 2 * ne;
     const double2 *yb = ya + nv;
-    double ar[RPW], ai[RPW], br[RPW], bi[RPW];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) ar[r] = ai[r] = br[r] = bi[r] = 0.0;
-    const int npair = nv >> 1;
-    for (int h = lane; h < npair; h += 64) {
-        const double2 a0 = ya[2 * h], a1 = ya[2 * h + 1], b0 = yb[2 * h], b1 = yb[2 * h + 1];
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            if (r < nr) {
-                const v2d m = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(M0 + (int64_t)r * ld) + h);
-                ar[r] += m.x * a0.x + m.y * a1.x; ai[r] += m.x * a0.y + m.y * a1.y;
-                br[r] += m.x * b0.x + m.y * b1.x; bi[r] += m.x * b0.y + m.y * b1.y;
-            }
+    for (int t = threadIdx.x; t < ncol; t += blockDim.x) { ys[t] = ya[c0 + t]; ys[SPLIT_CW_MAX + t] = yb[c0 + t]; }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = (ext ? blockIdx.x : blockIdx.x - te) * SPLIT_ROWS + wave;
+    if (i >= nv) return;
+    const double *Mr = (ext ? Me_inv : Mi_inv) + (int64_t)i * minv_ld(nv) + c0;   // c0 is even (multiple of 64)
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    for (int h = lane; 2 * h < ncol; h += 64) {
+        const int j = 2 * h;
+        if (j + 1 < ncol) {
+            const v2d m = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(Mr) + h);
+            const double2 a0 = ys[j], a1 = ys[j + 1], b0 = ys[SPLIT_CW_MAX + j], b1 = ys[SPLIT_CW_MAX + j + 1];
+            ar += m.x * a0.x + m.y * a1.x; ai += m.x * a0.y + m.y * a1.y;
+            br += m.x * b0.x + m.y * b1.x; bi += m.x * b0.y + m.y * b1.y;
+        } else {
+            const double m = Mr[j];
+            const double2 a0 = ys[j], b0 = ys[SPLIT_CW_MAX + j];
+            ar += m * a0.x; ai += m * a0.y; br += m * b0.x; bi += m * b0.y;
         }
     }
-    if ((nv & 1) && lane == 0) {
-        const double2 a = ya[nv - 1], b = yb[nv - 1];
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            if (r < nr) {
-                const double m = M0[(int64_t)r * ld + nv - 1];
-                ar[r] += m * a.x; ai[r] += m * a.y; br[r] += m * b.x; bi[r] += m * b.y;
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < RPW; ++r) {
-        ar[r] = wave_sum(ar[r]); ai[r] = wave_sum(ai[r]); br[r] = wave_sum(br[r]); bi[r] = wave_sum(bi[r]);
-    }
-    if (lane < nr) {
-        double2 *za = ext ? z : z + 2 * ne;
-        double sar = 0, sai = 0, sbr = 0, sbi = 0;
-#pragma unroll
-        for (int r = 0; r < RPW; ++r)
-            if (r == lane) { sar = ar[r]; sai = ai[r]; sbr = br[r]; sbi = bi[r]; }
-        za[i0 + lane] = make_double2(sar, sai);
-        za[i0 + lane + nv] = make_double2(sbr, sbi);
+    ar = wave_sum(ar); ai = wave_sum(ai); br = wave_sum(br); bi = wave_sum(bi);
+    if (lane == 0) {
+        const int row = ext ? i : ne + i;
+        part[(int64_t)chunk * (ne + ni) + row] = make_double4(ar, ai, br, bi);
     }
 }
 
-constexpr int MV_RPW = 2;     // rows per wave, dense mat-vec
-constexpr int MASS_RPW = 4;   // rows per wave, inverse-mass apply
-
-static inline dim3 rows_grid(int ne, int ni, int rpw)
+__global__ __launch_bounds__(256) void mass_combine_kernel(int ne, int ni, const double4 *__restrict__ part,
+                                                           double2 *__restrict__ z, const KrylovState *__restrict__ st)
 {
-    const int waves = (ne + rpw - 1) / rpw + (ni + rpw - 1) / rpw;
-    return dim3((waves + 3) / 4);
+    if (st && st->done) return;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= ne + ni) return;
+    const bool ext = row < ne;
+    const int i = ext ? row : row - ne;
+    const int nv = ext ? ne : ni;
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    const int nch = split_nchunk(nv);
+    for (int c = 0; c < nch; ++c) {
+        const double4 q = part[(int64_t)c * (ne + ni) + row];
+        ar += q.x; ai += q.y; br += q.z; bi += q.w;
+    }
+    double2 *za = ext ? z : z + 2 * ne;
+    za[i] = make_double2(ar, ai);
+    za[i + nv] = make_double2(br, bi);
+}
+
+static inline dim3 split_grid(int ne, int ni)
+{
+    const int tiles = (ne + SPLIT_ROWS - 1) / SPLIT_ROWS + (ni + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    return dim3(tiles, std::max(split_nchunk(ne), split_nchunk(ni)));
 }
 
 // ------------------------------------------------------ Krylov kernels
@@ -738,7 +755,7 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const double2 *src
 namespace {
 
 struct Work {
-    DevMem xin, y, z, b, r, Vb, partial, hsum, beta, yc, npart, R, g, cs, sn, state;
+    DevMem xin, y, z, b, r, Vb, partial, hsum, beta, yc, npart, R, g, cs, sn, state, part;
 };
 
 MtfArgs make_args(const bem_problem *p)
@@ -759,23 +776,38 @@ MtfArgs make_args(const bem_problem *p)
     return A;
 }
 
+size_t split_part_bytes(int ne, int ni)
+{
+    return (size_t)std::max(split_nchunk(ne), split_nchunk(ni)) * (ne + ni) * sizeof(double4);
+}
+
+// z = blockdiag(M_e, M_e, M_i, M_i)^-1 y
+bem_status apply_Minv(const bem_problem *p, const double2 *y, double2 *z, double4 *part, const KrylovState *kst)
+{
+    hipStream_t st = p->ctx->stream;
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
+    {
+        KTimer kt(p->ctx, K_MASS_APPLY);
+        launch_k(kt, mass_apply_part_kernel, split_grid(ne, ni), dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
+                 p->Minv[1].as<double>(), y, part, kst);
+    }
+    hipLaunchKernelGGL(mass_combine_kernel, dim3((ne + ni + 255) / 256), dim3(256), 0, st, ne, ni, part, z, kst);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+}
+
 bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, double2 *y, double2 *z, bool strong,
-                   const KrylovState *kst = nullptr)
+                   const KrylovState *kst, double4 *part)
 {
     hipStream_t st = p->ctx->stream;
     const int rows = A.ne + A.ni;
-    (void)rows;
     {
         KTimer kt(p->ctx, K_MTF_DENSE);
-        hipLaunchKernelGGL(mtf_dense_kernel<MV_RPW>, rows_grid(A.ne, A.ni, MV_RPW), dim3(256), 0, st, A, x, y, kst);
+        launch_k(kt, mtf_dense_part_kernel, split_grid(A.ne, A.ni), dim3(256), 0, st, A, x, part, kst);
     }
+    hipLaunchKernelGGL(mtf_combine_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, A, x, part, y, kst);
     BEM_HIP(hipGetLastError());
-    if (strong) {
-        KTimer kt(p->ctx, K_MASS_APPLY);
-        hipLaunchKernelGGL(mass_apply_kernel<MASS_RPW>, rows_grid(A.ne, A.ni, MASS_RPW), dim3(256), 0, st, A.ne, A.ni,
-                           p->Minv[0].as<double>(), p->Minv[1].as<double>(), y, z, kst);
-        BEM_HIP(hipGetLastError());
-    }
+    if (strong) return apply_Minv(p, y, z, part, kst);
     return BEM_OK;
 }
 
@@ -788,8 +820,9 @@ bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_m
     hipStream_t st = ctx->stream;
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne + 2 * ni;
     const size_t bytes = (size_t)n * sizeof(double2);
-    DevMem xu, xi, yi, zi, yu;
+    DevMem xu, xi, yi, zi, yu, part;
     bem_status s = dev_alloc(ctx, xu, bytes);
+    if (!s) s = dev_alloc(ctx, part, split_part_bytes(ne, ni));
     if (!s) s = dev_alloc(ctx, xi, bytes);
     if (!s) s = dev_alloc(ctx, yi, bytes);
     if (!s) s = dev_alloc(ctx, zi, bytes);
@@ -800,7 +833,7 @@ bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_m
     hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
                        p->inte->d.perm.as<int32_t>(), xu.as<double2>(), xi.as<double2>(), 1);
     MtfArgs A = make_args(p);
-    s = apply_A(p, A, xi.as<double2>(), yi.as<double2>(), zi.as<double2>(), strong != 0);
+    s = apply_A(p, A, xi.as<double2>(), yi.as<double2>(), zi.as<double2>(), strong != 0, nullptr, part.as<double4>());
     if (s) return s;
     hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
                        p->inte->d.perm.as<int32_t>(), strong ? zi.as<double2>() : yi.as<double2>(), yu.as<double2>(), 0);
@@ -874,6 +907,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     if (!s) s = dev_alloc(ctx, W.cs, (size_t)m * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.sn, (size_t)m * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.state, sizeof(KrylovState));
+    if (!s) s = dev_alloc(ctx, W.part, split_part_bytes(ne, ni));
     if (s) return s;
     KrylovState *hstate = nullptr;   // two pinned slots polled alternately
     BEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstate), 2 * sizeof(KrylovState), hipHostMallocDefault));
@@ -898,53 +932,72 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         s = rhs_internal(p, dirs + 3 * rhs, W.b.as<double2>());
         if (s) return s;
         // r0 = M^-1 b (x0 = 0), v0 = r0 / ||r0||, g = [beta0, 0, ...]
-        hipLaunchKernelGGL(mass_apply_kernel<MASS_RPW>, rows_grid(ne, ni, MASS_RPW), dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
-                           p->Minv[1].as<double>(), W.b.as<double2>(), W.r.as<double2>(), nullptr);
+        s = apply_Minv(p, W.b.as<double2>(), W.r.as<double2>(), W.part.as<double4>(), nullptr);
+        if (s) return s;
         hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, W.r.as<double2>(), W.npart.as<double>());
         hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), W.r.as<double2>(),
                            Vb, W.beta.as<double>());
         hipLaunchKernelGGL(krylov_init_kernel, dim3((m + 256) / 256), dim3(256), 0, st, m, W.beta.as<double>(),
                            W.g.as<double2>(), dst);
         BEM_HIP(hipGetLastError());
-        int issued = 0, checked_done = 0, slot = 0, pending = -1;
-        for (int j = 0; j < m; ++j) {
+        // Issue policy: steps go out in batches of BATCH while the host checks
+        // the state snapshot of the previous batch (the device never waits on
+        // the host).  Once the observed convergence rate predicts the end
+        // within the steps already queued plus two batches, each step is
+        // followed by a synchronous check, so no step is issued after the one
+        // that converges.
+        int slot = 0, pending = -1, last_j = 0;
+        double last_res = 1.0;
+        bool sync_mode = false, stop = false;
+        for (int j = 0; j < m && !stop; ++j) {
             const double2 *vj = Vb + (size_t)j * n;
-            s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst);
+            s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
             if (s) return s;
             for (int pass = 0; pass < 2; ++pass) {
                 {
                     KTimer kt(ctx, K_CGS_DOTS);
-                    hipLaunchKernelGGL(cgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4), dim3(256), 0, st, n, j + 1, Vb,
-                                       W.z.as<double2>(), W.partial.as<double2>(), dst);
+                    launch_k(kt, cgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4), dim3(256), 0, st, n, j + 1, Vb,
+                             W.z.as<double2>(), W.partial.as<double2>(), dst);
                 }
                 KTimer kt(ctx, K_CGS_UPDATE);
-                hipLaunchKernelGGL(cgs_update_kernel, gv, dim3(256), (size_t)(j + 1) * sizeof(double2), st, n, j + 1,
-                                   nchunk, Vb, W.partial.as<double2>(), W.z.as<double2>(), W.hsum.as<double2>(), pass,
-                                   W.npart.as<double>(), dst);
+                launch_k(kt, cgs_update_kernel, gv, dim3(256), (size_t)(j + 1) * sizeof(double2), st, n, j + 1, nchunk,
+                         Vb, W.partial.as<double2>(), W.z.as<double2>(), W.hsum.as<double2>(), pass,
+                         W.npart.as<double>(), dst);
             }
             {
                 KTimer kt(ctx, K_ARNOLDI_FINISH);
-                hipLaunchKernelGGL(arnoldi_finish_kernel, gv, dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, n,
-                                   nrow_blk, W.npart.as<double>(), W.z.as<double2>(), Vb + (size_t)(j + 1) * n, j, m,
-                                   opts->tol, W.hsum.as<double2>(), W.R.as<double2>(), W.g.as<double2>(),
-                                   W.cs.as<double2>(), W.sn.as<double2>(), dst);
+                launch_k(kt, arnoldi_finish_kernel, gv, dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, n,
+                         nrow_blk, W.npart.as<double>(), W.z.as<double2>(), Vb + (size_t)(j + 1) * n, j, m, opts->tol,
+                         W.hsum.as<double2>(), W.R.as<double2>(), W.g.as<double2>(), W.cs.as<double2>(),
+                         W.sn.as<double2>(), dst);
             }
             BEM_HIP(hipGetLastError());
-            issued = j + 1;
-            if (issued % BATCH == 0) {
-                // snapshot this batch's state; test the previous snapshot (already complete or nearly)
+            const int issued = j + 1;
+            if (sync_mode) {
                 BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
-                BEM_HIP(hipEventRecord(ev[slot], st));
-                if (pending >= 0) {
-                    BEM_HIP(hipEventSynchronize(ev[pending]));
-                    if (hstate[pending].done) { checked_done = 1; break; }
-                }
-                pending = slot;
-                slot ^= 1;
+                BEM_HIP(hipStreamSynchronize(st));
+                stop = hstate[slot].done != 0;
+                continue;
             }
+            if (issued % BATCH != 0) continue;
+            BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipEventRecord(ev[slot], st));
+            if (pending >= 0) {
+                BEM_HIP(hipEventSynchronize(ev[pending]));
+                const KrylovState &k = hstate[pending];
+                if (k.done) { stop = true; break; }
+                // steps still to go at the observed geometric rate
+                if (last_j > 0 && k.iters > last_j && k.resid > 0 && last_res > 0) {
+                    const double rate = std::pow(k.resid / last_res, 1.0 / (k.iters - last_j));
+                    const double togo = rate < 1.0 ? std::log(opts->tol / k.resid) / std::log(rate) : 1e30;
+                    if (togo <= (issued - k.iters) + 2 * BATCH) sync_mode = true;
+                }
+                last_j = k.iters;
+                last_res = k.resid;
+            }
+            pending = slot;
+            slot ^= 1;
         }
-        (void)checked_done;
-        (void)issued;
         KrylovState fin;
         BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
         BEM_HIP(hipStreamSynchronize(st));
@@ -968,11 +1021,11 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         hipLaunchKernelGGL(combine_kernel, gv, dim3(256), 0, st, n, k, Vb, W.yc.as<double2>(), W.xin.as<double2>());
         BEM_HIP(hipGetLastError());
         // true strong-form residual in FP64: M^-1 (b - A x)
-        s = apply_A(p, A, W.xin.as<double2>(), W.y.as<double2>(), W.z.as<double2>(), false);
+        s = apply_A(p, A, W.xin.as<double2>(), W.y.as<double2>(), W.z.as<double2>(), false, nullptr, W.part.as<double4>());
         if (s) return s;
         hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), W.y.as<double2>(), W.r.as<double2>());
-        hipLaunchKernelGGL(mass_apply_kernel<MASS_RPW>, rows_grid(ne, ni, MASS_RPW), dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
-                           p->Minv[1].as<double>(), W.r.as<double2>(), W.z.as<double2>(), nullptr);
+        s = apply_Minv(p, W.r.as<double2>(), W.z.as<double2>(), W.part.as<double4>(), nullptr);
+        if (s) return s;
         hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, W.z.as<double2>(), W.npart.as<double>());
         hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), W.z.as<double2>(),
                            W.r.as<double2>(), W.beta.as<double>() + 1);
