@@ -151,7 +151,9 @@ bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t max
 /* Dense Galerkin matrices V, K, T, D on both meshes (Sec. 2.1, 2.4, 5.1),
  * device-resident.  parts: bit 0 = contributions of triangle pairs that share
  * no vertex, bit 1 = pairs that share a vertex (3 = the full operators; other
- * values exist for testing). */
+ * values exist for testing).  Returns once the work is queued on the context
+ * stream (so host work such as bem_assemble_projection overlaps it); every
+ * later call on the problem is ordered after it. */
 bem_status bem_assemble_operators(bem_problem *p, int32_t parts);
 
 /* Mass matrices M_ext, M_int and the mortar matrix P_int,ext (N_int x N_ext)

@@ -127,6 +127,25 @@ void flush_kernel_timing(bem_ctx *c)
     c->pending.clear();
 }
 
+// Read the assembly timings once the queued assembly has finished.
+bem_status resolve_assembly_timing(bem_problem *p)
+{
+    if (!p->asm_timing_pending) return BEM_OK;
+    BEM_HIP(hipEventSynchronize(p->asm_ev[1][2]));
+    double t_reg = 0, t_sing = 0;
+    for (int m = 0; m < 2; ++m) {
+        float a = 0, b = 0;
+        BEM_HIP(hipEventElapsedTime(&a, p->asm_ev[m][0], p->asm_ev[m][1]));
+        BEM_HIP(hipEventElapsedTime(&b, p->asm_ev[m][1], p->asm_ev[m][2]));
+        t_reg += a;
+        t_sing += b;
+    }
+    p->t_regular_ms = t_reg;
+    p->t_singular_ms = t_sing;
+    p->asm_timing_pending = false;
+    return BEM_OK;
+}
+
 static double ms_since(std::chrono::steady_clock::time_point t0)
 {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -281,7 +300,15 @@ bem_status bem_problem_create(bem_ctx *ctx, const bem_mesh *ext, const bem_mesh 
     return BEM_OK;
 }
 
-void bem_problem_destroy(bem_problem *p) { delete p; }
+void bem_problem_destroy(bem_problem *p)
+{
+    if (!p) return;
+    (void)hipStreamSynchronize(p->ctx->stream);
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 3; ++q)
+            if (p->asm_ev[m][q]) (void)hipEventDestroy(p->asm_ev[m][q]);
+    delete p;
+}
 
 bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t maxit, size_t *bytes)
 {
@@ -335,41 +362,33 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
         ctx->in_use += scratch_bytes;
     }
     double2 *scratch = static_cast<double2 *>(ctx->scratch);
-    hipEvent_t ev[5];
-    for (auto &e : ev) BEM_HIP(hipEventCreate(&e));
-    BEM_HIP(hipEventRecord(ev[0], st));
-    float t_reg = 0, t_sing = 0;
+    // events: [mesh][0] before regular, [1] before singular, [2] after; resolved lazily
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 3; ++q)
+            if (!p->asm_ev[m][q]) BEM_HIP(hipEventCreate(&p->asm_ev[m][q]));
     for (int m = 0; m < 2; ++m) {
         double2 *ops[4];
         for (int op = 0; op < 4; ++op) ops[op] = p->ops[m][op].as<double2>();
         const size_t nv = meshes[m]->h.nv;
-        BEM_HIP(hipEventRecord(ev[1], st));
+        BEM_HIP(hipEventRecord(p->asm_ev[m][0], st));
         if (parts & 1) {
             bem_status s = launch_regular(meshes[m], ks[m], scratch, ops, st);
             if (s) return s;
         } else {
             for (int op = 0; op < 4; ++op) BEM_HIP(hipMemsetAsync(ops[op], 0, nv * nv * sizeof(double2), st));
         }
-        BEM_HIP(hipEventRecord(ev[2], st));
+        BEM_HIP(hipEventRecord(p->asm_ev[m][1], st));
         if (parts & 2) {
             bem_status s = launch_singular(meshes[m], ks[m], p->ng, p->gl_x, p->gl_w, scratch, ops, st);
             if (s) return s;
         }
-        BEM_HIP(hipEventRecord(ev[3], st));
-        BEM_HIP(hipEventSynchronize(ev[3]));
-        float a = 0, b = 0;
-        BEM_HIP(hipEventElapsedTime(&a, ev[1], ev[2]));
-        BEM_HIP(hipEventElapsedTime(&b, ev[2], ev[3]));
-        t_reg += a;
-        t_sing += b;
+        BEM_HIP(hipEventRecord(p->asm_ev[m][2], st));
     }
-    for (auto &e : ev) (void)hipEventDestroy(e);
-    flush_kernel_timing(ctx);
-    p->t_regular_ms = t_reg;
-    p->t_singular_ms = t_sing;
+    p->asm_timing_pending = true;
     p->ops_ready = true;
     return BEM_OK;
 }
+
 
 bem_status bem_assemble_projection(bem_problem *p)
 {

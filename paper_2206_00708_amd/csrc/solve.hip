@@ -63,8 +63,12 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 // streaming load of a complex128 matrix entry (read once, do not keep in cache)
 __device__ inline double2 ld_stream(const double2 *p)
 {
+#ifdef BEMTX_NO_NT
+    return *p;
+#else
     const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p));
     return make_double2(v.x, v.y);
+#endif
 }
 
 __device__ inline double wave_sum(double v)
@@ -373,8 +377,14 @@ struct MtfArgs {
 // fixed-order combine.  Rows of the two meshes form one grid; chunk widths
 // are multiples of 64 chosen per mesh.
 
-constexpr int SPLIT_CW_MAX = 512;   // columns per chunk (upper bound)
-constexpr int SPLIT_ROWS = 4;       // rows per workgroup (one per wave)
+#ifndef BEMTX_SPLIT_CW
+#define BEMTX_SPLIT_CW 512
+#endif
+#ifndef BEMTX_MV_UNROLL
+#define BEMTX_MV_UNROLL 1
+#endif
+constexpr int SPLIT_CW_MAX = BEMTX_SPLIT_CW;   // columns per chunk (upper bound)
+constexpr int SPLIT_ROWS = 4;                  // rows per workgroup (one per wave)
 
 __host__ __device__ inline int split_nchunk(int nv) { return (nv + SPLIT_CW_MAX - 1) / SPLIT_CW_MAX; }
 __host__ __device__ inline int split_cw(int nv)
@@ -407,6 +417,7 @@ __global__ __launch_bounds__(256) void mtf_dense_part_kernel(MtfArgs A, const do
     const double2 *Km = ext ? A.Ke : A.Ki, *Vm = ext ? A.Ve : A.Vi, *Dm = ext ? A.De : A.Di, *Tm = ext ? A.Te : A.Ti;
     const int64_t o = (int64_t)i * nv + c0;
     double ar = 0, ai = 0, br = 0, bi = 0;
+#pragma unroll BEMTX_MV_UNROLL
     for (int j = lane; j < ncol; j += 64) {
         const double2 k0 = ld_stream(&Km[o + j]), v0 = ld_stream(&Vm[o + j]);
         const double2 d0 = ld_stream(&Dm[o + j]), t0 = ld_stream(&Tm[o + j]);
@@ -740,6 +751,8 @@ __global__ void permute_mat_kernel(int nv, const int32_t *__restrict__ perm, con
     dst[(int64_t)iu * nv + ju] = src[(int64_t)perm[iu] * nv + perm[ju]];
 }
 
+bem_status resolve_assembly_timing(bem_problem *p);
+
 bem_status permute_matrix_out(const bem_problem *p, int mesh, const double2 *src, double2 *dst)
 {
     const bem_mesh *m = mesh == 0 ? p->ext : p->inte;
@@ -1044,6 +1057,8 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         if (!(fin.resid <= opts->tol)) all_conv = false;
     }
     const double t_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    s = resolve_assembly_timing(p);
+    if (s) return s;
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
         stats->iterations = total_it;
