@@ -80,8 +80,8 @@ typedef struct {
 typedef struct {
     double tol;               /* relative residual of the strong form, ||M^-1(b - A x)|| / ||M^-1 b|| */
     int32_t maxit;            /* Arnoldi steps (no restart, Sec. 5.1), 1..3000 */
-    int32_t ir_max;           /* BEM_C64_MIXED: outer refinement steps */
-    double ir_inner_tol;      /* BEM_C64_MIXED: inner GMRES tolerance */
+    int32_t ir_max;           /* BEM_C64_MIXED: outer refinement steps (0: 10) */
+    double ir_inner_tol;      /* BEM_C64_MIXED: inner GMRES tolerance (0: automatic) */
 } bem_solver_opts;
 
 typedef struct {
@@ -167,7 +167,8 @@ bem_status bem_assemble_projection(bem_problem *p);
  * "mtf:discrete") to x: y = A x (strong = 0) or y = blockdiag(M_e, M_e, M_i,
  * M_i)^-1 A x (strong = 1).  x, y: complex128 [2 N_ext + 2 N_int] in the
  * unknown order [v_ext, w_ext, v_int, w_int], caller numbering.  Needs both
- * assemblies. */
+ * assemblies.  BEM_C64_MIXED problems apply the complex64 operators with
+ * FP32 accumulation (the product GMRES uses). */
 bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space);
 
 /* Right-hand side [-f, -g, 0, 0] of the multiple-traces system for the
@@ -183,13 +184,18 @@ bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b
  * total field satisfies p = -v_ext, dp/dn+ = -w_ext on Gamma_ext and
  * p = -v_int, dp/dn- = -w_int on Gamma_int.  Returns BEM_W_NOCONV if a
  * right-hand side did not reach opts->tol within opts->maxit (its best
- * iterate is written).  stats may be NULL. */
+ * iterate is written).  stats may be NULL.
+ * BEM_C64_MIXED: iterative refinement; each step solves the correction
+ * system with GMRES on FP32 products (FP64 Krylov basis) to opts->ir_inner_tol
+ * (0: half the remaining reduction, at least 1e-6), then recomputes
+ * M^-1 (b - A x) with FP64 arithmetic on the stored operators; at most
+ * opts->ir_max steps (0: 10) and opts->maxit Arnoldi steps in total. */
 bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
                      void *traces, bem_memspace space, bem_stats *stats);
 
 /* Copy one dense operator: mesh 0 = exterior, 1 = interior; op one of 'V',
- * 'K', 'T', 'D'.  dst: complex128 [N][N] (BEM_C128 problems) in caller
- * numbering. */
+ * 'K', 'T', 'D'.  dst: [N][N] in caller numbering, complex128 for BEM_C128
+ * problems and complex64 for BEM_C64_MIXED (the stored values). */
 bem_status bem_copy_operator(const bem_problem *p, int32_t mesh, char op, void *dst, bem_memspace space);
 
 /* Copy the mortar matrix P_int,ext as CSR in caller numbering (host arrays).

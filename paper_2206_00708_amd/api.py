@@ -105,6 +105,7 @@ class Problem:
                                     ctypes.byref(q), ctypes.byref(h)))
         self._h = h
         self.n = 2 * ext.nv + 2 * inte.nv
+        self.precision = precision
 
     def close(self):
         if getattr(self, "_h", None):
@@ -137,10 +138,10 @@ class Problem:
         _check(N.load().bem_mtf_rhs(self._h, d.ctypes.data, d.shape[0], _ptr(b), DEVICE))
         return b
 
-    def solve(self, dirs, tol=1e-6, maxit=1000):
+    def solve(self, dirs, tol=1e-6, maxit=1000, ir_max=0, ir_inner_tol=0.0):
         d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
         out = torch.empty((d.shape[0], self.n), dtype=torch.complex128, device=self.ctx.device)
-        opts = N.SolverOpts(tol, maxit, 0, 0.0)
+        opts = N.SolverOpts(tol, maxit, ir_max, ir_inner_tol)
         st = N.Stats()
         code = _check(N.load().bem_solve(self._h, d.ctypes.data, d.shape[0], ctypes.byref(opts), _ptr(out), DEVICE,
                                          ctypes.byref(st)))
@@ -148,7 +149,8 @@ class Problem:
 
     def operator(self, mesh, op):
         nv = self.ext.nv if mesh == 0 else self.inte.nv
-        out = torch.empty((nv, nv), dtype=torch.complex128, device=self.ctx.device)
+        dt = torch.complex128 if self.precision == C128 else torch.complex64
+        out = torch.empty((nv, nv), dtype=dt, device=self.ctx.device)
         _check(N.load().bem_copy_operator(self._h, mesh, op.encode(), _ptr(out), DEVICE))
         return out
 

@@ -68,16 +68,16 @@ static bem_status upload(bem_ctx *ctx, DevMem &m, const std::vector<T> &v)
 
 // kernels (assemble.hip, solve.hip)
 bem_status launch_geometry(const bem_mesh *m, hipStream_t st);
-size_t tile_scratch_bytes(const bem_mesh *m);
-bem_status launch_regular(const bem_mesh *m, double k, double2 *scratch, double2 *ops[4], hipStream_t st);
-bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw,
-                           double2 *contrib, double2 *ops[4], hipStream_t st);
+size_t tile_scratch_bytes(const bem_mesh *m, size_t entry_bytes);
+bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch, void *ops[4], hipStream_t st);
+bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw, bool fp32,
+                           double2 *contrib, void *ops[4], hipStream_t st);
 bem_status launch_mass_inverse(bem_problem *p, int mesh);
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats);
 bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space);
 bem_status rhs_impl(bem_problem *p, const double *dirs, int nrhs, void *b, bem_memspace space);
-bem_status permute_matrix_out(const bem_problem *p, int mesh, const double2 *src, double2 *dst);
+bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, void *dst);
 
 const char *const kKernelNames[K_COUNT] = {"regular_tiles", "gather_tiles", "singular_pairs", "near_scatter",
                                            "mtf_dense", "mass_apply", "cgs_dots", "cgs_update", "arnoldi_finish",
@@ -245,6 +245,7 @@ bem_status bem_mesh_create(bem_ctx *ctx, const double *xyz, int64_t nv, const in
     if (s == BEM_OK) s = upload(ctx, m->d.star_ptr, m->h.star_ptr);
     if (s == BEM_OK) s = upload(ctx, m->d.star_ent, m->h.star_ent);
     if (s == BEM_OK) s = dev_alloc(ctx, m->d.geo, (size_t)nt * sizeof(TriGeo));
+    if (s == BEM_OK) s = dev_alloc(ctx, m->d.geof, (size_t)nt * sizeof(TriGeoF));
     if (s == BEM_OK) s = launch_geometry(m, ctx->stream);
     if (s == BEM_OK) {
         hipError_t e = hipStreamSynchronize(ctx->stream);
@@ -271,7 +272,7 @@ bem_status bem_problem_create(bem_ctx *ctx, const bem_mesh *ext, const bem_mesh 
     if (!(k_ext > 0) || !(k_int > 0) || !(rho_ext > 0) || !(rho_int > 0) || !std::isfinite(k_ext) ||
         !std::isfinite(k_int) || !std::isfinite(rho_ext) || !std::isfinite(rho_int))
         return set_error(BEM_E_ARG, "wavenumbers and densities must be positive and finite");
-    if (precision != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "only BEM_C128 is available in this build");
+    if (precision != BEM_C128 && precision != BEM_C64_MIXED) return set_error(BEM_E_ARG, "unknown precision");
     for (int m = 0; m < 2; ++m) {
         const bemtx::MeshData &h = m == 0 ? ext->h : inte->h;
         double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -314,9 +315,10 @@ bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t max
 {
     if (!p || !bytes || nrhs < 1 || maxit < 1) return set_error(BEM_E_ARG, "bad argument");
     const size_t ne = p->ext->h.nv, ni = p->inte->h.nv, n = 2 * ne + 2 * ni;
-    size_t b = 4 * (ne * ne + ni * ni) * sizeof(double2);          // dense operators
-    b += (ne * ne + ni * ni) * sizeof(double);                     // dense inverse masses
-    size_t scratch = std::max(tile_scratch_bytes(p->ext), tile_scratch_bytes(p->inte));
+    const size_t eb = p->prec == BEM_C128 ? sizeof(double2) : sizeof(float2);
+    size_t b = 4 * (ne * op_ld(ne) + ni * op_ld(ni)) * eb;         // dense operators
+    b += (ne * ne + ni * ni) * (p->prec == BEM_C128 ? sizeof(double) : sizeof(float));   // dense inverse masses
+    size_t scratch = std::max(tile_scratch_bytes(p->ext, eb), tile_scratch_bytes(p->inte, eb));
     scratch = std::max(scratch, std::max(p->ext->h.sing.size(), p->inte->h.sing.size()) * 36 * sizeof(double2));
     b += scratch;
     b += (size_t)nrhs * ((size_t)(maxit + 1) * n + 8 * n) * sizeof(double2);   // Krylov bases + work vectors
@@ -334,15 +336,17 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
     hipStream_t st = ctx->stream;
     const bem_mesh *meshes[2] = {p->ext, p->inte};
     const double ks[2] = {p->k_ext, p->k_int};
+    const bool fp32 = p->prec == BEM_C64_MIXED;
+    const size_t eb = fp32 ? sizeof(float2) : sizeof(double2);
     size_t scratch_bytes = 16;
     for (int m = 0; m < 2; ++m) {
-        scratch_bytes = std::max(scratch_bytes, tile_scratch_bytes(meshes[m]));
+        scratch_bytes = std::max(scratch_bytes, tile_scratch_bytes(meshes[m], eb));
         scratch_bytes = std::max(scratch_bytes, meshes[m]->h.sing.size() * 36 * sizeof(double2));
     }
     for (int m = 0; m < 2; ++m) {
         const size_t nv = meshes[m]->h.nv;
         for (int op = 0; op < 4; ++op) {
-            bem_status s = dev_alloc(ctx, p->ops[m][op], nv * nv * sizeof(double2));
+            bem_status s = dev_alloc(ctx, p->ops[m][op], nv * op_ld(nv) * eb);
             if (s) return s;
         }
     }
@@ -361,25 +365,26 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
         ctx->scratch_bytes = scratch_bytes;
         ctx->in_use += scratch_bytes;
     }
-    double2 *scratch = static_cast<double2 *>(ctx->scratch);
+    void *scratch = ctx->scratch;
     // events: [mesh][0] before regular, [1] before singular, [2] after; resolved lazily
     for (int m = 0; m < 2; ++m)
         for (int q = 0; q < 3; ++q)
             if (!p->asm_ev[m][q]) BEM_HIP(hipEventCreate(&p->asm_ev[m][q]));
     for (int m = 0; m < 2; ++m) {
-        double2 *ops[4];
-        for (int op = 0; op < 4; ++op) ops[op] = p->ops[m][op].as<double2>();
+        void *ops[4];
+        for (int op = 0; op < 4; ++op) ops[op] = p->ops[m][op].ptr;
         const size_t nv = meshes[m]->h.nv;
         BEM_HIP(hipEventRecord(p->asm_ev[m][0], st));
         if (parts & 1) {
-            bem_status s = launch_regular(meshes[m], ks[m], scratch, ops, st);
+            bem_status s = launch_regular(meshes[m], ks[m], fp32, scratch, ops, st);
             if (s) return s;
         } else {
-            for (int op = 0; op < 4; ++op) BEM_HIP(hipMemsetAsync(ops[op], 0, nv * nv * sizeof(double2), st));
+            for (int op = 0; op < 4; ++op) BEM_HIP(hipMemsetAsync(ops[op], 0, nv * op_ld(nv) * eb, st));
         }
         BEM_HIP(hipEventRecord(p->asm_ev[m][1], st));
         if (parts & 2) {
-            bem_status s = launch_singular(meshes[m], ks[m], p->ng, p->gl_x, p->gl_w, scratch, ops, st);
+            bem_status s = launch_singular(meshes[m], ks[m], p->ng, p->gl_x, p->gl_w, fp32,
+                                           static_cast<double2 *>(scratch), ops, st);
             if (s) return s;
         }
         BEM_HIP(hipEventRecord(p->asm_ev[m][2], st));
@@ -458,11 +463,12 @@ bem_status bem_copy_operator(const bem_problem *p, int32_t mesh, char op, void *
     if (!p->ops_ready) return set_error(BEM_E_STATE, "operators not assembled");
     const int o = (int)(f - names);
     const bem_mesh *m = mesh == 0 ? p->ext : p->inte;
-    const size_t nv = m->h.nv, bytes = nv * nv * sizeof(double2);
+    const size_t eb = p->prec == BEM_C128 ? sizeof(double2) : sizeof(float2);
+    const size_t nv = m->h.nv, bytes = nv * nv * eb;
     bem_ctx *ctx = p->ctx;
     BEM_HIP(hipSetDevice(ctx->device));
     if (space == BEM_DEVICE) {
-        bem_status s = permute_matrix_out(p, mesh, p->ops[mesh][o].as<double2>(), static_cast<double2 *>(dst));
+        bem_status s = permute_matrix_out(p, mesh, p->ops[mesh][o].ptr, dst);
         if (s) return s;
         BEM_HIP(hipStreamSynchronize(ctx->stream));
         return BEM_OK;
@@ -470,7 +476,7 @@ bem_status bem_copy_operator(const bem_problem *p, int32_t mesh, char op, void *
     DevMem tmp;
     bem_status s = dev_alloc(ctx, tmp, bytes);
     if (s) return s;
-    s = permute_matrix_out(p, mesh, p->ops[mesh][o].as<double2>(), tmp.as<double2>());
+    s = permute_matrix_out(p, mesh, p->ops[mesh][o].ptr, tmp.ptr);
     if (s) return s;
     BEM_HIP(hipMemcpyAsync(dst, tmp.ptr, bytes, hipMemcpyDeviceToHost, ctx->stream));
     BEM_HIP(hipStreamSynchronize(ctx->stream));

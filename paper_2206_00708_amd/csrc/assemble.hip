@@ -53,7 +53,7 @@ __device__ inline double dot3(const double *a, const double *b) { return a[0] * 
 }  // namespace
 
 __global__ void geometry_kernel(const double *__restrict__ xyz, const int32_t *__restrict__ tri, int nt,
-                                TriGeo *__restrict__ geo)
+                                TriGeo *__restrict__ geo, TriGeoF *__restrict__ geof)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
@@ -73,6 +73,16 @@ __global__ void geometry_kernel(const double *__restrict__ xyz, const int32_t *_
         for (int c = 0; c < 3; ++c)
             g.qp[q][c] = r6_bary(q, 0) * g.p[0][c] + r6_bary(q, 1) * g.p[1][c] + r6_bary(q, 2) * g.p[2][c];
     geo[t] = g;
+    TriGeoF f;
+    for (int c = 0; c < 3; ++c) f.c[c] = (g.p[0][c] + g.p[1][c] + g.p[2][c]) / 3.0;
+    for (int q = 0; q < 6; ++q)
+        for (int c = 0; c < 3; ++c) f.dq[q][c] = (float)(g.qp[q][c] - f.c[c]);
+    for (int c = 0; c < 3; ++c) f.n[c] = (float)g.n[c];
+    f.area = (float)g.area;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c) f.curl[a][c] = (float)g.curl[a][c];
+    f.pad = 0.f;
+    geof[t] = f;
 }
 
 // ------------------------------------------------------------ regular pairs
@@ -101,6 +111,46 @@ __device__ inline void tile_of(int64_t t, int nb, int &b1, int &b2)
     b1 = b;
     b2 = b + (int)(t - ((int64_t)b * nb - (int64_t)b * (b - 1) / 2));
 }
+
+// Per-slot sums of the staged 9 entries of every triangle pair of the tile,
+// in a fixed order: entry (q1, q2) adds the entries (a, b) of every pair
+// whose test triangle has slot q1 at corner a and trial triangle slot q2 at
+// corner b.  Written to out[4 * e + op] (tile layout [entry][op]).
+template <class R, class C2>
+__device__ inline void tile_slot_sums(int tid, int op, int ns1, int ns2, const uint8_t *c1, const uint8_t *c2,
+                                      const uint8_t *e1, const uint8_t *e2, const R *st_re, const R *st_im, C2 *out)
+{
+    for (int e = tid; e < SMAX * SMAX; e += 256) {
+        const int q1 = e / SMAX, q2 = e - q1 * SMAX;
+        if (q1 >= ns1 || q2 >= ns2) continue;
+        R re = 0, im = 0;
+        const int m1 = c1[q1], m2 = c2[q2];
+        for (int u = 0; u < m1; ++u) {
+            const int en1 = e1[q1 * LMAX + u];
+            const int tt1 = en1 / 3, a = en1 - 3 * tt1;
+            for (int v = 0; v < m2; ++v) {
+                const int en2 = e2[q2 * LMAX + v];
+                const int tt2 = en2 / 3, b = en2 - 3 * tt2;
+                const int idx = (tt1 * 16 + tt2) * 9 + 3 * a + b;
+                re += st_re[idx];
+                im += st_im[idx];
+            }
+        }
+        out[4 * e + op] = C2{re, im};
+    }
+}
+
+struct TileArgsF {
+    const TriGeoF *geof;
+    const int32_t *tri;
+    const int32_t *blk_start;
+    const int32_t *blk_nslot;
+    const uint8_t *slot_cnt;
+    const uint8_t *slot_ent;
+    int32_t nb;
+    double k;
+    float2 *scratch;       // [tile][SMAX*SMAX][op]
+};
 
 __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64_t tile0)
 {
@@ -228,67 +278,201 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
             }
         }
         __syncthreads();
-        for (int e = tid; e < SMAX * SMAX; e += 256) {
-            const int q1 = e / SMAX, q2 = e - q1 * SMAX;
-            if (q1 >= ns1 || q2 >= ns2) continue;
-            double re = 0.0, im = 0.0;
-            const int m1 = c1[q1], m2 = c2[q2];
-            for (int u = 0; u < m1; ++u) {
-                const int en1 = e1[q1 * LMAX + u];
-                const int tt1 = en1 / 3, a = en1 - 3 * tt1;
-                for (int v = 0; v < m2; ++v) {
-                    const int en2 = e2[q2 * LMAX + v];
-                    const int tt2 = en2 / 3, b = en2 - 3 * tt2;
-                    const int idx = (tt1 * 16 + tt2) * 9 + 3 * a + b;
-                    re += st_re[idx];
-                    im += st_im[idx];
+        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st_re, st_im, out);
+        __syncthreads();
+    }
+}
+
+// Mixed-precision form of the regular-pair tile (FP32 arithmetic, complex64
+// tiles).  The phase k|x - y| is split per triangle pair: with d0 the FP64
+// centroid difference and r0 = |d0|, exp(i k r) = exp(i k r0) exp(i k D)
+// where exp(i k r0) is evaluated once in FP64 and D = r - r0 =
+// (2 d0.e + |e|^2) / (r + r0), e = (x - c_x) - (y - c_y), is small and
+// accurate in FP32; FP32 alone would lose about k r * 6e-8 of phase.
+__global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, int64_t tile0)
+{
+    __shared__ TriGeoF gX[BT], gY[BT];
+    __shared__ int32_t vX[BT * 3], vY[BT * 3];
+    __shared__ uint8_t c1[SMAX], c2[SMAX], e1[SMAX * LMAX], e2[SMAX * LMAX];
+    __shared__ float st_re[256 * 9], st_im[256 * 9];
+
+    const int64_t tile = tile0 + blockIdx.x;
+    int b1, b2;
+    tile_of(tile, A.nb, b1, b2);
+    const int s1 = A.blk_start[b1], n1 = A.blk_start[b1 + 1] - s1;
+    const int s2 = A.blk_start[b2], n2 = A.blk_start[b2 + 1] - s2;
+    const int ns1 = A.blk_nslot[b1], ns2 = A.blk_nslot[b2];
+    const int tid = threadIdx.x;
+    {
+        const double *src1 = reinterpret_cast<const double *>(A.geof + s1);
+        const double *src2 = reinterpret_cast<const double *>(A.geof + s2);
+        double *d1 = reinterpret_cast<double *>(gX), *d2 = reinterpret_cast<double *>(gY);
+        const int w = sizeof(TriGeoF) / sizeof(double);
+        for (int q = tid; q < n1 * w; q += 256) d1[q] = src1[q];
+        for (int q = tid; q < n2 * w; q += 256) d2[q] = src2[q];
+        if (tid < n1 * 3) vX[tid] = A.tri[3 * s1 + tid];
+        if (tid < n2 * 3) vY[tid] = A.tri[3 * s2 + tid];
+        if (tid < SMAX) { c1[tid] = A.slot_cnt[b1 * SMAX + tid]; c2[tid] = A.slot_cnt[b2 * SMAX + tid]; }
+        for (int q = tid; q < SMAX * LMAX; q += 256) {
+            e1[q] = A.slot_ent[(size_t)b1 * SMAX * LMAX + q];
+            e2[q] = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
+        }
+    }
+    __syncthreads();
+
+    const int t1 = tid >> 4, t2 = tid & 15;
+    bool active = t1 < n1 && t2 < n2;
+    if (active) {
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) active = active && (vX[3 * t1 + a] != vY[3 * t2 + b]);
+    }
+    float vr[9], vi[9], kr[9], ki[9], tr[9], ti[9], sr = 0.f, si = 0.f;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) { vr[e] = vi[e] = kr[e] = ki[e] = tr[e] = ti[e] = 0.f; }
+    const float kf = (float)A.k;
+    if (active) {
+        const TriGeoF &X = gX[t1];
+        const TriGeoF &Y = gY[t2];
+        const double d00 = X.c[0] - Y.c[0], d01 = X.c[1] - Y.c[1], d02 = X.c[2] - Y.c[2];
+        const double r0 = sqrt(d00 * d00 + d01 * d01 + d02 * d02);
+        double s0, c0;
+        phase_sincos(A.k * r0, &s0, &c0);
+        const float e0r = (float)c0, e0i = (float)s0;
+        const float f00 = (float)d00, f01 = (float)d01, f02 = (float)d02, r0f = (float)r0;
+        const float nx0 = X.n[0], nx1 = X.n[1], nx2 = X.n[2];
+        const float ny0 = Y.n[0], ny1 = Y.n[1], ny2 = Y.n[2];
+#pragma unroll 1
+        for (int p = 0; p < 6; ++p) {
+            const float x0 = X.dq[p][0], x1 = X.dq[p][1], x2 = X.dq[p][2];
+            float hvr[3] = {0, 0, 0}, hvi[3] = {0, 0, 0}, hkr[3] = {0, 0, 0}, hki[3] = {0, 0, 0};
+            float htr[3] = {0, 0, 0}, hti[3] = {0, 0, 0}, hsr = 0.f, hsi = 0.f;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const float q0 = x0 - Y.dq[q][0], q1 = x1 - Y.dq[q][1], q2 = x2 - Y.dq[q][2];   // e
+                const float d0 = f00 + q0, d1 = f01 + q1, d2 = f02 + q2;                         // x - y
+                const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
+                const float rinv = __frsqrt_rn(r2);
+                const float r = r2 * rinv;
+                const float num = 2.f * (f00 * q0 + f01 * q1 + f02 * q2) + (q0 * q0 + q1 * q1 + q2 * q2);
+                const float dr = num / (r + r0f);
+                float sd, cd;
+                sincosf(kf * dr, &sd, &cd);
+                const float er = e0r * cd - e0i * sd, ei = e0r * sd + e0i * cd;   // exp(ikr)
+                const float gr = er * rinv, gi = ei * rinv;
+                const float kr_ = kf * r, rinv2 = rinv * rinv;
+                const float fr = (-gr - gi * kr_) * rinv2, fi = (gr * kr_ - gi) * rinv2;
+                const float dk = -(d0 * ny0 + d1 * ny1 + d2 * ny2);
+                const float dt = d0 * nx0 + d1 * nx1 + d2 * nx2;
+                const float gkr = fr * dk, gki = fi * dk, gtr = fr * dt, gti = fi * dt;
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const float W = (float)(r6_w(q) * r6_bary(q, b));
+                    hvr[b] += W * gr; hvi[b] += W * gi;
+                    hkr[b] += W * gkr; hki[b] += W * gki;
+                    htr[b] += W * gtr; hti[b] += W * gti;
+                }
+                hsr += (float)r6_w(q) * gr;
+                hsi += (float)r6_w(q) * gi;
+            }
+            const float wp = p < 3 ? (float)kW1 : (float)kW2;
+            const float ap = p < 3 ? (float)kA1 : (float)kA2;
+            const float am = p < 3 ? (float)(1.0 - 2.0 * kA1) : (float)(1.0 - 2.0 * kA2);
+            const int pc = p < 3 ? p : p - 3;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float W = wp * (a == pc ? am : ap);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    vr[3 * a + b] += W * hvr[b]; vi[3 * a + b] += W * hvi[b];
+                    kr[3 * a + b] += W * hkr[b]; ki[3 * a + b] += W * hki[b];
+                    tr[3 * a + b] += W * htr[b]; ti[3 * a + b] += W * hti[b];
                 }
             }
-            out[4 * e + op] = make_double2(re, im);
+            sr += wp * hsr;
+            si += wp * hsi;
         }
+        const float scale = X.area * Y.area * (float)kInv4Pi;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            vr[e] *= scale; vi[e] *= scale; kr[e] *= scale; ki[e] *= scale; tr[e] *= scale; ti[e] *= scale;
+        }
+        sr *= scale;
+        si *= scale;
+    }
+    float2 *out = A.scratch + tile * (4 * SMAX * SMAX);
+#pragma unroll 1
+    for (int op = 0; op < 4; ++op) {
+        if (op == 3 && active) {
+            const TriGeoF &X = gX[t1];
+            const TriGeoF &Y = gY[t2];
+            const float nn = X.n[0] * Y.n[0] + X.n[1] * Y.n[1] + X.n[2] * Y.n[2];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const float cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
+                    st_re[tid * 9 + 3 * a + b] = cc * sr - kf * kf * nn * vr[3 * a + b];
+                    st_im[tid * 9 + 3 * a + b] = cc * si - kf * kf * nn * vi[3 * a + b];
+                }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                float re = op == 0 ? vr[e] : (op == 1 ? kr[e] : (op == 2 ? tr[e] : 0.f));
+                float im = op == 0 ? vi[e] : (op == 1 ? ki[e] : (op == 2 ? ti[e] : 0.f));
+                st_re[tid * 9 + e] = active ? re : 0.f;
+                st_im[tid * 9 + e] = active ? im : 0.f;
+            }
+        }
+        __syncthreads();
+        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st_re, st_im, out);
         __syncthreads();
     }
 }
 
 // dense entry (i, j) from the tiles of the blocks that contain i and j
+template <class C2>
 __global__ __launch_bounds__(256) void gather_tiles_kernel(int nv, int nb, const int32_t *__restrict__ memb_ptr,
-                                                           const int32_t *__restrict__ memb,
-                                                           const double2 *__restrict__ scratch,
-                                                           double2 *__restrict__ V, double2 *__restrict__ K,
-                                                           double2 *__restrict__ T, double2 *__restrict__ D)
+                                                           const int32_t *__restrict__ memb, const C2 *__restrict__ scratch,
+                                                           C2 *__restrict__ V, C2 *__restrict__ K, C2 *__restrict__ T,
+                                                           C2 *__restrict__ D)
 {
+    using R = decltype(C2::x);
     const int i = blockIdx.y;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nv) return;
     const int pi0 = memb_ptr[i], pi1 = memb_ptr[i + 1];
     const int pj0 = memb_ptr[j], pj1 = memb_ptr[j + 1];
-    double2 v = make_double2(0, 0), kk = v, t = v, d = v;
+    R vx = 0, vy = 0, kx = 0, ky = 0, tx = 0, ty = 0, dx = 0, dy = 0;
     for (int p = pi0; p < pi1; ++p) {
         const int mi = memb[p], bi = mi >> 8, si = mi & 255;
         for (int q = pj0; q < pj1; ++q) {
             const int mj = memb[q], bj = mj >> 8, sj = mj & 255;
             const int lo = bi < bj ? bi : bj, hi = bi < bj ? bj : bi;
             const int64_t tile = (int64_t)lo * nb - (int64_t)lo * (lo - 1) / 2 + (hi - lo);
-            const double2 *tl = scratch + tile * (4 * SMAX * SMAX);
+            const C2 *tl = scratch + tile * (4 * SMAX * SMAX);
             if (bi <= bj) {
                 const int e = si * SMAX + sj;
-                const double2 a0 = tl[4 * e], a1 = tl[4 * e + 1], a2 = tl[4 * e + 2], a3 = tl[4 * e + 3];
-                v.x += a0.x; v.y += a0.y; kk.x += a1.x; kk.y += a1.y;
-                t.x += a2.x; t.y += a2.y; d.x += a3.x; d.y += a3.y;
+                const C2 a0 = tl[4 * e], a1 = tl[4 * e + 1], a2 = tl[4 * e + 2], a3 = tl[4 * e + 3];
+                vx += a0.x; vy += a0.y; kx += a1.x; ky += a1.y;
+                tx += a2.x; ty += a2.y; dx += a3.x; dy += a3.y;
             } else {
                 // tile of (bj, bi): test side is j; K and T swap under transposition
                 const int e = sj * SMAX + si;
-                const double2 a0 = tl[4 * e], a1 = tl[4 * e + 1], a2 = tl[4 * e + 2], a3 = tl[4 * e + 3];
-                v.x += a0.x; v.y += a0.y; kk.x += a2.x; kk.y += a2.y;
-                t.x += a1.x; t.y += a1.y; d.x += a3.x; d.y += a3.y;
+                const C2 a0 = tl[4 * e], a1 = tl[4 * e + 1], a2 = tl[4 * e + 2], a3 = tl[4 * e + 3];
+                vx += a0.x; vy += a0.y; kx += a2.x; ky += a2.y;
+                tx += a1.x; ty += a1.y; dx += a3.x; dy += a3.y;
             }
         }
     }
-    const int64_t o = (int64_t)i * nv + j;
-    V[o] = v;
-    K[o] = kk;
-    T[o] = t;
-    D[o] = d;
+    const int64_t o = (int64_t)i * op_ld(nv) + j;
+    V[o] = C2{vx, vy};
+    K[o] = C2{kx, ky};
+    T[o] = C2{tx, ty};
+    D[o] = C2{dx, dy};
+    if ((nv & 1) && j == nv - 1) {   // padding column of odd rows: zero
+        V[o + 1] = C2{0, 0};
+        K[o + 1] = C2{0, 0};
+        T[o + 1] = C2{0, 0};
+        D[o + 1] = C2{0, 0};
+    }
 }
 
 // ----------------------------------------------------------- singular pairs
@@ -424,13 +608,14 @@ __global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__
         }
 }
 
-// add the singular contributions to their dense entries (fixed order)
+// add the singular contributions (FP64) to their dense entries (fixed order)
+template <class C2>
 __global__ void near_scatter_kernel(int nv, int nnear, const int32_t *__restrict__ ni, const int32_t *__restrict__ nj,
                                     const int32_t *__restrict__ nptr, const int32_t *__restrict__ nsrc,
-                                    const SingPair *__restrict__ pairs, const double2 *__restrict__ contrib,
-                                    double2 *__restrict__ V, double2 *__restrict__ K, double2 *__restrict__ T,
-                                    double2 *__restrict__ D)
+                                    const double2 *__restrict__ contrib, C2 *__restrict__ V, C2 *__restrict__ K,
+                                    C2 *__restrict__ T, C2 *__restrict__ D)
 {
+    using R = decltype(C2::x);
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nnear) return;
     double2 s[4] = {make_double2(0, 0), make_double2(0, 0), make_double2(0, 0), make_double2(0, 0)};
@@ -439,13 +624,11 @@ __global__ void near_scatter_kernel(int nv, int nnear, const int32_t *__restrict
         const double2 *c = contrib + (int64_t)pid * 36 + ab;
         for (int op = 0; op < 4; ++op) { s[op].x += c[9 * op].x; s[op].y += c[9 * op].y; }
     }
-    const int64_t o = (int64_t)ni[e] * nv + nj[e];
-    double2 *dst[4] = {V, K, T, D};
+    const int64_t o = (int64_t)ni[e] * op_ld(nv) + nj[e];
+    C2 *dst[4] = {V, K, T, D};
     for (int op = 0; op < 4; ++op) {
-        double2 x = dst[op][o];
-        x.x += s[op].x;
-        x.y += s[op].y;
-        dst[op][o] = x;
+        const C2 x = dst[op][o];
+        dst[op][o] = C2{(R)((double)x.x + s[op].x), (R)((double)x.y + s[op].y)};
     }
 }
 
@@ -455,48 +638,76 @@ bem_status launch_geometry(const bem_mesh *m, hipStream_t st)
 {
     const int nt = (int)m->h.nt;
     hipLaunchKernelGGL(geometry_kernel, dim3((nt + 255) / 256), dim3(256), 0, st, m->d.xyz.as<double>(),
-                       m->d.tri.as<int32_t>(), nt, m->d.geo.as<TriGeo>());
+                       m->d.tri.as<int32_t>(), nt, m->d.geo.as<TriGeo>(), m->d.geof.as<TriGeoF>());
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
 
-size_t tile_scratch_bytes(const bem_mesh *m)
+// tile scratch of one mesh; entry size 16 B (complex128) or 8 B (complex64)
+size_t tile_scratch_bytes(const bem_mesh *m, size_t entry_bytes)
 {
     const int64_t nb = m->h.nb;
-    return (size_t)(nb * (nb + 1) / 2) * 4 * SMAX * SMAX * sizeof(double2);
+    return (size_t)(nb * (nb + 1) / 2) * 4 * SMAX * SMAX * entry_bytes;
 }
 
-bem_status launch_regular(const bem_mesh *m, double k, double2 *scratch, double2 *ops[4], hipStream_t st)
+bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch, void *ops[4], hipStream_t st)
 {
-    TileArgs A;
-    A.geo = m->d.geo.as<TriGeo>();
-    A.tri = m->d.tri.as<int32_t>();
-    A.blk_start = m->d.blk_start.as<int32_t>();
-    A.blk_nslot = m->d.blk_nslot.as<int32_t>();
-    A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
-    A.slot_ent = m->d.slot_ent.as<uint8_t>();
-    A.nb = m->h.nb;
-    A.k = k;
-    A.scratch = scratch;
-    const int64_t ntiles = (int64_t)A.nb * (A.nb + 1) / 2;
+    const int64_t nb = m->h.nb;
+    const int64_t ntiles = nb * (nb + 1) / 2;
     const int64_t chunk = 1 << 20;
-    for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
-        const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
-        KTimer kt(m->ctx, K_REGULAR);
-        launch_k(kt, regular_tiles_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
-        BEM_HIP(hipGetLastError());
+    if (!fp32) {
+        TileArgs A;
+        A.geo = m->d.geo.as<TriGeo>();
+        A.tri = m->d.tri.as<int32_t>();
+        A.blk_start = m->d.blk_start.as<int32_t>();
+        A.blk_nslot = m->d.blk_nslot.as<int32_t>();
+        A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
+        A.slot_ent = m->d.slot_ent.as<uint8_t>();
+        A.nb = (int32_t)nb;
+        A.k = k;
+        A.scratch = static_cast<double2 *>(scratch);
+        for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
+            const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
+            KTimer kt(m->ctx, K_REGULAR);
+            launch_k(kt, regular_tiles_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+            BEM_HIP(hipGetLastError());
+        }
+    } else {
+        TileArgsF A;
+        A.geof = m->d.geof.as<TriGeoF>();
+        A.tri = m->d.tri.as<int32_t>();
+        A.blk_start = m->d.blk_start.as<int32_t>();
+        A.blk_nslot = m->d.blk_nslot.as<int32_t>();
+        A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
+        A.slot_ent = m->d.slot_ent.as<uint8_t>();
+        A.nb = (int32_t)nb;
+        A.k = k;
+        A.scratch = static_cast<float2 *>(scratch);
+        for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
+            const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
+            KTimer kt(m->ctx, K_REGULAR);
+            launch_k(kt, regular_tiles_f32_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+            BEM_HIP(hipGetLastError());
+        }
     }
     const int nv = (int)m->h.nv;
     KTimer kt(m->ctx, K_GATHER);
-    launch_k(kt, gather_tiles_kernel, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, A.nb,
-                       m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(), scratch, ops[0], ops[1], ops[2],
-                       ops[3]);
+    if (!fp32)
+        launch_k(kt, gather_tiles_kernel<double2>, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, (int)nb,
+                 m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(), static_cast<const double2 *>(scratch),
+                 static_cast<double2 *>(ops[0]), static_cast<double2 *>(ops[1]), static_cast<double2 *>(ops[2]),
+                 static_cast<double2 *>(ops[3]));
+    else
+        launch_k(kt, gather_tiles_kernel<float2>, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, (int)nb,
+                 m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(), static_cast<const float2 *>(scratch),
+                 static_cast<float2 *>(ops[0]), static_cast<float2 *>(ops[1]), static_cast<float2 *>(ops[2]),
+                 static_cast<float2 *>(ops[3]));
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
 
-bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw,
-                           double2 *contrib, double2 *ops[4], hipStream_t st)
+bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw, bool fp32,
+                           double2 *contrib, void *ops[4], hipStream_t st)
 {
     GLTab gl;
     for (int i = 0; i < NG_MAX; ++i) { gl.x[i] = i < ng ? glx[i] : 0.0; gl.w[i] = i < ng ? glw[i] : 0.0; }
@@ -504,16 +715,23 @@ bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *gl
     if (np > 0) {
         KTimer kt(m->ctx, K_SINGULAR);
         launch_k(kt, singular_pairs_kernel, dim3((np + 15) / 16), dim3(256), 0, st, m->d.geo.as<TriGeo>(),
-                           m->d.sing.as<SingPair>(), np, ng, gl, k, contrib);
+                 m->d.sing.as<SingPair>(), np, ng, gl, k, contrib);
         BEM_HIP(hipGetLastError());
     }
     const int nn = (int)m->h.near_i.size();
     if (nn > 0) {
         KTimer kt(m->ctx, K_NEAR);
-        launch_k(kt, near_scatter_kernel, dim3((nn + 255) / 256), dim3(256), 0, st, (int)m->h.nv, nn,
-                           m->d.near_i.as<int32_t>(), m->d.near_j.as<int32_t>(), m->d.near_ptr.as<int32_t>(),
-                           m->d.near_src.as<int32_t>(), m->d.sing.as<SingPair>(), contrib, ops[0], ops[1], ops[2],
-                           ops[3]);
+        const int nv = (int)m->h.nv;
+        if (!fp32)
+            launch_k(kt, near_scatter_kernel<double2>, dim3((nn + 255) / 256), dim3(256), 0, st, nv, nn,
+                     m->d.near_i.as<int32_t>(), m->d.near_j.as<int32_t>(), m->d.near_ptr.as<int32_t>(),
+                     m->d.near_src.as<int32_t>(), (const double2 *)contrib, static_cast<double2 *>(ops[0]),
+                     static_cast<double2 *>(ops[1]), static_cast<double2 *>(ops[2]), static_cast<double2 *>(ops[3]));
+        else
+            launch_k(kt, near_scatter_kernel<float2>, dim3((nn + 255) / 256), dim3(256), 0, st, nv, nn,
+                     m->d.near_i.as<int32_t>(), m->d.near_j.as<int32_t>(), m->d.near_ptr.as<int32_t>(),
+                     m->d.near_src.as<int32_t>(), (const double2 *)contrib, static_cast<float2 *>(ops[0]),
+                     static_cast<float2 *>(ops[1]), static_cast<float2 *>(ops[2]), static_cast<float2 *>(ops[3]));
         BEM_HIP(hipGetLastError());
     }
     return BEM_OK;

@@ -23,6 +23,10 @@ constexpr int SMAX = 24;
 constexpr int LMAX = 12;
 constexpr int NG_MAX = 16;
 
+// Row stride (elements) of the dense operator matrices: even, so a row of
+// complex64 entries starts on a 16-byte boundary.
+__host__ __device__ inline int64_t op_ld(int64_t nv) { return (nv + 1) & ~int64_t(1); }
+
 // Per-triangle geometry table, built on the device (40 doubles, 320 B).
 struct alignas(16) TriGeo {
     double p[3][3];     // vertices in the triangle's own corner order
@@ -30,6 +34,18 @@ struct alignas(16) TriGeo {
     double n[3];        // unit normal (right-hand rule, outward)
     double area;
     double curl[3][3];  // surface curl of the P1 function of corner a
+};
+
+// Single-precision geometry for the mixed-precision regular kernel: the
+// centroid stays FP64 and the quadrature points are stored relative to it,
+// so differences of nearby points keep full FP32 accuracy.
+struct alignas(8) TriGeoF {
+    double c[3];        // centroid
+    float dq[6][3];     // quadrature points minus centroid
+    float n[3];
+    float area;
+    float curl[3][3];
+    float pad;
 };
 
 // Ordered singular pair: x on `tau` (test), y on `sig` (trial); kind = shared
@@ -83,6 +99,7 @@ struct MeshData {
 
 struct MeshDev {
     DevMem perm;   // caller vertex -> internal vertex (int32)
+    DevMem geof;   // TriGeoF table
     DevMem xyz, tri, blk_start, blk_nslot, slot_cnt, slot_ent, memb_ptr, memb, sing, near_i, near_j,
         near_ptr, near_src, star_ptr, star_ent, geo;
 };

@@ -52,8 +52,9 @@ __host__ __device__ constexpr double q6_bary(int q, int c)
 }
 __host__ __device__ constexpr double q6_w(int q) { return q < 3 ? kW1 : kW2; }
 
-// row stride of the dense inverse mass matrices: even, so rows are 16-byte aligned
-__host__ __device__ inline int minv_ld(int nv) { return (nv + 1) & ~1; }
+// row stride of the dense inverse mass matrices: rows start on 16-byte
+// boundaries (even for FP64 storage, a multiple of four for FP32)
+__host__ __device__ inline int minv_ld(int nv, bool f32) { return f32 ? (nv + 3) & ~3 : (nv + 1) & ~1; }
 
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -127,10 +128,10 @@ __global__ void rhs_kernel(int ne, int ni, const int32_t *__restrict__ star_ptr,
 
 // Column c = blockIdx.x of M^-1 (= row c, M is symmetric), blockDim 1024,
 // R rows per thread kept in registers; the search direction lives in LDS.
-template <int R>
+template <int R, class TOut>
 __global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, int ldm, const int32_t *__restrict__ mp,
                                                              const int32_t *__restrict__ mc,
-                                                             const double *__restrict__ mv, double *__restrict__ Minv)
+                                                             const double *__restrict__ mv, TOut *__restrict__ Minv)
 {
     extern __shared__ double dsh[];   // [nv]
     const int col = blockIdx.x;
@@ -182,7 +183,7 @@ __global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, int ldm, con
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         const int row = tid + 1024 * k;
-        if (row < nv) Minv[(int64_t)col * ldm + row] = x[k];
+        if (row < nv) Minv[(int64_t)col * ldm + row] = (TOut)x[k];
     }
 }
 
@@ -190,10 +191,10 @@ __global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, int ldm, con
 // [q][row] so that loads are coalesced, padding = zero entries on the
 // diagonal) read from L2 once per step for all C columns, and the search
 // directions double-buffered in LDS so that one barrier per step suffices.
-template <int R, int C>
+template <int R, int C, class TOut>
 __global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm, int W, const int32_t *__restrict__ ell_col,
                                                                  const double *__restrict__ ell_val,
-                                                                 double *__restrict__ Minv)
+                                                                 TOut *__restrict__ Minv)
 {
     extern __shared__ double dsh[];   // [2][C][nv]
     const int c0 = blockIdx.x * C;
@@ -255,47 +256,76 @@ __global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm,
         if (row < nv)
 #pragma unroll
             for (int c = 0; c < C; ++c)
-                if (c0 + c < nv) Minv[(int64_t)(c0 + c) * ldm + row] = x[k][c];
+                if (c0 + c < nv) Minv[(int64_t)(c0 + c) * ldm + row] = (TOut)x[k][c];
     }
 }
 
-template <int R>
+template <int R, class TOut>
 static bem_status launch_minv_r(bem_problem *p, int nv, int mesh)
 {
     const size_t lds = (size_t)nv * sizeof(double);
-    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_kernel<R>),
+    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_kernel<R, TOut>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer kt(p->ctx, K_MASS_INVERSE);
-    launch_k(kt, mass_inverse_kernel<R>, dim3(nv), dim3(1024), lds, p->ctx->stream, nv, minv_ld(nv),
-                       p->M_ptr[mesh].as<int32_t>(), p->M_col[mesh].as<int32_t>(), p->M_val[mesh].as<double>(),
-                       p->Minv[mesh].as<double>());
+    launch_k(kt, mass_inverse_kernel<R, TOut>, dim3(nv), dim3(1024), lds, p->ctx->stream, nv,
+             minv_ld(nv, sizeof(TOut) == 4), p->M_ptr[mesh].as<int32_t>(), p->M_col[mesh].as<int32_t>(),
+             p->M_val[mesh].as<double>(), p->Minv[mesh].as<TOut>());
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
 
-template <int R, int C>
+template <int R, int C, class TOut>
 static bem_status launch_minv_ell(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev)
 {
     const size_t lds = (size_t)2 * C * nv * sizeof(double);
-    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_ell_kernel<R, C>),
+    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_ell_kernel<R, C, TOut>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer kt(p->ctx, K_MASS_INVERSE);
-    launch_k(kt, mass_inverse_ell_kernel<R, C>, dim3((nv + C - 1) / C), dim3(1024), lds, p->ctx->stream, nv,
-                       minv_ld(nv), W, ec, ev, p->Minv[mesh].as<double>());
+    launch_k(kt, mass_inverse_ell_kernel<R, C, TOut>, dim3((nv + C - 1) / C), dim3(1024), lds, p->ctx->stream, nv,
+             minv_ld(nv, sizeof(TOut) == 4), W, ec, ev, p->Minv[mesh].as<TOut>());
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
 
-template <int R>
+template <int R, class TOut>
 static bem_status launch_minv_ell_r(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev)
 {
     // columns per workgroup: as many double-buffered directions as fit in 160 KiB of LDS
     const int cfit = (int)(163840 / (2 * (size_t)nv * sizeof(double)));
-    if (cfit >= 8) return launch_minv_ell<R, 8>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 4) return launch_minv_ell<R, 4>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 3) return launch_minv_ell<R, 3>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 2) return launch_minv_ell<R, 2>(p, nv, W, mesh, ec, ev);
-    return launch_minv_ell<R, 1>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 8) return launch_minv_ell<R, 8, TOut>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 4) return launch_minv_ell<R, 4, TOut>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 3) return launch_minv_ell<R, 3, TOut>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 2) return launch_minv_ell<R, 2, TOut>(p, nv, W, mesh, ec, ev);
+    return launch_minv_ell<R, 1, TOut>(p, nv, W, mesh, ec, ev);
+}
+
+template <class TOut>
+static bem_status launch_minv_ell_any(bem_problem *p, int nv, int W, int mesh, const int32_t *dc, const double *dv)
+{
+    switch ((nv + 1023) / 1024) {
+    case 1: return launch_minv_ell_r<1, TOut>(p, nv, W, mesh, dc, dv);
+    case 2: return launch_minv_ell_r<2, TOut>(p, nv, W, mesh, dc, dv);
+    case 3: return launch_minv_ell_r<3, TOut>(p, nv, W, mesh, dc, dv);
+    case 4: return launch_minv_ell_r<4, TOut>(p, nv, W, mesh, dc, dv);
+    case 5: case 6: return launch_minv_ell_r<6, TOut>(p, nv, W, mesh, dc, dv);
+    case 7: case 8: return launch_minv_ell_r<8, TOut>(p, nv, W, mesh, dc, dv);
+    default: return launch_minv_ell_r<10, TOut>(p, nv, W, mesh, dc, dv);
+    }
+}
+
+template <class TOut>
+static bem_status launch_minv_csr_any(bem_problem *p, int nv, int mesh)
+{
+    switch ((nv + 1023) / 1024) {
+    case 1: return launch_minv_r<1, TOut>(p, nv, mesh);
+    case 2: return launch_minv_r<2, TOut>(p, nv, mesh);
+    case 3: return launch_minv_r<3, TOut>(p, nv, mesh);
+    case 4: return launch_minv_r<4, TOut>(p, nv, mesh);
+    case 5: case 6: return launch_minv_r<6, TOut>(p, nv, mesh);
+    case 7: case 8: return launch_minv_r<8, TOut>(p, nv, mesh);
+    case 9: case 10: case 11: case 12: return launch_minv_r<12, TOut>(p, nv, mesh);
+    default: return launch_minv_r<16, TOut>(p, nv, mesh);
+    }
 }
 
 bem_status launch_mass_inverse(bem_problem *p, int mesh)
@@ -303,8 +333,12 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh)
     const bem_mesh *m = mesh == 0 ? p->ext : p->inte;
     const int nv = (int)m->h.nv;
     if (nv > 16 * 1024) return set_error(BEM_E_UNSUPPORTED, "mass inverse: more than 16384 vertices on one mesh");
-    bem_status s = dev_alloc(p->ctx, p->Minv[mesh], (size_t)nv * minv_ld(nv) * sizeof(double));
+    const bool f32 = p->prec == BEM_C64_MIXED;
+    const size_t bytes = (size_t)nv * minv_ld(nv, f32) * (f32 ? sizeof(float) : sizeof(double));
+    bem_status s = dev_alloc(p->ctx, p->Minv[mesh], bytes);
     if (s) return s;
+    // padding columns must read as zero (vector loads cover them)
+    BEM_HIP(hipMemsetAsync(p->Minv[mesh].ptr, 0, bytes, p->ctx->stream));
     const Csr &M = p->M[mesh];
     int W = 0;
     for (int64_t i = 0; i < M.nrows; ++i) W = std::max(W, M.ptr[i + 1] - M.ptr[i]);
@@ -331,28 +365,10 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh)
                                p->ctx->stream));
         const int32_t *dc = p->M_ell_col[mesh].as<int32_t>();
         const double *dv = p->M_ell_val[mesh].as<double>();
-        const int R = (nv + 1023) / 1024;
-        switch (R) {
-        case 1: return launch_minv_ell_r<1>(p, nv, W, mesh, dc, dv);
-        case 2: return launch_minv_ell_r<2>(p, nv, W, mesh, dc, dv);
-        case 3: return launch_minv_ell_r<3>(p, nv, W, mesh, dc, dv);
-        case 4: return launch_minv_ell_r<4>(p, nv, W, mesh, dc, dv);
-        case 5: case 6: return launch_minv_ell_r<6>(p, nv, W, mesh, dc, dv);
-        case 7: case 8: return launch_minv_ell_r<8>(p, nv, W, mesh, dc, dv);
-        default: return launch_minv_ell_r<10>(p, nv, W, mesh, dc, dv);
-        }
+        return f32 ? launch_minv_ell_any<float>(p, nv, W, mesh, dc, dv)
+                   : launch_minv_ell_any<double>(p, nv, W, mesh, dc, dv);
     }
-    const int R = (nv + 1023) / 1024;
-    switch (R) {
-    case 1: return launch_minv_r<1>(p, nv, mesh);
-    case 2: return launch_minv_r<2>(p, nv, mesh);
-    case 3: return launch_minv_r<3>(p, nv, mesh);
-    case 4: return launch_minv_r<4>(p, nv, mesh);
-    case 5: case 6: return launch_minv_r<6>(p, nv, mesh);
-    case 7: case 8: return launch_minv_r<8>(p, nv, mesh);
-    case 9: case 10: case 11: case 12: return launch_minv_r<12>(p, nv, mesh);
-    default: return launch_minv_r<16>(p, nv, mesh);
-    }
+    return f32 ? launch_minv_csr_any<float>(p, nv, mesh) : launch_minv_csr_any<double>(p, nv, mesh);
 }
 
 // --------------------------------------------------------------- mat-vec
@@ -367,7 +383,8 @@ struct KrylovState {
 
 struct MtfArgs {
     int ne, ni;
-    const double2 *Ve, *Ke, *Te, *De, *Vi, *Ki, *Ti, *Di;
+    int cw;                  // chunk width bound of the split-column dense kernels
+    const void *op[2][4];    // [mesh][V, K, T, D], row stride op_ld(nv), complex128 or complex64
     const int32_t *pie_ptr, *pie_col, *pei_ptr, *pei_col;
     const double *pie_val, *pei_val;
     double c_ext_v, c_ext_w, c_int_v, c_int_w;   // 1/2, 1/2 re/ri, -1/2, -1/2 ri/re
@@ -380,20 +397,40 @@ struct MtfArgs {
 #ifndef BEMTX_SPLIT_CW
 #define BEMTX_SPLIT_CW 512
 #endif
+#ifndef BEMTX_SPLIT_CW32
+#define BEMTX_SPLIT_CW32 1024
+#endif
 #ifndef BEMTX_MV_UNROLL
 #define BEMTX_MV_UNROLL 1
 #endif
-constexpr int SPLIT_CW_MAX = BEMTX_SPLIT_CW;   // columns per chunk (upper bound)
-constexpr int SPLIT_ROWS = 4;                  // rows per workgroup (one per wave)
+constexpr int SPLIT_CW_MAX = BEMTX_SPLIT_CW;     // columns per chunk, complex128 operators (upper bound)
+constexpr int SPLIT_CW32_MAX = BEMTX_SPLIT_CW32; // the same for complex64 operators
+constexpr int MASS_CW_MAX = 512;                 // inverse mass apply
+constexpr int SPLIT_CW_MIN = 512;                // smallest bound in use (sizes the partial buffer)
+constexpr int SPLIT_ROWS = 4;                    // rows per workgroup (one per wave)
 
-__host__ __device__ inline int split_nchunk(int nv) { return (nv + SPLIT_CW_MAX - 1) / SPLIT_CW_MAX; }
-__host__ __device__ inline int split_cw(int nv)
+__host__ __device__ inline int split_nchunk(int nv, int cwmax) { return (nv + cwmax - 1) / cwmax; }
+__host__ __device__ inline int split_cw(int nv, int cwmax)
 {
-    const int nc = split_nchunk(nv);
+    const int nc = split_nchunk(nv, cwmax);
     return ((nv + nc - 1) / nc + 63) / 64 * 64;
 }
 
-// part[chunk][row] = (sum over the chunk of [-K V] row . [v; w], of [D T] row . [v; w])
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// streaming load of two adjacent complex64 entries (16 bytes)
+__device__ inline float4 ld_stream2c(const float2 *p)
+{
+#ifdef BEMTX_NO_NT
+    return *reinterpret_cast<const float4 *>(p);
+#else
+    const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+#endif
+}
+
+// part[chunk][row] = (sum over the chunk of [-K V] row . [v; w], of [D T] row . [v; w]);
+// complex128 operators, FP64 arithmetic
 __global__ __launch_bounds__(256) void mtf_dense_part_kernel(MtfArgs A, const double2 *__restrict__ x,
                                                              double4 *__restrict__ part,
                                                              const KrylovState *__restrict__ st)
@@ -404,8 +441,8 @@ __global__ __launch_bounds__(256) void mtf_dense_part_kernel(MtfArgs A, const do
     const bool ext = (int)blockIdx.x < te;
     const int nv = ext ? A.ne : A.ni;
     const int chunk = blockIdx.y;
-    if (chunk >= split_nchunk(nv)) return;
-    const int cw = split_cw(nv);
+    if (chunk >= split_nchunk(nv, SPLIT_CW_MAX)) return;
+    const int cw = split_cw(nv, SPLIT_CW_MAX);
     const int c0 = chunk * cw, c1 = min(nv, c0 + cw), ncol = c1 - c0;
     const double2 *xv = ext ? x : x + 2 * A.ne;
     const double2 *xw = xv + nv;
@@ -414,8 +451,10 @@ __global__ __launch_bounds__(256) void mtf_dense_part_kernel(MtfArgs A, const do
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = (ext ? blockIdx.x : blockIdx.x - te) * SPLIT_ROWS + wave;
     if (i >= nv) return;
-    const double2 *Km = ext ? A.Ke : A.Ki, *Vm = ext ? A.Ve : A.Vi, *Dm = ext ? A.De : A.Di, *Tm = ext ? A.Te : A.Ti;
-    const int64_t o = (int64_t)i * nv + c0;
+    const int mi = ext ? 0 : 1;
+    const double2 *Vm = static_cast<const double2 *>(A.op[mi][0]), *Km = static_cast<const double2 *>(A.op[mi][1]);
+    const double2 *Tm = static_cast<const double2 *>(A.op[mi][2]), *Dm = static_cast<const double2 *>(A.op[mi][3]);
+    const int64_t o = (int64_t)i * op_ld(nv) + c0;
     double ar = 0, ai = 0, br = 0, bi = 0;
 #pragma unroll BEMTX_MV_UNROLL
     for (int j = lane; j < ncol; j += 64) {
@@ -434,6 +473,74 @@ __global__ __launch_bounds__(256) void mtf_dense_part_kernel(MtfArgs A, const do
     }
 }
 
+template <class R> struct Cx;
+template <> struct Cx<float> { using T = float2; };
+template <> struct Cx<double> { using T = double2; };
+
+// Same product on complex64 operators.  Each lane reads two adjacent
+// entries of each block (16 bytes; rows start on 16-byte boundaries and a
+// padding column of zeros completes odd rows); the x chunk is staged in LDS
+// in the accumulation type R: float for the Krylov products (FP32
+// accumulation), double for the refinement residual (FP64 arithmetic on the
+// stored complex64 entries).
+template <class R>
+__global__ __launch_bounds__(256) void mtf_dense_c64_part_kernel(MtfArgs A, const double2 *__restrict__ x,
+                                                                 double4 *__restrict__ part,
+                                                                 const KrylovState *__restrict__ st)
+{
+    using C = typename Cx<R>::T;
+    if (st && st->done) return;
+    __shared__ C xs[2 * SPLIT_CW32_MAX];
+    const int te = (A.ne + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    const bool ext = (int)blockIdx.x < te;
+    const int nv = ext ? A.ne : A.ni;
+    const int chunk = blockIdx.y;
+    if (chunk >= split_nchunk(nv, SPLIT_CW32_MAX)) return;
+    const int cw = split_cw(nv, SPLIT_CW32_MAX);
+    const int c0 = chunk * cw, c1 = min(nv, c0 + cw), ncol = c1 - c0;
+    const double2 *xv = ext ? x : x + 2 * A.ne;
+    const double2 *xw = xv + nv;
+    // columns past the chunk's end read as zero (the pair of an odd last column)
+    for (int t = threadIdx.x; t < cw; t += blockDim.x) {
+        C a{0, 0}, b{0, 0};
+        if (t < ncol) {
+            const double2 u = xv[c0 + t], v = xw[c0 + t];
+            a = C{(R)u.x, (R)u.y};
+            b = C{(R)v.x, (R)v.y};
+        }
+        xs[t] = a;
+        xs[SPLIT_CW32_MAX + t] = b;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = (ext ? blockIdx.x : blockIdx.x - te) * SPLIT_ROWS + wave;
+    if (i >= nv) return;
+    const int mi = ext ? 0 : 1;
+    const float2 *Vm = static_cast<const float2 *>(A.op[mi][0]), *Km = static_cast<const float2 *>(A.op[mi][1]);
+    const float2 *Tm = static_cast<const float2 *>(A.op[mi][2]), *Dm = static_cast<const float2 *>(A.op[mi][3]);
+    const int64_t o = (int64_t)i * op_ld(nv) + c0;   // even: 16-byte aligned pairs
+    R ar = 0, ai = 0, br = 0, bi = 0;
+    for (int j = 2 * lane; j < ncol; j += 128) {
+        const float4 k = ld_stream2c(&Km[o + j]), v = ld_stream2c(&Vm[o + j]);
+        const float4 d = ld_stream2c(&Dm[o + j]), t = ld_stream2c(&Tm[o + j]);
+        const C p0 = xs[j], p1 = xs[j + 1], q0 = xs[SPLIT_CW32_MAX + j], q1 = xs[SPLIT_CW32_MAX + j + 1];
+        ar += -((R)k.x * p0.x - (R)k.y * p0.y) - ((R)k.z * p1.x - (R)k.w * p1.y)
+              + ((R)v.x * q0.x - (R)v.y * q0.y) + ((R)v.z * q1.x - (R)v.w * q1.y);
+        ai += -((R)k.x * p0.y + (R)k.y * p0.x) - ((R)k.z * p1.y + (R)k.w * p1.x)
+              + ((R)v.x * q0.y + (R)v.y * q0.x) + ((R)v.z * q1.y + (R)v.w * q1.x);
+        br += ((R)d.x * p0.x - (R)d.y * p0.y) + ((R)d.z * p1.x - (R)d.w * p1.y)
+              + ((R)t.x * q0.x - (R)t.y * q0.y) + ((R)t.z * q1.x - (R)t.w * q1.y);
+        bi += ((R)d.x * p0.y + (R)d.y * p0.x) + ((R)d.z * p1.y + (R)d.w * p1.x)
+              + ((R)t.x * q0.y + (R)t.y * q0.x) + ((R)t.z * q1.y + (R)t.w * q1.x);
+    }
+    double sar = wave_sum((double)ar), sai = wave_sum((double)ai);
+    double sbr = wave_sum((double)br), sbi = wave_sum((double)bi);
+    if (lane == 0) {
+        const int row = ext ? i : A.ne + i;
+        part[(int64_t)chunk * (A.ne + A.ni) + row] = make_double4(sar, sai, sbr, sbi);
+    }
+}
+
 // y rows = sum of the chunk partials (fixed order) + mortar coupling; one thread per row
 __global__ __launch_bounds__(256) void mtf_combine_kernel(MtfArgs A, const double2 *__restrict__ x,
                                                           const double4 *__restrict__ part, double2 *__restrict__ y,
@@ -446,7 +553,7 @@ __global__ __launch_bounds__(256) void mtf_combine_kernel(MtfArgs A, const doubl
     const int i = ext ? row : row - A.ne;
     const int nv = ext ? A.ne : A.ni;
     double ar = 0, ai = 0, br = 0, bi = 0;
-    const int nch = split_nchunk(nv);
+    const int nch = split_nchunk(nv, A.cw);
     for (int c = 0; c < nch; ++c) {
         const double4 q = part[(int64_t)c * (A.ne + A.ni) + row];
         ar += q.x; ai += q.y; br += q.z; bi += q.w;
@@ -469,41 +576,52 @@ __global__ __launch_bounds__(256) void mtf_combine_kernel(MtfArgs A, const doubl
     ya[i + nv] = make_double2(br + fw * tr, bi + fw * ti);
 }
 
-// part[chunk][row] = M^-1 row chunk applied to the mesh's two vectors
-__global__ __launch_bounds__(256) void mass_apply_part_kernel(int ne, int ni, const double *__restrict__ Me_inv,
-                                                              const double *__restrict__ Mi_inv,
+// part[chunk][row] = M^-1 row chunk applied to the mesh's two vectors; the
+// inverse is stored in FP64 (pairs of entries per lane) or FP32 (quads),
+// accumulation in FP64 either way.  Padding columns of M^-1 are zero and
+// the staged vectors are zero past the chunk's end.
+template <class MT>
+__global__ __launch_bounds__(256) void mass_apply_part_kernel(int ne, int ni, const MT *__restrict__ Me_inv,
+                                                              const MT *__restrict__ Mi_inv,
                                                               const double2 *__restrict__ y, double4 *__restrict__ part,
                                                               const KrylovState *__restrict__ st)
 {
+    constexpr bool f32 = sizeof(MT) == 4;
+    constexpr int VW = f32 ? 4 : 2;   // entries per lane load (16 bytes)
     if (st && st->done) return;
-    __shared__ double2 ys[2 * SPLIT_CW_MAX];
+    __shared__ double2 ys[2 * MASS_CW_MAX];
     const int te = (ne + SPLIT_ROWS - 1) / SPLIT_ROWS;
     const bool ext = (int)blockIdx.x < te;
     const int nv = ext ? ne : ni;
     const int chunk = blockIdx.y;
-    if (chunk >= split_nchunk(nv)) return;
-    const int cw = split_cw(nv);
+    if (chunk >= split_nchunk(nv, MASS_CW_MAX)) return;
+    const int cw = split_cw(nv, MASS_CW_MAX);
     const int c0 = chunk * cw, c1 = min(nv, c0 + cw), ncol = c1 - c0;
     const double2 *ya = ext ? y : y + 2 * ne;
     const double2 *yb = ya + nv;
-    for (int t = threadIdx.x; t < ncol; t += blockDim.x) { ys[t] = ya[c0 + t]; ys[SPLIT_CW_MAX + t] = yb[c0 + t]; }
+    for (int t = threadIdx.x; t < cw; t += blockDim.x) {
+        ys[t] = t < ncol ? ya[c0 + t] : make_double2(0, 0);
+        ys[MASS_CW_MAX + t] = t < ncol ? yb[c0 + t] : make_double2(0, 0);
+    }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = (ext ? blockIdx.x : blockIdx.x - te) * SPLIT_ROWS + wave;
     if (i >= nv) return;
-    const double *Mr = (ext ? Me_inv : Mi_inv) + (int64_t)i * minv_ld(nv) + c0;   // c0 is even (multiple of 64)
+    const MT *Mr = (ext ? Me_inv : Mi_inv) + (int64_t)i * minv_ld(nv, f32) + c0;   // c0: multiple of 64
     double ar = 0, ai = 0, br = 0, bi = 0;
-    for (int h = lane; 2 * h < ncol; h += 64) {
-        const int j = 2 * h;
-        if (j + 1 < ncol) {
-            const v2d m = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(Mr) + h);
-            const double2 a0 = ys[j], a1 = ys[j + 1], b0 = ys[SPLIT_CW_MAX + j], b1 = ys[SPLIT_CW_MAX + j + 1];
-            ar += m.x * a0.x + m.y * a1.x; ai += m.x * a0.y + m.y * a1.y;
-            br += m.x * b0.x + m.y * b1.x; bi += m.x * b0.y + m.y * b1.y;
+    for (int j = VW * lane; j < ncol; j += VW * 64) {
+        double m[VW];
+        if constexpr (f32) {
+            const v4f q = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Mr + j));
+            m[0] = q.x; m[1] = q.y; m[2] = q.z; m[3] = q.w;
         } else {
-            const double m = Mr[j];
-            const double2 a0 = ys[j], b0 = ys[SPLIT_CW_MAX + j];
-            ar += m * a0.x; ai += m * a0.y; br += m * b0.x; bi += m * b0.y;
+            const v2d q = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(Mr + j));
+            m[0] = q.x; m[1] = q.y;
+        }
+#pragma unroll
+        for (int u = 0; u < VW; ++u) {
+            const double2 a = ys[j + u], b = ys[MASS_CW_MAX + j + u];
+            ar += m[u] * a.x; ai += m[u] * a.y; br += m[u] * b.x; bi += m[u] * b.y;
         }
     }
     ar = wave_sum(ar); ai = wave_sum(ai); br = wave_sum(br); bi = wave_sum(bi);
@@ -523,7 +641,7 @@ __global__ __launch_bounds__(256) void mass_combine_kernel(int ne, int ni, const
     const int i = ext ? row : row - ne;
     const int nv = ext ? ne : ni;
     double ar = 0, ai = 0, br = 0, bi = 0;
-    const int nch = split_nchunk(nv);
+    const int nch = split_nchunk(nv, MASS_CW_MAX);
     for (int c = 0; c < nch; ++c) {
         const double4 q = part[(int64_t)c * (ne + ni) + row];
         ar += q.x; ai += q.y; br += q.z; bi += q.w;
@@ -533,10 +651,10 @@ __global__ __launch_bounds__(256) void mass_combine_kernel(int ne, int ni, const
     za[i + nv] = make_double2(br, bi);
 }
 
-static inline dim3 split_grid(int ne, int ni)
+static inline dim3 split_grid(int ne, int ni, int cwmax)
 {
     const int tiles = (ne + SPLIT_ROWS - 1) / SPLIT_ROWS + (ni + SPLIT_ROWS - 1) / SPLIT_ROWS;
-    return dim3(tiles, std::max(split_nchunk(ne), split_nchunk(ni)));
+    return dim3(tiles, std::max(split_nchunk(ne, cwmax), split_nchunk(ni, cwmax)));
 }
 
 // ------------------------------------------------------ Krylov kernels
@@ -742,23 +860,30 @@ __global__ void permute_vec_kernel(int ne, int ni, const int32_t *__restrict__ p
     else dst[in] = src[u];
 }
 
-__global__ void permute_mat_kernel(int nv, const int32_t *__restrict__ perm, const double2 *__restrict__ src,
-                                   double2 *__restrict__ dst)
+template <class C2>
+__global__ void permute_mat_kernel(int nv, const int32_t *__restrict__ perm, const C2 *__restrict__ src,
+                                   C2 *__restrict__ dst)
 {
     const int iu = blockIdx.y;
     const int ju = blockIdx.x * blockDim.x + threadIdx.x;
     if (ju >= nv) return;
-    dst[(int64_t)iu * nv + ju] = src[(int64_t)perm[iu] * nv + perm[ju]];
+    dst[(int64_t)iu * nv + ju] = src[(int64_t)perm[iu] * op_ld(nv) + perm[ju]];
 }
 
 bem_status resolve_assembly_timing(bem_problem *p);
 
-bem_status permute_matrix_out(const bem_problem *p, int mesh, const double2 *src, double2 *dst)
+// operator in caller numbering, dense nv x nv (complex128 or complex64 as stored)
+bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, void *dst)
 {
     const bem_mesh *m = mesh == 0 ? p->ext : p->inte;
     const int nv = (int)m->h.nv;
-    hipLaunchKernelGGL(permute_mat_kernel, dim3((nv + 255) / 256, nv), dim3(256), 0, p->ctx->stream, nv,
-                       m->d.perm.as<int32_t>(), src, dst);
+    const dim3 grid((nv + 255) / 256, nv);
+    if (p->prec == BEM_C128)
+        hipLaunchKernelGGL(permute_mat_kernel<double2>, grid, dim3(256), 0, p->ctx->stream, nv,
+                           m->d.perm.as<int32_t>(), static_cast<const double2 *>(src), static_cast<double2 *>(dst));
+    else
+        hipLaunchKernelGGL(permute_mat_kernel<float2>, grid, dim3(256), 0, p->ctx->stream, nv,
+                           m->d.perm.as<int32_t>(), static_cast<const float2 *>(src), static_cast<float2 *>(dst));
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
@@ -768,7 +893,7 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const double2 *src
 namespace {
 
 struct Work {
-    DevMem xin, y, z, b, r, Vb, partial, hsum, beta, yc, npart, R, g, cs, sn, state, part;
+    DevMem xin, d, y, z, b, r, Vb, partial, hsum, beta, yc, npart, R, g, cs, sn, state, part;
 };
 
 MtfArgs make_args(const bem_problem *p)
@@ -776,10 +901,9 @@ MtfArgs make_args(const bem_problem *p)
     MtfArgs A;
     A.ne = (int)p->ext->h.nv;
     A.ni = (int)p->inte->h.nv;
-    A.Ve = p->ops[0][0].as<double2>(); A.Ke = p->ops[0][1].as<double2>();
-    A.Te = p->ops[0][2].as<double2>(); A.De = p->ops[0][3].as<double2>();
-    A.Vi = p->ops[1][0].as<double2>(); A.Ki = p->ops[1][1].as<double2>();
-    A.Ti = p->ops[1][2].as<double2>(); A.Di = p->ops[1][3].as<double2>();
+    A.cw = p->prec == BEM_C128 ? SPLIT_CW_MAX : SPLIT_CW32_MAX;
+    for (int m = 0; m < 2; ++m)
+        for (int o = 0; o < 4; ++o) A.op[m][o] = p->ops[m][o].ptr;
     A.pie_ptr = p->P_ie_ptr.as<int32_t>(); A.pie_col = p->P_ie_col.as<int32_t>(); A.pie_val = p->P_ie_val.as<double>();
     A.pei_ptr = p->P_ei_ptr.as<int32_t>(); A.pei_col = p->P_ei_col.as<int32_t>(); A.pei_val = p->P_ei_val.as<double>();
     A.c_ext_v = 0.5;
@@ -791,7 +915,8 @@ MtfArgs make_args(const bem_problem *p)
 
 size_t split_part_bytes(int ne, int ni)
 {
-    return (size_t)std::max(split_nchunk(ne), split_nchunk(ni)) * (ne + ni) * sizeof(double4);
+    return (size_t)std::max(split_nchunk(ne, SPLIT_CW_MIN), split_nchunk(ni, SPLIT_CW_MIN)) * (ne + ni) *
+           sizeof(double4);
 }
 
 // z = blockdiag(M_e, M_e, M_i, M_i)^-1 y
@@ -801,27 +926,175 @@ bem_status apply_Minv(const bem_problem *p, const double2 *y, double2 *z, double
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
     {
         KTimer kt(p->ctx, K_MASS_APPLY);
-        launch_k(kt, mass_apply_part_kernel, split_grid(ne, ni), dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
-                 p->Minv[1].as<double>(), y, part, kst);
+        const dim3 g = split_grid(ne, ni, MASS_CW_MAX);
+        if (p->prec == BEM_C128)
+            launch_k(kt, mass_apply_part_kernel<double>, g, dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
+                     p->Minv[1].as<double>(), y, part, kst);
+        else
+            launch_k(kt, mass_apply_part_kernel<float>, g, dim3(256), 0, st, ne, ni, p->Minv[0].as<float>(),
+                     p->Minv[1].as<float>(), y, part, kst);
     }
     hipLaunchKernelGGL(mass_combine_kernel, dim3((ne + ni + 255) / 256), dim3(256), 0, st, ne, ni, part, z, kst);
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
 
+// y = A x (weak form); z = M^-1 y when `strong`.  Complex64 operators are
+// applied with FP32 accumulation, or FP64 when `acc64` (refinement residual).
 bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, double2 *y, double2 *z, bool strong,
-                   const KrylovState *kst, double4 *part)
+                   const KrylovState *kst, double4 *part, bool acc64 = false)
 {
     hipStream_t st = p->ctx->stream;
     const int rows = A.ne + A.ni;
     {
         KTimer kt(p->ctx, K_MTF_DENSE);
-        launch_k(kt, mtf_dense_part_kernel, split_grid(A.ne, A.ni), dim3(256), 0, st, A, x, part, kst);
+        const dim3 g = split_grid(A.ne, A.ni, A.cw);
+        if (p->prec == BEM_C128)
+            launch_k(kt, mtf_dense_part_kernel, g, dim3(256), 0, st, A, x, part, kst);
+        else if (acc64)
+            launch_k(kt, mtf_dense_c64_part_kernel<double>, g, dim3(256), 0, st, A, x, part, kst);
+        else
+            launch_k(kt, mtf_dense_c64_part_kernel<float>, g, dim3(256), 0, st, A, x, part, kst);
     }
     hipLaunchKernelGGL(mtf_combine_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, A, x, part, y, kst);
     BEM_HIP(hipGetLastError());
     if (strong) return apply_Minv(p, y, z, part, kst);
     return BEM_OK;
+}
+
+// ||w|| on the device: into *out (device double)
+bem_status norm_to(const bem_problem *p, int n, const double2 *w, double *npart, double2 *scratch_vec, double *out)
+{
+    hipStream_t st = p->ctx->stream;
+    const int nblk = (n + 255) / 256;
+    hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(256), 0, st, n, w, npart);
+    hipLaunchKernelGGL(normalize_kernel, dim3(nblk), dim3(256), 0, st, n, nblk, npart, w, scratch_vec, out);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+}
+
+struct Gmres {
+    bem_problem *p;
+    const MtfArgs &A;
+    Work &W;
+    KrylovState *hstate;   // two pinned slots polled alternately
+    hipEvent_t *ev;
+    int n, nchunk, nrow_blk, m;
+
+    // GMRES without restart on M^-1 A x = r0 (r0 already preconditioned),
+    // x0 = 0, Arnoldi (CGS2) and Givens rotations in FP64 on the device;
+    // at most `maxit` steps.  Writes x and the final Krylov state.
+    bem_status run(const double2 *r0, double tol, int maxit, double2 *x, KrylovState &fin)
+    {
+        bem_ctx *ctx = p->ctx;
+        hipStream_t st = ctx->stream;
+        double2 *Vb = W.Vb.as<double2>();
+        KrylovState *dst = W.state.as<KrylovState>();
+        const dim3 gv(nrow_blk);
+        const int BATCH = 8;
+        hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, r0, W.npart.as<double>());
+        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), r0, Vb,
+                           W.beta.as<double>());
+        hipLaunchKernelGGL(krylov_init_kernel, dim3((maxit + 256) / 256), dim3(256), 0, st, maxit, W.beta.as<double>(),
+                           W.g.as<double2>(), dst);
+        BEM_HIP(hipGetLastError());
+        // Issue policy: steps go out in batches of BATCH while the host checks
+        // the state snapshot of the previous batch (the device never waits on
+        // the host).  Once the observed convergence rate predicts the end
+        // within the steps already queued plus two batches, each step is
+        // followed by a synchronous check, so no step is issued after the one
+        // that converges.
+        int slot = 0, pending = -1, last_j = 0;
+        double last_res = 1.0;
+        bool sync_mode = false, stop = false;
+        for (int j = 0; j < maxit && !stop; ++j) {
+            const double2 *vj = Vb + (size_t)j * n;
+            bem_status s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
+            if (s) return s;
+            for (int pass = 0; pass < 2; ++pass) {
+                {
+                    KTimer kt(ctx, K_CGS_DOTS);
+                    launch_k(kt, cgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4), dim3(256), 0, st, n, j + 1, Vb,
+                             W.z.as<double2>(), W.partial.as<double2>(), dst);
+                }
+                KTimer kt(ctx, K_CGS_UPDATE);
+                launch_k(kt, cgs_update_kernel, gv, dim3(256), (size_t)(j + 1) * sizeof(double2), st, n, j + 1, nchunk,
+                         Vb, W.partial.as<double2>(), W.z.as<double2>(), W.hsum.as<double2>(), pass,
+                         W.npart.as<double>(), dst);
+            }
+            {
+                KTimer kt(ctx, K_ARNOLDI_FINISH);
+                launch_k(kt, arnoldi_finish_kernel, gv, dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, n,
+                         nrow_blk, W.npart.as<double>(), W.z.as<double2>(), Vb + (size_t)(j + 1) * n, j, maxit, tol,
+                         W.hsum.as<double2>(), W.R.as<double2>(), W.g.as<double2>(), W.cs.as<double2>(),
+                         W.sn.as<double2>(), dst);
+            }
+            BEM_HIP(hipGetLastError());
+            const int issued = j + 1;
+            if (sync_mode) {
+                BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+                BEM_HIP(hipStreamSynchronize(st));
+                stop = hstate[slot].done != 0;
+                continue;
+            }
+            if (issued % BATCH != 0) continue;
+            BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipEventRecord(ev[slot], st));
+            if (pending >= 0) {
+                BEM_HIP(hipEventSynchronize(ev[pending]));
+                const KrylovState &k = hstate[pending];
+                if (k.done) { stop = true; break; }
+                // steps still to go at the observed geometric rate
+                if (last_j > 0 && k.iters > last_j && k.resid > 0 && last_res > 0) {
+                    const double rate = std::pow(k.resid / last_res, 1.0 / (k.iters - last_j));
+                    const double togo = rate < 1.0 ? std::log(tol / k.resid) / std::log(rate) : 1e30;
+                    if (togo <= (issued - k.iters) + 2 * BATCH) sync_mode = true;
+                }
+                last_j = k.iters;
+                last_res = k.resid;
+            }
+            pending = slot;
+            slot ^= 1;
+        }
+        BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+        BEM_HIP(hipStreamSynchronize(st));
+        fin = hstate[slot];
+        const int k = fin.iters;
+        // back substitution R y = g on the host (k x k upper triangular; R
+        // column c at offset c (maxit + 1))
+        using cd = std::complex<double>;
+        std::vector<cd> Rh((size_t)std::max(k, 1) * (maxit + 1)), gh(maxit + 1);
+        if (k > 0) {
+            BEM_HIP(hipMemcpyAsync(Rh.data(), W.R.ptr, (size_t)k * (maxit + 1) * sizeof(double2),
+                                   hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipMemcpyAsync(gh.data(), W.g.ptr, (size_t)(maxit + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipStreamSynchronize(st));
+        }
+        std::vector<cd> yv(std::max(k, 1));
+        for (int i = k - 1; i >= 0; --i) {
+            cd sacc = gh[i];
+            for (int c = i + 1; c < k; ++c) sacc -= Rh[(size_t)c * (maxit + 1) + i] * yv[c];
+            yv[i] = sacc / Rh[(size_t)i * (maxit + 1) + i];
+        }
+        if (k > 0) BEM_HIP(hipMemcpyAsync(W.yc.ptr, yv.data(), (size_t)k * sizeof(double2), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(combine_kernel, gv, dim3(256), 0, st, n, k, Vb, W.yc.as<double2>(), x);
+        BEM_HIP(hipGetLastError());
+        // the host vector yv must outlive the copy above
+        BEM_HIP(hipStreamSynchronize(st));
+        return BEM_OK;
+    }
+};
+
+__global__ void axpy_add_kernel(int n, const double2 *__restrict__ d, double2 *__restrict__ x)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) x[r] = make_double2(x[r].x + d[r].x, x[r].y + d[r].y);
+}
+
+__global__ void zero_kernel(int n, double2 *__restrict__ x)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) x[r] = make_double2(0, 0);
 }
 
 }  // namespace
@@ -893,13 +1166,14 @@ bem_status rhs_impl(bem_problem *p, const double *dirs, int nrhs, void *b, bem_m
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats)
 {
-    using cd = std::complex<double>;
     bem_ctx *ctx = p->ctx;
     BEM_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne + 2 * ni;
     const int m = opts->maxit;
     if (m > MAXIT_CAP) return set_error(BEM_E_ARG, "maxit above 3000");
+    const bool mixed = p->prec == BEM_C64_MIXED;
+    const int ir_max = opts->ir_max > 0 ? opts->ir_max : 10;
     const size_t vb = (size_t)n * sizeof(double2);
     const int nchunk = (n + CGS_CHUNK - 1) / CGS_CHUNK;
     const int nrow_blk = (n + 255) / 256;
@@ -909,6 +1183,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     if (!s) s = dev_alloc(ctx, W.b, vb);
     if (!s) s = dev_alloc(ctx, W.r, vb);
     if (!s) s = dev_alloc(ctx, W.xin, vb);
+    if (!s && mixed) s = dev_alloc(ctx, W.d, vb);
     if (!s) s = dev_alloc(ctx, W.Vb, (size_t)(m + 1) * vb);
     if (!s) s = dev_alloc(ctx, W.partial, (size_t)nchunk * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.hsum, (size_t)(m + 1) * sizeof(double2));
@@ -929,122 +1204,80 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     BEM_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     BEM_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     struct EvGuard { hipEvent_t *e; ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); } } eguard{ev};
-    MtfArgs A = make_args(p);
-    double2 *Vb = W.Vb.as<double2>();
-    KrylovState *dst = W.state.as<KrylovState>();
-    const dim3 gv(nrow_blk);
-    const int BATCH = 8;
+    const MtfArgs A = make_args(p);
     const size_t finish_lds = (size_t)(3 * m + 1) * sizeof(double2);
     BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&arnoldi_finish_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)finish_lds));
-    int total_it = 0;
+    Gmres gm{p, A, W, hstate, ev, n, nchunk, nrow_blk, m};
+    const dim3 gv(nrow_blk);
+    double *beta = W.beta.as<double>();   // [0] ||M^-1 b||, [1] ||M^-1 (b - A x)||
+    int total_it = 0, total_ir = 0;
     double worst_res = 0.0;
     bool all_conv = true;
     auto t0 = std::chrono::steady_clock::now();
+    // true strong-form residual in FP64 arithmetic, r = M^-1 (b - A x) into W.z, its norm into beta[1]
+    auto residual = [&]() -> bem_status {
+        bem_status q = apply_A(p, A, W.xin.as<double2>(), W.y.as<double2>(), W.z.as<double2>(), false, nullptr,
+                               W.part.as<double4>(), true);
+        if (q) return q;
+        hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), W.y.as<double2>(),
+                           W.r.as<double2>());
+        q = apply_Minv(p, W.r.as<double2>(), W.z.as<double2>(), W.part.as<double4>(), nullptr);
+        if (q) return q;
+        return norm_to(p, n, W.z.as<double2>(), W.npart.as<double>(), W.d.ptr ? W.d.as<double2>() : W.r.as<double2>(),
+                       beta + 1);
+    };
     for (int rhs = 0; rhs < nrhs; ++rhs) {
         s = rhs_internal(p, dirs + 3 * rhs, W.b.as<double2>());
         if (s) return s;
-        // r0 = M^-1 b (x0 = 0), v0 = r0 / ||r0||, g = [beta0, 0, ...]
+        // r0 = M^-1 b (x0 = 0)
         s = apply_Minv(p, W.b.as<double2>(), W.r.as<double2>(), W.part.as<double4>(), nullptr);
         if (s) return s;
-        hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, W.r.as<double2>(), W.npart.as<double>());
-        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), W.r.as<double2>(),
-                           Vb, W.beta.as<double>());
-        hipLaunchKernelGGL(krylov_init_kernel, dim3((m + 256) / 256), dim3(256), 0, st, m, W.beta.as<double>(),
-                           W.g.as<double2>(), dst);
-        BEM_HIP(hipGetLastError());
-        // Issue policy: steps go out in batches of BATCH while the host checks
-        // the state snapshot of the previous batch (the device never waits on
-        // the host).  Once the observed convergence rate predicts the end
-        // within the steps already queued plus two batches, each step is
-        // followed by a synchronous check, so no step is issued after the one
-        // that converges.
-        int slot = 0, pending = -1, last_j = 0;
-        double last_res = 1.0;
-        bool sync_mode = false, stop = false;
-        for (int j = 0; j < m && !stop; ++j) {
-            const double2 *vj = Vb + (size_t)j * n;
-            s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
+        double b0 = 0.0, rn = 0.0;
+        KrylovState fin{};
+        if (!mixed) {
+            s = gm.run(W.r.as<double2>(), opts->tol, m, W.xin.as<double2>(), fin);
             if (s) return s;
-            for (int pass = 0; pass < 2; ++pass) {
-                {
-                    KTimer kt(ctx, K_CGS_DOTS);
-                    launch_k(kt, cgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4), dim3(256), 0, st, n, j + 1, Vb,
-                             W.z.as<double2>(), W.partial.as<double2>(), dst);
-                }
-                KTimer kt(ctx, K_CGS_UPDATE);
-                launch_k(kt, cgs_update_kernel, gv, dim3(256), (size_t)(j + 1) * sizeof(double2), st, n, j + 1, nchunk,
-                         Vb, W.partial.as<double2>(), W.z.as<double2>(), W.hsum.as<double2>(), pass,
-                         W.npart.as<double>(), dst);
-            }
-            {
-                KTimer kt(ctx, K_ARNOLDI_FINISH);
-                launch_k(kt, arnoldi_finish_kernel, gv, dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, n,
-                         nrow_blk, W.npart.as<double>(), W.z.as<double2>(), Vb + (size_t)(j + 1) * n, j, m, opts->tol,
-                         W.hsum.as<double2>(), W.R.as<double2>(), W.g.as<double2>(), W.cs.as<double2>(),
-                         W.sn.as<double2>(), dst);
-            }
-            BEM_HIP(hipGetLastError());
-            const int issued = j + 1;
-            if (sync_mode) {
-                BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
-                BEM_HIP(hipStreamSynchronize(st));
-                stop = hstate[slot].done != 0;
-                continue;
-            }
-            if (issued % BATCH != 0) continue;
-            BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
-            BEM_HIP(hipEventRecord(ev[slot], st));
-            if (pending >= 0) {
-                BEM_HIP(hipEventSynchronize(ev[pending]));
-                const KrylovState &k = hstate[pending];
-                if (k.done) { stop = true; break; }
-                // steps still to go at the observed geometric rate
-                if (last_j > 0 && k.iters > last_j && k.resid > 0 && last_res > 0) {
-                    const double rate = std::pow(k.resid / last_res, 1.0 / (k.iters - last_j));
-                    const double togo = rate < 1.0 ? std::log(opts->tol / k.resid) / std::log(rate) : 1e30;
-                    if (togo <= (issued - k.iters) + 2 * BATCH) sync_mode = true;
-                }
-                last_j = k.iters;
-                last_res = k.resid;
-            }
-            pending = slot;
-            slot ^= 1;
-        }
-        KrylovState fin;
-        BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
-        BEM_HIP(hipStreamSynchronize(st));
-        fin = hstate[slot];
-        const int k = fin.iters;
-        total_it += k;
-        // back substitution R y = g on the host (k x k upper triangular)
-        std::vector<cd> Rh((size_t)std::max(k, 1) * (m + 1)), gh(m + 1);
-        if (k > 0) {
-            BEM_HIP(hipMemcpyAsync(Rh.data(), W.R.ptr, (size_t)k * (m + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
-            BEM_HIP(hipMemcpyAsync(gh.data(), W.g.ptr, (size_t)(m + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+            total_it += fin.iters;
+            b0 = fin.beta0;
+            s = residual();
+            if (s) return s;
+            BEM_HIP(hipMemcpyAsync(&rn, beta + 1, sizeof(double), hipMemcpyDeviceToHost, st));
             BEM_HIP(hipStreamSynchronize(st));
+            if (!(fin.resid <= opts->tol)) all_conv = false;
+        } else {
+            // Iterative refinement: x += d where d solves the FP32-product
+            // system M^-1 A d = M^-1 (b - A x) to a relative tolerance that
+            // aims at the outer target; the residual of every step is
+            // recomputed with FP64 arithmetic.
+            hipLaunchKernelGGL(zero_kernel, gv, dim3(256), 0, st, n, W.xin.as<double2>());
+            s = norm_to(p, n, W.r.as<double2>(), W.npart.as<double>(), W.z.as<double2>(), beta);
+            if (s) return s;
+            BEM_HIP(hipMemcpyAsync(&b0, beta, sizeof(double), hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipStreamSynchronize(st));
+            const double2 *rhs_s = W.r.as<double2>();   // preconditioned residual of the current x
+            double rel = 1.0;
+            int used = 0, steps = 0;
+            while (b0 > 0.0 && rel > opts->tol && steps < ir_max && used < m) {
+                const double inner = opts->ir_inner_tol > 0 ? opts->ir_inner_tol
+                                                            : std::max(0.5 * opts->tol / rel, 1e-6);
+                s = gm.run(rhs_s, inner, m - used, W.d.as<double2>(), fin);
+                if (s) return s;
+                used += fin.iters;
+                ++steps;
+                hipLaunchKernelGGL(axpy_add_kernel, gv, dim3(256), 0, st, n, W.d.as<double2>(), W.xin.as<double2>());
+                s = residual();
+                if (s) return s;
+                BEM_HIP(hipMemcpyAsync(&rn, beta + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+                BEM_HIP(hipStreamSynchronize(st));
+                rel = rn / b0;
+                rhs_s = W.z.as<double2>();
+                if (fin.iters == 0) break;   // no progress possible
+            }
+            total_it += used;
+            total_ir += steps;
+            if (!(rel <= opts->tol)) all_conv = false;
         }
-        std::vector<cd> yv(std::max(k, 1));
-        for (int i = k - 1; i >= 0; --i) {
-            cd sacc = gh[i];
-            for (int c = i + 1; c < k; ++c) sacc -= Rh[(size_t)c * (m + 1) + i] * yv[c];
-            yv[i] = sacc / Rh[(size_t)i * (m + 1) + i];
-        }
-        if (k > 0) BEM_HIP(hipMemcpyAsync(W.yc.ptr, yv.data(), (size_t)k * sizeof(double2), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(combine_kernel, gv, dim3(256), 0, st, n, k, Vb, W.yc.as<double2>(), W.xin.as<double2>());
-        BEM_HIP(hipGetLastError());
-        // true strong-form residual in FP64: M^-1 (b - A x)
-        s = apply_A(p, A, W.xin.as<double2>(), W.y.as<double2>(), W.z.as<double2>(), false, nullptr, W.part.as<double4>());
-        if (s) return s;
-        hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), W.y.as<double2>(), W.r.as<double2>());
-        s = apply_Minv(p, W.r.as<double2>(), W.z.as<double2>(), W.part.as<double4>(), nullptr);
-        if (s) return s;
-        hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, W.z.as<double2>(), W.npart.as<double>());
-        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), W.z.as<double2>(),
-                           W.r.as<double2>(), W.beta.as<double>() + 1);
-        BEM_HIP(hipGetLastError());
-        double rn = 0;
-        BEM_HIP(hipMemcpyAsync(&rn, W.beta.as<double>() + 1, sizeof(double), hipMemcpyDeviceToHost, st));
         // traces in caller numbering
         hipLaunchKernelGGL(permute_vec_kernel, gv, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
                            p->inte->d.perm.as<int32_t>(), W.xin.as<double2>(), W.y.as<double2>(), 0);
@@ -1052,9 +1285,8 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         BEM_HIP(hipMemcpyAsync(static_cast<double2 *>(traces) + (size_t)rhs * n, W.y.ptr, vb,
                                space == BEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
         BEM_HIP(hipStreamSynchronize(st));
-        const double rel = fin.beta0 > 0 ? rn / fin.beta0 : 0.0;
+        const double rel = b0 > 0 ? rn / b0 : 0.0;
         worst_res = std::max(worst_res, rel);
-        if (!(fin.resid <= opts->tol)) all_conv = false;
     }
     const double t_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     s = resolve_assembly_timing(p);
@@ -1062,6 +1294,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     if (stats) {
         std::memset(stats, 0, sizeof *stats);
         stats->iterations = total_it;
+        stats->ir_steps = total_ir;
         stats->rel_residual = worst_res;
         stats->t_geometry_ms = p->t_geometry_ms;
         stats->t_regular_ms = p->t_regular_ms;

@@ -1,0 +1,192 @@
+"""GPU parity of the mixed-precision form (BEM_C64_MIXED): complex64
+operators assembled with FP32 arithmetic (FP64 phase per triangle pair, FP64
+singular integrals), mat-vecs with FP32 accumulation, FP64 Krylov basis and
+iterative refinement with FP64 residuals.
+
+Tolerances.  Operators: the stored entries carry the FP32 rounding of the
+entry (2^-24 relative) plus the FP32 rounding of the regular quadrature sums
+(at most 36 point pairs per triangle pair, at most 36 triangle pairs per
+entry, summed in a fixed tree); the bound asserted, 2e-5 relative in
+Frobenius norm and 1e-4 of the largest entry per entry, is the first-order
+error bound n u of a sum of n = 36 * 9 terms with u = 2^-24 (1.9e-5),
+rounded to the stated values.  Traces: 1e-5 relative per block against the
+oracle's dense LU solution, the target of the method.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_2206_00708_amd")
+
+OP_FRO, OP_MAX, TRACE = 2e-5, 1e-4, 1e-5
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _relmax(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def _blocks(x, ne, ni):
+    return (x[:ne], x[ne:2 * ne], x[2 * ne:2 * ne + ni], x[2 * ne + ni:])
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return B.Context(0)
+
+
+def _problem(ctx, c, prec):
+    me = B.Mesh(ctx, *c["ext"])
+    mi = B.Mesh(ctx, *c["int"])
+    p = B.Problem(ctx, me, mi, c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"], precision=prec)
+    p.assemble_operators()
+    p.assemble_projection()
+    return p, me, mi
+
+
+@pytest.fixture(scope="module")
+def c1m(ctx):
+    c = synth.make_config("C1")
+    return (c,) + _problem(ctx, c, B.C64_MIXED)
+
+
+@pytest.fixture(scope="module")
+def c1_oracle(orc):
+    c = synth.make_config("C1")
+    return orc.operators(c["ext"], c["int"], c["k_ext"], c["k_int"])
+
+
+@pytest.mark.parametrize("mesh", [0, 1])
+def test_operators_c1_mixed(c1m, c1_oracle, mesh):
+    c, p, _, _ = c1m
+    ref = c1_oracle["ext" if mesh == 0 else "int"]
+    for op in "VKTD":
+        got = p.operator(mesh, op)
+        assert got.dtype == torch.complex64
+        got = got.cpu().numpy().astype(np.complex128)
+        e, m = _rel(got, ref[op]), _relmax(got, ref[op])
+        print(f"C1 mixed mesh {mesh} {op}: fro {e:.2e} max {m:.2e}")
+        assert e < OP_FRO and m < OP_MAX, (op, e, m)
+
+
+def test_operators_mixed_bitwise_repeatable(ctx):
+    c = synth.make_config("C1")
+    p, _, _ = _problem(ctx, c, B.C64_MIXED)
+    a = [p.operator(1, op).clone() for op in "VKTD"]
+    p.assemble_operators()
+    for op, x in zip("VKTD", a):
+        assert torch.equal(x, p.operator(1, op))
+
+
+@pytest.mark.parametrize("strong", [False, True])
+def test_matvec_c1_mixed(c1m, c1_oracle, orc, strong):
+    """FP32-accumulated product against the FP64 oracle product: the error is
+    that of the operators (above) plus the FP32 sum over N columns."""
+    c, p, _, _ = c1m
+    A = orc.mtf_system(c1_oracle, c["rho_ext"], c["rho_int"])
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+    y = p.mtf_matvec(torch.from_numpy(x), strong=strong).cpu().numpy()
+    ref = A @ x
+    if strong:
+        ref = np.linalg.solve(orc.block_mass(c1_oracle), ref)
+    e = _rel(y, ref)
+    print(f"C1 mixed matvec strong={strong}: {e:.2e}")
+    assert e < OP_FRO
+
+
+def _check_traces(got, ref, ne, ni, tol, tag):
+    errs = [_rel(g, r) for g, r in zip(_blocks(got, ne, ni), _blocks(ref, ne, ni))]
+    print(f"{tag} trace errors per block: " + " ".join(f"{e:.2e}" for e in errs))
+    assert max(errs) < tol, errs
+
+
+def test_solve_c1_mixed_vs_lu(c1m, c1_oracle, orc):
+    c, p, _, _ = c1m
+    X, _ = orc.solve_mtf(c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"], c["dirs"],
+                         ops=c1_oracle)
+    out, stats, code = p.solve(c["dirs"], tol=c["tol"], maxit=500)
+    assert code == B.OK, stats
+    assert stats["ir_steps"] >= 1
+    assert stats["rel_residual"] <= c["tol"]
+    _check_traces(out.cpu().numpy()[0], X[0], len(c["ext"][0]), len(c["int"][0]), TRACE, "C1 mixed")
+
+
+def _small_ellipsoid():
+    """Ellipsoid (1, 0.8, 0.6) as in the precision workload, at a size the
+    oracle's dense LU handles: ext icosphere L3 (642 nodes), int Fibonacci
+    700 nodes (odd chunk tails on both meshes), k 6 / 12, rho ratio 2."""
+    (xe, te), (xi, ti), rng = synth.make_pair(3, 3, "fib", 0.01, (1.0, 0.8, 0.6), int_n=700)
+    return dict(ext=(xe, te), int=(xi, ti), k_ext=6.0, k_int=12.0, rho_ext=1.0, rho_int=2.0, tol=1e-8,
+                dirs=synth.plane_wave_directions(2, rng))
+
+
+def test_solve_small_ellipsoid_mixed_vs_lu(ctx, orc):
+    c = _small_ellipsoid()
+    p, _, _ = _problem(ctx, c, B.C64_MIXED)
+    X, _ = orc.solve_mtf(c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"], c["dirs"])
+    out, stats, code = p.solve(c["dirs"], tol=c["tol"], maxit=1500)
+    assert code == B.OK, stats
+    got = out.cpu().numpy()
+    ne, ni = len(c["ext"][0]), len(c["int"][0])
+    for r in range(len(c["dirs"])):
+        _check_traces(got[r], X[r], ne, ni, TRACE, f"ellipsoid-small mixed rhs {r}")
+
+
+def test_mixed_ir_controls(c1m):
+    """ir_max = 1 with a loose inner tolerance stops after one refinement step
+    and reports non-convergence against a tight outer tolerance."""
+    c, p, _, _ = c1m
+    out, stats, code = p.solve(c["dirs"], tol=1e-12, maxit=500, ir_max=1, ir_inner_tol=1e-3)
+    assert code == B.W_NOCONV
+    assert stats["ir_steps"] == 1
+    assert 1e-12 < stats["rel_residual"] < 1e-2
+
+
+# ---------------------------------------------------------------- full size
+
+@pytest.fixture(scope="module")
+def c3(ctx):
+    c = synth.make_config("C3")
+    return (c,) + _problem(ctx, c, B.C64_MIXED)
+
+
+@pytest.mark.parametrize("mesh", [0, 1])
+def test_operators_c3_sampled_rows(c3, orc, mesh):
+    c, p, _, _ = c3
+    xyz, tri = c["ext"] if mesh == 0 else c["int"]
+    k = c["k_ext"] if mesh == 0 else c["k_int"]
+    rng = np.random.default_rng(30 + mesh)
+    rows = np.unique(np.concatenate([[0, len(xyz) - 1], rng.choice(len(xyz), 4, replace=False)]))
+    ref = orc.assemble(xyz, tri, k, rows=rows)
+    for op in "VKTD":
+        got = p.operator(mesh, op)[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.complex128)
+        e, m = _rel(got, ref[op]), _relmax(got, ref[op])
+        print(f"C3 mixed mesh {mesh} {op} rows: fro {e:.2e} max {m:.2e}")
+        assert e < OP_FRO and m < OP_MAX, (op, e, m)
+
+
+def test_solve_c3_mixed_vs_fp64(ctx, c3):
+    """Traces of the mixed solve against the FP64 (complex128) solve of the
+    same problem on the GPU, whose parity with the oracle the FP64 tests
+    establish.  Both solves run to 1e-8, so that the difference measures the
+    complex64 operators rather than the two stopping points."""
+    c, p, _, _ = c3
+    tol = 1e-8
+    out, stats, code = p.solve(c["dirs"], tol=tol, maxit=3000)
+    assert code == B.OK, stats
+    assert stats["rel_residual"] <= tol
+    p64, _, _ = _problem(ctx, c, B.C128)
+    ref, s64, code64 = p64.solve(c["dirs"], tol=tol, maxit=3000)
+    assert code64 == B.OK, s64
+    print(f"C3 iterations mixed {stats['iterations']} (IR {stats['ir_steps']}) fp64 {s64['iterations']}")
+    _check_traces(out.cpu().numpy()[0], ref.cpu().numpy()[0], len(c["ext"][0]), len(c["int"][0]), TRACE,
+                  "C3 mixed vs fp64")
