@@ -38,6 +38,28 @@ FP64_VEC_TFLOPS = 78.6       # MI355X FP64 vector, TFLOP/s
 # per-row contraction 19.
 FLOP_PER_POINT_PAIR = 139
 
+# HBM traffic per launch of the dominant kernel from the FETCH_SIZE and
+# WRITE_SIZE counters (rocprofv3 --pmc, one counter per run), each scaled by
+# the counter's reading for a plain 1 GiB device copy (FETCH x 2.000, WRITE x
+# 1.000), with the sha1 of the kernel source the counters were taken on; the
+# figure is reported only while that source is unchanged.
+COUNTED_TRAFFIC = {
+    "mtf_dense": {"bytes": 2.000 * 356341.0 * 1024 + 1.000 * 731.8 * 1024,
+                  "source": "paper_2206_00708_amd/csrc/solve.hip",
+                  "sha1": "93ca0d86c730340913dafbc5d2b90f79ea388d8c"},
+}
+
+
+def counted_traffic(kernel):
+    import hashlib
+    t = COUNTED_TRAFFIC.get(kernel)
+    if not t:
+        return None
+    with open(os.path.join(ROOT, t["source"]), "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != t["sha1"]:
+            return None
+    return round(t["bytes"])
+
 
 def cpu_oracle_baseline(c, budget_s=15.0):
     """FP64 oracle assembly throughput on a bounded row sample of the same
@@ -66,13 +88,79 @@ def cpu_oracle_baseline(c, budget_s=15.0):
                       f"({entries} entries, {dt:.1f} s)"}
 
 
+def precision_compare(ctx, B, synth, np, steps=2, tol=1e-7):
+    """The precision workload (ellipsoid (1, 0.8, 0.6), exterior icosphere L5
+    with 10242 nodes, interior Fibonacci grid with 8002 nodes, k 10 / 20, rho
+    ratio 2) solved end to end in the plain FP64 form and in the mixed form
+    (complex64 operators, FP32-accumulated products, FP64 Arnoldi and
+    refinement residuals).  Both run to a strong-form residual of 1e-7, ten
+    times below the workload's 1e-6, because at 1e-6 the two stopping points
+    alone differ by about 1.5e-5 in the traces; at 1e-7 both lie within 1e-5
+    of the exact discrete solution.  Reports step time, solves/s, the
+    mat-vec bandwidth and the trace difference between the two forms."""
+    import torch
+    c = synth.make_config("C3")
+    (xe, te), (xi, ti) = c["ext"], c["int"]
+    ne, ni = len(xe), len(xi)
+    res, traces = {}, {}
+    for name, prec, eb in (("fp64", B.C128, 16), ("c64_mixed", B.C64_MIXED, 8)):
+        lat = []
+        for rep in range(steps + 1):
+            if rep == 1:
+                ctx.set_kernel_timing(("mtf_dense",))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            me, mi = B.Mesh(ctx, xe, te), B.Mesh(ctx, xi, ti)
+            p = B.Problem(ctx, me, mi, c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"], precision=prec)
+            p.assemble_operators()
+            p.assemble_projection()
+            out, st, code = p.solve(c["dirs"], tol=tol, maxit=3000)
+            x = out.cpu().numpy()[0]
+            if rep > 0:
+                lat.append(time.perf_counter() - t0)
+            assert code == B.OK, st
+            del p, me, mi
+        ms, n = ctx.kernel_time("mtf_dense")
+        ctx.set_kernel_timing(())
+        traces[name] = x
+        res[name] = {"step_ms": round(1e3 * statistics.median(lat), 2),
+                     "solves_per_s": round(1.0 / statistics.median(lat), 3),
+                     "iterations": st["iterations"], "ir_steps": st["ir_steps"],
+                     "rel_residual": st["rel_residual"],
+                     "assembly_device_ms": round(st["t_regular_ms"] + st["t_singular_ms"], 2),
+                     "solve_ms": round(st["t_solve_ms"], 2),
+                     "mtf_dense_us": round(1e3 * ms / n, 2),
+                     "mtf_dense_GBps": round(4 * eb * (ne * ne + ni * ni) / (ms / n * 1e-3) / 1e9, 1)}
+    a, b = traces["c64_mixed"], traces["fp64"]
+    sl = [slice(0, ne), slice(ne, 2 * ne), slice(2 * ne, 2 * ne + ni), slice(2 * ne + ni, None)]
+    err = max(float(np.linalg.norm(a[q] - b[q]) / np.linalg.norm(b[q])) for q in sl)
+    return {"workload": f"ellipsoid-ico5/fib8002 MTF (n_ext {ne}, n_int {ni}, k 10/20, rho ratio 2), "
+                        f"1 plane wave, GMRES tol {tol:g}",
+            **res, "trace_rel_err_mixed_vs_fp64": err,
+            "speedup_mixed_vs_fp64": round(res["fp64"]["step_ms"] / res["c64_mixed"]["step_ms"], 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP64 vs mixed comparison")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
+                         "HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 4 * n, "launches": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding of the operators is a design note, not implemented", file=sys.stderr)
@@ -135,7 +223,7 @@ def main():
         ms, n = ktimes["mtf_dense"]
         ach = mv_bytes / (ms / n * 1e-3) / 1e9
         roof = {"kernel": "mtf_dense", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic("mtf_dense"),
                 "avg_launch_us": round(1e3 * ms / n, 2), "bytes_per_launch": mv_bytes}
     else:
         ms, n = ktimes["regular_tiles"]
@@ -172,6 +260,8 @@ def main():
         "rel_residual": stats["rel_residual"],
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 3) for k, v in ktimes.items()},
     }
+    if not args.no_precision:
+        line["precision"] = precision_compare(ctx, B, synth, np)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_oracle_baseline(c)
     print(json.dumps(line), flush=True)

@@ -187,7 +187,7 @@ bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b
  * iterate is written).  stats may be NULL.
  * BEM_C64_MIXED: iterative refinement; each step solves the correction
  * system with GMRES on FP32 products (FP64 Krylov basis) to opts->ir_inner_tol
- * (0: half the remaining reduction, at least 1e-6), then recomputes
+ * (0: half the remaining reduction, at least 1e-7), then recomputes
  * M^-1 (b - A x) with FP64 arithmetic on the stored operators; at most
  * opts->ir_max steps (0: 10) and opts->maxit Arnoldi steps in total. */
 bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,

@@ -67,7 +67,10 @@ class Context:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: the library may already be gone
+            pass
 
 
 class Mesh:
@@ -90,7 +93,10 @@ class Mesh:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: the library may already be gone
+            pass
 
 
 class Problem:
@@ -113,7 +119,10 @@ class Problem:
             self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: the library may already be gone
+            pass
 
     def footprint(self, nrhs=1, maxit=500):
         b = ctypes.c_size_t()

@@ -398,16 +398,32 @@ struct MtfArgs {
 #define BEMTX_SPLIT_CW 512
 #endif
 #ifndef BEMTX_SPLIT_CW32
-#define BEMTX_SPLIT_CW32 1024
+#define BEMTX_SPLIT_CW32 2048
 #endif
 #ifndef BEMTX_MV_UNROLL
 #define BEMTX_MV_UNROLL 1
 #endif
 constexpr int SPLIT_CW_MAX = BEMTX_SPLIT_CW;     // columns per chunk, complex128 operators (upper bound)
 constexpr int SPLIT_CW32_MAX = BEMTX_SPLIT_CW32; // the same for complex64 operators
-constexpr int MASS_CW_MAX = 512;                 // inverse mass apply
-constexpr int SPLIT_CW_MIN = 512;                // smallest bound in use (sizes the partial buffer)
-constexpr int SPLIT_ROWS = 4;                    // rows per workgroup (one per wave)
+#ifndef BEMTX_MASS_CW
+#define BEMTX_MASS_CW 1024
+#endif
+constexpr int MASS_CW_MAX = BEMTX_MASS_CW;       // inverse mass apply
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+constexpr int SPLIT_CW_MIN = cmin(cmin(SPLIT_CW_MAX, SPLIT_CW32_MAX), MASS_CW_MAX);   // sizes the partial buffer
+constexpr int SPLIT_ROWS = 4;                    // waves per workgroup (one row each in the dense kernels)
+#ifndef BEMTX_MASS_RW64
+#define BEMTX_MASS_RW64 4
+#endif
+#ifndef BEMTX_MASS_RW32
+#define BEMTX_MASS_RW32 8
+#endif
+constexpr int MASS_RW64 = BEMTX_MASS_RW64;       // rows per wave of the FP64 inverse-mass apply
+constexpr int MASS_RW32 = BEMTX_MASS_RW32;       // the same, FP32 storage
+#ifndef BEMTX_DENSE32_RW
+#define BEMTX_DENSE32_RW 1
+#endif
+constexpr int DENSE32_RW = BEMTX_DENSE32_RW;     // rows per wave of the complex64 dense product
 
 __host__ __device__ inline int split_nchunk(int nv, int cwmax) { return (nv + cwmax - 1) / cwmax; }
 __host__ __device__ inline int split_cw(int nv, int cwmax)
@@ -489,9 +505,10 @@ __global__ __launch_bounds__(256) void mtf_dense_c64_part_kernel(MtfArgs A, cons
                                                                  const KrylovState *__restrict__ st)
 {
     using C = typename Cx<R>::T;
+    constexpr int RW = DENSE32_RW, ROWS = SPLIT_ROWS * DENSE32_RW;
     if (st && st->done) return;
     __shared__ C xs[2 * SPLIT_CW32_MAX];
-    const int te = (A.ne + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    const int te = (A.ne + ROWS - 1) / ROWS;
     const bool ext = (int)blockIdx.x < te;
     const int nv = ext ? A.ne : A.ni;
     const int chunk = blockIdx.y;
@@ -513,31 +530,41 @@ __global__ __launch_bounds__(256) void mtf_dense_c64_part_kernel(MtfArgs A, cons
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = (ext ? blockIdx.x : blockIdx.x - te) * SPLIT_ROWS + wave;
-    if (i >= nv) return;
+    const int i0 = (ext ? blockIdx.x : blockIdx.x - te) * ROWS + wave * RW;
+    if (i0 >= nv) return;
     const int mi = ext ? 0 : 1;
     const float2 *Vm = static_cast<const float2 *>(A.op[mi][0]), *Km = static_cast<const float2 *>(A.op[mi][1]);
     const float2 *Tm = static_cast<const float2 *>(A.op[mi][2]), *Dm = static_cast<const float2 *>(A.op[mi][3]);
-    const int64_t o = (int64_t)i * op_ld(nv) + c0;   // even: 16-byte aligned pairs
-    R ar = 0, ai = 0, br = 0, bi = 0;
+    int64_t o[RW];   // even offsets: 16-byte aligned pairs; rows past nv repeat the last row (results unused)
+#pragma unroll
+    for (int u = 0; u < RW; ++u) o[u] = (int64_t)min(i0 + u, nv - 1) * op_ld(nv) + c0;
+    R ar[RW], ai[RW], br[RW], bi[RW];
+#pragma unroll
+    for (int u = 0; u < RW; ++u) ar[u] = ai[u] = br[u] = bi[u] = 0;
     for (int j = 2 * lane; j < ncol; j += 128) {
-        const float4 k = ld_stream2c(&Km[o + j]), v = ld_stream2c(&Vm[o + j]);
-        const float4 d = ld_stream2c(&Dm[o + j]), t = ld_stream2c(&Tm[o + j]);
         const C p0 = xs[j], p1 = xs[j + 1], q0 = xs[SPLIT_CW32_MAX + j], q1 = xs[SPLIT_CW32_MAX + j + 1];
-        ar += -((R)k.x * p0.x - (R)k.y * p0.y) - ((R)k.z * p1.x - (R)k.w * p1.y)
-              + ((R)v.x * q0.x - (R)v.y * q0.y) + ((R)v.z * q1.x - (R)v.w * q1.y);
-        ai += -((R)k.x * p0.y + (R)k.y * p0.x) - ((R)k.z * p1.y + (R)k.w * p1.x)
-              + ((R)v.x * q0.y + (R)v.y * q0.x) + ((R)v.z * q1.y + (R)v.w * q1.x);
-        br += ((R)d.x * p0.x - (R)d.y * p0.y) + ((R)d.z * p1.x - (R)d.w * p1.y)
-              + ((R)t.x * q0.x - (R)t.y * q0.y) + ((R)t.z * q1.x - (R)t.w * q1.y);
-        bi += ((R)d.x * p0.y + (R)d.y * p0.x) + ((R)d.z * p1.y + (R)d.w * p1.x)
-              + ((R)t.x * q0.y + (R)t.y * q0.x) + ((R)t.z * q1.y + (R)t.w * q1.x);
+#pragma unroll
+        for (int u = 0; u < RW; ++u) {
+            const float4 k = ld_stream2c(&Km[o[u] + j]), v = ld_stream2c(&Vm[o[u] + j]);
+            const float4 d = ld_stream2c(&Dm[o[u] + j]), t = ld_stream2c(&Tm[o[u] + j]);
+            ar[u] += -((R)k.x * p0.x - (R)k.y * p0.y) - ((R)k.z * p1.x - (R)k.w * p1.y)
+                     + ((R)v.x * q0.x - (R)v.y * q0.y) + ((R)v.z * q1.x - (R)v.w * q1.y);
+            ai[u] += -((R)k.x * p0.y + (R)k.y * p0.x) - ((R)k.z * p1.y + (R)k.w * p1.x)
+                     + ((R)v.x * q0.y + (R)v.y * q0.x) + ((R)v.z * q1.y + (R)v.w * q1.x);
+            br[u] += ((R)d.x * p0.x - (R)d.y * p0.y) + ((R)d.z * p1.x - (R)d.w * p1.y)
+                     + ((R)t.x * q0.x - (R)t.y * q0.y) + ((R)t.z * q1.x - (R)t.w * q1.y);
+            bi[u] += ((R)d.x * p0.y + (R)d.y * p0.x) + ((R)d.z * p1.y + (R)d.w * p1.x)
+                     + ((R)t.x * q0.y + (R)t.y * q0.x) + ((R)t.z * q1.y + (R)t.w * q1.x);
+        }
     }
-    double sar = wave_sum((double)ar), sai = wave_sum((double)ai);
-    double sbr = wave_sum((double)br), sbi = wave_sum((double)bi);
-    if (lane == 0) {
-        const int row = ext ? i : A.ne + i;
-        part[(int64_t)chunk * (A.ne + A.ni) + row] = make_double4(sar, sai, sbr, sbi);
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+        const double sar = wave_sum((double)ar[u]), sai = wave_sum((double)ai[u]);
+        const double sbr = wave_sum((double)br[u]), sbi = wave_sum((double)bi[u]);
+        if (lane == 0 && i0 + u < nv) {
+            const int row = ext ? i0 + u : A.ne + i0 + u;
+            part[(int64_t)chunk * (A.ne + A.ni) + row] = make_double4(sar, sai, sbr, sbi);
+        }
     }
 }
 
@@ -578,9 +605,11 @@ __global__ __launch_bounds__(256) void mtf_combine_kernel(MtfArgs A, const doubl
 
 // part[chunk][row] = M^-1 row chunk applied to the mesh's two vectors; the
 // inverse is stored in FP64 (pairs of entries per lane) or FP32 (quads),
-// accumulation in FP64 either way.  Padding columns of M^-1 are zero and
-// the staged vectors are zero past the chunk's end.
-template <class MT>
+// accumulation in FP64 either way.  Each wave applies RW rows, so that the
+// staged vector entries read from LDS serve RW rows of M^-1 (LDS traffic
+// per HBM byte falls by RW).  Padding columns of M^-1 are zero and the
+// staged vectors are zero past the chunk's end.
+template <class MT, int RW>
 __global__ __launch_bounds__(256) void mass_apply_part_kernel(int ne, int ni, const MT *__restrict__ Me_inv,
                                                               const MT *__restrict__ Mi_inv,
                                                               const double2 *__restrict__ y, double4 *__restrict__ part,
@@ -588,9 +617,10 @@ __global__ __launch_bounds__(256) void mass_apply_part_kernel(int ne, int ni, co
 {
     constexpr bool f32 = sizeof(MT) == 4;
     constexpr int VW = f32 ? 4 : 2;   // entries per lane load (16 bytes)
+    constexpr int ROWS = SPLIT_ROWS * RW;
     if (st && st->done) return;
     __shared__ double2 ys[2 * MASS_CW_MAX];
-    const int te = (ne + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    const int te = (ne + ROWS - 1) / ROWS;
     const bool ext = (int)blockIdx.x < te;
     const int nv = ext ? ne : ni;
     const int chunk = blockIdx.y;
@@ -605,29 +635,44 @@ __global__ __launch_bounds__(256) void mass_apply_part_kernel(int ne, int ni, co
     }
     __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = (ext ? blockIdx.x : blockIdx.x - te) * SPLIT_ROWS + wave;
-    if (i >= nv) return;
-    const MT *Mr = (ext ? Me_inv : Mi_inv) + (int64_t)i * minv_ld(nv, f32) + c0;   // c0: multiple of 64
-    double ar = 0, ai = 0, br = 0, bi = 0;
+    const int i0 = (ext ? blockIdx.x : blockIdx.x - te) * ROWS + wave * RW;
+    if (i0 >= nv) return;
+    const int ld = minv_ld(nv, f32);
+    const MT *Mbase = (ext ? Me_inv : Mi_inv) + c0;   // c0: multiple of 64
+    const MT *Mr[RW];
+#pragma unroll
+    for (int u = 0; u < RW; ++u) Mr[u] = Mbase + (int64_t)min(i0 + u, nv - 1) * ld;   // rows past nv: unused
+    double ar[RW], ai[RW], br[RW], bi[RW];
+#pragma unroll
+    for (int u = 0; u < RW; ++u) ar[u] = ai[u] = br[u] = bi[u] = 0.0;
     for (int j = VW * lane; j < ncol; j += VW * 64) {
-        double m[VW];
-        if constexpr (f32) {
-            const v4f q = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Mr + j));
-            m[0] = q.x; m[1] = q.y; m[2] = q.z; m[3] = q.w;
-        } else {
-            const v2d q = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(Mr + j));
-            m[0] = q.x; m[1] = q.y;
+        double m[RW][VW];
+#pragma unroll
+        for (int u = 0; u < RW; ++u) {
+            if constexpr (f32) {
+                const v4f q = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(Mr[u] + j));
+                m[u][0] = q.x; m[u][1] = q.y; m[u][2] = q.z; m[u][3] = q.w;
+            } else {
+                const v2d q = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(Mr[u] + j));
+                m[u][0] = q.x; m[u][1] = q.y;
+            }
         }
 #pragma unroll
-        for (int u = 0; u < VW; ++u) {
-            const double2 a = ys[j + u], b = ys[MASS_CW_MAX + j + u];
-            ar += m[u] * a.x; ai += m[u] * a.y; br += m[u] * b.x; bi += m[u] * b.y;
+        for (int e = 0; e < VW; ++e) {
+            const double2 a = ys[j + e], b = ys[MASS_CW_MAX + j + e];
+#pragma unroll
+            for (int u = 0; u < RW; ++u) {
+                ar[u] += m[u][e] * a.x; ai[u] += m[u][e] * a.y; br[u] += m[u][e] * b.x; bi[u] += m[u][e] * b.y;
+            }
         }
     }
-    ar = wave_sum(ar); ai = wave_sum(ai); br = wave_sum(br); bi = wave_sum(bi);
-    if (lane == 0) {
-        const int row = ext ? i : ne + i;
-        part[(int64_t)chunk * (ne + ni) + row] = make_double4(ar, ai, br, bi);
+#pragma unroll
+    for (int u = 0; u < RW; ++u) {
+        const double sar = wave_sum(ar[u]), sai = wave_sum(ai[u]), sbr = wave_sum(br[u]), sbi = wave_sum(bi[u]);
+        if (lane == 0 && i0 + u < nv) {
+            const int row = ext ? i0 + u : ne + i0 + u;
+            part[(int64_t)chunk * (ne + ni) + row] = make_double4(sar, sai, sbr, sbi);
+        }
     }
 }
 
@@ -651,9 +696,10 @@ __global__ __launch_bounds__(256) void mass_combine_kernel(int ne, int ni, const
     za[i + nv] = make_double2(br, bi);
 }
 
-static inline dim3 split_grid(int ne, int ni, int cwmax)
+static inline dim3 split_grid(int ne, int ni, int cwmax, int rw = 1)
 {
-    const int tiles = (ne + SPLIT_ROWS - 1) / SPLIT_ROWS + (ni + SPLIT_ROWS - 1) / SPLIT_ROWS;
+    const int rows = SPLIT_ROWS * rw;
+    const int tiles = (ne + rows - 1) / rows + (ni + rows - 1) / rows;
     return dim3(tiles, std::max(split_nchunk(ne, cwmax), split_nchunk(ni, cwmax)));
 }
 
@@ -926,13 +972,12 @@ bem_status apply_Minv(const bem_problem *p, const double2 *y, double2 *z, double
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
     {
         KTimer kt(p->ctx, K_MASS_APPLY);
-        const dim3 g = split_grid(ne, ni, MASS_CW_MAX);
         if (p->prec == BEM_C128)
-            launch_k(kt, mass_apply_part_kernel<double>, g, dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(),
-                     p->Minv[1].as<double>(), y, part, kst);
+            launch_k(kt, mass_apply_part_kernel<double, MASS_RW64>, split_grid(ne, ni, MASS_CW_MAX, MASS_RW64),
+                     dim3(256), 0, st, ne, ni, p->Minv[0].as<double>(), p->Minv[1].as<double>(), y, part, kst);
         else
-            launch_k(kt, mass_apply_part_kernel<float>, g, dim3(256), 0, st, ne, ni, p->Minv[0].as<float>(),
-                     p->Minv[1].as<float>(), y, part, kst);
+            launch_k(kt, mass_apply_part_kernel<float, MASS_RW32>, split_grid(ne, ni, MASS_CW_MAX, MASS_RW32),
+                     dim3(256), 0, st, ne, ni, p->Minv[0].as<float>(), p->Minv[1].as<float>(), y, part, kst);
     }
     hipLaunchKernelGGL(mass_combine_kernel, dim3((ne + ni + 255) / 256), dim3(256), 0, st, ne, ni, part, z, kst);
     BEM_HIP(hipGetLastError());
@@ -948,13 +993,14 @@ bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, dou
     const int rows = A.ne + A.ni;
     {
         KTimer kt(p->ctx, K_MTF_DENSE);
-        const dim3 g = split_grid(A.ne, A.ni, A.cw);
         if (p->prec == BEM_C128)
-            launch_k(kt, mtf_dense_part_kernel, g, dim3(256), 0, st, A, x, part, kst);
+            launch_k(kt, mtf_dense_part_kernel, split_grid(A.ne, A.ni, A.cw), dim3(256), 0, st, A, x, part, kst);
         else if (acc64)
-            launch_k(kt, mtf_dense_c64_part_kernel<double>, g, dim3(256), 0, st, A, x, part, kst);
+            launch_k(kt, mtf_dense_c64_part_kernel<double>, split_grid(A.ne, A.ni, A.cw, DENSE32_RW), dim3(256), 0,
+                     st, A, x, part, kst);
         else
-            launch_k(kt, mtf_dense_c64_part_kernel<float>, g, dim3(256), 0, st, A, x, part, kst);
+            launch_k(kt, mtf_dense_c64_part_kernel<float>, split_grid(A.ne, A.ni, A.cw, DENSE32_RW), dim3(256), 0,
+                     st, A, x, part, kst);
     }
     hipLaunchKernelGGL(mtf_combine_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, A, x, part, y, kst);
     BEM_HIP(hipGetLastError());
@@ -1260,7 +1306,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
             int used = 0, steps = 0;
             while (b0 > 0.0 && rel > opts->tol && steps < ir_max && used < m) {
                 const double inner = opts->ir_inner_tol > 0 ? opts->ir_inner_tol
-                                                            : std::max(0.5 * opts->tol / rel, 1e-6);
+                                                            : std::max(0.5 * opts->tol / rel, 1e-7);
                 s = gm.run(rhs_s, inner, m - used, W.d.as<double2>(), fin);
                 if (s) return s;
                 used += fin.iters;
