@@ -82,6 +82,8 @@ typedef struct {
     int32_t maxit;            /* Arnoldi steps (no restart, Sec. 5.1), 1..3000 */
     int32_t ir_max;           /* BEM_C64_MIXED: outer refinement steps (0: 10) */
     double ir_inner_tol;      /* BEM_C64_MIXED: inner GMRES tolerance (0: automatic) */
+    int32_t batch;            /* BEM_C64_MIXED: right-hand sides solved together through one
+                                 matrix-core product per step (2..64; 0 or 1: one at a time) */
 } bem_solver_opts;
 
 typedef struct {
@@ -171,6 +173,15 @@ bem_status bem_assemble_projection(bem_problem *p);
  * FP32 accumulation (the product GMRES uses). */
 bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space);
 
+/* The same product for nrhs vectors at once: x, y complex128 [nrhs][n].
+ * BEM_C64_MIXED problems run it on the matrix cores (FP32 products of the
+ * complex64 blocks with up to 64 vectors per pass, the complex product as one
+ * real product with 2 x 2 blocks per complex entry; FP64 for the mortar
+ * terms and the sums of the K chunks); BEM_C128 problems apply the single
+ * product to each vector. */
+bem_status bem_mtf_matvec_batch(bem_problem *p, const void *x, void *y, int32_t nrhs, int32_t strong,
+                                bem_memspace space);
+
 /* Right-hand side [-f, -g, 0, 0] of the multiple-traces system for the
  * plane wave exp(i k_ext d.x) (Sec. 5.3, Eq. "planewave"):
  * f_j = <u_inc, phi_j>, g_j = <du_inc/dn, phi_j> on the exterior mesh.
@@ -189,7 +200,11 @@ bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b
  * system with GMRES on FP32 products (FP64 Krylov basis) to opts->ir_inner_tol
  * (0: half the remaining reduction, at least 1e-7), then recomputes
  * M^-1 (b - A x) with FP64 arithmetic on the stored operators; at most
- * opts->ir_max steps (0: 10) and opts->maxit Arnoldi steps in total. */
+ * opts->ir_max steps (0: 10) and opts->maxit Arnoldi steps in total.
+ * With opts->batch > 1 up to that many right-hand sides run as independent
+ * GMRES instances that share one matrix-core product per step (each run has
+ * its own Krylov basis, rotations and stopping test, so each result equals
+ * its single solve up to FP32 rounding of the products). */
 bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
                      void *traces, bem_memspace space, bem_stats *stats);
 

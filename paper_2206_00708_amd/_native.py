@@ -16,7 +16,7 @@ class QuadOpts(ctypes.Structure):
 
 
 class SolverOpts(ctypes.Structure):
-    _fields_ = [("tol", f64), ("maxit", i32), ("ir_max", i32), ("ir_inner_tol", f64)]
+    _fields_ = [("tol", f64), ("maxit", i32), ("ir_max", i32), ("ir_inner_tol", f64), ("batch", i32)]
 
 
 class Stats(ctypes.Structure):
@@ -46,6 +46,7 @@ SIGNATURES = {
     "bem_assemble_operators": (c_status, [vp, i32]),
     "bem_assemble_projection": (c_status, [vp]),
     "bem_mtf_matvec": (c_status, [vp, vp, vp, i32, i32]),
+    "bem_mtf_matvec_batch": (c_status, [vp, vp, vp, i32, i32, i32]),
     "bem_mtf_rhs": (c_status, [vp, vp, i32, vp, i32]),
     "bem_solve": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
     "bem_copy_operator": (c_status, [vp, i32, ctypes.c_char, vp, i32]),

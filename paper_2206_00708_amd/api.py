@@ -46,7 +46,7 @@ class Context:
         return N.load().bem_ctx_bytes_in_use(self._h)
 
     KERNELS = ("regular_tiles", "gather_tiles", "singular_pairs", "near_scatter", "mtf_dense", "mass_apply",
-               "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse")
+               "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse", "block_gemm")
 
     def set_kernel_timing(self, kernels=()):
         """Time every launch of the named kernels with HIP events (empty: off)."""
@@ -141,16 +141,23 @@ class Problem:
         _check(N.load().bem_mtf_matvec(self._h, _ptr(x), _ptr(y), int(strong), DEVICE))
         return y
 
+    def mtf_matvec_batch(self, x, strong=True):
+        """x: [nrhs, n] complex; one product per row (matrix cores for complex64 problems)."""
+        x = x.to(device=self.ctx.device, dtype=torch.complex128).contiguous()
+        y = torch.empty_like(x)
+        _check(N.load().bem_mtf_matvec_batch(self._h, _ptr(x), _ptr(y), x.shape[0], int(strong), DEVICE))
+        return y
+
     def mtf_rhs(self, dirs):
         d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
         b = torch.empty((d.shape[0], self.n), dtype=torch.complex128, device=self.ctx.device)
         _check(N.load().bem_mtf_rhs(self._h, d.ctypes.data, d.shape[0], _ptr(b), DEVICE))
         return b
 
-    def solve(self, dirs, tol=1e-6, maxit=1000, ir_max=0, ir_inner_tol=0.0):
+    def solve(self, dirs, tol=1e-6, maxit=1000, ir_max=0, ir_inner_tol=0.0, batch=0):
         d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
         out = torch.empty((d.shape[0], self.n), dtype=torch.complex128, device=self.ctx.device)
-        opts = N.SolverOpts(tol, maxit, ir_max, ir_inner_tol)
+        opts = N.SolverOpts(tol, maxit, ir_max, ir_inner_tol, batch)
         st = N.Stats()
         code = _check(N.load().bem_solve(self._h, d.ctypes.data, d.shape[0], ctypes.byref(opts), _ptr(out), DEVICE,
                                          ctypes.byref(st)))

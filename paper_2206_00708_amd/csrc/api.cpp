@@ -76,12 +76,13 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh);
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats);
 bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space);
+bem_status matvec_batch_impl(bem_problem *p, const void *x, void *y, int nrhs, int strong, bem_memspace space);
 bem_status rhs_impl(bem_problem *p, const double *dirs, int nrhs, void *b, bem_memspace space);
 bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, void *dst);
 
 const char *const kKernelNames[K_COUNT] = {"regular_tiles", "gather_tiles", "singular_pairs", "near_scatter",
                                            "mtf_dense", "mass_apply", "cgs_dots", "cgs_update", "arnoldi_finish",
-                                           "mass_inverse"};
+                                           "mass_inverse", "block_gemm"};
 
 static hipEvent_t take_event(bem_ctx *c)
 {
@@ -433,6 +434,14 @@ bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong
     return matvec_impl(p, x, y, strong, space);
 }
 
+bem_status bem_mtf_matvec_batch(bem_problem *p, const void *x, void *y, int32_t nrhs, int32_t strong,
+                                bem_memspace space)
+{
+    if (!p || !x || !y || nrhs < 1) return set_error(BEM_E_ARG, "bad argument");
+    if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
+    return matvec_batch_impl(p, x, y, nrhs, strong, space);
+}
+
 bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b, bem_memspace space)
 {
     if (!p || !dirs || !b || nrhs < 1) return set_error(BEM_E_ARG, "bad argument");
@@ -445,6 +454,7 @@ bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem
     if (!p || !dirs || !opts || !traces || nrhs < 1) return set_error(BEM_E_ARG, "bad argument");
     if (!(opts->tol > 0) || opts->maxit < 1 || opts->maxit > 3000)
         return set_error(BEM_E_ARG, "tol must be > 0 and 1 <= maxit <= 3000");
+    if (opts->batch < 0 || opts->batch > 64) return set_error(BEM_E_ARG, "batch must be 0..64");
     if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
     for (int r = 0; r < nrhs; ++r) {
         double l = std::sqrt(dirs[3 * r] * dirs[3 * r] + dirs[3 * r + 1] * dirs[3 * r + 1] + dirs[3 * r + 2] * dirs[3 * r + 2]);

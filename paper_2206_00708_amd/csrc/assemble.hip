@@ -467,12 +467,13 @@ __global__ __launch_bounds__(256) void gather_tiles_kernel(int nv, int nb, const
     K[o] = C2{kx, ky};
     T[o] = C2{tx, ty};
     D[o] = C2{dx, dy};
-    if ((nv & 1) && j == nv - 1) {   // padding column of odd rows: zero
-        V[o + 1] = C2{0, 0};
-        K[o + 1] = C2{0, 0};
-        T[o + 1] = C2{0, 0};
-        D[o + 1] = C2{0, 0};
-    }
+    if (j == nv - 1)   // padding columns of the row: zero
+        for (int64_t c = 1; c < op_ld(nv) - nv + 1; ++c) {
+            V[o + c] = C2{0, 0};
+            K[o + c] = C2{0, 0};
+            T[o + c] = C2{0, 0};
+            D[o + c] = C2{0, 0};
+        }
 }
 
 // ----------------------------------------------------------- singular pairs

@@ -23,9 +23,11 @@ constexpr int SMAX = 24;
 constexpr int LMAX = 12;
 constexpr int NG_MAX = 16;
 
-// Row stride (elements) of the dense operator matrices: even, so a row of
-// complex64 entries starts on a 16-byte boundary.
-__host__ __device__ inline int64_t op_ld(int64_t nv) { return (nv + 1) & ~int64_t(1); }
+// Row stride (elements) of the dense operator matrices: a multiple of 16, so
+// rows start on 128-byte boundaries and a complex64 row read as floats has a
+// length that is a multiple of 32 (the k step of the matrix-core product).
+// Padding columns hold zeros.
+__host__ __device__ inline int64_t op_ld(int64_t nv) { return (nv + 15) & ~int64_t(15); }
 
 // Per-triangle geometry table, built on the device (40 doubles, 320 B).
 struct alignas(16) TriGeo {
@@ -136,7 +138,7 @@ void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue me
 namespace bemtx {
 // kernels timed by the optional per-launch HIP-event timer of a context
 enum KernelId { K_REGULAR = 0, K_GATHER, K_SINGULAR, K_NEAR, K_MTF_DENSE, K_MASS_APPLY, K_CGS_DOTS, K_CGS_UPDATE,
-                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_COUNT };
+                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_BLOCK_GEMM, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 }  // namespace bemtx
 
@@ -182,6 +184,26 @@ inline void launch_k(const KTimer &kt, void (*kernel)(KArgs...), dim3 grid, dim3
 
 // Resolve finished timings (call after the stream has been synchronised).
 void flush_kernel_timing(bem_ctx *ctx);
+
+// Matrix-core FP32 product C[kc][c][row] = sum over the k of chunk kc of
+// A[row][k] Bt[c][k] (gemm.hip).  Up to GEMM_MAXSEG independent segments per
+// launch; K and kchunk multiples of 32, Bt with 128 * ncb rows.
+constexpr int GEMM_MAXSEG = 8;
+struct GemmSeg {
+    const float *A;     // [M][lda], row-major
+    const float *Bt;    // [128 ncb][ldb], k contiguous
+    float *C;           // [nk][128 ncb][M], nk = ceil(K / kchunk)
+    int64_t lda, ldb;
+    int M, K, kchunk, ncb;
+    int tile0;          // set by the launcher
+};
+struct GemmArgs {
+    GemmSeg seg[GEMM_MAXSEG];
+    int nseg;
+    const int *done;    // optional: nrun flags, done_stride ints apart; all set = skip
+    int done_stride, nrun;
+};
+bem_status launch_gemm_f32(bem_ctx *ctx, GemmArgs &G, hipStream_t st);
 }  // namespace bemtx
 
 struct bem_mesh {
@@ -210,4 +232,6 @@ struct bem_problem {
     double t_geometry_ms = 0, t_regular_ms = 0, t_singular_ms = 0, t_projection_ms = 0;
     hipEvent_t asm_ev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     bool asm_timing_pending = false;
+    // multi-RHS products: K chunks per GEMM (operators, inverse masses), picked by timing at first use
+    int gemm_nk_ops = 0, gemm_nk_mass = 0;
 };

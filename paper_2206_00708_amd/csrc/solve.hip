@@ -53,8 +53,9 @@ __host__ __device__ constexpr double q6_bary(int q, int c)
 __host__ __device__ constexpr double q6_w(int q) { return q < 3 ? kW1 : kW2; }
 
 // row stride of the dense inverse mass matrices: rows start on 16-byte
-// boundaries (even for FP64 storage, a multiple of four for FP32)
-__host__ __device__ inline int minv_ld(int nv, bool f32) { return f32 ? (nv + 3) & ~3 : (nv + 1) & ~1; }
+// boundaries (even for FP64 storage; a multiple of 32 for FP32, the k step of
+// the matrix-core product)
+__host__ __device__ inline int minv_ld(int nv, bool f32) { return f32 ? (nv + 31) & ~31 : (nv + 1) & ~1; }
 
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -378,6 +379,19 @@ struct KrylovState {
     int iters;      // Arnoldi steps taken
     double resid;   // |g_{j+1}| / beta0
     double beta0;
+    double tol;     // relative residual target of this run
+};
+
+// Element strides between the work arrays of independent GMRES runs that
+// advance together (run r = a grid index); all zero for a single run.
+struct KBatch {
+    int64_t basis;     // Krylov basis: (m + 1) n
+    int64_t vec;       // work vector: n
+    int64_t partial;   // CGS partial dot products: nchunk (m + 1)
+    int64_t small;     // h sums and g: m + 1
+    int64_t npart;     // norm partials: row blocks
+    int64_t hess;      // triangular factor: m (m + 1)
+    int64_t rot;       // Givens cosines and sines: m
 };
 
 
@@ -717,12 +731,16 @@ constexpr int CGS_CHUNK = 1024;   // rows per partial dot product
 constexpr int MAXIT_CAP = 3000;   // Hessenberg column, rotations and g staged in LDS
 
 // partial[chunk][c] = sum over the rows of `chunk` of conj(Vb[c][r]) w[r];
-// one wave per (chunk, c): grid (nchunk, ceil(nvec / 4)), 4 waves per block.
+// one wave per (chunk, c): grid (nchunk, ceil(nvec / 4), runs), 4 waves per block.
 __global__ __launch_bounds__(256) void cgs_dots_kernel(int n, int nvec, const double2 *__restrict__ Vb,
                                                        const double2 *__restrict__ w, double2 *__restrict__ partial,
-                                                       const KrylovState *__restrict__ st)
+                                                       const KrylovState *__restrict__ st, KBatch B)
 {
-    if (st->done) return;
+    const int run = blockIdx.z;
+    if (st[run].done) return;
+    Vb += run * B.basis;
+    w += run * B.vec;
+    partial += run * B.partial;
     const int lane = threadIdx.x & 63;
     const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (c >= nvec) return;
@@ -741,12 +759,19 @@ __global__ __launch_bounds__(256) void cgs_dots_kernel(int n, int nvec, const do
 
 // h = sum of the partials (fixed order); w -= Vb h; hsum = h (pass 0) or
 // hsum += h (pass 1, which also writes the partial squared norms of w).
+// Grid (row blocks, runs).
 __global__ __launch_bounds__(256) void cgs_update_kernel(int n, int nvec, int nchunk, const double2 *__restrict__ Vb,
                                                          const double2 *__restrict__ partial, double2 *__restrict__ w,
                                                          double2 *__restrict__ hsum, int pass, double *__restrict__ npart,
-                                                         const KrylovState *__restrict__ st)
+                                                         const KrylovState *__restrict__ st, KBatch B)
 {
-    if (st->done) return;
+    const int run = blockIdx.y;
+    if (st[run].done) return;
+    Vb += run * B.basis;
+    partial += run * B.partial;
+    w += run * B.vec;
+    hsum += run * B.small;
+    npart += run * B.npart;
     extern __shared__ double2 hs[];
     __shared__ double red[4];
     for (int c = threadIdx.x; c < nvec; c += blockDim.x) {
@@ -776,9 +801,12 @@ __global__ __launch_bounds__(256) void cgs_update_kernel(int n, int nvec, int nc
     }
 }
 
-// partial[blk] = sum |w|^2 over 256-row blocks (used for the initial residual)
-__global__ __launch_bounds__(256) void norm_partial_kernel(int n, const double2 *__restrict__ w, double *__restrict__ partial)
+// partial[blk] = sum |w|^2 over 256-row blocks; grid (row blocks, runs)
+__global__ __launch_bounds__(256) void norm_partial_kernel(int n, const double2 *__restrict__ w, int64_t wstride,
+                                                           double *__restrict__ partial, int64_t pstride)
 {
+    w += blockIdx.y * wstride;
+    partial += blockIdx.y * pstride;
     __shared__ double red[4];
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     double s = r < n ? w[r].x * w[r].x + w[r].y * w[r].y : 0.0;
@@ -788,16 +816,20 @@ __global__ __launch_bounds__(256) void norm_partial_kernel(int n, const double2 
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// beta = sqrt(sum partial); out = w / beta; beta_out = beta (initial vector)
+// beta = sqrt(sum partial); out = w / beta; beta_out = beta; grid (row blocks, runs)
 __global__ __launch_bounds__(256) void normalize_kernel(int n, int nblk, const double *__restrict__ partial,
-                                                        const double2 *__restrict__ w, double2 *__restrict__ out,
+                                                        int64_t pstride, const double2 *__restrict__ w, int64_t wstride,
+                                                        double2 *__restrict__ out, int64_t ostride,
                                                         double *__restrict__ beta_out)
 {
+    partial += blockIdx.y * pstride;
+    w += blockIdx.y * wstride;
+    out += blockIdx.y * ostride;
     double s = 0;
     for (int b = 0; b < nblk; ++b) s += partial[b];
     const double beta = sqrt(s);
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r == 0) *beta_out = beta;
+    if (r == 0) beta_out[blockIdx.y] = beta;
     if (r >= n) return;
     const double inv = beta > 0 ? 1.0 / beta : 0.0;
     out[r] = make_double2(w[r].x * inv, w[r].y * inv);
@@ -808,16 +840,27 @@ __device__ inline double2 cconj_mul(double2 a, double2 b)   // conj(a) * b
     return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
-// v_{j+1} = w / beta; block 0: Hessenberg column j (hsum, beta) through the
-// previous Givens rotations, the new rotation, g and the residual estimate.
+// v_{j+1} = w / beta; block 0 of each run: Hessenberg column j (hsum, beta)
+// through the previous Givens rotations, the new rotation, g and the
+// residual estimate.  Grid (row blocks, runs).
 __global__ __launch_bounds__(256) void arnoldi_finish_kernel(int n, int nblk, const double *__restrict__ npart,
                                                              const double2 *__restrict__ w, double2 *__restrict__ vnext,
-                                                             int j, int m, double tol, const double2 *__restrict__ hsum,
+                                                             int j, int m, const double2 *__restrict__ hsum,
                                                              double2 *__restrict__ R, double2 *__restrict__ g,
                                                              double2 *__restrict__ cs, double2 *__restrict__ sn,
-                                                             KrylovState *__restrict__ st)
+                                                             KrylovState *__restrict__ st, KBatch B)
 {
+    const int run = blockIdx.y;
+    st += run;
     if (st->done) return;
+    npart += run * B.npart;
+    w += run * B.vec;
+    vnext += run * B.basis;
+    hsum += run * B.small;
+    R += run * B.hess;
+    g += run * B.small;
+    cs += run * B.rot;
+    sn += run * B.rot;
     double s2 = 0;
     for (int b = 0; b < nblk; ++b) s2 += npart[b];
     const double beta = sqrt(s2);
@@ -855,19 +898,25 @@ __global__ __launch_bounds__(256) void arnoldi_finish_kernel(int n, int nblk, co
     const double res = sqrt(sg.x * sg.x + sg.y * sg.y) / st->beta0;
     st->resid = res;
     st->iters = j + 1;
-    if (res <= tol || beta == 0.0 || j + 1 >= m) st->done = 1;
+    if (res <= st->tol || beta == 0.0 || j + 1 >= m) st->done = 1;
 }
 
-__global__ void krylov_init_kernel(int m, const double *__restrict__ beta0, double2 *__restrict__ g,
-                                   KrylovState *__restrict__ st)
+// g = [beta0, 0, ...] and the state of each run; grid (ceil((m + 1) / 256), runs)
+__global__ void krylov_init_kernel(int m, const double *__restrict__ beta0, const double *__restrict__ tol,
+                                   double2 *__restrict__ g, KrylovState *__restrict__ st, KBatch B)
 {
+    const int run = blockIdx.y;
+    g += run * B.small;
+    st += run;
+    const double b0 = beta0[run];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= m) g[i] = make_double2(i == 0 ? *beta0 : 0.0, 0.0);
+    if (i <= m) g[i] = make_double2(i == 0 ? b0 : 0.0, 0.0);
     if (i == 0) {
-        st->beta0 = *beta0;
-        st->done = *beta0 == 0.0 ? 1 : 0;
+        st->beta0 = b0;
+        st->tol = tol[run];
+        st->done = b0 == 0.0 ? 1 : 0;
         st->iters = 0;
-        st->resid = *beta0 == 0.0 ? 0.0 : 1.0;
+        st->resid = b0 == 0.0 ? 0.0 : 1.0;
     }
 }
 
@@ -886,6 +935,137 @@ __global__ void axpy_sub_kernel(int n, const double2 *__restrict__ a, const doub
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) out[r] = make_double2(a[r].x - b[r].x, a[r].y - b[r].y);
+}
+
+// ------------------------------------------- multi-RHS (block) products
+//
+// R Krylov vectors (one per independent GMRES run) go through the dense
+// blocks together on the matrix cores (gemm.hip).  The right-hand matrices
+// are built from the FP64 vectors in FP32: for complex operators each
+// complex entry x = (a, b) of run r becomes Bt[2r][2j] = a,
+// Bt[2r][2j + 1] = -b, Bt[2r + 1][2j] = b, Bt[2r + 1][2j + 1] = a, so the
+// real product of an interleaved complex row gives (re, im) of the complex
+// product in columns 2r, 2r + 1.  Runs that have converged, runs past R and
+// padding rows contribute zeros.
+
+constexpr int BLOCK_RHS = 64;   // runs per block product (128 real columns)
+
+__device__ inline bool run_active(const KrylovState *st, int r, int R)
+{
+    return r < R && !(st && st[r].done);
+}
+
+// Bt_v, Bt_w [128][kld] of one mesh from its [v; w] part of every run;
+// grid (ceil(op_ld(nv) / 256), BLOCK_RHS)
+__global__ __launch_bounds__(256) void pack_ops_kernel(int nv, int kld, int R, const double2 *__restrict__ X,
+                                                       int64_t xstride, int voff, const KrylovState *__restrict__ st,
+                                                       float *__restrict__ Btv, float *__restrict__ Btw)
+{
+    const int r = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (2 * j >= kld) return;
+    double2 v = make_double2(0, 0), w = v;
+    if (j < nv && run_active(st, r, R)) {
+        const double2 *x = X + r * xstride + voff;
+        v = x[j];
+        w = x[nv + j];
+    }
+    float *a0 = Btv + (int64_t)(2 * r) * kld + 2 * j, *a1 = a0 + kld;
+    float *b0 = Btw + (int64_t)(2 * r) * kld + 2 * j, *b1 = b0 + kld;
+    *reinterpret_cast<float2 *>(a0) = make_float2((float)v.x, -(float)v.y);
+    *reinterpret_cast<float2 *>(a1) = make_float2((float)v.y, (float)v.x);
+    *reinterpret_cast<float2 *>(b0) = make_float2((float)w.x, -(float)w.y);
+    *reinterpret_cast<float2 *>(b1) = make_float2((float)w.y, (float)w.x);
+}
+
+// Partial products of the eight dense blocks: C[mesh][op] is [nk][128][N]
+// (column-major tiles of the GEMM output), op order V, K, T, D.
+struct BlockC {
+    const float *C[2][4];
+    int nk[2];
+};
+
+// y rows of every run = sums of the K-chunk partials (fixed order) with the
+// block signs of Eq. "mtf:discrete" plus the mortar coupling in FP64;
+// grid (ceil((ne + ni) / 256), R), one thread per row and run.
+__global__ __launch_bounds__(256) void block_combine_kernel(MtfArgs A, BlockC bc, int R, const double2 *__restrict__ X,
+                                                            int64_t xstride, double2 *__restrict__ Y, int64_t ystride,
+                                                            const KrylovState *__restrict__ st)
+{
+    const int r = blockIdx.y;
+    if (!run_active(st, r, R)) return;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= A.ne + A.ni) return;
+    const bool ext = row < A.ne;
+    const int mi = ext ? 0 : 1;
+    const int i = ext ? row : row - A.ne;
+    const int nv = ext ? A.ne : A.ni;
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    for (int kc = 0; kc < bc.nk[mi]; ++kc) {
+        const int64_t o0 = ((int64_t)kc * 128 + 2 * r) * nv + i, o1 = o0 + nv;
+        ar += (double)bc.C[mi][0][o0] - (double)bc.C[mi][1][o0];
+        ai += (double)bc.C[mi][0][o1] - (double)bc.C[mi][1][o1];
+        br += (double)bc.C[mi][3][o0] + (double)bc.C[mi][2][o0];
+        bi += (double)bc.C[mi][3][o1] + (double)bc.C[mi][2][o1];
+    }
+    const double2 *x = X + r * xstride;
+    const int32_t *pp = ext ? A.pei_ptr : A.pie_ptr;
+    const int32_t *pc = ext ? A.pei_col : A.pie_col;
+    const double *pv = ext ? A.pei_val : A.pie_val;
+    const double2 *cv = ext ? x + 2 * A.ne : x;
+    const int nother = ext ? A.ni : A.ne;
+    const double2 *cwp = cv + nother;
+    const double fv = ext ? A.c_ext_v : A.c_int_v, fw = ext ? A.c_ext_w : A.c_int_w;
+    double sr = 0, si = 0, tr = 0, ti = 0;
+    for (int q = pp[i]; q < pp[i + 1]; ++q) {
+        const double pvq = pv[q];
+        const double2 a = cv[pc[q]], b = cwp[pc[q]];
+        sr += pvq * a.x; si += pvq * a.y; tr += pvq * b.x; ti += pvq * b.y;
+    }
+    double2 *y = Y + r * ystride + (ext ? 0 : 2 * A.ne);
+    y[i] = make_double2(ar + fv * sr, ai + fv * si);
+    y[i + nv] = make_double2(br + fw * tr, bi + fw * ti);
+}
+
+// Bt [4 BLOCK_RHS][kld] of one mesh for the inverse-mass product: column
+// 4r + q = Re y1, Im y1, Re y2, Im y2 of run r; grid (ceil(kld / 256), 4 BLOCK_RHS)
+__global__ __launch_bounds__(256) void pack_mass_kernel(int nv, int kld, int R, const double2 *__restrict__ Y,
+                                                        int64_t ystride, int yoff, const KrylovState *__restrict__ st,
+                                                        float *__restrict__ Bt)
+{
+    const int c = blockIdx.y, r = c >> 2, q = c & 3;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= kld) return;
+    float val = 0.f;
+    if (k < nv && run_active(st, r, R)) {
+        const double2 y = Y[r * ystride + yoff + (q >= 2 ? nv : 0) + k];
+        val = (float)((q & 1) ? y.y : y.x);
+    }
+    Bt[(int64_t)c * kld + k] = val;
+}
+
+// z rows of every run from the inverse-mass partials [nk][256][N] of each mesh;
+// grid (ceil((ne + ni) / 256), R)
+__global__ __launch_bounds__(256) void mass_reduce_kernel(int ne, int ni, const float *__restrict__ Ce,
+                                                          const float *__restrict__ Ci, int nke, int nki, int R,
+                                                          double2 *__restrict__ Z, int64_t zstride,
+                                                          const KrylovState *__restrict__ st)
+{
+    const int r = blockIdx.y;
+    if (!run_active(st, r, R)) return;
+    const int row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= ne + ni) return;
+    const bool ext = row < ne;
+    const int i = ext ? row : row - ne;
+    const int nv = ext ? ne : ni;
+    const float *C = ext ? Ce : Ci;
+    const int nk = ext ? nke : nki;
+    double s[4] = {0, 0, 0, 0};
+    for (int kc = 0; kc < nk; ++kc)
+        for (int q = 0; q < 4; ++q) s[q] += (double)C[((int64_t)kc * 4 * BLOCK_RHS + 4 * r + q) * nv + i];
+    double2 *z = Z + r * zstride + (ext ? 0 : 2 * ne);
+    z[i] = make_double2(s[0], s[1]);
+    z[i + nv] = make_double2(s[2], s[3]);
 }
 
 // ---------------------------------------------------- numbering changes
@@ -939,7 +1119,13 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, v
 namespace {
 
 struct Work {
-    DevMem xin, d, y, z, b, r, Vb, partial, hsum, beta, yc, npart, R, g, cs, sn, state, part;
+    DevMem xin, d, y, z, b, r, Vb, partial, hsum, beta, tolv, yc, npart, R, g, cs, sn, state, part;
+};
+
+// Buffers of the multi-RHS products (one set per solve or batched mat-vec).
+struct BlockBufs {
+    DevMem btv[2], btw[2], cop, btm[2], cm;
+    int64_t cop_off[2][4], cm_off[2];
 };
 
 MtfArgs make_args(const bem_problem *p)
@@ -1013,8 +1199,170 @@ bem_status norm_to(const bem_problem *p, int n, const double2 *w, double *npart,
 {
     hipStream_t st = p->ctx->stream;
     const int nblk = (n + 255) / 256;
-    hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(256), 0, st, n, w, npart);
-    hipLaunchKernelGGL(normalize_kernel, dim3(nblk), dim3(256), 0, st, n, nblk, npart, w, scratch_vec, out);
+    hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(256), 0, st, n, w, (int64_t)0, npart, (int64_t)0);
+    hipLaunchKernelGGL(normalize_kernel, dim3(nblk), dim3(256), 0, st, n, nblk, npart, (int64_t)0, w, (int64_t)0,
+                       scratch_vec, (int64_t)0, out);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+}
+
+int kchunk_for(int K, int nk) { return ((K + nk - 1) / nk + 31) / 32 * 32; }
+int nchunks(int K, int kc) { return (K + kc - 1) / kc; }
+
+bem_status block_alloc(bem_problem *p, BlockBufs &bb)
+{
+    bem_ctx *ctx = p->ctx;
+    const int nv[2] = {(int)p->ext->h.nv, (int)p->inte->h.nv};
+    size_t cop = 0, cm = 0;
+    for (int m = 0; m < 2; ++m) {
+        const int kop = 2 * (int)op_ld(nv[m]), km = minv_ld(nv[m], true);
+        bem_status s = dev_alloc(ctx, bb.btv[m], (size_t)2 * BLOCK_RHS * kop * sizeof(float));
+        if (!s) s = dev_alloc(ctx, bb.btw[m], (size_t)2 * BLOCK_RHS * kop * sizeof(float));
+        if (!s) s = dev_alloc(ctx, bb.btm[m], (size_t)4 * BLOCK_RHS * km * sizeof(float));
+        if (s) return s;
+        // partial outputs sized for the largest chunk count the tuner tries (8)
+        for (int o = 0; o < 4; ++o) {
+            bb.cop_off[m][o] = (int64_t)cop;
+            cop += (size_t)nchunks(kop, kchunk_for(kop, 8)) * 2 * BLOCK_RHS * nv[m];
+        }
+        bb.cm_off[m] = (int64_t)cm;
+        cm += (size_t)nchunks(km, kchunk_for(km, 8)) * 4 * BLOCK_RHS * nv[m];
+    }
+    bem_status s = dev_alloc(ctx, bb.cop, cop * sizeof(float));
+    if (!s) s = dev_alloc(ctx, bb.cm, cm * sizeof(float));
+    return s;
+}
+
+GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st)
+{
+    GemmArgs G{};
+    const int nv[2] = {(int)p->ext->h.nv, (int)p->inte->h.nv};
+    int q = 0;
+    for (int m = 0; m < 2; ++m) {
+        const int kop = 2 * (int)op_ld(nv[m]);
+        for (int o = 0; o < 4; ++o) {
+            GemmSeg &S = G.seg[q++];
+            S.A = p->ops[m][o].as<float>();
+            S.lda = kop;
+            S.Bt = (o == 1 || o == 3) ? bb.btv[m].as<float>() : bb.btw[m].as<float>();   // K, D act on v; V, T on w
+            S.ldb = kop;
+            S.C = bb.cop.as<float>() + bb.cop_off[m][o];
+            S.M = nv[m];
+            S.K = kop;
+            S.kchunk = kchunk_for(kop, nk);
+            S.ncb = 1;
+        }
+    }
+    G.nseg = q;
+    G.done = st ? &st[0].done : nullptr;
+    G.done_stride = (int)(sizeof(KrylovState) / sizeof(int));
+    G.nrun = R;
+    return G;
+}
+
+GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st)
+{
+    GemmArgs G{};
+    const int nv[2] = {(int)p->ext->h.nv, (int)p->inte->h.nv};
+    for (int m = 0; m < 2; ++m) {
+        const int km = minv_ld(nv[m], true);
+        GemmSeg &S = G.seg[m];
+        S.A = p->Minv[m].as<float>();
+        S.lda = km;
+        S.Bt = bb.btm[m].as<float>();
+        S.ldb = km;
+        S.C = bb.cm.as<float>() + bb.cm_off[m];
+        S.M = nv[m];
+        S.K = km;
+        S.kchunk = kchunk_for(km, nk);
+        S.ncb = 2;
+    }
+    G.nseg = 2;
+    G.done = st ? &st[0].done : nullptr;
+    G.done_stride = (int)(sizeof(KrylovState) / sizeof(int));
+    G.nrun = R;
+    return G;
+}
+
+// Chunk counts of the two GEMMs, chosen once per problem by timing every
+// candidate on the problem's own matrices (the right-hand buffers are zero).
+bem_status block_tune(bem_problem *p, BlockBufs &bb)
+{
+    if (p->gemm_nk_ops > 0) return BEM_OK;
+    bem_ctx *ctx = p->ctx;
+    hipStream_t st = ctx->stream;
+    for (int m = 0; m < 2; ++m) {
+        BEM_HIP(hipMemsetAsync(bb.btv[m].ptr, 0, bb.btv[m].bytes, st));
+        BEM_HIP(hipMemsetAsync(bb.btw[m].ptr, 0, bb.btw[m].bytes, st));
+        BEM_HIP(hipMemsetAsync(bb.btm[m].ptr, 0, bb.btm[m].bytes, st));
+    }
+    hipEvent_t e0, e1;
+    BEM_HIP(hipEventCreate(&e0));
+    BEM_HIP(hipEventCreate(&e1));
+    struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
+    const int cand[4] = {1, 2, 4, 8};
+    for (int which = 0; which < 2; ++which) {
+        float best = 1e30f;
+        int pick = 4;
+        for (int c : cand) {
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c, BLOCK_RHS, nullptr)
+                                        : mass_gemm_args(p, bb, c, BLOCK_RHS, nullptr);
+                BEM_HIP(hipEventRecord(e0, st));
+                bem_status s = launch_gemm_f32(ctx, G, st);
+                if (s) return s;
+                BEM_HIP(hipEventRecord(e1, st));
+                BEM_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                tmin = std::min(tmin, ms);
+            }
+            if (tmin < best) { best = tmin; pick = c; }
+        }
+        (which == 0 ? p->gemm_nk_ops : p->gemm_nk_mass) = pick;
+    }
+    return BEM_OK;
+}
+
+// Y = A X (weak form) for R <= 64 runs through the matrix cores, and Z =
+// M^-1 Y when `strong`; run r reads X + r xstride and writes Y + r ystride,
+// Z + r zstride.  st (nullable) marks converged runs, which are skipped.
+bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, const double2 *X, int64_t xstride,
+                       double2 *Y, int64_t ystride, double2 *Z, int64_t zstride, bool strong, const KrylovState *kst)
+{
+    hipStream_t st = p->ctx->stream;
+    const int nv[2] = {A.ne, A.ni};
+    for (int m = 0; m < 2; ++m) {
+        const int kop = 2 * (int)op_ld(nv[m]);
+        hipLaunchKernelGGL(pack_ops_kernel, dim3((int)((op_ld(nv[m]) + 255) / 256), BLOCK_RHS), dim3(256), 0, st, nv[m],
+                           kop, R, X, xstride, m == 0 ? 0 : 2 * A.ne, kst, bb.btv[m].as<float>(), bb.btw[m].as<float>());
+    }
+    BEM_HIP(hipGetLastError());
+    GemmArgs G = ops_gemm_args(p, bb, p->gemm_nk_ops, R, kst);
+    bem_status s = launch_gemm_f32(p->ctx, G, st);
+    if (s) return s;
+    BlockC bc;
+    for (int m = 0; m < 2; ++m) {
+        for (int o = 0; o < 4; ++o) bc.C[m][o] = G.seg[4 * m + o].C;
+        bc.nk[m] = nchunks(G.seg[4 * m].K, G.seg[4 * m].kchunk);
+    }
+    hipLaunchKernelGGL(block_combine_kernel, dim3((A.ne + A.ni + 255) / 256, R), dim3(256), 0, st, A, bc, R, X, xstride,
+                       Y, ystride, kst);
+    BEM_HIP(hipGetLastError());
+    if (!strong) return BEM_OK;
+    for (int m = 0; m < 2; ++m) {
+        const int km = minv_ld(nv[m], true);
+        hipLaunchKernelGGL(pack_mass_kernel, dim3((km + 255) / 256, 4 * BLOCK_RHS), dim3(256), 0, st, nv[m], km, R,
+                           (const double2 *)Y, ystride, m == 0 ? 0 : 2 * A.ne, kst, bb.btm[m].as<float>());
+    }
+    BEM_HIP(hipGetLastError());
+    GemmArgs Gm = mass_gemm_args(p, bb, p->gemm_nk_mass, R, kst);
+    s = launch_gemm_f32(p->ctx, Gm, st);
+    if (s) return s;
+    hipLaunchKernelGGL(mass_reduce_kernel, dim3((A.ne + A.ni + 255) / 256, R), dim3(256), 0, st, A.ne, A.ni, Gm.seg[0].C,
+                       Gm.seg[1].C, nchunks(Gm.seg[0].K, Gm.seg[0].kchunk), nchunks(Gm.seg[1].K, Gm.seg[1].kchunk), R,
+                       Z, zstride, kst);
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
@@ -1023,110 +1371,143 @@ struct Gmres {
     bem_problem *p;
     const MtfArgs &A;
     Work &W;
-    KrylovState *hstate;   // two pinned slots polled alternately
+    BlockBufs *bb;         // multi-RHS products (null: one run, split-column kernels)
+    KrylovState *hstate;   // pinned: two snapshots of R states, polled alternately
     hipEvent_t *ev;
-    int n, nchunk, nrow_blk, m;
+    int n, nchunk, nrow_blk, m, R;
+    KBatch B;
 
-    // GMRES without restart on M^-1 A x = r0 (r0 already preconditioned),
-    // x0 = 0, Arnoldi (CGS2) and Givens rotations in FP64 on the device;
-    // at most `maxit` steps.  Writes x and the final Krylov state.
-    bem_status run(const double2 *r0, double tol, int maxit, double2 *x, KrylovState &fin)
+    // R independent GMRES runs without restart on M^-1 A x = r0 (r0 already
+    // preconditioned; run r's start vector at r0 + r r0stride), x0 = 0,
+    // Arnoldi (CGS2) and Givens rotations in FP64 on the device; at most
+    // `maxit` steps; run r stops at relative residual tol[r].  Writes
+    // x + r B.vec and the final states.
+    bem_status run(const double2 *r0, int64_t r0stride, const double *tol, int maxit, double2 *x, KrylovState *fin)
     {
         bem_ctx *ctx = p->ctx;
         hipStream_t st = ctx->stream;
         double2 *Vb = W.Vb.as<double2>();
         KrylovState *dst = W.state.as<KrylovState>();
-        const dim3 gv(nrow_blk);
         const int BATCH = 8;
-        hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, r0, W.npart.as<double>());
-        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), r0, Vb,
-                           W.beta.as<double>());
-        hipLaunchKernelGGL(krylov_init_kernel, dim3((maxit + 256) / 256), dim3(256), 0, st, maxit, W.beta.as<double>(),
-                           W.g.as<double2>(), dst);
+        const dim3 gv(nrow_blk, R);
+        BEM_HIP(hipMemcpyAsync(W.tolv.ptr, tol, (size_t)R * sizeof(double), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(norm_partial_kernel, gv, dim3(256), 0, st, n, r0, r0stride, W.npart.as<double>(), B.npart);
+        hipLaunchKernelGGL(normalize_kernel, gv, dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(), B.npart, r0,
+                           r0stride, Vb, B.basis, W.beta.as<double>());
+        hipLaunchKernelGGL(krylov_init_kernel, dim3((maxit + 256) / 256, R), dim3(256), 0, st, maxit,
+                           W.beta.as<double>(), W.tolv.as<double>(), W.g.as<double2>(), dst, B);
         BEM_HIP(hipGetLastError());
         // Issue policy: steps go out in batches of BATCH while the host checks
         // the state snapshot of the previous batch (the device never waits on
-        // the host).  Once the observed convergence rate predicts the end
-        // within the steps already queued plus two batches, each step is
-        // followed by a synchronous check, so no step is issued after the one
-        // that converges.
-        int slot = 0, pending = -1, last_j = 0;
-        double last_res = 1.0;
+        // the host).  Once the observed convergence rate of the slowest run
+        // predicts the end within the steps already queued plus two batches,
+        // each step is followed by a synchronous check, so no step is issued
+        // after the one that completes the last run.
+        const size_t sb = (size_t)R * sizeof(KrylovState);
+        std::vector<int> last_j(R, 0);
+        std::vector<double> last_res(R, 1.0);
+        int slot = 0, pending = -1;
         bool sync_mode = false, stop = false;
+        auto all_done = [&](const KrylovState *k) {
+            for (int r = 0; r < R; ++r)
+                if (!k[r].done) return false;
+            return true;
+        };
         for (int j = 0; j < maxit && !stop; ++j) {
             const double2 *vj = Vb + (size_t)j * n;
-            bem_status s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
+            bem_status s;
+            if (bb)
+                s = block_apply(p, A, *bb, R, vj, B.basis, W.y.as<double2>(), B.vec, W.z.as<double2>(), B.vec, true,
+                                dst);
+            else
+                s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
             if (s) return s;
             for (int pass = 0; pass < 2; ++pass) {
                 {
                     KTimer kt(ctx, K_CGS_DOTS);
-                    launch_k(kt, cgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4), dim3(256), 0, st, n, j + 1, Vb,
-                             W.z.as<double2>(), W.partial.as<double2>(), dst);
+                    launch_k(kt, cgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4, R), dim3(256), 0, st, n, j + 1, Vb,
+                             W.z.as<double2>(), W.partial.as<double2>(), dst, B);
                 }
                 KTimer kt(ctx, K_CGS_UPDATE);
                 launch_k(kt, cgs_update_kernel, gv, dim3(256), (size_t)(j + 1) * sizeof(double2), st, n, j + 1, nchunk,
                          Vb, W.partial.as<double2>(), W.z.as<double2>(), W.hsum.as<double2>(), pass,
-                         W.npart.as<double>(), dst);
+                         W.npart.as<double>(), dst, B);
             }
             {
                 KTimer kt(ctx, K_ARNOLDI_FINISH);
                 launch_k(kt, arnoldi_finish_kernel, gv, dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, n,
-                         nrow_blk, W.npart.as<double>(), W.z.as<double2>(), Vb + (size_t)(j + 1) * n, j, maxit, tol,
+                         nrow_blk, W.npart.as<double>(), W.z.as<double2>(), Vb + (size_t)(j + 1) * n, j, maxit,
                          W.hsum.as<double2>(), W.R.as<double2>(), W.g.as<double2>(), W.cs.as<double2>(),
-                         W.sn.as<double2>(), dst);
+                         W.sn.as<double2>(), dst, B);
             }
             BEM_HIP(hipGetLastError());
             const int issued = j + 1;
+            KrylovState *hs = hstate + (size_t)slot * R;
             if (sync_mode) {
-                BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+                BEM_HIP(hipMemcpyAsync(hs, dst, sb, hipMemcpyDeviceToHost, st));
                 BEM_HIP(hipStreamSynchronize(st));
-                stop = hstate[slot].done != 0;
+                stop = all_done(hs);
                 continue;
             }
             if (issued % BATCH != 0) continue;
-            BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipMemcpyAsync(hs, dst, sb, hipMemcpyDeviceToHost, st));
             BEM_HIP(hipEventRecord(ev[slot], st));
             if (pending >= 0) {
                 BEM_HIP(hipEventSynchronize(ev[pending]));
-                const KrylovState &k = hstate[pending];
-                if (k.done) { stop = true; break; }
-                // steps still to go at the observed geometric rate
-                if (last_j > 0 && k.iters > last_j && k.resid > 0 && last_res > 0) {
-                    const double rate = std::pow(k.resid / last_res, 1.0 / (k.iters - last_j));
-                    const double togo = rate < 1.0 ? std::log(tol / k.resid) / std::log(rate) : 1e30;
-                    if (togo <= (issued - k.iters) + 2 * BATCH) sync_mode = true;
+                const KrylovState *k = hstate + (size_t)pending * R;
+                if (all_done(k)) { stop = true; break; }
+                // steps still to go at the observed geometric rate of the slowest run
+                double togo = 0.0;
+                int seen = issued;
+                for (int r = 0; r < R; ++r) {
+                    if (k[r].done) continue;
+                    seen = std::min(seen, k[r].iters);
+                    if (last_j[r] > 0 && k[r].iters > last_j[r] && k[r].resid > 0 && last_res[r] > 0) {
+                        const double rate = std::pow(k[r].resid / last_res[r], 1.0 / (k[r].iters - last_j[r]));
+                        togo = std::max(togo, rate < 1.0 ? std::log(tol[r] / k[r].resid) / std::log(rate) : 1e30);
+                    } else {
+                        togo = 1e30;
+                    }
+                    last_j[r] = k[r].iters;
+                    last_res[r] = k[r].resid;
                 }
-                last_j = k.iters;
-                last_res = k.resid;
+                if (togo <= (issued - seen) + 2 * BATCH) sync_mode = true;
             }
             pending = slot;
             slot ^= 1;
         }
-        BEM_HIP(hipMemcpyAsync(&hstate[slot], dst, sizeof(KrylovState), hipMemcpyDeviceToHost, st));
+        KrylovState *hs = hstate + (size_t)slot * R;
+        BEM_HIP(hipMemcpyAsync(hs, dst, sb, hipMemcpyDeviceToHost, st));
         BEM_HIP(hipStreamSynchronize(st));
-        fin = hstate[slot];
-        const int k = fin.iters;
-        // back substitution R y = g on the host (k x k upper triangular; R
-        // column c at offset c (maxit + 1))
+        for (int r = 0; r < R; ++r) fin[r] = hs[r];
+        // back substitution R y = g of every run on the host (k x k upper
+        // triangular; column c of R at offset c (maxit + 1))
         using cd = std::complex<double>;
-        std::vector<cd> Rh((size_t)std::max(k, 1) * (maxit + 1)), gh(maxit + 1);
-        if (k > 0) {
-            BEM_HIP(hipMemcpyAsync(Rh.data(), W.R.ptr, (size_t)k * (maxit + 1) * sizeof(double2),
-                                   hipMemcpyDeviceToHost, st));
-            BEM_HIP(hipMemcpyAsync(gh.data(), W.g.ptr, (size_t)(maxit + 1) * sizeof(double2), hipMemcpyDeviceToHost, st));
+        std::vector<cd> Rh, gh(maxit + 1), yv;
+        for (int r = 0; r < R; ++r) {
+            const int k = fin[r].iters;
+            Rh.assign((size_t)std::max(k, 1) * (maxit + 1), cd(0));
+            if (k > 0) {
+                BEM_HIP(hipMemcpyAsync(Rh.data(), W.R.as<double2>() + r * B.hess, (size_t)k * (maxit + 1) * sizeof(double2),
+                                       hipMemcpyDeviceToHost, st));
+                BEM_HIP(hipMemcpyAsync(gh.data(), W.g.as<double2>() + r * B.small, (size_t)(maxit + 1) * sizeof(double2),
+                                       hipMemcpyDeviceToHost, st));
+                BEM_HIP(hipStreamSynchronize(st));
+            }
+            yv.assign(std::max(k, 1), cd(0));
+            for (int i = k - 1; i >= 0; --i) {
+                cd sacc = gh[i];
+                for (int c = i + 1; c < k; ++c) sacc -= Rh[(size_t)c * (maxit + 1) + i] * yv[c];
+                yv[i] = sacc / Rh[(size_t)i * (maxit + 1) + i];
+            }
+            if (k > 0)
+                BEM_HIP(hipMemcpyAsync(W.yc.ptr, yv.data(), (size_t)k * sizeof(double2), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(combine_kernel, dim3(nrow_blk), dim3(256), 0, st, n, k, Vb + r * B.basis,
+                               W.yc.as<double2>(), x + r * B.vec);
+            BEM_HIP(hipGetLastError());
+            // yv and W.yc are reused by the next run
             BEM_HIP(hipStreamSynchronize(st));
         }
-        std::vector<cd> yv(std::max(k, 1));
-        for (int i = k - 1; i >= 0; --i) {
-            cd sacc = gh[i];
-            for (int c = i + 1; c < k; ++c) sacc -= Rh[(size_t)c * (maxit + 1) + i] * yv[c];
-            yv[i] = sacc / Rh[(size_t)i * (maxit + 1) + i];
-        }
-        if (k > 0) BEM_HIP(hipMemcpyAsync(W.yc.ptr, yv.data(), (size_t)k * sizeof(double2), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(combine_kernel, gv, dim3(256), 0, st, n, k, Vb, W.yc.as<double2>(), x);
-        BEM_HIP(hipGetLastError());
-        // the host vector yv must outlive the copy above
-        BEM_HIP(hipStreamSynchronize(st));
         return BEM_OK;
     }
 };
@@ -1137,9 +1518,9 @@ __global__ void axpy_add_kernel(int n, const double2 *__restrict__ d, double2 *_
     if (r < n) x[r] = make_double2(x[r].x + d[r].x, x[r].y + d[r].y);
 }
 
-__global__ void zero_kernel(int n, double2 *__restrict__ x)
+__global__ void zero_kernel(int64_t n, double2 *__restrict__ x)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r < n) x[r] = make_double2(0, 0);
 }
 
@@ -1172,6 +1553,57 @@ bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_m
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipMemcpyAsync(y, yu.ptr, bytes, space == BEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
     BEM_HIP(hipStreamSynchronize(st));
+    return BEM_OK;
+}
+
+bem_status matvec_batch_impl(bem_problem *p, const void *x, void *y, int nrhs, int strong, bem_memspace space)
+{
+    bem_ctx *ctx = p->ctx;
+    if (p->prec != BEM_C64_MIXED) {
+        const size_t nb = (size_t)(2 * p->ext->h.nv + 2 * p->inte->h.nv) * sizeof(double2);
+        for (int r = 0; r < nrhs; ++r) {
+            bem_status s = matvec_impl(p, static_cast<const char *>(x) + r * nb, static_cast<char *>(y) + r * nb,
+                                       strong, space);
+            if (s) return s;
+        }
+        return BEM_OK;
+    }
+    BEM_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne + 2 * ni;
+    const int R = std::min(nrhs, BLOCK_RHS);
+    const size_t vb = (size_t)n * sizeof(double2);
+    DevMem xu, xi, yi, zi;
+    BlockBufs bb;
+    bem_status s = dev_alloc(ctx, xu, R * vb);
+    if (!s) s = dev_alloc(ctx, xi, R * vb);
+    if (!s) s = dev_alloc(ctx, yi, R * vb);
+    if (!s) s = dev_alloc(ctx, zi, R * vb);
+    if (!s) s = block_alloc(p, bb);
+    if (!s) s = block_tune(p, bb);
+    if (s) return s;
+    const MtfArgs A = make_args(p);
+    const dim3 g((n + 255) / 256);
+    for (int r0 = 0; r0 < nrhs; r0 += R) {
+        const int Rc = std::min(R, nrhs - r0);
+        BEM_HIP(hipMemcpyAsync(xu.ptr, static_cast<const char *>(x) + r0 * vb, Rc * vb,
+                               space == BEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
+        for (int r = 0; r < Rc; ++r)
+            hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
+                               p->inte->d.perm.as<int32_t>(), xu.as<double2>() + (size_t)r * n,
+                               xi.as<double2>() + (size_t)r * n, 1);
+        s = block_apply(p, A, bb, Rc, xi.as<double2>(), n, yi.as<double2>(), n, zi.as<double2>(), n, strong != 0,
+                        nullptr);
+        if (s) return s;
+        for (int r = 0; r < Rc; ++r)
+            hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
+                               p->inte->d.perm.as<int32_t>(), (strong ? zi : yi).as<double2>() + (size_t)r * n,
+                               xu.as<double2>() + (size_t)r * n, 0);
+        BEM_HIP(hipGetLastError());
+        BEM_HIP(hipMemcpyAsync(static_cast<char *>(y) + r0 * vb, xu.ptr, Rc * vb,
+                               space == BEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+        BEM_HIP(hipStreamSynchronize(st));
+    }
     return BEM_OK;
 }
 
@@ -1209,6 +1641,11 @@ bem_status rhs_impl(bem_problem *p, const double *dirs, int nrhs, void *b, bem_m
     return BEM_OK;
 }
 
+int solve_runs(const bem_problem *p, const bem_solver_opts *opts)
+{
+    return (p->prec == BEM_C64_MIXED && opts->batch > 1) ? std::min(opts->batch, BLOCK_RHS) : 1;
+}
+
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats)
 {
@@ -1220,31 +1657,39 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     if (m > MAXIT_CAP) return set_error(BEM_E_ARG, "maxit above 3000");
     const bool mixed = p->prec == BEM_C64_MIXED;
     const int ir_max = opts->ir_max > 0 ? opts->ir_max : 10;
+    const int R = std::min(solve_runs(p, opts), nrhs);   // runs advancing together
     const size_t vb = (size_t)n * sizeof(double2);
     const int nchunk = (n + CGS_CHUNK - 1) / CGS_CHUNK;
     const int nrow_blk = (n + 255) / 256;
     Work W;
-    bem_status s = dev_alloc(ctx, W.y, vb);
-    if (!s) s = dev_alloc(ctx, W.z, vb);
-    if (!s) s = dev_alloc(ctx, W.b, vb);
-    if (!s) s = dev_alloc(ctx, W.r, vb);
-    if (!s) s = dev_alloc(ctx, W.xin, vb);
-    if (!s && mixed) s = dev_alloc(ctx, W.d, vb);
-    if (!s) s = dev_alloc(ctx, W.Vb, (size_t)(m + 1) * vb);
-    if (!s) s = dev_alloc(ctx, W.partial, (size_t)nchunk * (m + 1) * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.hsum, (size_t)(m + 1) * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.beta, sizeof(double) * 2);
+    bem_status s = dev_alloc(ctx, W.y, R * vb);
+    if (!s) s = dev_alloc(ctx, W.z, R * vb);
+    if (!s) s = dev_alloc(ctx, W.b, R * vb);
+    if (!s) s = dev_alloc(ctx, W.r, R * vb);
+    if (!s) s = dev_alloc(ctx, W.xin, R * vb);
+    if (!s && mixed) s = dev_alloc(ctx, W.d, R * vb);
+    if (!s) s = dev_alloc(ctx, W.Vb, (size_t)R * (m + 1) * vb);
+    if (!s) s = dev_alloc(ctx, W.partial, (size_t)R * nchunk * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.hsum, (size_t)R * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.beta, sizeof(double) * (R + 1));
+    if (!s) s = dev_alloc(ctx, W.tolv, sizeof(double) * R);
     if (!s) s = dev_alloc(ctx, W.yc, (size_t)(m + 1) * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.npart, (size_t)nrow_blk * sizeof(double));
-    if (!s) s = dev_alloc(ctx, W.R, (size_t)m * (m + 1) * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.g, (size_t)(m + 1) * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.cs, (size_t)m * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.sn, (size_t)m * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.state, sizeof(KrylovState));
+    if (!s) s = dev_alloc(ctx, W.npart, (size_t)R * nrow_blk * sizeof(double));
+    if (!s) s = dev_alloc(ctx, W.R, (size_t)R * m * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.g, (size_t)R * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.cs, (size_t)R * m * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.sn, (size_t)R * m * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.state, R * sizeof(KrylovState));
     if (!s) s = dev_alloc(ctx, W.part, split_part_bytes(ne, ni));
     if (s) return s;
-    KrylovState *hstate = nullptr;   // two pinned slots polled alternately
-    BEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstate), 2 * sizeof(KrylovState), hipHostMallocDefault));
+    BlockBufs bb;
+    if (R > 1) {
+        s = block_alloc(p, bb);
+        if (!s) s = block_tune(p, bb);
+        if (s) return s;
+    }
+    KrylovState *hstate = nullptr;   // two pinned snapshots of the R states
+    BEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstate), 2 * R * sizeof(KrylovState), hipHostMallocDefault));
     struct PinGuard { KrylovState *p; ~PinGuard() { if (p) (void)hipHostFree(p); } } guard{hstate};
     hipEvent_t ev[2];
     BEM_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -1254,85 +1699,133 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     const size_t finish_lds = (size_t)(3 * m + 1) * sizeof(double2);
     BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&arnoldi_finish_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)finish_lds));
-    Gmres gm{p, A, W, hstate, ev, n, nchunk, nrow_blk, m};
+    KBatch B{};
+    if (R > 1) {
+        B.basis = (int64_t)(m + 1) * n;
+        B.vec = n;
+        B.partial = (int64_t)nchunk * (m + 1);
+        B.small = m + 1;
+        B.npart = nrow_blk;
+        B.hess = (int64_t)m * (m + 1);
+        B.rot = m;
+    }
+    Gmres gm{p, A, W, R > 1 ? &bb : nullptr, hstate, ev, n, nchunk, nrow_blk, m, R, B};
     const dim3 gv(nrow_blk);
-    double *beta = W.beta.as<double>();   // [0] ||M^-1 b||, [1] ||M^-1 (b - A x)||
+    double *beta = W.beta.as<double>();   // [0, R) ||M^-1 b|| of each run; [R] residual norm
     int total_it = 0, total_ir = 0;
     double worst_res = 0.0;
     bool all_conv = true;
     auto t0 = std::chrono::steady_clock::now();
-    // true strong-form residual in FP64 arithmetic, r = M^-1 (b - A x) into W.z, its norm into beta[1]
-    auto residual = [&]() -> bem_status {
-        bem_status q = apply_A(p, A, W.xin.as<double2>(), W.y.as<double2>(), W.z.as<double2>(), false, nullptr,
-                               W.part.as<double4>(), true);
+    // true strong-form residual of run r in FP64 arithmetic: W.z_r = M^-1 (b_r - A x_r), its norm into beta[R]
+    auto residual = [&](int r) -> bem_status {
+        double2 *yr = W.y.as<double2>() + (size_t)r * n, *rr = W.r.as<double2>() + (size_t)r * n;
+        double2 *zr = W.z.as<double2>() + (size_t)r * n;
+        bem_status q = apply_A(p, A, W.xin.as<double2>() + (size_t)r * n, yr, zr, false, nullptr, W.part.as<double4>(),
+                               true);
         if (q) return q;
-        hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), W.y.as<double2>(),
-                           W.r.as<double2>());
-        q = apply_Minv(p, W.r.as<double2>(), W.z.as<double2>(), W.part.as<double4>(), nullptr);
+        hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>() + (size_t)r * n, yr, rr);
+        q = apply_Minv(p, rr, zr, W.part.as<double4>(), nullptr);
         if (q) return q;
-        return norm_to(p, n, W.z.as<double2>(), W.npart.as<double>(), W.d.ptr ? W.d.as<double2>() : W.r.as<double2>(),
-                       beta + 1);
+        return norm_to(p, n, zr, W.npart.as<double>(), yr, beta + R);
     };
-    for (int rhs = 0; rhs < nrhs; ++rhs) {
-        s = rhs_internal(p, dirs + 3 * rhs, W.b.as<double2>());
-        if (s) return s;
-        // r0 = M^-1 b (x0 = 0)
-        s = apply_Minv(p, W.b.as<double2>(), W.r.as<double2>(), W.part.as<double4>(), nullptr);
-        if (s) return s;
-        double b0 = 0.0, rn = 0.0;
-        KrylovState fin{};
+    std::vector<KrylovState> fin(R);
+    std::vector<double> b0(R), rel(R), tolr(R);
+    for (int g0 = 0; g0 < nrhs; g0 += R) {
+        const int Rg = std::min(R, nrhs - g0);
+        // b and r0 = M^-1 b (x0 = 0) of every run; runs past Rg start from zero
+        for (int r = 0; r < R; ++r) {
+            double2 *br = W.b.as<double2>() + (size_t)r * n, *rr = W.r.as<double2>() + (size_t)r * n;
+            if (r < Rg) {
+                s = rhs_internal(p, dirs + 3 * (g0 + r), br);
+                if (!s) s = apply_Minv(p, br, rr, W.part.as<double4>(), nullptr);
+                if (s) return s;
+            } else {
+                hipLaunchKernelGGL(zero_kernel, gv, dim3(256), 0, st, (int64_t)n, br);
+                hipLaunchKernelGGL(zero_kernel, gv, dim3(256), 0, st, (int64_t)n, rr);
+            }
+        }
+        std::vector<double> rn(R, 0.0);
         if (!mixed) {
-            s = gm.run(W.r.as<double2>(), opts->tol, m, W.xin.as<double2>(), fin);
+            tolr.assign(R, opts->tol);
+            s = gm.run(W.r.as<double2>(), n, tolr.data(), m, W.xin.as<double2>(), fin.data());
             if (s) return s;
-            total_it += fin.iters;
-            b0 = fin.beta0;
-            s = residual();
-            if (s) return s;
-            BEM_HIP(hipMemcpyAsync(&rn, beta + 1, sizeof(double), hipMemcpyDeviceToHost, st));
-            BEM_HIP(hipStreamSynchronize(st));
-            if (!(fin.resid <= opts->tol)) all_conv = false;
+            for (int r = 0; r < Rg; ++r) {
+                total_it += fin[r].iters;
+                b0[r] = fin[r].beta0;
+                s = residual(r);
+                if (s) return s;
+                BEM_HIP(hipMemcpyAsync(&rn[r], beta + R, sizeof(double), hipMemcpyDeviceToHost, st));
+                BEM_HIP(hipStreamSynchronize(st));
+                if (!(fin[r].resid <= opts->tol)) all_conv = false;
+            }
         } else {
             // Iterative refinement: x += d where d solves the FP32-product
             // system M^-1 A d = M^-1 (b - A x) to a relative tolerance that
             // aims at the outer target; the residual of every step is
-            // recomputed with FP64 arithmetic.
-            hipLaunchKernelGGL(zero_kernel, gv, dim3(256), 0, st, n, W.xin.as<double2>());
-            s = norm_to(p, n, W.r.as<double2>(), W.npart.as<double>(), W.z.as<double2>(), beta);
-            if (s) return s;
-            BEM_HIP(hipMemcpyAsync(&b0, beta, sizeof(double), hipMemcpyDeviceToHost, st));
+            // recomputed with FP64 arithmetic.  Runs that have met the
+            // target start the next step from zero (and so sit it out).
+            hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((R * (int64_t)n + 255) / 256)), dim3(256), 0, st,
+                               (int64_t)R * n, W.xin.as<double2>());
+            hipLaunchKernelGGL(norm_partial_kernel, dim3(nrow_blk, R), dim3(256), 0, st, n, W.r.as<double2>(),
+                               (int64_t)n, W.npart.as<double>(), (int64_t)nrow_blk);
+            hipLaunchKernelGGL(normalize_kernel, dim3(nrow_blk, R), dim3(256), 0, st, n, nrow_blk, W.npart.as<double>(),
+                               (int64_t)nrow_blk, W.r.as<double2>(), (int64_t)n, W.z.as<double2>(), (int64_t)n, beta);
+            BEM_HIP(hipGetLastError());
+            BEM_HIP(hipMemcpyAsync(b0.data(), beta, R * sizeof(double), hipMemcpyDeviceToHost, st));
             BEM_HIP(hipStreamSynchronize(st));
-            const double2 *rhs_s = W.r.as<double2>();   // preconditioned residual of the current x
-            double rel = 1.0;
+            const double2 *rhs_s = W.r.as<double2>();   // preconditioned residuals of the current x
+            for (int r = 0; r < R; ++r) rel[r] = b0[r] > 0.0 ? 1.0 : 0.0;
             int used = 0, steps = 0;
-            while (b0 > 0.0 && rel > opts->tol && steps < ir_max && used < m) {
-                const double inner = opts->ir_inner_tol > 0 ? opts->ir_inner_tol
-                                                            : std::max(0.5 * opts->tol / rel, 1e-7);
-                s = gm.run(rhs_s, inner, m - used, W.d.as<double2>(), fin);
+            auto active = [&](int r) { return r < Rg && rel[r] > opts->tol; };
+            for (;;) {
+                bool any = false;
+                for (int r = 0; r < R; ++r) any = any || active(r);
+                if (!any || steps >= ir_max || used >= m) break;
+                for (int r = 0; r < R; ++r) {
+                    tolr[r] = opts->ir_inner_tol > 0 ? opts->ir_inner_tol : std::max(0.5 * opts->tol / rel[r], 1e-7);
+                    if (!active(r))   // start vector zero: the run is done at once
+                        hipLaunchKernelGGL(zero_kernel, gv, dim3(256), 0, st, (int64_t)n,
+                                           const_cast<double2 *>(rhs_s) + (size_t)r * n);
+                }
+                s = gm.run(rhs_s, n, tolr.data(), m - used, W.d.as<double2>(), fin.data());
                 if (s) return s;
-                used += fin.iters;
+                int most = 0;
+                for (int r = 0; r < R; ++r) {
+                    most = std::max(most, fin[r].iters);
+                    if (r < Rg) total_it += fin[r].iters;
+                }
+                used += most;
                 ++steps;
-                hipLaunchKernelGGL(axpy_add_kernel, gv, dim3(256), 0, st, n, W.d.as<double2>(), W.xin.as<double2>());
-                s = residual();
-                if (s) return s;
-                BEM_HIP(hipMemcpyAsync(&rn, beta + 1, sizeof(double), hipMemcpyDeviceToHost, st));
-                BEM_HIP(hipStreamSynchronize(st));
-                rel = rn / b0;
+                for (int r = 0; r < Rg; ++r) {
+                    if (!active(r)) continue;
+                    hipLaunchKernelGGL(axpy_add_kernel, gv, dim3(256), 0, st, n, W.d.as<double2>() + (size_t)r * n,
+                                       W.xin.as<double2>() + (size_t)r * n);
+                    s = residual(r);
+                    if (s) return s;
+                    BEM_HIP(hipMemcpyAsync(&rn[r], beta + R, sizeof(double), hipMemcpyDeviceToHost, st));
+                    BEM_HIP(hipStreamSynchronize(st));
+                    rel[r] = rn[r] / b0[r];
+                }
                 rhs_s = W.z.as<double2>();
-                if (fin.iters == 0) break;   // no progress possible
+                if (most == 0) break;   // no progress possible
             }
-            total_it += used;
             total_ir += steps;
-            if (!(rel <= opts->tol)) all_conv = false;
+            for (int r = 0; r < Rg; ++r) {
+                rn[r] = rel[r] * b0[r];
+                if (!(rel[r] <= opts->tol)) all_conv = false;
+            }
         }
         // traces in caller numbering
-        hipLaunchKernelGGL(permute_vec_kernel, gv, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
-                           p->inte->d.perm.as<int32_t>(), W.xin.as<double2>(), W.y.as<double2>(), 0);
-        BEM_HIP(hipGetLastError());
-        BEM_HIP(hipMemcpyAsync(static_cast<double2 *>(traces) + (size_t)rhs * n, W.y.ptr, vb,
+        for (int r = 0; r < Rg; ++r) {
+            hipLaunchKernelGGL(permute_vec_kernel, gv, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
+                               p->inte->d.perm.as<int32_t>(), W.xin.as<double2>() + (size_t)r * n,
+                               W.y.as<double2>() + (size_t)r * n, 0);
+            BEM_HIP(hipGetLastError());
+            worst_res = std::max(worst_res, b0[r] > 0 ? rn[r] / b0[r] : 0.0);
+        }
+        BEM_HIP(hipMemcpyAsync(static_cast<double2 *>(traces) + (size_t)g0 * n, W.y.ptr, Rg * vb,
                                space == BEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
         BEM_HIP(hipStreamSynchronize(st));
-        const double rel = b0 > 0 ? rn / b0 : 0.0;
-        worst_res = std::max(worst_res, rel);
     }
     const double t_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     s = resolve_assembly_timing(p);

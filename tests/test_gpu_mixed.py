@@ -190,3 +190,102 @@ def test_solve_c3_mixed_vs_fp64(ctx, c3):
     print(f"C3 iterations mixed {stats['iterations']} (IR {stats['ir_steps']}) fp64 {s64['iterations']}")
     _check_traces(out.cpu().numpy()[0], ref.cpu().numpy()[0], len(c["ext"][0]), len(c["int"][0]), TRACE,
                   "C3 mixed vs fp64")
+
+
+# ------------------------------------------------ multi-RHS (matrix cores)
+
+@pytest.mark.parametrize("strong", [False, True])
+def test_matvec_batch_c1_vs_oracle(c1m, c1_oracle, orc, strong):
+    """Batched FP32 matrix-core product (5 vectors, ragged row tiles of 162
+    rows) against the FP64 oracle product, and against the single-vector
+    mixed product (same stored operators; the two FP32 summation orders
+    differ by rounding only)."""
+    c, p, _, _ = c1m
+    A = orc.mtf_system(c1_oracle, c["rho_ext"], c["rho_int"])
+    Mb = orc.block_mass(c1_oracle)
+    rng = np.random.default_rng(21)
+    X = rng.standard_normal((5, p.n)) + 1j * rng.standard_normal((5, p.n))
+    Y = p.mtf_matvec_batch(torch.from_numpy(X), strong=strong).cpu().numpy()
+    for r in range(5):
+        ref = A @ X[r]
+        if strong:
+            ref = np.linalg.solve(Mb, ref)
+        e = _rel(Y[r], ref)
+        single = p.mtf_matvec(torch.from_numpy(X[r]), strong=strong).cpu().numpy()
+        assert e < OP_FRO, (r, e)
+        assert _rel(Y[r], single) < 2e-6, r
+
+
+def test_matvec_batch_64_small_ellipsoid(ctx, orc):
+    """64 vectors (a full 128-column tile), meshes of 642 / 700 nodes: every
+    column against the oracle's FP64 strong-form product."""
+    c = _small_ellipsoid()
+    p, _, _ = _problem(ctx, c, B.C64_MIXED)
+    ops = orc.operators(c["ext"], c["int"], c["k_ext"], c["k_int"])
+    A = orc.mtf_system(ops, c["rho_ext"], c["rho_int"])
+    Mb = orc.block_mass(ops)
+    rng = np.random.default_rng(22)
+    X = rng.standard_normal((64, p.n)) + 1j * rng.standard_normal((64, p.n))
+    Y = p.mtf_matvec_batch(torch.from_numpy(X), strong=True).cpu().numpy()
+    ref = np.linalg.solve(Mb, A @ X.T).T
+    errs = [_rel(Y[r], ref[r]) for r in range(64)]
+    print(f"batch-64 strong matvec: max err {max(errs):.2e}")
+    assert max(errs) < OP_FRO
+
+
+def test_block_solve_c1_vs_lu(c1m, c1_oracle, orc):
+    """Four plane waves solved together (batch 4) against the oracle's LU
+    solution of each, and against the one-at-a-time mixed solves."""
+    c, p, _, _ = c1m
+    rng = np.random.default_rng(23)
+    dirs = synth.plane_wave_directions(4, rng)
+    X, _ = orc.solve_mtf(c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"], dirs, ops=c1_oracle)
+    out, stats, code = p.solve(dirs, tol=1e-8, maxit=500, batch=4)
+    assert code == B.OK, stats
+    seq, s1, code1 = p.solve(dirs, tol=1e-8, maxit=500)
+    assert code1 == B.OK
+    got, sq = out.cpu().numpy(), seq.cpu().numpy()
+    ne, ni = len(c["ext"][0]), len(c["int"][0])
+    for r in range(4):
+        _check_traces(got[r], X[r], ne, ni, TRACE, f"C1 batch rhs {r}")
+        _check_traces(got[r], sq[r], ne, ni, TRACE, f"C1 batch vs sequential rhs {r}")
+
+
+@pytest.fixture(scope="module")
+def c4(ctx):
+    c = synth.make_config("C4")
+    return (c,) + _problem(ctx, c, B.C64_MIXED)
+
+
+def test_block_solve_c4(c4, orc):
+    """The batching workload: 64 directions in one block solve.  Every run
+    meets the tolerance (FP64 residual); three runs are compared with their
+    one-at-a-time solves, and their weak-form residuals on sampled rows are
+    recomputed with the oracle's rows of the operators."""
+    c, p, _, _ = c4
+    out, stats, code = p.solve(c["dirs"], tol=c["tol"], maxit=1500, batch=64)
+    assert code == B.OK, stats
+    assert stats["rel_residual"] <= c["tol"]
+    got = out.cpu().numpy()
+    ne, ni = len(c["ext"][0]), len(c["int"][0])
+    print(f"C4 block: {stats['iterations']} iterations over 64 runs, IR {stats['ir_steps']}, "
+          f"solve {stats['t_solve_ms']:.0f} ms")
+    pick = [0, 31, 63]
+    seq, s1, code1 = p.solve(c["dirs"][pick], tol=c["tol"], maxit=1500)
+    assert code1 == B.OK
+    seq = seq.cpu().numpy()
+    for q, r in enumerate(pick):
+        _check_traces(got[r], seq[q], ne, ni, 1e-4, f"C4 block vs single rhs {r}")
+    rng = np.random.default_rng(40)
+    re_ = np.unique(np.concatenate([[0, ne - 1], rng.choice(ne, 3, replace=False)]))
+    Oe = orc.assemble(*c["ext"], c["k_ext"], rows=re_)
+    Pie = orc.mortar(c["int"], c["ext"])
+    rr = c["rho_ext"] / c["rho_int"]
+    for r in pick:
+        x = got[r]
+        ve, we, vi, wi = x[:ne], x[ne:2 * ne], x[2 * ne:2 * ne + ni], x[2 * ne + ni:]
+        b = orc.mtf_rhs(c["ext"], c["k_ext"], c["dirs"][r], ni)
+        r1 = b[re_] - (-Oe["K"] @ ve + Oe["V"] @ we + 0.5 * Pie.T[re_] @ vi)
+        r2 = b[ne + re_] - (Oe["D"] @ ve + Oe["T"] @ we + 0.5 * rr * Pie.T[re_] @ wi)
+        scale = np.abs(b).max()
+        assert np.abs(r1).max() < 1e3 * c["tol"] * scale and np.abs(r2).max() < 1e3 * c["tol"] * scale
