@@ -140,6 +140,108 @@ def precision_compare(ctx, B, synth, np, steps=2, tol=1e-7):
             "speedup_mixed_vs_fp64": round(res["fp64"]["step_ms"] / res["c64_mixed"]["step_ms"], 3)}
 
 
+FP32_MFMA_TFLOPS = 157.3    # MI355X dense FP32 matrix-core peak, TFLOP/s
+
+
+def batching_compare(ctx, B, synth, np, tol=1e-7, sample=2):
+    """The batching workload (ellipsoid (1, 0.8, 0.6), ico L5 with 10242 nodes
+    / Fibonacci 8000 nodes, k 8 / 12, rho ratio 2, 64 plane waves): one block
+    solve of all 64 directions in the mixed form (64 independent GMRES runs
+    sharing one matrix-core product per step) against one-at-a-time solves of
+    the mixed and of the plain FP64 form, timed on the first `sample`
+    directions.  tol 1e-7 for all forms (the tolerance at which the traces of
+    every form lie within 1e-5 of the exact discrete solution).  The block
+    GEMM is reported against the FP32 matrix-core peak with 2048 (N_e^2 +
+    N_i^2) useful flops per launch (8 real flops per complex multiply-add, 4
+    blocks per mesh, 64 vectors)."""
+    import torch
+    c = synth.make_config("C4")
+    (xe, te), (xi, ti) = c["ext"], c["int"]
+    ne, ni = len(xe), len(xi)
+    dirs = c["dirs"]
+
+    def setup(prec):
+        me, mi = B.Mesh(ctx, xe, te), B.Mesh(ctx, xi, ti)
+        p = B.Problem(ctx, me, mi, c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"], precision=prec)
+        p.assemble_operators()
+        p.assemble_projection()
+        return p, me, mi
+
+    res = {}
+    p, me, mi = setup(B.C64_MIXED)
+    p.solve(dirs[:4], tol=tol, maxit=1500, batch=4)    # first use: picks the GEMM K split by timing
+    torch.cuda.synchronize()
+    ctx.set_kernel_timing(("block_gemm", "mass_gemm"))
+    t0 = time.perf_counter()
+    out, st, code = p.solve(dirs, tol=tol, maxit=1500, batch=64)
+    blk = out.cpu().numpy()
+    dt = time.perf_counter() - t0
+    assert code == B.OK, st
+    gms, gn = ctx.kernel_time("block_gemm")
+    mms, mn = ctx.kernel_time("mass_gemm")
+    ctx.set_kernel_timing(())
+    flops = 2048.0 * (ne * ne + ni * ni)
+    ach = flops / (gms / gn * 1e-3) / 1e12
+    res["block_c64_mixed"] = {"solves": 64, "solve_ms": round(1e3 * dt, 1), "solves_per_s": round(64 / dt, 2),
+                              "iterations_total": st["iterations"], "ir_steps": st["ir_steps"],
+                              "rel_residual": st["rel_residual"]}
+    res["roofline"] = {"kernel": "block_gemm", "bound": "mfma", "achieved": round(ach, 1), "peak": FP32_MFMA_TFLOPS,
+                       "unit": "TFLOP/s", "frac": round(ach / FP32_MFMA_TFLOPS, 4), "traffic": None,
+                       "avg_launch_us": round(1e3 * gms / gn, 1), "flop_per_launch": flops,
+                       "mass_gemm_tflops": round(512.0 * (ne * ne + ni * ni) / (mms / mn * 1e-3) / 1e12, 1)}
+    t0 = time.perf_counter()
+    seq, s1, c1 = p.solve(dirs[:sample], tol=tol, maxit=1500)
+    seq = seq.cpu().numpy()
+    dt1 = time.perf_counter() - t0
+    res["single_c64_mixed"] = {"solves": sample, "ms_per_solve": round(1e3 * dt1 / sample, 1),
+                               "solves_per_s": round(sample / dt1, 2), "iterations": s1["iterations"]}
+    del p, me, mi
+    p, me, mi = setup(B.C128)
+    t0 = time.perf_counter()
+    ref, s2, c2 = p.solve(dirs[:sample], tol=tol, maxit=1500)
+    ref = ref.cpu().numpy()
+    dt2 = time.perf_counter() - t0
+    res["single_fp64"] = {"solves": sample, "ms_per_solve": round(1e3 * dt2 / sample, 1),
+                          "solves_per_s": round(sample / dt2, 2), "iterations": s2["iterations"]}
+    del p, me, mi
+    sl = [slice(0, ne), slice(ne, 2 * ne), slice(2 * ne, 2 * ne + ni), slice(2 * ne + ni, None)]
+    err = max(float(np.linalg.norm(blk[r][q] - ref[r][q]) / np.linalg.norm(ref[r][q]))
+              for r in range(sample) for q in sl)
+    return {"workload": f"ellipsoid-ico5/fib8000 MTF (n_ext {ne}, n_int {ni}, k 8/12, rho ratio 2), 64 plane waves, "
+                        f"GMRES tol {tol:g}",
+            **res, "trace_rel_err_block_vs_fp64": err,
+            "speedup_block_vs_fp64": round(res["block_c64_mixed"]["solves_per_s"] / res["single_fp64"]["solves_per_s"],
+                                           2),
+            "speedup_block_vs_single_mixed": round(res["block_c64_mixed"]["solves_per_s"] /
+                                                   res["single_c64_mixed"]["solves_per_s"], 2)}
+
+
+def serving_run(B, synth, n_requests=24, slots=4, tol=1e-5, maxit=1000):
+    """The serving workload: the first `n_requests` of the seeded Poisson
+    stream (mean 20 requests/s; random ellipsoids with semi-axes in
+    [0.5, 1.5], exterior icosphere L3-L5, interior Fibonacci grid at 0.7-1.3
+    times the exterior node count, k_ext in [1, 15], k_int = k_ext x [1.2,
+    2.5], rho ratio 1.5, 1-16 plane waves) released at their arrival times
+    into a server with `slots` workers (mixed precision, all directions of a
+    request solved together, admission by device footprint).  Meshes are
+    generated before the clock starts (they are the requests' inputs)."""
+    from paper_2206_00708_amd import serve
+    qs = synth.serving_stream()[:n_requests]
+    reqs = []
+    for i, q in enumerate(qs):
+        ext, inte = synth.request_meshes(q)
+        reqs.append(serve.Request(i, q["t_arrival"], ext, inte, q["k_ext"], q["k_int"], q["rho_ext"], q["rho_int"],
+                                  synth.request_directions(q)))
+    srv = serve.Server(slots=slots, tol=tol, maxit=maxit)
+    res, summ = srv.run(reqs, realtime=True)
+    srv.close()
+    iters = [r.stats["iterations"] for r in res.values() if r.stats]
+    summ["workload"] = (f"seeded Poisson stream, first {n_requests} requests (mean 20 req/s), random ellipsoids, "
+                        f"ext L3-L5, complex64 + FP64 refinement, tol {tol:g}, maxit {maxit}")
+    summ["iterations_median"] = int(statistics.median(iters)) if iters else 0
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +249,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP64 vs mixed comparison")
+    ap.add_argument("--no-batching", action="store_true", help="skip the multi-RHS comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
                          "HBM byte counters) and exit")
@@ -262,6 +366,10 @@ def main():
     }
     if not args.no_precision:
         line["precision"] = precision_compare(ctx, B, synth, np)
+    if not args.no_batching:
+        line["batching"] = batching_compare(ctx, B, synth, np)
+    if not args.no_serving:
+        line["serving"] = serving_run(B, synth)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_oracle_baseline(c)
     print(json.dumps(line), flush=True)

@@ -113,10 +113,17 @@ void bem_ctx_destroy(bem_ctx *ctx);
 /* Device bytes currently held by problems of the context. */
 size_t bem_ctx_bytes_in_use(const bem_ctx *ctx);
 
+/* Free the assembly scratch the context keeps between problems (the
+ * block-pair tiles of the regular-pair assembly, grown to the largest mesh
+ * assembled so far); the next assembly allocates it again.  Synchronises the
+ * context stream.  For callers that account device memory per request. */
+bem_status bem_ctx_trim(bem_ctx *ctx);
+
 /* Per-kernel device time.  Kernels, by bit index: 0 "regular_tiles",
  * 1 "gather_tiles", 2 "singular_pairs", 3 "near_scatter", 4 "mtf_dense",
  * 5 "mass_apply", 6 "cgs_dots", 7 "cgs_update", 8 "arnoldi_finish",
- * 9 "mass_inverse".  Every launch of a kernel whose bit is set in
+ * 9 "mass_inverse", 10 "block_gemm" (multi-RHS operator product), 11
+ * "mass_gemm" (multi-RHS inverse-mass product).  Every launch of a kernel whose bit is set in
  * kernel_mask is bracketed by HIP events on the context stream (a few
  * microseconds of overhead per launch); 0 disables.  Setting the mask resets
  * the totals.  bem_ctx_kernel_time synchronises the stream and returns the
@@ -146,8 +153,10 @@ bem_status bem_problem_create(bem_ctx *ctx, const bem_mesh *ext, const bem_mesh 
 void bem_problem_destroy(bem_problem *p);
 
 /* Device bytes the problem needs with `nrhs` right-hand sides and `maxit`
- * Krylov steps (operators, projections, Krylov bases, scratch); for admission
- * control.  May be called before assembly. */
+ * Krylov steps (operators, projections, Krylov bases and triangular factors,
+ * assembly scratch; for BEM_C64_MIXED problems all nrhs runs advancing
+ * together, up to 64, with the buffers of the matrix-core products); for
+ * admission control.  May be called before assembly. */
 bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t maxit, size_t *bytes);
 
 /* Dense Galerkin matrices V, K, T, D on both meshes (Sec. 2.1, 2.4, 5.1),

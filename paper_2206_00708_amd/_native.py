@@ -34,6 +34,7 @@ SIGNATURES = {
     "bem_ctx_create": (c_status, [i32, vp, sz, ctypes.POINTER(vp)]),
     "bem_ctx_destroy": (None, [vp]),
     "bem_ctx_bytes_in_use": (sz, [vp]),
+    "bem_ctx_trim": (c_status, [vp]),
     "bem_ctx_set_kernel_timing": (c_status, [vp, ctypes.c_uint32]),
     "bem_ctx_kernel_time": (c_status, [vp, ctypes.c_char_p, ctypes.POINTER(f64), ctypes.POINTER(i64)]),
     "bem_mesh_create": (c_status, [vp, vp, i64, vp, i64, ctypes.POINTER(vp)]),

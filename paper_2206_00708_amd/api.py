@@ -45,8 +45,12 @@ class Context:
     def bytes_in_use(self):
         return N.load().bem_ctx_bytes_in_use(self._h)
 
+    def trim(self):
+        """bem_ctx_trim: free the assembly scratch kept between problems."""
+        _check(N.load().bem_ctx_trim(self._h))
+
     KERNELS = ("regular_tiles", "gather_tiles", "singular_pairs", "near_scatter", "mtf_dense", "mass_apply",
-               "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse", "block_gemm")
+               "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse", "block_gemm", "mass_gemm")
 
     def set_kernel_timing(self, kernels=()):
         """Time every launch of the named kernels with HIP events (empty: off)."""

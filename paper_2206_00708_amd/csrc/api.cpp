@@ -82,7 +82,7 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, v
 
 const char *const kKernelNames[K_COUNT] = {"regular_tiles", "gather_tiles", "singular_pairs", "near_scatter",
                                            "mtf_dense", "mass_apply", "cgs_dots", "cgs_update", "arnoldi_finish",
-                                           "mass_inverse", "block_gemm"};
+                                           "mass_inverse", "block_gemm", "mass_gemm"};
 
 static hipEvent_t take_event(bem_ctx *c)
 {
@@ -187,6 +187,20 @@ void bem_ctx_destroy(bem_ctx *ctx)
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     delete ctx;
+}
+
+bem_status bem_ctx_trim(bem_ctx *ctx)
+{
+    if (!ctx) return set_error(BEM_E_ARG, "null context");
+    BEM_HIP(hipSetDevice(ctx->device));
+    BEM_HIP(hipStreamSynchronize(ctx->stream));
+    if (ctx->scratch) {
+        BEM_HIP(hipFree(ctx->scratch));
+        ctx->in_use -= ctx->scratch_bytes;
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    return BEM_OK;
 }
 
 bem_status bem_ctx_set_kernel_timing(bem_ctx *ctx, uint32_t kernel_mask)
@@ -322,7 +336,15 @@ bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t max
     size_t scratch = std::max(tile_scratch_bytes(p->ext, eb), tile_scratch_bytes(p->inte, eb));
     scratch = std::max(scratch, std::max(p->ext->h.sing.size(), p->inte->h.sing.size()) * 36 * sizeof(double2));
     b += scratch;
-    b += (size_t)nrhs * ((size_t)(maxit + 1) * n + 8 * n) * sizeof(double2);   // Krylov bases + work vectors
+    // runs that advance together: every right-hand side of a complex64 problem (up to 64 per block), else one
+    const size_t R = p->prec == BEM_C64_MIXED ? (size_t)std::min(nrhs, 64) : 1;
+    b += R * ((size_t)(maxit + 1) * n + 8 * n) * sizeof(double2);                 // Krylov bases + work vectors
+    b += R * (size_t)maxit * (maxit + 1) * sizeof(double2);                       // triangular factors
+    if (R > 1) {   // right-hand matrices and K-chunk partials of the matrix-core products
+        const size_t kop = 2 * (op_ld(ne) + op_ld(ni)), km = ((ne + 31) & ~size_t(31)) + ((ni + 31) & ~size_t(31));
+        b += (2 * 128 * kop + 256 * km) * sizeof(float);
+        b += (8 * 128 * 4 + 8 * 256) * (ne + ni) * sizeof(float);
+    }
     b += 64 * (ne + ni) * sizeof(double);                          // sparse couplings (bound)
     *bytes = b;
     return BEM_OK;

@@ -15,7 +15,8 @@
 // 128-row x 128-column tile over one K chunk: 32-float slices of A (128 rows)
 // and Bt (128 columns) are staged in LDS (double-buffered, rows padded to
 // 36 floats), each wave owns 32 rows x 128 columns (four 32 x 32
-// accumulators) and issues 16 MFMAs per 8 k values.  Partial tiles of the K
+// accumulators) and issues 16 MFMAs per 8 k values; for fewer right-hand
+// columns the tile narrows to 32 or 64 columns (one or two accumulators).  Partial tiles of the K
 // chunks go to separate output slices; the caller sums them in a fixed
 // order (no atomics, deterministic).  The launch returns at once when the
 // Krylov runs it serves have all converged.
@@ -28,17 +29,19 @@ namespace {
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int GT_M = 128;   // rows per tile
-constexpr int GT_N = 128;   // columns per tile
+constexpr int GT_N = 128;   // columns per column block of Bt and C
 constexpr int GT_K = 32;    // k per LDS stage
 constexpr int GT_LD = GT_K + 4;
 
 }  // namespace
 
-// One segment: C[kc][cb * 128 + c][row] = sum over the k of chunk kc of A[row][k] Bt[cb * 128 + c][k].
+// One segment: C[kc][cb * 128 + c][row] = sum over the k of chunk kc of A[row][k] Bt[cb * 128 + c][k],
+// for the first 32 NT columns c of each 128-column block (NT = 1, 2, 4).
+template <int NT>
 __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
 {
     __shared__ float As[2][GT_M * GT_LD];
-    __shared__ float Bs[2][GT_N * GT_LD];
+    __shared__ float Bs[2][32 * NT * GT_LD];
     if (G.done) {   // every run has converged: nothing left to compute
         bool all = true;
         for (int r = 0; r < G.nrun; ++r) all = all && G.done[(int64_t)r * G.done_stride] != 0;
@@ -70,22 +73,25 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
     const float *bg = SB + (int64_t)(cb * GT_N + lr) * ldb + lc;
     const int64_t astep = (int64_t)32 * lda, bstep = (int64_t)32 * ldb;
     // row offsets of the other three loads (rows past M clamp to the last row)
-    int64_t aoff[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-        aoff[q] = (int64_t)(min(rt * GT_M + lr + 32 * q, M - 1) - min(rt * GT_M + lr, M - 1)) * lda;
+    const int arow0 = min(rt * GT_M + lr, M - 1);
+    const int64_t aoff1 = (int64_t)(min(rt * GT_M + lr + 32, M - 1) - arow0) * lda;
+    const int64_t aoff2 = (int64_t)(min(rt * GT_M + lr + 64, M - 1) - arow0) * lda;
+    const int64_t aoff3 = (int64_t)(min(rt * GT_M + lr + 96, M - 1) - arow0) * lda;
     (void)astep;
     float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    (void)rb1; (void)rb2; (void)rb3;
 #define GEMM_FETCH(k)                                                              \
     do {                                                                           \
-        ra0 = *reinterpret_cast<const float4 *>(ag + aoff[0] + (k));               \
-        ra1 = *reinterpret_cast<const float4 *>(ag + aoff[1] + (k));               \
-        ra2 = *reinterpret_cast<const float4 *>(ag + aoff[2] + (k));               \
-        ra3 = *reinterpret_cast<const float4 *>(ag + aoff[3] + (k));               \
+        ra0 = *reinterpret_cast<const float4 *>(ag + (k));                         \
+        ra1 = *reinterpret_cast<const float4 *>(ag + aoff1 + (k));                 \
+        ra2 = *reinterpret_cast<const float4 *>(ag + aoff2 + (k));                 \
+        ra3 = *reinterpret_cast<const float4 *>(ag + aoff3 + (k));                 \
         rb0 = *reinterpret_cast<const float4 *>(bg + (k));                         \
-        rb1 = *reinterpret_cast<const float4 *>(bg + bstep + (k));                 \
-        rb2 = *reinterpret_cast<const float4 *>(bg + 2 * bstep + (k));             \
-        rb3 = *reinterpret_cast<const float4 *>(bg + 3 * bstep + (k));             \
+        if constexpr (NT > 1) rb1 = *reinterpret_cast<const float4 *>(bg + bstep + (k)); \
+        if constexpr (NT > 2) {                                                    \
+            rb2 = *reinterpret_cast<const float4 *>(bg + 2 * bstep + (k));         \
+            rb3 = *reinterpret_cast<const float4 *>(bg + 3 * bstep + (k));         \
+        }                                                                          \
     } while (0)
 #define GEMM_STASH(b)                                                              \
     do {                                                                           \
@@ -95,14 +101,16 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
         *reinterpret_cast<float4 *>(da + 64 * GT_LD) = ra2;                        \
         *reinterpret_cast<float4 *>(da + 96 * GT_LD) = ra3;                        \
         *reinterpret_cast<float4 *>(db) = rb0;                                     \
-        *reinterpret_cast<float4 *>(db + 32 * GT_LD) = rb1;                        \
-        *reinterpret_cast<float4 *>(db + 64 * GT_LD) = rb2;                        \
-        *reinterpret_cast<float4 *>(db + 96 * GT_LD) = rb3;                        \
+        if constexpr (NT > 1) *reinterpret_cast<float4 *>(db + 32 * GT_LD) = rb1;  \
+        if constexpr (NT > 2) {                                                    \
+            *reinterpret_cast<float4 *>(db + 64 * GT_LD) = rb2;                    \
+            *reinterpret_cast<float4 *>(db + 96 * GT_LD) = rb3;                    \
+        }                                                                          \
     } while (0)
 
-    v16f acc[4];
+    v16f acc[NT];
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int n = 0; n < NT; ++n)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[n][v] = 0.f;
 
@@ -120,12 +128,12 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
 #pragma unroll
         for (int kk = 0; kk < GT_K; kk += 8) {
             const float4 a = *reinterpret_cast<const float4 *>(as + kk);
-            float4 b[4];
+            float4 b[NT];
 #pragma unroll
-            for (int n = 0; n < 4; ++n) b[n] = *reinterpret_cast<const float4 *>(bs + n * 32 * GT_LD + kk);
+            for (int n = 0; n < NT; ++n) b[n] = *reinterpret_cast<const float4 *>(bs + n * 32 * GT_LD + kk);
             // lanes 0-31 hold k = kk..kk+3, lanes 32-63 k = kk+4..kk+7: MFMA q adds k pair (kk+q, kk+4+q)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) {
+            for (int n = 0; n < NT; ++n) {
                 acc[n] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b[n].x, acc[n], 0, 0, 0);
                 acc[n] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b[n].y, acc[n], 0, 0, 0);
                 acc[n] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b[n].z, acc[n], 0, 0, 0);
@@ -151,13 +159,13 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
         const int row = rt * GT_M + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
         if (row < M)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) Cb[(int64_t)n * 32 * M + row] = acc[n][v];
+            for (int n = 0; n < NT; ++n) Cb[(int64_t)n * 32 * M + row] = acc[n][v];
     }
 }
 
 // Fills tile0 of every segment and launches; K and the K chunks must be
 // multiples of 32, lda >= K, ldb >= K, and Bt zero where A has padding.
-bem_status launch_gemm_f32(bem_ctx *ctx, GemmArgs &G, hipStream_t st)
+bem_status launch_gemm_f32(bem_ctx *ctx, GemmArgs &G, hipStream_t st, int kernel_id)
 {
     int tiles = 0;
     for (int s = 0; s < G.nseg; ++s) {
@@ -169,8 +177,13 @@ bem_status launch_gemm_f32(bem_ctx *ctx, GemmArgs &G, hipStream_t st)
         tiles += ((S.M + GT_M - 1) / GT_M) * S.ncb * nk;
     }
     if (tiles == 0) return BEM_OK;
-    KTimer kt(ctx, K_BLOCK_GEMM);
-    launch_k(kt, gemm_f32_kernel, dim3(tiles), dim3(256), 0, st, G);
+    KTimer kt(ctx, kernel_id);
+    if (G.nt == 1)
+        launch_k(kt, gemm_f32_kernel<1>, dim3(tiles), dim3(256), 0, st, G);
+    else if (G.nt == 2)
+        launch_k(kt, gemm_f32_kernel<2>, dim3(tiles), dim3(256), 0, st, G);
+    else
+        launch_k(kt, gemm_f32_kernel<4>, dim3(tiles), dim3(256), 0, st, G);
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }

@@ -138,7 +138,7 @@ void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue me
 namespace bemtx {
 // kernels timed by the optional per-launch HIP-event timer of a context
 enum KernelId { K_REGULAR = 0, K_GATHER, K_SINGULAR, K_NEAR, K_MTF_DENSE, K_MASS_APPLY, K_CGS_DOTS, K_CGS_UPDATE,
-                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_BLOCK_GEMM, K_COUNT };
+                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_BLOCK_GEMM, K_MASS_GEMM, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 }  // namespace bemtx
 
@@ -202,8 +202,9 @@ struct GemmArgs {
     int nseg;
     const int *done;    // optional: nrun flags, done_stride ints apart; all set = skip
     int done_stride, nrun;
+    int nt;             // columns computed per 128-column block: 32 nt (nt = 1, 2, 4)
 };
-bem_status launch_gemm_f32(bem_ctx *ctx, GemmArgs &G, hipStream_t st);
+bem_status launch_gemm_f32(bem_ctx *ctx, GemmArgs &G, hipStream_t st, int kernel_id);
 }  // namespace bemtx
 
 struct bem_mesh {
@@ -232,6 +233,7 @@ struct bem_problem {
     double t_geometry_ms = 0, t_regular_ms = 0, t_singular_ms = 0, t_projection_ms = 0;
     hipEvent_t asm_ev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     bool asm_timing_pending = false;
-    // multi-RHS products: K chunks per GEMM (operators, inverse masses), picked by timing at first use
-    int gemm_nk_ops = 0, gemm_nk_mass = 0;
+    // multi-RHS products: K chunks per GEMM [operators, inverse masses][tile width 32, 64, 128
+    // columns], picked by timing at first use
+    int gemm_nk[2][3] = {{0, 0, 0}, {0, 0, 0}};
 };

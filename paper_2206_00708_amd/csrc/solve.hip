@@ -1044,11 +1044,11 @@ __global__ __launch_bounds__(256) void pack_mass_kernel(int nv, int kld, int R, 
     Bt[(int64_t)c * kld + k] = val;
 }
 
-// z rows of every run from the inverse-mass partials [nk][256][N] of each mesh;
+// z rows of every run from the inverse-mass partials [nk][ccols][N] of each mesh;
 // grid (ceil((ne + ni) / 256), R)
 __global__ __launch_bounds__(256) void mass_reduce_kernel(int ne, int ni, const float *__restrict__ Ce,
-                                                          const float *__restrict__ Ci, int nke, int nki, int R,
-                                                          double2 *__restrict__ Z, int64_t zstride,
+                                                          const float *__restrict__ Ci, int nke, int nki, int ccols,
+                                                          int R, double2 *__restrict__ Z, int64_t zstride,
                                                           const KrylovState *__restrict__ st)
 {
     const int r = blockIdx.y;
@@ -1062,7 +1062,7 @@ __global__ __launch_bounds__(256) void mass_reduce_kernel(int ne, int ni, const 
     const int nk = ext ? nke : nki;
     double s[4] = {0, 0, 0, 0};
     for (int kc = 0; kc < nk; ++kc)
-        for (int q = 0; q < 4; ++q) s[q] += (double)C[((int64_t)kc * 4 * BLOCK_RHS + 4 * r + q) * nv + i];
+        for (int q = 0; q < 4; ++q) s[q] += (double)C[((int64_t)kc * ccols + 4 * r + q) * nv + i];
     double2 *z = Z + r * zstride + (ext ? 0 : 2 * ne);
     z[i] = make_double2(s[0], s[1]);
     z[i + nv] = make_double2(s[2], s[3]);
@@ -1233,9 +1233,21 @@ bem_status block_alloc(bem_problem *p, BlockBufs &bb)
     return s;
 }
 
+// tile width (in 32-column units) and 128-column blocks for `cols` right-hand columns
+void gemm_width(int cols, int &nt, int &ncb)
+{
+    ncb = (cols + 127) / 128;
+    nt = cols <= 32 ? 1 : cols <= 64 ? 2 : 4;
+    if (ncb > 1) nt = 4;
+}
+int nt_index(int nt) { return nt == 1 ? 0 : nt == 2 ? 1 : 2; }
+
 GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st)
 {
     GemmArgs G{};
+    int nt, ncb;
+    gemm_width(2 * R, nt, ncb);
+    G.nt = nt;
     const int nv[2] = {(int)p->ext->h.nv, (int)p->inte->h.nv};
     int q = 0;
     for (int m = 0; m < 2; ++m) {
@@ -1263,6 +1275,9 @@ GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const
 GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st)
 {
     GemmArgs G{};
+    int nt, ncb;
+    gemm_width(4 * R, nt, ncb);
+    G.nt = nt;
     const int nv[2] = {(int)p->ext->h.nv, (int)p->inte->h.nv};
     for (int m = 0; m < 2; ++m) {
         const int km = minv_ld(nv[m], true);
@@ -1275,7 +1290,7 @@ GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, cons
         S.M = nv[m];
         S.K = km;
         S.kchunk = kchunk_for(km, nk);
-        S.ncb = 2;
+        S.ncb = ncb;
     }
     G.nseg = 2;
     G.done = st ? &st[0].done : nullptr;
@@ -1284,11 +1299,15 @@ GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, cons
     return G;
 }
 
-// Chunk counts of the two GEMMs, chosen once per problem by timing every
-// candidate on the problem's own matrices (the right-hand buffers are zero).
-bem_status block_tune(bem_problem *p, BlockBufs &bb)
+// K chunk count of one GEMM (which = 0 operators, 1 inverse masses) for R
+// runs, chosen once per problem and tile width by timing every candidate on
+// the problem's own matrices (right-hand buffers zeroed first).
+bem_status block_tune(bem_problem *p, BlockBufs &bb, int which, int R, int &nk)
 {
-    if (p->gemm_nk_ops > 0) return BEM_OK;
+    int nt, ncb;
+    gemm_width(which == 0 ? 2 * R : 4 * R, nt, ncb);
+    int &slot = p->gemm_nk[which][nt_index(nt)];
+    if (slot > 0) { nk = slot; return BEM_OK; }
     bem_ctx *ctx = p->ctx;
     hipStream_t st = ctx->stream;
     for (int m = 0; m < 2; ++m) {
@@ -1301,27 +1320,24 @@ bem_status block_tune(bem_problem *p, BlockBufs &bb)
     BEM_HIP(hipEventCreate(&e1));
     struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
     const int cand[4] = {1, 2, 4, 8};
-    for (int which = 0; which < 2; ++which) {
-        float best = 1e30f;
-        int pick = 4;
-        for (int c : cand) {
-            float tmin = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
-                GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c, BLOCK_RHS, nullptr)
-                                        : mass_gemm_args(p, bb, c, BLOCK_RHS, nullptr);
-                BEM_HIP(hipEventRecord(e0, st));
-                bem_status s = launch_gemm_f32(ctx, G, st);
-                if (s) return s;
-                BEM_HIP(hipEventRecord(e1, st));
-                BEM_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                tmin = std::min(tmin, ms);
-            }
-            if (tmin < best) { best = tmin; pick = c; }
+    float best = 1e30f;
+    int pick = 4;
+    for (int c : cand) {
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c, R, nullptr) : mass_gemm_args(p, bb, c, R, nullptr);
+            BEM_HIP(hipEventRecord(e0, st));
+            bem_status s = launch_gemm_f32(ctx, G, st, which == 0 ? K_BLOCK_GEMM : K_MASS_GEMM);
+            if (s) return s;
+            BEM_HIP(hipEventRecord(e1, st));
+            BEM_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            tmin = std::min(tmin, ms);
         }
-        (which == 0 ? p->gemm_nk_ops : p->gemm_nk_mass) = pick;
+        if (tmin < best) { best = tmin; pick = c; }
     }
+    slot = nk = pick;
     return BEM_OK;
 }
 
@@ -1333,14 +1349,18 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
 {
     hipStream_t st = p->ctx->stream;
     const int nv[2] = {A.ne, A.ni};
+    int nk_ops = 0, nk_mass = 0;   // (tuning, at first use, zeroes the right-hand buffers: before packing)
+    bem_status s = block_tune(p, bb, 0, R, nk_ops);
+    if (!s && strong) s = block_tune(p, bb, 1, R, nk_mass);
+    if (s) return s;
     for (int m = 0; m < 2; ++m) {
         const int kop = 2 * (int)op_ld(nv[m]);
         hipLaunchKernelGGL(pack_ops_kernel, dim3((int)((op_ld(nv[m]) + 255) / 256), BLOCK_RHS), dim3(256), 0, st, nv[m],
                            kop, R, X, xstride, m == 0 ? 0 : 2 * A.ne, kst, bb.btv[m].as<float>(), bb.btw[m].as<float>());
     }
     BEM_HIP(hipGetLastError());
-    GemmArgs G = ops_gemm_args(p, bb, p->gemm_nk_ops, R, kst);
-    bem_status s = launch_gemm_f32(p->ctx, G, st);
+    GemmArgs G = ops_gemm_args(p, bb, nk_ops, R, kst);
+    s = launch_gemm_f32(p->ctx, G, st, K_BLOCK_GEMM);
     if (s) return s;
     BlockC bc;
     for (int m = 0; m < 2; ++m) {
@@ -1357,12 +1377,12 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
                            (const double2 *)Y, ystride, m == 0 ? 0 : 2 * A.ne, kst, bb.btm[m].as<float>());
     }
     BEM_HIP(hipGetLastError());
-    GemmArgs Gm = mass_gemm_args(p, bb, p->gemm_nk_mass, R, kst);
-    s = launch_gemm_f32(p->ctx, Gm, st);
+    GemmArgs Gm = mass_gemm_args(p, bb, nk_mass, R, kst);
+    s = launch_gemm_f32(p->ctx, Gm, st, K_MASS_GEMM);
     if (s) return s;
     hipLaunchKernelGGL(mass_reduce_kernel, dim3((A.ne + A.ni + 255) / 256, R), dim3(256), 0, st, A.ne, A.ni, Gm.seg[0].C,
-                       Gm.seg[1].C, nchunks(Gm.seg[0].K, Gm.seg[0].kchunk), nchunks(Gm.seg[1].K, Gm.seg[1].kchunk), R,
-                       Z, zstride, kst);
+                       Gm.seg[1].C, nchunks(Gm.seg[0].K, Gm.seg[0].kchunk), nchunks(Gm.seg[1].K, Gm.seg[1].kchunk),
+                       128 * Gm.seg[0].ncb, R, Z, zstride, kst);
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
@@ -1580,7 +1600,6 @@ bem_status matvec_batch_impl(bem_problem *p, const void *x, void *y, int nrhs, i
     if (!s) s = dev_alloc(ctx, yi, R * vb);
     if (!s) s = dev_alloc(ctx, zi, R * vb);
     if (!s) s = block_alloc(p, bb);
-    if (!s) s = block_tune(p, bb);
     if (s) return s;
     const MtfArgs A = make_args(p);
     const dim3 g((n + 255) / 256);
@@ -1685,7 +1704,6 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     BlockBufs bb;
     if (R > 1) {
         s = block_alloc(p, bb);
-        if (!s) s = block_tune(p, bb);
         if (s) return s;
     }
     KrylovState *hstate = nullptr;   // two pinned snapshots of the R states

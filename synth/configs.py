@@ -90,3 +90,17 @@ def serving_stream(n_requests=500, rate=20.0, seed=5):
                          k_ext=ke, k_int=ki, rho_ext=1.0, rho_int=1.5, nrhs=nrhs,
                          seed=int(rng.integers(1 << 31))))
     return reqs
+
+
+def request_meshes(req):
+    """Exterior icosphere and independent interior Fibonacci grid of one
+    serving request (ellipsoid with the request's semi-axes, 1 % jitter)."""
+    (xe, te), (xi, ti), _ = make_pair(req["seed"], req["ext_level"], "fib", 0.01, req["axes"],
+                                      int_n=req["int_n"])
+    return (xe, te), (xi, ti)
+
+
+def request_directions(req):
+    """The request's plane-wave directions (seeded by the request)."""
+    return plane_wave_directions(req["nrhs"], np.random.default_rng(req["seed"] + 1))
+
