@@ -206,9 +206,12 @@ bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b
  * right-hand side did not reach opts->tol within opts->maxit (its best
  * iterate is written).  stats may be NULL.
  * BEM_C64_MIXED: iterative refinement; each step solves the correction
- * system with GMRES on FP32 products (FP64 Krylov basis) to opts->ir_inner_tol
- * (0: half the remaining reduction, at least 1e-7), then recomputes
- * M^-1 (b - A x) with FP64 arithmetic on the stored operators; at most
+ * system with GMRES (FP64 Krylov basis) to opts->ir_inner_tol (0: half the
+ * remaining reduction, at least 1e-7), its products of the complex64
+ * operators accumulated in FP32 once the residual estimate is below 2e4
+ * times that tolerance and in FP64 before (single right-hand side; block
+ * runs use FP32 throughout), then recomputes M^-1 (b - A x) with FP64
+ * arithmetic on the stored operators; at most
  * opts->ir_max steps (0: 10) and opts->maxit Arnoldi steps in total.
  * With opts->batch > 1 up to that many right-hand sides run as independent
  * GMRES instances that share one matrix-core product per step (each run has

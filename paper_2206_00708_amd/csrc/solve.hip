@@ -10,7 +10,7 @@
 //
 //   mass_inverse kernels   dense M^-1 by Chebyshev iteration on Jacobi-scaled
 //                          M (the spectrum of diag(M)^-1 M of P1 triangles
-//                          lies in [1/2, 2], so 40 steps reach rounding
+//                          lies in [1/2, 2], so 36 steps reach FP64 rounding
 //                          level); search directions live in LDS, several
 //                          columns per workgroup.
 //   mtf_dense_part         the four dense blocks of each row streamed once
@@ -128,9 +128,10 @@ __global__ void rhs_kernel(int ne, int ni, const int32_t *__restrict__ star_ptr,
 
 
 // Column c = blockIdx.x of M^-1 (= row c, M is symmetric), blockDim 1024,
-// R rows per thread kept in registers; the search direction lives in LDS.
+// R rows per thread kept in registers; the search direction lives in LDS;
+// nsteps Chebyshev steps.
 template <int R, class TOut>
-__global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, int ldm, const int32_t *__restrict__ mp,
+__global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, int ldm, int nsteps, const int32_t *__restrict__ mp,
                                                              const int32_t *__restrict__ mc,
                                                              const double *__restrict__ mv, TOut *__restrict__ Minv)
 {
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, int ldm, con
     }
     double rho = 1.0 / sigma1;
     __syncthreads();
-    for (int it = 0; it < 40; ++it) {
+    for (int it = 0; it < nsteps; ++it) {
         const double rho_new = 1.0 / (2.0 * sigma1 - rho);
 #pragma unroll
         for (int k = 0; k < R; ++k) {
@@ -191,13 +192,15 @@ __global__ __launch_bounds__(1024) void mass_inverse_kernel(int nv, int ldm, con
 // Same iteration for C columns per workgroup: M in ELL form (width W, layout
 // [q][row] so that loads are coalesced, padding = zero entries on the
 // diagonal) read from L2 once per step for all C columns, and the search
-// directions double-buffered in LDS so that one barrier per step suffices.
-template <int R, int C, class TOut>
-__global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm, int W, const int32_t *__restrict__ ell_col,
+// directions double-buffered in LDS so that one barrier per step suffices
+// (DB), or single-buffered with a second barrier when two copies do not fit.
+template <int R, int C, class TOut, bool DB>
+__global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm, int W, int nsteps,
+                                                                 const int32_t *__restrict__ ell_col,
                                                                  const double *__restrict__ ell_val,
                                                                  TOut *__restrict__ Minv)
 {
-    extern __shared__ double dsh[];   // [2][C][nv]
+    extern __shared__ double dsh[];   // [2][C][nv] (double-buffered) or [C][nv]
     const int c0 = blockIdx.x * C;
     const int tid = threadIdx.x;
     const double lmin = 0.5, lmax = 2.0;
@@ -222,10 +225,11 @@ __global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm,
     double rho = 1.0 / sigma1;
     int cur = 0;
     __syncthreads();
-    for (int it = 0; it < 40; ++it) {
+    for (int it = 0; it < nsteps; ++it) {
         const double rho_new = 1.0 / (2.0 * sigma1 - rho);
-        const double *dold = dsh + cur * C * nv;
-        double *dnew = dsh + (cur ^ 1) * C * nv;
+        const double *dold = dsh + (DB ? cur * C * nv : 0);
+        double *dnew = dsh + (DB ? (cur ^ 1) * C * nv : 0);
+        double dk[R][C];   // single buffer: directions kept until every product of the step is done
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             const int row = tid + 1024 * k;
@@ -244,7 +248,18 @@ __global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm,
                 const double d = dold[c * nv + row];
                 x[k][c] += d;
                 r[k][c] -= ad[c];
-                dnew[c * nv + row] = rho_new * rho * d + (2.0 * rho_new / delta) * dg[k] * r[k][c];
+                dk[k][c] = rho_new * rho * d + (2.0 * rho_new / delta) * dg[k] * r[k][c];
+                if (DB) dnew[c * nv + row] = dk[k][c];
+            }
+        }
+        if (!DB) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                const int row = tid + 1024 * k;
+                if (row < nv)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) dnew[c * nv + row] = dk[k][c];
             }
         }
         rho = rho_new;
@@ -261,6 +276,11 @@ __global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm,
     }
 }
 
+// Chebyshev steps for the stored precision: the error falls by 1/3 per step
+// on a spectrum inside [1/2, 2] (bound 2 (1/3)^k), so 36 steps reach 1e-17
+// (FP64 storage) and 18 steps 5e-9 (FP32 storage, below its rounding).
+template <class TOut> constexpr int chebyshev_steps() { return sizeof(TOut) == 4 ? 18 : 36; }
+
 template <int R, class TOut>
 static bem_status launch_minv_r(bem_problem *p, int nv, int mesh)
 {
@@ -269,21 +289,22 @@ static bem_status launch_minv_r(bem_problem *p, int nv, int mesh)
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer kt(p->ctx, K_MASS_INVERSE);
     launch_k(kt, mass_inverse_kernel<R, TOut>, dim3(nv), dim3(1024), lds, p->ctx->stream, nv,
-             minv_ld(nv, sizeof(TOut) == 4), p->M_ptr[mesh].as<int32_t>(), p->M_col[mesh].as<int32_t>(),
+             minv_ld(nv, sizeof(TOut) == 4), chebyshev_steps<TOut>(), p->M_ptr[mesh].as<int32_t>(),
+             p->M_col[mesh].as<int32_t>(),
              p->M_val[mesh].as<double>(), p->Minv[mesh].as<TOut>());
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
 
-template <int R, int C, class TOut>
+template <int R, int C, class TOut, bool DB>
 static bem_status launch_minv_ell(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev)
 {
-    const size_t lds = (size_t)2 * C * nv * sizeof(double);
-    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_ell_kernel<R, C, TOut>),
+    const size_t lds = (size_t)(DB ? 2 : 1) * C * nv * sizeof(double);
+    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_ell_kernel<R, C, TOut, DB>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer kt(p->ctx, K_MASS_INVERSE);
-    launch_k(kt, mass_inverse_ell_kernel<R, C, TOut>, dim3((nv + C - 1) / C), dim3(1024), lds, p->ctx->stream, nv,
-             minv_ld(nv, sizeof(TOut) == 4), W, ec, ev, p->Minv[mesh].as<TOut>());
+    launch_k(kt, mass_inverse_ell_kernel<R, C, TOut, DB>, dim3((nv + C - 1) / C), dim3(1024), lds, p->ctx->stream,
+             nv, minv_ld(nv, sizeof(TOut) == 4), W, chebyshev_steps<TOut>(), ec, ev, p->Minv[mesh].as<TOut>());
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
@@ -293,11 +314,12 @@ static bem_status launch_minv_ell_r(bem_problem *p, int nv, int W, int mesh, con
 {
     // columns per workgroup: as many double-buffered directions as fit in 160 KiB of LDS
     const int cfit = (int)(163840 / (2 * (size_t)nv * sizeof(double)));
-    if (cfit >= 8) return launch_minv_ell<R, 8, TOut>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 4) return launch_minv_ell<R, 4, TOut>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 3) return launch_minv_ell<R, 3, TOut>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 2) return launch_minv_ell<R, 2, TOut>(p, nv, W, mesh, ec, ev);
-    return launch_minv_ell<R, 1, TOut>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 8) return launch_minv_ell<R, 8, TOut, true>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 4) return launch_minv_ell<R, 4, TOut, true>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 3) return launch_minv_ell<R, 3, TOut, true>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 2) return launch_minv_ell<R, 2, TOut, true>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 1) return launch_minv_ell<R, 1, TOut, true>(p, nv, W, mesh, ec, ev);
+    return launch_minv_ell<R, 1, TOut, false>(p, nv, W, mesh, ec, ev);
 }
 
 template <class TOut>
@@ -310,7 +332,10 @@ static bem_status launch_minv_ell_any(bem_problem *p, int nv, int W, int mesh, c
     case 4: return launch_minv_ell_r<4, TOut>(p, nv, W, mesh, dc, dv);
     case 5: case 6: return launch_minv_ell_r<6, TOut>(p, nv, W, mesh, dc, dv);
     case 7: case 8: return launch_minv_ell_r<8, TOut>(p, nv, W, mesh, dc, dv);
-    default: return launch_minv_ell_r<10, TOut>(p, nv, W, mesh, dc, dv);
+    case 9: case 10: return launch_minv_ell_r<10, TOut>(p, nv, W, mesh, dc, dv);
+    case 11: case 12: return launch_minv_ell_r<12, TOut>(p, nv, W, mesh, dc, dv);
+    case 13: case 14: case 15: case 16: return launch_minv_ell_r<16, TOut>(p, nv, W, mesh, dc, dv);
+    default: return launch_minv_ell_r<20, TOut>(p, nv, W, mesh, dc, dv);
     }
 }
 
@@ -343,7 +368,7 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh)
     const Csr &M = p->M[mesh];
     int W = 0;
     for (int64_t i = 0; i < M.nrows; ++i) W = std::max(W, M.ptr[i + 1] - M.ptr[i]);
-    if (2 * (size_t)nv * sizeof(double) <= 163840) {
+    if ((size_t)nv * sizeof(double) <= 163840) {
         // ELL, [q][row], padded with zeros on the diagonal
         auto &ec = p->ell_col_h[mesh];
         auto &ev = p->ell_val_h[mesh];
@@ -1396,6 +1421,7 @@ struct Gmres {
     hipEvent_t *ev;
     int n, nchunk, nrow_blk, m, R;
     KBatch B;
+    double acc64_above = 0.0;   // single run, complex64: FP64 accumulation while the residual estimate exceeds this
 
     // R independent GMRES runs without restart on M^-1 A x = r0 (r0 already
     // preconditioned; run r's start vector at r0 + r r0stride), x0 = 0,
@@ -1428,6 +1454,7 @@ struct Gmres {
         std::vector<double> last_res(R, 1.0);
         int slot = 0, pending = -1;
         bool sync_mode = false, stop = false;
+        bool acc64 = acc64_above > 0.0;   // switched off once a polled estimate falls below acc64_above
         auto all_done = [&](const KrylovState *k) {
             for (int r = 0; r < R; ++r)
                 if (!k[r].done) return false;
@@ -1440,7 +1467,7 @@ struct Gmres {
                 s = block_apply(p, A, *bb, R, vj, B.basis, W.y.as<double2>(), B.vec, W.z.as<double2>(), B.vec, true,
                                 dst);
             else
-                s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
+                s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>(), acc64);
             if (s) return s;
             for (int pass = 0; pass < 2; ++pass) {
                 {
@@ -1467,6 +1494,7 @@ struct Gmres {
                 BEM_HIP(hipMemcpyAsync(hs, dst, sb, hipMemcpyDeviceToHost, st));
                 BEM_HIP(hipStreamSynchronize(st));
                 stop = all_done(hs);
+                if (acc64 && hs[0].resid < acc64_above) acc64 = false;
                 continue;
             }
             if (issued % BATCH != 0) continue;
@@ -1476,6 +1504,7 @@ struct Gmres {
                 BEM_HIP(hipEventSynchronize(ev[pending]));
                 const KrylovState *k = hstate + (size_t)pending * R;
                 if (all_done(k)) { stop = true; break; }
+                if (acc64 && k[0].resid < acc64_above) acc64 = false;
                 // steps still to go at the observed geometric rate of the slowest run
                 double togo = 0.0;
                 int seen = issued;
@@ -1805,6 +1834,14 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
                         hipLaunchKernelGGL(zero_kernel, gv, dim3(256), 0, st, (int64_t)n,
                                            const_cast<double2 *>(rhs_s) + (size_t)r * n);
                 }
+                // Inexact Krylov: the product error a GMRES step tolerates grows as
+                // the residual falls (relative to the target), so the single-run
+                // inner solve accumulates the complex64 products in FP64 while
+                // its residual estimate is above 2e4 times its tolerance and in
+                // FP32 after that; the early FP32 errors would otherwise leave a
+                // gap between the estimate and the true residual that costs a
+                // restarted refinement step.  (Block runs: FP32 matrix cores.)
+                gm.acc64_above = R == 1 ? std::min(1.0, 2e4 * tolr[0]) : 0.0;
                 s = gm.run(rhs_s, n, tolr.data(), m - used, W.d.as<double2>(), fin.data());
                 if (s) return s;
                 int most = 0;
