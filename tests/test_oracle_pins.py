@@ -219,6 +219,26 @@ def test_calderon_projectors(orc):
     assert np.all(res[1] < 0.05), res
 
 
+def test_calderon_identity_squared(orc):
+    """The Calderon operator A = [[-K, V], [D, T]] squares to I/4 on a closed
+    surface; discretely (M^-1 A)^2 x -> x / 4 for smooth traces x as the mesh
+    is refined (ellipsoid, icosphere L2 and L3).  A wrong sign, a dropped term
+    or a transposed block of any of the four operators breaks it."""
+    k = 1.5
+    err = []
+    for L in (2, 3):
+        xyz, tri = synth.icosphere(L)
+        xyz = synth.scale_to_ellipsoid(xyz, (1.0, 0.8, 0.6))
+        o = orc.assemble(xyz, tri, k)
+        M = orc.mass(xyz, tri)
+        A = np.block([[-o["K"], o["V"]], [o["D"], o["T"]]])
+        Z = np.zeros_like(M)
+        Bm = np.linalg.solve(np.block([[M, Z], [Z, M]]), A)
+        x = np.concatenate([xyz[:, 0] + 0.5 * xyz[:, 1] * xyz[:, 2], np.cos(xyz[:, 2]) + xyz[:, 0]]).astype(complex)
+        err.append(np.linalg.norm(Bm @ (Bm @ x) - x / 4) / np.linalg.norm(x / 4))
+    assert err[1] < err[0] / 3 and err[1] < 5e-3, err
+
+
 def test_plane_wave_loads_divergence_theorem(orc):
     """sum_j f_j = int_Gamma u_inc and sum_j g_j = int_Gamma d_n u_inc
     = -k^2 int_Omega u_inc; on the unit sphere these tend to
