@@ -14,7 +14,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
+#include <condition_variable>
+#include <mutex>
 #include <thread>
 
 #include "internal.h"
@@ -32,18 +35,101 @@ static uint64_t spread3(uint64_t v)
     return v;
 }
 
+// Persistent worker threads for parallel_for (host table building and the
+// mortar).  One parallel_for owns the pool at a time; a call that finds it
+// busy (another thread of the caller inside the library) runs its range
+// inline, so concurrent callers never wait on each other.
+namespace {
+class Pool {
+  public:
+    static Pool &get()
+    {
+        // never destroyed: the workers wait on its condition variable until the process ends
+        static Pool *pool = new Pool;
+        return *pool;
+    }
+    int size() const { return (int)workers_.size() + 1; }
+    std::mutex owner;   // held for the duration of one parallel_for
+
+    // run f(part) for part in [0, nparts) on the workers and the caller
+    void run(int nparts, const std::function<void(int)> &f)
+    {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            job_ = &f;
+            nparts_ = nparts;
+            next_ = 1;   // the caller takes part 0
+            done_ = 0;
+            ++gen_;
+        }
+        cv_.notify_all();
+        f(0);
+        int mine;
+        while ((mine = take()) >= 0) { f(mine); finish(); }
+        std::unique_lock<std::mutex> lk(m_);
+        cv_done_.wait(lk, [&] { return done_ == nparts_ - 1; });
+        job_ = nullptr;
+    }
+
+  private:
+    Pool()
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        const int nw = (int)std::max(0u, std::min(16u, hw ? hw : 1u) - 1u);
+        for (int i = 0; i < nw; ++i) workers_.emplace_back([this] { loop(); });
+        for (auto &w : workers_) w.detach();   // live until the process ends
+    }
+    int take()
+    {
+        std::lock_guard<std::mutex> lk(m_);
+        if (!job_ || next_ >= nparts_) return -1;
+        return next_++;
+    }
+    void finish()
+    {
+        std::lock_guard<std::mutex> lk(m_);
+        if (++done_ == nparts_ - 1) cv_done_.notify_all();
+    }
+    void loop()
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int)> *job;
+            int part;
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return gen_ != seen && job_ && next_ < nparts_; });
+                seen = gen_;
+                job = job_;
+                part = next_++;
+            }
+            (*job)(part);
+            finish();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex m_;
+    std::condition_variable cv_, cv_done_;
+    const std::function<void(int)> *job_ = nullptr;
+    int nparts_ = 0, next_ = 0, done_ = 0;
+    uint64_t gen_ = 0;
+};
+}  // namespace
+
 void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &f)
 {
-    unsigned hw = std::thread::hardware_concurrency();
-    int64_t nth = std::max<int64_t>(1, std::min<int64_t>(16, hw ? hw : 1));
-    nth = std::min<int64_t>(nth, std::max<int64_t>(1, n / std::max<int64_t>(1, grain)));
+    Pool &pool = Pool::get();
+    int64_t nth = std::min<int64_t>(pool.size(), std::max<int64_t>(1, n / std::max<int64_t>(1, grain)));
     if (nth <= 1) {
         f(0, n);
         return;
     }
-    std::vector<std::thread> pool;
-    for (int64_t t = 0; t < nth; ++t) pool.emplace_back(f, n * t / nth, n * (t + 1) / nth);
-    for (auto &th : pool) th.join();
+    std::unique_lock<std::mutex> own(pool.owner, std::try_to_lock);
+    if (!own.owns_lock()) {   // pool in use by another caller: run inline
+        f(0, n);
+        return;
+    }
+    pool.run((int)nth, [&](int part) { f(n * part / nth, n * (part + 1) / nth); });
 }
 
 bem_status mesh_prepare(MeshData &m)
@@ -70,10 +156,11 @@ bem_status mesh_prepare(MeshData &m)
                 e[3 * t + a] = u << 32 | w;
                 r[3 * t + a] = w << 32 | u;
             }
+        std::thread sorter([&r] { std::sort(r.begin(), r.end()); });
         std::sort(e.begin(), e.end());
+        sorter.join();
         if (std::adjacent_find(e.begin(), e.end()) != e.end())
             return set_error(BEM_E_MESH, "edge used twice with the same orientation (non-manifold or flipped)");
-        std::sort(r.begin(), r.end());
         if (e != r) return set_error(BEM_E_MESH, "mesh is not closed or not consistently oriented");
     }
     double vol = 0.0, amax = 0.0, amin = 1e300;
@@ -154,7 +241,7 @@ bem_status mesh_prepare(MeshData &m)
     m.blk_slots.assign((size_t)nb * SMAX, -1);
     m.slot_cnt.assign((size_t)nb * SMAX, 0);
     m.slot_ent.assign((size_t)nb * SMAX * LMAX, 0);
-    std::vector<std::vector<int32_t>> memb_lists(nv);
+    m.memb_ptr.assign(nv + 1, 0);
     for (int b = 0; b < nb; ++b) {
         std::vector<int32_t> vs;
         for (int32_t t = m.blk_start[b]; t < m.blk_start[b + 1]; ++t)
@@ -165,7 +252,7 @@ bem_status mesh_prepare(MeshData &m)
         m.blk_nslot[b] = (int32_t)vs.size();
         for (size_t s = 0; s < vs.size(); ++s) {
             m.blk_slots[(size_t)b * SMAX + s] = vs[s];
-            memb_lists[vs[s]].push_back(b << 8 | (int32_t)s);
+            m.memb_ptr[vs[s] + 1]++;
         }
         for (int32_t t = m.blk_start[b]; t < m.blk_start[b + 1]; ++t)
             for (int a = 0; a < 3; ++a) {
@@ -176,11 +263,14 @@ bem_status mesh_prepare(MeshData &m)
                 ++cnt;
             }
     }
-    m.memb_ptr.assign(nv + 1, 0);
-    for (int64_t v = 0; v < nv; ++v) m.memb_ptr[v + 1] = m.memb_ptr[v] + (int32_t)memb_lists[v].size();
+    // vertex -> (block, slot) memberships, blocks ascending
+    for (int64_t v = 0; v < nv; ++v) m.memb_ptr[v + 1] += m.memb_ptr[v];
     m.memb.resize(m.memb_ptr[nv]);
-    for (int64_t v = 0; v < nv; ++v)
-        std::copy(memb_lists[v].begin(), memb_lists[v].end(), m.memb.begin() + m.memb_ptr[v]);
+    {
+        std::vector<int32_t> mfill(m.memb_ptr.begin(), m.memb_ptr.end() - 1);
+        for (int b = 0; b < nb; ++b)
+            for (int s = 0; s < m.blk_nslot[b]; ++s) m.memb[mfill[m.blk_slots[(size_t)b * SMAX + s]]++] = b << 8 | s;
+    }
 
     // ---- vertex stars (internal numbering)
     m.star_ptr.assign(nv + 1, 0);
@@ -193,11 +283,13 @@ bem_status mesh_prepare(MeshData &m)
             for (int a = 0; a < 3; ++a) m.star_ent[fill[m.tri[3 * t + a]]++] = (int32_t)(3 * t + a);
     }
 
-    // ---- ordered singular pairs, kinds 3 / 2 / 1, corner permutations
-    std::vector<SingPair> by_kind[4];
-    for (int k = 1; k <= 3; ++k) by_kind[k].reserve(k == 1 ? 10 * nt : (k == 2 ? 3 * nt : nt));
-    std::vector<int64_t> seen_by(nt, -1);
-    for (int64_t t = 0; t < nt; ++t) {
+    // ---- ordered singular pairs, kinds 3 / 2 / 1, corner permutations.
+    // Kind-major order, within a kind by test triangle t, for each t in the
+    // order its vertex stars list the trial triangles.  Chunks of t in
+    // parallel, concatenated in t order.
+    std::vector<int32_t> pcnt[4];   // pcnt[k][t]: first pair of kind k and test triangle t, within kind k
+    for (int k = 1; k <= 3; ++k) pcnt[k].assign(nt + 1, 0);
+    auto pairs_of = [&](int64_t t, std::vector<int64_t> &seen_by, auto &&emit) {
         for (int a = 0; a < 3; ++a) {
             int32_t v = m.tri[3 * t + a];
             for (int32_t e = m.star_ptr[v]; e < m.star_ptr[v + 1]; ++e) {
@@ -222,75 +314,123 @@ bem_status mesh_prepare(MeshData &m)
                 sp.sig = s;
                 sp.kind = ns;
                 sp.perm = px[0] | px[1] << 2 | px[2] << 4 | py[0] << 6 | py[1] << 8 | py[2] << 10;
-                by_kind[ns].push_back(sp);
+                emit(ns, sp);
+            }
+        }
+    };
+    // chunks of test triangles in parallel, each into its own per-kind lists
+    const int64_t nchunk_t = std::min<int64_t>(nt, 128);
+    std::vector<std::vector<SingPair>> chunk_pairs[4];
+    for (int k = 1; k <= 3; ++k) chunk_pairs[k].resize(nchunk_t);
+    parallel_for(nchunk_t, 1, [&](int64_t c0, int64_t c1) {
+        std::vector<int64_t> seen_by(nt, -1);
+        for (int64_t c = c0; c < c1; ++c)
+            for (int64_t t = nt * c / nchunk_t; t < nt * (c + 1) / nchunk_t; ++t)
+                pairs_of(t, seen_by, [&](int k, const SingPair &sp) {
+                    chunk_pairs[k][c].push_back(sp);
+                    pcnt[k][t + 1]++;
+                });
+    });
+    int64_t kbase[4] = {0, 0, 0, 0};
+    {
+        int64_t acc = 0;
+        for (int k = 3; k >= 1; --k) {
+            for (int64_t t = 0; t < nt; ++t) pcnt[k][t + 1] += pcnt[k][t];
+            kbase[k] = acc;
+            m.nsing_kind[k] = pcnt[k][nt];
+            acc += pcnt[k][nt];
+        }
+        m.sing.resize((size_t)acc);
+        for (int k = 3; k >= 1; --k) {
+            int64_t at = kbase[k];
+            for (auto &cp : chunk_pairs[k]) {
+                std::copy(cp.begin(), cp.end(), m.sing.begin() + at);
+                at += (int64_t)cp.size();
             }
         }
     }
-    m.sing.clear();
-    for (int kind = 3; kind >= 1; --kind) {
-        m.nsing_kind[kind] = (int32_t)by_kind[kind].size();
-        m.sing.insert(m.sing.end(), by_kind[kind].begin(), by_kind[kind].end());
-    }
 
-    // ---- near entries: unique (i, j) touched by singular pairs, contributions in pair order
+    // ---- near entries: unique (i, j) touched by singular pairs, contributions in pair order.
+    // Row i collects, kind by kind and triangle by triangle of its star (the
+    // global pair order restricted to the row), the 3 entries (i, j) of every
+    // pair whose test triangle holds i; columns are numbered by first
+    // appearance.  Chunks of rows in parallel, concatenated in row order.
     {
         const size_t nc = m.sing.size() * 9;
-        std::vector<int32_t> row_cnt(nv + 1, 0);
-        for (size_t p = 0; p < m.sing.size(); ++p)
-            for (int a = 0; a < 3; ++a) row_cnt[m.tri[3 * m.sing[p].tau + a] + 1] += 3;
-        for (int64_t v = 0; v < nv; ++v) row_cnt[v + 1] += row_cnt[v];
-        std::vector<int32_t> fill(row_cnt.begin(), row_cnt.end() - 1);
-        std::vector<std::pair<int32_t, int32_t>> byrow(nc);   // (j, src), grouped by i, src ascending
-        for (size_t p = 0; p < m.sing.size(); ++p)
-            for (int a = 0; a < 3; ++a) {
-                const int32_t i = m.tri[3 * m.sing[p].tau + a];
-                for (int b = 0; b < 3; ++b)
-                    byrow[fill[i]++] = {m.tri[3 * m.sing[p].sig + b], (int32_t)(p * 9 + a * 3 + b)};
-            }
-        // group each row's contributions by column j in order of first appearance
-        // (deterministic; contributions keep their pair order within an entry);
-        // rows in parallel: count distinct columns, prefix, then fill
-        std::vector<int32_t> nuniq(nv + 1, 0);
-        auto group_rows = [&](int64_t r0, int64_t r1, bool fill) {
-            std::vector<int32_t> mark(nv, -1), slot_of(nv, 0), ucol, ucnt, off;
-            for (int64_t i = r0; i < r1; ++i) {
-                ucol.clear();
-                ucnt.clear();
-                for (int32_t e = row_cnt[i]; e < row_cnt[i + 1]; ++e) {
-                    const int32_t j = byrow[e].first;
-                    if (mark[j] != (int32_t)i) {
-                        mark[j] = (int32_t)i;
-                        slot_of[j] = (int32_t)ucol.size();
-                        ucol.push_back(j);
-                        ucnt.push_back(0);
-                    }
-                    ucnt[slot_of[j]]++;
+        auto row_entries = [&](int64_t i, std::vector<std::pair<int32_t, int32_t>> &out) {
+            out.clear();
+            for (int k = 3; k >= 1; --k)
+                for (int32_t e = m.star_ptr[i]; e < m.star_ptr[i + 1]; ++e) {
+                    const int32_t t = m.star_ent[e] / 3, a = m.star_ent[e] - 3 * (m.star_ent[e] / 3);
+                    for (int64_t p = kbase[k] + pcnt[k][t]; p < kbase[k] + pcnt[k][t + 1]; ++p)
+                        for (int b = 0; b < 3; ++b)
+                            out.push_back({m.tri[3 * m.sing[p].sig + b], (int32_t)(p * 9 + a * 3 + b)});
                 }
-                if (!fill) {
-                    nuniq[i + 1] = (int32_t)ucol.size();
-                    continue;
-                }
-                off.resize(ucol.size());
-                int32_t acc = row_cnt[i];
-                for (size_t u = 0; u < ucol.size(); ++u) {
-                    const size_t k = (size_t)nuniq[i] + u;
-                    m.near_ptr[k] = acc;
-                    m.near_i[k] = (int32_t)i;
-                    m.near_j[k] = ucol[u];
-                    off[u] = acc;
-                    acc += ucnt[u];
-                }
-                for (int32_t e = row_cnt[i]; e < row_cnt[i + 1]; ++e)
-                    m.near_src[off[slot_of[byrow[e].first]]++] = byrow[e].second;
-            }
         };
-        parallel_for(nv, 256, [&](int64_t a, int64_t b) { group_rows(a, b, false); });
-        for (int64_t i = 0; i < nv; ++i) nuniq[i + 1] += nuniq[i];
-        m.near_i.assign(nuniq[nv], 0);
-        m.near_j.assign(nuniq[nv], 0);
-        m.near_ptr.assign(nuniq[nv], 0);
-        m.near_src.assign(nc, 0);
-        parallel_for(nv, 256, [&](int64_t a, int64_t b) { group_rows(a, b, true); });
+        // rows in chunks, in parallel; each chunk keeps its unique columns
+        // (with their contribution counts) and its grouped sources
+        struct RowChunk { std::vector<int32_t> row, col, cnt, src; };
+        const int64_t nchunk_r = std::min<int64_t>(nv, 128);
+        std::vector<RowChunk> rc(nchunk_r);
+        parallel_for(nchunk_r, 1, [&](int64_t c0, int64_t c1) {
+            std::vector<int32_t> mark(nv, -1), slot_of(nv, 0), ucol, ucnt, off;
+            std::vector<std::pair<int32_t, int32_t>> ent;
+            for (int64_t c = c0; c < c1; ++c) {
+                RowChunk &R = rc[c];
+                for (int64_t i = nv * c / nchunk_r; i < nv * (c + 1) / nchunk_r; ++i) {
+                    row_entries(i, ent);
+                    ucol.clear();
+                    ucnt.clear();
+                    for (const auto &e : ent) {
+                        const int32_t j = e.first;
+                        if (mark[j] != (int32_t)i) {
+                            mark[j] = (int32_t)i;
+                            slot_of[j] = (int32_t)ucol.size();
+                            ucol.push_back(j);
+                            ucnt.push_back(0);
+                        }
+                        ucnt[slot_of[j]]++;
+                    }
+                    off.resize(ucol.size());
+                    int32_t acc = (int32_t)R.src.size();
+                    for (size_t u = 0; u < ucol.size(); ++u) {
+                        R.row.push_back((int32_t)i);
+                        R.col.push_back(ucol[u]);
+                        R.cnt.push_back(ucnt[u]);
+                        off[u] = acc;
+                        acc += ucnt[u];
+                    }
+                    R.src.resize(acc);
+                    for (const auto &e : ent) R.src[off[slot_of[e.first]]++] = e.second;
+                }
+            }
+        });
+        size_t nent = 0, nsrc = 0;
+        std::vector<size_t> ent0(nchunk_r), src0(nchunk_r);
+        for (int64_t c = 0; c < nchunk_r; ++c) {
+            ent0[c] = nent;
+            src0[c] = nsrc;
+            nent += rc[c].row.size();
+            nsrc += rc[c].src.size();
+        }
+        if (nsrc != nc) return set_error(BEM_E_MESH, "internal: singular contribution count");
+        m.near_i.resize(nent);
+        m.near_j.resize(nent);
+        m.near_ptr.resize(nent);
+        m.near_src.resize(nc);
+        parallel_for(nchunk_r, 1, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c) {
+                const RowChunk &R = rc[c];
+                int32_t acc = (int32_t)src0[c];
+                for (size_t u = 0; u < R.row.size(); ++u) {
+                    m.near_i[ent0[c] + u] = R.row[u];
+                    m.near_j[ent0[c] + u] = R.col[u];
+                    m.near_ptr[ent0[c] + u] = acc;
+                    acc += R.cnt[u];
+                }
+                std::copy(R.src.begin(), R.src.end(), m.near_src.begin() + src0[c]);
+            }
+        });
         m.near_ptr.push_back((int32_t)nc);
     }
     return BEM_OK;
