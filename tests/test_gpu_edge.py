@@ -1,0 +1,114 @@
+"""GPU edge cases through the C ABI: degenerate and limiting configurations
+of the method, checked against the oracle (tolerances as in the parity
+tests: operators 1e-12 (FP64), mortar 1e-14, traces 1e-5)."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_2206_00708_amd")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return B.Context(0)
+
+
+def _problem(ctx, ext, inte, ke, ki, re=1.0, ri=1.0, prec=B.C128):
+    me, mi = B.Mesh(ctx, *ext), B.Mesh(ctx, *inte)
+    p = B.Problem(ctx, me, mi, ke, ki, re, ri, precision=prec)
+    p.assemble_operators()
+    p.assemble_projection()
+    return p, me, mi
+
+
+def _blocks(x, ne, ni):
+    return (x[:ne], x[ne:2 * ne], x[2 * ne:2 * ne + ni], x[2 * ne + ni:])
+
+
+@pytest.mark.parametrize("prec", [B.C128, B.C64_MIXED])
+def test_transparent_body(ctx, orc, prec):
+    """k_int = k_ext and equal densities: the body is invisible.  The solve
+    matches the oracle's LU solution, and -v_ext is the incident wave at the
+    exterior nodes up to the discretisation error."""
+    c = synth.make_config("C1")
+    p, _, _ = _problem(ctx, c["ext"], c["int"], 2.0, 2.0, prec=prec)
+    d = np.array([[0.0, 0.6, 0.8]])
+    X, _ = orc.solve_mtf(c["ext"], c["int"], 2.0, 2.0, 1.0, 1.0, d)
+    out, st, code = p.solve(d, tol=1e-9, maxit=600)
+    assert code == B.OK, st
+    x = out.cpu().numpy()[0]
+    ne, ni = len(c["ext"][0]), len(c["int"][0])
+    for g, r in zip(_blocks(x, ne, ni), _blocks(X[0], ne, ni)):
+        assert _rel(g, r) < 1e-5
+    u = np.exp(1j * 2.0 * c["ext"][0] @ d[0])
+    assert _rel(-x[:ne], u) < 0.05
+
+
+def test_identical_meshes_projection_is_mass(ctx, orc):
+    """One mesh for both sides (the conforming limit): the mortar matrix is
+    the mass matrix, to rounding."""
+    xyz, tri = synth.icosphere(2)
+    p, _, _ = _problem(ctx, (xyz, tri), (xyz, tri), 2.0, 3.0)
+    import scipy.sparse as sp
+    rp, col, val = p.projection()
+    P = sp.csr_matrix((val, col, rp), shape=(len(xyz), len(xyz))).toarray()
+    M = orc.mass(xyz, tri)
+    assert np.abs(P - M).max() < 1e-14 * np.abs(M).max()
+
+
+def test_maxit_one(ctx):
+    c = synth.make_config("C1")
+    for prec, batch in ((B.C128, 0), (B.C64_MIXED, 0), (B.C64_MIXED, 3)):
+        p, _, _ = _problem(ctx, c["ext"], c["int"], c["k_ext"], c["k_int"], prec=prec)
+        d = synth.plane_wave_directions(3, np.random.default_rng(8))
+        out, st, code = p.solve(d, tol=1e-12, maxit=1, ir_max=1, batch=batch)
+        assert code == B.W_NOCONV
+        assert 1 <= st["iterations"] <= 3
+        assert np.all(np.isfinite(out.cpu().numpy()))
+
+
+def test_batches_beyond_64(ctx):
+    """70 directions with batch 64: two groups (64 + 6 runs); columns of both
+    groups equal their one-at-a-time solves."""
+    c = synth.make_config("C1")
+    p, _, _ = _problem(ctx, c["ext"], c["int"], c["k_ext"], c["k_int"], prec=B.C64_MIXED)
+    d = synth.plane_wave_directions(70, np.random.default_rng(9))
+    out, st, code = p.solve(d, tol=1e-8, maxit=400, batch=64)
+    assert code == B.OK, st
+    pick = [0, 63, 64, 69]
+    seq, s1, c1 = p.solve(d[pick], tol=1e-8, maxit=400)
+    assert c1 == B.OK
+    got, sq = out.cpu().numpy(), seq.cpu().numpy()
+    for q, r in enumerate(pick):
+        assert _rel(got[r], sq[q]) < 1e-6, r
+
+
+def test_tetrahedron_matrix_cores(ctx, orc):
+    """Four vertices per mesh (GEMM tiles far larger than the matrices, one K
+    stage): batched products and a batched solve against the oracle."""
+    xyz = np.array([[1.0, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]]) * 0.5
+    tri = synth.orient_outward(xyz, np.array([[0, 1, 2], [0, 1, 3], [0, 2, 3], [1, 2, 3]], dtype=np.int32))
+    p, _, _ = _problem(ctx, (xyz, tri), (xyz, tri), 1.3, 2.1, prec=B.C64_MIXED)
+    ops = orc.operators((xyz, tri), (xyz, tri), 1.3, 2.1)
+    A = orc.mtf_system(ops, 1.0, 1.0)
+    rng = np.random.default_rng(10)
+    X = rng.standard_normal((3, 16)) + 1j * rng.standard_normal((3, 16))
+    Y = p.mtf_matvec_batch(torch.from_numpy(X), strong=False).cpu().numpy()
+    for r in range(3):
+        assert _rel(Y[r], A @ X[r]) < 2e-5
+    d = synth.plane_wave_directions(3, rng)
+    Xs, _ = orc.solve_mtf((xyz, tri), (xyz, tri), 1.3, 2.1, 1.0, 1.0, d, ops=ops)
+    out, st, code = p.solve(d, tol=1e-9, maxit=64, batch=3)
+    assert code == B.OK, st
+    got = out.cpu().numpy()
+    for r in range(3):
+        assert _rel(got[r], Xs[r]) < 1e-5
