@@ -73,6 +73,7 @@ bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch,
 bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw, bool fp32,
                            double2 *contrib, void *ops[4], hipStream_t st);
 bem_status launch_mass_inverse(bem_problem *p, int mesh);
+bem_status launch_sym_corrections(bem_problem *p, int mesh);
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats);
 bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space);
@@ -257,6 +258,7 @@ bem_status bem_mesh_create(bem_ctx *ctx, const double *xyz, int64_t nv, const in
     if (s == BEM_OK) s = upload(ctx, m->d.near_j, m->h.near_j);
     if (s == BEM_OK) s = upload(ctx, m->d.near_ptr, m->h.near_ptr);
     if (s == BEM_OK) s = upload(ctx, m->d.near_src, m->h.near_src);
+    if (s == BEM_OK) s = upload(ctx, m->d.near_row, m->h.near_row);
     if (s == BEM_OK) s = upload(ctx, m->d.star_ptr, m->h.star_ptr);
     if (s == BEM_OK) s = upload(ctx, m->d.star_ent, m->h.star_ent);
     if (s == BEM_OK) s = dev_alloc(ctx, m->d.geo, (size_t)nt * sizeof(TriGeo));
@@ -411,6 +413,8 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
             if (s) return s;
         }
         BEM_HIP(hipEventRecord(p->asm_ev[m][2], st));
+        bem_status s = launch_sym_corrections(p, m);
+        if (s) return s;
     }
     p->asm_timing_pending = true;
     p->ops_ready = true;

@@ -94,6 +94,7 @@ struct MeshData {
     std::vector<SingPair> sing;        // sorted by kind (3, 2, 1)
     int32_t nsing_kind[4] = {0, 0, 0, 0};
     std::vector<int32_t> near_i, near_j, near_ptr, near_src;   // src = pair*9 + a*3 + b
+    std::vector<int32_t> near_row;   // near entries of row i: [near_row[i], near_row[i + 1])
     // vertex star (RHS gather): triangle*3 + corner
     std::vector<int32_t> star_ptr, star_ent;
     double area_total = 0.0;
@@ -103,7 +104,7 @@ struct MeshDev {
     DevMem perm;   // caller vertex -> internal vertex (int32)
     DevMem geof;   // TriGeoF table
     DevMem xyz, tri, blk_start, blk_nslot, slot_cnt, slot_ent, memb_ptr, memb, sing, near_i, near_j,
-        near_ptr, near_src, star_ptr, star_ent, geo;
+        near_ptr, near_src, near_row, star_ptr, star_ent, geo;
 };
 
 // CSR in internal numbering
@@ -227,6 +228,9 @@ struct bem_problem {
     bemtx::Csr M[2], P_ie, P_ei;
     bemtx::DevMem P_ie_ptr, P_ie_col, P_ie_val, P_ei_ptr, P_ei_col, P_ei_val;
     bemtx::DevMem Minv[2];          // dense real inverse mass matrices (FP64)
+    // per near entry (i, j) of each mesh: V_ij - V_ji (j < i, else 0), D_ij - D_ji (likewise),
+    // T_ij - K_ji, complex128; the mat-vec reads only K and the upper triangles of V and D
+    bemtx::DevMem corr[2];
     std::vector<int32_t> ell_col_h[2];   // host staging of the ELL mass rows (kept for async copies)
     std::vector<double> ell_val_h[2];
     bemtx::DevMem M_ptr[2], M_col[2], M_val[2], M_ell_col[2], M_ell_val[2];

@@ -432,6 +432,9 @@ bem_status mesh_prepare(MeshData &m)
             }
         });
         m.near_ptr.push_back((int32_t)nc);
+        m.near_row.assign(nv + 1, 0);
+        for (size_t e = 0; e < nent; ++e) m.near_row[m.near_i[e] + 1]++;
+        for (int64_t v = 0; v < nv; ++v) m.near_row[v + 1] += m.near_row[v];
     }
     return BEM_OK;
 }

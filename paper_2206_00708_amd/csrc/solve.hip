@@ -1,4 +1,4 @@
-// Multiple-traces system (Sec. 3.3, Eq. "mtf:discrete") on the device, FP64:
+// Multiple-traces system (Sec. 3.3, Eq. "mtf:discrete") on the device:
 //
 //   [ -K_e   V_e    1/2 P_ei              0               ] [v_e]   [-f]
 //   [  D_e   T_e    0                    1/2 (re/ri) P_ei ] [w_e] = [-g]
@@ -13,13 +13,18 @@
 //                          lies in [1/2, 2], so 36 steps reach FP64 rounding
 //                          level); search directions live in LDS, several
 //                          columns per workgroup.
-//   mtf_dense_part         the four dense blocks of each row streamed once
-//                          (complex128, 16 B per lane, coalesced,
-//                          non-temporal) against a column chunk of [v; w]
-//                          staged in LDS; per-chunk partial sums.
-//   mtf_combine            fixed-order sum of the chunk partials plus the
-//                          mortar coupling of the row (CSR).
-//   mass_apply_part/combine  z = M^-1 y, same split-column scheme.
+//   mtf_sym_tile           one product with the dense blocks of both meshes,
+//                          K read in full, V and D only on and above the
+//                          diagonal, T = K^T (64 x 64 or 128 x 128 tiles,
+//                          16-byte non-temporal loads; row sums reduced with
+//                          DPP, column sums per lane); per-tile partials.
+//   mtf_sym_combine        fixed-order sum of the tile partials, the
+//                          near-entry corrections of the parts that are not
+//                          symmetric, and the mortar coupling of the row.
+//   mass_apply_part/combine  z = M^-1 y, split-column scheme: a chunk of y
+//                          staged in LDS, several rows per wave.
+//   block products         R Krylov vectors at once on the matrix cores
+//                          (gemm.hip) for batched right-hand sides.
 //   cgs_dots / cgs_update / arnoldi_finish   classical Gram-Schmidt with one
 //                          re-orthogonalisation in FP64 and the Givens
 //                          rotations of the new Hessenberg column on the
@@ -422,35 +427,24 @@ struct KBatch {
 
 struct MtfArgs {
     int ne, ni;
-    int cw;                  // chunk width bound of the split-column dense kernels
     const void *op[2][4];    // [mesh][V, K, T, D], row stride op_ld(nv), complex128 or complex64
     const int32_t *pie_ptr, *pie_col, *pei_ptr, *pei_col;
     const double *pie_val, *pei_val;
     double c_ext_v, c_ext_w, c_int_v, c_int_w;   // 1/2, 1/2 re/ri, -1/2, -1/2 ri/re
+    const int32_t *near_row[2], *near_j[2];      // near entries of each mesh, by row
+    const double2 *corr[2];                      // [near entry][3]: V_ij - V_ji, D_ij - D_ji (j < i), T_ij - K_ji
+    int sym_ts;                                  // tile edge of the symmetric tile form
 };
 
-// ---- split-column forms: x chunk staged in LDS, per-chunk partial sums,
-// fixed-order combine.  Rows of the two meshes form one grid; chunk widths
-// are multiples of 64 chosen per mesh.
+// ---- split-column form of the inverse-mass apply: a chunk of the vectors
+// staged in LDS, per-chunk partial sums, fixed-order combine.  Rows of the
+// two meshes form one grid; chunk widths are multiples of 64 chosen per mesh.
 
-#ifndef BEMTX_SPLIT_CW
-#define BEMTX_SPLIT_CW 512
-#endif
-#ifndef BEMTX_SPLIT_CW32
-#define BEMTX_SPLIT_CW32 2048
-#endif
-#ifndef BEMTX_MV_UNROLL
-#define BEMTX_MV_UNROLL 1
-#endif
-constexpr int SPLIT_CW_MAX = BEMTX_SPLIT_CW;     // columns per chunk, complex128 operators (upper bound)
-constexpr int SPLIT_CW32_MAX = BEMTX_SPLIT_CW32; // the same for complex64 operators
 #ifndef BEMTX_MASS_CW
 #define BEMTX_MASS_CW 1024
 #endif
-constexpr int MASS_CW_MAX = BEMTX_MASS_CW;       // inverse mass apply
-constexpr int cmin(int a, int b) { return a < b ? a : b; }
-constexpr int SPLIT_CW_MIN = cmin(cmin(SPLIT_CW_MAX, SPLIT_CW32_MAX), MASS_CW_MAX);   // sizes the partial buffer
-constexpr int SPLIT_ROWS = 4;                    // waves per workgroup (one row each in the dense kernels)
+constexpr int MASS_CW_MAX = BEMTX_MASS_CW;       // columns per chunk of the inverse-mass apply (upper bound)
+constexpr int SPLIT_ROWS = 4;                    // waves per workgroup
 #ifndef BEMTX_MASS_RW64
 #define BEMTX_MASS_RW64 4
 #endif
@@ -459,10 +453,6 @@ constexpr int SPLIT_ROWS = 4;                    // waves per workgroup (one row
 #endif
 constexpr int MASS_RW64 = BEMTX_MASS_RW64;       // rows per wave of the FP64 inverse-mass apply
 constexpr int MASS_RW32 = BEMTX_MASS_RW32;       // the same, FP32 storage
-#ifndef BEMTX_DENSE32_RW
-#define BEMTX_DENSE32_RW 1
-#endif
-constexpr int DENSE32_RW = BEMTX_DENSE32_RW;     // rows per wave of the complex64 dense product
 
 __host__ __device__ inline int split_nchunk(int nv, int cwmax) { return (nv + cwmax - 1) / cwmax; }
 __host__ __device__ inline int split_cw(int nv, int cwmax)
@@ -484,162 +474,322 @@ __device__ inline float4 ld_stream2c(const float2 *p)
 #endif
 }
 
-// part[chunk][row] = (sum over the chunk of [-K V] row . [v; w], of [D T] row . [v; w]);
-// complex128 operators, FP64 arithmetic
-__global__ __launch_bounds__(256) void mtf_dense_part_kernel(MtfArgs A, const double2 *__restrict__ x,
-                                                             double4 *__restrict__ part,
-                                                             const KrylovState *__restrict__ st)
-{
-    if (st && st->done) return;
-    __shared__ double2 xs[2 * SPLIT_CW_MAX];
-    const int te = (A.ne + SPLIT_ROWS - 1) / SPLIT_ROWS;
-    const bool ext = (int)blockIdx.x < te;
-    const int nv = ext ? A.ne : A.ni;
-    const int chunk = blockIdx.y;
-    if (chunk >= split_nchunk(nv, SPLIT_CW_MAX)) return;
-    const int cw = split_cw(nv, SPLIT_CW_MAX);
-    const int c0 = chunk * cw, c1 = min(nv, c0 + cw), ncol = c1 - c0;
-    const double2 *xv = ext ? x : x + 2 * A.ne;
-    const double2 *xw = xv + nv;
-    for (int t = threadIdx.x; t < ncol; t += blockDim.x) { xs[t] = xv[c0 + t]; xs[SPLIT_CW_MAX + t] = xw[c0 + t]; }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = (ext ? blockIdx.x : blockIdx.x - te) * SPLIT_ROWS + wave;
-    if (i >= nv) return;
-    const int mi = ext ? 0 : 1;
-    const double2 *Vm = static_cast<const double2 *>(A.op[mi][0]), *Km = static_cast<const double2 *>(A.op[mi][1]);
-    const double2 *Tm = static_cast<const double2 *>(A.op[mi][2]), *Dm = static_cast<const double2 *>(A.op[mi][3]);
-    const int64_t o = (int64_t)i * op_ld(nv) + c0;
-    double ar = 0, ai = 0, br = 0, bi = 0;
-#pragma unroll BEMTX_MV_UNROLL
-    for (int j = lane; j < ncol; j += 64) {
-        const double2 k0 = ld_stream(&Km[o + j]), v0 = ld_stream(&Vm[o + j]);
-        const double2 d0 = ld_stream(&Dm[o + j]), t0 = ld_stream(&Tm[o + j]);
-        const double2 p0 = xs[j], q0 = xs[SPLIT_CW_MAX + j];
-        ar += -(k0.x * p0.x - k0.y * p0.y) + (v0.x * q0.x - v0.y * q0.y);
-        ai += -(k0.x * p0.y + k0.y * p0.x) + (v0.x * q0.y + v0.y * q0.x);
-        br += (d0.x * p0.x - d0.y * p0.y) + (t0.x * q0.x - t0.y * q0.y);
-        bi += (d0.x * p0.y + d0.y * p0.x) + (t0.x * q0.y + t0.y * q0.x);
-    }
-    ar = wave_sum(ar); ai = wave_sum(ai); br = wave_sum(br); bi = wave_sum(bi);
-    if (lane == 0) {
-        const int row = ext ? i : A.ne + i;
-        part[(int64_t)chunk * (A.ne + A.ni) + row] = make_double4(ar, ai, br, bi);
-    }
-}
-
 template <class R> struct Cx;
 template <> struct Cx<float> { using T = float2; };
 template <> struct Cx<double> { using T = double2; };
 
-// Same product on complex64 operators.  Each lane reads two adjacent
-// entries of each block (16 bytes; rows start on 16-byte boundaries and a
-// padding column of zeros completes odd rows); the x chunk is staged in LDS
-// in the accumulation type R: float for the Krylov products (FP32
-// accumulation), double for the refinement residual (FP64 arithmetic on the
-// stored complex64 entries).
-template <class R>
-__global__ __launch_bounds__(256) void mtf_dense_c64_part_kernel(MtfArgs A, const double2 *__restrict__ x,
-                                                                 double4 *__restrict__ part,
-                                                                 const KrylovState *__restrict__ st)
+// ---- symmetric tile form: K is read in full and V, D only on and above the
+// diagonal; T = K^T.  Exact up to rounding for the regular-pair part, whose
+// element blocks are computed once per unordered pair and give V_ij = V_ji,
+// D_ij = D_ji, T_ij = K_ji; the singular rule is applied to both orders of a
+// vertex-sharing pair and is not symmetric to rounding, so the differences
+// on those entries (the near entries) are added by the combine kernel.  One
+// workgroup per pair of 64 x 64 tiles (a <= b): the tiles (a, b) of K, V, D
+// and (b, a) of K are streamed once; products along rows reduce across the
+// wave (DPP), products down columns accumulate per lane.  The partial sums of row
+// tile R with column tile Cc go to part[Cc][row] (each written by exactly one
+// workgroup) and are summed in a fixed order.
+
+// Tile edge: 64 for complex128 (one column per lane, 16-byte loads), 128 for
+// complex64 (two adjacent columns per lane, 16-byte loads).
+template <class E> constexpr int sym_tile() { return sizeof(E) == 16 ? 64 : 128; }
+__host__ __device__ inline int sym_ntile(int nv, int ts) { return (nv + ts - 1) / ts; }
+
+// task t -> tile pair (a, b), a <= b, in row-major order of the upper triangle
+__device__ inline void sym_pair(int64_t t, int nt, int &a, int &b)
 {
-    using C = typename Cx<R>::T;
-    constexpr int RW = DENSE32_RW, ROWS = SPLIT_ROWS * DENSE32_RW;
-    if (st && st->done) return;
-    __shared__ C xs[2 * SPLIT_CW32_MAX];
-    const int te = (A.ne + ROWS - 1) / ROWS;
-    const bool ext = (int)blockIdx.x < te;
-    const int nv = ext ? A.ne : A.ni;
-    const int chunk = blockIdx.y;
-    if (chunk >= split_nchunk(nv, SPLIT_CW32_MAX)) return;
-    const int cw = split_cw(nv, SPLIT_CW32_MAX);
-    const int c0 = chunk * cw, c1 = min(nv, c0 + cw), ncol = c1 - c0;
-    const double2 *xv = ext ? x : x + 2 * A.ne;
-    const double2 *xw = xv + nv;
-    // columns past the chunk's end read as zero (the pair of an odd last column)
-    for (int t = threadIdx.x; t < cw; t += blockDim.x) {
-        C a{0, 0}, b{0, 0};
-        if (t < ncol) {
-            const double2 u = xv[c0 + t], v = xw[c0 + t];
-            a = C{(R)u.x, (R)u.y};
-            b = C{(R)v.x, (R)v.y};
-        }
-        xs[t] = a;
-        xs[SPLIT_CW32_MAX + t] = b;
+    int lo = 0, hi = nt - 1;
+    while (lo < hi) {   // largest a with first(a) <= t, first(a) = a nt - a (a - 1) / 2
+        const int mid = (lo + hi + 1) / 2;
+        if ((int64_t)mid * nt - (int64_t)mid * (mid - 1) / 2 <= t) lo = mid; else hi = mid - 1;
     }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i0 = (ext ? blockIdx.x : blockIdx.x - te) * ROWS + wave * RW;
-    if (i0 >= nv) return;
-    const int mi = ext ? 0 : 1;
-    const float2 *Vm = static_cast<const float2 *>(A.op[mi][0]), *Km = static_cast<const float2 *>(A.op[mi][1]);
-    const float2 *Tm = static_cast<const float2 *>(A.op[mi][2]), *Dm = static_cast<const float2 *>(A.op[mi][3]);
-    int64_t o[RW];   // even offsets: 16-byte aligned pairs; rows past nv repeat the last row (results unused)
-#pragma unroll
-    for (int u = 0; u < RW; ++u) o[u] = (int64_t)min(i0 + u, nv - 1) * op_ld(nv) + c0;
-    R ar[RW], ai[RW], br[RW], bi[RW];
-#pragma unroll
-    for (int u = 0; u < RW; ++u) ar[u] = ai[u] = br[u] = bi[u] = 0;
-    for (int j = 2 * lane; j < ncol; j += 128) {
-        const C p0 = xs[j], p1 = xs[j + 1], q0 = xs[SPLIT_CW32_MAX + j], q1 = xs[SPLIT_CW32_MAX + j + 1];
-#pragma unroll
-        for (int u = 0; u < RW; ++u) {
-            const float4 k = ld_stream2c(&Km[o[u] + j]), v = ld_stream2c(&Vm[o[u] + j]);
-            const float4 d = ld_stream2c(&Dm[o[u] + j]), t = ld_stream2c(&Tm[o[u] + j]);
-            ar[u] += -((R)k.x * p0.x - (R)k.y * p0.y) - ((R)k.z * p1.x - (R)k.w * p1.y)
-                     + ((R)v.x * q0.x - (R)v.y * q0.y) + ((R)v.z * q1.x - (R)v.w * q1.y);
-            ai[u] += -((R)k.x * p0.y + (R)k.y * p0.x) - ((R)k.z * p1.y + (R)k.w * p1.x)
-                     + ((R)v.x * q0.y + (R)v.y * q0.x) + ((R)v.z * q1.y + (R)v.w * q1.x);
-            br[u] += ((R)d.x * p0.x - (R)d.y * p0.y) + ((R)d.z * p1.x - (R)d.w * p1.y)
-                     + ((R)t.x * q0.x - (R)t.y * q0.y) + ((R)t.z * q1.x - (R)t.w * q1.y);
-            bi[u] += ((R)d.x * p0.y + (R)d.y * p0.x) + ((R)d.z * p1.y + (R)d.w * p1.x)
-                     + ((R)t.x * q0.y + (R)t.y * q0.x) + ((R)t.z * q1.y + (R)t.w * q1.x);
-        }
+    a = lo;
+    b = a + (int)(t - ((int64_t)a * nt - (int64_t)a * (a - 1) / 2));
+}
+
+__device__ inline double2 ld_entry(const double2 *p) { return ld_stream(p); }
+__device__ inline float4 ld_entry2(const float2 *p) { return ld_stream2c(p); }   // two adjacent complex64
+
+// Sum over the 64 lanes of a wave with DPP moves (row shifts within each row
+// of 16 lanes, then row broadcasts 15 and 31); the total lands in lane 63.
+template <int CTRL, int RM = 0xF> __device__ inline float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, RM, 0xF, true));
+}
+template <int CTRL, int RM = 0xF> __device__ inline double dpp_mov(double v)
+{
+    int2 q = __builtin_bit_cast(int2, v);
+    q.x = __builtin_amdgcn_update_dpp(0, q.x, CTRL, RM, 0xF, true);
+    q.y = __builtin_amdgcn_update_dpp(0, q.y, CTRL, RM, 0xF, true);
+    return __builtin_bit_cast(double, q);
+}
+template <class R> __device__ inline R wsum63(R v)
+{
+    v += dpp_mov<0x111>(v);        // row_shr:1
+    v += dpp_mov<0x112>(v);        // row_shr:2
+    v += dpp_mov<0x114>(v);        // row_shr:4
+    v += dpp_mov<0x118>(v);        // row_shr:8  (lane 15 of each row: the row's sum)
+    v += dpp_mov<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_mov<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+template <class R> struct CAcc {   // complex accumulator in the arithmetic type R
+    R x = 0, y = 0;
+    template <class A, class B> __device__ void mac(const A &a, const B &b)
+    {
+        x += (R)a.x * b.x - (R)a.y * b.y;
+        y += (R)a.x * b.y + (R)a.y * b.x;
     }
-#pragma unroll
-    for (int u = 0; u < RW; ++u) {
-        const double sar = wave_sum((double)ar[u]), sai = wave_sum((double)ai[u]);
-        const double sbr = wave_sum((double)br[u]), sbi = wave_sum((double)bi[u]);
-        if (lane == 0 && i0 + u < nv) {
-            const int row = ext ? i0 + u : A.ne + i0 + u;
-            part[(int64_t)chunk * (A.ne + A.ni) + row] = make_double4(sar, sai, sbr, sbi);
+    template <class A, class B> __device__ void msub(const A &a, const B &b)
+    {
+        x -= (R)a.x * b.x - (R)a.y * b.y;
+        y -= (R)a.x * b.y + (R)a.y * b.x;
+    }
+};
+
+// entries (row, col0 .. col0 + CPL - 1) of one operator, zero outside nv x nv
+template <class E, class C, int CPL>
+__device__ inline void ld_cols(const E *M, int64_t ld, int row, int col0, int nv, C (&out)[CPL])
+{
+    using R = decltype(C::x);
+    if constexpr (CPL == 1) {
+        out[0] = C{0, 0};
+        if (row < nv && col0 < nv) {
+            const E e = ld_entry(M + row * ld + col0);
+            out[0] = C{(R)e.x, (R)e.y};
+        }
+    } else {
+        out[0] = out[1] = C{0, 0};
+        if (row < nv && col0 < nv) {   // col0 even and the row stride a multiple of 16: the pair is in the row
+            const float4 e = ld_entry2(M + row * ld + col0);
+            out[0] = C{(R)e.x, (R)e.y};
+            if (col0 + 1 < nv) out[1] = C{(R)e.z, (R)e.w};
         }
     }
 }
 
-// y rows = sum of the chunk partials (fixed order) + mortar coupling; one thread per row
-__global__ __launch_bounds__(256) void mtf_combine_kernel(MtfArgs A, const double2 *__restrict__ x,
-                                                          const double4 *__restrict__ part, double2 *__restrict__ y,
-                                                          const KrylovState *__restrict__ st)
+template <class E, class R>
+__global__ __launch_bounds__(256) void mtf_sym_tile_kernel(MtfArgs A, const double2 *__restrict__ x,
+                                                           double4 *__restrict__ part,
+                                                           const KrylovState *__restrict__ st)
+{
+    using C = typename Cx<R>::T;
+    constexpr int TS = sym_tile<E>(), CPL = TS / 64, RPW = TS / 4;   // tile edge, columns per lane, rows per wave
+    if (st && st->done) return;
+    __shared__ C sva[TS], swa[TS], svb[TS], swb[TS];
+    __shared__ C rowres[3][TS];
+    __shared__ C colres[4][3][TS];
+    int64_t t = blockIdx.x;
+    const int nte = sym_ntile(A.ne, TS), nti = sym_ntile(A.ni, TS);
+    const int64_t te = (int64_t)nte * (nte + 1) / 2;
+    const bool ext = t < te;
+    if (!ext) t -= te;
+    const int nt = ext ? nte : nti;
+    int a, b;
+    sym_pair(t, nt, a, b);
+    const int nv = ext ? A.ne : A.ni;
+    const int mi = ext ? 0 : 1;
+    const E *Vm = static_cast<const E *>(A.op[mi][0]), *Km = static_cast<const E *>(A.op[mi][1]);
+    const E *Dm = static_cast<const E *>(A.op[mi][3]);
+    const int64_t ld = op_ld(nv);
+    const double2 *xv = ext ? x : x + 2 * A.ne, *xw = xv + nv;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const C zero{0, 0};
+    for (int q = tid; q < TS; q += 256) {
+        const int ia = a * TS + q, ib = b * TS + q;
+        sva[q] = ia < nv ? C{(R)xv[ia].x, (R)xv[ia].y} : zero;
+        swa[q] = ia < nv ? C{(R)xw[ia].x, (R)xw[ia].y} : zero;
+        svb[q] = ib < nv ? C{(R)xv[ib].x, (R)xv[ib].y} : zero;
+        swb[q] = ib < nv ? C{(R)xw[ib].x, (R)xw[ib].y} : zero;
+    }
+    __syncthreads();
+    const bool diag = a == b;
+    const int c0 = lane * CPL;                  // this lane's first column inside the tile
+    const int j0 = b * TS + c0, ja0 = a * TS + c0;
+    C vb[CPL], wb[CPL], va[CPL];
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) { vb[u] = svb[c0 + u]; wb[u] = swb[c0 + u]; va[u] = sva[c0 + u]; }
+    CAcc<R> c1b[CPL], c2b[CPL], c2a[CPL];
+#pragma unroll 2
+    for (int rr = 0; rr < RPW; ++rr) {
+        const int r = wave * RPW + rr;
+        const int i = a * TS + r, ib = b * TS + r;
+        C kab[CPL], vab[CPL], dab[CPL], kba[CPL];
+        ld_cols<E, C, CPL>(Km, ld, i, j0, nv, kab);
+        ld_cols<E, C, CPL>(Vm, ld, i, j0, nv, vab);
+        ld_cols<E, C, CPL>(Dm, ld, i, j0, nv, dab);
+        if (!diag) ld_cols<E, C, CPL>(Km, ld, ib, ja0, nv, kba);
+        else
+#pragma unroll
+            for (int u = 0; u < CPL; ++u) kba[u] = zero;
+        const C wi = swa[r], vi = sva[r], wbr = swb[r];
+        CAcc<R> y1, y2, y1b;
+#pragma unroll
+        for (int u = 0; u < CPL; ++u) {
+            const int c = c0 + u;
+            // rows of tile a: y1 -= K v, y1 += V w, y2 += D v (V, D on and above the diagonal)
+            y1.msub(kab[u], vb[u]);
+            if (!diag || c >= r) {
+                y1.mac(vab[u], wb[u]);
+                y2.mac(dab[u], vb[u]);
+            }
+            // rows of tile b (column c): y2 += K^T w; y1 += V^T w, y2 += D^T v strictly above the diagonal
+            c2b[u].mac(kab[u], wi);
+            if (!diag || c > r) {
+                c1b[u].mac(vab[u], wi);
+                c2b[u].mac(dab[u], vi);
+            }
+            // tile (b, a) of K: rows of b: y1 -= K v_a; rows of a (column c): y2 += K^T w_b
+            y1b.msub(kba[u], va[u]);
+            c2a[u].mac(kba[u], wbr);
+        }
+        const R s0 = wsum63(y1.x), s1 = wsum63(y1.y), s2 = wsum63(y2.x), s3 = wsum63(y2.y), s4 = wsum63(y1b.x),
+                s5 = wsum63(y1b.y);
+        if (lane == 63) {
+            rowres[0][r] = C{s0, s1};
+            rowres[1][r] = C{s2, s3};
+            rowres[2][r] = C{s4, s5};
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CPL; ++u) {
+        colres[wave][0][c0 + u] = C{c1b[u].x, c1b[u].y};
+        colres[wave][1][c0 + u] = C{c2b[u].x, c2b[u].y};
+        colres[wave][2][c0 + u] = C{c2a[u].x, c2a[u].y};
+    }
+    __syncthreads();
+    for (int r = tid; r < TS; r += 256) {
+        double c1x = 0, c1y = 0, c2x = 0, c2y = 0, c3x = 0, c3y = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            c1x += (double)colres[w][0][r].x; c1y += (double)colres[w][0][r].y;
+            c2x += (double)colres[w][1][r].x; c2y += (double)colres[w][1][r].y;
+            c3x += (double)colres[w][2][r].x; c3y += (double)colres[w][2][r].y;
+        }
+        const int64_t stride = (int64_t)A.ne + A.ni;
+        const int off = ext ? 0 : A.ne;
+        const int i = a * TS + r, ib = b * TS + r;
+        if (diag) {
+            if (i < nv)
+                part[(int64_t)a * stride + off + i] = make_double4((double)rowres[0][r].x + c1x, (double)rowres[0][r].y + c1y,
+                                                                   (double)rowres[1][r].x + c2x, (double)rowres[1][r].y + c2y);
+        } else {
+            if (i < nv)
+                part[(int64_t)b * stride + off + i] = make_double4((double)rowres[0][r].x, (double)rowres[0][r].y,
+                                                                   (double)rowres[1][r].x + c3x, (double)rowres[1][r].y + c3y);
+            if (ib < nv)
+                part[(int64_t)a * stride + off + ib] = make_double4((double)rowres[2][r].x + c1x, (double)rowres[2][r].y + c1y,
+                                                                    c2x, c2y);
+        }
+    }
+}
+
+// y rows = sum of the tile partials of the row + the near-entry corrections
+// + mortar coupling.  16 lanes per row (one DPP row): each lane takes every
+// 16th term of the three sums, and a fixed reduction tree within the row
+// finishes them (deterministic).
+template <class R> __device__ inline R rsum15(R v)   // sum over the 16 lanes of a DPP row, in lane 15
+{
+    v += dpp_mov<0x111>(v);
+    v += dpp_mov<0x112>(v);
+    v += dpp_mov<0x114>(v);
+    v += dpp_mov<0x118>(v);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void mtf_sym_combine_kernel(MtfArgs A, const double2 *__restrict__ x,
+                                                              const double4 *__restrict__ part,
+                                                              double2 *__restrict__ y,
+                                                              const KrylovState *__restrict__ st)
 {
     if (st && st->done) return;
-    const int row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= A.ne + A.ni) return;
+    const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int l16 = threadIdx.x & 15;
+    const bool live = row < A.ne + A.ni;   // whole DPP rows are live or not: no divergence inside a reduction
     const bool ext = row < A.ne;
-    const int i = ext ? row : row - A.ne;
+    const int mi = ext ? 0 : 1;
+    const int i = live ? (ext ? row : row - A.ne) : 0;
     const int nv = ext ? A.ne : A.ni;
-    double ar = 0, ai = 0, br = 0, bi = 0;
-    const int nch = split_nchunk(nv, A.cw);
-    for (int c = 0; c < nch; ++c) {
-        const double4 q = part[(int64_t)c * (A.ne + A.ni) + row];
-        ar += q.x; ai += q.y; br += q.z; bi += q.w;
+    double ar = 0, ai = 0, br = 0, bi = 0, sr = 0, si = 0, tr = 0, ti = 0;
+    if (live) {
+        const int nt = sym_ntile(nv, A.sym_ts);
+        const int64_t pstride = (int64_t)A.ne + A.ni;
+        for (int c = l16; c < nt; c += 16) {
+            const double4 q = part[(int64_t)c * pstride + row];
+            ar += q.x; ai += q.y; br += q.z; bi += q.w;
+        }
+        const double2 *xm = ext ? x : x + 2 * A.ne;   // this mesh's [v; w]
+        for (int e = A.near_row[mi][i] + l16; e < A.near_row[mi][i + 1]; e += 16) {
+            const int jn = A.near_j[mi][e];
+            const double2 cv = A.corr[mi][3 * e], cd = A.corr[mi][3 * e + 1], ct = A.corr[mi][3 * e + 2];
+            const double2 vj = xm[jn], wj = xm[nv + jn];
+            ar += cv.x * wj.x - cv.y * wj.y; ai += cv.x * wj.y + cv.y * wj.x;
+            br += cd.x * vj.x - cd.y * vj.y + ct.x * wj.x - ct.y * wj.y;
+            bi += cd.x * vj.y + cd.y * vj.x + ct.x * wj.y + ct.y * wj.x;
+        }
+        const int32_t *pp = ext ? A.pei_ptr : A.pie_ptr;
+        const int32_t *pc = ext ? A.pei_col : A.pie_col;
+        const double *pv = ext ? A.pei_val : A.pie_val;
+        const double2 *cvx = ext ? x + 2 * A.ne : x;
+        const int nother = ext ? A.ni : A.ne;
+        const double2 *cwx = cvx + nother;
+        for (int q = pp[i] + l16; q < pp[i + 1]; q += 16) {
+            const double pvq = pv[q];
+            const double2 av = cvx[pc[q]], bw = cwx[pc[q]];
+            sr += pvq * av.x; si += pvq * av.y; tr += pvq * bw.x; ti += pvq * bw.y;
+        }
     }
-    const int32_t *pp = ext ? A.pei_ptr : A.pie_ptr;
-    const int32_t *pc = ext ? A.pei_col : A.pie_col;
-    const double *pv = ext ? A.pei_val : A.pie_val;
-    const double2 *cv = ext ? x + 2 * A.ne : x;
-    const int nother = ext ? A.ni : A.ne;
-    const double2 *cw = cv + nother;
-    const double fv = ext ? A.c_ext_v : A.c_int_v, fw = ext ? A.c_ext_w : A.c_int_w;
-    double sr = 0, si = 0, tr = 0, ti = 0;
-    for (int q = pp[i]; q < pp[i + 1]; ++q) {
-        const double pvq = pv[q];
-        const double2 a = cv[pc[q]], b = cw[pc[q]];
-        sr += pvq * a.x; si += pvq * a.y; tr += pvq * b.x; ti += pvq * b.y;
+    ar = rsum15(ar); ai = rsum15(ai); br = rsum15(br); bi = rsum15(bi);
+    sr = rsum15(sr); si = rsum15(si); tr = rsum15(tr); ti = rsum15(ti);
+    if (live && l16 == 15) {
+        const double fv = ext ? A.c_ext_v : A.c_int_v, fw = ext ? A.c_ext_w : A.c_int_w;
+        double2 *ya = ext ? y : y + 2 * A.ne;
+        ya[i] = make_double2(ar + fv * sr, ai + fv * si);
+        ya[i + nv] = make_double2(br + fw * tr, bi + fw * ti);
     }
-    double2 *ya = ext ? y : y + 2 * A.ne;
-    ya[i] = make_double2(ar + fv * sr, ai + fv * si);
-    ya[i + nv] = make_double2(br + fw * tr, bi + fw * ti);
+}
+
+// corr[e] of every near entry (i, j) of one mesh from the stored operators
+template <class E>
+__global__ void sym_corr_kernel(int nv, int nn, const int32_t *__restrict__ ni_, const int32_t *__restrict__ nj_,
+                                const E *__restrict__ V, const E *__restrict__ K, const E *__restrict__ T,
+                                const E *__restrict__ D, double2 *__restrict__ corr)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nn) return;
+    const int64_t ld = op_ld(nv);
+    const int i = ni_[e], jn = nj_[e];
+    const int64_t o = i * ld + jn, ot = jn * ld + i;
+    double2 cv = make_double2(0, 0), cd = cv;
+    if (jn < i) {
+        cv = make_double2((double)V[o].x - (double)V[ot].x, (double)V[o].y - (double)V[ot].y);
+        cd = make_double2((double)D[o].x - (double)D[ot].x, (double)D[o].y - (double)D[ot].y);
+    }
+    const double2 ct = make_double2((double)T[o].x - (double)K[ot].x, (double)T[o].y - (double)K[ot].y);
+    corr[3 * (int64_t)e] = cv;
+    corr[3 * (int64_t)e + 1] = cd;
+    corr[3 * (int64_t)e + 2] = ct;
+}
+
+bem_status launch_sym_corrections(bem_problem *p, int mesh)
+{
+    const bem_mesh *m = mesh == 0 ? p->ext : p->inte;
+    const int nv = (int)m->h.nv, nn = (int)m->h.near_i.size();
+    bem_status s = dev_alloc(p->ctx, p->corr[mesh], (size_t)std::max(nn, 1) * 3 * sizeof(double2));
+    if (s) return s;
+    if (nn == 0) return BEM_OK;
+    const dim3 g((nn + 255) / 256);
+    if (p->prec == BEM_C128)
+        hipLaunchKernelGGL(sym_corr_kernel<double2>, g, dim3(256), 0, p->ctx->stream, nv, nn, m->d.near_i.as<int32_t>(),
+                           m->d.near_j.as<int32_t>(), p->ops[mesh][0].as<double2>(), p->ops[mesh][1].as<double2>(),
+                           p->ops[mesh][2].as<double2>(), p->ops[mesh][3].as<double2>(), p->corr[mesh].as<double2>());
+    else
+        hipLaunchKernelGGL(sym_corr_kernel<float2>, g, dim3(256), 0, p->ctx->stream, nv, nn, m->d.near_i.as<int32_t>(),
+                           m->d.near_j.as<int32_t>(), p->ops[mesh][0].as<float2>(), p->ops[mesh][1].as<float2>(),
+                           p->ops[mesh][2].as<float2>(), p->ops[mesh][3].as<float2>(), p->corr[mesh].as<double2>());
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
 }
 
 // part[chunk][row] = M^-1 row chunk applied to the mesh's two vectors; the
@@ -1158,7 +1308,6 @@ MtfArgs make_args(const bem_problem *p)
     MtfArgs A;
     A.ne = (int)p->ext->h.nv;
     A.ni = (int)p->inte->h.nv;
-    A.cw = p->prec == BEM_C128 ? SPLIT_CW_MAX : SPLIT_CW32_MAX;
     for (int m = 0; m < 2; ++m)
         for (int o = 0; o < 4; ++o) A.op[m][o] = p->ops[m][o].ptr;
     A.pie_ptr = p->P_ie_ptr.as<int32_t>(); A.pie_col = p->P_ie_col.as<int32_t>(); A.pie_val = p->P_ie_val.as<double>();
@@ -1167,13 +1316,21 @@ MtfArgs make_args(const bem_problem *p)
     A.c_ext_w = 0.5 * p->rho_ext / p->rho_int;
     A.c_int_v = -0.5;
     A.c_int_w = -0.5 * p->rho_int / p->rho_ext;
+    A.sym_ts = p->prec == BEM_C128 ? sym_tile<double2>() : sym_tile<float2>();
+    const bem_mesh *ms[2] = {p->ext, p->inte};
+    for (int m = 0; m < 2; ++m) {
+        A.near_row[m] = ms[m]->d.near_row.as<int32_t>();
+        A.near_j[m] = ms[m]->d.near_j.as<int32_t>();
+        A.corr[m] = p->corr[m].as<double2>();
+    }
     return A;
 }
 
 size_t split_part_bytes(int ne, int ni)
 {
-    return (size_t)std::max(split_nchunk(ne, SPLIT_CW_MIN), split_nchunk(ni, SPLIT_CW_MIN)) * (ne + ni) *
-           sizeof(double4);
+    const int nchunk = std::max({split_nchunk(ne, MASS_CW_MAX), split_nchunk(ni, MASS_CW_MAX), sym_ntile(ne, 64),
+                                 sym_ntile(ni, 64)});
+    return (size_t)nchunk * (ne + ni) * sizeof(double4);
 }
 
 // z = blockdiag(M_e, M_e, M_i, M_i)^-1 y
@@ -1202,18 +1359,18 @@ bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, dou
 {
     hipStream_t st = p->ctx->stream;
     const int rows = A.ne + A.ni;
+    const int nte = sym_ntile(A.ne, A.sym_ts), nti = sym_ntile(A.ni, A.sym_ts);
+    const dim3 g((unsigned)((int64_t)nte * (nte + 1) / 2 + (int64_t)nti * (nti + 1) / 2));
     {
         KTimer kt(p->ctx, K_MTF_DENSE);
         if (p->prec == BEM_C128)
-            launch_k(kt, mtf_dense_part_kernel, split_grid(A.ne, A.ni, A.cw), dim3(256), 0, st, A, x, part, kst);
+            launch_k(kt, mtf_sym_tile_kernel<double2, double>, g, dim3(256), 0, st, A, x, part, kst);
         else if (acc64)
-            launch_k(kt, mtf_dense_c64_part_kernel<double>, split_grid(A.ne, A.ni, A.cw, DENSE32_RW), dim3(256), 0,
-                     st, A, x, part, kst);
+            launch_k(kt, mtf_sym_tile_kernel<float2, double>, g, dim3(256), 0, st, A, x, part, kst);
         else
-            launch_k(kt, mtf_dense_c64_part_kernel<float>, split_grid(A.ne, A.ni, A.cw, DENSE32_RW), dim3(256), 0,
-                     st, A, x, part, kst);
+            launch_k(kt, mtf_sym_tile_kernel<float2, float>, g, dim3(256), 0, st, A, x, part, kst);
     }
-    hipLaunchKernelGGL(mtf_combine_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, A, x, part, y, kst);
+    hipLaunchKernelGGL(mtf_sym_combine_kernel, dim3((rows + 15) / 16), dim3(256), 0, st, A, x, part, y, kst);
     BEM_HIP(hipGetLastError());
     if (strong) return apply_Minv(p, y, z, part, kst);
     return BEM_OK;
