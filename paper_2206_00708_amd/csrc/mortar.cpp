@@ -13,16 +13,66 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <thread>
 
 #include "internal.h"
 
 namespace bemtx {
 
+// CSR from row-grouped entries: ent[ptr[i], ptr[i + 1]) are the entries of
+// row i in generation order.  Duplicate columns are summed in that order
+// (first occurrence first), then the distinct columns of a row are sorted.
+// Rows are independent and split over the host workers.
+static void rows_to_csr(int64_t nrows, int64_t ncols, const std::vector<int32_t> &ptr,
+                        std::vector<std::pair<int32_t, double>> &ent, Csr &A)
+{
+    std::vector<int32_t> ucnt(nrows, 0);
+    parallel_for(nrows, 64, [&](int64_t r0, int64_t r1) {
+        std::vector<int32_t> mark(ncols, -1), pos(ncols, 0);
+        for (int64_t i = r0; i < r1; ++i) {
+            auto *e = ent.data() + ptr[i];
+            const int32_t n = ptr[i + 1] - ptr[i];
+            int32_t m = 0;
+            for (int32_t q = 0; q < n; ++q) {
+                const int32_t c = e[q].first;
+                if (mark[c] != (int32_t)i) {
+                    mark[c] = (int32_t)i;
+                    pos[c] = m;
+                    e[m++] = e[q];
+                } else {
+                    e[pos[c]].second += e[q].second;
+                }
+            }
+            std::sort(e, e + m, [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
+                return x.first < y.first;
+            });
+            ucnt[i] = m;
+        }
+    });
+    A.nrows = nrows;
+    A.ncols = ncols;
+    A.ptr.assign(nrows + 1, 0);
+    for (int64_t i = 0; i < nrows; ++i) A.ptr[i + 1] = A.ptr[i] + ucnt[i];
+    A.col.resize(A.ptr[nrows]);
+    A.val.resize(A.ptr[nrows]);
+    parallel_for(nrows, 256, [&](int64_t r0, int64_t r1) {
+        for (int64_t i = r0; i < r1; ++i)
+            for (int32_t q = 0; q < ucnt[i]; ++q) {
+                A.col[A.ptr[i] + q] = ent[ptr[i] + q].first;
+                A.val[A.ptr[i] + q] = ent[ptr[i] + q].second;
+            }
+    });
+}
+
 void mass_csr(const MeshData &m, Csr &M)
 {
     const int64_t nv = m.nv, nt = m.nt;
-    std::vector<std::vector<std::pair<int32_t, double>>> rows(nv);
+    // entries of row v[i] in triangle order: (v[j], |t| (1 + [i == j]) / 12)
+    std::vector<int32_t> ptr(nv + 1, 0);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int i = 0; i < 3; ++i) ptr[m.tri[3 * t + i] + 1] += 3;
+    for (int64_t i = 0; i < nv; ++i) ptr[i + 1] += ptr[i];
+    std::vector<std::pair<int32_t, double>> ent(ptr[nv]);
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
     for (int64_t t = 0; t < nt; ++t) {
         const int32_t *v = &m.tri[3 * t];
         const double *p0 = &m.xyz[3 * v[0]], *p1 = &m.xyz[3 * v[1]], *p2 = &m.xyz[3 * v[2]];
@@ -31,25 +81,9 @@ void mass_csr(const MeshData &m, Csr &M)
         double c[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
         double area = 0.5 * std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
         for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) rows[v[i]].push_back({v[j], area * (i == j ? 2.0 : 1.0) / 12.0});
+            for (int j = 0; j < 3; ++j) ent[fill[v[i]]++] = {v[j], area * (i == j ? 2.0 : 1.0) / 12.0};
     }
-    M.nrows = M.ncols = nv;
-    M.ptr.assign(nv + 1, 0);
-    M.col.clear();
-    M.val.clear();
-    for (int64_t i = 0; i < nv; ++i) {
-        auto &r = rows[i];
-        std::stable_sort(r.begin(), r.end(), [](auto &x, auto &y) { return x.first < y.first; });
-        for (size_t q = 0; q < r.size(); ++q) {
-            if (q > 0 && r[q].first == r[q - 1].first) {
-                M.val.back() += r[q].second;
-            } else {
-                M.col.push_back(r[q].first);
-                M.val.push_back(r[q].second);
-            }
-        }
-        M.ptr[i + 1] = (int32_t)M.col.size();
-    }
+    rows_to_csr(nv, nv, ptr, ent, M);
 }
 
 void transpose_csr(const Csr &A, Csr &At)
@@ -168,125 +202,135 @@ bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *co
         grid[((size_t)cidx(ci[3 * t]) * ncell + cidx(ci[3 * t + 1])) * ncell + cidx(ci[3 * t + 2])].push_back((int32_t)t);
 
     // per exterior facet: (interior triangle, 3x3 block) contributions, facets split over host threads
-    struct Contrib { int32_t ti; double blk[3][3]; };
-    std::vector<std::vector<Contrib>> per_facet(nte);
+    // (contiguous facet chunks, so the concatenation of the chunk lists is in facet order)
+    struct Contrib { int32_t ti, te; double blk[3][3]; };
+    const int64_t nchunk = std::min<int64_t>(nte, 256);
+    std::vector<std::vector<Contrib>> per_chunk(nchunk);
     std::vector<double> defect(nte, 0.0);
-    auto work = [&](int64_t te_begin, int64_t te_end) {
-        for (int64_t te = te_begin; te < te_end; ++te) {
-            const int32_t *ve = &me.tri[3 * te];
-            Facet F = make_facet(&me.xyz[3 * ve[0]], &me.xyz[3 * ve[1]], &me.xyz[3 * ve[2]]);
-            double scale = std::fabs(F.v[1].x) + std::fabs(F.v[2].x) + std::fabs(F.v[2].y);
-            double tol = 1e-12 * scale * scale;
-            double plane = dot(F.n, F.o);
-            double covered = 0.0;
-            int gx = cidx(ce[3 * te]), gy = cidx(ce[3 * te + 1]), gz = cidx(ce[3 * te + 2]);
-            for (int dx = -1; dx <= 1; ++dx)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dz = -1; dz <= 1; ++dz) {
-                        int x = gx + dx, y = gy + dy, z = gz + dz;
-                        if (x < 0 || y < 0 || z < 0 || x >= ncell || y >= ncell || z >= ncell) continue;
-                        for (int32_t ti : grid[((size_t)x * ncell + y) * ncell + z]) {
-                            double d2 = 0;
-                            for (int k = 0; k < 3; ++k) d2 += (ci[3 * ti + k] - ce[3 * te + k]) * (ci[3 * ti + k] - ce[3 * te + k]);
-                            if (std::sqrt(d2) > (ri[ti] + re[te]) * 1.0001 + 1e-12) continue;
-                            const int32_t *vi = &mi.tri[3 * ti];
-                            V2 S[3];
-                            bool ok = true;
-                            for (int a = 0; a < 3; ++a) {
-                                const double *p = &mi.xyz[3 * vi[a]];
-                                double den = dot(F.n, p);
-                                if (!(den > 0.0)) { ok = false; break; }
-                                double sc = plane / den;
-                                double q[3] = {sc * p[0] - F.o[0], sc * p[1] - F.o[1], sc * p[2] - F.o[2]};
-                                S[a] = {dot(q, F.e1), dot(q, F.e2)};
-                            }
-                            if (!ok || orient(S[0], S[1], S[2]) <= 0.0) continue;
-                            // exterior facet clipped by the three edges of the projected interior triangle
-                            V2 poly[12], tmp[12];
-                            int n = 3;
-                            for (int a = 0; a < 3; ++a) poly[a] = F.v[a];
-                            for (int a = 0; a < 3 && n >= 3; ++a) {
-                                n = keep_left(poly, n, S[a], S[(a + 1) % 3], tol, tmp);
-                                std::memcpy(poly, tmp, n * sizeof(V2));
-                            }
-                            if (n < 3) continue;
-                            double apoly = 0.0;
-                            for (int k = 1; k + 1 < n; ++k) apoly += 0.5 * orient(poly[0], poly[k], poly[k + 1]);
-                            if (apoly < 1e-14 * F.area) continue;
-                            covered += apoly;
-                            Contrib c;
-                            c.ti = ti;
-                            std::memset(c.blk, 0, sizeof c.blk);
-                            for (int k = 1; k + 1 < n; ++k) {
-                                V2 A = poly[0], B = poly[k], C = poly[k + 1];
-                                double at = 0.5 * orient(A, B, C);
-                                // 3-point interior rule, exact for quadratics
-                                const double w1 = 2.0 / 3.0, w2 = 1.0 / 6.0;
-                                const double L[3][3] = {{w1, w2, w2}, {w2, w1, w2}, {w2, w2, w1}};
-                                for (int g = 0; g < 3; ++g) {
-                                    V2 q = {L[g][0] * A.x + L[g][1] * B.x + L[g][2] * C.x,
-                                            L[g][0] * A.y + L[g][1] * B.y + L[g][2] * C.y};
-                                    double li[3], le[3];
-                                    bary(S[0], S[1], S[2], q, li);
-                                    bary(F.v[0], F.v[1], F.v[2], q, le);
-                                    for (int a = 0; a < 3; ++a)
-                                        for (int b = 0; b < 3; ++b) c.blk[a][b] += at / 3.0 * li[a] * le[b];
+    auto work = [&](int64_t c0, int64_t c1) {
+        for (int64_t ch = c0; ch < c1; ++ch) {
+            std::vector<Contrib> &out = per_chunk[ch];
+            for (int64_t te = nte * ch / nchunk; te < nte * (ch + 1) / nchunk; ++te) {
+                const int32_t *ve = &me.tri[3 * te];
+                Facet F = make_facet(&me.xyz[3 * ve[0]], &me.xyz[3 * ve[1]], &me.xyz[3 * ve[2]]);
+                double scale = std::fabs(F.v[1].x) + std::fabs(F.v[2].x) + std::fabs(F.v[2].y);
+                double tol = 1e-12 * scale * scale;
+                double plane = dot(F.n, F.o);
+                double covered = 0.0;
+                int gx = cidx(ce[3 * te]), gy = cidx(ce[3 * te + 1]), gz = cidx(ce[3 * te + 2]);
+                for (int dx = -1; dx <= 1; ++dx)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dz = -1; dz <= 1; ++dz) {
+                            int x = gx + dx, y = gy + dy, z = gz + dz;
+                            if (x < 0 || y < 0 || z < 0 || x >= ncell || y >= ncell || z >= ncell) continue;
+                            for (int32_t ti : grid[((size_t)x * ncell + y) * ncell + z]) {
+                                double d2 = 0;
+                                for (int k = 0; k < 3; ++k) d2 += (ci[3 * ti + k] - ce[3 * te + k]) * (ci[3 * ti + k] - ce[3 * te + k]);
+                                if (std::sqrt(d2) > (ri[ti] + re[te]) * 1.0001 + 1e-12) continue;
+                                const int32_t *vi = &mi.tri[3 * ti];
+                                V2 S[3];
+                                bool ok = true;
+                                for (int a = 0; a < 3; ++a) {
+                                    const double *p = &mi.xyz[3 * vi[a]];
+                                    double den = dot(F.n, p);
+                                    if (!(den > 0.0)) { ok = false; break; }
+                                    double sc = plane / den;
+                                    double q[3] = {sc * p[0] - F.o[0], sc * p[1] - F.o[1], sc * p[2] - F.o[2]};
+                                    S[a] = {dot(q, F.e1), dot(q, F.e2)};
                                 }
+                                if (!ok || orient(S[0], S[1], S[2]) <= 0.0) continue;
+                                // exterior facet clipped by the three edges of the projected interior triangle
+                                V2 poly[12], tmp[12];
+                                int n = 3;
+                                for (int a = 0; a < 3; ++a) poly[a] = F.v[a];
+                                for (int a = 0; a < 3 && n >= 3; ++a) {
+                                    n = keep_left(poly, n, S[a], S[(a + 1) % 3], tol, tmp);
+                                    std::memcpy(poly, tmp, n * sizeof(V2));
+                                }
+                                if (n < 3) continue;
+                                double apoly = 0.0;
+                                for (int k = 1; k + 1 < n; ++k) apoly += 0.5 * orient(poly[0], poly[k], poly[k + 1]);
+                                if (apoly < 1e-14 * F.area) continue;
+                                covered += apoly;
+                                Contrib c;
+                                c.ti = ti;
+                                c.te = (int32_t)te;
+                                std::memset(c.blk, 0, sizeof c.blk);
+                                for (int k = 1; k + 1 < n; ++k) {
+                                    V2 A = poly[0], B = poly[k], C = poly[k + 1];
+                                    double at = 0.5 * orient(A, B, C);
+                                    // 3-point interior rule, exact for quadratics
+                                    const double w1 = 2.0 / 3.0, w2 = 1.0 / 6.0;
+                                    const double L[3][3] = {{w1, w2, w2}, {w2, w1, w2}, {w2, w2, w1}};
+                                    for (int g = 0; g < 3; ++g) {
+                                        V2 q = {L[g][0] * A.x + L[g][1] * B.x + L[g][2] * C.x,
+                                                L[g][0] * A.y + L[g][1] * B.y + L[g][2] * C.y};
+                                        double li[3], le[3];
+                                        bary(S[0], S[1], S[2], q, li);
+                                        bary(F.v[0], F.v[1], F.v[2], q, le);
+                                        for (int a = 0; a < 3; ++a)
+                                            for (int b = 0; b < 3; ++b) c.blk[a][b] += at / 3.0 * li[a] * le[b];
+                                    }
+                                }
+                                out.push_back(c);
                             }
-                            per_facet[te].push_back(c);
                         }
-                    }
-            defect[te] = std::fabs(covered - F.area) / F.area;
+                defect[te] = std::fabs(covered - F.area) / F.area;
+            }
         }
     };
-    {
-        unsigned hw = std::thread::hardware_concurrency();
-        int nth = (int)std::max(1u, std::min(16u, hw ? hw : 1u));
-        if (nte < 256) nth = 1;
-        std::vector<std::thread> pool;
-        for (int t = 0; t < nth; ++t)
-            pool.emplace_back(work, nte * t / nth, nte * (t + 1) / nth);
-        for (auto &th : pool) th.join();
-    }
+    parallel_for(nchunk, 1, work);
     double worst = 0.0;
     for (double d : defect) worst = std::max(worst, d);
     if (coverage_defect) *coverage_defect = worst;
-    // COO in facet order -> rows by counting sort -> columns by stable sort, duplicates summed in order
-    std::vector<int32_t> cnt(mi.nv + 1, 0);
-    for (int64_t te = 0; te < nte; ++te)
-        for (const Contrib &c : per_facet[te])
-            for (int a = 0; a < 3; ++a) cnt[mi.tri[3 * c.ti + a] + 1] += 3;
-    for (int64_t i = 0; i < mi.nv; ++i) cnt[i + 1] += cnt[i];
-    std::vector<std::pair<int32_t, double>> ent(cnt[mi.nv]);
+    // entries grouped by interior row, each row in facet order, then CSR.
+    // Contributions are numbered in facet order and listed per interior
+    // triangle; a row gathers the lists of the triangles around its vertex and
+    // sorts them by that number, so rows fill independently.
+    std::vector<const Contrib *> all;
+    for (const auto &chunk : per_chunk)
+        for (const Contrib &c : chunk) all.push_back(&c);
+    const int64_t ncon = (int64_t)all.size();
+    std::vector<int32_t> tptr(nti + 1, 0), tcon(ncon);
+    for (const Contrib *c : all) tptr[c->ti + 1]++;
+    for (int64_t t = 0; t < nti; ++t) tptr[t + 1] += tptr[t];
     {
-        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
-        for (int64_t te = 0; te < nte; ++te)
-            for (const Contrib &c : per_facet[te])
-                for (int a = 0; a < 3; ++a) {
-                    const int32_t i = mi.tri[3 * c.ti + a];
-                    for (int b = 0; b < 3; ++b) ent[fill[i]++] = {me.tri[3 * te + b], c.blk[a][b]};
-                }
+        std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+        for (int64_t k = 0; k < ncon; ++k) tcon[fill[all[k]->ti]++] = (int32_t)k;
     }
-    P.nrows = mi.nv;
-    P.ncols = me.nv;
-    P.ptr.assign(mi.nv + 1, 0);
-    P.col.clear();
-    P.val.clear();
+    // triangles around each interior vertex
+    std::vector<int32_t> vptr(mi.nv + 1, 0), vtri(3 * nti);
+    for (int64_t t = 0; t < nti; ++t)
+        for (int a = 0; a < 3; ++a) vptr[mi.tri[3 * t + a] + 1]++;
+    for (int64_t i = 0; i < mi.nv; ++i) vptr[i + 1] += vptr[i];
+    {
+        std::vector<int32_t> fill(vptr.begin(), vptr.end() - 1);
+        for (int64_t t = 0; t < nti; ++t)
+            for (int a = 0; a < 3; ++a) vtri[fill[mi.tri[3 * t + a]]++] = (int32_t)t;
+    }
+    std::vector<int32_t> cnt(mi.nv + 1, 0);
     for (int64_t i = 0; i < mi.nv; ++i) {
-        auto b0 = ent.begin() + cnt[i], b1 = ent.begin() + cnt[i + 1];
-        std::stable_sort(b0, b1, [](const std::pair<int32_t, double> &x, const std::pair<int32_t, double> &y) {
-            return x.first < y.first;
-        });
-        for (auto it = b0; it != b1; ++it) {
-            if (it != b0 && it->first == (it - 1)->first) {
-                P.val.back() += it->second;
-            } else {
-                P.col.push_back(it->first);
-                P.val.push_back(it->second);
+        int32_t n = 0;
+        for (int32_t q = vptr[i]; q < vptr[i + 1]; ++q) n += tptr[vtri[q] + 1] - tptr[vtri[q]];
+        cnt[i + 1] = cnt[i] + 3 * n;
+    }
+    std::vector<std::pair<int32_t, double>> ent(cnt[mi.nv]);
+    parallel_for(mi.nv, 64, [&](int64_t r0, int64_t r1) {
+        std::vector<int32_t> ks;
+        for (int64_t i = r0; i < r1; ++i) {
+            ks.clear();
+            for (int32_t q = vptr[i]; q < vptr[i + 1]; ++q)
+                for (int32_t u = tptr[vtri[q]]; u < tptr[vtri[q] + 1]; ++u) ks.push_back(tcon[u]);
+            std::sort(ks.begin(), ks.end());
+            int32_t w = cnt[i];
+            for (int32_t k : ks) {
+                const Contrib &c = *all[k];
+                const int a = mi.tri[3 * c.ti] == i ? 0 : mi.tri[3 * c.ti + 1] == i ? 1 : 2;
+                for (int b = 0; b < 3; ++b) ent[w++] = {me.tri[3 * c.te + b], c.blk[a][b]};
             }
         }
-        P.ptr[i + 1] = (int32_t)P.col.size();
-    }
+    });
+    rows_to_csr(mi.nv, me.nv, cnt, ent, P);
     if (worst > 1e-6)
         return set_error(BEM_E_MESH_MISMATCH, "projected interior mesh leaves an exterior facet uncovered (relative defect " +
                                                   std::to_string(worst) + ")");
