@@ -121,9 +121,11 @@ bem_status bem_ctx_trim(bem_ctx *ctx);
 
 /* Per-kernel device time.  Kernels, by bit index: 0 "regular_tiles",
  * 1 "gather_tiles", 2 "singular_pairs", 3 "near_scatter", 4 "mtf_dense",
- * 5 "mass_apply", 6 "cgs_dots", 7 "cgs_update", 8 "arnoldi_finish",
- * 9 "mass_inverse", 10 "block_gemm" (multi-RHS operator product), 11
- * "mass_gemm" (multi-RHS inverse-mass product).  Every launch of a kernel whose bit is set in
+ * 5 "mass_apply", 6 "cgs_dots" (Gram-Schmidt dot products), 7 "cgs_update"
+ * (Gram-Schmidt update), 8 "arnoldi_finish" (Hessenberg column, Givens
+ * rotation, residual estimate), 9 "mass_inverse", 10 "block_gemm"
+ * (multi-RHS operator product), 11 "mass_gemm" (multi-RHS inverse-mass
+ * product), 12 "krylov_normalize" (new Krylov vector scaled to unit norm).  Every launch of a kernel whose bit is set in
  * kernel_mask is bracketed by HIP events on the context stream (a few
  * microseconds of overhead per launch); 0 disables.  Setting the mask resets
  * the totals.  bem_ctx_kernel_time synchronises the stream and returns the
@@ -153,7 +155,7 @@ bem_status bem_problem_create(bem_ctx *ctx, const bem_mesh *ext, const bem_mesh 
 void bem_problem_destroy(bem_problem *p);
 
 /* Device bytes the problem needs with `nrhs` right-hand sides and `maxit`
- * Krylov steps (operators, projections, Krylov bases and triangular factors,
+ * Krylov steps (operators, projections, Krylov bases, Hessenberg and triangular factors,
  * assembly scratch; for BEM_C64_MIXED problems all nrhs runs advancing
  * together, up to 64, with the buffers of the matrix-core products); for
  * admission control.  May be called before assembly. */

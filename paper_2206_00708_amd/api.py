@@ -50,7 +50,8 @@ class Context:
         _check(N.load().bem_ctx_trim(self._h))
 
     KERNELS = ("regular_tiles", "gather_tiles", "singular_pairs", "near_scatter", "mtf_dense", "mass_apply",
-               "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse", "block_gemm", "mass_gemm")
+               "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse", "block_gemm", "mass_gemm",
+               "krylov_normalize")
 
     def set_kernel_timing(self, kernels=()):
         """Time every launch of the named kernels with HIP events (empty: off)."""

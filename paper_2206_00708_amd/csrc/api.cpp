@@ -83,7 +83,7 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, v
 
 const char *const kKernelNames[K_COUNT] = {"regular_tiles", "gather_tiles", "singular_pairs", "near_scatter",
                                            "mtf_dense", "mass_apply", "cgs_dots", "cgs_update", "arnoldi_finish",
-                                           "mass_inverse", "block_gemm", "mass_gemm"};
+                                           "mass_inverse", "block_gemm", "mass_gemm", "krylov_normalize"};
 
 static hipEvent_t take_event(bem_ctx *c)
 {
@@ -341,7 +341,8 @@ bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t max
     // runs that advance together: every right-hand side of a complex64 problem (up to 64 per block), else one
     const size_t R = p->prec == BEM_C64_MIXED ? (size_t)std::min(nrhs, 64) : 1;
     b += R * ((size_t)(maxit + 1) * n + 8 * n) * sizeof(double2);                 // Krylov bases + work vectors
-    b += R * (size_t)maxit * (maxit + 1) * sizeof(double2);                       // triangular factors
+    b += 2 * R * (size_t)maxit * (maxit + 1) * sizeof(double2);                   // Hessenberg matrices, triangular factors
+    b += R * ((n + 1023) / 1024) * 2 * (size_t)(maxit + 1) * sizeof(double2);     // Gram-Schmidt partial dot products
     if (R > 1) {   // right-hand matrices and K-chunk partials of the matrix-core products
         const size_t kop = 2 * (op_ld(ne) + op_ld(ni)), km = ((ne + 31) & ~size_t(31)) + ((ni + 31) & ~size_t(31));
         b += (2 * 128 * kop + 256 * km) * sizeof(float);

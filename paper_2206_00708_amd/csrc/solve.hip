@@ -417,11 +417,12 @@ struct KrylovState {
 struct KBatch {
     int64_t basis;     // Krylov basis: (m + 1) n
     int64_t vec;       // work vector: n
-    int64_t partial;   // CGS partial dot products: nchunk (m + 1)
-    int64_t small;     // h sums and g: m + 1
+    int64_t partial;   // partial dot products: nchunk 2 (m + 1)
+    int64_t small;     // pending Hessenberg column and g: m + 1
     int64_t npart;     // norm partials: row blocks
-    int64_t hess;      // triangular factor: m (m + 1)
+    int64_t hess;      // triangular factor, and the Hessenberg matrix: m (m + 1)
     int64_t rot;       // Givens cosines and sines: m
+    int64_t coef;      // Gram-Schmidt coefficients of the step: 2 m + 4
 };
 
 
@@ -548,24 +549,23 @@ template <class R> struct CAcc {   // complex accumulator in the arithmetic type
     }
 };
 
-// entries (row, col0 .. col0 + CPL - 1) of one operator, zero outside nv x nv
+// entries (row, col0 .. col0 + CPL - 1) of one operator, zero outside nv x nv.
+// Branch-free: an entry outside the matrix is loaded from a valid address
+// (row and column clamped) and replaced by zero, so the loads of a row issue
+// back to back and the compiler can count them in flight.
 template <class E, class C, int CPL>
 __device__ inline void ld_cols(const E *M, int64_t ld, int row, int col0, int nv, C (&out)[CPL])
 {
     using R = decltype(C::x);
+    const bool ok = row < nv && col0 < nv;
+    const E *p = M + (int64_t)min(row, nv - 1) * ld + (col0 < nv ? col0 : 0);
     if constexpr (CPL == 1) {
-        out[0] = C{0, 0};
-        if (row < nv && col0 < nv) {
-            const E e = ld_entry(M + row * ld + col0);
-            out[0] = C{(R)e.x, (R)e.y};
-        }
-    } else {
-        out[0] = out[1] = C{0, 0};
-        if (row < nv && col0 < nv) {   // col0 even and the row stride a multiple of 16: the pair is in the row
-            const float4 e = ld_entry2(M + row * ld + col0);
-            out[0] = C{(R)e.x, (R)e.y};
-            if (col0 + 1 < nv) out[1] = C{(R)e.z, (R)e.w};
-        }
+        const E e = ld_entry(p);
+        out[0] = ok ? C{(R)e.x, (R)e.y} : C{0, 0};
+    } else {   // col0 even and the row stride a multiple of 16: the pair is in the row
+        const float4 e = ld_entry2(p);
+        out[0] = ok ? C{(R)e.x, (R)e.y} : C{0, 0};
+        out[1] = ok && col0 + 1 < nv ? C{(R)e.z, (R)e.w} : C{0, 0};
     }
 }
 
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(256) void mtf_sym_tile_kernel(MtfArgs A, const doub
 #pragma unroll
     for (int u = 0; u < CPL; ++u) { vb[u] = svb[c0 + u]; wb[u] = swb[c0 + u]; va[u] = sva[c0 + u]; }
     CAcc<R> c1b[CPL], c2b[CPL], c2a[CPL];
-#pragma unroll 2
+#pragma unroll 1
     for (int rr = 0; rr < RPW; ++rr) {
         const int r = wave * RPW + rr;
         const int i = a * TS + r, ib = b * TS + r;
@@ -894,20 +894,40 @@ static inline dim3 split_grid(int ne, int ni, int cwmax, int rw = 1)
 
 // ------------------------------------------------------ Krylov kernels
 //
-// One Arnoldi step j of GMRES on z = M^-1 A v_j, without a host round trip:
-//   dots(pass 0) -> update(pass 0) -> dots(pass 1) -> update(pass 1, partial
-//   norms) -> arnoldi_finish (beta, v_{j+1} = w / beta, and in block 0 the
-//   Givens rotations of the new Hessenberg column and the residual estimate).
-// Every kernel returns at once when the state says the iteration has
-// converged, so steps issued ahead of the host's convergence check cost only
-// their launch.
+// Arnoldi (Sec. 5.1: GMRES without restart) with classical Gram-Schmidt and
+// a re-orthogonalisation delayed by one step (the DCGS2 scheme of
+// Swirydowicz et al., 2021, and Bielich et al., 2022): every new vector is
+// orthogonalised twice, as in CGS2, but the second pass of step j shares
+// its sweeps over the basis with the first pass of step j + 1, so a step
+// reads the basis twice instead of four times.  Step j, V = v_0 .. v_{j-1}:
+//   slot j of the basis holds u_j (one Gram-Schmidt pass, unit norm) and
+//   w = M^-1 A u_j;
+//   dots:      a = V^H u_j, alpha = |u_j|^2, b = V^H w, gamma = u_j^H w;
+//   hess:      nu = sqrt(alpha - |a|^2), so that v_j = (u_j - V a) / nu;
+//              the pending column j-1 of the Hessenberg matrix becomes
+//              h_{j-1} + beta_{j-1} a over the subdiagonal beta_{j-1} nu
+//              (because u_j = nu v_j + V a), then its Givens rotation and the
+//              residual estimate of the j-dimensional space;
+//              c_j = (gamma - a^H b) / nu = v_j^H w;
+//   update:    v_j into slot j and y = w - V b - v_j c_j into slot j+1;
+//              since w = nu M^-1 A v_j + M^-1 A V a and M^-1 A V = [V v_j] Hbar,
+//              M^-1 A v_j = [V v_j] h_j + y / nu with the pending column
+//              h_j = ([b; c_j] - Hbar a) / nu, formed by extra waves;
+//   normalise: u_{j+1} = y / |y| and beta_j = |y| / nu.
+// The residual estimate of dimension j appears in step j (one operator
+// product after the one that made the space).  Sums run in a fixed order;
+// every kernel returns at once when the state says the run has converged, so
+// steps issued ahead of the host's convergence check cost only their launch.
 
 constexpr int CGS_CHUNK = 1024;   // rows per partial dot product
+constexpr int UPD_ROWS = 64;      // rows per workgroup of the update sweep
 constexpr int MAXIT_CAP = 3000;   // Hessenberg column, rotations and g staged in LDS
 
-// partial[chunk][c] = sum over the rows of `chunk` of conj(Vb[c][r]) w[r];
-// one wave per (chunk, c): grid (nchunk, ceil(nvec / 4), runs), 4 waves per block.
-__global__ __launch_bounds__(256) void cgs_dots_kernel(int n, int nvec, const double2 *__restrict__ Vb,
+// partial[chunk][c] = sum over the chunk's rows of conj(V_c) u_j and
+// partial[chunk][j + 1 + c] = that of conj(V_c) w, for c = 0..j (slot j is
+// u_j itself: alpha and gamma).  One wave per (chunk, c); grid (nchunk,
+// ceil((j + 1) / 4), runs).
+__global__ __launch_bounds__(256) void dgs_dots_kernel(int n, int j, const double2 *__restrict__ Vb,
                                                        const double2 *__restrict__ w, double2 *__restrict__ partial,
                                                        const KrylovState *__restrict__ st, KBatch B)
 {
@@ -918,62 +938,239 @@ __global__ __launch_bounds__(256) void cgs_dots_kernel(int n, int nvec, const do
     partial += run * B.partial;
     const int lane = threadIdx.x & 63;
     const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (c >= nvec) return;
+    if (c > j) return;
     const int r0 = blockIdx.x * CGS_CHUNK, r1 = min(n, r0 + CGS_CHUNK);
-    const double2 *vc = Vb + (int64_t)c * n;
-    double sr = 0, si = 0;
+    const double2 *vc = Vb + (int64_t)c * n, *u = Vb + (int64_t)j * n;
+    double ur = 0, ui = 0, wr = 0, wi = 0;
     for (int r = r0 + lane; r < r1; r += 64) {
-        const double2 a = vc[r], b = w[r];
-        sr += a.x * b.x + a.y * b.y;
-        si += a.x * b.y - a.y * b.x;
+        const double2 a = vc[r], x = u[r], y = w[r];
+        ur += a.x * x.x + a.y * x.y;
+        ui += a.x * x.y - a.y * x.x;
+        wr += a.x * y.x + a.y * y.y;
+        wi += a.x * y.y - a.y * y.x;
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) partial[(int64_t)blockIdx.x * nvec + c] = make_double2(sr, si);
+    ur = wave_sum(ur);
+    ui = wave_sum(ui);
+    wr = wave_sum(wr);
+    wi = wave_sum(wi);
+    if (lane == 0) {
+        double2 *pc = partial + (int64_t)blockIdx.x * 2 * (j + 1);
+        pc[c] = make_double2(ur, ui);
+        pc[j + 1 + c] = make_double2(wr, wi);
+    }
 }
 
-// h = sum of the partials (fixed order); w -= Vb h; hsum = h (pass 0) or
-// hsum += h (pass 1, which also writes the partial squared norms of w).
-// Grid (row blocks, runs).
-__global__ __launch_bounds__(256) void cgs_update_kernel(int n, int nvec, int nchunk, const double2 *__restrict__ Vb,
-                                                         const double2 *__restrict__ partial, double2 *__restrict__ w,
-                                                         double2 *__restrict__ hsum, int pass, double *__restrict__ npart,
-                                                         const KrylovState *__restrict__ st, KBatch B)
+__device__ inline double2 cconj_mul(double2 a, double2 b)   // conj(a) * b
+{
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Sums of the partials into coef ([0, j) a, [j] alpha, [j + 1, 2j + 1) b,
+// [2j + 1] gamma); nu; the final column j - 1 of the Hessenberg matrix
+// (kept row-major in H, row stride m) and, by thread 0, its Givens rotation,
+// g and the residual estimate; then coef[j] = (1 / nu, nu) and coef[2j + 1] =
+// c_j for the update.  coef[2m + 3] holds beta_{j-1}.  One workgroup per run.
+__global__ __launch_bounds__(256) void dgs_hess_kernel(int j, int m, int nchunk, const double2 *__restrict__ partial,
+                                                       double2 *__restrict__ coef, const double2 *__restrict__ hsum,
+                                                       double2 *__restrict__ H, double2 *__restrict__ R,
+                                                       double2 *__restrict__ g, double2 *__restrict__ cs,
+                                                       double2 *__restrict__ sn, KrylovState *__restrict__ st, KBatch B)
+{
+    const int run = blockIdx.x;
+    st += run;
+    if (st->done) return;
+    partial += run * B.partial;
+    coef += run * B.coef;
+    hsum += run * B.small;
+    H += run * B.hess;
+    R += run * B.hess;
+    g += run * B.small;
+    cs += run * B.rot;
+    sn += run * B.rot;
+    const int tid = threadIdx.x, nk = 2 * (j + 1);
+    for (int k = tid; k < nk; k += 256) {
+        double2 sum = make_double2(0, 0);
+        for (int c = 0; c < nchunk; ++c) sum = cadd(sum, partial[(int64_t)c * nk + k]);
+        coef[k] = sum;
+    }
+    __syncthreads();
+    __shared__ double red[3][4];
+    double aa = 0, abr = 0, abi = 0;
+    for (int k = tid; k < j; k += 256) {
+        const double2 a = coef[k], b = coef[j + 1 + k];
+        aa += a.x * a.x + a.y * a.y;
+        abr += a.x * b.x + a.y * b.y;
+        abi += a.x * b.y - a.y * b.x;
+    }
+    aa = wave_sum(aa);
+    abr = wave_sum(abr);
+    abi = wave_sum(abi);
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = aa;
+        red[1][tid >> 6] = abr;
+        red[2][tid >> 6] = abi;
+    }
+    __syncthreads();
+    aa = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    abr = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    abi = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    const double nu2 = coef[j].x - aa;
+    const double nu = nu2 > 0 ? sqrt(nu2) : 0.0;
+    const double2 gamma = coef[2 * j + 1];
+    const double beta_prev = coef[2 * m + 3].x;
+    extern __shared__ double2 sh[];   // [h: j + 1][cs: j][sn: j]
+    double2 *hl = sh, *csl = sh + (j + 1), *snl = csl + j;
+    // final column j - 1: rows 0..j-1 h_{j-1} + beta_{j-1} a, row j beta_{j-1} nu
+    const double sub = beta_prev * nu;
+    if (j > 0) {
+        for (int i = tid; i < j; i += 256) {
+            const double2 a = coef[i], h = hsum[i];
+            const double2 v = make_double2(h.x + beta_prev * a.x, h.y + beta_prev * a.y);
+            hl[i] = v;
+            H[(int64_t)i * m + (j - 1)] = v;
+        }
+        if (tid == 0) H[(int64_t)j * m + (j - 1)] = make_double2(sub, 0.0);
+        for (int i = tid; i < j - 1; i += 256) { csl[i] = cs[i]; snl[i] = sn[i]; }
+    }
+    __syncthreads();   // every thread has read coef before thread 0 rewrites it
+    if (tid != 0) return;
+    bool done = false;
+    if (j > 0) {
+        // Givens rotation of column jc = j - 1 after the previous jc rotations
+        const int jc = j - 1;
+        double2 *col = R + (int64_t)jc * (m + 1);
+        double2 t = hl[0];
+        for (int i = 0; i < jc; ++i) {
+            const double2 a = t, b = hl[i + 1], c = csl[i], sv = snl[i];
+            const double2 ca = cconj_mul(c, a), sb = cconj_mul(sv, b);
+            col[i] = make_double2(ca.x + sb.x, ca.y + sb.y);
+            const double2 sa = cmul(sv, a), cb = cmul(c, b);
+            t = make_double2(cb.x - sa.x, cb.y - sa.y);
+        }
+        const double den = sqrt(t.x * t.x + t.y * t.y + sub * sub);
+        double2 c = make_double2(1, 0), sv = make_double2(0, 0);
+        if (den > 0) { c = make_double2(t.x / den, t.y / den); sv = make_double2(sub / den, 0.0); }
+        cs[jc] = c;
+        sn[jc] = sv;
+        col[jc] = make_double2(den, 0.0);
+        const double2 gj = g[jc];
+        g[jc] = cconj_mul(c, gj);
+        const double2 sg = cmul(sv, gj);
+        g[jc + 1] = make_double2(-sg.x, -sg.y);
+        const double res = sqrt(sg.x * sg.x + sg.y * sg.y) / st->beta0;
+        st->resid = res;
+        st->iters = j;
+        done = res <= st->tol || sub == 0.0 || j >= m;
+    }
+    if (!(nu > 0)) done = true;   // u_j in the span of V: the space is invariant
+    if (done) {
+        st->done = 1;
+        return;
+    }
+    const double inv = 1.0 / nu;
+    coef[j] = make_double2(inv, nu);
+    coef[2 * j + 1] = make_double2((gamma.x - abr) * inv, (gamma.y - abi) * inv);
+}
+
+// Blocks [0, nupd): 64 rows each (four waves split the basis columns, summed
+// in LDS in a fixed order); v_j = (u_j - V a) / nu into slot j, y = w - V b -
+// v_j c_j into slot j + 1, partial |y|^2 per block.  Blocks from nupd on: one
+// wave per row r <= j of the pending column, h_j[r] = ([b; c_j][r] -
+// sum over i >= r - 1 of H[r][i] a_i) / nu.  Grid (nupd + ceil((j + 1) / 4), runs).
+__global__ __launch_bounds__(256) void dgs_update_kernel(int n, int j, int m, int nupd, double2 *__restrict__ Vb,
+                                                         const double2 *__restrict__ w, const double2 *__restrict__ coef,
+                                                         const double2 *__restrict__ H, double2 *__restrict__ hsum,
+                                                         double *__restrict__ npart, const KrylovState *__restrict__ st,
+                                                         KBatch B)
 {
     const int run = blockIdx.y;
     if (st[run].done) return;
     Vb += run * B.basis;
-    partial += run * B.partial;
     w += run * B.vec;
+    coef += run * B.coef;
+    H += run * B.hess;
     hsum += run * B.small;
     npart += run * B.npart;
-    extern __shared__ double2 hs[];
-    __shared__ double red[4];
-    for (int c = threadIdx.x; c < nvec; c += blockDim.x) {
-        double2 s = make_double2(0, 0);
-        for (int b = 0; b < nchunk; ++b) s = cadd(s, partial[(int64_t)b * nvec + c]);
-        hs[c] = s;
-        if (blockIdx.x == 0) hsum[c] = pass ? cadd(hsum[c], s) : s;
-    }
-    __syncthreads();
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    double nrm = 0.0;
-    if (r < n) {
-        double2 acc = w[r];
-        for (int c = 0; c < nvec; ++c) {
-            const double2 v = Vb[(int64_t)c * n + r], h = hs[c];
-            acc.x -= v.x * h.x - v.y * h.y;
-            acc.y -= v.x * h.y + v.y * h.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double inv_nu = coef[j].x;
+    if ((int)blockIdx.x >= nupd) {
+        const int r = ((int)blockIdx.x - nupd) * 4 + wave;
+        if (r > j) return;
+        const double2 *hrow = H + (int64_t)r * m;
+        double sr = 0, si = 0;
+        for (int i = max(r - 1, 0) + lane; i < j; i += 64) {
+            const double2 h = hrow[i], a = coef[i];
+            sr += h.x * a.x - h.y * a.y;
+            si += h.x * a.y + h.y * a.x;
         }
-        w[r] = acc;
-        nrm = acc.x * acc.x + acc.y * acc.y;
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) {
+            const double2 bb = coef[j + 1 + r];
+            hsum[r] = make_double2((bb.x - sr) * inv_nu, (bb.y - si) * inv_nu);
+        }
+        return;
     }
-    if (pass) {
-        nrm = wave_sum(nrm);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nrm;
-        __syncthreads();
-        if (threadIdx.x == 0) npart[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    const int row = blockIdx.x * UPD_ROWS + lane;
+    const bool live = row < n;
+    double ur = 0, ui = 0, wr = 0, wi = 0;
+    if (live)
+        for (int c = wave; c < j; c += 4) {
+            const double2 v = Vb[(int64_t)c * n + row], a = coef[c], b = coef[j + 1 + c];
+            ur += v.x * a.x - v.y * a.y;
+            ui += v.x * a.y + v.y * a.x;
+            wr += v.x * b.x - v.y * b.y;
+            wi += v.x * b.y + v.y * b.x;
+        }
+    __shared__ double4 acc[3][UPD_ROWS];
+    if (wave > 0) acc[wave - 1][lane] = make_double4(ur, ui, wr, wi);
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double4 t = acc[q][lane];
+        ur += t.x; ui += t.y; wr += t.z; wi += t.w;
     }
+    double nrm = 0.0;
+    if (live) {
+        const double2 u = Vb[(int64_t)j * n + row], x = w[row], cj = coef[2 * j + 1];
+        const double2 v = make_double2((u.x - ur) * inv_nu, (u.y - ui) * inv_nu);
+        const double2 y = make_double2(x.x - wr - (v.x * cj.x - v.y * cj.y), x.y - wi - (v.x * cj.y + v.y * cj.x));
+        Vb[(int64_t)j * n + row] = v;
+        Vb[(int64_t)(j + 1) * n + row] = y;
+        nrm = y.x * y.x + y.y * y.y;
+    }
+    nrm = wave_sum(nrm);
+    if (lane == 0) npart[blockIdx.x] = nrm;
+}
+
+// u_{j+1} = y / |y| in place in slot j + 1 (|y|^2 from the nupd partials, summed
+// in the same order by every block); block 0 stores beta_j = |y| / nu.
+// Grid (ceil(n / 256), runs).
+__global__ __launch_bounds__(256) void dgs_normalize_kernel(int n, int j, int m, int nupd,
+                                                            const double *__restrict__ npart, double2 *__restrict__ Vb,
+                                                            double2 *__restrict__ coef,
+                                                            const KrylovState *__restrict__ st, KBatch B)
+{
+    const int run = blockIdx.y;
+    if (st[run].done) return;
+    npart += run * B.npart;
+    Vb += run * B.basis;
+    coef += run * B.coef;
+    __shared__ double red[4];
+    double s2 = 0;
+    for (int b = threadIdx.x; b < nupd; b += 256) s2 += npart[b];
+    s2 = wave_sum(s2);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s2;
+    __syncthreads();
+    const double yn = sqrt(red[0] + red[1] + red[2] + red[3]);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    double2 *y = Vb + (int64_t)(j + 1) * n;
+    if (r < n) {
+        const double inv = yn > 0 ? 1.0 / yn : 0.0;
+        y[r] = make_double2(y[r].x * inv, y[r].y * inv);
+    }
+    if (r == 0) coef[2 * m + 3] = make_double2(yn / coef[j].y, 0.0);
 }
 
 // partial[blk] = sum |w|^2 over 256-row blocks; grid (row blocks, runs)
@@ -1008,72 +1205,6 @@ __global__ __launch_bounds__(256) void normalize_kernel(int n, int nblk, const d
     if (r >= n) return;
     const double inv = beta > 0 ? 1.0 / beta : 0.0;
     out[r] = make_double2(w[r].x * inv, w[r].y * inv);
-}
-
-__device__ inline double2 cconj_mul(double2 a, double2 b)   // conj(a) * b
-{
-    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
-}
-
-// v_{j+1} = w / beta; block 0 of each run: Hessenberg column j (hsum, beta)
-// through the previous Givens rotations, the new rotation, g and the
-// residual estimate.  Grid (row blocks, runs).
-__global__ __launch_bounds__(256) void arnoldi_finish_kernel(int n, int nblk, const double *__restrict__ npart,
-                                                             const double2 *__restrict__ w, double2 *__restrict__ vnext,
-                                                             int j, int m, const double2 *__restrict__ hsum,
-                                                             double2 *__restrict__ R, double2 *__restrict__ g,
-                                                             double2 *__restrict__ cs, double2 *__restrict__ sn,
-                                                             KrylovState *__restrict__ st, KBatch B)
-{
-    const int run = blockIdx.y;
-    st += run;
-    if (st->done) return;
-    npart += run * B.npart;
-    w += run * B.vec;
-    vnext += run * B.basis;
-    hsum += run * B.small;
-    R += run * B.hess;
-    g += run * B.small;
-    cs += run * B.rot;
-    sn += run * B.rot;
-    double s2 = 0;
-    for (int b = 0; b < nblk; ++b) s2 += npart[b];
-    const double beta = sqrt(s2);
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) {
-        const double inv = beta > 0 ? 1.0 / beta : 0.0;
-        vnext[r] = make_double2(w[r].x * inv, w[r].y * inv);
-    }
-    if (blockIdx.x != 0) return;
-    extern __shared__ double2 sh[];   // [h: j+1][cs: j][sn: j]
-    double2 *hl = sh, *csl = sh + (j + 1), *snl = csl + j;
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) hl[i] = hsum[i];
-    for (int i = threadIdx.x; i < j; i += blockDim.x) { csl[i] = cs[i]; snl[i] = sn[i]; }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double2 *col = R + (int64_t)j * (m + 1);
-    double2 t = hl[0];
-    for (int i = 0; i < j; ++i) {
-        const double2 a = t, b = hl[i + 1], c = csl[i], sv = snl[i];
-        const double2 ca = cconj_mul(c, a), sb = cconj_mul(sv, b);
-        col[i] = make_double2(ca.x + sb.x, ca.y + sb.y);
-        const double2 sa = cmul(sv, a), cb = cmul(c, b);
-        t = make_double2(cb.x - sa.x, cb.y - sa.y);
-    }
-    const double den = sqrt(t.x * t.x + t.y * t.y + beta * beta);
-    double2 c = make_double2(1, 0), sv = make_double2(0, 0);
-    if (den > 0) { c = make_double2(t.x / den, t.y / den); sv = make_double2(beta / den, 0.0); }
-    cs[j] = c;
-    sn[j] = sv;
-    col[j] = make_double2(den, 0.0);
-    const double2 gj = g[j];
-    g[j] = cconj_mul(c, gj);
-    const double2 sg = cmul(sv, gj);
-    g[j + 1] = make_double2(-sg.x, -sg.y);
-    const double res = sqrt(sg.x * sg.x + sg.y * sg.y) / st->beta0;
-    st->resid = res;
-    st->iters = j + 1;
-    if (res <= st->tol || beta == 0.0 || j + 1 >= m) st->done = 1;
 }
 
 // g = [beta0, 0, ...] and the state of each run; grid (ceil((m + 1) / 256), runs)
@@ -1294,7 +1425,7 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, v
 namespace {
 
 struct Work {
-    DevMem xin, d, y, z, b, r, Vb, partial, hsum, beta, tolv, yc, npart, R, g, cs, sn, state, part;
+    DevMem xin, d, y, z, b, r, Vb, partial, hsum, beta, tolv, yc, npart, R, H, coef, g, cs, sn, state, part;
 };
 
 // Buffers of the multi-RHS products (one set per solve or batched mat-vec).
@@ -1576,15 +1707,16 @@ struct Gmres {
     BlockBufs *bb;         // multi-RHS products (null: one run, split-column kernels)
     KrylovState *hstate;   // pinned: two snapshots of R states, polled alternately
     hipEvent_t *ev;
-    int n, nchunk, nrow_blk, m, R;
+    int n, nchunk, nrow_blk, nupd, m, R;
     KBatch B;
     double acc64_above = 0.0;   // single run, complex64: FP64 accumulation while the residual estimate exceeds this
 
     // R independent GMRES runs without restart on M^-1 A x = r0 (r0 already
     // preconditioned; run r's start vector at r0 + r r0stride), x0 = 0,
-    // Arnoldi (CGS2) and Givens rotations in FP64 on the device; at most
-    // `maxit` steps; run r stops at relative residual tol[r].  Writes
-    // x + r B.vec and the final states.
+    // Arnoldi (Gram-Schmidt with delayed re-orthogonalisation) and Givens
+    // rotations in FP64 on the device; Krylov spaces of dimension at most
+    // `maxit`; run r stops at relative residual tol[r].  Writes x + r B.vec
+    // and the final states.
     bem_status run(const double2 *r0, int64_t r0stride, const double *tol, int maxit, double2 *x, KrylovState *fin)
     {
         bem_ctx *ctx = p->ctx;
@@ -1617,7 +1749,8 @@ struct Gmres {
                 if (!k[r].done) return false;
             return true;
         };
-        for (int j = 0; j < maxit && !stop; ++j) {
+        // step j applies the operator to u_j and completes dimension j (j = maxit: completion only)
+        for (int j = 0; j <= maxit && !stop; ++j) {
             const double2 *vj = Vb + (size_t)j * n;
             bem_status s;
             if (bb)
@@ -1626,23 +1759,28 @@ struct Gmres {
             else
                 s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>(), acc64);
             if (s) return s;
-            for (int pass = 0; pass < 2; ++pass) {
-                {
-                    KTimer kt(ctx, K_CGS_DOTS);
-                    launch_k(kt, cgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4, R), dim3(256), 0, st, n, j + 1, Vb,
-                             W.z.as<double2>(), W.partial.as<double2>(), dst, B);
-                }
-                KTimer kt(ctx, K_CGS_UPDATE);
-                launch_k(kt, cgs_update_kernel, gv, dim3(256), (size_t)(j + 1) * sizeof(double2), st, n, j + 1, nchunk,
-                         Vb, W.partial.as<double2>(), W.z.as<double2>(), W.hsum.as<double2>(), pass,
-                         W.npart.as<double>(), dst, B);
+            {
+                KTimer kt(ctx, K_CGS_DOTS);
+                launch_k(kt, dgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4, R), dim3(256), 0, st, n, j, Vb,
+                         W.z.as<double2>(), W.partial.as<double2>(), dst, B);
             }
             {
                 KTimer kt(ctx, K_ARNOLDI_FINISH);
-                launch_k(kt, arnoldi_finish_kernel, gv, dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, n,
-                         nrow_blk, W.npart.as<double>(), W.z.as<double2>(), Vb + (size_t)(j + 1) * n, j, maxit,
-                         W.hsum.as<double2>(), W.R.as<double2>(), W.g.as<double2>(), W.cs.as<double2>(),
+                launch_k(kt, dgs_hess_kernel, dim3(R), dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, j, maxit,
+                         nchunk, W.partial.as<double2>(), W.coef.as<double2>(), W.hsum.as<double2>(),
+                         W.H.as<double2>(), W.R.as<double2>(), W.g.as<double2>(), W.cs.as<double2>(),
                          W.sn.as<double2>(), dst, B);
+            }
+            if (j < maxit) {
+                {
+                    KTimer kt(ctx, K_CGS_UPDATE);
+                    launch_k(kt, dgs_update_kernel, dim3(nupd + (j + 1 + 3) / 4, R), dim3(256), 0, st, n, j, maxit,
+                             nupd, Vb, W.z.as<double2>(), W.coef.as<double2>(), W.H.as<double2>(),
+                             W.hsum.as<double2>(), W.npart.as<double>(), dst, B);
+                }
+                KTimer kt(ctx, K_KRYLOV_NORM);
+                launch_k(kt, dgs_normalize_kernel, gv, dim3(256), 0, st, n, j, maxit, nupd, W.npart.as<double>(), Vb,
+                         W.coef.as<double2>(), dst, B);
             }
             BEM_HIP(hipGetLastError());
             const int issued = j + 1;
@@ -1865,7 +2003,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     const int R = std::min(solve_runs(p, opts), nrhs);   // runs advancing together
     const size_t vb = (size_t)n * sizeof(double2);
     const int nchunk = (n + CGS_CHUNK - 1) / CGS_CHUNK;
-    const int nrow_blk = (n + 255) / 256;
+    const int nrow_blk = (n + 255) / 256, nupd = (n + UPD_ROWS - 1) / UPD_ROWS;
     Work W;
     bem_status s = dev_alloc(ctx, W.y, R * vb);
     if (!s) s = dev_alloc(ctx, W.z, R * vb);
@@ -1874,13 +2012,15 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     if (!s) s = dev_alloc(ctx, W.xin, R * vb);
     if (!s && mixed) s = dev_alloc(ctx, W.d, R * vb);
     if (!s) s = dev_alloc(ctx, W.Vb, (size_t)R * (m + 1) * vb);
-    if (!s) s = dev_alloc(ctx, W.partial, (size_t)R * nchunk * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.partial, (size_t)R * nchunk * 2 * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.hsum, (size_t)R * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.beta, sizeof(double) * (R + 1));
     if (!s) s = dev_alloc(ctx, W.tolv, sizeof(double) * R);
     if (!s) s = dev_alloc(ctx, W.yc, (size_t)(m + 1) * sizeof(double2));
-    if (!s) s = dev_alloc(ctx, W.npart, (size_t)R * nrow_blk * sizeof(double));
+    if (!s) s = dev_alloc(ctx, W.npart, (size_t)R * std::max(nrow_blk, nupd) * sizeof(double));
     if (!s) s = dev_alloc(ctx, W.R, (size_t)R * m * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.H, (size_t)R * m * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.coef, (size_t)R * (2 * m + 4) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.g, (size_t)R * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.cs, (size_t)R * m * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.sn, (size_t)R * m * sizeof(double2));
@@ -1901,19 +2041,20 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     struct EvGuard { hipEvent_t *e; ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); } } eguard{ev};
     const MtfArgs A = make_args(p);
     const size_t finish_lds = (size_t)(3 * m + 1) * sizeof(double2);
-    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&arnoldi_finish_kernel),
+    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&dgs_hess_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)finish_lds));
     KBatch B{};
     if (R > 1) {
         B.basis = (int64_t)(m + 1) * n;
         B.vec = n;
-        B.partial = (int64_t)nchunk * (m + 1);
+        B.partial = (int64_t)nchunk * 2 * (m + 1);
         B.small = m + 1;
-        B.npart = nrow_blk;
+        B.npart = std::max(nrow_blk, nupd);
         B.hess = (int64_t)m * (m + 1);
         B.rot = m;
+        B.coef = 2 * m + 4;
     }
-    Gmres gm{p, A, W, R > 1 ? &bb : nullptr, hstate, ev, n, nchunk, nrow_blk, m, R, B};
+    Gmres gm{p, A, W, R > 1 ? &bb : nullptr, hstate, ev, n, nchunk, nrow_blk, nupd, m, R, B};
     const dim3 gv(nrow_blk);
     double *beta = W.beta.as<double>();   // [0, R) ||M^-1 b|| of each run; [R] residual norm
     int total_it = 0, total_ir = 0;
