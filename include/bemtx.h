@@ -110,13 +110,17 @@ const char *bem_last_error(void);
  * problem and mesh of the context. */
 bem_status bem_ctx_create(int32_t device, void *hip_stream, size_t hbm_budget_bytes, bem_ctx **out);
 void bem_ctx_destroy(bem_ctx *ctx);
-/* Device bytes currently held by problems of the context. */
+/* Device bytes currently held by the context: buffers of its meshes and
+ * problems, the assembly scratch, and the blocks the library has released
+ * and keeps for reuse (freed by bem_ctx_trim, bem_ctx_destroy, or when an
+ * allocation would otherwise exceed hbm_budget_bytes or device memory). */
 size_t bem_ctx_bytes_in_use(const bem_ctx *ctx);
 
 /* Free the assembly scratch the context keeps between problems (the
  * block-pair tiles of the regular-pair assembly, grown to the largest mesh
- * assembled so far); the next assembly allocates it again.  Synchronises the
- * context stream.  For callers that account device memory per request. */
+ * assembled so far) and the released blocks kept for reuse; later calls
+ * allocate again.  Synchronises the context stream.  For callers that
+ * account device memory per request. */
 bem_status bem_ctx_trim(bem_ctx *ctx);
 
 /* Per-kernel device time.  Kernels, by bit index: 0 "regular_tiles",

@@ -25,11 +25,43 @@ bem_status hip_error(hipError_t e, const char *what)
     return set_error(BEM_E_DEVICE, std::string(hipGetErrorString(e)) + " in " + what);
 }
 
+// Released blocks go to the context's reuse cache (size classes: powers of
+// two up to 1 MiB, then multiples of 2 MiB), so repeated solves and meshes of
+// the same sizes allocate without hipMalloc / hipFree.
+static size_t size_class(size_t bytes)
+{
+    if (bytes <= 256) return 256;
+    if (bytes <= (size_t(1) << 20)) {
+        size_t c = 512;
+        while (c < bytes) c <<= 1;
+        return c;
+    }
+    const size_t g = size_t(2) << 20;
+    return (bytes + g - 1) / g * g;
+}
+
+// free cached blocks (largest first) until `need` more bytes fit the budget, or all of them
+static void drop_cached(bem_ctx *ctx, size_t need)
+{
+    while (!ctx->free_blocks.empty() && (need == 0 || ctx->in_use + need > ctx->budget)) {
+        auto it = std::prev(ctx->free_blocks.end());
+        (void)hipFree(it->second);
+        ctx->in_use -= it->first;
+        ctx->cached_bytes -= it->first;
+        ctx->free_blocks.erase(it);
+    }
+}
+
 void DevMem::release()
 {
     if (ptr) {
-        (void)hipFree(ptr);
-        if (ctx) ctx->in_use -= bytes;
+        if (ctx) {
+            std::lock_guard<std::mutex> lk(ctx->mem_mu);
+            ctx->free_blocks.emplace(bytes, ptr);
+            ctx->cached_bytes += bytes;
+        } else {
+            (void)hipFree(ptr);
+        }
     }
     ptr = nullptr;
     bytes = 0;
@@ -41,19 +73,36 @@ bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes)
 {
     if (m.ptr && m.bytes >= bytes) return BEM_OK;
     m.release();
-    if (bytes == 0) bytes = 16;
-    if (ctx->budget && ctx->in_use + bytes > ctx->budget)
-        return set_error(BEM_E_OOM, "context HBM budget exceeded (" + std::to_string(ctx->in_use + bytes) + " > " +
+    const size_t cls = size_class(bytes);
+    std::lock_guard<std::mutex> lk(ctx->mem_mu);
+    // a cached block of this class (or at most a quarter larger)
+    auto it = ctx->free_blocks.lower_bound(cls);
+    if (it != ctx->free_blocks.end() && it->first <= cls + cls / 4) {
+        m.ptr = it->second;
+        m.bytes = it->first;
+        m.ctx = ctx;
+        ctx->cached_bytes -= it->first;
+        ctx->free_blocks.erase(it);
+        return BEM_OK;
+    }
+    if (ctx->budget && ctx->in_use + cls > ctx->budget) drop_cached(ctx, cls);
+    if (ctx->budget && ctx->in_use + cls > ctx->budget)
+        return set_error(BEM_E_OOM, "context HBM budget exceeded (" + std::to_string(ctx->in_use + cls) + " > " +
                                         std::to_string(ctx->budget) + " bytes)");
     BEM_HIP(hipSetDevice(ctx->device));
-    hipError_t e = hipMalloc(&m.ptr, bytes);
+    hipError_t e = hipMalloc(&m.ptr, cls);
+    if (e == hipErrorOutOfMemory && !ctx->free_blocks.empty()) {   // return the cache to the device and retry
+        (void)hipGetLastError();
+        drop_cached(ctx, 0);
+        e = hipMalloc(&m.ptr, cls);
+    }
     if (e != hipSuccess) {
         m.ptr = nullptr;
         return hip_error(e, "hipMalloc");
     }
-    m.bytes = bytes;
+    m.bytes = cls;
     m.ctx = ctx;
-    ctx->in_use += bytes;
+    ctx->in_use += cls;
     return BEM_OK;
 }
 
@@ -187,6 +236,10 @@ void bem_ctx_destroy(bem_ctx *ctx)
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
+    {
+        std::lock_guard<std::mutex> lk(ctx->mem_mu);
+        drop_cached(ctx, 0);
+    }
     delete ctx;
 }
 
@@ -201,6 +254,8 @@ bem_status bem_ctx_trim(bem_ctx *ctx)
         ctx->scratch = nullptr;
         ctx->scratch_bytes = 0;
     }
+    std::lock_guard<std::mutex> lk(ctx->mem_mu);
+    drop_cached(ctx, 0);
     return BEM_OK;
 }
 
@@ -384,9 +439,16 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
             ctx->scratch = nullptr;
             ctx->scratch_bytes = 0;
         }
+        std::lock_guard<std::mutex> lk(ctx->mem_mu);
+        if (ctx->budget && ctx->in_use + scratch_bytes > ctx->budget) drop_cached(ctx, scratch_bytes);
         if (ctx->budget && ctx->in_use + scratch_bytes > ctx->budget)
             return set_error(BEM_E_OOM, "context HBM budget exceeded by the assembly scratch");
         hipError_t e = hipMalloc(&ctx->scratch, scratch_bytes);
+        if (e == hipErrorOutOfMemory && !ctx->free_blocks.empty()) {
+            (void)hipGetLastError();
+            drop_cached(ctx, 0);
+            e = hipMalloc(&ctx->scratch, scratch_bytes);
+        }
         if (e != hipSuccess) { ctx->scratch = nullptr; return hip_error(e, "hipMalloc(scratch)"); }
         ctx->scratch_bytes = scratch_bytes;
         ctx->in_use += scratch_bytes;

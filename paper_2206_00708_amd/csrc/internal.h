@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <utility>
 #include <string>
 #include <vector>
@@ -158,6 +160,14 @@ struct bem_ctx {
     // assembly scratch (block-pair tiles, singular contributions), grown on demand
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    // Device blocks the library has released, kept for reuse by size class
+    // (all work of a context is ordered on its stream, so a block may be
+    // handed out again without waiting for the kernels that used it).
+    // in_use counts them until bem_ctx_trim, bem_ctx_destroy or a budget
+    // shortfall returns them to the device.
+    std::multimap<size_t, void *> free_blocks;
+    size_t cached_bytes = 0;
+    std::mutex mem_mu;
 };
 
 namespace bemtx {

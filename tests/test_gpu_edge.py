@@ -112,3 +112,44 @@ def test_tetrahedron_matrix_cores(ctx, orc):
     got = out.cpu().numpy()
     for r in range(3):
         assert _rel(got[r], Xs[r]) < 1e-5
+
+
+def test_released_blocks_reused_and_trimmed():
+    """Released device blocks are kept by the context and handed out again:
+    a second identical solve gives the same traces bit for bit and holds no
+    more device memory than the first; bem_ctx_trim returns every byte of a
+    context whose meshes and problems are gone.  Under a budget that the
+    cache would exceed, cached blocks are dropped instead of failing."""
+    small = synth.make_config("C1")
+    ext, inte, _ = synth.make_pair(11, 3, "fib", 0.01, (1.0, 1.0, 1.0), int_n=500)
+    big = {"ext": ext, "int": inte, "k_ext": 3.0, "k_int": 5.0, "rho_ext": 1.0, "rho_int": 1.5}
+    d = np.array([[0.0, 0.0, 1.0]])
+
+    def run(cx, c):
+        p, me, mi = _problem(cx, c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
+        out, st, code = p.solve(d, tol=1e-8, maxit=300)
+        assert code == B.OK, st
+        x, used = out.cpu().numpy(), cx.bytes_in_use()
+        p.close(); me.close(); mi.close()
+        return x, used
+
+    cx = B.Context(0)
+    x1, used1 = run(cx, small)
+    x2, used2 = run(cx, small)
+    assert np.array_equal(x1, x2)
+    assert used2 <= used1
+    assert cx.bytes_in_use() > 0   # released blocks and the assembly scratch are still held
+    cx.trim()
+    assert cx.bytes_in_use() == 0
+    xb, used_big = run(cx, big)
+    cx.trim()
+    cx.close()
+    # small then big under a budget that both fit only if the small problem's cached blocks are dropped
+    assert used_big > used1
+    budget = used_big + used1 // 2
+    cb = B.Context(0, hbm_budget_bytes=budget)
+    xs, _ = run(cb, small)
+    xb2, _ = run(cb, big)
+    assert np.array_equal(xs, x1) and np.array_equal(xb2, xb)
+    assert cb.bytes_in_use() <= budget
+    cb.close()
