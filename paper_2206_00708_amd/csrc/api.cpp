@@ -107,11 +107,12 @@ bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes)
 }
 
 template <class T>
-static bem_status upload(bem_ctx *ctx, DevMem &m, const std::vector<T> &v)
+static bem_status upload(bem_ctx *ctx, DevMem &m, const std::vector<T> &v, hipStream_t st = nullptr)
 {
     bem_status s = dev_alloc(ctx, m, v.size() * sizeof(T));
     if (s) return s;
-    if (!v.empty()) BEM_HIP(hipMemcpyAsync(m.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    if (!v.empty())
+        BEM_HIP(hipMemcpyAsync(m.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st ? st : ctx->stream));
     return BEM_OK;
 }
 
@@ -121,7 +122,7 @@ size_t tile_scratch_bytes(const bem_mesh *m, size_t entry_bytes);
 bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch, void *ops[4], hipStream_t st);
 bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw, bool fp32,
                            double2 *contrib, void *ops[4], hipStream_t st);
-bem_status launch_mass_inverse(bem_problem *p, int mesh);
+bem_status launch_mass_inverse(bem_problem *p, int mesh, hipStream_t st);
 bem_status launch_sym_corrections(bem_problem *p, int mesh);
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats);
@@ -233,6 +234,10 @@ void bem_ctx_destroy(bem_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->aux) {
+        (void)hipStreamSynchronize(ctx->aux);
+        (void)hipStreamDestroy(ctx->aux);
+    }
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
@@ -377,9 +382,12 @@ void bem_problem_destroy(bem_problem *p)
 {
     if (!p) return;
     (void)hipStreamSynchronize(p->ctx->stream);
+    if (p->ctx->aux) (void)hipStreamSynchronize(p->ctx->aux);
     for (int m = 0; m < 2; ++m)
         for (int q = 0; q < 3; ++q)
             if (p->asm_ev[m][q]) (void)hipEventDestroy(p->asm_ev[m][q]);
+    if (p->ev_pre_asm) (void)hipEventDestroy(p->ev_pre_asm);
+    if (p->ev_proj) (void)hipEventDestroy(p->ev_proj);
     delete p;
 }
 
@@ -415,6 +423,9 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
     bem_ctx *ctx = p->ctx;
     BEM_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
+    // the projection set-up on the auxiliary stream may start once the work queued before this point is done
+    if (!p->ev_pre_asm) BEM_HIP(hipEventCreateWithFlags(&p->ev_pre_asm, hipEventDisableTiming));
+    BEM_HIP(hipEventRecord(p->ev_pre_asm, st));
     const bem_mesh *meshes[2] = {p->ext, p->inte};
     const double ks[2] = {p->k_ext, p->k_int};
     const bool fp32 = p->prec == BEM_C64_MIXED;
@@ -497,20 +508,33 @@ bem_status bem_assemble_projection(bem_problem *p)
     bem_status s = mortar_csr(p->inte->h, p->ext->h, p->P_ie, &defect);
     if (s) return s;
     transpose_csr(p->P_ie, p->P_ei);
-    s = upload(ctx, p->P_ie_ptr, p->P_ie.ptr);
-    if (!s) s = upload(ctx, p->P_ie_col, p->P_ie.col);
-    if (!s) s = upload(ctx, p->P_ie_val, p->P_ie.val);
-    if (!s) s = upload(ctx, p->P_ei_ptr, p->P_ei.ptr);
-    if (!s) s = upload(ctx, p->P_ei_col, p->P_ei.col);
-    if (!s) s = upload(ctx, p->P_ei_val, p->P_ei.val);
+    // uploads and inverse masses on the auxiliary stream, after the work queued
+    // on the main stream before the operator assembly (or before this call),
+    // so that they overlap the assembly; the main stream waits for them
+    if (!ctx->aux) BEM_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    hipStream_t ax = ctx->aux;
+    if (!p->ev_pre_asm) {
+        BEM_HIP(hipEventCreateWithFlags(&p->ev_pre_asm, hipEventDisableTiming));
+        BEM_HIP(hipEventRecord(p->ev_pre_asm, ctx->stream));
+    }
+    if (!p->ev_proj) BEM_HIP(hipEventCreateWithFlags(&p->ev_proj, hipEventDisableTiming));
+    BEM_HIP(hipStreamWaitEvent(ax, p->ev_pre_asm, 0));
+    s = upload(ctx, p->P_ie_ptr, p->P_ie.ptr, ax);
+    if (!s) s = upload(ctx, p->P_ie_col, p->P_ie.col, ax);
+    if (!s) s = upload(ctx, p->P_ie_val, p->P_ie.val, ax);
+    if (!s) s = upload(ctx, p->P_ei_ptr, p->P_ei.ptr, ax);
+    if (!s) s = upload(ctx, p->P_ei_col, p->P_ei.col, ax);
+    if (!s) s = upload(ctx, p->P_ei_val, p->P_ei.val, ax);
     for (int m = 0; m < 2 && !s; ++m) {
-        s = upload(ctx, p->M_ptr[m], p->M[m].ptr);
-        if (!s) s = upload(ctx, p->M_col[m], p->M[m].col);
-        if (!s) s = upload(ctx, p->M_val[m], p->M[m].val);
-        if (!s) s = launch_mass_inverse(p, m);
+        s = upload(ctx, p->M_ptr[m], p->M[m].ptr, ax);
+        if (!s) s = upload(ctx, p->M_col[m], p->M[m].col, ax);
+        if (!s) s = upload(ctx, p->M_val[m], p->M[m].val, ax);
+        if (!s) s = launch_mass_inverse(p, m, ax);
     }
     if (s) return s;
-    BEM_HIP(hipStreamSynchronize(ctx->stream));
+    BEM_HIP(hipEventRecord(p->ev_proj, ax));
+    BEM_HIP(hipStreamWaitEvent(ctx->stream, p->ev_proj, 0));
+    BEM_HIP(hipStreamSynchronize(ax));
     p->t_projection_ms = ms_since(t0);
     p->proj_ready = true;
     return BEM_OK;

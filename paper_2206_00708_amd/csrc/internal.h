@@ -148,6 +148,9 @@ extern const char *const kKernelNames[K_COUNT];
 struct bem_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream (default priority) for the mass and mortar set-up, so that
+    // it overlaps the operator assembly on `stream`; created at first use
+    hipStream_t aux = nullptr;
     size_t budget = 0;
     size_t in_use = 0;
     // per-kernel timing (HIP events around each launch on `stream`)
@@ -247,6 +250,10 @@ struct bem_problem {
     double t_geometry_ms = 0, t_regular_ms = 0, t_singular_ms = 0, t_projection_ms = 0;
     hipEvent_t asm_ev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     bool asm_timing_pending = false;
+    // ordering of the set-up on the auxiliary stream: it starts after the work
+    // queued on the main stream before the operator assembly (ev_pre_asm), and
+    // the main stream waits for its end (ev_proj)
+    hipEvent_t ev_pre_asm = nullptr, ev_proj = nullptr;
     // multi-RHS products: K chunks per GEMM [operators, inverse masses][tile width 32, 64, 128
     // columns], picked by timing at first use
     int gemm_nk[2][3] = {{0, 0, 0}, {0, 0, 0}};

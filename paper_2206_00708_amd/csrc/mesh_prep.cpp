@@ -146,22 +146,34 @@ bem_status mesh_prepare(MeshData &m)
     }
     for (int64_t v = 0; v < nv; ++v)
         if (!used[v]) return set_error(BEM_E_MESH, "unused vertex " + std::to_string(v));
-    // closed, consistently oriented: every directed edge once, its reverse present
+    // closed, consistently oriented: every directed edge once, its reverse
+    // present.  Directed edges are listed per start vertex (counting sort);
+    // both conditions are checked inside the short lists of the two ends.
     {
-        std::vector<uint64_t> e(3 * nt), r(3 * nt);
+        std::vector<int32_t> optr(nv + 1, 0), oto(3 * nt);
         for (int64_t t = 0; t < nt; ++t)
             for (int a = 0; a < 3; ++a) {
-                uint64_t u = (uint32_t)T[3 * t + a], w = (uint32_t)T[3 * t + (a + 1) % 3];
-                if (u == w) return set_error(BEM_E_MESH, "repeated vertex in a triangle");
-                e[3 * t + a] = u << 32 | w;
-                r[3 * t + a] = w << 32 | u;
+                if (T[3 * t + a] == T[3 * t + (a + 1) % 3])
+                    return set_error(BEM_E_MESH, "repeated vertex in a triangle");
+                optr[T[3 * t + a] + 1]++;
             }
-        std::thread sorter([&r] { std::sort(r.begin(), r.end()); });
-        std::sort(e.begin(), e.end());
-        sorter.join();
-        if (std::adjacent_find(e.begin(), e.end()) != e.end())
-            return set_error(BEM_E_MESH, "edge used twice with the same orientation (non-manifold or flipped)");
-        if (e != r) return set_error(BEM_E_MESH, "mesh is not closed or not consistently oriented");
+        for (int64_t v = 0; v < nv; ++v) optr[v + 1] += optr[v];
+        {
+            std::vector<int32_t> fill(optr.begin(), optr.end() - 1);
+            for (int64_t t = 0; t < nt; ++t)
+                for (int a = 0; a < 3; ++a) oto[fill[T[3 * t + a]]++] = T[3 * t + (a + 1) % 3];
+        }
+        bool dup = false, open = false;
+        for (int64_t u = 0; u < nv && !dup; ++u)
+            for (int32_t q = optr[u]; q < optr[u + 1]; ++q) {
+                const int32_t w = oto[q];
+                for (int32_t q2 = optr[u]; q2 < q; ++q2) dup = dup || oto[q2] == w;
+                bool back = false;
+                for (int32_t q2 = optr[w]; q2 < optr[w + 1]; ++q2) back = back || oto[q2] == (int32_t)u;
+                open = open || !back;
+            }
+        if (dup) return set_error(BEM_E_MESH, "edge used twice with the same orientation (non-manifold or flipped)");
+        if (open) return set_error(BEM_E_MESH, "mesh is not closed or not consistently oriented");
     }
     double vol = 0.0, amax = 0.0, amin = 1e300;
     m.area_total = 0.0;

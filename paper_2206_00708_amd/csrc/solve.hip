@@ -287,13 +287,13 @@ __global__ __launch_bounds__(1024) void mass_inverse_ell_kernel(int nv, int ldm,
 template <class TOut> constexpr int chebyshev_steps() { return sizeof(TOut) == 4 ? 18 : 36; }
 
 template <int R, class TOut>
-static bem_status launch_minv_r(bem_problem *p, int nv, int mesh)
+static bem_status launch_minv_r(bem_problem *p, int nv, int mesh, hipStream_t st)
 {
     const size_t lds = (size_t)nv * sizeof(double);
     BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_kernel<R, TOut>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer kt(p->ctx, K_MASS_INVERSE);
-    launch_k(kt, mass_inverse_kernel<R, TOut>, dim3(nv), dim3(1024), lds, p->ctx->stream, nv,
+    launch_k(kt, mass_inverse_kernel<R, TOut>, dim3(nv), dim3(1024), lds, st, nv,
              minv_ld(nv, sizeof(TOut) == 4), chebyshev_steps<TOut>(), p->M_ptr[mesh].as<int32_t>(),
              p->M_col[mesh].as<int32_t>(),
              p->M_val[mesh].as<double>(), p->Minv[mesh].as<TOut>());
@@ -302,64 +302,67 @@ static bem_status launch_minv_r(bem_problem *p, int nv, int mesh)
 }
 
 template <int R, int C, class TOut, bool DB>
-static bem_status launch_minv_ell(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev)
+static bem_status launch_minv_ell(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev,
+                                  hipStream_t st)
 {
     const size_t lds = (size_t)(DB ? 2 : 1) * C * nv * sizeof(double);
     BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&mass_inverse_ell_kernel<R, C, TOut, DB>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     KTimer kt(p->ctx, K_MASS_INVERSE);
-    launch_k(kt, mass_inverse_ell_kernel<R, C, TOut, DB>, dim3((nv + C - 1) / C), dim3(1024), lds, p->ctx->stream,
+    launch_k(kt, mass_inverse_ell_kernel<R, C, TOut, DB>, dim3((nv + C - 1) / C), dim3(1024), lds, st,
              nv, minv_ld(nv, sizeof(TOut) == 4), W, chebyshev_steps<TOut>(), ec, ev, p->Minv[mesh].as<TOut>());
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
 
 template <int R, class TOut>
-static bem_status launch_minv_ell_r(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev)
+static bem_status launch_minv_ell_r(bem_problem *p, int nv, int W, int mesh, const int32_t *ec, const double *ev,
+                                    hipStream_t st)
 {
     // columns per workgroup: as many double-buffered directions as fit in 160 KiB of LDS
     const int cfit = (int)(163840 / (2 * (size_t)nv * sizeof(double)));
-    if (cfit >= 8) return launch_minv_ell<R, 8, TOut, true>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 4) return launch_minv_ell<R, 4, TOut, true>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 3) return launch_minv_ell<R, 3, TOut, true>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 2) return launch_minv_ell<R, 2, TOut, true>(p, nv, W, mesh, ec, ev);
-    if (cfit >= 1) return launch_minv_ell<R, 1, TOut, true>(p, nv, W, mesh, ec, ev);
-    return launch_minv_ell<R, 1, TOut, false>(p, nv, W, mesh, ec, ev);
+    if (cfit >= 8) return launch_minv_ell<R, 8, TOut, true>(p, nv, W, mesh, ec, ev, st);
+    if (cfit >= 4) return launch_minv_ell<R, 4, TOut, true>(p, nv, W, mesh, ec, ev, st);
+    if (cfit >= 3) return launch_minv_ell<R, 3, TOut, true>(p, nv, W, mesh, ec, ev, st);
+    if (cfit >= 2) return launch_minv_ell<R, 2, TOut, true>(p, nv, W, mesh, ec, ev, st);
+    if (cfit >= 1) return launch_minv_ell<R, 1, TOut, true>(p, nv, W, mesh, ec, ev, st);
+    return launch_minv_ell<R, 1, TOut, false>(p, nv, W, mesh, ec, ev, st);
 }
 
 template <class TOut>
-static bem_status launch_minv_ell_any(bem_problem *p, int nv, int W, int mesh, const int32_t *dc, const double *dv)
+static bem_status launch_minv_ell_any(bem_problem *p, int nv, int W, int mesh, const int32_t *dc, const double *dv,
+                                      hipStream_t st)
 {
     switch ((nv + 1023) / 1024) {
-    case 1: return launch_minv_ell_r<1, TOut>(p, nv, W, mesh, dc, dv);
-    case 2: return launch_minv_ell_r<2, TOut>(p, nv, W, mesh, dc, dv);
-    case 3: return launch_minv_ell_r<3, TOut>(p, nv, W, mesh, dc, dv);
-    case 4: return launch_minv_ell_r<4, TOut>(p, nv, W, mesh, dc, dv);
-    case 5: case 6: return launch_minv_ell_r<6, TOut>(p, nv, W, mesh, dc, dv);
-    case 7: case 8: return launch_minv_ell_r<8, TOut>(p, nv, W, mesh, dc, dv);
-    case 9: case 10: return launch_minv_ell_r<10, TOut>(p, nv, W, mesh, dc, dv);
-    case 11: case 12: return launch_minv_ell_r<12, TOut>(p, nv, W, mesh, dc, dv);
-    case 13: case 14: case 15: case 16: return launch_minv_ell_r<16, TOut>(p, nv, W, mesh, dc, dv);
-    default: return launch_minv_ell_r<20, TOut>(p, nv, W, mesh, dc, dv);
+    case 1: return launch_minv_ell_r<1, TOut>(p, nv, W, mesh, dc, dv, st);
+    case 2: return launch_minv_ell_r<2, TOut>(p, nv, W, mesh, dc, dv, st);
+    case 3: return launch_minv_ell_r<3, TOut>(p, nv, W, mesh, dc, dv, st);
+    case 4: return launch_minv_ell_r<4, TOut>(p, nv, W, mesh, dc, dv, st);
+    case 5: case 6: return launch_minv_ell_r<6, TOut>(p, nv, W, mesh, dc, dv, st);
+    case 7: case 8: return launch_minv_ell_r<8, TOut>(p, nv, W, mesh, dc, dv, st);
+    case 9: case 10: return launch_minv_ell_r<10, TOut>(p, nv, W, mesh, dc, dv, st);
+    case 11: case 12: return launch_minv_ell_r<12, TOut>(p, nv, W, mesh, dc, dv, st);
+    case 13: case 14: case 15: case 16: return launch_minv_ell_r<16, TOut>(p, nv, W, mesh, dc, dv, st);
+    default: return launch_minv_ell_r<20, TOut>(p, nv, W, mesh, dc, dv, st);
     }
 }
 
 template <class TOut>
-static bem_status launch_minv_csr_any(bem_problem *p, int nv, int mesh)
+static bem_status launch_minv_csr_any(bem_problem *p, int nv, int mesh, hipStream_t st)
 {
     switch ((nv + 1023) / 1024) {
-    case 1: return launch_minv_r<1, TOut>(p, nv, mesh);
-    case 2: return launch_minv_r<2, TOut>(p, nv, mesh);
-    case 3: return launch_minv_r<3, TOut>(p, nv, mesh);
-    case 4: return launch_minv_r<4, TOut>(p, nv, mesh);
-    case 5: case 6: return launch_minv_r<6, TOut>(p, nv, mesh);
-    case 7: case 8: return launch_minv_r<8, TOut>(p, nv, mesh);
-    case 9: case 10: case 11: case 12: return launch_minv_r<12, TOut>(p, nv, mesh);
-    default: return launch_minv_r<16, TOut>(p, nv, mesh);
+    case 1: return launch_minv_r<1, TOut>(p, nv, mesh, st);
+    case 2: return launch_minv_r<2, TOut>(p, nv, mesh, st);
+    case 3: return launch_minv_r<3, TOut>(p, nv, mesh, st);
+    case 4: return launch_minv_r<4, TOut>(p, nv, mesh, st);
+    case 5: case 6: return launch_minv_r<6, TOut>(p, nv, mesh, st);
+    case 7: case 8: return launch_minv_r<8, TOut>(p, nv, mesh, st);
+    case 9: case 10: case 11: case 12: return launch_minv_r<12, TOut>(p, nv, mesh, st);
+    default: return launch_minv_r<16, TOut>(p, nv, mesh, st);
     }
 }
 
-bem_status launch_mass_inverse(bem_problem *p, int mesh)
+bem_status launch_mass_inverse(bem_problem *p, int mesh, hipStream_t st)
 {
     const bem_mesh *m = mesh == 0 ? p->ext : p->inte;
     const int nv = (int)m->h.nv;
@@ -369,7 +372,7 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh)
     bem_status s = dev_alloc(p->ctx, p->Minv[mesh], bytes);
     if (s) return s;
     // padding columns must read as zero (vector loads cover them)
-    BEM_HIP(hipMemsetAsync(p->Minv[mesh].ptr, 0, bytes, p->ctx->stream));
+    BEM_HIP(hipMemsetAsync(p->Minv[mesh].ptr, 0, bytes, st));
     const Csr &M = p->M[mesh];
     int W = 0;
     for (int64_t i = 0; i < M.nrows; ++i) W = std::max(W, M.ptr[i + 1] - M.ptr[i]);
@@ -391,15 +394,15 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh)
         if (!s) s = dev_alloc(p->ctx, p->M_ell_val[mesh], ev.size() * sizeof(double));
         if (s) return s;
         BEM_HIP(hipMemcpyAsync(p->M_ell_col[mesh].ptr, ec.data(), ec.size() * sizeof(int32_t), hipMemcpyHostToDevice,
-                               p->ctx->stream));
+                               st));
         BEM_HIP(hipMemcpyAsync(p->M_ell_val[mesh].ptr, ev.data(), ev.size() * sizeof(double), hipMemcpyHostToDevice,
-                               p->ctx->stream));
+                               st));
         const int32_t *dc = p->M_ell_col[mesh].as<int32_t>();
         const double *dv = p->M_ell_val[mesh].as<double>();
-        return f32 ? launch_minv_ell_any<float>(p, nv, W, mesh, dc, dv)
-                   : launch_minv_ell_any<double>(p, nv, W, mesh, dc, dv);
+        return f32 ? launch_minv_ell_any<float>(p, nv, W, mesh, dc, dv, st)
+                   : launch_minv_ell_any<double>(p, nv, W, mesh, dc, dv, st);
     }
-    return f32 ? launch_minv_csr_any<float>(p, nv, mesh) : launch_minv_csr_any<double>(p, nv, mesh);
+    return f32 ? launch_minv_csr_any<float>(p, nv, mesh, st) : launch_minv_csr_any<double>(p, nv, mesh, st);
 }
 
 // --------------------------------------------------------------- mat-vec
