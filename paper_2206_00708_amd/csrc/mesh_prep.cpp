@@ -16,6 +16,7 @@
 #include <cstring>
 #include <functional>
 #include <numeric>
+#include <atomic>
 #include <condition_variable>
 #include <mutex>
 #include <thread>
@@ -254,27 +255,33 @@ bem_status mesh_prepare(MeshData &m)
     m.slot_cnt.assign((size_t)nb * SMAX, 0);
     m.slot_ent.assign((size_t)nb * SMAX * LMAX, 0);
     m.memb_ptr.assign(nv + 1, 0);
-    for (int b = 0; b < nb; ++b) {
-        std::vector<int32_t> vs;
-        for (int32_t t = m.blk_start[b]; t < m.blk_start[b + 1]; ++t)
-            for (int a = 0; a < 3; ++a) vs.push_back(m.tri[3 * t + a]);
-        std::sort(vs.begin(), vs.end());
-        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
-        if ((int)vs.size() > SMAX) return set_error(BEM_E_MESH, "internal: block vertex overflow");
-        m.blk_nslot[b] = (int32_t)vs.size();
-        for (size_t s = 0; s < vs.size(); ++s) {
-            m.blk_slots[(size_t)b * SMAX + s] = vs[s];
-            m.memb_ptr[vs[s] + 1]++;
+    // blocks are independent (each writes only its own slot tables): in parallel
+    std::atomic<int> slot_err{0};   // 1: vertex overflow, 2: valence
+    parallel_for(nb, 16, [&](int64_t b0, int64_t b1) {
+        int32_t vs[3 * BT];
+        for (int64_t b = b0; b < b1; ++b) {
+            int nvs = 0;
+            for (int32_t t = m.blk_start[b]; t < m.blk_start[b + 1]; ++t)
+                for (int a = 0; a < 3; ++a) vs[nvs++] = m.tri[3 * t + a];
+            std::sort(vs, vs + nvs);
+            nvs = (int)(std::unique(vs, vs + nvs) - vs);
+            if (nvs > SMAX) { slot_err = 1; return; }
+            m.blk_nslot[b] = nvs;
+            for (int q = 0; q < nvs; ++q) m.blk_slots[(size_t)b * SMAX + q] = vs[q];
+            for (int32_t t = m.blk_start[b]; t < m.blk_start[b + 1]; ++t)
+                for (int a = 0; a < 3; ++a) {
+                    const int q = (int)(std::lower_bound(vs, vs + nvs, m.tri[3 * t + a]) - vs);
+                    uint8_t &cnt = m.slot_cnt[(size_t)b * SMAX + q];
+                    if (cnt >= LMAX) { slot_err = 2; return; }
+                    m.slot_ent[((size_t)b * SMAX + q) * LMAX + cnt] = (uint8_t)((t - m.blk_start[b]) * 3 + a);
+                    ++cnt;
+                }
         }
-        for (int32_t t = m.blk_start[b]; t < m.blk_start[b + 1]; ++t)
-            for (int a = 0; a < 3; ++a) {
-                int s = (int)(std::lower_bound(vs.begin(), vs.end(), m.tri[3 * t + a]) - vs.begin());
-                uint8_t &cnt = m.slot_cnt[(size_t)b * SMAX + s];
-                if (cnt >= LMAX) return set_error(BEM_E_MESH, "vertex valence too high (> 12 corners in one block)");
-                m.slot_ent[((size_t)b * SMAX + s) * LMAX + cnt] = (uint8_t)((t - m.blk_start[b]) * 3 + a);
-                ++cnt;
-            }
-    }
+    });
+    if (slot_err == 1) return set_error(BEM_E_MESH, "internal: block vertex overflow");
+    if (slot_err == 2) return set_error(BEM_E_MESH, "vertex valence too high (> 12 corners in one block)");
+    for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < m.blk_nslot[b]; ++q) m.memb_ptr[m.blk_slots[(size_t)b * SMAX + q] + 1]++;
     // vertex -> (block, slot) memberships, blocks ascending
     for (int64_t v = 0; v < nv; ++v) m.memb_ptr[v + 1] += m.memb_ptr[v];
     m.memb.resize(m.memb_ptr[nv]);
@@ -330,18 +337,14 @@ bem_status mesh_prepare(MeshData &m)
             }
         }
     };
-    // chunks of test triangles in parallel, each into its own per-kind lists
+    // two passes over chunks of test triangles in parallel: count the pairs of
+    // each (kind, t), then write them at their final places (no staging lists)
     const int64_t nchunk_t = std::min<int64_t>(nt, 128);
-    std::vector<std::vector<SingPair>> chunk_pairs[4];
-    for (int k = 1; k <= 3; ++k) chunk_pairs[k].resize(nchunk_t);
     parallel_for(nchunk_t, 1, [&](int64_t c0, int64_t c1) {
         std::vector<int64_t> seen_by(nt, -1);
         for (int64_t c = c0; c < c1; ++c)
             for (int64_t t = nt * c / nchunk_t; t < nt * (c + 1) / nchunk_t; ++t)
-                pairs_of(t, seen_by, [&](int k, const SingPair &sp) {
-                    chunk_pairs[k][c].push_back(sp);
-                    pcnt[k][t + 1]++;
-                });
+                pairs_of(t, seen_by, [&](int k, const SingPair &) { pcnt[k][t + 1]++; });
     });
     int64_t kbase[4] = {0, 0, 0, 0};
     {
@@ -353,14 +356,15 @@ bem_status mesh_prepare(MeshData &m)
             acc += pcnt[k][nt];
         }
         m.sing.resize((size_t)acc);
-        for (int k = 3; k >= 1; --k) {
-            int64_t at = kbase[k];
-            for (auto &cp : chunk_pairs[k]) {
-                std::copy(cp.begin(), cp.end(), m.sing.begin() + at);
-                at += (int64_t)cp.size();
-            }
-        }
     }
+    parallel_for(nchunk_t, 1, [&](int64_t c0, int64_t c1) {
+        std::vector<int64_t> seen_by(nt, -1);
+        for (int64_t c = c0; c < c1; ++c)
+            for (int64_t t = nt * c / nchunk_t; t < nt * (c + 1) / nchunk_t; ++t) {
+                int64_t at[4] = {0, kbase[1] + pcnt[1][t], kbase[2] + pcnt[2][t], kbase[3] + pcnt[3][t]};
+                pairs_of(t, seen_by, [&](int k, const SingPair &sp) { m.sing[at[k]++] = sp; });
+            }
+    });
 
     // ---- near entries: unique (i, j) touched by singular pairs, contributions in pair order.
     // Row i collects, kind by kind and triangle by triangle of its star (the

@@ -970,7 +970,8 @@ __device__ inline double2 cconj_mul(double2 a, double2 b)   // conj(a) * b
 
 // Sums of the partials into coef ([0, j) a, [j] alpha, [j + 1, 2j + 1) b,
 // [2j + 1] gamma); nu; the final column j - 1 of the Hessenberg matrix
-// (kept row-major in H, row stride m) and, by thread 0, its Givens rotation,
+// (kept row-major in H, row stride m) and, by the first wave, its Givens rotation
+// (the earlier rotations as a scanned affine recurrence),
 // g and the residual estimate; then coef[j] = (1 / nu, nu) and coef[2j + 1] =
 // c_j for the update.  coef[2m + 3] holds beta_{j-1}.  One workgroup per run.
 __global__ __launch_bounds__(256) void dgs_hess_kernel(int j, int m, int nchunk, const double2 *__restrict__ partial,
@@ -1036,35 +1037,68 @@ __global__ __launch_bounds__(256) void dgs_hess_kernel(int j, int m, int nchunk,
         for (int i = tid; i < j - 1; i += 256) { csl[i] = cs[i]; snl[i] = sn[i]; }
     }
     __syncthreads();   // every thread has read coef before thread 0 rewrites it
-    if (tid != 0) return;
+    if (tid >= 64) return;
+    const int lane = tid;
     bool done = false;
     if (j > 0) {
-        // Givens rotation of column jc = j - 1 after the previous jc rotations
+        // Givens rotations 0 .. jc-1 applied to column jc = j - 1.  With s_i
+        // real they form the affine recurrence t_{i+1} = -s_i t_i + c_i h_{i+1}
+        // (t_0 = h_0; entry i of the rotated column is conj(c_i) t_i + s_i h_{i+1}),
+        // so one wave takes it in segments: each lane composes the maps of its
+        // steps, the composites are scanned across the wave, and each lane
+        // replays its steps from its start value.
         const int jc = j - 1;
         double2 *col = R + (int64_t)jc * (m + 1);
-        double2 t = hl[0];
-        for (int i = 0; i < jc; ++i) {
-            const double2 a = t, b = hl[i + 1], c = csl[i], sv = snl[i];
-            const double2 ca = cconj_mul(c, a), sb = cconj_mul(sv, b);
-            col[i] = make_double2(ca.x + sb.x, ca.y + sb.y);
-            const double2 sa = cmul(sv, a), cb = cmul(c, b);
-            t = make_double2(cb.x - sa.x, cb.y - sa.y);
+        const int L = (jc + 63) / 64;
+        const int i0 = min(jc, lane * L), i1 = min(jc, i0 + L);
+        double P = 1.0, Qx = 0.0, Qy = 0.0;   // t_end = P t_start + Q over the lane's steps
+        for (int i = i0; i < i1; ++i) {
+            const double a = -snl[i].x;
+            const double2 cb = cmul(csl[i], hl[i + 1]);
+            P *= a;
+            Qx = a * Qx + cb.x;
+            Qy = a * Qy + cb.y;
         }
-        const double den = sqrt(t.x * t.x + t.y * t.y + sub * sub);
-        double2 c = make_double2(1, 0), sv = make_double2(0, 0);
-        if (den > 0) { c = make_double2(t.x / den, t.y / den); sv = make_double2(sub / den, 0.0); }
-        cs[jc] = c;
-        sn[jc] = sv;
-        col[jc] = make_double2(den, 0.0);
-        const double2 gj = g[jc];
-        g[jc] = cconj_mul(c, gj);
-        const double2 sg = cmul(sv, gj);
-        g[jc + 1] = make_double2(-sg.x, -sg.y);
-        const double res = sqrt(sg.x * sg.x + sg.y * sg.y) / st->beta0;
-        st->resid = res;
-        st->iters = j;
-        done = res <= st->tol || sub == 0.0 || j >= m;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {   // inclusive scan: the maps of lanes 0..lane, later after earlier
+            const double Pp = __shfl_up(P, off, 64), Qpx = __shfl_up(Qx, off, 64), Qpy = __shfl_up(Qy, off, 64);
+            if (lane >= off) {
+                Qx = P * Qpx + Qx;
+                Qy = P * Qpy + Qy;
+                P *= Pp;
+            }
+        }
+        const double Pe = __shfl_up(P, 1, 64), Qex = __shfl_up(Qx, 1, 64), Qey = __shfl_up(Qy, 1, 64);
+        const double2 h0 = hl[0];
+        double2 t = lane == 0 ? h0 : make_double2(Pe * h0.x + Qex, Pe * h0.y + Qey);
+        for (int i = i0; i < i1; ++i) {
+            const double2 b = hl[i + 1], c = csl[i];
+            const double sv = snl[i].x;
+            const double2 ca = cconj_mul(c, t), cb = cmul(c, b);
+            col[i] = make_double2(ca.x + sv * b.x, ca.y + sv * b.y);
+            t = make_double2(cb.x - sv * t.x, cb.y - sv * t.y);
+        }
+        // lanes past the last step hold t_jc unchanged; lane 63 always does
+        t.x = __shfl(t.x, 63, 64);
+        t.y = __shfl(t.y, 63, 64);
+        if (lane == 0) {
+            const double den = sqrt(t.x * t.x + t.y * t.y + sub * sub);
+            double2 c = make_double2(1, 0), sv = make_double2(0, 0);
+            if (den > 0) { c = make_double2(t.x / den, t.y / den); sv = make_double2(sub / den, 0.0); }
+            cs[jc] = c;
+            sn[jc] = sv;
+            col[jc] = make_double2(den, 0.0);
+            const double2 gj = g[jc];
+            g[jc] = cconj_mul(c, gj);
+            const double2 sg = cmul(sv, gj);
+            g[jc + 1] = make_double2(-sg.x, -sg.y);
+            const double res = sqrt(sg.x * sg.x + sg.y * sg.y) / st->beta0;
+            st->resid = res;
+            st->iters = j;
+            done = res <= st->tol || sub == 0.0 || j >= m;
+        }
     }
+    if (lane != 0) return;
     if (!(nu > 0)) done = true;   // u_j in the span of V: the space is invariant
     if (done) {
         st->done = 1;
