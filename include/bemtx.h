@@ -175,7 +175,11 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts);
 
 /* Mass matrices M_ext, M_int and the mortar matrix P_int,ext (N_int x N_ext)
  * with P_ext,int = P_int,ext^T (Sec. 3.1), device-resident, plus the dense
- * inverse mass matrices used by the strong form (Sec. 3.3).
+ * inverse mass matrices used by the strong form (Sec. 3.3).  The sparse
+ * matrices are built on the host; their uploads and the inverse masses run
+ * on a second stream of the context, ordered after the work queued before
+ * bem_assemble_operators and before every later call on the problem, so
+ * that they overlap a queued operator assembly.  Returns when they are done.
  * BEM_E_MESH_MISMATCH if the projected interior mesh leaves part of an
  * exterior facet uncovered (relative area defect above 1e-6). */
 bem_status bem_assemble_projection(bem_problem *p);

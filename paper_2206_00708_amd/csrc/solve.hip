@@ -70,12 +70,8 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 // streaming load of a complex128 matrix entry (read once, do not keep in cache)
 __device__ inline double2 ld_stream(const double2 *p)
 {
-#ifdef BEMTX_NO_NT
-    return *p;
-#else
     const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(p));
     return make_double2(v.x, v.y);
-#endif
 }
 
 __device__ inline double wave_sum(double v)
@@ -444,19 +440,10 @@ struct MtfArgs {
 // staged in LDS, per-chunk partial sums, fixed-order combine.  Rows of the
 // two meshes form one grid; chunk widths are multiples of 64 chosen per mesh.
 
-#ifndef BEMTX_MASS_CW
-#define BEMTX_MASS_CW 1024
-#endif
-constexpr int MASS_CW_MAX = BEMTX_MASS_CW;       // columns per chunk of the inverse-mass apply (upper bound)
-constexpr int SPLIT_ROWS = 4;                    // waves per workgroup
-#ifndef BEMTX_MASS_RW64
-#define BEMTX_MASS_RW64 4
-#endif
-#ifndef BEMTX_MASS_RW32
-#define BEMTX_MASS_RW32 8
-#endif
-constexpr int MASS_RW64 = BEMTX_MASS_RW64;       // rows per wave of the FP64 inverse-mass apply
-constexpr int MASS_RW32 = BEMTX_MASS_RW32;       // the same, FP32 storage
+constexpr int MASS_CW_MAX = 1024;   // columns per chunk of the inverse-mass apply (upper bound)
+constexpr int SPLIT_ROWS = 4;       // waves per workgroup
+constexpr int MASS_RW64 = 4;        // rows per wave of the FP64 inverse-mass apply
+constexpr int MASS_RW32 = 8;        // the same, FP32 storage
 
 __host__ __device__ inline int split_nchunk(int nv, int cwmax) { return (nv + cwmax - 1) / cwmax; }
 __host__ __device__ inline int split_cw(int nv, int cwmax)
@@ -470,12 +457,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // streaming load of two adjacent complex64 entries (16 bytes)
 __device__ inline float4 ld_stream2c(const float2 *p)
 {
-#ifdef BEMTX_NO_NT
-    return *reinterpret_cast<const float4 *>(p);
-#else
     const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(p));
     return make_float4(v.x, v.y, v.z, v.w);
-#endif
 }
 
 template <class R> struct Cx;
