@@ -153,3 +153,28 @@ def test_released_blocks_reused_and_trimmed():
     assert np.array_equal(xs, x1) and np.array_equal(xb2, xb)
     assert cb.bytes_in_use() <= budget
     cb.close()
+
+
+def test_projection_before_operators_same_traces():
+    """bem_assemble_projection runs on the context's second stream; called
+    before bem_assemble_operators (or after it, the usual order) it must give
+    the same solve, bit for bit."""
+    c = synth.make_config("C1")
+    d = np.array([[0.0, 0.0, 1.0]])
+    cx = B.Context(0)
+    outs = []
+    for first_projection in (False, True):
+        me, mi = B.Mesh(cx, *c["ext"]), B.Mesh(cx, *c["int"])
+        p = B.Problem(cx, me, mi, c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
+        if first_projection:
+            p.assemble_projection()
+            p.assemble_operators()
+        else:
+            p.assemble_operators()
+            p.assemble_projection()
+        out, st, code = p.solve(d, tol=1e-8, maxit=300)
+        assert code == B.OK, st
+        outs.append(out.cpu().numpy())
+        p.close(); me.close(); mi.close()
+    assert np.array_equal(outs[0], outs[1])
+    cx.close()
