@@ -118,7 +118,7 @@ __device__ inline void tile_of(int64_t t, int nb, int &b1, int &b2)
 // corner b.  Written to out[4 * e + op] (tile layout [entry][op]).
 template <class R, class C2>
 __device__ inline void tile_slot_sums(int tid, int op, int ns1, int ns2, const uint8_t *c1, const uint8_t *c2,
-                                      const uint8_t *e1, const uint8_t *e2, const R *st_re, const R *st_im, C2 *out)
+                                      const uint16_t *o1, const uint8_t *o2, const R *st_re, const R *st_im, C2 *out)
 {
     for (int e = tid; e < SMAX * SMAX; e += 256) {
         const int q1 = e / SMAX, q2 = e - q1 * SMAX;
@@ -126,12 +126,9 @@ __device__ inline void tile_slot_sums(int tid, int op, int ns1, int ns2, const u
         R re = 0, im = 0;
         const int m1 = c1[q1], m2 = c2[q2];
         for (int u = 0; u < m1; ++u) {
-            const int en1 = e1[q1 * LMAX + u];
-            const int tt1 = en1 / 3, a = en1 - 3 * tt1;
+            const int i1 = o1[q1 * LMAX + u];
             for (int v = 0; v < m2; ++v) {
-                const int en2 = e2[q2 * LMAX + v];
-                const int tt2 = en2 / 3, b = en2 - 3 * tt2;
-                const int idx = (tt1 * 16 + tt2) * 9 + 3 * a + b;
+                const int idx = i1 + o2[q2 * LMAX + v];
                 re += st_re[idx];
                 im += st_im[idx];
             }
@@ -156,7 +153,9 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
 {
     __shared__ TriGeo gX[BT], gY[BT];
     __shared__ int32_t vX[BT * 3], vY[BT * 3];
-    __shared__ uint8_t c1[SMAX], c2[SMAX], e1[SMAX * LMAX], e2[SMAX * LMAX];
+    __shared__ uint8_t c1[SMAX], c2[SMAX];
+    __shared__ uint16_t e1[SMAX * LMAX];   // slot corner (t, a) of block 1 as the offset 144 t + 3 a of its entries
+    __shared__ uint8_t e2[SMAX * LMAX];    // slot corner (t, b) of block 2 as the offset 9 t + b
     __shared__ double st_re[256 * 9], st_im[256 * 9];
 
     const int64_t tile = tile0 + blockIdx.x;
@@ -177,8 +176,9 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
         if (tid < n2 * 3) vY[tid] = A.tri[3 * s2 + tid];
         if (tid < SMAX) { c1[tid] = A.slot_cnt[b1 * SMAX + tid]; c2[tid] = A.slot_cnt[b2 * SMAX + tid]; }
         for (int q = tid; q < SMAX * LMAX; q += 256) {
-            e1[q] = A.slot_ent[(size_t)b1 * SMAX * LMAX + q];
-            e2[q] = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
+            const int en1 = A.slot_ent[(size_t)b1 * SMAX * LMAX + q], en2 = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
+            e1[q] = (uint16_t)((en1 / 3) * 144 + 3 * (en1 % 3));
+            e2[q] = (uint8_t)((en2 / 3) * 9 + en2 % 3);
         }
     }
     __syncthreads();
@@ -293,7 +293,9 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
 {
     __shared__ TriGeoF gX[BT], gY[BT];
     __shared__ int32_t vX[BT * 3], vY[BT * 3];
-    __shared__ uint8_t c1[SMAX], c2[SMAX], e1[SMAX * LMAX], e2[SMAX * LMAX];
+    __shared__ uint8_t c1[SMAX], c2[SMAX];
+    __shared__ uint16_t e1[SMAX * LMAX];   // slot corner (t, a) of block 1 as the offset 144 t + 3 a of its entries
+    __shared__ uint8_t e2[SMAX * LMAX];    // slot corner (t, b) of block 2 as the offset 9 t + b
     __shared__ float st_re[256 * 9], st_im[256 * 9];
 
     const int64_t tile = tile0 + blockIdx.x;
@@ -314,8 +316,9 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
         if (tid < n2 * 3) vY[tid] = A.tri[3 * s2 + tid];
         if (tid < SMAX) { c1[tid] = A.slot_cnt[b1 * SMAX + tid]; c2[tid] = A.slot_cnt[b2 * SMAX + tid]; }
         for (int q = tid; q < SMAX * LMAX; q += 256) {
-            e1[q] = A.slot_ent[(size_t)b1 * SMAX * LMAX + q];
-            e2[q] = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
+            const int en1 = A.slot_ent[(size_t)b1 * SMAX * LMAX + q], en2 = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
+            e1[q] = (uint16_t)((en1 / 3) * 144 + 3 * (en1 % 3));
+            e2[q] = (uint8_t)((en2 / 3) * 9 + en2 % 3);
         }
     }
     __syncthreads();
