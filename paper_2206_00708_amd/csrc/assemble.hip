@@ -116,10 +116,11 @@ __device__ inline void tile_of(int64_t t, int nb, int &b1, int &b2)
 // in a fixed order: entry (q1, q2) adds the entries (a, b) of every pair
 // whose test triangle has slot q1 at corner a and trial triangle slot q2 at
 // corner b.  Written to out[4 * e + op] (tile layout [entry][op]).
-template <class R, class C2>
+template <class C2>
 __device__ inline void tile_slot_sums(int tid, int op, int ns1, int ns2, const uint8_t *c1, const uint8_t *c2,
-                                      const uint16_t *o1, const uint8_t *o2, const R *st_re, const R *st_im, C2 *out)
+                                      const uint16_t *o1, const uint8_t *o2, const C2 *st, C2 *out)
 {
+    using R = decltype(C2::x);
     for (int e = tid; e < SMAX * SMAX; e += 256) {
         const int q1 = e / SMAX, q2 = e - q1 * SMAX;
         if (q1 >= ns1 || q2 >= ns2) continue;
@@ -129,8 +130,9 @@ __device__ inline void tile_slot_sums(int tid, int op, int ns1, int ns2, const u
             const int i1 = o1[q1 * LMAX + u];
             for (int v = 0; v < m2; ++v) {
                 const int idx = i1 + o2[q2 * LMAX + v];
-                re += st_re[idx];
-                im += st_im[idx];
+                const C2 q = st[idx];
+                re += q.x;
+                im += q.y;
             }
         }
         out[4 * e + op] = C2{re, im};
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
     __shared__ uint8_t c1[SMAX], c2[SMAX];
     __shared__ uint16_t e1[SMAX * LMAX];   // slot corner (t, a) of block 1 as the offset 144 t + 3 a of its entries
     __shared__ uint8_t e2[SMAX * LMAX];    // slot corner (t, b) of block 2 as the offset 9 t + b
-    __shared__ double st_re[256 * 9], st_im[256 * 9];
+    __shared__ double2 st[256 * 9];   // the 9 entries of every thread's pair, one operator at a time
 
     const int64_t tile = tile0 + blockIdx.x;
     int b1, b2;
@@ -265,20 +267,19 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
                     const double cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
-                    st_re[tid * 9 + 3 * a + b] = cc * sr - k * k * nn * vr[3 * a + b];
-                    st_im[tid * 9 + 3 * a + b] = cc * si - k * k * nn * vi[3 * a + b];
+                    st[tid * 9 + 3 * a + b] = make_double2(cc * sr - k * k * nn * vr[3 * a + b],
+                                                           cc * si - k * k * nn * vi[3 * a + b]);
                 }
         } else {
 #pragma unroll
             for (int e = 0; e < 9; ++e) {
                 double re = op == 0 ? vr[e] : (op == 1 ? kr[e] : (op == 2 ? tr[e] : 0.0));
                 double im = op == 0 ? vi[e] : (op == 1 ? ki[e] : (op == 2 ? ti[e] : 0.0));
-                st_re[tid * 9 + e] = active ? re : 0.0;
-                st_im[tid * 9 + e] = active ? im : 0.0;
+                st[tid * 9 + e] = active ? make_double2(re, im) : make_double2(0.0, 0.0);
             }
         }
         __syncthreads();
-        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st_re, st_im, out);
+        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st, out);
         __syncthreads();
     }
 }
@@ -296,7 +297,7 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
     __shared__ uint8_t c1[SMAX], c2[SMAX];
     __shared__ uint16_t e1[SMAX * LMAX];   // slot corner (t, a) of block 1 as the offset 144 t + 3 a of its entries
     __shared__ uint8_t e2[SMAX * LMAX];    // slot corner (t, b) of block 2 as the offset 9 t + b
-    __shared__ float st_re[256 * 9], st_im[256 * 9];
+    __shared__ float2 st[256 * 9];
 
     const int64_t tile = tile0 + blockIdx.x;
     int b1, b2;
@@ -412,20 +413,19 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
                     const float cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
-                    st_re[tid * 9 + 3 * a + b] = cc * sr - kf * kf * nn * vr[3 * a + b];
-                    st_im[tid * 9 + 3 * a + b] = cc * si - kf * kf * nn * vi[3 * a + b];
+                    st[tid * 9 + 3 * a + b] = make_float2(cc * sr - kf * kf * nn * vr[3 * a + b],
+                                                          cc * si - kf * kf * nn * vi[3 * a + b]);
                 }
         } else {
 #pragma unroll
             for (int e = 0; e < 9; ++e) {
                 float re = op == 0 ? vr[e] : (op == 1 ? kr[e] : (op == 2 ? tr[e] : 0.f));
                 float im = op == 0 ? vi[e] : (op == 1 ? ki[e] : (op == 2 ? ti[e] : 0.f));
-                st_re[tid * 9 + e] = active ? re : 0.f;
-                st_im[tid * 9 + e] = active ? im : 0.f;
+                st[tid * 9 + e] = active ? make_float2(re, im) : make_float2(0.f, 0.f);
             }
         }
         __syncthreads();
-        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st_re, st_im, out);
+        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st, out);
         __syncthreads();
     }
 }
