@@ -142,7 +142,7 @@ def precision_compare(ctx, B, synth, np, steps=2, tol=1e-7):
                      "solves_per_s": round(1.0 / statistics.median(lat), 3),
                      "iterations": st["iterations"], "ir_steps": st["ir_steps"],
                      "rel_residual": st["rel_residual"],
-                     "assembly_device_ms": round(st["t_regular_ms"] + st["t_singular_ms"], 2),
+                     "assembly_device_ms": round(st["t_assembly_ms"], 2),
                      "solve_ms": round(st["t_solve_ms"], 2),
                      "mtf_dense_us": round(1e3 * ms / n, 2),
                      "mtf_dense_GBps": round(eb * (ne * ne + ne * (ne + 1) + ni * ni + ni * (ni + 1)) /
@@ -312,7 +312,7 @@ def main():
         torch.cuda.synchronize()   # traces stay in device memory (HBM-resident output)
         t4 = time.perf_counter()
         for k, v in (("mesh_problem", t1 - t), ("operators_enqueue", t2 - t1), ("projection", t3 - t2),
-                     ("solve", t4 - t3), ("assembly_device", 1e-3 * (stats["t_regular_ms"] + stats["t_singular_ms"]))):
+                     ("solve", t4 - t3), ("assembly_device", 1e-3 * stats["t_assembly_ms"])):
             ph.setdefault(k, []).append(v)
         assert code == B.OK, stats
         return out, stats

@@ -90,10 +90,13 @@ typedef struct {
     int32_t iterations;       /* total Arnoldi steps over all right-hand sides */
     int32_t ir_steps;
     double rel_residual;      /* worst strong-form relative residual, recomputed in FP64 at exit */
-    double t_geometry_ms, t_regular_ms, t_singular_ms, t_projection_ms;
-    double t_matrix_ms;       /* operators + projection */
+    double t_geometry_ms;
+    double t_regular_ms, t_singular_ms;   /* device time of each part, summed over the two meshes */
+    double t_projection_ms;   /* host time of bem_assemble_projection */
+    double t_matrix_ms;       /* t_assembly_ms + t_projection_ms */
     double t_solve_ms;
     double t_iter_ms;         /* t_solve / iterations */
+    double t_assembly_ms;     /* device span of the operator assembly of both meshes */
 } bem_stats;
 
 typedef struct bem_ctx bem_ctx;

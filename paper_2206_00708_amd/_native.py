@@ -22,7 +22,8 @@ class SolverOpts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", i32), ("ir_steps", i32), ("rel_residual", f64),
                 ("t_geometry_ms", f64), ("t_regular_ms", f64), ("t_singular_ms", f64),
-                ("t_projection_ms", f64), ("t_matrix_ms", f64), ("t_solve_ms", f64), ("t_iter_ms", f64)]
+                ("t_projection_ms", f64), ("t_matrix_ms", f64), ("t_solve_ms", f64), ("t_iter_ms", f64),
+                ("t_assembly_ms", f64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -123,7 +123,7 @@ bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch,
 bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw, bool fp32,
                            double2 *contrib, void *ops[4], hipStream_t st);
 bem_status launch_mass_inverse(bem_problem *p, int mesh, hipStream_t st);
-bem_status launch_sym_corrections(bem_problem *p, int mesh);
+bem_status launch_sym_corrections(bem_problem *p, int mesh, hipStream_t st);
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats);
 bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space);
@@ -184,6 +184,8 @@ bem_status resolve_assembly_timing(bem_problem *p)
 {
     if (!p->asm_timing_pending) return BEM_OK;
     BEM_HIP(hipEventSynchronize(p->asm_ev[1][2]));
+    float span = 0;
+    BEM_HIP(hipEventElapsedTime(&span, p->asm_ev[0][0], p->asm_ev[1][2]));
     double t_reg = 0, t_sing = 0;
     for (int m = 0; m < 2; ++m) {
         float a = 0, b = 0;
@@ -194,6 +196,7 @@ bem_status resolve_assembly_timing(bem_problem *p)
     }
     p->t_regular_ms = t_reg;
     p->t_singular_ms = t_sing;
+    p->t_assembly_ms = span;
     p->asm_timing_pending = false;
     return BEM_OK;
 }
@@ -487,7 +490,7 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
             if (s) return s;
         }
         BEM_HIP(hipEventRecord(p->asm_ev[m][2], st));
-        bem_status s = launch_sym_corrections(p, m);
+        bem_status s = launch_sym_corrections(p, m, st);
         if (s) return s;
     }
     p->asm_timing_pending = true;
@@ -504,13 +507,11 @@ bem_status bem_assemble_projection(bem_problem *p)
     auto t0 = std::chrono::steady_clock::now();
     mass_csr(p->ext->h, p->M[0]);
     mass_csr(p->inte->h, p->M[1]);
-    double defect = 0;
-    bem_status s = mortar_csr(p->inte->h, p->ext->h, p->P_ie, &defect);
-    if (s) return s;
-    transpose_csr(p->P_ie, p->P_ei);
     // uploads and inverse masses on the auxiliary stream, after the work queued
     // on the main stream before the operator assembly (or before this call),
-    // so that they overlap the assembly; the main stream waits for them
+    // so that they overlap the assembly; the inverse masses are queued before
+    // the host builds the mortar projection, which then overlaps them too; the
+    // main stream waits for all of it
     if (!ctx->aux) BEM_HIP(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
     hipStream_t ax = ctx->aux;
     if (!p->ev_pre_asm) {
@@ -519,18 +520,24 @@ bem_status bem_assemble_projection(bem_problem *p)
     }
     if (!p->ev_proj) BEM_HIP(hipEventCreateWithFlags(&p->ev_proj, hipEventDisableTiming));
     BEM_HIP(hipStreamWaitEvent(ax, p->ev_pre_asm, 0));
-    s = upload(ctx, p->P_ie_ptr, p->P_ie.ptr, ax);
-    if (!s) s = upload(ctx, p->P_ie_col, p->P_ie.col, ax);
-    if (!s) s = upload(ctx, p->P_ie_val, p->P_ie.val, ax);
-    if (!s) s = upload(ctx, p->P_ei_ptr, p->P_ei.ptr, ax);
-    if (!s) s = upload(ctx, p->P_ei_col, p->P_ei.col, ax);
-    if (!s) s = upload(ctx, p->P_ei_val, p->P_ei.val, ax);
+    bem_status s = BEM_OK;
     for (int m = 0; m < 2 && !s; ++m) {
         s = upload(ctx, p->M_ptr[m], p->M[m].ptr, ax);
         if (!s) s = upload(ctx, p->M_col[m], p->M[m].col, ax);
         if (!s) s = upload(ctx, p->M_val[m], p->M[m].val, ax);
         if (!s) s = launch_mass_inverse(p, m, ax);
     }
+    if (s) return s;
+    double defect = 0;
+    s = mortar_csr(p->inte->h, p->ext->h, p->P_ie, &defect);
+    if (s) return s;
+    transpose_csr(p->P_ie, p->P_ei);
+    s = upload(ctx, p->P_ie_ptr, p->P_ie.ptr, ax);
+    if (!s) s = upload(ctx, p->P_ie_col, p->P_ie.col, ax);
+    if (!s) s = upload(ctx, p->P_ie_val, p->P_ie.val, ax);
+    if (!s) s = upload(ctx, p->P_ei_ptr, p->P_ei.ptr, ax);
+    if (!s) s = upload(ctx, p->P_ei_col, p->P_ei.col, ax);
+    if (!s) s = upload(ctx, p->P_ei_val, p->P_ei.val, ax);
     if (s) return s;
     BEM_HIP(hipEventRecord(p->ev_proj, ax));
     BEM_HIP(hipStreamWaitEvent(ctx->stream, p->ev_proj, 0));

@@ -247,7 +247,7 @@ struct bem_problem {
     std::vector<int32_t> ell_col_h[2];   // host staging of the ELL mass rows (kept for async copies)
     std::vector<double> ell_val_h[2];
     bemtx::DevMem M_ptr[2], M_col[2], M_val[2], M_ell_col[2], M_ell_val[2];
-    double t_geometry_ms = 0, t_regular_ms = 0, t_singular_ms = 0, t_projection_ms = 0;
+    double t_geometry_ms = 0, t_regular_ms = 0, t_singular_ms = 0, t_projection_ms = 0, t_assembly_ms = 0;
     hipEvent_t asm_ev[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
     bool asm_timing_pending = false;
     // ordering of the set-up on the auxiliary stream: it starts after the work
