@@ -112,31 +112,54 @@ __device__ inline void tile_of(int64_t t, int nb, int &b1, int &b2)
     b2 = b + (int)(t - ((int64_t)b * nb - (int64_t)b * (b - 1) / 2));
 }
 
-// Per-slot sums of the staged 9 entries of every triangle pair of the tile,
-// in a fixed order: entry (q1, q2) adds the entries (a, b) of every pair
-// whose test triangle has slot q1 at corner a and trial triangle slot q2 at
-// corner b.  Written to out[4 * e + op] (tile layout [entry][op]).
+// Per-slot sums of the staged 9 entries of every triangle pair of the tile:
+// entry (q1, q2) adds the entries (a, b) of every pair whose test triangle
+// has slot q1 at corner a and trial triangle slot q2 at corner b.  The sum
+// separates over the two blocks, so it runs in two stages whose loop lengths
+// are the same on every lane of a wave:
+//   1. P[u][q2] = sum over the corners (t2, b) of trial slot q2 of the entry
+//      of test corner u = (t1, a); one lane per test corner, one trial slot
+//      per wave at a time;
+//   2. entry (q1, q2) = sum over the test corners u of slot q1 of P[u][q2];
+//      one lane per trial slot, one test slot per half-wave at a time.
+// Staged entries: st[t1 * ST_ROW + 9 t2 + 3 a + b] (the row padding keeps
+// the 16-byte reads of stage 1 on distinct LDS banks).  Fixed summation
+// order; written to out[4 * e + op] (tile layout [entry][op]).
+constexpr int ST_ROW = 9 * BT + 1;
+
 template <class C2>
 __device__ inline void tile_slot_sums(int tid, int op, int ns1, int ns2, const uint8_t *c1, const uint8_t *c2,
-                                      const uint16_t *o1, const uint8_t *o2, const C2 *st, C2 *out)
+                                      const uint8_t *u1, const uint8_t *o2, const C2 *st, C2 *P, C2 *out)
 {
     using R = decltype(C2::x);
-    for (int e = tid; e < SMAX * SMAX; e += 256) {
-        const int q1 = e / SMAX, q2 = e - q1 * SMAX;
-        if (q1 >= ns1 || q2 >= ns2) continue;
-        R re = 0, im = 0;
-        const int m1 = c1[q1], m2 = c2[q2];
-        for (int u = 0; u < m1; ++u) {
-            const int i1 = o1[q1 * LMAX + u];
+    const int wave = tid >> 6, lane = tid & 63;
+    if (lane < 3 * BT) {
+        const int t = lane / 3, a = lane - 3 * t;
+        const C2 *row = st + t * ST_ROW + 3 * a;
+        for (int q2 = wave; q2 < ns2; q2 += 4) {
+            const int m2 = c2[q2];
+            R re = 0, im = 0;
             for (int v = 0; v < m2; ++v) {
-                const int idx = i1 + o2[q2 * LMAX + v];
-                const C2 q = st[idx];
-                re += q.x;
-                im += q.y;
+                const C2 x = row[o2[q2 * LMAX + v]];
+                re += x.x;
+                im += x.y;
             }
+            P[lane * SMAX + q2] = C2{re, im};
         }
-        out[4 * e + op] = C2{re, im};
     }
+    __syncthreads();
+    const int q2 = lane & 31;
+    if (q2 < ns2)
+        for (int q1 = wave + 4 * (lane >> 5); q1 < ns1; q1 += 8) {
+            const int m1 = c1[q1];
+            R re = 0, im = 0;
+            for (int u = 0; u < m1; ++u) {
+                const C2 x = P[u1[q1 * LMAX + u] * SMAX + q2];
+                re += x.x;
+                im += x.y;
+            }
+            out[4 * (q1 * SMAX + q2) + op] = C2{re, im};
+        }
 }
 
 struct TileArgsF {
@@ -156,9 +179,10 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
     __shared__ TriGeo gX[BT], gY[BT];
     __shared__ int32_t vX[BT * 3], vY[BT * 3];
     __shared__ uint8_t c1[SMAX], c2[SMAX];
-    __shared__ uint16_t e1[SMAX * LMAX];   // slot corner (t, a) of block 1 as the offset 144 t + 3 a of its entries
+    __shared__ uint8_t e1[SMAX * LMAX];    // slot corner (t, a) of block 1 as the test corner 3 t + a
     __shared__ uint8_t e2[SMAX * LMAX];    // slot corner (t, b) of block 2 as the offset 9 t + b
-    __shared__ double2 st[256 * 9];   // the 9 entries of every thread's pair, one operator at a time
+    __shared__ double2 st[BT * ST_ROW];   // the 9 entries of every thread's pair, one operator at a time
+    __shared__ double2 P[3 * BT * SMAX];  // test corner x trial slot partial sums
 
     const int64_t tile = tile0 + blockIdx.x;
     int b1, b2;
@@ -179,13 +203,13 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
         if (tid < SMAX) { c1[tid] = A.slot_cnt[b1 * SMAX + tid]; c2[tid] = A.slot_cnt[b2 * SMAX + tid]; }
         for (int q = tid; q < SMAX * LMAX; q += 256) {
             const int en1 = A.slot_ent[(size_t)b1 * SMAX * LMAX + q], en2 = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
-            e1[q] = (uint16_t)((en1 / 3) * 144 + 3 * (en1 % 3));
+            e1[q] = (uint8_t)en1;
             e2[q] = (uint8_t)((en2 / 3) * 9 + en2 % 3);
         }
     }
     __syncthreads();
 
-    const int t1 = tid >> 4, t2 = tid & 15;
+    const int t1 = tid >> 4, t2 = tid & 15, sbase = t1 * ST_ROW + 9 * t2;
     bool active = t1 < n1 && t2 < n2;
     if (active) {
         for (int a = 0; a < 3; ++a)
@@ -267,7 +291,7 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
                     const double cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
-                    st[tid * 9 + 3 * a + b] = make_double2(cc * sr - k * k * nn * vr[3 * a + b],
+                    st[sbase + 3 * a + b] = make_double2(cc * sr - k * k * nn * vr[3 * a + b],
                                                            cc * si - k * k * nn * vi[3 * a + b]);
                 }
         } else {
@@ -275,11 +299,11 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
             for (int e = 0; e < 9; ++e) {
                 double re = op == 0 ? vr[e] : (op == 1 ? kr[e] : (op == 2 ? tr[e] : 0.0));
                 double im = op == 0 ? vi[e] : (op == 1 ? ki[e] : (op == 2 ? ti[e] : 0.0));
-                st[tid * 9 + e] = active ? make_double2(re, im) : make_double2(0.0, 0.0);
+                st[sbase + e] = active ? make_double2(re, im) : make_double2(0.0, 0.0);
             }
         }
         __syncthreads();
-        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st, out);
+        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st, P, out);
         __syncthreads();
     }
 }
@@ -295,9 +319,10 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
     __shared__ TriGeoF gX[BT], gY[BT];
     __shared__ int32_t vX[BT * 3], vY[BT * 3];
     __shared__ uint8_t c1[SMAX], c2[SMAX];
-    __shared__ uint16_t e1[SMAX * LMAX];   // slot corner (t, a) of block 1 as the offset 144 t + 3 a of its entries
+    __shared__ uint8_t e1[SMAX * LMAX];    // slot corner (t, a) of block 1 as the test corner 3 t + a
     __shared__ uint8_t e2[SMAX * LMAX];    // slot corner (t, b) of block 2 as the offset 9 t + b
-    __shared__ float2 st[256 * 9];
+    __shared__ float2 st[BT * ST_ROW];
+    __shared__ float2 P[3 * BT * SMAX];
 
     const int64_t tile = tile0 + blockIdx.x;
     int b1, b2;
@@ -318,13 +343,13 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
         if (tid < SMAX) { c1[tid] = A.slot_cnt[b1 * SMAX + tid]; c2[tid] = A.slot_cnt[b2 * SMAX + tid]; }
         for (int q = tid; q < SMAX * LMAX; q += 256) {
             const int en1 = A.slot_ent[(size_t)b1 * SMAX * LMAX + q], en2 = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
-            e1[q] = (uint16_t)((en1 / 3) * 144 + 3 * (en1 % 3));
+            e1[q] = (uint8_t)en1;
             e2[q] = (uint8_t)((en2 / 3) * 9 + en2 % 3);
         }
     }
     __syncthreads();
 
-    const int t1 = tid >> 4, t2 = tid & 15;
+    const int t1 = tid >> 4, t2 = tid & 15, sbase = t1 * ST_ROW + 9 * t2;
     bool active = t1 < n1 && t2 < n2;
     if (active) {
         for (int a = 0; a < 3; ++a)
@@ -413,7 +438,7 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
                     const float cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
-                    st[tid * 9 + 3 * a + b] = make_float2(cc * sr - kf * kf * nn * vr[3 * a + b],
+                    st[sbase + 3 * a + b] = make_float2(cc * sr - kf * kf * nn * vr[3 * a + b],
                                                           cc * si - kf * kf * nn * vi[3 * a + b]);
                 }
         } else {
@@ -421,11 +446,11 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
             for (int e = 0; e < 9; ++e) {
                 float re = op == 0 ? vr[e] : (op == 1 ? kr[e] : (op == 2 ? tr[e] : 0.f));
                 float im = op == 0 ? vi[e] : (op == 1 ? ki[e] : (op == 2 ? ti[e] : 0.f));
-                st[tid * 9 + e] = active ? make_float2(re, im) : make_float2(0.f, 0.f);
+                st[sbase + e] = active ? make_float2(re, im) : make_float2(0.f, 0.f);
             }
         }
         __syncthreads();
-        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st, out);
+        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st, P, out);
         __syncthreads();
     }
 }
