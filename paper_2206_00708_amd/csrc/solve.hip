@@ -15,7 +15,7 @@
 //                          columns per workgroup.
 //   mtf_sym_tile           one product with the dense blocks of both meshes,
 //                          K read in full, V and D only on and above the
-//                          diagonal, T = K^T (64 x 64 or 128 x 128 tiles,
+//                          diagonal, T = K^T (128 x 128 tiles,
 //                          16-byte non-temporal loads; row sums reduced with
 //                          DPP, column sums per lane); per-tile partials.
 //   mtf_sym_combine        fixed-order sum of the tile partials, the
@@ -471,15 +471,18 @@ template <> struct Cx<double> { using T = double2; };
 // D_ij = D_ji, T_ij = K_ji; the singular rule is applied to both orders of a
 // vertex-sharing pair and is not symmetric to rounding, so the differences
 // on those entries (the near entries) are added by the combine kernel.  One
-// workgroup per pair of 64 x 64 tiles (a <= b): the tiles (a, b) of K, V, D
+// workgroup per pair of 128 x 128 tiles (a <= b): the tiles (a, b) of K, V, D
 // and (b, a) of K are streamed once; products along rows reduce across the
 // wave (DPP), products down columns accumulate per lane.  The partial sums of row
 // tile R with column tile Cc go to part[Cc][row] (each written by exactly one
 // workgroup) and are summed in a fixed order.
 
-// Tile edge: 64 for complex128 (one column per lane, 16-byte loads), 128 for
-// complex64 (two adjacent columns per lane, 16-byte loads).
-template <class E> constexpr int sym_tile() { return sizeof(E) == 16 ? 64 : 128; }
+// Tile edge 128, two columns per lane: for complex128 the columns lane and
+// lane + 64 (every 16-byte load of a wave covers 1 KB of a row, the two
+// together the row's 2 KB), for complex64 two adjacent columns (one 16-byte
+// load).  The wider rows of the tile keep DRAM accesses in longer runs than
+// 64-column tiles do.
+template <class E> constexpr int sym_tile() { return 128; }
 __host__ __device__ inline int sym_ntile(int nv, int ts) { return (nv + ts - 1) / ts; }
 
 // task t -> tile pair (a, b), a <= b, in row-major order of the upper triangle
@@ -545,7 +548,14 @@ __device__ inline void ld_cols(const E *M, int64_t ld, int row, int col0, int nv
     using R = decltype(C::x);
     const bool ok = row < nv && col0 < nv;
     const E *p = M + (int64_t)min(row, nv - 1) * ld + (col0 < nv ? col0 : 0);
-    if constexpr (CPL == 1) {
+    if constexpr (sizeof(E) == 16 && CPL == 2) {   // columns col0 and col0 + 64
+        const E e0 = ld_entry(p);
+        out[0] = ok ? C{(R)e0.x, (R)e0.y} : C{0, 0};
+        const bool ok1 = row < nv && col0 + 64 < nv;
+        const E *p1 = M + (int64_t)min(row, nv - 1) * ld + (col0 + 64 < nv ? col0 + 64 : 0);
+        const E e1 = ld_entry(p1);
+        out[1] = ok1 ? C{(R)e1.x, (R)e1.y} : C{0, 0};
+    } else if constexpr (CPL == 1) {
         const E e = ld_entry(p);
         out[0] = ok ? C{(R)e.x, (R)e.y} : C{0, 0};
     } else {   // col0 even and the row stride a multiple of 16: the pair is in the row
@@ -591,11 +601,13 @@ __global__ __launch_bounds__(256) void mtf_sym_tile_kernel(MtfArgs A, const doub
     }
     __syncthreads();
     const bool diag = a == b;
-    const int c0 = lane * CPL;                  // this lane's first column inside the tile
+    constexpr bool split = sizeof(E) == 16;    // complex128: columns lane + 64 u, else adjacent pairs
+    const int c0 = split ? lane : lane * CPL;  // this lane's first column inside the tile
     const int j0 = b * TS + c0, ja0 = a * TS + c0;
+    auto colof = [&](int u) { return split ? c0 + 64 * u : c0 + u; };
     C vb[CPL], wb[CPL], va[CPL];
 #pragma unroll
-    for (int u = 0; u < CPL; ++u) { vb[u] = svb[c0 + u]; wb[u] = swb[c0 + u]; va[u] = sva[c0 + u]; }
+    for (int u = 0; u < CPL; ++u) { vb[u] = svb[colof(u)]; wb[u] = swb[colof(u)]; va[u] = sva[colof(u)]; }
     CAcc<R> c1b[CPL], c2b[CPL], c2a[CPL];
 #pragma unroll 1
     for (int rr = 0; rr < RPW; ++rr) {
@@ -613,7 +625,7 @@ __global__ __launch_bounds__(256) void mtf_sym_tile_kernel(MtfArgs A, const doub
         CAcc<R> y1, y2, y1b;
 #pragma unroll
         for (int u = 0; u < CPL; ++u) {
-            const int c = c0 + u;
+            const int c = colof(u);
             // rows of tile a: y1 -= K v, y1 += V w, y2 += D v (V, D on and above the diagonal)
             y1.msub(kab[u], vb[u]);
             if (!diag || c >= r) {
@@ -640,9 +652,9 @@ __global__ __launch_bounds__(256) void mtf_sym_tile_kernel(MtfArgs A, const doub
     }
 #pragma unroll
     for (int u = 0; u < CPL; ++u) {
-        colres[wave][0][c0 + u] = C{c1b[u].x, c1b[u].y};
-        colres[wave][1][c0 + u] = C{c2b[u].x, c2b[u].y};
-        colres[wave][2][c0 + u] = C{c2a[u].x, c2a[u].y};
+        colres[wave][0][colof(u)] = C{c1b[u].x, c1b[u].y};
+        colres[wave][1][colof(u)] = C{c2b[u].x, c2b[u].y};
+        colres[wave][2][colof(u)] = C{c2a[u].x, c2a[u].y};
     }
     __syncthreads();
     for (int r = tid; r < TS; r += 256) {
@@ -1481,8 +1493,8 @@ MtfArgs make_args(const bem_problem *p)
 
 size_t split_part_bytes(int ne, int ni)
 {
-    const int nchunk = std::max({split_nchunk(ne, MASS_CW_MAX), split_nchunk(ni, MASS_CW_MAX), sym_ntile(ne, 64),
-                                 sym_ntile(ni, 64)});
+    const int nchunk = std::max({split_nchunk(ne, MASS_CW_MAX), split_nchunk(ni, MASS_CW_MAX), sym_ntile(ne, sym_tile<double2>()),
+                                 sym_ntile(ni, sym_tile<double2>())});
     return (size_t)nchunk * (ne + ni) * sizeof(double4);
 }
 
