@@ -106,8 +106,8 @@ bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes)
     return BEM_OK;
 }
 
-template <class T>
-static bem_status upload(bem_ctx *ctx, DevMem &m, const std::vector<T> &v, hipStream_t st = nullptr)
+template <class T, class A>
+static bem_status upload(bem_ctx *ctx, DevMem &m, const std::vector<T, A> &v, hipStream_t st = nullptr)
 {
     bem_status s = dev_alloc(ctx, m, v.size() * sizeof(T));
     if (s) return s;

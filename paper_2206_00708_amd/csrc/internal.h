@@ -10,6 +10,8 @@
 #include <mutex>
 #include <utility>
 #include <string>
+#include <cstdlib>
+#include <new>
 #include <vector>
 
 #include "../../include/bemtx.h"
@@ -74,26 +76,60 @@ struct DevMem {
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
 
+// Host blocks of 128 KB and more (mesh tables, CSR arrays) come from a
+// process-wide cache of freed blocks (exact sizes rounded to 64 KB, at most
+// 256 MB kept): a mesh built after another of similar size reuses resident
+// pages instead of mapping and faulting in fresh ones.
+void *host_block_get(size_t bytes);
+void host_block_put(void *p, size_t bytes);
+constexpr size_t kHostBlockMin = size_t(128) << 10;
+inline size_t host_block_round(size_t bytes) { return (bytes + 0xFFFF) & ~size_t(0xFFFF); }
+
+template <class T> struct HostCacheAlloc {
+    using value_type = T;
+    HostCacheAlloc() = default;
+    template <class U> HostCacheAlloc(const HostCacheAlloc<U> &) {}
+    T *allocate(size_t n)
+    {
+        const size_t b = n * sizeof(T);
+        if (b < kHostBlockMin) {
+            void *p = std::malloc(b ? b : 1);
+            if (!p) throw std::bad_alloc();
+            return static_cast<T *>(p);
+        }
+        return static_cast<T *>(host_block_get(host_block_round(b)));
+    }
+    void deallocate(T *p, size_t n)
+    {
+        const size_t b = n * sizeof(T);
+        if (b < kHostBlockMin) std::free(p);
+        else host_block_put(p, host_block_round(b));
+    }
+    template <class U> bool operator==(const HostCacheAlloc<U> &) const { return true; }
+    template <class U> bool operator!=(const HostCacheAlloc<U> &) const { return false; }
+};
+template <class T> using HVec = std::vector<T, HostCacheAlloc<T>>;
+
 // Host-side mesh tables (internal numbering) and their device copies.
 struct MeshData {
     int64_t nv = 0, nt = 0;
-    std::vector<double> xyz_user;      // caller numbering
-    std::vector<int32_t> tri_user;
-    std::vector<int32_t> v_of_int;     // internal vertex -> caller vertex
-    std::vector<int32_t> int_of_v;     // caller vertex -> internal vertex
-    std::vector<double> xyz;           // internal numbering [nv][3]
-    std::vector<int32_t> tri;          // internal triangles, internal vertex ids [nt][3]
+    HVec<double> xyz_user;      // caller numbering
+    HVec<int32_t> tri_user;
+    HVec<int32_t> v_of_int;     // internal vertex -> caller vertex
+    HVec<int32_t> int_of_v;     // caller vertex -> internal vertex
+    HVec<double> xyz;           // internal numbering [nv][3]
+    HVec<int32_t> tri;          // internal triangles, internal vertex ids [nt][3]
     // blocks
     int32_t nb = 0;
-    std::vector<int32_t> blk_start;    // [nb+1]
-    std::vector<int32_t> blk_nslot;    // [nb]
-    std::vector<int32_t> blk_slots;    // [nb][SMAX] internal vertex ids
-    std::vector<uint8_t> slot_cnt;     // [nb][SMAX]
-    std::vector<uint8_t> slot_ent;     // [nb][SMAX][LMAX] = tlocal*3 + corner
-    std::vector<int32_t> memb_ptr;     // [nv+1]
-    std::vector<int32_t> memb;         // block<<8 | slot
+    HVec<int32_t> blk_start;    // [nb+1]
+    HVec<int32_t> blk_nslot;    // [nb]
+    HVec<int32_t> blk_slots;    // [nb][SMAX] internal vertex ids
+    HVec<uint8_t> slot_cnt;     // [nb][SMAX]
+    HVec<uint8_t> slot_ent;     // [nb][SMAX][LMAX] = tlocal*3 + corner
+    HVec<int32_t> memb_ptr;     // [nv+1]
+    HVec<int32_t> memb;         // block<<8 | slot
     // singular pairs and near-field scatter lists
-    std::vector<SingPair> sing;        // sorted by kind (3, 2, 1)
+    HVec<SingPair> sing;        // sorted by kind (3, 2, 1)
     int32_t nsing_kind[4] = {0, 0, 0, 0};
     std::vector<int32_t> near_i, near_j, near_ptr, near_src;   // src = pair*9 + a*3 + b
     std::vector<int32_t> near_row;   // near entries of row i: [near_row[i], near_row[i + 1])
@@ -112,8 +148,8 @@ struct MeshDev {
 // CSR in internal numbering
 struct Csr {
     int64_t nrows = 0, ncols = 0;
-    std::vector<int32_t> ptr, col;
-    std::vector<double> val;
+    HVec<int32_t> ptr, col;
+    HVec<double> val;
 };
 
 bem_status set_error(bem_status code, const std::string &msg);

@@ -18,6 +18,7 @@
 #include <numeric>
 #include <atomic>
 #include <condition_variable>
+#include <map>
 #include <mutex>
 #include <thread>
 
@@ -116,6 +117,52 @@ class Pool {
     uint64_t gen_ = 0;
 };
 }  // namespace
+
+namespace {
+struct HostBlocks {
+    std::mutex mu;
+    std::multimap<size_t, void *> free_blocks;   // exact (rounded) size -> block
+    size_t cached = 0;
+    static HostBlocks &get()
+    {
+        static HostBlocks *h = new HostBlocks;   // never destroyed: blocks may come back during exit
+        return *h;
+    }
+};
+constexpr size_t kHostCacheMax = size_t(256) << 20;
+}  // namespace
+
+void *host_block_get(size_t bytes)
+{
+    HostBlocks &h = HostBlocks::get();
+    {
+        std::lock_guard<std::mutex> lk(h.mu);
+        auto it = h.free_blocks.find(bytes);
+        if (it != h.free_blocks.end()) {
+            void *p = it->second;
+            h.free_blocks.erase(it);
+            h.cached -= bytes;
+            return p;
+        }
+    }
+    void *p = std::malloc(bytes);
+    if (!p) throw std::bad_alloc();
+    return p;
+}
+
+void host_block_put(void *p, size_t bytes)
+{
+    HostBlocks &h = HostBlocks::get();
+    {
+        std::lock_guard<std::mutex> lk(h.mu);
+        if (h.cached + bytes <= kHostCacheMax) {
+            h.free_blocks.emplace(bytes, p);
+            h.cached += bytes;
+            return;
+        }
+    }
+    std::free(p);
+}
 
 void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &f)
 {
