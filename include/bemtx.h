@@ -132,7 +132,8 @@ bem_status bem_ctx_trim(bem_ctx *ctx);
  * (Gram-Schmidt update), 8 "arnoldi_finish" (Hessenberg column, Givens
  * rotation, residual estimate), 9 "mass_inverse", 10 "block_gemm"
  * (multi-RHS operator product), 11 "mass_gemm" (multi-RHS inverse-mass
- * product), 12 "krylov_normalize" (new Krylov vector scaled to unit norm).  Every launch of a kernel whose bit is set in
+ * product), 12 "krylov_normalize" (new Krylov vector scaled to unit norm),
+ * 13 "field" (field off the surface, bem_field).  Every launch of a kernel whose bit is set in
  * kernel_mask is bracketed by HIP events on the context stream (a few
  * microseconds of overhead per launch); 0 disables.  Setting the mask resets
  * the totals.  bem_ctx_kernel_time synchronises the stream and returns the
@@ -232,6 +233,38 @@ bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b
  * its single solve up to FP32 rounding of the products). */
 bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
                      void *traces, bem_memspace space, bem_stats *stats);
+
+/* Total acoustic field at points off the surface, from the unknowns of
+ * bem_solve, by the representation formulas (Sec. 2, Eq. "representation"):
+ * at an exterior point the incident wave exp(i k_ext d.x) plus
+ * [SLP_ext w_ext - DLP_ext v_ext](x), at an interior point
+ * [DLP_int v_int - SLP_int w_int](x) (the interior potentials of the
+ * printed system are -gamma_D p and -gamma_N p), with
+ * [SLP psi](x) = int G psi, [DLP phi](x) = int dG/dn(y) phi,
+ * G = exp(i k r) / (4 pi r), outward normals, the P1 functions of the
+ * nodal unknowns, and each triangle integral by the 6-point rule of the
+ * regular assembly (no near-surface refinement: points close to a mesh get
+ * that rule's error; a point on a quadrature point gives a non-finite value).
+ * dirs: host double[nrhs][3] unit vectors, the plane waves of the solve;
+ * traces: complex128 [nrhs][2 N_ext + 2 N_int] as written by bem_solve;
+ * points: double [npts][3]; region: int32 [npts], 0 exterior, 1 interior
+ * (bem_mesh_winding of the exterior mesh decides it where the caller has no
+ * better rule); field: complex128 [nrhs][npts], caller order.  traces,
+ * points, region and field are all in `space`; the call copies the points
+ * and regions to the host to sort them by region, and synchronises the
+ * context stream.  Errors: BEM_E_ARG (null pointers with npts > 0, a
+ * region other than 0 or 1, directions not of unit length, more than 2^28
+ * points), BEM_E_OOM, BEM_E_DEVICE.  npts = 0 does nothing. */
+bem_status bem_field(bem_problem *p, const double *dirs, int32_t nrhs, const void *traces, const double *points,
+                     const int32_t *region, int64_t npts, void *field, bem_memspace space);
+
+/* Winding numbers of a mesh at points: the sum over triangles of the signed
+ * solid angle (Van Oosterom and Strackee, 1983) over 4 pi, 1 inside a
+ * closed outward-oriented mesh and 0 outside (up to rounding), in between
+ * near the surface.  points: double [npts][3]; w: double [npts]; both in
+ * `space`.  Synchronises the context stream.  Errors: BEM_E_ARG,
+ * BEM_E_OOM, BEM_E_DEVICE. */
+bem_status bem_mesh_winding(const bem_mesh *m, const double *points, int64_t npts, double *w, bem_memspace space);
 
 /* Copy one dense operator: mesh 0 = exterior, 1 = interior; op one of 'V',
  * 'K', 'T', 'D'.  dst: [N][N] in caller numbering, complex128 for BEM_C128

@@ -31,6 +31,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _dev_f64(a, device):
+    """A contiguous float64 device tensor holding a (tensor or array-like)."""
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
 class Context:
     """bem_ctx_create / bem_ctx_destroy on a torch device and stream."""
 
@@ -51,7 +58,7 @@ class Context:
 
     KERNELS = ("regular_tiles", "gather_tiles", "singular_pairs", "near_scatter", "mtf_dense", "mass_apply",
                "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse", "block_gemm", "mass_gemm",
-               "krylov_normalize")
+               "krylov_normalize", "field")
 
     def set_kernel_timing(self, kernels=()):
         """Time every launch of the named kernels with HIP events (empty: off)."""
@@ -91,6 +98,14 @@ class Mesh:
                                  self.tri.shape[0], ctypes.byref(h)))
         self._h = h
         self.nv = self.xyz.shape[0]
+
+    def winding(self, points):
+        """bem_mesh_winding: winding numbers (1 inside, 0 outside) at points
+        float64 [m,3] (a device tensor, or anything numpy takes)."""
+        pts = _dev_f64(points, self.ctx.device).reshape(-1, 3)
+        out = torch.empty(pts.shape[0], dtype=torch.float64, device=self.ctx.device)
+        _check(N.load().bem_mesh_winding(self._h, _ptr(pts), pts.shape[0], _ptr(out), DEVICE))
+        return out
 
     def close(self):
         if getattr(self, "_h", None):
@@ -167,6 +182,24 @@ class Problem:
         code = _check(N.load().bem_solve(self._h, d.ctypes.data, d.shape[0], ctypes.byref(opts), _ptr(out), DEVICE,
                                          ctypes.byref(st)))
         return out, st.as_dict(), code
+
+    def field(self, dirs, traces, points, region=None):
+        """bem_field: total field [nrhs, m] at points [m,3] from the traces of
+        solve() for the plane waves dirs; region [m] is 1 for interior and 0
+        for exterior points (default: by the exterior mesh's winding number,
+        interior where it exceeds 1/2)."""
+        d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
+        pts = _dev_f64(points, self.ctx.device).reshape(-1, 3)
+        if region is None:
+            region = (self.ext.winding(pts) > 0.5).to(torch.int32)
+        reg = torch.as_tensor(region, device=self.ctx.device).to(torch.int32).contiguous()
+        x = traces.to(device=self.ctx.device, dtype=torch.complex128).contiguous()
+        if x.numel() != d.shape[0] * self.n or reg.numel() != pts.shape[0]:
+            raise ValueError("traces must be [nrhs, n] and region [m]")
+        out = torch.empty((d.shape[0], pts.shape[0]), dtype=torch.complex128, device=self.ctx.device)
+        _check(N.load().bem_field(self._h, d.ctypes.data, d.shape[0], _ptr(x), _ptr(pts), _ptr(reg), pts.shape[0],
+                                  _ptr(out), DEVICE))
+        return out
 
     def operator(self, mesh, op):
         nv = self.ext.nv if mesh == 0 else self.inte.nv

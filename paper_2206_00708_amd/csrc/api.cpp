@@ -124,6 +124,11 @@ bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *gl
                            double2 *contrib, void *ops[4], hipStream_t st);
 bem_status launch_mass_inverse(bem_problem *p, int mesh, hipStream_t st);
 bem_status launch_sym_corrections(bem_problem *p, int mesh, hipStream_t st);
+bem_status launch_field_region(bem_problem *p, int region, int np, const double *pts, const int32_t *dst_index,
+                               const double2 *x_int, const double *dir, double2 *field, DevMem &dens, DevMem &part,
+                               hipStream_t st);
+bem_status launch_field_permute(bem_problem *p, const double2 *x_caller, double2 *x_int, hipStream_t st);
+bem_status launch_winding(const bem_mesh *m, int np, const double *pts, double *w, DevMem &part, hipStream_t st);
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats);
 bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space);
@@ -133,7 +138,7 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, v
 
 const char *const kKernelNames[K_COUNT] = {"regular_tiles", "gather_tiles", "singular_pairs", "near_scatter",
                                            "mtf_dense", "mass_apply", "cgs_dots", "cgs_update", "arnoldi_finish",
-                                           "mass_inverse", "block_gemm", "mass_gemm", "krylov_normalize"};
+                                           "mass_inverse", "block_gemm", "mass_gemm", "krylov_normalize", "field"};
 
 static hipEvent_t take_event(bem_ctx *c)
 {
@@ -706,6 +711,104 @@ bem_status bem_host_gauss_legendre(int32_t n, double *x, double *w)
 {
     if (n < 1 || n > NG_MAX || !x || !w) return set_error(BEM_E_ARG, "n must be in 1..16");
     gauss_legendre01(n, x, w);
+    return BEM_OK;
+}
+
+
+bem_status bem_field(bem_problem *p, const double *dirs, int32_t nrhs, const void *traces, const double *points,
+                     const int32_t *region, int64_t npts, void *field, bem_memspace space)
+{
+    if (!p || !dirs || !traces || nrhs < 1 || npts < 0) return set_error(BEM_E_ARG, "bad argument");
+    if (npts > 0 && (!points || !region || !field)) return set_error(BEM_E_ARG, "null points, region or field");
+    if (npts > (int64_t)1 << 28) return set_error(BEM_E_ARG, "at most 2^28 points per call");
+    if (space != BEM_HOST && space != BEM_DEVICE) return set_error(BEM_E_ARG, "bad memory space");
+    for (int r = 0; r < nrhs; ++r) {
+        const double l = std::sqrt(dirs[3 * r] * dirs[3 * r] + dirs[3 * r + 1] * dirs[3 * r + 1] + dirs[3 * r + 2] * dirs[3 * r + 2]);
+        if (!(std::fabs(l - 1.0) < 1e-6)) return set_error(BEM_E_ARG, "directions must be unit vectors");
+    }
+    if (npts == 0) return BEM_OK;
+    bem_ctx *ctx = p->ctx;
+    BEM_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int np = (int)npts;
+    // points and regions on the host, to sort the points by region
+    std::vector<double> hp;
+    std::vector<int32_t> hr;
+    const double *P = points;
+    const int32_t *Rg = region;
+    if (space == BEM_DEVICE) {
+        hp.resize((size_t)3 * np);
+        hr.resize(np);
+        BEM_HIP(hipMemcpyAsync(hp.data(), points, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        BEM_HIP(hipMemcpyAsync(hr.data(), region, hr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        BEM_HIP(hipStreamSynchronize(st));
+        P = hp.data();
+        Rg = hr.data();
+    }
+    std::vector<int32_t> order;
+    order.reserve(np);
+    int cnt[2] = {0, 0};
+    for (int m = 0; m < 2; ++m)
+        for (int i = 0; i < np; ++i) {
+            if (Rg[i] != 0 && Rg[i] != 1) return set_error(BEM_E_ARG, "region must be 0 (exterior) or 1 (interior)");
+            if (Rg[i] == m) { order.push_back(i); ++cnt[m]; }
+        }
+    std::vector<double> sp((size_t)3 * np);
+    for (int o = 0; o < np; ++o)
+        for (int c = 0; c < 3; ++c) sp[(size_t)3 * o + c] = P[(size_t)3 * order[o] + c];
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne + 2 * ni;
+    DevMem dpts, didx, xin, xint, fout, dens, part;
+    bem_status s = upload(ctx, dpts, sp);
+    if (!s) s = upload(ctx, didx, order);
+    if (!s) s = dev_alloc(ctx, xint, (size_t)n * sizeof(double2));
+    if (s) return s;
+    const double2 *X = static_cast<const double2 *>(traces);
+    if (space == BEM_HOST) {
+        s = dev_alloc(ctx, xin, (size_t)nrhs * n * sizeof(double2));
+        if (!s) s = dev_alloc(ctx, fout, (size_t)nrhs * np * sizeof(double2));
+        if (s) return s;
+        BEM_HIP(hipMemcpyAsync(xin.ptr, traces, (size_t)nrhs * n * sizeof(double2), hipMemcpyHostToDevice, st));
+        X = xin.as<double2>();
+    }
+    double2 *Fo = space == BEM_HOST ? fout.as<double2>() : static_cast<double2 *>(field);
+    for (int r = 0; r < nrhs; ++r) {
+        s = launch_field_permute(p, X + (size_t)r * n, xint.as<double2>(), st);
+        for (int m = 0, off = 0; m < 2 && !s; off += cnt[m], ++m)
+            s = launch_field_region(p, m, cnt[m], dpts.as<double>() + (size_t)3 * off, didx.as<int32_t>() + off,
+                                    xint.as<double2>(), dirs + 3 * r, Fo + (size_t)r * np, dens, part, st);
+        if (s) return s;
+    }
+    if (space == BEM_HOST)
+        BEM_HIP(hipMemcpyAsync(field, Fo, (size_t)nrhs * np * sizeof(double2), hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
+    return BEM_OK;
+}
+
+bem_status bem_mesh_winding(const bem_mesh *m, const double *points, int64_t npts, double *w, bem_memspace space)
+{
+    if (!m || npts < 0 || (npts > 0 && (!points || !w))) return set_error(BEM_E_ARG, "bad argument");
+    if (npts > (int64_t)1 << 28) return set_error(BEM_E_ARG, "at most 2^28 points per call");
+    if (space != BEM_HOST && space != BEM_DEVICE) return set_error(BEM_E_ARG, "bad memory space");
+    if (npts == 0) return BEM_OK;
+    bem_ctx *ctx = m->ctx;
+    BEM_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const int np = (int)npts;
+    DevMem dpts, dw, part;
+    const double *Pd = points;
+    double *Wd = w;
+    if (space == BEM_HOST) {
+        bem_status s = dev_alloc(ctx, dpts, (size_t)3 * np * sizeof(double));
+        if (!s) s = dev_alloc(ctx, dw, (size_t)np * sizeof(double));
+        if (s) return s;
+        BEM_HIP(hipMemcpyAsync(dpts.ptr, points, (size_t)3 * np * sizeof(double), hipMemcpyHostToDevice, st));
+        Pd = dpts.as<double>();
+        Wd = dw.as<double>();
+    }
+    bem_status s = launch_winding(m, np, Pd, Wd, part, st);
+    if (s) return s;
+    if (space == BEM_HOST) BEM_HIP(hipMemcpyAsync(w, Wd, (size_t)np * sizeof(double), hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
     return BEM_OK;
 }
 

@@ -29,24 +29,12 @@
 
 #include "internal.h"
 #include "phase.h"
+#include "rule6.h"
 
 namespace bemtx {
 
 namespace {
 
-constexpr double kA1 = 0.445948490915964886318329253883;
-constexpr double kW1 = 0.223381589678011465944827736698;
-constexpr double kA2 = 0.091576213509770743459571463402;
-constexpr double kW2 = 0.109951743655321867388505596635;
-constexpr double kInv4Pi = 0.0795774715459476678844418816863;
-
-// Barycentric coordinate c of point q of the 6-point rule, and its weight
-// (weights sum to one; multiply by the area).
-__host__ __device__ constexpr double r6_bary(int q, int c)
-{
-    return q < 3 ? (c == q ? 1.0 - 2.0 * kA1 : kA1) : (c == q - 3 ? 1.0 - 2.0 * kA2 : kA2);
-}
-__host__ __device__ constexpr double r6_w(int q) { return q < 3 ? kW1 : kW2; }
 
 __device__ inline double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 

@@ -177,7 +177,7 @@ void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue me
 namespace bemtx {
 // kernels timed by the optional per-launch HIP-event timer of a context
 enum KernelId { K_REGULAR = 0, K_GATHER, K_SINGULAR, K_NEAR, K_MTF_DENSE, K_MASS_APPLY, K_CGS_DOTS, K_CGS_UPDATE,
-                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_BLOCK_GEMM, K_MASS_GEMM, K_KRYLOV_NORM, K_COUNT };
+                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_BLOCK_GEMM, K_MASS_GEMM, K_KRYLOV_NORM, K_FIELD, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 }  // namespace bemtx
 
