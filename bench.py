@@ -258,6 +258,62 @@ def serving_run(B, synth, n_requests=24, slots=4, tol=1e-5, maxit=1000):
     return summ
 
 
+# FP64 operations per quadrature-point evaluation of the field kernel (FMA =
+# 2): y - x 3, r^2 5, 1/r 1, k r 2, phase reduction and sin/cos polynomials
+# 45, exp(ikr)/r 2, (y - x).n / r^2 7, the radial factor 6, the two complex
+# products and sums 16.
+FIELD_FLOP_PER_EVAL = 87
+
+
+def field_run(ctx, B, synth, np, reps=5):
+    """Field evaluation on the C2 body: the traces of one solve, then the
+    total field on a 100 x 100 grid of the plane z = 0 over [-2, 2]^2 (the
+    paper's accuracy grid, 100 x 100 points over the body and a margin of
+    half its size, Sec. 6.2), regions from the exterior mesh's winding
+    number.  Reports the field call's wall time, the field kernel's device
+    time (HIP events) and its FP64 rate by the operation count above."""
+    import torch
+    c = synth.make_config("C2")
+    me, mi = B.Mesh(ctx, *c["ext"]), B.Mesh(ctx, *c["int"])
+    p = B.Problem(ctx, me, mi, c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
+    p.assemble_operators()
+    p.assemble_projection()
+    x, st, code = p.solve(c["dirs"], tol=c["tol"], maxit=2000)
+    g = np.linspace(-2.0, 2.0, 100)
+    gx, gy = np.meshgrid(g, g, indexing="ij")
+    pts = torch.as_tensor(np.stack([gx.ravel(), gy.ravel(), np.zeros(gx.size)], axis=1), device=ctx.device)
+    me.winding(pts)   # warm-up (first launch loads the kernels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    region = (me.winding(pts) > 0.5).to(torch.int32)
+    torch.cuda.synchronize()
+    t_wind = time.perf_counter() - t0
+    p.field(c["dirs"], x, pts, region)   # warm-up
+    ctx.set_kernel_timing(("field",))
+    lat = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f = p.field(c["dirs"], x, pts, region)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    ms, n = ctx.kernel_time("field")
+    ctx.set_kernel_timing(())
+    n_in = int(region.sum().item())
+    n_out = pts.shape[0] - n_in
+    evals = 6 * (n_out * len(c["ext"][1]) + n_in * len(c["int"][1]))
+    dev_ms = ms / reps   # both regions' launches of one call
+    tf = FIELD_FLOP_PER_EVAL * evals / (dev_ms * 1e-3) / 1e12
+    return {"workload": "C2 body, 100 x 100 grid on z = 0 over [-2, 2]^2, 1 plane wave",
+            "points": int(pts.shape[0]), "interior_points": n_in, "quadrature_evaluations": evals,
+            "call_ms": round(1e3 * float(np.median(lat)), 3), "kernel_ms": round(dev_ms, 3),
+            "points_per_s": round(pts.shape[0] / float(np.median(lat)), 1),
+            "winding_ms": round(1e3 * t_wind, 3),
+            "roofline": {"kernel": "field_partial", "bound": "alu", "achieved": round(tf, 2), "peak": 78.6,
+                         "unit": "TFLOP/s", "frac": round(tf / 78.6, 4), "flop_per_eval": FIELD_FLOP_PER_EVAL},
+            "max_abs_field": round(float(f.abs().max().item()), 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +323,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the FP64 vs mixed comparison")
     ap.add_argument("--no-batching", action="store_true", help="skip the multi-RHS comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
+    ap.add_argument("--no-field", action="store_true", help="skip the field evaluation")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
                          "HBM byte counters) and exit")
@@ -387,6 +444,8 @@ def main():
         line["precision"] = precision_compare(ctx, B, synth, np)
     if not args.no_batching:
         line["batching"] = batching_compare(ctx, B, synth, np)
+    if not args.no_field:
+        line["field"] = field_run(ctx, B, synth, np)
     if not args.no_serving:
         ctx.trim()   # the serving workers size their budget from free HBM: return this context's blocks first
         torch.cuda.empty_cache()
