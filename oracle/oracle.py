@@ -18,6 +18,10 @@ primitives and no blocking or reordering:
   solve_mtf(...)          x = A^{-1} b by dense LU: GMRES on the mass-
                           preconditioned (strong) form M^{-1} A x = M^{-1} b
                           reaches exactly this solution (Sec. 3.3, 5.1)
+  pmchwt_system(...)      the exterior PMCHWT matrix as printed in Sec. 3.3,
+                          interior operators scaled as in the single-trace
+                          Calderon system of Sec. 2.3
+  solve_pmchwt(...)       its exact discrete solution by dense LU
   projection_error(...)   E_int, E_ext of Sec. 5.2
 """
 import ctypes
@@ -209,6 +213,42 @@ def solve_mtf(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4, op
     A = mtf_system(ops, rho_ext, rho_int)
     ni = ops["M_i"].shape[0]
     B = np.stack([mtf_rhs(ext_mesh, k_ext, d, ni) for d in np.atleast_2d(dirs)], axis=1)
+    X = np.linalg.solve(A, B)
+    return X.T, ops
+
+
+def pmchwt_system(ops, rho_ext, rho_int):
+    """The weak-form exterior PMCHWT matrix (Sec. 3.3, Eq. "pmchwt:discrete"),
+    with the interior Calderon operator scaled as in Eq.
+    "calderon:stf:extint" (V_i by rho_int / rho_ext, D_i by rho_ext / rho_int):
+        [ -K_e - hat(K_i)                  V_e + (ri/re) hat(V_i) ]
+        [  D_e + (re/ri) hat(D_i)          T_e + hat(T_i)         ]
+    hat(X) = P_ei M_i^-1 X M_i^-1 P_ie; unknowns [gamma_D p, gamma_N p] on
+    the exterior mesh, right-hand side [f, g]."""
+    Oe, Oi, P_ie, M_i = ops["ext"], ops["int"], ops["P_ie"], ops["M_i"]
+    P_ei = P_ie.T
+
+    def hat(X):
+        return P_ei @ np.linalg.solve(M_i, X @ np.linalg.solve(M_i, P_ie))
+
+    a = rho_int / rho_ext
+    return np.block([
+        [-Oe["K"] - hat(Oi["K"]), Oe["V"] + a * hat(Oi["V"])],
+        [Oe["D"] + hat(Oi["D"]) / a, Oe["T"] + hat(Oi["T"])],
+    ])
+
+
+def pmchwt_rhs(ext_mesh, k_ext, d):
+    f, g = plane_wave_rhs(*ext_mesh, k_ext, d)
+    return np.concatenate([f, g])
+
+
+def solve_pmchwt(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4, ops=None):
+    """Exact discrete exterior PMCHWT solution(s) by dense LU: (x [nrhs, 2 N_ext], ops)."""
+    if ops is None:
+        ops = operators(ext_mesh, int_mesh, k_ext, k_int, ng=ng)
+    A = pmchwt_system(ops, rho_ext, rho_int)
+    B = np.stack([pmchwt_rhs(ext_mesh, k_ext, d) for d in np.atleast_2d(dirs)], axis=1)
     X = np.linalg.solve(A, B)
     return X.T, ops
 

@@ -383,3 +383,53 @@ def test_transparent_body(orc):
     ue, ui = np.exp(1j * k * xe @ d), np.exp(1j * k * xi @ d)
     assert np.linalg.norm(-x[:ne] - ue) / np.linalg.norm(ue) < 0.02
     assert np.linalg.norm(-x[2 * ne:2 * ne + ni] - ui) / np.linalg.norm(ui) < 0.02
+
+
+# ------------------------------------------------------------- exterior PMCHWT
+
+def test_pmchwt_mie_convergence(orc):
+    """Exact discrete exterior PMCHWT solution vs the penetrable-sphere series
+    (unknowns: p and dp+/dn on the exterior mesh): O(h^2) on conforming and
+    nonconforming grids, with a density contrast so that the scaling of the
+    interior single- and double-layer blocks is tested."""
+    ke, ki, re, ri = 2.0, 3.0, 1.0, 1.5
+    d = np.array([0.0, 0.0, 1.0])
+    for int_kind in ("ico", "fib"):
+        errs = []
+        for L in (1, 2, 3):
+            n_int = {1: 30, 2: 120, 3: 500}[L]
+            (xe, te), (xi, ti), _ = synth.configs.make_pair(7, L, int_kind, 0.01, (1, 1, 1), int_level=L,
+                                                            int_n=n_int)
+            X, _ = orc.solve_pmchwt((xe, te), (xi, ti), ke, ki, re, ri, d)
+            ne = len(xe)
+            p, dpp, _ = mie_traces(xe, d, ke, ki, re, ri)
+            e = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+            errs.append([e(X[0][:ne], p), e(X[0][ne:], dpp)])
+        errs = np.array(errs)
+        assert np.all(errs[1] < errs[0] / 2.5) and np.all(errs[2] < errs[1] / 2.5), (int_kind, errs)
+        assert np.all(errs[2] < 0.03), (int_kind, errs)
+
+
+def test_pmchwt_identical_meshes(orc):
+    """One mesh on both sides: the mortar matrix is the mass matrix, so every
+    hat(X) reduces to X and the system is the conforming single-trace one."""
+    xyz, tri = synth.icosphere(1)
+    ops = orc.operators((xyz, tri), (xyz, tri), 2.0, 3.0)
+    A = orc.pmchwt_system(ops, 1.0, 2.0)
+    Oe, Oi = ops["ext"], ops["int"]
+    ref = np.block([[-Oe["K"] - Oi["K"], Oe["V"] + 2.0 * Oi["V"]], [Oe["D"] + 0.5 * Oi["D"], Oe["T"] + Oi["T"]]])
+    assert np.abs(A - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_pmchwt_agrees_with_mtf(orc):
+    """Both formulations discretise the same transmission problem: their
+    exterior traces agree to the discretisation error (MTF unknowns are
+    -p and -dp+/dn)."""
+    ke, ki, re, ri = 2.0, 3.0, 1.0, 2.0
+    d = np.array([0.6, 0.0, 0.8])
+    (xe, te), (xi, ti), _ = synth.configs.make_pair(9, 3, "fib", 0.02, (1.0, 0.9, 0.8), int_n=500)
+    Xm, ops = orc.solve_mtf((xe, te), (xi, ti), ke, ki, re, ri, d)
+    Xp, _ = orc.solve_pmchwt((xe, te), (xi, ti), ke, ki, re, ri, d, ops=ops)
+    ne = len(xe)
+    e = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert e(Xp[0][:ne], -Xm[0][:ne]) < 0.02 and e(Xp[0][ne:], -Xm[0][ne:2 * ne]) < 0.05
