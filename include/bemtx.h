@@ -234,6 +234,27 @@ bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b
 bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
                      void *traces, bem_memspace space, bem_stats *stats);
 
+/* Exterior PMCHWT formulation (Sec. 3.3, Eq. "pmchwt:discrete"): on the
+ * exterior mesh, [-K_e - hat(K_i), V_e + a hat(V_i); D_e + hat(D_i) / a,
+ * T_e + hat(T_i)] [v; w] = [f; g] with hat(X) = P_ext,int M_int^-1 X
+ * M_int^-1 P_int,ext and a = rho_int / rho_ext (the interior operators
+ * scaled as in the single-trace Calderon system, Sec. 2.3), f, g as in
+ * bem_mtf_rhs.  The unknowns are the traces of the total field on the
+ * exterior mesh: v = p, w = dp/dn+.  Uses the operators and projection of
+ * the problem (assemble both first; BEM_E_STATE otherwise).
+ * bem_solve_pmchwt: GMRES without restart on the mass-preconditioned form
+ * M_ext^-1 A x = M_ext^-1 [f; g], x0 = 0, FP64 Arnoldi as in bem_solve, one
+ * right-hand side at a time; traces: complex128 [nrhs][2 N_ext] in caller
+ * numbering, in `space`; BEM_W_NOCONV as in bem_solve; BEM_E_UNSUPPORTED
+ * for BEM_C64_MIXED problems (opts->batch and the refinement fields are
+ * not used).
+ * bem_pmchwt_matvec: y = A x (strong = 0) or M_ext^-1 A x (strong = 1),
+ * x, y: complex128 [2 N_ext] in caller numbering, in `space`; synchronises
+ * the context stream. */
+bem_status bem_solve_pmchwt(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
+                            void *traces, bem_memspace space, bem_stats *stats);
+bem_status bem_pmchwt_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space);
+
 /* Total acoustic field at points off the surface, from the unknowns of
  * bem_solve, by the representation formulas (Sec. 2, Eq. "representation"):
  * at an exterior point the incident wave exp(i k_ext d.x) plus

@@ -54,6 +54,8 @@ SIGNATURES = {
     "bem_copy_operator": (c_status, [vp, i32, ctypes.c_char, vp, i32]),
     "bem_copy_projection": (c_status, [vp, vp, vp, vp, ctypes.POINTER(i64)]),
     "bem_field": (c_status, [vp, vp, i32, vp, vp, vp, i64, vp, i32]),
+    "bem_solve_pmchwt": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
+    "bem_pmchwt_matvec": (c_status, [vp, vp, vp, i32, i32]),
     "bem_mesh_winding": (c_status, [vp, vp, i64, vp, i32]),
     "bem_check_mesh": (c_status, [vp, i64, vp, i64]),
     "bem_host_mortar": (c_status, [vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, vp, ctypes.POINTER(i64),

@@ -1541,6 +1541,121 @@ bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, dou
     return BEM_OK;
 }
 
+// ---- exterior PMCHWT (Sec. 3.3, Eq. "pmchwt:discrete"): with x = [v; w] on
+// the exterior mesh, A x = C_ext x + P_ei M_i^-1 C_int M_i^-1 P_ie x, where
+// C_ext = [-K_e V_e; D_e T_e] and C_int = [-K_i a V_i; D_i / a T_i],
+// a = rho_int / rho_ext (the scaled interior Calderon operator of the
+// single-trace system, Sec. 2.3).  With u = M_i^-1 P_ie x, one pass of the
+// multiple-traces tile products over [v; w; u_a; a u_b] (mortar terms off)
+// gives C_ext x on the exterior rows and, on the interior rows,
+// [-K_i u_a + a V_i u_b; D_i u_a + a T_i u_b], whose second row times 1/a is
+// the second row of C_int u.
+
+// X[0, 2 ne) = x; T = [P_ie v; a P_ie w] (interior layout)
+__global__ __launch_bounds__(256) void pmchwt_project_kernel(int ne, int ni, const int32_t *__restrict__ ptr,
+                                                             const int32_t *__restrict__ col,
+                                                             const double *__restrict__ val, double a,
+                                                             const double2 *__restrict__ x, double2 *__restrict__ X,
+                                                             double2 *__restrict__ T, const KrylovState *__restrict__ st)
+{
+    if (st && st->done) return;
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < 2 * ne) {
+        X[u] = x[u];
+        return;
+    }
+    const int i = u - 2 * ne;
+    if (i >= ni) return;
+    double vr = 0, vi = 0, wr = 0, wi = 0;
+    for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+        const double pv = val[k];
+        const double2 v = x[col[k]], w = x[ne + col[k]];
+        vr += pv * v.x; vi += pv * v.y; wr += pv * w.x; wi += pv * w.y;
+    }
+    T[i] = make_double2(vr, vi);
+    T[ni + i] = make_double2(a * wr, a * wi);
+}
+
+// Rr = Y[0, 2 ne) + [P_ei Q_a; b P_ei Q_b]
+__global__ __launch_bounds__(256) void pmchwt_lift_kernel(int ne, int ni, const int32_t *__restrict__ ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const double *__restrict__ val, double b,
+                                                          const double2 *__restrict__ Y, const double2 *__restrict__ Q,
+                                                          double2 *__restrict__ Rr, const KrylovState *__restrict__ st)
+{
+    if (st && st->done) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ne) return;
+    double ar = 0, ai = 0, br = 0, bi = 0;
+    for (int k = ptr[j]; k < ptr[j + 1]; ++k) {
+        const double pv = val[k];
+        const double2 qa = Q[col[k]], qb = Q[ni + col[k]];
+        ar += pv * qa.x; ai += pv * qa.y; br += pv * qb.x; bi += pv * qb.y;
+    }
+    const double2 ya = Y[j], yb = Y[ne + j];
+    Rr[j] = make_double2(ya.x + ar, ya.y + ai);
+    Rr[ne + j] = make_double2(yb.x + b * br, yb.y + b * bi);
+}
+
+// z = blockdiag(M, M)^-1 y on one mesh (y, z: that mesh's two vectors)
+bem_status apply_Minv_mesh(const bem_problem *p, int mesh, const double2 *y, double2 *z, double4 *part,
+                           const KrylovState *kst)
+{
+    hipStream_t st = p->ctx->stream;
+    const int ne = mesh == 0 ? (int)p->ext->h.nv : 0, ni = mesh == 1 ? (int)p->inte->h.nv : 0;
+    {
+        KTimer kt(p->ctx, K_MASS_APPLY);
+        launch_k(kt, mass_apply_part_kernel<double, MASS_RW64>, split_grid(ne, ni, MASS_CW_MAX, MASS_RW64), dim3(256),
+                 0, st, ne, ni, p->Minv[0].as<double>(), p->Minv[1].as<double>(), y, part, kst);
+    }
+    hipLaunchKernelGGL(mass_combine_kernel, dim3((ne + ni + 255) / 256), dim3(256), 0, st, ne, ni, part, z, kst);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+}
+
+struct PmchwtBufs {
+    MtfArgs A0;            // the multiple-traces arguments with the mortar terms off
+    DevMem X, Y, T, Q, Rr; // [2 ne + 2 ni] x2, [2 ni] x2, [2 ne]
+};
+
+bem_status pmchwt_alloc(bem_problem *p, PmchwtBufs &pb)
+{
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
+    const size_t nm = (size_t)(2 * ne + 2 * ni) * sizeof(double2);
+    pb.A0 = make_args(p);
+    pb.A0.c_ext_v = pb.A0.c_ext_w = pb.A0.c_int_v = pb.A0.c_int_w = 0.0;
+    bem_status s = dev_alloc(p->ctx, pb.X, nm);
+    if (!s) s = dev_alloc(p->ctx, pb.Y, nm);
+    if (!s) s = dev_alloc(p->ctx, pb.T, (size_t)2 * ni * sizeof(double2));
+    if (!s) s = dev_alloc(p->ctx, pb.Q, (size_t)2 * ni * sizeof(double2));
+    if (!s) s = dev_alloc(p->ctx, pb.Rr, (size_t)2 * ne * sizeof(double2));
+    return s;
+}
+
+// y = A x (weak form, 2 ne, internal numbering); with `strong`, z = M_e^-1 y
+bem_status apply_pmchwt(const bem_problem *p, const PmchwtBufs &pb, const double2 *x, double2 *y, double2 *z,
+                        bool strong, const KrylovState *kst, double4 *part)
+{
+    hipStream_t st = p->ctx->stream;
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
+    const double a = p->rho_int / p->rho_ext;
+    double2 *X = pb.X.as<double2>(), *Y = pb.Y.as<double2>(), *T = pb.T.as<double2>(), *Q = pb.Q.as<double2>();
+    hipLaunchKernelGGL(pmchwt_project_kernel, dim3((2 * ne + ni + 255) / 256), dim3(256), 0, st, ne, ni,
+                       p->P_ie_ptr.as<int32_t>(), p->P_ie_col.as<int32_t>(), p->P_ie_val.as<double>(), a, x, X, T, kst);
+    BEM_HIP(hipGetLastError());
+    bem_status s = apply_Minv_mesh(p, 1, T, X + 2 * ne, part, kst);
+    if (!s) s = apply_A(p, pb.A0, X, Y, nullptr, false, kst, part);
+    if (!s) s = apply_Minv_mesh(p, 1, Y + 2 * ne, Q, part, kst);
+    if (s) return s;
+    double2 *out = strong ? pb.Rr.as<double2>() : y;
+    hipLaunchKernelGGL(pmchwt_lift_kernel, dim3((ne + 255) / 256), dim3(256), 0, st, ne, ni,
+                       p->P_ei_ptr.as<int32_t>(), p->P_ei_col.as<int32_t>(), p->P_ei_val.as<double>(), 1.0 / a, Y, Q,
+                       out, kst);
+    BEM_HIP(hipGetLastError());
+    if (strong) return apply_Minv_mesh(p, 0, out, z, part, kst);
+    return BEM_OK;
+}
+
 // ||w|| on the device: into *out (device double)
 bem_status norm_to(const bem_problem *p, int n, const double2 *w, double *npart, double2 *scratch_vec, double *out)
 {
@@ -1744,6 +1859,7 @@ struct Gmres {
     int n, nchunk, nrow_blk, nupd, m, R;
     KBatch B;
     double acc64_above = 0.0;   // single run, complex64: FP64 accumulation while the residual estimate exceeds this
+    const PmchwtBufs *pm = nullptr;   // exterior PMCHWT system (one run, FP64) instead of the multiple-traces one
 
     // R independent GMRES runs without restart on M^-1 A x = r0 (r0 already
     // preconditioned; run r's start vector at r0 + r r0stride), x0 = 0,
@@ -1787,7 +1903,9 @@ struct Gmres {
         for (int j = 0; j <= maxit && !stop; ++j) {
             const double2 *vj = Vb + (size_t)j * n;
             bem_status s;
-            if (bb)
+            if (pm)
+                s = apply_pmchwt(p, *pm, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
+            else if (bb)
                 s = block_apply(p, A, *bb, R, vj, B.basis, W.y.as<double2>(), B.vec, W.z.as<double2>(), B.vec, true,
                                 dst);
             else
@@ -2232,6 +2350,159 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         stats->t_iter_ms = total_it > 0 ? t_solve / total_it : 0.0;
     }
     return all_conv ? BEM_OK : set_error(BEM_W_NOCONV, "GMRES reached maxit before the tolerance");
+}
+
+// [f; g] of the PMCHWT system from the multiple-traces right-hand side [-f; -g; 0; 0]
+__global__ void pmchwt_rhs_kernel(int n, const double2 *__restrict__ b_mtf, double2 *__restrict__ b)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) b[r] = make_double2(-b_mtf[r].x, -b_mtf[r].y);
+}
+
+// Exterior PMCHWT solve (Sec. 3.3, Eq. "pmchwt:discrete"): GMRES without
+// restart on the mass-preconditioned form M_e^-1 A x = M_e^-1 [f; g], one
+// right-hand side at a time, FP64 throughout; unknowns [gamma_D p,
+// gamma_N p] on the exterior mesh.
+bem_status pmchwt_solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
+                             bem_memspace space, bem_stats *stats)
+{
+    bem_ctx *ctx = p->ctx;
+    BEM_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (p->prec != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "PMCHWT: complex128 problems only");
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne, nm = 2 * ne + 2 * ni;
+    const int m = opts->maxit;
+    const int R = 1;
+    const size_t vb = (size_t)n * sizeof(double2);
+    const int nchunk = (n + CGS_CHUNK - 1) / CGS_CHUNK;
+    const int nrow_blk = (n + 255) / 256, nupd = (n + UPD_ROWS - 1) / UPD_ROWS;
+    Work W;
+    bem_status s = dev_alloc(ctx, W.y, vb);
+    if (!s) s = dev_alloc(ctx, W.z, vb);
+    if (!s) s = dev_alloc(ctx, W.b, (size_t)nm * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.d, vb);
+    if (!s) s = dev_alloc(ctx, W.r, vb);
+    if (!s) s = dev_alloc(ctx, W.xin, vb);
+    if (!s) s = dev_alloc(ctx, W.Vb, (size_t)(m + 1) * vb);
+    if (!s) s = dev_alloc(ctx, W.partial, (size_t)nchunk * 2 * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.hsum, (size_t)(m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.beta, sizeof(double) * (R + 1));
+    if (!s) s = dev_alloc(ctx, W.tolv, sizeof(double) * R);
+    if (!s) s = dev_alloc(ctx, W.yc, (size_t)(m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.npart, (size_t)std::max(nrow_blk, nupd) * sizeof(double));
+    if (!s) s = dev_alloc(ctx, W.R, (size_t)m * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.H, (size_t)m * (m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.coef, (size_t)(2 * m + 4) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.g, (size_t)(m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.cs, (size_t)m * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.sn, (size_t)m * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.state, sizeof(KrylovState));
+    if (!s) s = dev_alloc(ctx, W.part, split_part_bytes(ne, ni));
+    PmchwtBufs pb;
+    if (!s) s = pmchwt_alloc(p, pb);
+    if (s) return s;
+    KrylovState *hstate = nullptr;
+    BEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstate), 2 * R * sizeof(KrylovState), hipHostMallocDefault));
+    struct PinGuard { KrylovState *p; ~PinGuard() { if (p) (void)hipHostFree(p); } } guard{hstate};
+    hipEvent_t ev[2];
+    BEM_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    BEM_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    struct EvGuard { hipEvent_t *e; ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); } } eguard{ev};
+    const size_t finish_lds = (size_t)(3 * m + 1) * sizeof(double2);
+    BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&dgs_hess_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)finish_lds));
+    KBatch B{};
+    Gmres gm{p, pb.A0, W, nullptr, hstate, ev, n, nchunk, nrow_blk, nupd, m, R, B};
+    gm.pm = &pb;
+    const dim3 gv(nrow_blk);
+    double *beta = W.beta.as<double>();
+    double2 *bp = W.d.as<double2>();
+    int total_it = 0;
+    double worst_res = 0.0;
+    bool all_conv = true;
+    auto t0 = std::chrono::steady_clock::now();
+    for (int r = 0; r < nrhs; ++r) {
+        s = rhs_internal(p, dirs + 3 * r, W.b.as<double2>());
+        if (s) return s;
+        hipLaunchKernelGGL(pmchwt_rhs_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), bp);
+        s = apply_Minv_mesh(p, 0, bp, W.r.as<double2>(), W.part.as<double4>(), nullptr);
+        if (s) return s;
+        KrylovState fin;
+        const double tol = opts->tol;
+        s = gm.run(W.r.as<double2>(), n, &tol, m, W.xin.as<double2>(), &fin);
+        if (s) return s;
+        total_it += fin.iters;
+        // true strong-form residual M_e^-1 (b - A x), FP64
+        s = apply_pmchwt(p, pb, W.xin.as<double2>(), W.y.as<double2>(), nullptr, false, nullptr, W.part.as<double4>());
+        if (s) return s;
+        hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, bp, W.y.as<double2>(), W.r.as<double2>());
+        s = apply_Minv_mesh(p, 0, W.r.as<double2>(), W.z.as<double2>(), W.part.as<double4>(), nullptr);
+        if (!s) s = norm_to(p, n, W.z.as<double2>(), W.npart.as<double>(), W.y.as<double2>(), beta + R);
+        if (s) return s;
+        double rn = 0.0;
+        BEM_HIP(hipMemcpyAsync(&rn, beta + R, sizeof(double), hipMemcpyDeviceToHost, st));
+        BEM_HIP(hipStreamSynchronize(st));
+        const double rel = fin.beta0 > 0 ? rn / fin.beta0 : 0.0;
+        worst_res = std::max(worst_res, rel);
+        if (!(fin.resid <= opts->tol)) all_conv = false;
+        hipLaunchKernelGGL(permute_vec_kernel, gv, dim3(256), 0, st, ne, 0, p->ext->d.perm.as<int32_t>(),
+                           p->ext->d.perm.as<int32_t>(), W.xin.as<double2>(), W.y.as<double2>(), 0);
+        BEM_HIP(hipGetLastError());
+        BEM_HIP(hipMemcpyAsync(static_cast<double2 *>(traces) + (size_t)r * n, W.y.ptr, vb,
+                               space == BEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+        BEM_HIP(hipStreamSynchronize(st));
+    }
+    const double t_solve = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    s = resolve_assembly_timing(p);
+    if (s) return s;
+    if (stats) {
+        std::memset(stats, 0, sizeof *stats);
+        stats->iterations = total_it;
+        stats->rel_residual = worst_res;
+        stats->t_geometry_ms = p->t_geometry_ms;
+        stats->t_regular_ms = p->t_regular_ms;
+        stats->t_singular_ms = p->t_singular_ms;
+        stats->t_projection_ms = p->t_projection_ms;
+        stats->t_matrix_ms = p->t_assembly_ms + p->t_projection_ms;
+        stats->t_assembly_ms = p->t_assembly_ms;
+        stats->t_solve_ms = t_solve;
+        stats->t_iter_ms = total_it > 0 ? t_solve / total_it : 0.0;
+    }
+    return all_conv ? BEM_OK : set_error(BEM_W_NOCONV, "GMRES reached maxit before the tolerance");
+}
+
+// y = A x or M_e^-1 A x of the PMCHWT system; x, y: [2 N_ext] caller numbering
+bem_status pmchwt_matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space)
+{
+    bem_ctx *ctx = p->ctx;
+    BEM_HIP(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    if (p->prec != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "PMCHWT: complex128 problems only");
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne;
+    const size_t bytes = (size_t)n * sizeof(double2);
+    DevMem xu, xi, yi, zi, yu, part;
+    PmchwtBufs pb;
+    bem_status s = dev_alloc(ctx, xu, bytes);
+    if (!s) s = dev_alloc(ctx, xi, bytes);
+    if (!s) s = dev_alloc(ctx, yi, bytes);
+    if (!s) s = dev_alloc(ctx, zi, bytes);
+    if (!s) s = dev_alloc(ctx, yu, bytes);
+    if (!s) s = dev_alloc(ctx, part, split_part_bytes(ne, ni));
+    if (!s) s = pmchwt_alloc(p, pb);
+    if (s) return s;
+    BEM_HIP(hipMemcpyAsync(xu.ptr, x, bytes, space == BEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st));
+    const dim3 g((n + 255) / 256);
+    const int32_t *pe = p->ext->d.perm.as<int32_t>();
+    hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, 0, pe, pe, xu.as<double2>(), xi.as<double2>(), 1);
+    s = apply_pmchwt(p, pb, xi.as<double2>(), yi.as<double2>(), zi.as<double2>(), strong != 0, nullptr,
+                     part.as<double4>());
+    if (s) return s;
+    hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, 0, pe, pe,
+                       strong ? zi.as<double2>() : yi.as<double2>(), yu.as<double2>(), 0);
+    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipMemcpyAsync(y, yu.ptr, bytes, space == BEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    BEM_HIP(hipStreamSynchronize(st));
+    return BEM_OK;
 }
 
 }  // namespace bemtx

@@ -1,0 +1,103 @@
+"""Exterior PMCHWT (Sec. 3.3) through the C ABI against the oracle: products
+(weak and mass-preconditioned) to 1e-11, the solve against the oracle's LU
+solution to 1e-5 (the bar of the multiple-traces parity tests), and at C2
+the true residual and the agreement with the multiple-traces traces."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_2206_00708_amd")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return B.Context(0)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _problem(ctx, ext, inte, ke, ki, re, ri, prec=B.C128, assemble=True):
+    me, mi = B.Mesh(ctx, *ext), B.Mesh(ctx, *inte)
+    p = B.Problem(ctx, me, mi, ke, ki, re, ri, precision=prec)
+    if assemble:
+        p.assemble_operators()
+        p.assemble_projection()
+    return p, me, mi
+
+
+def _ellipsoid():
+    return synth.configs.make_pair(11, 3, "fib", 0.02, (1.0, 0.8, 0.6), int_n=700)
+
+
+@pytest.mark.parametrize("case", ["C1", "ellipsoid"])
+def test_pmchwt_products_match_oracle(ctx, orc, case):
+    if case == "C1":
+        c = synth.make_config("C1")
+        ext, inte, ke, ki, re, ri = c["ext"], c["int"], c["k_ext"], c["k_int"], 1.0, 1.5
+    else:
+        ext, inte, _ = _ellipsoid()
+        ke, ki, re, ri = 3.0, 5.0, 1.0, 2.0
+    p, me, mi = _problem(ctx, ext, inte, ke, ki, re, ri)
+    ops = orc.operators(ext, inte, ke, ki)
+    A = orc.pmchwt_system(ops, re, ri)
+    ne = len(ext[0])
+    x = np.random.default_rng(2).standard_normal(2 * ne) + 1j * np.random.default_rng(3).standard_normal(2 * ne)
+    y = p.pmchwt_matvec(torch.as_tensor(x), strong=False).cpu().numpy()
+    assert _rel(y, A @ x) < 1e-11
+    z = p.pmchwt_matvec(torch.as_tensor(x), strong=True).cpu().numpy()
+    Me = ops["M_e"]
+    zr = np.concatenate([np.linalg.solve(Me, (A @ x)[:ne]), np.linalg.solve(Me, (A @ x)[ne:])])
+    assert _rel(z, zr) < 1e-11
+
+
+def test_pmchwt_solve_matches_oracle_lu(ctx, orc):
+    ext, inte, _ = _ellipsoid()
+    ke, ki, re, ri = 3.0, 5.0, 1.0, 2.0
+    p, me, mi = _problem(ctx, ext, inte, ke, ki, re, ri)
+    d = synth.plane_wave_directions(2, np.random.default_rng(5))
+    out, st, code = p.solve_pmchwt(d, tol=1e-9, maxit=1500)
+    assert code == B.OK, st
+    X, _ = orc.solve_pmchwt(ext, inte, ke, ki, re, ri, d)
+    got = out.cpu().numpy()
+    ne = len(ext[0])
+    for r in range(2):
+        assert _rel(got[r][:ne], X[r][:ne]) < 1e-5 and _rel(got[r][ne:], X[r][ne:]) < 1e-5
+    assert st["rel_residual"] < 2e-9
+
+
+def test_pmchwt_c2_residual_and_mtf_agreement(ctx):
+    """C2: the true strong-form residual meets the tolerance, and the exterior
+    traces agree with the multiple-traces solve (-v_ext, -w_ext) to the
+    discretisation error."""
+    c = synth.make_config("C2")
+    p, me, mi = _problem(ctx, c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
+    xp, sp, code = p.solve_pmchwt(c["dirs"], tol=1e-6, maxit=2000)
+    assert code == B.OK, sp
+    assert sp["rel_residual"] < 2e-6
+    xm, sm, code = p.solve(c["dirs"], tol=1e-6, maxit=2000)
+    assert code == B.OK, sm
+    ne = len(c["ext"][0])
+    a, b = xp.cpu().numpy()[0], xm.cpu().numpy()[0]
+    assert _rel(a[:ne], -b[:ne]) < 0.05 and _rel(a[ne:], -b[ne:2 * ne]) < 0.1
+
+
+def test_pmchwt_errors(ctx):
+    c = synth.make_config("C1")
+    p, me, mi = _problem(ctx, c["ext"], c["int"], 2.0, 3.0, 1.0, 1.0, assemble=False)
+    with pytest.raises(B.BemError):
+        p.solve_pmchwt(c["dirs"])
+    q, me2, mi2 = _problem(ctx, c["ext"], c["int"], 2.0, 3.0, 1.0, 1.0, prec=B.C64_MIXED)
+    with pytest.raises(B.BemError):
+        q.solve_pmchwt(c["dirs"])
+    r, me3, mi3 = _problem(ctx, c["ext"], c["int"], 2.0, 3.0, 1.0, 1.0)
+    with pytest.raises(B.BemError):
+        r.solve_pmchwt(np.array([[0.0, 0.0, 2.0]]))
+    out, st, code = r.solve_pmchwt(c["dirs"], tol=1e-14, maxit=3)
+    assert code == B.W_NOCONV and np.all(np.isfinite(out.cpu().numpy()))
