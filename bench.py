@@ -282,7 +282,7 @@ def field_run(ctx, B, synth, np, reps=5):
     g = np.linspace(-2.0, 2.0, 100)
     gx, gy = np.meshgrid(g, g, indexing="ij")
     pts = torch.as_tensor(np.stack([gx.ravel(), gy.ravel(), np.zeros(gx.size)], axis=1), device=ctx.device)
-    me.winding(pts)   # warm-up (first launch loads the kernels)
+    (me.winding(pts) > 0.5).to(torch.int32)   # warm-up (first launches load the kernels, torch's too)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     region = (me.winding(pts) > 0.5).to(torch.int32)
@@ -314,6 +314,45 @@ def field_run(ctx, B, synth, np, reps=5):
             "max_abs_field": round(float(f.abs().max().item()), 4)}
 
 
+def pmchwt_run(ctx, B, synth, np, reps=3):
+    """The exterior PMCHWT formulation (Sec. 3.3) beside the multiple-traces
+    one on the C2 workload, after the same assembly: GMRES iterations, solve
+    time, time per iteration, and the relative difference of the exterior
+    traces (PMCHWT unknowns p and dp/dn+, multiple-traces -v_ext and -w_ext;
+    both solved to the workload's tolerance, 1e-6)."""
+    import torch
+    c = synth.make_config("C2")
+    me, mi = B.Mesh(ctx, *c["ext"]), B.Mesh(ctx, *c["int"])
+    p = B.Problem(ctx, me, mi, c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
+    p.assemble_operators()
+    p.assemble_projection()
+    p.solve_pmchwt(c["dirs"], tol=c["tol"], maxit=2000)   # warm-up
+    res = {}
+    for name in ("pmchwt", "mtf"):
+        lat = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "pmchwt":
+                x, st, code = p.solve_pmchwt(c["dirs"], tol=c["tol"], maxit=2000)
+            else:
+                x, st, code = p.solve(c["dirs"], tol=c["tol"], maxit=2000)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+        t = float(np.median(lat))
+        res[name] = {"iterations": st["iterations"], "solve_ms": round(1e3 * t, 3),
+                     "ms_per_iteration": round(1e3 * t / max(1, st["iterations"]), 4),
+                     "rel_residual": st["rel_residual"], "code": int(code)}
+        res[name + "_x"] = x.cpu().numpy()[0]
+    ne = len(c["ext"][0])
+    a, b = res.pop("pmchwt_x"), res.pop("mtf_x")
+    e = lambda u, v: float(np.linalg.norm(u - v) / np.linalg.norm(v))
+    res["trace_rel_diff_p"] = e(a[:ne], -b[:ne])
+    res["trace_rel_diff_dpdn"] = e(a[ne:], -b[ne:2 * ne])
+    res["workload"] = "C2 (sphere ico4 / Fibonacci 2002, k 5/8, rho ratio 1.5), 1 plane wave, tol 1e-6"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -324,6 +363,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the multi-RHS comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-field", action="store_true", help="skip the field evaluation")
+    ap.add_argument("--no-pmchwt", action="store_true", help="skip the PMCHWT comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
                          "HBM byte counters) and exit")
@@ -446,6 +486,8 @@ def main():
         line["batching"] = batching_compare(ctx, B, synth, np)
     if not args.no_field:
         line["field"] = field_run(ctx, B, synth, np)
+    if not args.no_pmchwt:
+        line["pmchwt"] = pmchwt_run(ctx, B, synth, np)
     if not args.no_serving:
         ctx.trim()   # the serving workers size their budget from free HBM: return this context's blocks first
         torch.cuda.empty_cache()
