@@ -22,6 +22,9 @@ primitives and no blocking or reordering:
                           interior operators scaled as in the single-trace
                           Calderon system of Sec. 2.3
   solve_pmchwt(...)       its exact discrete solution by dense LU
+  high_contrast_neumann_system(...), solve_high_contrast_neumann(...)
+                          the exterior high-contrast Neumann formulation
+                          (indirect single-layer representation outside)
   projection_error(...)   E_int, E_ext of Sec. 5.2
 """
 import ctypes
@@ -249,6 +252,46 @@ def solve_pmchwt(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4,
         ops = operators(ext_mesh, int_mesh, k_ext, k_int, ng=ng)
     A = pmchwt_system(ops, rho_ext, rho_int)
     B = np.stack([pmchwt_rhs(ext_mesh, k_ext, d) for d in np.atleast_2d(dirs)], axis=1)
+    X = np.linalg.solve(A, B)
+    return X.T, ops
+
+
+def high_contrast_neumann_system(ops, rho_ext, rho_int):
+    """The weak-form exterior high-contrast Neumann matrix (Sec. 3.3, discrete
+    form of Eq. "highcontrast:ext:neu"):
+        [ 1/2 M_e - hat(T_i)     -(re/ri) hat(D_i) M_e^-1 V_e ]
+        [ M_e                     1/2 M_e - T_e               ]
+    hat(X) = P_ei M_i^-1 X M_i^-1 P_ie; unknowns [gamma_N p, mu] on the
+    exterior mesh (mu: the single-layer density of the scattered field)."""
+    Oe, Oi, P_ie, M_i, M_e = ops["ext"], ops["int"], ops["P_ie"], ops["M_i"], ops["M_e"]
+    P_ei = P_ie.T
+
+    def hat(X):
+        return P_ei @ np.linalg.solve(M_i, X @ np.linalg.solve(M_i, P_ie))
+
+    c = rho_ext / rho_int
+    return np.block([
+        [0.5 * M_e - hat(Oi["T"]), -c * hat(Oi["D"]) @ np.linalg.solve(M_e, Oe["V"])],
+        [M_e, 0.5 * M_e - Oe["T"]],
+    ])
+
+
+def high_contrast_neumann_rhs(ops, ext_mesh, k_ext, d, rho_ext, rho_int):
+    """[(re/ri) hat(D_i) M_e^-1 f; g]: the hypersingular operator acts on the
+    Dirichlet trace of the incident wave, whose P1 coefficients are M_e^-1 f."""
+    f, g = plane_wave_rhs(*ext_mesh, k_ext, d)
+    P_ie, M_i, M_e = ops["P_ie"], ops["M_i"], ops["M_e"]
+    hatD = P_ie.T @ np.linalg.solve(M_i, ops["int"]["D"] @ np.linalg.solve(M_i, P_ie))
+    return np.concatenate([(rho_ext / rho_int) * hatD @ np.linalg.solve(M_e, f), g])
+
+
+def solve_high_contrast_neumann(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4, ops=None):
+    """Exact discrete solution(s) by dense LU: (x [nrhs, 2 N_ext], ops)."""
+    if ops is None:
+        ops = operators(ext_mesh, int_mesh, k_ext, k_int, ng=ng)
+    A = high_contrast_neumann_system(ops, rho_ext, rho_int)
+    B = np.stack([high_contrast_neumann_rhs(ops, ext_mesh, k_ext, d, rho_ext, rho_int)
+                  for d in np.atleast_2d(dirs)], axis=1)
     X = np.linalg.solve(A, B)
     return X.T, ops
 

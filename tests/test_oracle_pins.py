@@ -433,3 +433,40 @@ def test_pmchwt_agrees_with_mtf(orc):
     ne = len(xe)
     e = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
     assert e(Xp[0][:ne], -Xm[0][:ne]) < 0.02 and e(Xp[0][ne:], -Xm[0][ne:2 * ne]) < 0.05
+
+
+# ------------------------------------------------ exterior high-contrast Neumann
+
+def test_high_contrast_neumann_mie(orc):
+    """Exact discrete exterior high-contrast Neumann solution: its first
+    unknown converges at O(h^2) to dp+/dn of the penetrable-sphere series on
+    conforming and nonconforming grids, and its second, the density mu of
+    the scattered field u_s = SLP_ext mu, reproduces the exterior field.
+    The right-hand side's hypersingular term acts on M_e^-1 f (the P1
+    coefficients of the incident Dirichlet trace): taken on f itself, as the
+    discrete form is printed, the error stays near 100 %."""
+    from mie import mie_field
+    from oracle import field as F
+    ke, ki, re, ri = 2.0, 3.0, 1.0, 1.5
+    d = np.array([0.0, 0.0, 1.0])
+    e = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    for int_kind in ("ico", "fib"):
+        errs = []
+        for L in (1, 2, 3):
+            (xe, te), (xi, ti), _ = synth.configs.make_pair(7, L, int_kind, 0.01, (1, 1, 1), int_level=L,
+                                                            int_n={1: 30, 2: 120, 3: 500}[L])
+            X, ops = orc.solve_high_contrast_neumann((xe, te), (xi, ti), ke, ki, re, ri, d)
+            ne = len(xe)
+            _, dpp, _ = mie_traces(xe, d, ke, ki, re, ri)
+            errs.append(e(X[0][:ne], dpp))
+        assert errs[1] < errs[0] / 2.5 and errs[2] < errs[1] / 2.5 and errs[2] < 0.02, (int_kind, errs)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((12, 3)); u /= np.linalg.norm(u, axis=1)[:, None]
+    pts = 1.8 * u
+    tot = np.exp(1j * ke * pts @ d) + F.potentials(xe, te, ke, np.zeros(ne), X[0][ne:], pts)
+    assert e(tot, mie_field(pts, d, ke, ki, re, ri)) < 0.01
+    A = orc.high_contrast_neumann_system(ops, re, ri)
+    f, g = orc.plane_wave_rhs(xe, te, ke, d)
+    hatD = ops["P_ie"].T @ np.linalg.solve(ops["M_i"], ops["int"]["D"] @ np.linalg.solve(ops["M_i"], ops["P_ie"]))
+    literal = np.linalg.solve(A, np.concatenate([(re / ri) * hatD @ f, g]))
+    assert e(literal[:ne], mie_traces(xe, d, ke, ki, re, ri)[1]) > 0.5
