@@ -255,6 +255,20 @@ bem_status bem_solve_pmchwt(bem_problem *p, const double *dirs, int32_t nrhs, co
                             void *traces, bem_memspace space, bem_stats *stats);
 bem_status bem_pmchwt_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space);
 
+/* Exterior high-contrast Neumann formulation (Sec. 2.4, Eq.
+ * "highcontrast:ext:neu", discrete form of Sec. 3.3): on the exterior mesh,
+ *   [1/2 M_e - hat(T_i), -c hat(D_i) M_e^-1 V_e; M_e, 1/2 M_e - T_e] [a; b]
+ *     = [c hat(D_i) M_e^-1 f; g],  c = rho_ext / rho_int,
+ * hat(X) = P_ext,int M_int^-1 X M_int^-1 P_int,ext; a = dp/dn+ on the
+ * exterior mesh and b = mu, the density of the scattered field
+ * u_s = [SLP_ext mu] (indirect representation).  The hypersingular term of
+ * the right-hand side acts on the P1 coefficients M_e^-1 f of the incident
+ * Dirichlet trace.  bem_solve_hc_neumann and bem_hc_neumann_matvec behave as
+ * bem_solve_pmchwt and bem_pmchwt_matvec (same arguments, layouts, errors). */
+bem_status bem_solve_hc_neumann(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
+                                void *traces, bem_memspace space, bem_stats *stats);
+bem_status bem_hc_neumann_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space);
+
 /* Total acoustic field at points off the surface, from the unknowns of
  * bem_solve, by the representation formulas (Sec. 2, Eq. "representation"):
  * at an exterior point the incident wave exp(i k_ext d.x) plus

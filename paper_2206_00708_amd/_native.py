@@ -56,6 +56,8 @@ SIGNATURES = {
     "bem_field": (c_status, [vp, vp, i32, vp, vp, vp, i64, vp, i32]),
     "bem_solve_pmchwt": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
     "bem_pmchwt_matvec": (c_status, [vp, vp, vp, i32, i32]),
+    "bem_solve_hc_neumann": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
+    "bem_hc_neumann_matvec": (c_status, [vp, vp, vp, i32, i32]),
     "bem_mesh_winding": (c_status, [vp, vp, i64, vp, i32]),
     "bem_check_mesh": (c_status, [vp, i64, vp, i64]),
     "bem_host_mortar": (c_status, [vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, vp, ctypes.POINTER(i64),

@@ -201,23 +201,35 @@ class Problem:
                                   _ptr(out), DEVICE))
         return out
 
-    def solve_pmchwt(self, dirs, tol=1e-6, maxit=1000):
-        """bem_solve_pmchwt: exterior PMCHWT traces [nrhs, 2 N_ext] (p, dp/dn+)."""
+    def _ext_solve(self, fn, dirs, tol, maxit):
         d = np.ascontiguousarray(np.atleast_2d(dirs), dtype=np.float64)
-        ne = self.ext.nv
-        out = torch.empty((d.shape[0], 2 * ne), dtype=torch.complex128, device=self.ctx.device)
+        out = torch.empty((d.shape[0], 2 * self.ext.nv), dtype=torch.complex128, device=self.ctx.device)
         opts = N.SolverOpts(tol, maxit, 0, 0.0, 0)
         st = N.Stats()
-        code = _check(N.load().bem_solve_pmchwt(self._h, d.ctypes.data, d.shape[0], ctypes.byref(opts), _ptr(out),
-                                                DEVICE, ctypes.byref(st)))
+        code = _check(fn(self._h, d.ctypes.data, d.shape[0], ctypes.byref(opts), _ptr(out), DEVICE, ctypes.byref(st)))
         return out, st.as_dict(), code
+
+    def _ext_matvec(self, fn, x, strong):
+        xx = x.to(device=self.ctx.device, dtype=torch.complex128).contiguous()
+        y = torch.empty_like(xx)
+        _check(fn(self._h, _ptr(xx), _ptr(y), int(strong), DEVICE))
+        return y
+
+    def solve_pmchwt(self, dirs, tol=1e-6, maxit=1000):
+        """bem_solve_pmchwt: exterior PMCHWT traces [nrhs, 2 N_ext] (p, dp/dn+)."""
+        return self._ext_solve(N.load().bem_solve_pmchwt, dirs, tol, maxit)
 
     def pmchwt_matvec(self, x, strong=True):
         """bem_pmchwt_matvec on a complex128 vector of length 2 N_ext."""
-        xx = x.to(device=self.ctx.device, dtype=torch.complex128).contiguous()
-        y = torch.empty_like(xx)
-        _check(N.load().bem_pmchwt_matvec(self._h, _ptr(xx), _ptr(y), int(strong), DEVICE))
-        return y
+        return self._ext_matvec(N.load().bem_pmchwt_matvec, x, strong)
+
+    def solve_hc_neumann(self, dirs, tol=1e-6, maxit=1000):
+        """bem_solve_hc_neumann: [nrhs, 2 N_ext] = (dp/dn+, mu) on the exterior mesh."""
+        return self._ext_solve(N.load().bem_solve_hc_neumann, dirs, tol, maxit)
+
+    def hc_neumann_matvec(self, x, strong=True):
+        """bem_hc_neumann_matvec on a complex128 vector of length 2 N_ext."""
+        return self._ext_matvec(N.load().bem_hc_neumann_matvec, x, strong)
 
     def operator(self, mesh, op):
         nv = self.ext.nv if mesh == 0 else self.inte.nv

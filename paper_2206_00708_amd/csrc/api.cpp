@@ -124,9 +124,9 @@ bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *gl
                            double2 *contrib, void *ops[4], hipStream_t st);
 bem_status launch_mass_inverse(bem_problem *p, int mesh, hipStream_t st);
 bem_status launch_sym_corrections(bem_problem *p, int mesh, hipStream_t st);
-bem_status pmchwt_solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
-                             bem_memspace space, bem_stats *stats);
-bem_status pmchwt_matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space);
+bem_status ext_form_solve_impl(bem_problem *p, int form, const double *dirs, int nrhs, const bem_solver_opts *opts,
+                               void *traces, bem_memspace space, bem_stats *stats);
+bem_status ext_form_matvec_impl(bem_problem *p, int form, const void *x, void *y, int strong, bem_memspace space);
 bem_status launch_field_region(bem_problem *p, int region, int np, const double *pts, const int32_t *dst_index,
                                const double2 *x_int, const double *dir, double2 *field, DevMem &dens, DevMem &part,
                                hipStream_t st);
@@ -816,8 +816,8 @@ bem_status bem_mesh_winding(const bem_mesh *m, const double *points, int64_t npt
 }
 
 
-bem_status bem_solve_pmchwt(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
-                            void *traces, bem_memspace space, bem_stats *stats)
+static bem_status ext_form_check(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
+                                 void *traces, bem_memspace space)
 {
     if (!p || !dirs || !opts || !traces || nrhs < 1) return set_error(BEM_E_ARG, "bad argument");
     if (!(opts->tol > 0) || opts->maxit < 1 || opts->maxit > 3000)
@@ -828,15 +828,41 @@ bem_status bem_solve_pmchwt(bem_problem *p, const double *dirs, int32_t nrhs, co
         const double l = std::sqrt(dirs[3 * r] * dirs[3 * r] + dirs[3 * r + 1] * dirs[3 * r + 1] + dirs[3 * r + 2] * dirs[3 * r + 2]);
         if (!(std::fabs(l - 1.0) < 1e-6)) return set_error(BEM_E_ARG, "directions must be unit vectors");
     }
-    return pmchwt_solve_impl(p, dirs, nrhs, opts, traces, space, stats);
+    return BEM_OK;
 }
 
-bem_status bem_pmchwt_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space)
+static bem_status ext_form_matvec_check(bem_problem *p, const void *x, void *y, bem_memspace space)
 {
     if (!p || !x || !y) return set_error(BEM_E_ARG, "null argument");
     if (space != BEM_HOST && space != BEM_DEVICE) return set_error(BEM_E_ARG, "bad memory space");
     if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
-    return pmchwt_matvec_impl(p, x, y, strong, space);
+    return BEM_OK;
+}
+
+bem_status bem_solve_pmchwt(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
+                            void *traces, bem_memspace space, bem_stats *stats)
+{
+    bem_status s = ext_form_check(p, dirs, nrhs, opts, traces, space);
+    return s ? s : ext_form_solve_impl(p, 1, dirs, nrhs, opts, traces, space, stats);
+}
+
+bem_status bem_pmchwt_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space)
+{
+    bem_status s = ext_form_matvec_check(p, x, y, space);
+    return s ? s : ext_form_matvec_impl(p, 1, x, y, strong, space);
+}
+
+bem_status bem_solve_hc_neumann(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts,
+                                void *traces, bem_memspace space, bem_stats *stats)
+{
+    bem_status s = ext_form_check(p, dirs, nrhs, opts, traces, space);
+    return s ? s : ext_form_solve_impl(p, 2, dirs, nrhs, opts, traces, space, stats);
+}
+
+bem_status bem_hc_neumann_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space)
+{
+    bem_status s = ext_form_matvec_check(p, x, y, space);
+    return s ? s : ext_form_matvec_impl(p, 2, x, y, strong, space);
 }
 
 }  // extern "C"

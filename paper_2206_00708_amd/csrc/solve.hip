@@ -434,6 +434,7 @@ struct MtfArgs {
     const int32_t *near_row[2], *near_j[2];      // near entries of each mesh, by row
     const double2 *corr[2];                      // [near entry][3]: V_ij - V_ji, D_ij - D_ji (j < i), T_ij - K_ji
     int sym_ts;                                  // tile edge of the symmetric tile form
+    int no_mortar;                               // 1: no mortar terms (the combine skips them)
 };
 
 // ---- split-column form of the inverse-mass apply: a chunk of the vectors
@@ -726,16 +727,18 @@ __global__ __launch_bounds__(256) void mtf_sym_combine_kernel(MtfArgs A, const d
             br += cd.x * vj.x - cd.y * vj.y + ct.x * wj.x - ct.y * wj.y;
             bi += cd.x * vj.y + cd.y * vj.x + ct.x * wj.y + ct.y * wj.x;
         }
-        const int32_t *pp = ext ? A.pei_ptr : A.pie_ptr;
-        const int32_t *pc = ext ? A.pei_col : A.pie_col;
-        const double *pv = ext ? A.pei_val : A.pie_val;
-        const double2 *cvx = ext ? x + 2 * A.ne : x;
-        const int nother = ext ? A.ni : A.ne;
-        const double2 *cwx = cvx + nother;
-        for (int q = pp[i] + l16; q < pp[i + 1]; q += 16) {
-            const double pvq = pv[q];
-            const double2 av = cvx[pc[q]], bw = cwx[pc[q]];
-            sr += pvq * av.x; si += pvq * av.y; tr += pvq * bw.x; ti += pvq * bw.y;
+        if (!A.no_mortar) {
+            const int32_t *pp = ext ? A.pei_ptr : A.pie_ptr;
+            const int32_t *pc = ext ? A.pei_col : A.pie_col;
+            const double *pv = ext ? A.pei_val : A.pie_val;
+            const double2 *cvx = ext ? x + 2 * A.ne : x;
+            const int nother = ext ? A.ni : A.ne;
+            const double2 *cwx = cvx + nother;
+            for (int q = pp[i] + l16; q < pp[i + 1]; q += 16) {
+                const double pvq = pv[q];
+                const double2 av = cvx[pc[q]], bw = cwx[pc[q]];
+                sr += pvq * av.x; si += pvq * av.y; tr += pvq * bw.x; ti += pvq * bw.y;
+            }
         }
     }
     ar = rsum15(ar); ai = rsum15(ai); br = rsum15(br); bi = rsum15(bi);
@@ -1482,6 +1485,7 @@ MtfArgs make_args(const bem_problem *p)
     A.c_int_v = -0.5;
     A.c_int_w = -0.5 * p->rho_int / p->rho_ext;
     A.sym_ts = p->prec == BEM_C128 ? sym_tile<double2>() : sym_tile<float2>();
+    A.no_mortar = 0;
     const bem_mesh *ms[2] = {p->ext, p->inte};
     for (int m = 0; m < 2; ++m) {
         A.near_row[m] = ms[m]->d.near_row.as<int32_t>();
@@ -1613,9 +1617,14 @@ bem_status apply_Minv_mesh(const bem_problem *p, int mesh, const double2 *y, dou
     return BEM_OK;
 }
 
+enum ExtForm { FORM_PMCHWT = 1, FORM_HCN = 2 };   // exterior formulations on [v; w] of the exterior mesh
+
 struct PmchwtBufs {
+    int form = FORM_PMCHWT;
     MtfArgs A0;            // the multiple-traces arguments with the mortar terms off
+    MtfArgs Ai;            // the same on the interior mesh alone
     DevMem X, Y, T, Q, Rr; // [2 ne + 2 ni] x2, [2 ni] x2, [2 ne]
+    DevMem X2, Y2, S, W2;  // high-contrast Neumann: [2 ni], [2 ni], [2 ne], [2 ni]
 };
 
 bem_status pmchwt_alloc(bem_problem *p, PmchwtBufs &pb)
@@ -1624,11 +1633,20 @@ bem_status pmchwt_alloc(bem_problem *p, PmchwtBufs &pb)
     const size_t nm = (size_t)(2 * ne + 2 * ni) * sizeof(double2);
     pb.A0 = make_args(p);
     pb.A0.c_ext_v = pb.A0.c_ext_w = pb.A0.c_int_v = pb.A0.c_int_w = 0.0;
+    pb.A0.no_mortar = 1;
+    pb.Ai = pb.A0;
+    pb.Ai.ne = 0;   // tiles, rows and partials of the interior mesh only
     bem_status s = dev_alloc(p->ctx, pb.X, nm);
     if (!s) s = dev_alloc(p->ctx, pb.Y, nm);
     if (!s) s = dev_alloc(p->ctx, pb.T, (size_t)2 * ni * sizeof(double2));
     if (!s) s = dev_alloc(p->ctx, pb.Q, (size_t)2 * ni * sizeof(double2));
     if (!s) s = dev_alloc(p->ctx, pb.Rr, (size_t)2 * ne * sizeof(double2));
+    if (!s && pb.form == FORM_HCN) {
+        s = dev_alloc(p->ctx, pb.X2, (size_t)2 * ni * sizeof(double2));
+        if (!s) s = dev_alloc(p->ctx, pb.Y2, (size_t)2 * ni * sizeof(double2));
+        if (!s) s = dev_alloc(p->ctx, pb.S, (size_t)2 * ne * sizeof(double2));
+        if (!s) s = dev_alloc(p->ctx, pb.W2, (size_t)2 * ni * sizeof(double2));
+    }
     return s;
 }
 
@@ -1654,6 +1672,152 @@ bem_status apply_pmchwt(const bem_problem *p, const PmchwtBufs &pb, const double
     BEM_HIP(hipGetLastError());
     if (strong) return apply_Minv_mesh(p, 0, out, z, part, kst);
     return BEM_OK;
+}
+
+// ---- exterior high-contrast Neumann (discrete form of Eq.
+// "highcontrast:ext:neu", Sec. 3.3), unknowns [a; b] = [gamma_N p; mu]:
+//   row 1: 1/2 M_e a - hat(T_i) a - c hat(D_i) M_e^-1 V_e b,   c = rho_ext / rho_int
+//   row 2: M_e a + 1/2 M_e b - T_e b
+// with hat(X) = P_ei M_i^-1 X M_i^-1 P_ie.  With u_b = M_i^-1 P_ie a and
+// u_a = c M_i^-1 P_ie M_e^-1 V_e b, the hatted terms of row 1 are
+// P_ei M_i^-1 (T_i u_b + D_i u_a): one tile pass over [0; b; 0; u_b] gives
+// V_e b, T_e b and T_i u_b, one interior pass over [u_a; 0] gives D_i u_a.
+
+// out_a = s P x (+ add), out_b = 0, over the rows of the CSR matrix (ptr null: out_a = x (+ add))
+__global__ __launch_bounds__(256) void hcn_spmv_kernel(int nrows, const int32_t *__restrict__ ptr,
+                                                       const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                       const double2 *__restrict__ x, double sc,
+                                                       const double2 *__restrict__ add, double2 *__restrict__ out_a,
+                                                       double2 *__restrict__ out_b, const KrylovState *__restrict__ st)
+{
+    if (st && st->done) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nrows) return;
+    double r = 0, im = 0;
+    if (ptr) {
+        for (int k = ptr[i]; k < ptr[i + 1]; ++k) {
+            const double pv = val[k];
+            const double2 v = x[col[k]];
+            r += pv * v.x; im += pv * v.y;
+        }
+        r *= sc; im *= sc;
+    } else {
+        r = x[i].x; im = x[i].y;
+    }
+    if (add) { r += add[i].x; im += add[i].y; }
+    out_a[i] = make_double2(r, im);
+    if (out_b) out_b[i] = make_double2(0.0, 0.0);
+}
+
+// rows of the high-contrast product: out[j] = 1/2 (M_e a)_j - (P_ei q)_j,
+// out[ne + j] = (M_e a)_j + 1/2 (M_e b)_j - (T_e b)_j
+__global__ __launch_bounds__(256) void hcn_rows_kernel(int ne, const int32_t *__restrict__ mptr,
+                                                       const int32_t *__restrict__ mcol, const double *__restrict__ mval,
+                                                       const int32_t *__restrict__ pptr, const int32_t *__restrict__ pcol,
+                                                       const double *__restrict__ pval, const double2 *__restrict__ x,
+                                                       const double2 *__restrict__ q, const double2 *__restrict__ Teb,
+                                                       double2 *__restrict__ out, const KrylovState *__restrict__ st)
+{
+    if (st && st->done) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= ne) return;
+    double ar = 0, ai = 0, br = 0, bi = 0, qr = 0, qi = 0;
+    for (int k = mptr[j]; k < mptr[j + 1]; ++k) {
+        const double mv = mval[k];
+        const double2 a = x[mcol[k]], b = x[ne + mcol[k]];
+        ar += mv * a.x; ai += mv * a.y; br += mv * b.x; bi += mv * b.y;
+    }
+    for (int k = pptr[j]; k < pptr[j + 1]; ++k) {
+        const double pv = pval[k];
+        const double2 v = q[pcol[k]];
+        qr += pv * v.x; qi += pv * v.y;
+    }
+    out[j] = make_double2(0.5 * ar - qr, 0.5 * ai - qi);
+    out[ne + j] = make_double2(ar + 0.5 * br - Teb[j].x, ai + 0.5 * bi - Teb[j].y);
+}
+
+// X2 = [c M_i^-1 P_ie M_e^-1 v; 0] for an exterior vector v (through pb.T); returns in pb.X2
+bem_status hcn_to_interior(const bem_problem *p, const PmchwtBufs &pb, const double2 *v_ext_minv, double c,
+                           const KrylovState *kst, double4 *part)
+{
+    hipStream_t st = p->ctx->stream;
+    const int ni = (int)p->inte->h.nv;
+    double2 *T = pb.T.as<double2>();
+    hipLaunchKernelGGL(hcn_spmv_kernel, dim3((ni + 255) / 256), dim3(256), 0, st, ni, p->P_ie_ptr.as<int32_t>(),
+                       p->P_ie_col.as<int32_t>(), p->P_ie_val.as<double>(), v_ext_minv, c, nullptr, T, T + ni, kst);
+    BEM_HIP(hipGetLastError());
+    return apply_Minv_mesh(p, 1, T, pb.X2.as<double2>(), part, kst);
+}
+
+bem_status apply_hcn(const bem_problem *p, const PmchwtBufs &pb, const double2 *x, double2 *y, double2 *z,
+                     bool strong, const KrylovState *kst, double4 *part)
+{
+    hipStream_t st = p->ctx->stream;
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
+    const double c = p->rho_ext / p->rho_int;
+    double2 *X = pb.X.as<double2>(), *Y = pb.Y.as<double2>(), *T = pb.T.as<double2>(), *Q = pb.Q.as<double2>();
+    double2 *S = pb.S.as<double2>(), *Y2 = pb.Y2.as<double2>(), *W2 = pb.W2.as<double2>();
+    const dim3 ge((ne + 255) / 256), gi((ni + 255) / 256);
+    // X = [0; b; M_i^-1 [0; P_ie a]] = [0; b; 0; u_b]
+    hipLaunchKernelGGL(hcn_spmv_kernel, ge, dim3(256), 0, st, ne, nullptr, nullptr, nullptr, x + ne, 1.0, nullptr,
+                       X + ne, X, kst);
+    hipLaunchKernelGGL(hcn_spmv_kernel, gi, dim3(256), 0, st, ni, p->P_ie_ptr.as<int32_t>(), p->P_ie_col.as<int32_t>(),
+                       p->P_ie_val.as<double>(), x, 1.0, nullptr, T + ni, T, kst);
+    BEM_HIP(hipGetLastError());
+    bem_status s = apply_Minv_mesh(p, 1, T, X + 2 * ne, part, kst);
+    // Y = [V_e b; T_e b; V_i u_b; T_i u_b]
+    if (!s) s = apply_A(p, pb.A0, X, Y, nullptr, false, kst, part);
+    // S = M_e^-1 [V_e b; T_e b]; X2 = [u_a; 0]; Y2 = [-K_i u_a; D_i u_a]
+    if (!s) s = apply_Minv_mesh(p, 0, Y, S, part, kst);
+    if (!s) s = hcn_to_interior(p, pb, S, c, kst, part);
+    if (!s) s = apply_A(p, pb.Ai, pb.X2.as<double2>(), Y2, nullptr, false, kst, part);
+    if (s) return s;
+    // Q = M_i^-1 [T_i u_b + D_i u_a; 0]
+    hipLaunchKernelGGL(hcn_spmv_kernel, gi, dim3(256), 0, st, ni, nullptr, nullptr, nullptr, Y + 2 * ne + ni, 1.0,
+                       Y2 + ni, W2, W2 + ni, kst);
+    BEM_HIP(hipGetLastError());
+    s = apply_Minv_mesh(p, 1, W2, Q, part, kst);
+    if (s) return s;
+    double2 *out = strong ? pb.Rr.as<double2>() : y;
+    hipLaunchKernelGGL(hcn_rows_kernel, ge, dim3(256), 0, st, ne, p->M_ptr[0].as<int32_t>(), p->M_col[0].as<int32_t>(),
+                       p->M_val[0].as<double>(), p->P_ei_ptr.as<int32_t>(), p->P_ei_col.as<int32_t>(),
+                       p->P_ei_val.as<double>(), x, Q, Y + ne, out, kst);
+    BEM_HIP(hipGetLastError());
+    (void)T;
+    if (strong) return apply_Minv_mesh(p, 0, out, z, part, kst);
+    return BEM_OK;
+}
+
+// right-hand side [c hat(D_i) M_e^-1 f; g] from [f; g]
+bem_status hcn_rhs(const bem_problem *p, const PmchwtBufs &pb, const double2 *fg, double2 *b, double4 *part)
+{
+    hipStream_t st = p->ctx->stream;
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
+    const double c = p->rho_ext / p->rho_int;
+    double2 *S = pb.S.as<double2>(), *Y2 = pb.Y2.as<double2>(), *W2 = pb.W2.as<double2>(), *Q = pb.Q.as<double2>();
+    const dim3 ge((ne + 255) / 256), gi((ni + 255) / 256);
+    bem_status s = apply_Minv_mesh(p, 0, fg, S, part, nullptr);
+    if (!s) s = hcn_to_interior(p, pb, S, c, nullptr, part);
+    if (!s) s = apply_A(p, pb.Ai, pb.X2.as<double2>(), Y2, nullptr, false, nullptr, part);
+    if (s) return s;
+    hipLaunchKernelGGL(hcn_spmv_kernel, gi, dim3(256), 0, st, ni, nullptr, nullptr, nullptr, Y2 + ni, 1.0, nullptr,
+                       W2, W2 + ni, nullptr);
+    BEM_HIP(hipGetLastError());
+    s = apply_Minv_mesh(p, 1, W2, Q, part, nullptr);
+    if (s) return s;
+    hipLaunchKernelGGL(hcn_spmv_kernel, ge, dim3(256), 0, st, ne, p->P_ei_ptr.as<int32_t>(), p->P_ei_col.as<int32_t>(),
+                       p->P_ei_val.as<double>(), Q, 1.0, nullptr, b, nullptr, nullptr);
+    hipLaunchKernelGGL(hcn_spmv_kernel, ge, dim3(256), 0, st, ne, nullptr, nullptr, nullptr, fg + ne, 1.0, nullptr,
+                       b + ne, nullptr, nullptr);
+    BEM_HIP(hipGetLastError());
+    return BEM_OK;
+}
+
+bem_status apply_ext_form(const bem_problem *p, const PmchwtBufs &pb, const double2 *x, double2 *y, double2 *z,
+                          bool strong, const KrylovState *kst, double4 *part)
+{
+    return pb.form == FORM_HCN ? apply_hcn(p, pb, x, y, z, strong, kst, part)
+                               : apply_pmchwt(p, pb, x, y, z, strong, kst, part);
 }
 
 // ||w|| on the device: into *out (device double)
@@ -1904,7 +2068,7 @@ struct Gmres {
             const double2 *vj = Vb + (size_t)j * n;
             bem_status s;
             if (pm)
-                s = apply_pmchwt(p, *pm, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
+                s = apply_ext_form(p, *pm, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
             else if (bb)
                 s = block_apply(p, A, *bb, R, vj, B.basis, W.y.as<double2>(), B.vec, W.z.as<double2>(), B.vec, true,
                                 dst);
@@ -2359,17 +2523,19 @@ __global__ void pmchwt_rhs_kernel(int n, const double2 *__restrict__ b_mtf, doub
     if (r < n) b[r] = make_double2(-b_mtf[r].x, -b_mtf[r].y);
 }
 
-// Exterior PMCHWT solve (Sec. 3.3, Eq. "pmchwt:discrete"): GMRES without
-// restart on the mass-preconditioned form M_e^-1 A x = M_e^-1 [f; g], one
-// right-hand side at a time, FP64 throughout; unknowns [gamma_D p,
-// gamma_N p] on the exterior mesh.
-bem_status pmchwt_solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
-                             bem_memspace space, bem_stats *stats)
+// Exterior formulations (Sec. 3.3): PMCHWT (Eq. "pmchwt:discrete", unknowns
+// [gamma_D p, gamma_N p], right-hand side [f; g]) or high-contrast Neumann
+// (Eq. "highcontrast:ext:neu", unknowns [gamma_N p, mu], right-hand side
+// [c hat(D_i) M_e^-1 f; g]); GMRES without restart on the mass-preconditioned
+// form M_e^-1 A x = M_e^-1 rhs, one right-hand side at a time, FP64
+// throughout.
+bem_status ext_form_solve_impl(bem_problem *p, int form, const double *dirs, int nrhs, const bem_solver_opts *opts,
+                               void *traces, bem_memspace space, bem_stats *stats)
 {
     bem_ctx *ctx = p->ctx;
     BEM_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    if (p->prec != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "PMCHWT: complex128 problems only");
+    if (p->prec != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "exterior formulations: complex128 problems only");
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne, nm = 2 * ne + 2 * ni;
     const int m = opts->maxit;
     const int R = 1;
@@ -2399,6 +2565,7 @@ bem_status pmchwt_solve_impl(bem_problem *p, const double *dirs, int nrhs, const
     if (!s) s = dev_alloc(ctx, W.state, sizeof(KrylovState));
     if (!s) s = dev_alloc(ctx, W.part, split_part_bytes(ne, ni));
     PmchwtBufs pb;
+    pb.form = form;
     if (!s) s = pmchwt_alloc(p, pb);
     if (s) return s;
     KrylovState *hstate = nullptr;
@@ -2424,7 +2591,13 @@ bem_status pmchwt_solve_impl(bem_problem *p, const double *dirs, int nrhs, const
     for (int r = 0; r < nrhs; ++r) {
         s = rhs_internal(p, dirs + 3 * r, W.b.as<double2>());
         if (s) return s;
-        hipLaunchKernelGGL(pmchwt_rhs_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), bp);
+        if (form == FORM_HCN) {
+            hipLaunchKernelGGL(pmchwt_rhs_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), W.z.as<double2>());
+            s = hcn_rhs(p, pb, W.z.as<double2>(), bp, W.part.as<double4>());
+            if (s) return s;
+        } else {
+            hipLaunchKernelGGL(pmchwt_rhs_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>(), bp);
+        }
         s = apply_Minv_mesh(p, 0, bp, W.r.as<double2>(), W.part.as<double4>(), nullptr);
         if (s) return s;
         KrylovState fin;
@@ -2433,7 +2606,7 @@ bem_status pmchwt_solve_impl(bem_problem *p, const double *dirs, int nrhs, const
         if (s) return s;
         total_it += fin.iters;
         // true strong-form residual M_e^-1 (b - A x), FP64
-        s = apply_pmchwt(p, pb, W.xin.as<double2>(), W.y.as<double2>(), nullptr, false, nullptr, W.part.as<double4>());
+        s = apply_ext_form(p, pb, W.xin.as<double2>(), W.y.as<double2>(), nullptr, false, nullptr, W.part.as<double4>());
         if (s) return s;
         hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, bp, W.y.as<double2>(), W.r.as<double2>());
         s = apply_Minv_mesh(p, 0, W.r.as<double2>(), W.z.as<double2>(), W.part.as<double4>(), nullptr);
@@ -2471,17 +2644,18 @@ bem_status pmchwt_solve_impl(bem_problem *p, const double *dirs, int nrhs, const
     return all_conv ? BEM_OK : set_error(BEM_W_NOCONV, "GMRES reached maxit before the tolerance");
 }
 
-// y = A x or M_e^-1 A x of the PMCHWT system; x, y: [2 N_ext] caller numbering
-bem_status pmchwt_matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space)
+// y = A x or M_e^-1 A x of an exterior formulation; x, y: [2 N_ext] caller numbering
+bem_status ext_form_matvec_impl(bem_problem *p, int form, const void *x, void *y, int strong, bem_memspace space)
 {
     bem_ctx *ctx = p->ctx;
     BEM_HIP(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
-    if (p->prec != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "PMCHWT: complex128 problems only");
+    if (p->prec != BEM_C128) return set_error(BEM_E_UNSUPPORTED, "exterior formulations: complex128 problems only");
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne;
     const size_t bytes = (size_t)n * sizeof(double2);
     DevMem xu, xi, yi, zi, yu, part;
     PmchwtBufs pb;
+    pb.form = form;
     bem_status s = dev_alloc(ctx, xu, bytes);
     if (!s) s = dev_alloc(ctx, xi, bytes);
     if (!s) s = dev_alloc(ctx, yi, bytes);
@@ -2494,8 +2668,8 @@ bem_status pmchwt_matvec_impl(bem_problem *p, const void *x, void *y, int strong
     const dim3 g((n + 255) / 256);
     const int32_t *pe = p->ext->d.perm.as<int32_t>();
     hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, 0, pe, pe, xu.as<double2>(), xi.as<double2>(), 1);
-    s = apply_pmchwt(p, pb, xi.as<double2>(), yi.as<double2>(), zi.as<double2>(), strong != 0, nullptr,
-                     part.as<double4>());
+    s = apply_ext_form(p, pb, xi.as<double2>(), yi.as<double2>(), zi.as<double2>(), strong != 0, nullptr,
+                       part.as<double4>());
     if (s) return s;
     hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, 0, pe, pe,
                        strong ? zi.as<double2>() : yi.as<double2>(), yu.as<double2>(), 0);

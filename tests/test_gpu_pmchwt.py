@@ -101,3 +101,54 @@ def test_pmchwt_errors(ctx):
         r.solve_pmchwt(np.array([[0.0, 0.0, 2.0]]))
     out, st, code = r.solve_pmchwt(c["dirs"], tol=1e-14, maxit=3)
     assert code == B.W_NOCONV and np.all(np.isfinite(out.cpu().numpy()))
+
+
+# ------------------------------------------------ exterior high-contrast Neumann
+
+@pytest.mark.parametrize("case", ["C1", "ellipsoid"])
+def test_hc_neumann_products_match_oracle(ctx, orc, case):
+    if case == "C1":
+        c = synth.make_config("C1")
+        ext, inte, ke, ki, re, ri = c["ext"], c["int"], c["k_ext"], c["k_int"], 1.0, 1.5
+    else:
+        ext, inte, _ = _ellipsoid()
+        ke, ki, re, ri = 3.0, 5.0, 1.0, 2.0
+    p, me, mi = _problem(ctx, ext, inte, ke, ki, re, ri)
+    ops = orc.operators(ext, inte, ke, ki)
+    A = orc.high_contrast_neumann_system(ops, re, ri)
+    ne = len(ext[0])
+    x = np.random.default_rng(8).standard_normal(2 * ne) + 1j * np.random.default_rng(9).standard_normal(2 * ne)
+    y = p.hc_neumann_matvec(torch.as_tensor(x), strong=False).cpu().numpy()
+    assert _rel(y, A @ x) < 1e-11
+    z = p.hc_neumann_matvec(torch.as_tensor(x), strong=True).cpu().numpy()
+    Me = ops["M_e"]
+    zr = np.concatenate([np.linalg.solve(Me, (A @ x)[:ne]), np.linalg.solve(Me, (A @ x)[ne:])])
+    assert _rel(z, zr) < 1e-11
+
+
+def test_hc_neumann_solve_matches_oracle_lu(ctx, orc):
+    ext, inte, _ = _ellipsoid()
+    ke, ki, re, ri = 3.0, 5.0, 1.0, 2.0
+    p, me, mi = _problem(ctx, ext, inte, ke, ki, re, ri)
+    d = synth.plane_wave_directions(2, np.random.default_rng(5))
+    out, st, code = p.solve_hc_neumann(d, tol=1e-9, maxit=1500)
+    assert code == B.OK, st
+    X, _ = orc.solve_high_contrast_neumann(ext, inte, ke, ki, re, ri, d)
+    got = out.cpu().numpy()
+    ne = len(ext[0])
+    for r in range(2):
+        assert _rel(got[r][:ne], X[r][:ne]) < 1e-5 and _rel(got[r][ne:], X[r][ne:]) < 1e-5
+    assert st["rel_residual"] < 2e-9
+
+
+def test_hc_neumann_c2_agrees_with_mtf(ctx):
+    """C2: the Neumann trace of the high-contrast solve agrees with the
+    multiple-traces -w_ext to the discretisation error."""
+    c = synth.make_config("C2")
+    p, me, mi = _problem(ctx, c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
+    xh, sh, code = p.solve_hc_neumann(c["dirs"], tol=1e-6, maxit=2000)
+    assert code == B.OK, sh
+    assert sh["rel_residual"] < 2e-6
+    xm, sm, code = p.solve(c["dirs"], tol=1e-6, maxit=2000)
+    ne = len(c["ext"][0])
+    assert _rel(xh.cpu().numpy()[0][:ne], -xm.cpu().numpy()[0][ne:2 * ne]) < 0.1
