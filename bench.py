@@ -315,11 +315,12 @@ def field_run(ctx, B, synth, np, reps=5):
 
 
 def pmchwt_run(ctx, B, synth, np, reps=3):
-    """The exterior PMCHWT formulation (Sec. 3.3) beside the multiple-traces
-    one on the C2 workload, after the same assembly: GMRES iterations, solve
-    time, time per iteration, and the relative difference of the exterior
-    traces (PMCHWT unknowns p and dp/dn+, multiple-traces -v_ext and -w_ext;
-    both solved to the workload's tolerance, 1e-6)."""
+    """The exterior PMCHWT and high-contrast Neumann formulations (Sec. 3.3)
+    beside the multiple-traces one on the C2 workload, after the same
+    assembly: GMRES iterations, solve time, time per iteration, and the
+    relative difference of the exterior traces (PMCHWT unknowns p and
+    dp/dn+, high-contrast dp/dn+ and mu, multiple-traces -v_ext and -w_ext;
+    all solved to the workload's tolerance, 1e-6)."""
     import torch
     c = synth.make_config("C2")
     me, mi = B.Mesh(ctx, *c["ext"]), B.Mesh(ctx, *c["int"])
@@ -328,13 +329,16 @@ def pmchwt_run(ctx, B, synth, np, reps=3):
     p.assemble_projection()
     p.solve_pmchwt(c["dirs"], tol=c["tol"], maxit=2000)   # warm-up
     res = {}
-    for name in ("pmchwt", "mtf"):
+    p.solve_hc_neumann(c["dirs"], tol=c["tol"], maxit=2000)   # warm-up
+    for name in ("pmchwt", "hc_neumann", "mtf"):
         lat = []
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if name == "pmchwt":
                 x, st, code = p.solve_pmchwt(c["dirs"], tol=c["tol"], maxit=2000)
+            elif name == "hc_neumann":
+                x, st, code = p.solve_hc_neumann(c["dirs"], tol=c["tol"], maxit=2000)
             else:
                 x, st, code = p.solve(c["dirs"], tol=c["tol"], maxit=2000)
             torch.cuda.synchronize()
@@ -345,10 +349,11 @@ def pmchwt_run(ctx, B, synth, np, reps=3):
                      "rel_residual": st["rel_residual"], "code": int(code)}
         res[name + "_x"] = x.cpu().numpy()[0]
     ne = len(c["ext"][0])
-    a, b = res.pop("pmchwt_x"), res.pop("mtf_x")
+    a, h, b = res.pop("pmchwt_x"), res.pop("hc_neumann_x"), res.pop("mtf_x")
     e = lambda u, v: float(np.linalg.norm(u - v) / np.linalg.norm(v))
     res["trace_rel_diff_p"] = e(a[:ne], -b[:ne])
     res["trace_rel_diff_dpdn"] = e(a[ne:], -b[ne:2 * ne])
+    res["hc_neumann_rel_diff_dpdn"] = e(h[:ne], -b[ne:2 * ne])
     res["workload"] = "C2 (sphere ico4 / Fibonacci 2002, k 5/8, rho ratio 1.5), 1 plane wave, tol 1e-6"
     return res
 
@@ -363,7 +368,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the multi-RHS comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-field", action="store_true", help="skip the field evaluation")
-    ap.add_argument("--no-pmchwt", action="store_true", help="skip the PMCHWT comparison")
+    ap.add_argument("--no-pmchwt", action="store_true", help="skip the comparison of the exterior formulations")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
                          "HBM byte counters) and exit")
