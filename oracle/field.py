@@ -85,10 +85,21 @@ def winding(xyz, tri, points):
     return np.array([np.sum(solid_angles(xyz, tri, x)) / (4.0 * np.pi) for x in points])
 
 
-def mtf_field(ext_mesh, int_mesh, k_ext, k_int, x, d, points, region):
+def incident(k, d, points, kind=0):
+    """The plane wave exp(i k d.x) (kind 0) or the point source
+    exp(i k |x - d|) / (4 pi |x - d|) (kind 1) at points [m][3]."""
+    points = np.asarray(points, dtype=np.float64).reshape(-1, 3)
+    if kind == 0:
+        return np.exp(1j * k * (points @ np.asarray(d, dtype=np.float64)))
+    r = np.linalg.norm(points - np.asarray(d, dtype=np.float64)[None, :], axis=1)
+    return np.exp(1j * k * r) / (4.0 * np.pi * r)
+
+
+def mtf_field(ext_mesh, int_mesh, k_ext, k_int, x, d, points, region, kind=0):
     """Total field at points from the unknowns x = [v_e, w_e, v_i, w_i] of one
-    plane wave exp(i k_ext d.x); region[m] = 1 for interior points (interior
-    formula), 0 for exterior ones (incident plus scattered field)."""
+    incident field (kind 0: plane wave exp(i k_ext d.x); kind 1: point source
+    at d); region[m] = 1 for interior points (interior formula), 0 for
+    exterior ones (incident plus scattered field)."""
     ne, ni = len(ext_mesh[0]), len(int_mesh[0])
     x = np.asarray(x, dtype=np.complex128)
     v_e, w_e = x[:ne], x[ne:2 * ne]
@@ -99,8 +110,7 @@ def mtf_field(ext_mesh, int_mesh, k_ext, k_int, x, d, points, region):
     ext = region == 0
     if ext.any():
         xe = points[ext]
-        out[ext] = np.exp(1j * k_ext * (xe @ np.asarray(d, dtype=np.float64))) + \
-            potentials(*ext_mesh, k_ext, v_e, w_e, xe)
+        out[ext] = incident(k_ext, d, xe, kind) + potentials(*ext_mesh, k_ext, v_e, w_e, xe)
     if (~ext).any():
         out[~ext] = potentials(*int_mesh, k_int, -v_i, -w_i, points[~ext])
     return out

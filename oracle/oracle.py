@@ -13,6 +13,8 @@ primitives and no blocking or reordering:
   mass(xyz, tri)          M[i][j] = <phi_i, phi_j>  (Sec. 3.1)
   plane_wave_rhs(...)     f_j = <u_inc, phi_j>, g_j = <d_n u_inc, phi_j>
                           with u_inc = exp(i k d.x)  (plane wave, Sec. 5.3)
+  point_source_rhs(...)   the same for u_inc = exp(i k r) / (4 pi r),
+                          r = |x - x0|  (point source, Sec. 6.4)
   mtf_system(...)         the discrete multiple-traces system as printed in
                           Sec. 3.3, with right-hand side [-f, -g, 0, 0]
   solve_mtf(...)          x = A^{-1} b by dense LU: GMRES on the mass-
@@ -160,6 +162,31 @@ def plane_wave_rhs(xyz, tri, k, d):
     return f, g
 
 
+def point_source_rhs(xyz, tri, k, x0):
+    """f_j = <u_inc, phi_j>, g_j = <d_n u_inc, phi_j> for the point source
+    u_inc(x) = exp(i k |x - x0|) / (4 pi |x - x0|) (Sec. 6.4), with
+    d_n u_inc = exp(i k r)(i k r - 1)((x - x0).n) / (4 pi r^3); every
+    triangle by the 6-point rule (area times the weights)."""
+    xyz, tri = _mesh(xyz, tri)
+    bary, w = rule6()
+    P = xyz[tri]
+    cr = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    n = cr / (2.0 * area)[:, None]
+    Y = np.einsum("qa,tac->tqc", bary, P)
+    R = Y - np.asarray(x0, dtype=np.float64)[None, None, :]
+    r = np.linalg.norm(R, axis=2)
+    e = np.exp(1j * k * r) / (4.0 * np.pi * r)
+    du = e * (1j * k * r - 1.0) * np.einsum("tqc,tc->tq", R, n) / r ** 2
+    f = np.zeros(xyz.shape[0], dtype=np.complex128)
+    g = np.zeros(xyz.shape[0], dtype=np.complex128)
+    for a in range(3):
+        wa = area[:, None] * w[None, :] * bary[None, :, a]
+        np.add.at(f, tri[:, a], np.sum(wa * e, axis=1))
+        np.add.at(g, tri[:, a], np.sum(wa * du, axis=1))
+    return f, g
+
+
 def operators(ext_mesh, int_mesh, k_ext, k_int, ng=4):
     """All dense operators and sparse couplings of the multiple-traces system."""
     Oe = assemble(*ext_mesh, k_ext, ng=ng)
@@ -188,8 +215,10 @@ def mtf_system(ops, rho_ext, rho_int):
     return A
 
 
-def mtf_rhs(ext_mesh, k_ext, d, n_int):
-    f, g = plane_wave_rhs(*ext_mesh, k_ext, d)
+def mtf_rhs(ext_mesh, k_ext, d, n_int, incident=0):
+    """[-f, -g, 0, 0] for the plane wave of direction d (incident 0) or the
+    point source at d (incident 1)."""
+    f, g = plane_wave_rhs(*ext_mesh, k_ext, d) if incident == 0 else point_source_rhs(*ext_mesh, k_ext, d)
     return np.concatenate([-f, -g, np.zeros(2 * n_int, dtype=np.complex128)])
 
 
@@ -209,13 +238,14 @@ def strong_matvec(A, M, x):
     return np.linalg.solve(M, A @ x)
 
 
-def solve_mtf(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4, ops=None):
-    """Exact discrete MTF solution(s) by dense LU; returns (x [nrhs, n], ops)."""
+def solve_mtf(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4, ops=None, incident=0):
+    """Exact discrete MTF solution(s) by dense LU; returns (x [nrhs, n], ops).
+    dirs: plane-wave directions (incident 0) or point-source positions (1)."""
     if ops is None:
         ops = operators(ext_mesh, int_mesh, k_ext, k_int, ng=ng)
     A = mtf_system(ops, rho_ext, rho_int)
     ni = ops["M_i"].shape[0]
-    B = np.stack([mtf_rhs(ext_mesh, k_ext, d, ni) for d in np.atleast_2d(dirs)], axis=1)
+    B = np.stack([mtf_rhs(ext_mesh, k_ext, d, ni, incident) for d in np.atleast_2d(dirs)], axis=1)
     X = np.linalg.solve(A, B)
     return X.T, ops
 

@@ -470,3 +470,40 @@ def test_high_contrast_neumann_mie(orc):
     hatD = ops["P_ie"].T @ np.linalg.solve(ops["M_i"], ops["int"]["D"] @ np.linalg.solve(ops["M_i"], ops["P_ie"]))
     literal = np.linalg.solve(A, np.concatenate([(re / ri) * hatD @ f, g]))
     assert e(literal[:ne], mie_traces(xe, d, ke, ki, re, ri)[1]) > 0.5
+
+
+# ------------------------------------------------------------- point source
+
+def test_point_source_far_away_is_a_plane_wave(orc):
+    """A source at x0 = -R d: |x - x0| = R + d.x + O(|x|^2 / R), so the loads
+    scaled by 4 pi R exp(-i k R) approach those of the plane wave of
+    direction d at O(k / R); this pins the kernel, its normal derivative and
+    its sign."""
+    xyz, tri = synth.icosphere(2)
+    k = 2.0
+    d = np.array([0.6, 0.0, 0.8])
+    fp, gp = orc.plane_wave_rhs(xyz, tri, k, d)
+    errs = []
+    for R in (1e3, 1e4):
+        f, g = orc.point_source_rhs(xyz, tri, k, -R * d)
+        sc = 4 * np.pi * R * np.exp(-1j * k * R)
+        errs.append(max(np.abs(sc * f - fp).max() / np.abs(fp).max(), np.abs(sc * g - gp).max() / np.abs(gp).max()))
+    assert errs[1] < 5e-4 and errs[1] < errs[0] / 5, errs
+
+
+def test_point_source_transparent_body(orc):
+    """k_int = k_ext, equal densities: the traces are those of the point
+    source itself, and so is the field inside and outside."""
+    from oracle import field as F
+    k = 1.5
+    x0 = np.array([0.3, -0.2, 2.5])
+    (xe, te), (xi, ti), _ = synth.configs.make_pair(8, 3, "fib", 0.02, (1, 1, 1), int_n=500)
+    X, _ = orc.solve_mtf((xe, te), (xi, ti), k, k, 1.0, 1.0, x0, incident=1)
+    x = X[0]
+    ne = len(xe)
+    u = F.incident(k, x0, xe, 1)
+    e = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert e(-x[:ne], u) < 0.02
+    pts = np.array([[0.1, 0.2, -0.3], [0.0, 0.0, 0.4], [2.0, 0.5, 0.0], [-1.0, 1.5, 1.0]])
+    f = F.mtf_field((xe, te), (xi, ti), k, k, x, x0, pts, np.array([1, 1, 0, 0]), kind=1)
+    assert e(f, F.incident(k, x0, pts, 1)) < 0.02
