@@ -205,6 +205,14 @@ bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong
 bem_status bem_mtf_matvec_batch(bem_problem *p, const void *x, void *y, int32_t nrhs, int32_t strong,
                                 bem_memspace space);
 
+/* Incident field of the problem's solves, right-hand sides and fields:
+ * kind 0 (the default) plane waves exp(i k_ext d.x) (Sec. 5.3), whose `dirs`
+ * arguments are unit directions; kind 1 point sources
+ * exp(i k_ext |x - x0|) / (4 pi |x - x0|) (Sec. 6.4), whose `dirs` arguments
+ * are the source positions x0 (finite; a source on or near the exterior
+ * mesh makes the loads' quadrature inaccurate).  BEM_E_ARG for another kind. */
+bem_status bem_problem_set_incident(bem_problem *p, int32_t kind);
+
 /* Right-hand side [-f, -g, 0, 0] of the multiple-traces system for the
  * plane wave exp(i k_ext d.x) (Sec. 5.3, Eq. "planewave"):
  * f_j = <u_inc, phi_j>, g_j = <du_inc/dn, phi_j> on the exterior mesh.

@@ -183,6 +183,11 @@ class Problem:
                                          ctypes.byref(st)))
         return out, st.as_dict(), code
 
+    def set_incident(self, kind):
+        """bem_problem_set_incident: 0 plane waves (dirs are directions), 1 point
+        sources (dirs are source positions)."""
+        _check(N.load().bem_problem_set_incident(self._h, int(kind)))
+
     def field(self, dirs, traces, points, region=None):
         """bem_field: total field [nrhs, m] at points [m,3] from the traces of
         solve() for the plane waves dirs; region [m] is 1 for interior and 0

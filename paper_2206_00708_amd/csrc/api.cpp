@@ -570,10 +570,36 @@ bem_status bem_mtf_matvec_batch(bem_problem *p, const void *x, void *y, int32_t 
     return matvec_batch_impl(p, x, y, nrhs, strong, space);
 }
 
+// the incident fields of a call: unit directions (plane waves) or finite
+// positions (point sources), by the problem's setting
+static bem_status check_sources(const bem_problem *p, const double *dirs, int32_t nrhs)
+{
+    for (int r = 0; r < nrhs; ++r) {
+        const double *d = dirs + 3 * r;
+        if (p->incident == 1) {
+            if (!(std::isfinite(d[0]) && std::isfinite(d[1]) && std::isfinite(d[2])))
+                return set_error(BEM_E_ARG, "point-source positions must be finite");
+        } else {
+            const double l = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(std::fabs(l - 1.0) < 1e-6)) return set_error(BEM_E_ARG, "directions must be unit vectors");
+        }
+    }
+    return BEM_OK;
+}
+
+bem_status bem_problem_set_incident(bem_problem *p, int32_t kind)
+{
+    if (!p) return set_error(BEM_E_ARG, "null problem");
+    if (kind != 0 && kind != 1) return set_error(BEM_E_ARG, "incident kind must be 0 (plane waves) or 1 (point sources)");
+    p->incident = kind;
+    return BEM_OK;
+}
+
 bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b, bem_memspace space)
 {
     if (!p || !dirs || !b || nrhs < 1) return set_error(BEM_E_ARG, "bad argument");
-    return rhs_impl(p, dirs, nrhs, b, space);
+    bem_status s = check_sources(p, dirs, nrhs);
+    return s ? s : rhs_impl(p, dirs, nrhs, b, space);
 }
 
 bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem_solver_opts *opts, void *traces,
@@ -584,11 +610,8 @@ bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem
         return set_error(BEM_E_ARG, "tol must be > 0 and 1 <= maxit <= 3000");
     if (opts->batch < 0 || opts->batch > 64) return set_error(BEM_E_ARG, "batch must be 0..64");
     if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
-    for (int r = 0; r < nrhs; ++r) {
-        double l = std::sqrt(dirs[3 * r] * dirs[3 * r] + dirs[3 * r + 1] * dirs[3 * r + 1] + dirs[3 * r + 2] * dirs[3 * r + 2]);
-        if (!(std::fabs(l - 1.0) < 1e-6)) return set_error(BEM_E_ARG, "directions must be unit vectors");
-    }
-    return solve_impl(p, dirs, nrhs, opts, traces, space, stats);
+    bem_status s = check_sources(p, dirs, nrhs);
+    return s ? s : solve_impl(p, dirs, nrhs, opts, traces, space, stats);
 }
 
 bem_status bem_copy_operator(const bem_problem *p, int32_t mesh, char op, void *dst, bem_memspace space)
@@ -725,9 +748,9 @@ bem_status bem_field(bem_problem *p, const double *dirs, int32_t nrhs, const voi
     if (npts > 0 && (!points || !region || !field)) return set_error(BEM_E_ARG, "null points, region or field");
     if (npts > (int64_t)1 << 28) return set_error(BEM_E_ARG, "at most 2^28 points per call");
     if (space != BEM_HOST && space != BEM_DEVICE) return set_error(BEM_E_ARG, "bad memory space");
-    for (int r = 0; r < nrhs; ++r) {
-        const double l = std::sqrt(dirs[3 * r] * dirs[3 * r] + dirs[3 * r + 1] * dirs[3 * r + 1] + dirs[3 * r + 2] * dirs[3 * r + 2]);
-        if (!(std::fabs(l - 1.0) < 1e-6)) return set_error(BEM_E_ARG, "directions must be unit vectors");
+    {
+        bem_status sc = check_sources(p, dirs, nrhs);
+        if (sc) return sc;
     }
     if (npts == 0) return BEM_OK;
     bem_ctx *ctx = p->ctx;
@@ -824,9 +847,9 @@ static bem_status ext_form_check(bem_problem *p, const double *dirs, int32_t nrh
         return set_error(BEM_E_ARG, "tol must be > 0 and 1 <= maxit <= 3000");
     if (space != BEM_HOST && space != BEM_DEVICE) return set_error(BEM_E_ARG, "bad memory space");
     if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
-    for (int r = 0; r < nrhs; ++r) {
-        const double l = std::sqrt(dirs[3 * r] * dirs[3 * r] + dirs[3 * r + 1] * dirs[3 * r + 1] + dirs[3 * r + 2] * dirs[3 * r + 2]);
-        if (!(std::fabs(l - 1.0) < 1e-6)) return set_error(BEM_E_ARG, "directions must be unit vectors");
+    {
+        bem_status sc = check_sources(p, dirs, nrhs);
+        if (sc) return sc;
     }
     return BEM_OK;
 }

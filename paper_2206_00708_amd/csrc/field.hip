@@ -141,7 +141,7 @@ __global__ __launch_bounds__(FLD_PB) void field_partial_kernel(int np, const dou
 __global__ __launch_bounds__(256) void field_combine_kernel(int np, int nchunk, const double2 *__restrict__ part,
                                                             const double *__restrict__ pts,
                                                             const int32_t *__restrict__ dst_index, int add_incident,
-                                                            double k, double d0, double d1, double d2,
+                                                            int kind, double k, double d0, double d1, double d2,
                                                             double2 *__restrict__ field)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -154,11 +154,18 @@ __global__ __launch_bounds__(256) void field_combine_kernel(int np, int nchunk, 
     }
     sr *= kInv4Pi;
     si *= kInv4Pi;
-    if (add_incident) {
+    if (add_incident && kind == 0) {   // plane wave exp(i k d.x)
         double sn, cs;
         phase_sincos(k * (d0 * pts[3 * i] + d1 * pts[3 * i + 1] + d2 * pts[3 * i + 2]), &sn, &cs);
         sr += cs;
         si += sn;
+    } else if (add_incident) {         // point source exp(i k r) / (4 pi r), r = |x - x0|
+        const double R0 = pts[3 * i] - d0, R1 = pts[3 * i + 1] - d1, R2 = pts[3 * i + 2] - d2;
+        const double r = sqrt(R0 * R0 + R1 * R1 + R2 * R2);
+        double sn, cs;
+        phase_sincos(k * r, &sn, &cs);
+        sr += cs * kInv4Pi / r;
+        si += sn * kInv4Pi / r;
     }
     field[dst_index[i]] = make_double2(sr, si);
 }
@@ -255,7 +262,8 @@ bem_status launch_field_region(bem_problem *p, int region, int np, const double 
         BEM_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(field_combine_kernel, dim3((np + 255) / 256), dim3(256), 0, st, np, nchunk,
-                       part.as<double2>(), pts, dst_index, region == 0 ? 1 : 0, p->k_ext, dir[0], dir[1], dir[2],
+                       part.as<double2>(), pts, dst_index, region == 0 ? 1 : 0, p->incident, p->k_ext, dir[0], dir[1],
+                       dir[2],
                        field);
     BEM_HIP(hipGetLastError());
     return BEM_OK;

@@ -88,8 +88,10 @@ __device__ inline double wave_sum(double v)
 // b = [-f, -g, 0, 0] in internal numbering for one direction d:
 // f_j = sum over triangles t at j of A_t sum_q w_q lambda_j(q) exp(i k d.x_q),
 // g_j = the same with the factor i k (d.n_t).
+// incident field: kind 0 the plane wave exp(i k d.x) (Sec. 5.3), kind 1 the
+// point source exp(i k |x - x0|) / (4 pi |x - x0|) at x0 = (d0, d1, d2) (Sec. 6.4)
 __global__ void rhs_kernel(int ne, int ni, const int32_t *__restrict__ star_ptr, const int32_t *__restrict__ star_ent,
-                           const TriGeo *__restrict__ geo, double k, double d0, double d1, double d2,
+                           const TriGeo *__restrict__ geo, double k, int kind, double d0, double d1, double d2,
                            double2 *__restrict__ b)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,22 +106,42 @@ __global__ void rhs_kernel(int ne, int ni, const int32_t *__restrict__ star_ptr,
         const TriGeo &g = geo[t];
         const double dn = d0 * g.n[0] + d1 * g.n[1] + d2 * g.n[2];
         double sr = 0.0, si = 0.0;
-        for (int q = 0; q < 6; ++q) {
-            const double ph = k * (d0 * g.qp[q][0] + d1 * g.qp[q][1] + d2 * g.qp[q][2]);
-            double s, c;
-            phase_sincos(ph, &s, &c);
-            const double w = q6_w(q) * q6_bary(q, a);
-            sr += w * c;
-            si += w * s;
-        }
-        sr *= g.area;
-        si *= g.area;
-        if (is_g) {   // i k dn (sr + i si)
-            re += -k * dn * si;
-            im += k * dn * sr;
+        if (kind == 0) {
+            for (int q = 0; q < 6; ++q) {
+                const double ph = k * (d0 * g.qp[q][0] + d1 * g.qp[q][1] + d2 * g.qp[q][2]);
+                double s, c;
+                phase_sincos(ph, &s, &c);
+                const double w = q6_w(q) * q6_bary(q, a);
+                sr += w * c;
+                si += w * s;
+            }
+            sr *= g.area;
+            si *= g.area;
+            if (is_g) {   // i k dn (sr + i si)
+                re += -k * dn * si;
+                im += k * dn * sr;
+            } else {
+                re += sr;
+                im += si;
+            }
         } else {
-            re += sr;
-            im += si;
+            for (int q = 0; q < 6; ++q) {
+                const double R0 = g.qp[q][0] - d0, R1 = g.qp[q][1] - d1, R2 = g.qp[q][2] - d2;   // y - x0
+                const double r = sqrt(R0 * R0 + R1 * R1 + R2 * R2), inv = 0.0795774715459476678844418816863 / r;
+                double s, c;
+                phase_sincos(k * r, &s, &c);
+                const double w = q6_w(q) * q6_bary(q, a);
+                if (is_g) {   // exp(ikr)(ikr - 1)((y - x0).n) / (4 pi r^3)
+                    const double f = (R0 * g.n[0] + R1 * g.n[1] + R2 * g.n[2]) / (r * r) * inv;
+                    sr += w * (-c - s * k * r) * f;
+                    si += w * (c * k * r - s) * f;
+                } else {
+                    sr += w * c * inv;
+                    si += w * s * inv;
+                }
+            }
+            re += sr * g.area;
+            im += si * g.area;
         }
     }
     b[j] = make_double2(-re, -im);
@@ -2271,7 +2293,7 @@ static bem_status rhs_internal(bem_problem *p, const double *d, double2 *b)
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne + 2 * ni;
     hipLaunchKernelGGL(rhs_kernel, dim3((n + 255) / 256), dim3(256), 0, p->ctx->stream, ne, ni,
                        p->ext->d.star_ptr.as<int32_t>(), p->ext->d.star_ent.as<int32_t>(), p->ext->d.geo.as<TriGeo>(),
-                       p->k_ext, d[0], d[1], d[2], b);
+                       p->k_ext, p->incident, d[0], d[1], d[2], b);
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
