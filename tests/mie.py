@@ -22,7 +22,7 @@ def mie_traces(points, d, k_e, k_i, rho_e, rho_i, nmax=None):
     """Surface values p, dp+/dr, dp-/dr at unit-sphere points (radial normal)."""
     xe, xi = k_e, k_i
     if nmax is None:
-        nmax = int(xe + 4 * xe ** (1 / 3) + 10 + xi)
+        nmax = int(abs(xe) + 4 * abs(xe) ** (1 / 3) + 10 + abs(xi))
     g = (k_i * rho_e) / (k_e * rho_i)
     ct = np.clip(points @ d / np.linalg.norm(points, axis=1), -1, 1)
     p = np.zeros(points.shape[0], dtype=complex)
@@ -46,7 +46,7 @@ def mie_field(points, d, k_e, k_i, rho_e, rho_i, nmax=None):
     (continuity of p at r = 1)."""
     xe, xi = k_e, k_i
     if nmax is None:
-        nmax = int(xe + 4 * xe ** (1 / 3) + 10 + xi)
+        nmax = int(abs(xe) + 4 * abs(xe) ** (1 / 3) + 10 + abs(xi))
     g = (k_i * rho_e) / (k_e * rho_i)
     points = np.asarray(points, dtype=float)
     r = np.linalg.norm(points, axis=1)

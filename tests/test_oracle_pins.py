@@ -507,3 +507,29 @@ def test_point_source_transparent_body(orc):
     pts = np.array([[0.1, 0.2, -0.3], [0.0, 0.0, 0.4], [2.0, 0.5, 0.0], [-1.0, 1.5, 1.0]])
     f = F.mtf_field((xe, te), (xi, ti), k, k, x, x0, pts, np.array([1, 1, 0, 0]), kind=1)
     assert e(f, F.incident(k, x0, pts, 1)) < 0.02
+
+
+# ------------------------------------------------------ absorbing interior
+
+def test_complex_interior_wavenumber_mie(orc):
+    """An absorbing interior (k_int = 3 + 0.6 i, the power-law attenuation of
+    the foam model, Sec. 6.4): the discrete MTF solution converges at O(h^2)
+    to the penetrable-sphere series with the complex wavenumber, on
+    conforming and nonconforming grids."""
+    ke, ki, re, ri = 2.0, 3.0 + 0.6j, 1.0, 1.5
+    d = np.array([0.0, 0.0, 1.0])
+    e = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    for int_kind in ("ico", "fib"):
+        errs = []
+        for L in (1, 2, 3):
+            (xe, te), (xi, ti), _ = synth.configs.make_pair(7, L, int_kind, 0.01, (1, 1, 1), int_level=L,
+                                                            int_n={1: 30, 2: 120, 3: 500}[L])
+            X, _ = orc.solve_mtf((xe, te), (xi, ti), ke, ki, re, ri, d)
+            x = X[0]; ne, ni = len(xe), len(xi)
+            p, dpp, _ = mie_traces(xe, d, ke, ki, re, ri)
+            pi, _, dpmi = mie_traces(xi, d, ke, ki, re, ri)
+            errs.append([e(-x[:ne], p), e(-x[ne:2 * ne], dpp), e(-x[2 * ne:2 * ne + ni], pi),
+                         e(-x[2 * ne + ni:], dpmi)])
+        errs = np.array(errs)
+        assert np.all(errs[1] < errs[0] / 2.5) and np.all(errs[2] < errs[1] / 2.5), (int_kind, errs)
+        assert np.all(errs[2] < 0.03), (int_kind, errs)
