@@ -213,6 +213,17 @@ bem_status bem_mtf_matvec_batch(bem_problem *p, const void *x, void *y, int32_t 
  * mesh makes the loads' quadrature inaccurate).  BEM_E_ARG for another kind. */
 bem_status bem_problem_set_incident(bem_problem *p, int32_t kind);
 
+/* Absorbing interior (the foam model of Sec. 6.4, whose interior wavenumber
+ * carries an imaginary part that grows with frequency): the interior
+ * wavenumber becomes k_int + i k_int_imag, so that the interior Green's
+ * function is exp(i k_int r - k_int_imag r) / (4 pi r) in the assembly of the
+ * interior operators (regular and singular pairs, both precisions) and in the
+ * interior field of bem_field.  k_int_imag >= 0 and finite, else BEM_E_ARG;
+ * 0 (the default) is the lossless medium.  A changed value marks the
+ * assembled operators stale: call bem_assemble_operators again before a
+ * solve (BEM_E_STATE otherwise). */
+bem_status bem_problem_set_k_int_imag(bem_problem *p, double k_int_imag);
+
 /* Right-hand side [-f, -g, 0, 0] of the multiple-traces system for the
  * plane wave exp(i k_ext d.x) (Sec. 5.3, Eq. "planewave"):
  * f_j = <u_inc, phi_j>, g_j = <du_inc/dn, phi_j> on the exterior mesh.

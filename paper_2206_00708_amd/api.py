@@ -188,6 +188,11 @@ class Problem:
         sources (dirs are source positions)."""
         _check(N.load().bem_problem_set_incident(self._h, int(kind)))
 
+    def set_k_int_imag(self, k_int_imag):
+        """bem_problem_set_k_int_imag: interior wavenumber k_int + i k_int_imag
+        (absorbing interior); assemble again afterwards."""
+        _check(N.load().bem_problem_set_k_int_imag(self._h, float(k_int_imag)))
+
     def field(self, dirs, traces, points, region=None):
         """bem_field: total field [nrhs, m] at points [m,3] from the traces of
         solve() for the plane waves dirs; region [m] is 1 for interior and 0

@@ -119,8 +119,8 @@ static bem_status upload(bem_ctx *ctx, DevMem &m, const std::vector<T, A> &v, hi
 // kernels (assemble.hip, solve.hip)
 bem_status launch_geometry(const bem_mesh *m, hipStream_t st);
 size_t tile_scratch_bytes(const bem_mesh *m, size_t entry_bytes);
-bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch, void *ops[4], hipStream_t st);
-bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw, bool fp32,
+bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, void *scratch, void *ops[4], hipStream_t st);
+bem_status launch_singular(const bem_mesh *m, double k, double kim, int ng, const double *glx, const double *glw, bool fp32,
                            double2 *contrib, void *ops[4], hipStream_t st);
 bem_status launch_mass_inverse(bem_problem *p, int mesh, hipStream_t st);
 bem_status launch_sym_corrections(bem_problem *p, int mesh, hipStream_t st);
@@ -439,6 +439,7 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
     BEM_HIP(hipEventRecord(p->ev_pre_asm, st));
     const bem_mesh *meshes[2] = {p->ext, p->inte};
     const double ks[2] = {p->k_ext, p->k_int};
+    const double kims[2] = {0.0, p->k_int_im};
     const bool fp32 = p->prec == BEM_C64_MIXED;
     const size_t eb = fp32 ? sizeof(float2) : sizeof(double2);
     size_t scratch_bytes = 16;
@@ -486,14 +487,14 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts)
         const size_t nv = meshes[m]->h.nv;
         BEM_HIP(hipEventRecord(p->asm_ev[m][0], st));
         if (parts & 1) {
-            bem_status s = launch_regular(meshes[m], ks[m], fp32, scratch, ops, st);
+            bem_status s = launch_regular(meshes[m], ks[m], kims[m], fp32, scratch, ops, st);
             if (s) return s;
         } else {
             for (int op = 0; op < 4; ++op) BEM_HIP(hipMemsetAsync(ops[op], 0, nv * op_ld(nv) * eb, st));
         }
         BEM_HIP(hipEventRecord(p->asm_ev[m][1], st));
         if (parts & 2) {
-            bem_status s = launch_singular(meshes[m], ks[m], p->ng, p->gl_x, p->gl_w, fp32,
+            bem_status s = launch_singular(meshes[m], ks[m], kims[m], p->ng, p->gl_x, p->gl_w, fp32,
                                            static_cast<double2 *>(scratch), ops, st);
             if (s) return s;
         }
@@ -592,6 +593,16 @@ bem_status bem_problem_set_incident(bem_problem *p, int32_t kind)
     if (!p) return set_error(BEM_E_ARG, "null problem");
     if (kind != 0 && kind != 1) return set_error(BEM_E_ARG, "incident kind must be 0 (plane waves) or 1 (point sources)");
     p->incident = kind;
+    return BEM_OK;
+}
+
+bem_status bem_problem_set_k_int_imag(bem_problem *p, double k_int_imag)
+{
+    if (!p) return set_error(BEM_E_ARG, "null problem");
+    if (!(k_int_imag >= 0) || !std::isfinite(k_int_imag))
+        return set_error(BEM_E_ARG, "the imaginary part of the interior wavenumber must be finite and >= 0");
+    if (k_int_imag != p->k_int_im) p->ops_ready = false;   // assembled operators belong to the old wavenumber
+    p->k_int_im = k_int_imag;
     return BEM_OK;
 }
 

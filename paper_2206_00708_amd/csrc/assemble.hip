@@ -84,6 +84,7 @@ struct TileArgs {
     const uint8_t *slot_ent;
     int32_t nb;
     double k;
+    double kim;            // imaginary part of the wavenumber (read by the absorbing instantiation only)
     double2 *scratch;      // [tile][SMAX*SMAX][op]
 };
 
@@ -159,9 +160,13 @@ struct TileArgsF {
     const uint8_t *slot_ent;
     int32_t nb;
     double k;
+    double kim;            // imaginary part of the wavenumber (read by the absorbing instantiation only)
     float2 *scratch;       // [tile][SMAX*SMAX][op]
 };
 
+// CK: complex wavenumber k + i kim (an absorbing medium), G = exp(i k r - kim r) / (4 pi r);
+// the real-k instantiation is the one the benchmarks time.
+template <bool CK>
 __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64_t tile0)
 {
     __shared__ TriGeo gX[BT], gY[BT];
@@ -226,10 +231,18 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
                 const double kr_ = k * r;
                 double sn, cs;
                 phase_sincos(kr_, &sn, &cs);
-                const double gr = cs * rinv, gi = sn * rinv;           // exp(ikr)/r
+                double gr = cs * rinv, gi = sn * rinv;                 // exp(ikr)/r
                 const double rinv2 = rinv * rinv;
-                const double fr = (-gr - gi * kr_) * rinv2;            // exp(ikr)(ikr-1)/r^3
-                const double fi = (gr * kr_ - gi) * rinv2;
+                double fr, fi;                                         // exp(ikr)(ikr-1)/r^3
+                if constexpr (CK) {
+                    const double dmp = exp(-A.kim * r), am = -1.0 - A.kim * r;
+                    gr *= dmp; gi *= dmp;
+                    fr = (gr * am - gi * kr_) * rinv2;
+                    fi = (gr * kr_ + gi * am) * rinv2;
+                } else {
+                    fr = (-gr - gi * kr_) * rinv2;
+                    fi = (gr * kr_ - gi) * rinv2;
+                }
                 const double dk = -(d0 * ny0 + d1 * ny1 + d2 * ny2);  // (y-x).n_y
                 const double dt = d0 * nx0 + d1 * nx1 + d2 * nx2;     // (x-y).n_x
                 const double gkr = fr * dk, gki = fi * dk, gtr = fr * dt, gti = fi * dt;
@@ -279,8 +292,15 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
                     const double cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
-                    st[sbase + 3 * a + b] = make_double2(cc * sr - k * k * nn * vr[3 * a + b],
-                                                           cc * si - k * k * nn * vi[3 * a + b]);
+                    if constexpr (CK) {   // complex k^2
+                        const double k2r = k * k - A.kim * A.kim, k2i = 2.0 * k * A.kim;
+                        const double v_r = vr[3 * a + b], v_i = vi[3 * a + b];
+                        st[sbase + 3 * a + b] = make_double2(cc * sr - nn * (k2r * v_r - k2i * v_i),
+                                                               cc * si - nn * (k2r * v_i + k2i * v_r));
+                    } else {
+                        st[sbase + 3 * a + b] = make_double2(cc * sr - k * k * nn * vr[3 * a + b],
+                                                               cc * si - k * k * nn * vi[3 * a + b]);
+                    }
                 }
         } else {
 #pragma unroll
@@ -302,6 +322,9 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
 // where exp(i k r0) is evaluated once in FP64 and D = r - r0 =
 // (2 d0.e + |e|^2) / (r + r0), e = (x - c_x) - (y - c_y), is small and
 // accurate in FP32; FP32 alone would lose about k r * 6e-8 of phase.
+// CK as in the FP64 kernel: the damping exp(-kim r) splits like the phase,
+// exp(-kim r0) in FP64 per pair and exp(-kim D) in FP32 per point.
+template <bool CK>
 __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, int64_t tile0)
 {
     __shared__ TriGeoF gX[BT], gY[BT];
@@ -354,6 +377,11 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
         const double r0 = sqrt(d00 * d00 + d01 * d01 + d02 * d02);
         double s0, c0;
         phase_sincos(A.k * r0, &s0, &c0);
+        if constexpr (CK) {
+            const double dm0 = exp(-A.kim * r0);
+            s0 *= dm0;
+            c0 *= dm0;
+        }
         const float e0r = (float)c0, e0i = (float)s0;
         const float f00 = (float)d00, f01 = (float)d01, f02 = (float)d02, r0f = (float)r0;
         const float nx0 = X.n[0], nx1 = X.n[1], nx2 = X.n[2];
@@ -374,10 +402,22 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
                 const float dr = num / (r + r0f);
                 float sd, cd;
                 sincosf(kf * dr, &sd, &cd);
-                const float er = e0r * cd - e0i * sd, ei = e0r * sd + e0i * cd;   // exp(ikr)
-                const float gr = er * rinv, gi = ei * rinv;
+                float er = e0r * cd - e0i * sd, ei = e0r * sd + e0i * cd;   // exp(ikr)
                 const float kr_ = kf * r, rinv2 = rinv * rinv;
-                const float fr = (-gr - gi * kr_) * rinv2, fi = (gr * kr_ - gi) * rinv2;
+                float fr, fi;
+                if constexpr (CK) {
+                    const float dd = expf(-(float)A.kim * dr), am = -1.f - (float)A.kim * r;
+                    er *= dd;
+                    ei *= dd;
+                    const float gr = er * rinv, gi = ei * rinv;
+                    fr = (gr * am - gi * kr_) * rinv2;
+                    fi = (gr * kr_ + gi * am) * rinv2;
+                } else {
+                    const float gr = er * rinv, gi = ei * rinv;
+                    fr = (-gr - gi * kr_) * rinv2;
+                    fi = (gr * kr_ - gi) * rinv2;
+                }
+                const float gr = er * rinv, gi = ei * rinv;
                 const float dk = -(d0 * ny0 + d1 * ny1 + d2 * ny2);
                 const float dt = d0 * nx0 + d1 * nx1 + d2 * nx2;
                 const float gkr = fr * dk, gki = fi * dk, gtr = fr * dt, gti = fi * dt;
@@ -426,8 +466,15 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
                     const float cc = X.curl[a][0] * Y.curl[b][0] + X.curl[a][1] * Y.curl[b][1] + X.curl[a][2] * Y.curl[b][2];
-                    st[sbase + 3 * a + b] = make_float2(cc * sr - kf * kf * nn * vr[3 * a + b],
-                                                          cc * si - kf * kf * nn * vi[3 * a + b]);
+                    if constexpr (CK) {   // complex k^2
+                        const float k2r = (float)(A.k * A.k - A.kim * A.kim), k2i = (float)(2.0 * A.k * A.kim);
+                        const float v_r = vr[3 * a + b], v_i = vi[3 * a + b];
+                        st[sbase + 3 * a + b] = make_float2(cc * sr - nn * (k2r * v_r - k2i * v_i),
+                                                              cc * si - nn * (k2r * v_i + k2i * v_r));
+                    } else {
+                        st[sbase + 3 * a + b] = make_float2(cc * sr - kf * kf * nn * vr[3 * a + b],
+                                                              cc * si - kf * kf * nn * vi[3 * a + b]);
+                    }
                 }
         } else {
 #pragma unroll
@@ -532,9 +579,10 @@ __device__ inline void ss_map(int kind, int reg, double xi, double e1, double e2
     }
 }
 
+template <bool CK>
 __global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__restrict__ geo,
                                                              const SingPair *__restrict__ pairs, int npairs, int ng,
-                                                             GLTab gl, double k, double2 *__restrict__ out)
+                                                             GLTab gl, double k, double kim, double2 *__restrict__ out)
 {
     const int grp = threadIdx.x >> 4, lane = threadIdx.x & 15;
     const int pid = blockIdx.x * 16 + grp;
@@ -577,9 +625,18 @@ __global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__
                     const double r = r2 * rinv, kr_ = k * r;
                     double sn, cs;
                     phase_sincos(kr_, &sn, &cs);
-                    const double gr = cs * rinv * wt, gi = sn * rinv * wt;
+                    double gr = cs * rinv * wt, gi = sn * rinv * wt;
                     const double rinv2 = rinv * rinv;
-                    const double fr = (-gr - gi * kr_) * rinv2, fi = (gr * kr_ - gi) * rinv2;
+                    double fr, fi;
+                    if constexpr (CK) {
+                        const double dmp = exp(-kim * r), am = -1.0 - kim * r;
+                        gr *= dmp; gi *= dmp;
+                        fr = (gr * am - gi * kr_) * rinv2;
+                        fi = (gr * kr_ + gi * am) * rinv2;
+                    } else {
+                        fr = (-gr - gi * kr_) * rinv2;
+                        fi = (gr * kr_ - gi) * rinv2;
+                    }
                     const double dk = -(d[0] * ny[0] + d[1] * ny[1] + d[2] * ny[2]);
                     const double dt = d[0] * nx[0] + d[1] * nx[1] + d[2] * nx[2];
                     const double phx[3] = {1.0 - xs0, xs0 - xs1, xs1}, phy[3] = {1.0 - ys0, ys0 - ys1, ys1};
@@ -621,7 +678,13 @@ __global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__
             o[e] = make_double2(Vr, Vi);
             o[9 + e] = make_double2(kr[re] * scale, ki[re] * scale);
             o[18 + e] = make_double2(tr[re] * scale, ti[re] * scale);
-            o[27 + e] = make_double2(cc * sr * scale - k * k * nn * Vr, cc * si * scale - k * k * nn * Vi);
+            if constexpr (CK) {
+                const double k2r = k * k - kim * kim, k2i = 2.0 * k * kim;
+                o[27 + e] = make_double2(cc * sr * scale - nn * (k2r * Vr - k2i * Vi),
+                                         cc * si * scale - nn * (k2r * Vi + k2i * Vr));
+            } else {
+                o[27 + e] = make_double2(cc * sr * scale - k * k * nn * Vr, cc * si * scale - k * k * nn * Vi);
+            }
         }
 }
 
@@ -667,7 +730,7 @@ size_t tile_scratch_bytes(const bem_mesh *m, size_t entry_bytes)
     return (size_t)(nb * (nb + 1) / 2) * 4 * SMAX * SMAX * entry_bytes;
 }
 
-bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch, void *ops[4], hipStream_t st)
+bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, void *scratch, void *ops[4], hipStream_t st)
 {
     const int64_t nb = m->h.nb;
     const int64_t ntiles = nb * (nb + 1) / 2;
@@ -682,11 +745,15 @@ bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch,
         A.slot_ent = m->d.slot_ent.as<uint8_t>();
         A.nb = (int32_t)nb;
         A.k = k;
+        A.kim = kim;
         A.scratch = static_cast<double2 *>(scratch);
         for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
             const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
             KTimer kt(m->ctx, K_REGULAR);
-            launch_k(kt, regular_tiles_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+            if (kim != 0.0)
+                launch_k(kt, regular_tiles_kernel<true>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+            else
+                launch_k(kt, regular_tiles_kernel<false>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
             BEM_HIP(hipGetLastError());
         }
     } else {
@@ -699,11 +766,15 @@ bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch,
         A.slot_ent = m->d.slot_ent.as<uint8_t>();
         A.nb = (int32_t)nb;
         A.k = k;
+        A.kim = kim;
         A.scratch = static_cast<float2 *>(scratch);
         for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
             const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
             KTimer kt(m->ctx, K_REGULAR);
-            launch_k(kt, regular_tiles_f32_kernel, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+            if (kim != 0.0)
+                launch_k(kt, regular_tiles_f32_kernel<true>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+            else
+                launch_k(kt, regular_tiles_f32_kernel<false>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
             BEM_HIP(hipGetLastError());
         }
     }
@@ -723,7 +794,7 @@ bem_status launch_regular(const bem_mesh *m, double k, bool fp32, void *scratch,
     return BEM_OK;
 }
 
-bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *glx, const double *glw, bool fp32,
+bem_status launch_singular(const bem_mesh *m, double k, double kim, int ng, const double *glx, const double *glw, bool fp32,
                            double2 *contrib, void *ops[4], hipStream_t st)
 {
     GLTab gl;
@@ -731,8 +802,12 @@ bem_status launch_singular(const bem_mesh *m, double k, int ng, const double *gl
     const int np = (int)m->h.sing.size();
     if (np > 0) {
         KTimer kt(m->ctx, K_SINGULAR);
-        launch_k(kt, singular_pairs_kernel, dim3((np + 15) / 16), dim3(256), 0, st, m->d.geo.as<TriGeo>(),
-                 m->d.sing.as<SingPair>(), np, ng, gl, k, contrib);
+        if (kim != 0.0)
+            launch_k(kt, singular_pairs_kernel<true>, dim3((np + 15) / 16), dim3(256), 0, st, m->d.geo.as<TriGeo>(),
+                     m->d.sing.as<SingPair>(), np, ng, gl, k, kim, contrib);
+        else
+            launch_k(kt, singular_pairs_kernel<false>, dim3((np + 15) / 16), dim3(256), 0, st, m->d.geo.as<TriGeo>(),
+                     m->d.sing.as<SingPair>(), np, ng, gl, k, kim, contrib);
         BEM_HIP(hipGetLastError());
     }
     const int nn = (int)m->h.near_i.size();

@@ -94,8 +94,10 @@ __global__ __launch_bounds__(256) void field_density_kernel(int nt, const TriGeo
 // part[chunk][i] = sum over the chunk's triangles and quadrature points of
 // G psi - dG/dn phi at point i, times 4 pi (the factor is applied once in
 // the combine).
+// CK: complex wavenumber k + i kim (absorbing medium), G = exp(i k r - kim r) / (4 pi r).
+template <bool CK>
 __global__ __launch_bounds__(FLD_PB) void field_partial_kernel(int np, const double *__restrict__ pts, int nt, int tpc,
-                                                               const FieldTri *__restrict__ ft, double k,
+                                                               const FieldTri *__restrict__ ft, double k, double kim,
                                                                double2 *__restrict__ part)
 {
     __shared__ FieldTri sh[FLD_TS];
@@ -126,9 +128,18 @@ __global__ __launch_bounds__(FLD_PB) void field_partial_kernel(int np, const dou
                     const double kr = k * (r2 * rinv);
                     double sn, cs;
                     phase_sincos(kr, &sn, &cs);
-                    const double gr = cs * rinv, gi = sn * rinv;                     // exp(ikr) / r
+                    double gr = cs * rinv, gi = sn * rinv;                           // exp(ikr) / r
                     const double s = (d0 * f.n[0] + d1 * f.n[1] + d2 * f.n[2]) * rinv * rinv;
-                    const double fr = (-gr - gi * kr) * s, fi = (gr * kr - gi) * s;  // exp(ikr)(ikr - 1)(y-x).n / r^3
+                    double fr, fi;                                                   // exp(ikr)(ikr - 1)(y-x).n / r^3
+                    if constexpr (CK) {
+                        const double r = r2 * rinv, dmp = exp(-kim * r), am = -1.0 - kim * r;
+                        gr *= dmp; gi *= dmp;
+                        fr = (gr * am - gi * kr) * s;
+                        fi = (gr * kr + gi * am) * s;
+                    } else {
+                        fr = (-gr - gi * kr) * s;
+                        fi = (gr * kr - gi) * s;
+                    }
                     const double2 ps = f.psi[q], ph = f.phi[q];
                     ar += gr * ps.x - gi * ps.y - (fr * ph.x - fi * ph.y);
                     ai += gr * ps.y + gi * ps.x - (fr * ph.y + fi * ph.x);
@@ -243,7 +254,7 @@ bem_status launch_field_region(bem_problem *p, int region, int np, const double 
     if (np == 0) return BEM_OK;
     const bem_mesh *m = region == 0 ? p->ext : p->inte;
     const int nt = (int)m->h.nt, ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
-    const double k = region == 0 ? p->k_ext : p->k_int;
+    const double k = region == 0 ? p->k_ext : p->k_int, kim = region == 0 ? 0.0 : p->k_int_im;
     const double2 *phi = region == 0 ? x_int : x_int + 2 * ne;
     const double2 *psi = region == 0 ? x_int + ne : x_int + 2 * ne + ni;
     bem_status s = dev_alloc(p->ctx, dens, (size_t)nt * sizeof(FieldTri));
@@ -257,8 +268,12 @@ bem_status launch_field_region(bem_problem *p, int region, int np, const double 
     BEM_HIP(hipGetLastError());
     {
         KTimer kt(p->ctx, K_FIELD);
-        launch_k(kt, field_partial_kernel, dim3((np + FLD_PB - 1) / FLD_PB, nchunk), dim3(FLD_PB), 0, st, np, pts, nt,
-                 tpc, dens.as<FieldTri>(), k, part.as<double2>());
+        if (kim != 0.0)
+            launch_k(kt, field_partial_kernel<true>, dim3((np + FLD_PB - 1) / FLD_PB, nchunk), dim3(FLD_PB), 0, st, np,
+                     pts, nt, tpc, dens.as<FieldTri>(), k, kim, part.as<double2>());
+        else
+            launch_k(kt, field_partial_kernel<false>, dim3((np + FLD_PB - 1) / FLD_PB, nchunk), dim3(FLD_PB), 0, st, np,
+                     pts, nt, tpc, dens.as<FieldTri>(), k, kim, part.as<double2>());
         BEM_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(field_combine_kernel, dim3((np + 255) / 256), dim3(256), 0, st, np, nchunk,

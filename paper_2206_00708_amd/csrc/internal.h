@@ -267,6 +267,7 @@ struct bem_problem {
     bem_ctx *ctx = nullptr;
     const bem_mesh *ext = nullptr, *inte = nullptr;
     double k_ext = 0, k_int = 0, rho_ext = 1, rho_int = 1;
+    double k_int_im = 0;   // imaginary part of the interior wavenumber (absorbing interior)
     int incident = 0;   // 0: plane waves (dirs are directions), 1: point sources (dirs are positions)
     bem_precision prec = BEM_C128;
     int ng = 4;
