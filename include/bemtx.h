@@ -133,7 +133,8 @@ bem_status bem_ctx_trim(bem_ctx *ctx);
  * rotation, residual estimate), 9 "mass_inverse", 10 "block_gemm"
  * (multi-RHS operator product), 11 "mass_gemm" (multi-RHS inverse-mass
  * product), 12 "krylov_normalize" (new Krylov vector scaled to unit norm),
- * 13 "field" (field off the surface, bem_field).  Every launch of a kernel whose bit is set in
+ * 13 "field" (field off the surface, bem_field), 14 "mortar" (the two passes
+ * of the device mortar geometry, bem_problem_set_mortar).  Every launch of a kernel whose bit is set in
  * kernel_mask is bracketed by HIP events on the context stream (a few
  * microseconds of overhead per launch); 0 disables.  Setting the mask resets
  * the totals.  bem_ctx_kernel_time synchronises the stream and returns the
@@ -187,6 +188,23 @@ bem_status bem_assemble_operators(bem_problem *p, int32_t parts);
  * BEM_E_MESH_MISMATCH if the projected interior mesh leaves part of an
  * exterior facet uncovered (relative area defect above 1e-6). */
 bem_status bem_assemble_projection(bem_problem *p);
+
+/* Where the next bem_assemble_projection computes the geometry of the mortar
+ * matrix P_int,ext (Sec. 3.1: central projection of every candidate interior
+ * triangle onto an exterior facet, clipping of the two, and the exact
+ * integral of the product of the P1 bases over the intersection):
+ * on_device = 0 on the host threads (the default), 1 in kernels on the
+ * context's second stream, one wave per exterior facet, with the same
+ * arithmetic steps.  Either way the contributions are listed in exterior
+ * facet order and the host forms the CSR from them, so the two settings give
+ * the same matrix up to rounding (the device may contract products into
+ * fused multiply-adds).  BEM_E_ARG for another value. */
+bem_status bem_problem_set_mortar(bem_problem *p, int32_t on_device);
+
+/* Wall-clock milliseconds of the mortar step (geometry and CSR) of the last
+ * bem_assemble_projection, by the setting above.  BEM_E_STATE before the
+ * projection is assembled. */
+bem_status bem_problem_mortar_ms(const bem_problem *p, double *ms);
 
 /* Apply the discrete multiple-traces matrix of Sec. 3.3 (Eq.
  * "mtf:discrete") to x: y = A x (strong = 0) or y = blockdiag(M_e, M_e, M_i,

@@ -56,6 +56,8 @@ SIGNATURES = {
     "bem_field": (c_status, [vp, vp, i32, vp, vp, vp, i64, vp, i32]),
     "bem_problem_set_incident": (c_status, [vp, i32]),
     "bem_problem_set_k_int_imag": (c_status, [vp, f64]),
+    "bem_problem_set_mortar": (c_status, [vp, i32]),
+    "bem_problem_mortar_ms": (c_status, [vp, ctypes.POINTER(f64)]),
     "bem_solve_pmchwt": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
     "bem_pmchwt_matvec": (c_status, [vp, vp, vp, i32, i32]),
     "bem_solve_hc_neumann": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),

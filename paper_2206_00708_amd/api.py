@@ -58,7 +58,7 @@ class Context:
 
     KERNELS = ("regular_tiles", "gather_tiles", "singular_pairs", "near_scatter", "mtf_dense", "mass_apply",
                "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse", "block_gemm", "mass_gemm",
-               "krylov_normalize", "field")
+               "krylov_normalize", "field", "mortar")
 
     def set_kernel_timing(self, kernels=()):
         """Time every launch of the named kernels with HIP events (empty: off)."""
@@ -108,8 +108,11 @@ class Mesh:
         return out
 
     def close(self):
+        # a mesh outlived by its context (an unordered teardown at interpreter
+        # exit) is left alone: the context's destruction ended its device state
         if getattr(self, "_h", None):
-            N.load().bem_mesh_destroy(self._h)
+            if getattr(self.ctx, "_h", None):
+                N.load().bem_mesh_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -135,7 +138,8 @@ class Problem:
 
     def close(self):
         if getattr(self, "_h", None):
-            N.load().bem_problem_destroy(self._h)
+            if getattr(self.ctx, "_h", None):   # as for meshes: never after the context
+                N.load().bem_problem_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -187,6 +191,16 @@ class Problem:
         """bem_problem_set_incident: 0 plane waves (dirs are directions), 1 point
         sources (dirs are source positions)."""
         _check(N.load().bem_problem_set_incident(self._h, int(kind)))
+
+    def set_mortar(self, on_device):
+        """bem_problem_set_mortar: mortar geometry on the device (True) or the host."""
+        _check(N.load().bem_problem_set_mortar(self._h, int(on_device)))
+
+    def mortar_ms(self):
+        """bem_problem_mortar_ms: wall time of the last projection set-up's mortar step."""
+        v = ctypes.c_double()
+        _check(N.load().bem_problem_mortar_ms(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_k_int_imag(self, k_int_imag):
         """bem_problem_set_k_int_imag: interior wavenumber k_int + i k_int_imag

@@ -141,7 +141,7 @@ bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, v
 
 const char *const kKernelNames[K_COUNT] = {"regular_tiles", "gather_tiles", "singular_pairs", "near_scatter",
                                            "mtf_dense", "mass_apply", "cgs_dots", "cgs_update", "arnoldi_finish",
-                                           "mass_inverse", "block_gemm", "mass_gemm", "krylov_normalize", "field"};
+                                           "mass_inverse", "block_gemm", "mass_gemm", "krylov_normalize", "field", "mortar"};
 
 static hipEvent_t take_event(bem_ctx *c)
 {
@@ -530,6 +530,13 @@ bem_status bem_assemble_projection(bem_problem *p)
     if (!p->ev_proj) BEM_HIP(hipEventCreateWithFlags(&p->ev_proj, hipEventDisableTiming));
     BEM_HIP(hipStreamWaitEvent(ax, p->ev_pre_asm, 0));
     bem_status s = BEM_OK;
+    double defect = 0;
+    if (p->mortar_dev) {   // geometry on the device, on the auxiliary stream before the inverse masses
+        const auto tm = std::chrono::steady_clock::now();
+        s = mortar_csr_device(ctx, p->inte, p->ext, ax, p->P_ie, &defect);
+        if (s) return s;
+        p->t_mortar_ms = ms_since(tm);
+    }
     for (int m = 0; m < 2 && !s; ++m) {
         s = upload(ctx, p->M_ptr[m], p->M[m].ptr, ax);
         if (!s) s = upload(ctx, p->M_col[m], p->M[m].col, ax);
@@ -537,9 +544,12 @@ bem_status bem_assemble_projection(bem_problem *p)
         if (!s) s = launch_mass_inverse(p, m, ax);
     }
     if (s) return s;
-    double defect = 0;
-    s = mortar_csr(p->inte->h, p->ext->h, p->P_ie, &defect);
-    if (s) return s;
+    if (!p->mortar_dev) {
+        const auto tm = std::chrono::steady_clock::now();
+        s = mortar_csr(p->inte->h, p->ext->h, p->P_ie, &defect);
+        if (s) return s;
+        p->t_mortar_ms = ms_since(tm);
+    }
     transpose_csr(p->P_ie, p->P_ei);
     s = upload(ctx, p->P_ie_ptr, p->P_ie.ptr, ax);
     if (!s) s = upload(ctx, p->P_ie_col, p->P_ie.col, ax);
@@ -593,6 +603,22 @@ bem_status bem_problem_set_incident(bem_problem *p, int32_t kind)
     if (!p) return set_error(BEM_E_ARG, "null problem");
     if (kind != 0 && kind != 1) return set_error(BEM_E_ARG, "incident kind must be 0 (plane waves) or 1 (point sources)");
     p->incident = kind;
+    return BEM_OK;
+}
+
+bem_status bem_problem_set_mortar(bem_problem *p, int32_t on_device)
+{
+    if (!p) return set_error(BEM_E_ARG, "null problem");
+    if (on_device != 0 && on_device != 1) return set_error(BEM_E_ARG, "on_device must be 0 or 1");
+    p->mortar_dev = on_device;
+    return BEM_OK;
+}
+
+bem_status bem_problem_mortar_ms(const bem_problem *p, double *ms)
+{
+    if (!p || !ms) return set_error(BEM_E_ARG, "null argument");
+    if (!p->proj_ready) return set_error(BEM_E_STATE, "assemble the projection first");
+    *ms = p->t_mortar_ms;
     return BEM_OK;
 }
 

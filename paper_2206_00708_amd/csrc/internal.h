@@ -169,6 +169,22 @@ void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, in
 bem_status mesh_prepare(MeshData &m);                    // validation + tables (host)
 void mass_csr(const MeshData &m, Csr &M);
 bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *coverage_defect);
+// candidate search of the mortar assembly: the cones of both meshes'
+// triangles seen from the origin, and the interior triangles by cell of a
+// [-1, 1]^3 grid of cone centres (CSR, ascending within a cell)
+struct MortarGrid {
+    std::vector<double> ci, ri, ce, re;
+    int ncell = 1;
+    double h = 2.0;
+    std::vector<int32_t> cell_ptr, cell_tri;
+};
+void mortar_grid(const MeshData &mi, const MeshData &me, MortarGrid &g);
+// P_int,ext from the pair contributions in facet order: interior triangle
+// ti[k], exterior facet te[k], block blk[9 k + 3 a + b]
+bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *me, hipStream_t st, Csr &P,
+                             double *coverage_defect);
+bem_status mortar_from_contribs(const MeshData &mi, const MeshData &me, int64_t ncon, const int32_t *ti,
+                                const int32_t *te, const double *blk, double worst, Csr &P);
 void transpose_csr(const Csr &A, Csr &At);
 void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue method
 
@@ -177,7 +193,7 @@ void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue me
 namespace bemtx {
 // kernels timed by the optional per-launch HIP-event timer of a context
 enum KernelId { K_REGULAR = 0, K_GATHER, K_SINGULAR, K_NEAR, K_MTF_DENSE, K_MASS_APPLY, K_CGS_DOTS, K_CGS_UPDATE,
-                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_BLOCK_GEMM, K_MASS_GEMM, K_KRYLOV_NORM, K_FIELD, K_COUNT };
+                K_ARNOLDI_FINISH, K_MASS_INVERSE, K_BLOCK_GEMM, K_MASS_GEMM, K_KRYLOV_NORM, K_FIELD, K_MORTAR, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 }  // namespace bemtx
 
@@ -268,6 +284,8 @@ struct bem_problem {
     const bem_mesh *ext = nullptr, *inte = nullptr;
     double k_ext = 0, k_int = 0, rho_ext = 1, rho_int = 1;
     double k_int_im = 0;   // imaginary part of the interior wavenumber (absorbing interior)
+    int mortar_dev = 0;        // mortar geometry on the device (1) or the host (0)
+    double t_mortar_ms = 0;    // wall time of the mortar step of the last projection set-up
     int incident = 0;   // 0: plane waves (dirs are directions), 1: point sources (dirs are positions)
     bem_precision prec = BEM_C128;
     int ng = 4;

@@ -15,6 +15,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "mortar_geom.h"
 
 namespace bemtx {
 
@@ -104,175 +105,76 @@ void transpose_csr(const Csr &A, Csr &At)
         }
 }
 
-namespace {
-
-struct V2 { double x, y; };
-inline double orient(V2 a, V2 b, V2 c) { return (b.x - a.x) * (c.y - a.y) - (b.y - a.y) * (c.x - a.x); }
-
-// Keep the part of convex polygon `in` on the left of the directed line a->b;
-// boundary points (within tol) are kept.
-int keep_left(const V2 *in, int n, V2 a, V2 b, double tol, V2 *out)
+void mortar_grid(const MeshData &mi, const MeshData &me, MortarGrid &g)
 {
-    int m = 0;
-    for (int i = 0; i < n; ++i) {
-        V2 cur = in[i], nxt = in[(i + 1) % n];
-        double sc = orient(a, b, cur), sn = orient(a, b, nxt);
-        bool ic = sc >= -tol, inn = sn >= -tol;
-        if (ic) out[m++] = cur;
-        if (ic != inn) {
-            double s = sc / (sc - sn);
-            out[m++] = {cur.x + s * (nxt.x - cur.x), cur.y + s * (nxt.y - cur.y)};
-        }
-    }
-    return m;
-}
-
-struct Facet {
-    double o[3], e1[3], e2[3], n[3];
-    V2 v[3];
-    double area;
-};
-
-inline double dot(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
-
-Facet make_facet(const double *p0, const double *p1, const double *p2)
-{
-    Facet f;
-    double a[3], b[3];
-    for (int c = 0; c < 3; ++c) { a[c] = p1[c] - p0[c]; b[c] = p2[c] - p0[c]; f.o[c] = p0[c]; }
-    double nn[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
-    double ln = std::sqrt(dot(nn, nn)), la = std::sqrt(dot(a, a));
-    for (int c = 0; c < 3; ++c) { f.n[c] = nn[c] / ln; f.e1[c] = a[c] / la; }
-    f.e2[0] = f.n[1] * f.e1[2] - f.n[2] * f.e1[1];
-    f.e2[1] = f.n[2] * f.e1[0] - f.n[0] * f.e1[2];
-    f.e2[2] = f.n[0] * f.e1[1] - f.n[1] * f.e1[0];
-    f.area = 0.5 * ln;
-    const double *P[3] = {p0, p1, p2};
-    for (int k = 0; k < 3; ++k) {
-        double d[3] = {P[k][0] - p0[0], P[k][1] - p0[1], P[k][2] - p0[2]};
-        f.v[k] = {dot(d, f.e1), dot(d, f.e2)};
-    }
-    return f;
-}
-
-// barycentric coordinates of q in triangle (a, b, c)
-inline void bary(V2 a, V2 b, V2 c, V2 q, double *l)
-{
-    double det = orient(a, b, c);
-    l[1] = orient(a, q, c) / det;
-    l[2] = orient(a, b, q) / det;
-    l[0] = 1.0 - l[1] - l[2];
-}
-
-}  // namespace
-
-bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *coverage_defect)
-{
-    const int64_t nti = mi.nt, nte = me.nt;
-    // cone of each triangle seen from the origin: centre direction and chord radius
     auto cones = [](const MeshData &m, std::vector<double> &c, std::vector<double> &r) {
         c.assign(3 * m.nt, 0.0);
         r.assign(m.nt, 0.0);
         for (int64_t t = 0; t < m.nt; ++t) {
-            double u[3][3], s[3] = {0, 0, 0};
-            for (int a = 0; a < 3; ++a) {
-                const double *p = &m.xyz[3 * m.tri[3 * t + a]];
-                double l = std::sqrt(dot(p, p));
-                for (int k = 0; k < 3; ++k) { u[a][k] = p[k] / l; s[k] += u[a][k]; }
-            }
-            double ls = std::sqrt(dot(s, s));
-            for (int k = 0; k < 3; ++k) c[3 * t + k] = s[k] / ls;
-            for (int a = 0; a < 3; ++a) {
-                double d2 = 0;
-                for (int k = 0; k < 3; ++k) d2 += (u[a][k] - c[3 * t + k]) * (u[a][k] - c[3 * t + k]);
-                r[t] = std::max(r[t], std::sqrt(d2));
-            }
+            const int32_t *v = &m.tri[3 * t];
+            mgeo::cone(&m.xyz[3 * v[0]], &m.xyz[3 * v[1]], &m.xyz[3 * v[2]], &c[3 * t], &r[t]);
         }
     };
-    std::vector<double> ci, ri, ce, re;
-    cones(mi, ci, ri);
-    cones(me, ce, re);
-    double rmax_i = *std::max_element(ri.begin(), ri.end()), rmax_e = *std::max_element(re.begin(), re.end());
-    double cell = 1.05 * (rmax_i + rmax_e) + 1e-12;
-    int ncell = std::max(1, std::min(256, (int)std::floor(2.0 / cell)));
-    double h = 2.0 / ncell;
-    auto cidx = [&](double x) { return std::min(ncell - 1, std::max(0, (int)std::floor((x + 1.0) / h))); };
-    std::vector<std::vector<int32_t>> grid((size_t)ncell * ncell * ncell);
-    for (int64_t t = 0; t < nti; ++t)
-        grid[((size_t)cidx(ci[3 * t]) * ncell + cidx(ci[3 * t + 1])) * ncell + cidx(ci[3 * t + 2])].push_back((int32_t)t);
+    cones(mi, g.ci, g.ri);
+    cones(me, g.ce, g.re);
+    const double rmax_i = *std::max_element(g.ri.begin(), g.ri.end()), rmax_e = *std::max_element(g.re.begin(), g.re.end());
+    const double cell = 1.05 * (rmax_i + rmax_e) + 1e-12;
+    g.ncell = std::max(1, std::min(256, (int)std::floor(2.0 / cell)));
+    g.h = 2.0 / g.ncell;
+    const int64_t nc = (int64_t)g.ncell * g.ncell * g.ncell;
+    std::vector<int32_t> cid(mi.nt);
+    g.cell_ptr.assign(nc + 1, 0);
+    for (int64_t t = 0; t < mi.nt; ++t) {
+        cid[t] = (int32_t)(((int64_t)mgeo::cell_of(g.ci[3 * t], g.ncell, g.h) * g.ncell +
+                            mgeo::cell_of(g.ci[3 * t + 1], g.ncell, g.h)) * g.ncell +
+                           mgeo::cell_of(g.ci[3 * t + 2], g.ncell, g.h));
+        g.cell_ptr[cid[t] + 1]++;
+    }
+    for (int64_t c = 0; c < nc; ++c) g.cell_ptr[c + 1] += g.cell_ptr[c];
+    g.cell_tri.resize(mi.nt);
+    std::vector<int32_t> fill(g.cell_ptr.begin(), g.cell_ptr.end() - 1);
+    for (int64_t t = 0; t < mi.nt; ++t) g.cell_tri[fill[cid[t]]++] = (int32_t)t;   // ascending within a cell
+}
 
+bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *coverage_defect)
+{
+    const int64_t nte = me.nt;
+    MortarGrid g;
+    mortar_grid(mi, me, g);
     // per exterior facet: (interior triangle, 3x3 block) contributions, facets split over host threads
     // (contiguous facet chunks, so the concatenation of the chunk lists is in facet order)
-    struct Contrib { int32_t ti, te; double blk[3][3]; };
+    struct Chunk { std::vector<int32_t> ti, te; std::vector<double> blk; int overflow = 0; };
     const int64_t nchunk = std::min<int64_t>(nte, 256);
-    std::vector<std::vector<Contrib>> per_chunk(nchunk);
+    std::vector<Chunk> per_chunk(nchunk);
     std::vector<double> defect(nte, 0.0);
     auto work = [&](int64_t c0, int64_t c1) {
         for (int64_t ch = c0; ch < c1; ++ch) {
-            std::vector<Contrib> &out = per_chunk[ch];
+            Chunk &out = per_chunk[ch];
             for (int64_t te = nte * ch / nchunk; te < nte * (ch + 1) / nchunk; ++te) {
                 const int32_t *ve = &me.tri[3 * te];
-                Facet F = make_facet(&me.xyz[3 * ve[0]], &me.xyz[3 * ve[1]], &me.xyz[3 * ve[2]]);
-                double scale = std::fabs(F.v[1].x) + std::fabs(F.v[2].x) + std::fabs(F.v[2].y);
-                double tol = 1e-12 * scale * scale;
-                double plane = dot(F.n, F.o);
+                const mgeo::Facet F = mgeo::make_facet(&me.xyz[3 * ve[0]], &me.xyz[3 * ve[1]], &me.xyz[3 * ve[2]]);
                 double covered = 0.0;
-                int gx = cidx(ce[3 * te]), gy = cidx(ce[3 * te + 1]), gz = cidx(ce[3 * te + 2]);
+                const int gx = mgeo::cell_of(g.ce[3 * te], g.ncell, g.h), gy = mgeo::cell_of(g.ce[3 * te + 1], g.ncell, g.h),
+                          gz = mgeo::cell_of(g.ce[3 * te + 2], g.ncell, g.h);
                 for (int dx = -1; dx <= 1; ++dx)
                     for (int dy = -1; dy <= 1; ++dy)
                         for (int dz = -1; dz <= 1; ++dz) {
-                            int x = gx + dx, y = gy + dy, z = gz + dz;
-                            if (x < 0 || y < 0 || z < 0 || x >= ncell || y >= ncell || z >= ncell) continue;
-                            for (int32_t ti : grid[((size_t)x * ncell + y) * ncell + z]) {
-                                double d2 = 0;
-                                for (int k = 0; k < 3; ++k) d2 += (ci[3 * ti + k] - ce[3 * te + k]) * (ci[3 * ti + k] - ce[3 * te + k]);
-                                if (std::sqrt(d2) > (ri[ti] + re[te]) * 1.0001 + 1e-12) continue;
+                            const int x = gx + dx, y = gy + dy, z = gz + dz;
+                            if (x < 0 || y < 0 || z < 0 || x >= g.ncell || y >= g.ncell || z >= g.ncell) continue;
+                            const int64_t c = ((int64_t)x * g.ncell + y) * g.ncell + z;
+                            for (int32_t q = g.cell_ptr[c]; q < g.cell_ptr[c + 1]; ++q) {
+                                const int32_t ti = g.cell_tri[q];
+                                if (!mgeo::cones_meet(&g.ci[3 * ti], g.ri[ti], &g.ce[3 * te], g.re[te])) continue;
                                 const int32_t *vi = &mi.tri[3 * ti];
-                                V2 S[3];
-                                bool ok = true;
-                                for (int a = 0; a < 3; ++a) {
-                                    const double *p = &mi.xyz[3 * vi[a]];
-                                    double den = dot(F.n, p);
-                                    if (!(den > 0.0)) { ok = false; break; }
-                                    double sc = plane / den;
-                                    double q[3] = {sc * p[0] - F.o[0], sc * p[1] - F.o[1], sc * p[2] - F.o[2]};
-                                    S[a] = {dot(q, F.e1), dot(q, F.e2)};
-                                }
-                                if (!ok || orient(S[0], S[1], S[2]) <= 0.0) continue;
-                                // exterior facet clipped by the three edges of the projected interior triangle
-                                V2 poly[12], tmp[12];
-                                int n = 3;
-                                for (int a = 0; a < 3; ++a) poly[a] = F.v[a];
-                                for (int a = 0; a < 3 && n >= 3; ++a) {
-                                    n = keep_left(poly, n, S[a], S[(a + 1) % 3], tol, tmp);
-                                    std::memcpy(poly, tmp, n * sizeof(V2));
-                                }
-                                if (n < 3) continue;
-                                double apoly = 0.0;
-                                for (int k = 1; k + 1 < n; ++k) apoly += 0.5 * orient(poly[0], poly[k], poly[k + 1]);
-                                if (apoly < 1e-14 * F.area) continue;
-                                covered += apoly;
-                                Contrib c;
-                                c.ti = ti;
-                                c.te = (int32_t)te;
-                                std::memset(c.blk, 0, sizeof c.blk);
-                                for (int k = 1; k + 1 < n; ++k) {
-                                    V2 A = poly[0], B = poly[k], C = poly[k + 1];
-                                    double at = 0.5 * orient(A, B, C);
-                                    // 3-point interior rule, exact for quadratics
-                                    const double w1 = 2.0 / 3.0, w2 = 1.0 / 6.0;
-                                    const double L[3][3] = {{w1, w2, w2}, {w2, w1, w2}, {w2, w2, w1}};
-                                    for (int g = 0; g < 3; ++g) {
-                                        V2 q = {L[g][0] * A.x + L[g][1] * B.x + L[g][2] * C.x,
-                                                L[g][0] * A.y + L[g][1] * B.y + L[g][2] * C.y};
-                                        double li[3], le[3];
-                                        bary(S[0], S[1], S[2], q, li);
-                                        bary(F.v[0], F.v[1], F.v[2], q, le);
-                                        for (int a = 0; a < 3; ++a)
-                                            for (int b = 0; b < 3; ++b) c.blk[a][b] += at / 3.0 * li[a] * le[b];
-                                    }
-                                }
-                                out.push_back(c);
+                                double blk[3][3], ap = 0.0;
+                                const int r = mgeo::pair_block(F, &mi.xyz[3 * vi[0]], &mi.xyz[3 * vi[1]], &mi.xyz[3 * vi[2]], blk, &ap);
+                                if (r < 0) out.overflow = 1;
+                                if (r <= 0) continue;
+                                covered += ap;
+                                out.ti.push_back(ti);
+                                out.te.push_back((int32_t)te);
+                                for (int a = 0; a < 3; ++a)
+                                    for (int b = 0; b < 3; ++b) out.blk.push_back(blk[a][b]);
                             }
                         }
                 defect[te] = std::fabs(covered - F.area) / F.area;
@@ -283,20 +185,31 @@ bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *co
     double worst = 0.0;
     for (double d : defect) worst = std::max(worst, d);
     if (coverage_defect) *coverage_defect = worst;
+    std::vector<int32_t> ti, te;
+    std::vector<double> blk;
+    for (const Chunk &c : per_chunk) {
+        if (c.overflow) return set_error(BEM_E_MESH, "degenerate facet intersection in the mortar projection");
+        ti.insert(ti.end(), c.ti.begin(), c.ti.end());
+        te.insert(te.end(), c.te.begin(), c.te.end());
+        blk.insert(blk.end(), c.blk.begin(), c.blk.end());
+    }
+    return mortar_from_contribs(mi, me, (int64_t)ti.size(), ti.data(), te.data(), blk.data(), worst, P);
+}
+
+bem_status mortar_from_contribs(const MeshData &mi, const MeshData &me, int64_t ncon, const int32_t *cti,
+                                const int32_t *cte, const double *cblk, double worst, Csr &P)
+{
+    const int64_t nti = mi.nt;
     // entries grouped by interior row, each row in facet order, then CSR.
     // Contributions are numbered in facet order and listed per interior
     // triangle; a row gathers the lists of the triangles around its vertex and
     // sorts them by that number, so rows fill independently.
-    std::vector<const Contrib *> all;
-    for (const auto &chunk : per_chunk)
-        for (const Contrib &c : chunk) all.push_back(&c);
-    const int64_t ncon = (int64_t)all.size();
     std::vector<int32_t> tptr(nti + 1, 0), tcon(ncon);
-    for (const Contrib *c : all) tptr[c->ti + 1]++;
+    for (int64_t k = 0; k < ncon; ++k) tptr[cti[k] + 1]++;
     for (int64_t t = 0; t < nti; ++t) tptr[t + 1] += tptr[t];
     {
         std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
-        for (int64_t k = 0; k < ncon; ++k) tcon[fill[all[k]->ti]++] = (int32_t)k;
+        for (int64_t k = 0; k < ncon; ++k) tcon[fill[cti[k]]++] = (int32_t)k;
     }
     // triangles around each interior vertex
     std::vector<int32_t> vptr(mi.nv + 1, 0), vtri(3 * nti);
@@ -324,9 +237,9 @@ bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *co
             std::sort(ks.begin(), ks.end());
             int32_t w = cnt[i];
             for (int32_t k : ks) {
-                const Contrib &c = *all[k];
-                const int a = mi.tri[3 * c.ti] == i ? 0 : mi.tri[3 * c.ti + 1] == i ? 1 : 2;
-                for (int b = 0; b < 3; ++b) ent[w++] = {me.tri[3 * c.te + b], c.blk[a][b]};
+                const int32_t t = cti[k];
+                const int a = mi.tri[3 * t] == i ? 0 : mi.tri[3 * t + 1] == i ? 1 : 2;
+                for (int b = 0; b < 3; ++b) ent[w++] = {me.tri[3 * cte[k] + b], cblk[9 * (int64_t)k + 3 * a + b]};
             }
         }
     });
