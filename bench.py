@@ -358,6 +358,47 @@ def pmchwt_run(ctx, B, synth, np, reps=3):
     return res
 
 
+def mortar_run(ctx, B, synth, np):
+    """The mortar step of the projection set-up (Sec. 3.1) with its geometry
+    on the host threads and on the device, at C3 (ellipsoid ico5 / Fibonacci
+    8002) and on a sphere pair with a denser interior grid (ico5, 10242 nodes /
+    Fibonacci 16000; the dense inverse masses take at most 16384 nodes):
+    wall time of the step (geometry and CSR), the device kernels' time, and
+    whether the two give the same matrix."""
+    import torch
+    cases = [("C3", synth.make_config("C3")),
+             ("sphere ico5 / Fibonacci 16000", None)]
+    res = {}
+    for name, c in cases:
+        if c is None:
+            ext, inte, _ = synth.configs.make_pair(13, 5, "fib", 0.01, (1.0, 1.0, 1.0), int_n=16000)
+            c = {"ext": ext, "int": inte, "k_ext": 5.0, "k_int": 8.0}
+        me, mi = B.Mesh(ctx, *c["ext"]), B.Mesh(ctx, *c["int"])
+        out = {"n_ext": len(c["ext"][0]), "n_int": len(c["int"][0])}
+        P = {}
+        for on in (False, True, False, True):   # each setting twice; the second run is reported
+            p = B.Problem(ctx, me, mi, c["k_ext"], c["k_int"], 1.0, 1.5)
+            p.set_mortar(on)
+            if on:
+                ctx.set_kernel_timing(("mortar",))
+            p.assemble_projection()
+            key = "device" if on else "host"
+            out[key + "_ms"] = round(p.mortar_ms(), 3)
+            if on:
+                out["device_kernel_ms"] = round(ctx.kernel_time("mortar")[0], 3)
+                ctx.set_kernel_timing(())
+            P[key] = p.projection()
+            del p
+            torch.cuda.synchronize()
+        (rh, ch, vh), (rd, cd, vd) = P["host"], P["device"]
+        out["nnz"] = int(len(vh))
+        out["same_sparsity"] = bool(np.array_equal(rh, rd) and np.array_equal(ch, cd))
+        out["max_rel_value_diff"] = float(np.abs(vh - vd).max() / np.abs(vh).max()) if out["same_sparsity"] else None
+        out["speedup"] = round(out["host_ms"] / out["device_ms"], 2)
+        res[name] = out
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +410,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--no-field", action="store_true", help="skip the field evaluation")
     ap.add_argument("--no-pmchwt", action="store_true", help="skip the comparison of the exterior formulations")
+    ap.add_argument("--no-mortar", action="store_true", help="skip the host vs device mortar comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
                          "HBM byte counters) and exit")
@@ -493,6 +535,8 @@ def main():
         line["field"] = field_run(ctx, B, synth, np)
     if not args.no_pmchwt:
         line["pmchwt"] = pmchwt_run(ctx, B, synth, np)
+    if not args.no_mortar:
+        line["mortar"] = mortar_run(ctx, B, synth, np)
     if not args.no_serving:
         ctx.trim()   # the serving workers size their budget from free HBM: return this context's blocks first
         torch.cuda.empty_cache()

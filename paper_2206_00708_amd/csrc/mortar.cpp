@@ -23,8 +23,8 @@ namespace bemtx {
 // row i in generation order.  Duplicate columns are summed in that order
 // (first occurrence first), then the distinct columns of a row are sorted.
 // Rows are independent and split over the host workers.
-static void rows_to_csr(int64_t nrows, int64_t ncols, const std::vector<int32_t> &ptr,
-                        std::vector<std::pair<int32_t, double>> &ent, Csr &A)
+template <class PtrVec, class EntVec>
+static void rows_to_csr(int64_t nrows, int64_t ncols, const PtrVec &ptr, EntVec &ent, Csr &A)
 {
     std::vector<int32_t> ucnt(nrows, 0);
     parallel_for(nrows, 64, [&](int64_t r0, int64_t r1) {
@@ -185,15 +185,24 @@ bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *co
     double worst = 0.0;
     for (double d : defect) worst = std::max(worst, d);
     if (coverage_defect) *coverage_defect = worst;
-    std::vector<int32_t> ti, te;
-    std::vector<double> blk;
-    for (const Chunk &c : per_chunk) {
-        if (c.overflow) return set_error(BEM_E_MESH, "degenerate facet intersection in the mortar projection");
-        ti.insert(ti.end(), c.ti.begin(), c.ti.end());
-        te.insert(te.end(), c.te.begin(), c.te.end());
-        blk.insert(blk.end(), c.blk.begin(), c.blk.end());
+    // one array in facet order: chunk offsets, then the chunks copied in parallel
+    std::vector<int64_t> coff(nchunk + 1, 0);
+    for (int64_t ch = 0; ch < nchunk; ++ch) {
+        if (per_chunk[ch].overflow) return set_error(BEM_E_MESH, "degenerate facet intersection in the mortar projection");
+        coff[ch + 1] = coff[ch] + (int64_t)per_chunk[ch].ti.size();
     }
-    return mortar_from_contribs(mi, me, (int64_t)ti.size(), ti.data(), te.data(), blk.data(), worst, P);
+    const int64_t ncon = coff[nchunk];
+    HVec<int32_t> ti(ncon), te(ncon);
+    HVec<double> blk(9 * ncon);
+    parallel_for(nchunk, 1, [&](int64_t c0, int64_t c1) {
+        for (int64_t ch = c0; ch < c1; ++ch) {
+            const Chunk &c = per_chunk[ch];
+            std::copy(c.ti.begin(), c.ti.end(), ti.begin() + coff[ch]);
+            std::copy(c.te.begin(), c.te.end(), te.begin() + coff[ch]);
+            std::copy(c.blk.begin(), c.blk.end(), blk.begin() + 9 * coff[ch]);
+        }
+    });
+    return mortar_from_contribs(mi, me, ncon, ti.data(), te.data(), blk.data(), worst, P);
 }
 
 bem_status mortar_from_contribs(const MeshData &mi, const MeshData &me, int64_t ncon, const int32_t *cti,
@@ -204,7 +213,7 @@ bem_status mortar_from_contribs(const MeshData &mi, const MeshData &me, int64_t 
     // Contributions are numbered in facet order and listed per interior
     // triangle; a row gathers the lists of the triangles around its vertex and
     // sorts them by that number, so rows fill independently.
-    std::vector<int32_t> tptr(nti + 1, 0), tcon(ncon);
+    HVec<int32_t> tptr(nti + 1, 0), tcon(ncon);
     for (int64_t k = 0; k < ncon; ++k) tptr[cti[k] + 1]++;
     for (int64_t t = 0; t < nti; ++t) tptr[t + 1] += tptr[t];
     {
@@ -212,7 +221,7 @@ bem_status mortar_from_contribs(const MeshData &mi, const MeshData &me, int64_t 
         for (int64_t k = 0; k < ncon; ++k) tcon[fill[cti[k]]++] = (int32_t)k;
     }
     // triangles around each interior vertex
-    std::vector<int32_t> vptr(mi.nv + 1, 0), vtri(3 * nti);
+    HVec<int32_t> vptr(mi.nv + 1, 0), vtri(3 * nti);
     for (int64_t t = 0; t < nti; ++t)
         for (int a = 0; a < 3; ++a) vptr[mi.tri[3 * t + a] + 1]++;
     for (int64_t i = 0; i < mi.nv; ++i) vptr[i + 1] += vptr[i];
@@ -221,13 +230,13 @@ bem_status mortar_from_contribs(const MeshData &mi, const MeshData &me, int64_t 
         for (int64_t t = 0; t < nti; ++t)
             for (int a = 0; a < 3; ++a) vtri[fill[mi.tri[3 * t + a]]++] = (int32_t)t;
     }
-    std::vector<int32_t> cnt(mi.nv + 1, 0);
+    HVec<int32_t> cnt(mi.nv + 1, 0);
     for (int64_t i = 0; i < mi.nv; ++i) {
         int32_t n = 0;
         for (int32_t q = vptr[i]; q < vptr[i + 1]; ++q) n += tptr[vtri[q] + 1] - tptr[vtri[q]];
         cnt[i + 1] = cnt[i] + 3 * n;
     }
-    std::vector<std::pair<int32_t, double>> ent(cnt[mi.nv]);
+    HVec<std::pair<int32_t, double>> ent(cnt[mi.nv]);
     parallel_for(mi.nv, 64, [&](int64_t r0, int64_t r1) {
         std::vector<int32_t> ks;
         for (int64_t i = r0; i < r1; ++i) {

@@ -179,8 +179,8 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     for (int t = 0; t < nte; ++t) off[t + 1] = off[t] + cnt[t];
     const int64_t ncon = off[nte];
     if (ncon > INT32_MAX) return set_error(BEM_E_UNSUPPORTED, "too many mortar contributions");
-    std::vector<int32_t> ti(ncon), te(ncon);
-    std::vector<double> blk(9 * ncon);
+    HVec<int32_t> ti(ncon), te(ncon);
+    HVec<double> blk(9 * ncon);
     if (ncon > 0) {
         s = upload_vec(ctx, d_off, off, st);
         if (!s) s = dev_alloc(ctx, d_ti, (size_t)ncon * sizeof(int32_t));
