@@ -1,10 +1,11 @@
-// The L2 mortar matrix P_int,ext (Sec. 3.1) with its geometry on the device:
-// the central projection, clipping and quadrature of every candidate
-// (exterior facet, interior triangle) pair run in kernels, with the steps of
-// the host assembly (mortar_geom.h), and the contributions come back in the
-// host's facet order, so the CSR the host then forms from them (integer
-// grouping and per-row sums, O(contributions)) is the host assembly's up to
-// rounding.
+// The L2 mortar matrix P_int,ext (Sec. 3.1) on the device: the central
+// projection, clipping and quadrature of every candidate (exterior facet,
+// interior triangle) pair run in kernels with the steps of the host assembly
+// (mortar_geom.h), the contributions are numbered in the host's facet order,
+// and the CSR rows are formed in a kernel with the host grouping's steps and
+// summation order, so the matrix is the host assembly's up to the rounding of
+// the pair integrals.  The host keeps the candidate grid and the listing of
+// the contributions per interior triangle (integer work, O(n)).
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -114,9 +115,97 @@ __global__ __launch_bounds__(256) void mortar_facet_kernel(MortarDevArgs A, int3
     }
 }
 
-template <class T>
-bem_status upload_vec(bem_ctx *ctx, DevMem &m, const std::vector<T> &v, hipStream_t st)
+constexpr int kRowStar = 16;   // triangles around a vertex held by the row kernel
+constexpr int kRowCols = 64;   // distinct columns of a row held by the row kernel
+
+// One thread per interior vertex i, a row of P_int,ext, with the steps of the
+// host grouping: the contributions of the triangles around i, merged in
+// contribution order (each triangle's list is ascending), give 3 entries each
+// (the facet's vertices b, the block's row of i's corner a); duplicate columns
+// are summed in that order, then the distinct columns are sorted.  Pass 0
+// counts the columns, pass 1 writes them at rowptr[i].  A row beyond the
+// local buffers sets *flag = 1 (the host then groups the matrix itself); a
+// pass 1 that disagrees with pass 0 sets 2 and writes nothing past its row.
+template <bool WRITE>
+__global__ __launch_bounds__(256) void mortar_rows_kernel(int nv, const int32_t *__restrict__ star_ptr,
+                                                          const int32_t *__restrict__ star_ent,
+                                                          const int32_t *__restrict__ tptr, const int32_t *__restrict__ tcon,
+                                                          const int32_t *__restrict__ con_te,
+                                                          const int32_t *__restrict__ tri_e,
+                                                          const double *__restrict__ con_blk, int32_t *__restrict__ count,
+                                                          const int64_t *__restrict__ rowptr, int32_t *__restrict__ col,
+                                                          double *__restrict__ val, int32_t *__restrict__ flag)
 {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nv) return;
+    const int s0 = star_ptr[i], ns = star_ptr[i + 1] - s0;
+    if (ns > kRowStar) {
+        flag[0] = 1;
+        return;
+    }
+    int cur[kRowStar], end[kRowStar], cor[kRowStar];
+    for (int q = 0; q < ns; ++q) {
+        const int e = star_ent[s0 + q], t = e / 3;
+        cor[q] = e - 3 * t;
+        cur[q] = tptr[t];
+        end[q] = tptr[t + 1];
+    }
+    int cols[kRowCols];
+    double vals[kRowCols];
+    int m = 0;
+    for (;;) {
+        int best = -1, bk = 0x7fffffff;
+        for (int q = 0; q < ns; ++q)
+            if (cur[q] < end[q]) {
+                const int k = tcon[cur[q]];
+                if (k < bk) { bk = k; best = q; }
+            }
+        if (best < 0) break;
+        ++cur[best];
+        const int te = con_te[bk], a = cor[best];
+        for (int b = 0; b < 3; ++b) {
+            const int c = tri_e[3 * te + b];
+            const double v = con_blk[9 * (int64_t)bk + 3 * a + b];
+            int p = -1;
+            for (int r = 0; r < m; ++r)
+                if (cols[r] == c) { p = r; break; }
+            if (p >= 0) {
+                vals[p] += v;
+            } else {
+                if (m >= kRowCols) {
+                    flag[0] = 1;
+                    return;
+                }
+                cols[m] = c;
+                vals[m] = v;
+                ++m;
+            }
+        }
+    }
+    for (int r = 1; r < m; ++r) {   // distinct columns, ascending
+        const int c = cols[r];
+        const double v = vals[r];
+        int q = r - 1;
+        while (q >= 0 && cols[q] > c) { cols[q + 1] = cols[q]; vals[q + 1] = vals[q]; --q; }
+        cols[q + 1] = c;
+        vals[q + 1] = v;
+    }
+    if (!WRITE) {
+        count[i] = m;
+        return;
+    }
+    const int64_t o = rowptr[i];
+    if (rowptr[i + 1] - o != m) {
+        flag[0] = 2;
+        return;
+    }
+    for (int r = 0; r < m; ++r) { col[o + r] = cols[r]; val[o + r] = vals[r]; }
+}
+
+template <class V>
+bem_status upload_vec(bem_ctx *ctx, DevMem &m, const V &v, hipStream_t st)
+{
+    using T = typename V::value_type;
     bem_status s = dev_alloc(ctx, m, std::max<size_t>(1, v.size()) * sizeof(T));
     if (s) return s;
     if (!v.empty()) BEM_HIP(hipMemcpyAsync(m.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
@@ -180,7 +269,6 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     const int64_t ncon = off[nte];
     if (ncon > INT32_MAX) return set_error(BEM_E_UNSUPPORTED, "too many mortar contributions");
     HVec<int32_t> ti(ncon), te(ncon);
-    HVec<double> blk(9 * ncon);
     if (ncon > 0) {
         s = upload_vec(ctx, d_off, off, st);
         if (!s) s = dev_alloc(ctx, d_ti, (size_t)ncon * sizeof(int32_t));
@@ -193,7 +281,6 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
             BEM_HIP(hipGetLastError());
         }
         BEM_HIP(hipMemcpyAsync(ti.data(), d_ti.ptr, (size_t)ncon * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        BEM_HIP(hipMemcpyAsync(blk.data(), d_blk.ptr, (size_t)ncon * 9 * sizeof(double), hipMemcpyDeviceToHost, st));
         BEM_HIP(hipMemcpyAsync(&ovf, d_ovf.ptr, sizeof ovf, hipMemcpyDeviceToHost, st));
         BEM_HIP(hipStreamSynchronize(st));
         if (ovf) return set_error(BEM_E_DEVICE, "mortar passes disagree on the contributions");
@@ -203,7 +290,77 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     double worst = 0.0;
     for (double d : def) worst = std::max(worst, d);
     if (coverage_defect) *coverage_defect = worst;
-    return mortar_from_contribs(mi->h, me->h, ncon, ti.data(), te.data(), blk.data(), worst, P);
+    if (worst > 1e-6)
+        return set_error(BEM_E_MESH_MISMATCH, "projected interior mesh leaves an exterior facet uncovered (relative defect " +
+                                                  std::to_string(worst) + ")");
+    // rows on the device: the contributions listed per interior triangle (a
+    // counting sort on the host, O(contributions)), then the row kernel
+    const int64_t nti = mi->h.nt, nvi = mi->h.nv;
+    HVec<int32_t> tptr(nti + 1, 0), tcon(std::max<int64_t>(1, ncon));
+    for (int64_t k = 0; k < ncon; ++k) tptr[ti[k] + 1]++;
+    for (int64_t t = 0; t < nti; ++t) tptr[t + 1] += tptr[t];
+    {
+        std::vector<int32_t> fill(tptr.begin(), tptr.end() - 1);
+        for (int64_t k = 0; k < ncon; ++k) tcon[fill[ti[k]]++] = (int32_t)k;
+    }
+    DevMem d_te, d_tptr, d_tcon, d_rcnt, d_rptr, d_col, d_val;
+    s = upload_vec(ctx, d_te, te, st);
+    if (!s) s = upload_vec(ctx, d_tptr, tptr, st);
+    if (!s) s = upload_vec(ctx, d_tcon, tcon, st);
+    if (!s) s = dev_alloc(ctx, d_rcnt, (size_t)nvi * sizeof(int32_t));
+    if (s) return s;
+    const double *blk_dev = ncon > 0 ? d_blk.as<double>() : nullptr;
+    const dim3 rgrid((unsigned)((nvi + 255) / 256));
+    {
+        KTimer kt(ctx, K_MORTAR);
+        launch_k(kt, mortar_rows_kernel<false>, rgrid, dim3(256), 0, st, (int)nvi, mi->d.star_ptr.as<int32_t>(),
+                 mi->d.star_ent.as<int32_t>(), d_tptr.as<int32_t>(), d_tcon.as<int32_t>(), d_te.as<int32_t>(),
+                 me->d.tri.as<int32_t>(), blk_dev, d_rcnt.as<int32_t>(), (const int64_t *)nullptr, (int32_t *)nullptr,
+                 (double *)nullptr, d_ovf.as<int32_t>());
+        BEM_HIP(hipGetLastError());
+    }
+    std::vector<int32_t> rcnt(nvi);
+    BEM_HIP(hipMemcpyAsync(rcnt.data(), d_rcnt.ptr, (size_t)nvi * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipMemcpyAsync(&ovf, d_ovf.ptr, sizeof ovf, hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
+    if (ovf) {   // a row beyond the kernel's buffers: the host groups the contributions
+        HVec<double> blk(9 * ncon);
+        if (ncon > 0) {
+            BEM_HIP(hipMemcpyAsync(blk.data(), d_blk.ptr, (size_t)ncon * 9 * sizeof(double), hipMemcpyDeviceToHost, st));
+            BEM_HIP(hipStreamSynchronize(st));
+        }
+        return mortar_from_contribs(mi->h, me->h, ncon, ti.data(), te.data(), blk.data(), worst, P);
+    }
+    std::vector<int64_t> rptr(nvi + 1, 0);
+    for (int64_t r = 0; r < nvi; ++r) rptr[r + 1] = rptr[r] + rcnt[r];
+    const int64_t nnz = rptr[nvi];
+    if (nnz > INT32_MAX) return set_error(BEM_E_UNSUPPORTED, "too many mortar nonzeros");
+    s = upload_vec(ctx, d_rptr, rptr, st);
+    if (!s) s = dev_alloc(ctx, d_col, std::max<int64_t>(1, nnz) * sizeof(int32_t));
+    if (!s) s = dev_alloc(ctx, d_val, std::max<int64_t>(1, nnz) * sizeof(double));
+    if (s) return s;
+    {
+        KTimer kt(ctx, K_MORTAR);
+        launch_k(kt, mortar_rows_kernel<true>, rgrid, dim3(256), 0, st, (int)nvi, mi->d.star_ptr.as<int32_t>(),
+                 mi->d.star_ent.as<int32_t>(), d_tptr.as<int32_t>(), d_tcon.as<int32_t>(), d_te.as<int32_t>(),
+                 me->d.tri.as<int32_t>(), blk_dev, (int32_t *)nullptr, d_rptr.as<int64_t>(), d_col.as<int32_t>(),
+                 d_val.as<double>(), d_ovf.as<int32_t>());
+        BEM_HIP(hipGetLastError());
+    }
+    P.nrows = nvi;
+    P.ncols = me->h.nv;
+    P.ptr.resize(nvi + 1);
+    for (int64_t r = 0; r <= nvi; ++r) P.ptr[r] = (int32_t)rptr[r];
+    P.col.resize(nnz);
+    P.val.resize(nnz);
+    if (nnz > 0) {
+        BEM_HIP(hipMemcpyAsync(P.col.data(), d_col.ptr, (size_t)nnz * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        BEM_HIP(hipMemcpyAsync(P.val.data(), d_val.ptr, (size_t)nnz * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    BEM_HIP(hipMemcpyAsync(&ovf, d_ovf.ptr, sizeof ovf, hipMemcpyDeviceToHost, st));
+    BEM_HIP(hipStreamSynchronize(st));
+    if (ovf) return set_error(BEM_E_DEVICE, "mortar row passes disagree");
+    return BEM_OK;
 }
 
 }  // namespace bemtx
