@@ -126,8 +126,9 @@ constexpr int kRowCols = 64;   // distinct columns of a row held by the row kern
 // counts the columns, pass 1 writes them at rowptr[i].  A row beyond the
 // local buffers sets *flag = 1 (the host then groups the matrix itself); a
 // pass 1 that disagrees with pass 0 sets 2 and writes nothing past its row.
+constexpr int kRowBlock = 64;   // one wave per workgroup: the few row waves spread over the compute units
 template <bool WRITE>
-__global__ __launch_bounds__(256) void mortar_rows_kernel(int nv, const int32_t *__restrict__ star_ptr,
+__global__ __launch_bounds__(kRowBlock) void mortar_rows_kernel(int nv, const int32_t *__restrict__ star_ptr,
                                                           const int32_t *__restrict__ star_ent,
                                                           const int32_t *__restrict__ tptr, const int32_t *__restrict__ tcon,
                                                           const int32_t *__restrict__ con_te,
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(256) void mortar_rows_kernel(int nv, const int32_t 
                                                           const int64_t *__restrict__ rowptr, int32_t *__restrict__ col,
                                                           double *__restrict__ val, int32_t *__restrict__ flag)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int i = blockIdx.x * kRowBlock + threadIdx.x;
     if (i >= nv) return;
     const int s0 = star_ptr[i], ns = star_ptr[i + 1] - s0;
     if (ns > kRowStar) {
@@ -310,10 +311,10 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     if (!s) s = dev_alloc(ctx, d_rcnt, (size_t)nvi * sizeof(int32_t));
     if (s) return s;
     const double *blk_dev = ncon > 0 ? d_blk.as<double>() : nullptr;
-    const dim3 rgrid((unsigned)((nvi + 255) / 256));
+    const dim3 rgrid((unsigned)((nvi + kRowBlock - 1) / kRowBlock));
     {
         KTimer kt(ctx, K_MORTAR);
-        launch_k(kt, mortar_rows_kernel<false>, rgrid, dim3(256), 0, st, (int)nvi, mi->d.star_ptr.as<int32_t>(),
+        launch_k(kt, mortar_rows_kernel<false>, rgrid, dim3(kRowBlock), 0, st, (int)nvi, mi->d.star_ptr.as<int32_t>(),
                  mi->d.star_ent.as<int32_t>(), d_tptr.as<int32_t>(), d_tcon.as<int32_t>(), d_te.as<int32_t>(),
                  me->d.tri.as<int32_t>(), blk_dev, d_rcnt.as<int32_t>(), (const int64_t *)nullptr, (int32_t *)nullptr,
                  (double *)nullptr, d_ovf.as<int32_t>());
@@ -341,7 +342,7 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     if (s) return s;
     {
         KTimer kt(ctx, K_MORTAR);
-        launch_k(kt, mortar_rows_kernel<true>, rgrid, dim3(256), 0, st, (int)nvi, mi->d.star_ptr.as<int32_t>(),
+        launch_k(kt, mortar_rows_kernel<true>, rgrid, dim3(kRowBlock), 0, st, (int)nvi, mi->d.star_ptr.as<int32_t>(),
                  mi->d.star_ent.as<int32_t>(), d_tptr.as<int32_t>(), d_tcon.as<int32_t>(), d_te.as<int32_t>(),
                  me->d.tri.as<int32_t>(), blk_dev, (int32_t *)nullptr, d_rptr.as<int64_t>(), d_col.as<int32_t>(),
                  d_val.as<double>(), d_ovf.as<int32_t>());
