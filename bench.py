@@ -399,6 +399,40 @@ def mortar_run(ctx, B, synth, np):
     return res
 
 
+def incident_run(ctx, B, synth, np):
+    """The C2 workload with the foam model's variations (Sec. 6.4) beside the
+    lossless plane wave: an absorbing interior (k_int + 0.5 i, the
+    complex-wavenumber instantiation of the regular assembly) and a point
+    source at (0, 0, 3): regular-assembly kernel time, GMRES steps and solve
+    time to the workload tolerance."""
+    import torch
+    c = synth.make_config("C2")
+    res = {}
+    for name, kim, kind, src in (("plane wave", 0.0, 0, c["dirs"]),
+                                 ("absorbing interior, k_int + 0.5i", 0.5, 0, c["dirs"]),
+                                 ("point source at (0, 0, 3)", 0.0, 1, np.array([[0.0, 0.0, 3.0]]))):
+        me, mi = B.Mesh(ctx, *c["ext"]), B.Mesh(ctx, *c["int"])
+        p = B.Problem(ctx, me, mi, c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
+        p.set_k_int_imag(kim)
+        p.set_incident(kind)
+        ctx.set_kernel_timing(("regular_tiles",))
+        p.assemble_operators()
+        p.assemble_projection()
+        reg_ms = ctx.kernel_time("regular_tiles")[0]
+        ctx.set_kernel_timing(())
+        p.solve(src, tol=c["tol"], maxit=2000)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, code = p.solve(src, tol=c["tol"], maxit=2000)
+        torch.cuda.synchronize()
+        res[name] = {"regular_kernel_ms": round(reg_ms, 3), "iterations": st["iterations"],
+                     "solve_ms": round(1e3 * (time.perf_counter() - t0), 3), "rel_residual": st["rel_residual"],
+                     "code": int(code)}
+        del p, me, mi
+    res["workload"] = "C2 (sphere ico4 / Fibonacci 2002, k 5/8, rho ratio 1.5), tol 1e-6"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -411,6 +445,7 @@ def main():
     ap.add_argument("--no-field", action="store_true", help="skip the field evaluation")
     ap.add_argument("--no-pmchwt", action="store_true", help="skip the comparison of the exterior formulations")
     ap.add_argument("--no-mortar", action="store_true", help="skip the host vs device mortar comparison")
+    ap.add_argument("--no-incident", action="store_true", help="skip the absorbing-interior and point-source runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes 5 times (reference for the "
                          "HBM byte counters) and exit")
@@ -537,6 +572,8 @@ def main():
         line["pmchwt"] = pmchwt_run(ctx, B, synth, np)
     if not args.no_mortar:
         line["mortar"] = mortar_run(ctx, B, synth, np)
+    if not args.no_incident:
+        line["incident"] = incident_run(ctx, B, synth, np)
     if not args.no_serving:
         ctx.trim()   # the serving workers size their budget from free HBM: return this context's blocks first
         torch.cuda.empty_cache()
