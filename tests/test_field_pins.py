@@ -149,3 +149,27 @@ def test_field_of_transparent_body(orc):
     f = F.mtf_field((xe, te), (xi, ti), k, k, X[0], d, pts, np.array([1, 1, 0, 0]))
     inc = np.exp(1j * k * pts @ d)
     assert np.max(np.abs(f - inc)) < 0.02, np.abs(f - inc)
+
+
+def test_absorbing_interior_field_converges_to_mie(orc):
+    """Absorbing interior (k_int = 3 + 0.6 i, Sec. 6.4): the field off the
+    surface converges at O(h^2) to the penetrable-sphere series evaluated with
+    the complex wavenumber, inside (where the interior potentials carry
+    exp(i k r) with the complex k) and outside."""
+    ke, ki, re, ri = 2.0, 3.0 + 0.6j, 1.0, 1.5
+    d = np.array([0.0, 0.0, 1.0])
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((12, 3)); u /= np.linalg.norm(u, axis=1)[:, None]
+    pts = np.concatenate([0.5 * u, 1.8 * u])
+    region = np.array([1] * 12 + [0] * 12)
+    ref = mie_field(pts, d, ke, ki, re, ri)
+    errs = []
+    for L in (1, 2, 3):
+        (xe, te), (xi, ti), _ = synth.configs.make_pair(7, L, "ico", 0.01, (1, 1, 1), int_level=L)
+        X, _ = orc.solve_mtf((xe, te), (xi, ti), ke, ki, re, ri, d)
+        f = F.mtf_field((xe, te), (xi, ti), ke, ki, X[0], d, pts, region)
+        errs.append([np.linalg.norm(f[:12] - ref[:12]) / np.linalg.norm(ref[:12]),
+                     np.linalg.norm(f[12:] - ref[12:]) / np.linalg.norm(ref[12:])])
+    errs = np.array(errs)
+    assert np.all(errs[1] < errs[0] / 2.5) and np.all(errs[2] < errs[1] / 2.5), errs
+    assert np.all(errs[2] < 0.01), errs
