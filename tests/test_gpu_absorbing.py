@@ -113,3 +113,15 @@ def test_absorption_checks_and_stale_operators(ctx, c1):
     p.assemble_operators()
     out, st, code = p.solve(np.array([[0.0, 0.0, 1.0]]), tol=1e-6, maxit=200)
     assert code == B.OK
+
+
+def test_absorbing_solve_mixed(ctx, orc, c1, c1_ops):
+    """The mixed form end to end (complex64 operators from the FP32
+    complex-wavenumber kernel, FP64 refinement) against the oracle's LU
+    solution, to the same 1e-5 as the lossless mixed solves."""
+    p, _, _ = _problem(ctx, c1, B.C64_MIXED)
+    d = np.array([[0.0, 0.6, 0.8]])
+    out, st, code = p.solve(d, tol=c1["tol"], maxit=500)
+    assert code == B.OK, st
+    X, _ = orc.solve_mtf(c1["ext"], c1["int"], c1["k_ext"], c1["k_int"] + 1j * K_IM, 1.0, 1.5, d, ops=c1_ops)
+    assert _rel(out.cpu().numpy()[0], X[0]) < 1e-5
