@@ -20,6 +20,10 @@ primitives and no blocking or reordering:
   solve_mtf(...)          x = A^{-1} b by dense LU: GMRES on the mass-
                           preconditioned (strong) form M^{-1} A x = M^{-1} b
                           reaches exactly this solution (Sec. 3.3, 5.1)
+  solve_mtf_inplace(...)  the same solution for systems of tens of thousands
+                          of unknowns: the block matrix is filled in place,
+                          operator rows a chunk at a time, and factorised in
+                          place (no second copy of the matrix)
   pmchwt_system(...)      the exterior PMCHWT matrix as printed in Sec. 3.3,
                           interior operators scaled as in the single-trace
                           Calderon system of Sec. 2.3
@@ -248,6 +252,56 @@ def solve_mtf(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4, op
     B = np.stack([mtf_rhs(ext_mesh, k_ext, d, ni, incident) for d in np.atleast_2d(dirs)], axis=1)
     X = np.linalg.solve(A, B)
     return X.T, ops
+
+
+def solve_mtf_inplace(ext_mesh, int_mesh, k_ext, k_int, rho_ext, rho_int, dirs, ng=4, chunk=512,
+                      incident=0, log=None):
+    """Exact discrete MTF solution(s) by dense LU, as solve_mtf, for systems
+    whose operators and block matrix do not fit in memory side by side
+    (36,488 unknowns: 21.3 GB for the matrix alone).  The matrix of
+    mtf_system (same blocks, same printed signs, Sec. 3.3) is allocated once
+    in column-major order and filled with the operator rows of each mesh
+    `chunk` rows at a time; LAPACK's LU with partial pivoting (getrf) then
+    overwrites it, and getrs solves for every right-hand side.
+    Returns x [nrhs, n]."""
+    import time
+    from scipy.linalg import lu_factor, lu_solve
+    xe, te = _mesh(*ext_mesh)
+    xi, ti = _mesh(*int_mesh)
+    ne, ni = xe.shape[0], xi.shape[0]
+    n = 2 * ne + 2 * ni
+    t0 = time.time()
+    A = np.zeros((n, n), dtype=np.complex128, order="F")
+    for (xyz, tri, k, off, nv) in ((xe, te, k_ext, 0, ne), (xi, ti, k_int, 2 * ne, ni)):
+        for r0 in range(0, nv, chunk):
+            rows = np.arange(r0, min(nv, r0 + chunk), dtype=np.int64)
+            O = assemble(xyz, tri, k, ng=ng, rows=rows)
+            r = off + rows
+            A[r, off:off + nv] = -O["K"]
+            A[r, off + nv:off + 2 * nv] = O["V"]
+            A[nv + r, off:off + nv] = O["D"]
+            A[nv + r, off + nv:off + 2 * nv] = O["T"]
+            del O
+            if log:
+                log(f"  {'exterior' if off == 0 else 'interior'} rows {rows[-1] + 1}/{nv}"
+                    f" ({time.time() - t0:.0f} s)")
+    P_ie = mortar((xi, ti), (xe, te))
+    A[0:ne, 2 * ne:2 * ne + ni] = 0.5 * P_ie.T
+    A[ne:2 * ne, 2 * ne + ni:] = 0.5 * (rho_ext / rho_int) * P_ie.T
+    A[2 * ne:2 * ne + ni, 0:ne] = -0.5 * P_ie
+    A[2 * ne + ni:, ne:2 * ne] = -0.5 * (rho_int / rho_ext) * P_ie
+    del P_ie
+    B = np.stack([mtf_rhs((xe, te), k_ext, d, ni, incident) for d in np.atleast_2d(dirs)], axis=1)
+    t1 = time.time()
+    if log:
+        log(f"  matrix {n} x {n} filled in {t1 - t0:.0f} s; LU ...")
+    lu, piv = lu_factor(A, overwrite_a=True, check_finite=False)
+    if not np.shares_memory(lu, A):
+        raise MemoryError("getrf copied the matrix")
+    X = lu_solve((lu, piv), B, check_finite=False)
+    if log:
+        log(f"  LU and solve {time.time() - t1:.0f} s")
+    return np.ascontiguousarray(X.T)
 
 
 def pmchwt_system(ops, rho_ext, rho_int):

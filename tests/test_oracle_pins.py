@@ -385,6 +385,35 @@ def test_transparent_body(orc):
     assert np.linalg.norm(-x[2 * ne:2 * ne + ni] - ui) / np.linalg.norm(ui) < 0.02
 
 
+def test_inplace_lu_solution(orc):
+    """solve_mtf_inplace (row chunks written into a column-major matrix, LU in
+    place; it writes the large-workload golden traces) against two pins: the
+    transparent body, whose traces are the incident wave, and the
+    penetrable-sphere series on a nonconforming pair; ragged chunks (7 rows)
+    exercise every block boundary.  It also agrees with solve_mtf."""
+    k = 1.5
+    d = np.array([[0.6, 0.0, 0.8], [0.0, 1.0, 0.0]])
+    (xe, te), (xi, ti), _ = synth.configs.make_pair(9, 2, "ico", 0.02, (1, 0.9, 0.8), int_level=2)
+    X = orc.solve_mtf_inplace((xe, te), (xi, ti), k, k, 1.0, 1.0, d, chunk=7)
+    ne, ni = len(xe), len(xi)
+    for r in range(2):
+        ue, ui = np.exp(1j * k * xe @ d[r]), np.exp(1j * k * xi @ d[r])
+        assert np.linalg.norm(-X[r, :ne] - ue) / np.linalg.norm(ue) < 0.02
+        assert np.linalg.norm(-X[r, 2 * ne:2 * ne + ni] - ui) / np.linalg.norm(ui) < 0.02
+    ke, ki, re, ri = 2.0, 3.0, 1.0, 1.5
+    dz = np.array([0.0, 0.0, 1.0])
+    (xe, te), (xi, ti), _ = synth.configs.make_pair(7, 2, "ico", 0.01, (1, 1, 1), int_level=2)
+    X = orc.solve_mtf_inplace((xe, te), (xi, ti), ke, ki, re, ri, dz, chunk=7)[0]
+    ne, ni = len(xe), len(xi)
+    p, dpp, _ = mie_traces(xe, dz, ke, ki, re, ri)
+    pi, _, dpmi = mie_traces(xi, dz, ke, ki, re, ri)
+    e = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    errs = [e(-X[:ne], p), e(-X[ne:2 * ne], dpp), e(-X[2 * ne:2 * ne + ni], pi), e(-X[2 * ne + ni:], dpmi)]
+    assert max(errs) < 0.06, errs
+    Y, _ = orc.solve_mtf((xe, te), (xi, ti), ke, ki, re, ri, dz)
+    assert np.abs(X - Y[0]).max() < 1e-12 * np.abs(Y[0]).max()
+
+
 # ------------------------------------------------------------- exterior PMCHWT
 
 def test_pmchwt_mie_convergence(orc):
