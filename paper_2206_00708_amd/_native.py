@@ -48,6 +48,7 @@ SIGNATURES = {
     "bem_assemble_operators": (c_status, [vp, i32]),
     "bem_assemble_projection": (c_status, [vp]),
     "bem_mtf_matvec": (c_status, [vp, vp, vp, i32, i32]),
+    "bem_mtf_matvec_noalloc": (c_status, [vp, vp, vp, i32]),
     "bem_mtf_matvec_batch": (c_status, [vp, vp, vp, i32, i32, i32]),
     "bem_mtf_rhs": (c_status, [vp, vp, i32, vp, i32]),
     "bem_solve": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),

@@ -165,6 +165,18 @@ class Problem:
         _check(N.load().bem_mtf_matvec(self._h, _ptr(x), _ptr(y), int(strong), DEVICE))
         return y
 
+    def mtf_matvec_noalloc(self, x, y=None, strong=True):
+        """bem_mtf_matvec_noalloc: the same product with the library's static
+        work array (no device allocation by the library); asynchronous on
+        the context's stream.  x, y: complex128 device tensors of length n."""
+        x = x.to(device=self.ctx.device, dtype=torch.complex128).contiguous()
+        if y is None:
+            y = torch.empty_like(x)
+        if y.dtype != torch.complex128 or not y.is_contiguous() or y.numel() != x.numel() or y.device != x.device:
+            raise ValueError("y must be a contiguous complex128 tensor like x")
+        _check(N.load().bem_mtf_matvec_noalloc(self._h, _ptr(x), _ptr(y), int(strong)))
+        return y
+
     def mtf_matvec_batch(self, x, strong=True):
         """x: [nrhs, n] complex; one product per row (matrix cores for complex64 problems)."""
         x = x.to(device=self.ctx.device, dtype=torch.complex128).contiguous()

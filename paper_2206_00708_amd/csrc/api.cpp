@@ -135,6 +135,8 @@ bem_status launch_winding(const bem_mesh *m, int np, const double *pts, double *
 bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_solver_opts *opts, void *traces,
                       bem_memspace space, bem_stats *stats);
 bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_memspace space);
+bem_status matvec_noalloc_impl(bem_problem *p, const void *x, void *y, int strong);
+bem_status noalloc_scratch_init(int device);
 bem_status matvec_batch_impl(bem_problem *p, const void *x, void *y, int nrhs, int strong, bem_memspace space);
 bem_status rhs_impl(bem_problem *p, const double *dirs, int nrhs, void *b, bem_memspace space);
 bem_status permute_matrix_out(const bem_problem *p, int mesh, const void *src, void *dst);
@@ -155,9 +157,13 @@ static hipEvent_t take_event(bem_ctx *c)
     return e;
 }
 
+static thread_local bool t_no_timing = false;
+NoTiming::NoTiming() : prev(t_no_timing) { t_no_timing = true; }
+NoTiming::~NoTiming() { t_no_timing = prev; }
+
 KTimer::KTimer(bem_ctx *ctx, int kid) : c(ctx), id(kid)
 {
-    if (!c || !(c->ktiming >> kid & 1u)) return;
+    if (!c || t_no_timing || !(c->ktiming >> kid & 1u)) return;
     a = take_event(c);
     b = take_event(c);
     if (!a || !b) {
@@ -233,6 +239,9 @@ bem_status bem_ctx_create(int32_t device, void *hip_stream, size_t hbm_budget_by
     BEM_HIP(hipGetDeviceProperties(&prop, device));
     if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
         return set_error(BEM_E_UNSUPPORTED, std::string("built for gfx950, device is ") + prop.gcnArchName);
+    // the static work array of bem_mtf_matvec_noalloc: its address on this device
+    const bem_status ss = noalloc_scratch_init(device);
+    if (ss) return ss;
     bem_ctx *c = new bem_ctx;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -571,6 +580,12 @@ bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong
     if (!p || !x || !y) return set_error(BEM_E_ARG, "null argument");
     if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
     return matvec_impl(p, x, y, strong, space);
+}
+
+bem_status bem_mtf_matvec_noalloc(bem_problem *p, const void *x, void *y, int32_t strong)
+{
+    if (!p || !x || !y) return set_error(BEM_E_ARG, "null argument");
+    return matvec_noalloc_impl(p, x, y, strong);   // size check first, then the assembly state
 }
 
 bem_status bem_mtf_matvec_batch(bem_problem *p, const void *x, void *y, int32_t nrhs, int32_t strong,

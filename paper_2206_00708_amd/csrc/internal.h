@@ -237,6 +237,14 @@ struct KTimer {
     ~KTimer();
 };
 
+// While one of these lives on a thread, KTimer takes no events on that
+// thread (calls that must not create events or touch the context's pool).
+struct NoTiming {
+    bool prev;
+    NoTiming();
+    ~NoTiming();
+};
+
 // Launch `kernel` on `st`, timed by `kt` when it holds events.
 template <typename... KArgs, typename... Args>
 inline void launch_k(const KTimer &kt, void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t shmem, hipStream_t st,

@@ -37,6 +37,9 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -2235,6 +2238,85 @@ bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_m
     BEM_HIP(hipGetLastError());
     BEM_HIP(hipMemcpyAsync(y, yu.ptr, bytes, space == BEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
     BEM_HIP(hipStreamSynchronize(st));
+    return BEM_OK;
+}
+
+// ---- the product without allocations: work buffers in one static device
+// array per GPU, for callers that cannot allocate (graph capture, tight
+// serving loops).  Host code never passes the array's name to a kernel (in
+// host code it is a stand-in, not a device address): its address on each
+// device is looked up once, at context creation with that device current,
+// and kept per device.
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;   // device -> address of that device's copy of `scratch`
+}  // namespace
+
+bem_status noalloc_scratch_init(int device)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return BEM_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return set_error(BEM_E_DEVICE, "hipGetSymbolAddress(scratch) returned no address");
+    g_scratch_ptr[device] = ptr;
+    return BEM_OK;
+}
+
+size_t noalloc_scratch_bytes() { return NOALLOC_SCRATCH_BYTES; }
+
+// Work buffers of one product carved from the static array: the permuted
+// input, the weak and strong results (n complex128 each) and the partial
+// sums of the tile and inverse-mass kernels.
+static size_t noalloc_need(int ne, int ni, size_t off[4])
+{
+    const size_t vb = ((size_t)(2 * ne + 2 * ni) * sizeof(double2) + 255) & ~size_t(255);
+    off[0] = 0;
+    off[1] = vb;
+    off[2] = 2 * vb;
+    off[3] = 3 * vb;
+    return 3 * vb + split_part_bytes(ne, ni);
+}
+
+bem_status matvec_noalloc_impl(bem_problem *p, const void *x, void *y, int strong)
+{
+    bem_ctx *ctx = p->ctx;
+    const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv, n = 2 * ne + 2 * ni;
+    size_t off[4];
+    const size_t need = noalloc_need(ne, ni, off);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return set_error(BEM_E_UNSUPPORTED, "bem_mtf_matvec_noalloc: the product needs " + std::to_string(need) +
+                                                " bytes of work space, more than the static " +
+                                                std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte array");
+    if (!p->ops_ready || !p->proj_ready) return set_error(BEM_E_STATE, "assemble operators and projection first");
+    BEM_HIP(hipSetDevice(ctx->device));
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        auto it = g_scratch_ptr.find(ctx->device);
+        if (it == g_scratch_ptr.end()) return set_error(BEM_E_STATE, "static work array not set up on this device");
+        base = static_cast<unsigned char *>(it->second);
+    }
+    double2 *xi = reinterpret_cast<double2 *>(base + off[0]);
+    double2 *yi = reinterpret_cast<double2 *>(base + off[1]);
+    double2 *zi = reinterpret_cast<double2 *>(base + off[2]);
+    double4 *part = reinterpret_cast<double4 *>(base + off[3]);
+    hipStream_t st = ctx->stream;
+    NoTiming nt;   // per-kernel timing would take events from the context's pool
+    const dim3 g((n + 255) / 256);
+    hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
+                       p->inte->d.perm.as<int32_t>(), static_cast<const double2 *>(x), xi, 1);
+    MtfArgs A = make_args(p);
+    bem_status s = apply_A(p, A, xi, yi, zi, strong != 0, nullptr, part);
+    if (s) return s;
+    hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
+                       p->inte->d.perm.as<int32_t>(), strong ? zi : yi, static_cast<double2 *>(y), 0);
+    BEM_HIP(hipGetLastError());
     return BEM_OK;
 }
 

@@ -1,0 +1,77 @@
+"""bem_mtf_matvec_noalloc (work buffers in the library's static device array,
+no allocation) against bem_mtf_matvec on the same problems: two calls in a
+row through the C ABI, the second on a smaller problem, in both precisions,
+weak and strong form; and the size limit.  Bar: the FP64 parity tolerance
+of the product (1e-12 relative); the two run the same kernels in the same
+order, so the results are expected to agree bitwise."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+B = pytest.importorskip("paper_2206_00708_amd")
+from paper_2206_00708_amd import _native as N  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    return B.Context(0)
+
+
+def _problem(ctx, ext, inte, k_ext, k_int, prec):
+    me, mi = B.Mesh(ctx, *ext), B.Mesh(ctx, *inte)
+    p = B.Problem(ctx, me, mi, k_ext, k_int, 1.0, 2.0, precision=prec)
+    p.assemble_operators()
+    p.assemble_projection()
+    return p, me, mi
+
+
+def _noalloc(p, x, strong):
+    """The C-ABI call itself: device pointers in and out."""
+    y = torch.full_like(x, float("nan"))
+    code = N.load().bem_mtf_matvec_noalloc(p._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                           int(strong))
+    assert code == 0, N.load().bem_last_error().decode()
+    torch.cuda.synchronize()
+    return y
+
+
+@pytest.mark.parametrize("prec", [B.C128, B.C64_MIXED], ids=["fp64", "mixed"])
+def test_noalloc_matches_matvec_two_calls(ctx, prec):
+    big = synth.make_pair(3, 3, "fib", 0.01, (1.0, 0.8, 0.6), int_n=700)
+    small = synth.make_config("C1")
+    cases = [(big[0], big[1], 6.0, 12.0), (small["ext"], small["int"], small["k_ext"], small["k_int"])]
+    rng = np.random.default_rng(77)
+    for ext, inte, ke, ki in cases:   # the second call runs on a smaller problem
+        p, me, mi = _problem(ctx, ext, inte, ke, ki, prec)
+        for strong in (1, 0):
+            x = rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n)
+            xt = torch.from_numpy(x).to(ctx.device)
+            ref = p.mtf_matvec(xt, strong=bool(strong)).cpu().numpy()
+            got = _noalloc(p, xt, strong).cpu().numpy()
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print(f"n {p.n} prec {prec} strong {strong}: max rel diff {err:.1e}, "
+                  f"bitwise {np.array_equal(got, ref)}")
+            assert np.all(np.isfinite(got))
+            assert err <= 1e-12
+        del p, me, mi
+
+
+def test_noalloc_rejects_oversized(ctx):
+    """12,000 + 12,000 vertices need about 74 MB of work space: rejected
+    before any launch (no assembly needed for the check)."""
+    xyz, tri = synth.meshes.fibonacci_sphere(12000)
+    ext = inte = (xyz, synth.meshes.orient_outward(xyz, tri))
+    me, mi = B.Mesh(ctx, *ext), B.Mesh(ctx, *inte)
+    p = B.Problem(ctx, me, mi, 2.0, 3.0)
+    x = torch.zeros(p.n, dtype=torch.complex128, device=ctx.device)
+    y = torch.zeros_like(x)
+    code = N.load().bem_mtf_matvec_noalloc(p._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), 1)
+    assert code == -7, code
+    assert "static" in N.load().bem_last_error().decode()
