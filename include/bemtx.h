@@ -201,6 +201,26 @@ bem_status bem_assemble_projection(bem_problem *p);
  * fused multiply-adds).  BEM_E_ARG for another value. */
 bem_status bem_problem_set_mortar(bem_problem *p, int32_t on_device);
 
+/* How the mass-matrix preconditioner blockdiag(M_e, M_e, M_i, M_i)^-1 of
+ * the strong form (Sec. 3.3) is applied: mode 1 through dense inverse mass
+ * matrices built once per projection set-up (O(N^2) memory; at most 16,384
+ * vertices per mesh, else BEM_E_UNSUPPORTED at the set-up); mode 2 without
+ * forming M^-1, by Chebyshev iteration on diag(M)^-1 M (its spectrum lies
+ * in [1/2, 2] on every P1 mesh, so k steps reduce the error by 4 3^-k;
+ * 36 steps for BEM_C128, 24 for BEM_C64_MIXED), 12 steps per launch on
+ * overlapping vertex patches, O(N) memory and no size limit (a vertex may
+ * have at most 15 neighbours, else BEM_E_MESH at the set-up); mode 0 (the
+ * default) picks mode 2 when the dense inverses would exceed 256 MB or a mesh
+ * has more than 16,384 vertices, else mode 1.  Both apply M^-1 to FP64
+ * rounding in the FP64 form.  Takes effect at the next
+ * bem_assemble_projection (a changed mode marks the projection stale).
+ * BEM_E_ARG for another mode. */
+bem_status bem_problem_set_mass_apply(bem_problem *p, int32_t mode);
+
+/* The choice of the last projection set-up: *sparse = 1 for the Chebyshev
+ * apply, 0 for dense inverses.  BEM_E_STATE before the projection. */
+bem_status bem_problem_mass_apply(const bem_problem *p, int32_t *sparse);
+
 /* Wall-clock milliseconds of the mortar step (geometry and CSR) of the last
  * bem_assemble_projection, by the setting above.  BEM_E_STATE before the
  * projection is assembled. */

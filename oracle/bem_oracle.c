@@ -36,6 +36,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -104,6 +105,10 @@ void orc_rule6(double *bary18, double *w6)
 }
 
 void orc_gauss01(int n, double *x, double *w) { gauss01(n, x, w); }
+
+/* Thread count of the OpenMP loops (the CPU timing runs one thread and all). */
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* --------------------------------------------------------------- geometry */
 

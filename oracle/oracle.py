@@ -71,8 +71,19 @@ def lib():
         L.orc_gauss01.argtypes = [i32, p, p]
         L.orc_ss_poly.argtypes = [i32, i32, i32, i32, i32, i32]
         L.orc_ss_poly.restype = d
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_max_threads.restype = i32
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """OpenMP threads of the C loops (for timing at one thread and at all)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads():
+    return int(lib().orc_max_threads())
 
 
 def _ptr(a):

@@ -59,6 +59,8 @@ SIGNATURES = {
     "bem_problem_set_k_int_imag": (c_status, [vp, f64]),
     "bem_problem_set_mortar": (c_status, [vp, i32]),
     "bem_problem_mortar_ms": (c_status, [vp, ctypes.POINTER(f64)]),
+    "bem_problem_set_mass_apply": (c_status, [vp, i32]),
+    "bem_problem_mass_apply": (c_status, [vp, ctypes.POINTER(i32)]),
     "bem_solve_pmchwt": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
     "bem_pmchwt_matvec": (c_status, [vp, vp, vp, i32, i32]),
     "bem_solve_hc_neumann": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),

@@ -208,6 +208,19 @@ class Problem:
         """bem_problem_set_mortar: mortar geometry on the device (True) or the host."""
         _check(N.load().bem_problem_set_mortar(self._h, int(on_device)))
 
+    MASS_AUTO, MASS_DENSE, MASS_SPARSE = 0, 1, 2
+
+    def set_mass_apply(self, mode):
+        """bem_problem_set_mass_apply: 0 by size, 1 dense inverse masses, 2 the
+        sparse Chebyshev apply; takes effect at the next assemble_projection."""
+        _check(N.load().bem_problem_set_mass_apply(self._h, int(mode)))
+
+    def mass_apply_sparse(self):
+        """bem_problem_mass_apply: True when the last projection set-up chose the sparse apply."""
+        v = ctypes.c_int32()
+        _check(N.load().bem_problem_mass_apply(self._h, ctypes.byref(v)))
+        return bool(v.value)
+
     def mortar_ms(self):
         """bem_problem_mortar_ms: wall time of the last projection set-up's mortar step."""
         v = ctypes.c_double()

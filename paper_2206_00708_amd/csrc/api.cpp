@@ -59,6 +59,10 @@ void DevMem::release()
             std::lock_guard<std::mutex> lk(ctx->mem_mu);
             ctx->free_blocks.emplace(bytes, ptr);
             ctx->cached_bytes += bytes;
+            // marks the main-stream work that may still use the block (see dev_alloc)
+            if (!ctx->release_ev && hipSetDevice(ctx->device) == hipSuccess)
+                (void)hipEventCreateWithFlags(&ctx->release_ev, hipEventDisableTiming);
+            if (ctx->release_ev) (void)hipEventRecord(ctx->release_ev, ctx->stream);
         } else {
             (void)hipFree(ptr);
         }
@@ -69,7 +73,7 @@ void DevMem::release()
 
 DevMem::~DevMem() { release(); }
 
-bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes)
+bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes, hipStream_t use)
 {
     if (m.ptr && m.bytes >= bytes) return BEM_OK;
     m.release();
@@ -83,6 +87,8 @@ bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes)
         m.ctx = ctx;
         ctx->cached_bytes -= it->first;
         ctx->free_blocks.erase(it);
+        // another stream: wait for the main-stream work queued up to the latest release
+        if (use && use != ctx->stream && ctx->release_ev) BEM_HIP(hipStreamWaitEvent(use, ctx->release_ev, 0));
         return BEM_OK;
     }
     if (ctx->budget && ctx->in_use + cls > ctx->budget) drop_cached(ctx, cls);
@@ -109,7 +115,7 @@ bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes)
 template <class T, class A>
 static bem_status upload(bem_ctx *ctx, DevMem &m, const std::vector<T, A> &v, hipStream_t st = nullptr)
 {
-    bem_status s = dev_alloc(ctx, m, v.size() * sizeof(T));
+    bem_status s = dev_alloc(ctx, m, v.size() * sizeof(T), st);
     if (s) return s;
     if (!v.empty())
         BEM_HIP(hipMemcpyAsync(m.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st ? st : ctx->stream));
@@ -259,6 +265,7 @@ void bem_ctx_destroy(bem_ctx *ctx)
         (void)hipStreamDestroy(ctx->aux);
     }
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    if (ctx->release_ev) (void)hipEventDestroy(ctx->release_ev);
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     {
@@ -411,13 +418,49 @@ void bem_problem_destroy(bem_problem *p)
     delete p;
 }
 
+// Dense inverse masses stream (N_e^2 + N_i^2) entries per apply; above this
+// many bytes the sparse Chebyshev apply (three or two launches on the
+// patches, tens of microseconds together) is the faster one, and above
+// 16,384 vertices on a mesh the dense inverse is not built at all.
+constexpr size_t kMassDenseMaxBytes = size_t(256) << 20;
+
+static bool pick_mass_sparse(const bem_problem *p)
+{
+    const size_t ne = p->ext->h.nv, ni = p->inte->h.nv;
+    if (p->mass_mode == 2) return true;
+    if (p->mass_mode == 1) return false;
+    if (std::max(ne, ni) > 16384) return true;
+    return (ne * ne + ni * ni) * (p->prec == BEM_C128 ? sizeof(double) : sizeof(float)) > kMassDenseMaxBytes;
+}
+
+bem_status bem_problem_set_mass_apply(bem_problem *p, int32_t mode)
+{
+    if (!p) return set_error(BEM_E_ARG, "null problem");
+    if (mode < 0 || mode > 2) return set_error(BEM_E_ARG, "mass apply mode must be 0 (by size), 1 (dense) or 2 (sparse)");
+    if (mode != p->mass_mode) p->proj_ready = false;   // takes effect at the next projection set-up
+    p->mass_mode = mode;
+    return BEM_OK;
+}
+
+bem_status bem_problem_mass_apply(const bem_problem *p, int32_t *sparse)
+{
+    if (!p || !sparse) return set_error(BEM_E_ARG, "null argument");
+    if (!p->proj_ready) return set_error(BEM_E_STATE, "assemble the projection first");
+    *sparse = p->mass_sparse ? 1 : 0;
+    return BEM_OK;
+}
+
 bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t maxit, size_t *bytes)
 {
     if (!p || !bytes || nrhs < 1 || maxit < 1) return set_error(BEM_E_ARG, "bad argument");
     const size_t ne = p->ext->h.nv, ni = p->inte->h.nv, n = 2 * ne + 2 * ni;
     const size_t eb = p->prec == BEM_C128 ? sizeof(double2) : sizeof(float2);
     size_t b = 4 * (ne * op_ld(ne) + ni * op_ld(ni)) * eb;         // dense operators
-    b += (ne * ne + ni * ni) * (p->prec == BEM_C128 ? sizeof(double) : sizeof(float));   // dense inverse masses
+    const bool sparse_mass = pick_mass_sparse(p);
+    if (sparse_mass)   // patch tables: at most 8 patch copies of each vertex with its row (bound)
+        b += 8 * (ne + ni) * (3 * sizeof(int32_t) + sizeof(double) + 14 * (sizeof(int32_t) + sizeof(double)));
+    else
+        b += (ne * ne + ni * ni) * (p->prec == BEM_C128 ? sizeof(double) : sizeof(float));   // dense inverse masses
     size_t scratch = std::max(tile_scratch_bytes(p->ext, eb), tile_scratch_bytes(p->inte, eb));
     scratch = std::max(scratch, std::max(p->ext->h.sing.size(), p->inte->h.sing.size()) * 36 * sizeof(double2));
     b += scratch;
@@ -430,6 +473,7 @@ bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t max
         const size_t kop = 2 * (op_ld(ne) + op_ld(ni)), km = ((ne + 31) & ~size_t(31)) + ((ni + 31) & ~size_t(31));
         b += (2 * 128 * kop + 256 * km) * sizeof(float);
         b += (8 * 128 * 4 + 8 * 256) * (ne + ni) * sizeof(float);
+        if (sparse_mass) b += 6 * 64 * n * sizeof(double2);   // Chebyshev work sets of the block apply
     }
     b += 64 * (ne + ni) * sizeof(double);                          // sparse couplings (bound)
     *bytes = b;
@@ -538,6 +582,13 @@ bem_status bem_assemble_projection(bem_problem *p)
     }
     if (!p->ev_proj) BEM_HIP(hipEventCreateWithFlags(&p->ev_proj, hipEventDisableTiming));
     BEM_HIP(hipStreamWaitEvent(ax, p->ev_pre_asm, 0));
+    if (p->proj_ready) {
+        // a second set-up rewrites this problem's tables in place: first let the main-stream work that may
+        // read them (an asynchronous product) finish
+        BEM_HIP(hipEventRecord(p->ev_proj, ctx->stream));
+        BEM_HIP(hipStreamWaitEvent(ax, p->ev_proj, 0));
+    }
+    p->proj_ready = false;
     bem_status s = BEM_OK;
     double defect = 0;
     if (p->mortar_dev) {   // geometry on the device, on the auxiliary stream before the inverse masses
@@ -550,7 +601,21 @@ bem_status bem_assemble_projection(bem_problem *p)
         s = upload(ctx, p->M_ptr[m], p->M[m].ptr, ax);
         if (!s) s = upload(ctx, p->M_col[m], p->M[m].col, ax);
         if (!s) s = upload(ctx, p->M_val[m], p->M[m].val, ax);
-        if (!s) s = launch_mass_inverse(p, m, ax);
+    }
+    if (s) return s;
+    p->mass_sparse = pick_mass_sparse(p);
+    if (p->mass_sparse) {   // patch tables of the sparse apply (host), no dense inverse
+        for (int m = 0; m < 2; ++m) p->Minv[m].release();
+        s = cheb_tables(p->M, CHEB_S, p->cheb);
+        if (!s) s = upload(ctx, p->cheb_pmesh, p->cheb.pmesh, ax);
+        if (!s) s = upload(ctx, p->cheb_vbeg, p->cheb.vbeg, ax);
+        if (!s) s = upload(ctx, p->cheb_cnt, p->cheb.cnt, ax);
+        if (!s) s = upload(ctx, p->cheb_vert, p->cheb.vert, ax);
+        if (!s) s = upload(ctx, p->cheb_dinv, p->cheb.dinv, ax);
+        if (!s) s = upload(ctx, p->cheb_ecol, p->cheb.ecol, ax);
+        if (!s) s = upload(ctx, p->cheb_eval, p->cheb.eval, ax);
+    } else {
+        for (int m = 0; m < 2 && !s; ++m) s = launch_mass_inverse(p, m, ax);
     }
     if (s) return s;
     if (!p->mortar_dev) {

@@ -160,7 +160,11 @@ bem_status hip_error(hipError_t e, const char *what);
         if (e_ != hipSuccess) return ::bemtx::hip_error(e_, #call);       \
     } while (0)
 
-bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes);
+// Device memory of at least `bytes` for m, from the context's reuse cache
+// when a block fits.  `use`: the stream that will first touch the block; a
+// cached block handed to a stream other than the context's main stream
+// waits there for the main-stream work queued before the block's release.
+bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes, hipStream_t use = nullptr);
 
 // Run f(begin, end) over [0, n) split into contiguous ranges on up to 16 host
 // threads (serial below `grain` items).  Ranges are fixed by n, so results
@@ -186,6 +190,30 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
 bem_status mortar_from_contribs(const MeshData &mi, const MeshData &me, int64_t ncon, const int32_t *ti,
                                 const int32_t *te, const double *blk, double worst, Csr &P);
 void transpose_csr(const Csr &A, Csr &At);
+
+// Sparse inverse-mass apply (mass_cheb.cpp): Chebyshev iteration on the
+// Jacobi-scaled mass matrix, s steps per launch on overlapping patches of
+// vertices (owned range + every vertex within s edges, listed by distance).
+constexpr int CHEB_OWN_MAX = 512;    // owned vertices per patch (halved until the patches fit)
+constexpr int CHEB_LMAX = 2048;      // vertices per patch: 2 per thread of a 1024-thread workgroup
+constexpr int CHEB_WMAX = 16;        // entries per mass-matrix row (the vertex and its neighbours)
+constexpr int CHEB_S = 12;           // steps per launch
+struct ChebTables {
+    int s = 0, own = 0, lmax = 0;
+    int nparts[2] = {0, 0};           // patches of each mesh (mesh 0 first)
+    HVec<int32_t> pmesh;              // [patch] mesh
+    HVec<int32_t> vbeg;               // [patch + 1] offsets of the local vertex lists
+    HVec<int32_t> cnt;                // [patch][s + 1] vertices within d edges of the owned range
+    HVec<int32_t> vert;               // local vertex -> mesh vertex (internal numbering)
+    HVec<double> dinv;                // 1 / M_vv
+    HVec<int32_t> rptr;               // [local vertex + 1] row starts into col / val (rows within s - 1 edges)
+    HVec<int32_t> col;                // local column index within the patch
+    HVec<double> val;
+    int ell_w = 0;                    // the rows as ELL blocks: patch p at ell_w vbeg[p], [q][local row]
+    HVec<uint16_t> ecol;
+    HVec<double> eval;
+};
+bem_status cheb_tables(const Csr M[2], int s, ChebTables &T);
 void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue method
 
 }  // namespace bemtx
@@ -215,12 +243,15 @@ struct bem_ctx {
     // assembly scratch (block-pair tiles, singular contributions), grown on demand
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
-    // Device blocks the library has released, kept for reuse by size class
-    // (all work of a context is ordered on its stream, so a block may be
-    // handed out again without waiting for the kernels that used it).
-    // in_use counts them until bem_ctx_trim, bem_ctx_destroy or a budget
-    // shortfall returns them to the device.
+    // Device blocks the library has released, kept for reuse by size class.
+    // Main-stream reuse needs no wait (stream order); every release records
+    // release_ev on the main stream, and a cached block handed to the
+    // auxiliary stream first waits for it.  Work on the auxiliary stream
+    // ends before the call that queued it returns.  in_use counts the
+    // blocks until bem_ctx_trim, bem_ctx_destroy or a budget shortfall
+    // returns them to the device.
     std::multimap<size_t, void *> free_blocks;
+    hipEvent_t release_ev = nullptr;
     size_t cached_bytes = 0;
     std::mutex mem_mu;
 };
@@ -304,7 +335,13 @@ struct bem_problem {
     // sparse couplings and masses
     bemtx::Csr M[2], P_ie, P_ei;
     bemtx::DevMem P_ie_ptr, P_ie_col, P_ie_val, P_ei_ptr, P_ei_col, P_ei_val;
-    bemtx::DevMem Minv[2];          // dense real inverse mass matrices (FP64)
+    bemtx::DevMem Minv[2];          // dense real inverse mass matrices (FP64 or FP32), when mass_sparse is off
+    // inverse-mass apply: mass_mode 0 picks by size, 1 dense M^-1, 2 sparse Chebyshev; mass_sparse is the
+    // choice of the last projection set-up
+    int mass_mode = 0;
+    bool mass_sparse = false;
+    bemtx::ChebTables cheb;
+    bemtx::DevMem cheb_pmesh, cheb_vbeg, cheb_cnt, cheb_vert, cheb_dinv, cheb_ecol, cheb_eval;
     // per near entry (i, j) of each mesh: V_ij - V_ji (j < i, else 0), D_ij - D_ji (likewise),
     // T_ij - K_ji, complex128; the mat-vec reads only K and the upper triangles of V and D
     bemtx::DevMem corr[2];

@@ -207,7 +207,7 @@ template <class V>
 bem_status upload_vec(bem_ctx *ctx, DevMem &m, const V &v, hipStream_t st)
 {
     using T = typename V::value_type;
-    bem_status s = dev_alloc(ctx, m, std::max<size_t>(1, v.size()) * sizeof(T));
+    bem_status s = dev_alloc(ctx, m, std::max<size_t>(1, v.size()) * sizeof(T), st);
     if (s) return s;
     if (!v.empty()) BEM_HIP(hipMemcpyAsync(m.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
     return BEM_OK;
@@ -228,10 +228,10 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     if (!s) s = upload_vec(ctx, d_re, g.re, st);
     if (!s) s = upload_vec(ctx, d_cptr, g.cell_ptr, st);
     if (!s) s = upload_vec(ctx, d_ctri, g.cell_tri, st);
-    if (!s) s = dev_alloc(ctx, d_count, (size_t)nte * sizeof(int32_t));
-    if (!s) s = dev_alloc(ctx, d_def, (size_t)nte * sizeof(double));
-    if (!s) s = dev_alloc(ctx, d_ovf, sizeof(int32_t));
-    if (!s) s = dev_alloc(ctx, d_off, ((size_t)nte + 1) * sizeof(int64_t));
+    if (!s) s = dev_alloc(ctx, d_count, (size_t)nte * sizeof(int32_t), st);
+    if (!s) s = dev_alloc(ctx, d_def, (size_t)nte * sizeof(double), st);
+    if (!s) s = dev_alloc(ctx, d_ovf, sizeof(int32_t), st);
+    if (!s) s = dev_alloc(ctx, d_off, ((size_t)nte + 1) * sizeof(int64_t), st);
     if (s) return s;
     MortarDevArgs A;
     A.xi = mi->d.xyz.as<double>();
@@ -272,8 +272,8 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     HVec<int32_t> ti(ncon), te(ncon);
     if (ncon > 0) {
         s = upload_vec(ctx, d_off, off, st);
-        if (!s) s = dev_alloc(ctx, d_ti, (size_t)ncon * sizeof(int32_t));
-        if (!s) s = dev_alloc(ctx, d_blk, (size_t)ncon * 9 * sizeof(double));
+        if (!s) s = dev_alloc(ctx, d_ti, (size_t)ncon * sizeof(int32_t), st);
+        if (!s) s = dev_alloc(ctx, d_blk, (size_t)ncon * 9 * sizeof(double), st);
         if (s) return s;
         {
             KTimer kt(ctx, K_MORTAR);
@@ -308,7 +308,7 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     s = upload_vec(ctx, d_te, te, st);
     if (!s) s = upload_vec(ctx, d_tptr, tptr, st);
     if (!s) s = upload_vec(ctx, d_tcon, tcon, st);
-    if (!s) s = dev_alloc(ctx, d_rcnt, (size_t)nvi * sizeof(int32_t));
+    if (!s) s = dev_alloc(ctx, d_rcnt, (size_t)nvi * sizeof(int32_t), st);
     if (s) return s;
     const double *blk_dev = ncon > 0 ? d_blk.as<double>() : nullptr;
     const dim3 rgrid((unsigned)((nvi + kRowBlock - 1) / kRowBlock));
@@ -337,8 +337,8 @@ bem_status mortar_csr_device(bem_ctx *ctx, const bem_mesh *mi, const bem_mesh *m
     const int64_t nnz = rptr[nvi];
     if (nnz > INT32_MAX) return set_error(BEM_E_UNSUPPORTED, "too many mortar nonzeros");
     s = upload_vec(ctx, d_rptr, rptr, st);
-    if (!s) s = dev_alloc(ctx, d_col, std::max<int64_t>(1, nnz) * sizeof(int32_t));
-    if (!s) s = dev_alloc(ctx, d_val, std::max<int64_t>(1, nnz) * sizeof(double));
+    if (!s) s = dev_alloc(ctx, d_col, std::max<int64_t>(1, nnz) * sizeof(int32_t), st);
+    if (!s) s = dev_alloc(ctx, d_val, std::max<int64_t>(1, nnz) * sizeof(double), st);
     if (s) return s;
     {
         KTimer kt(ctx, K_MORTAR);

@@ -390,7 +390,7 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh, hipStream_t st)
     if (nv > 16 * 1024) return set_error(BEM_E_UNSUPPORTED, "mass inverse: more than 16384 vertices on one mesh");
     const bool f32 = p->prec == BEM_C64_MIXED;
     const size_t bytes = (size_t)nv * minv_ld(nv, f32) * (f32 ? sizeof(float) : sizeof(double));
-    bem_status s = dev_alloc(p->ctx, p->Minv[mesh], bytes);
+    bem_status s = dev_alloc(p->ctx, p->Minv[mesh], bytes, st);
     if (s) return s;
     // padding columns must read as zero (vector loads cover them)
     BEM_HIP(hipMemsetAsync(p->Minv[mesh].ptr, 0, bytes, st));
@@ -411,8 +411,8 @@ bem_status launch_mass_inverse(bem_problem *p, int mesh, hipStream_t st)
             }
             for (; q < W; ++q) ec[(size_t)q * nv + i] = i;
         }
-        s = dev_alloc(p->ctx, p->M_ell_col[mesh], ec.size() * sizeof(int32_t));
-        if (!s) s = dev_alloc(p->ctx, p->M_ell_val[mesh], ev.size() * sizeof(double));
+        s = dev_alloc(p->ctx, p->M_ell_col[mesh], ec.size() * sizeof(int32_t), st);
+        if (!s) s = dev_alloc(p->ctx, p->M_ell_val[mesh], ev.size() * sizeof(double), st);
         if (s) return s;
         BEM_HIP(hipMemcpyAsync(p->M_ell_col[mesh].ptr, ec.data(), ec.size() * sizeof(int32_t), hipMemcpyHostToDevice,
                                st));
@@ -911,6 +911,133 @@ __global__ __launch_bounds__(256) void mass_combine_kernel(int ne, int ni, const
     double2 *za = ext ? z : z + 2 * ne;
     za[i] = make_double2(ar, ai);
     za[i + nv] = make_double2(br, bi);
+}
+
+// ---- sparse inverse-mass apply: Chebyshev iteration on diag(M)^-1 M, whose
+// spectrum lies in [1/2, 2] on every P1 mesh (error 4 3^-k after k steps),
+// s steps per launch on the overlapping patches of ChebTables: a workgroup
+// loads its patch's iterate x, residual r and direction d (from y in the
+// first launch), keeps x, r and its rows of M (ELL, up to W entries) in
+// registers and d in LDS, and at step t updates the vertices within s - t
+// edges of its owned range, which read only vertices updated at step t - 1.
+// The owned range's state goes to the other work set (launches alternate
+// between two, so that no patch reads what another writes in the same
+// launch), and in the last launch x goes to z.  Fixed summation order:
+// deterministic.
+struct ChebArgs {
+    const int32_t *pmesh, *vbeg, *cnt, *vert;
+    const uint16_t *ecol;
+    const double *dinv, *eval;
+    int s, w;           // steps per launch, ELL width
+    int nvm[2];         // vertices of each mesh
+    int64_t base[2];    // offset of each mesh's first vector in y, z and the work vectors
+    int64_t wn;         // length of one work vector
+};
+
+constexpr double CHEB_THETA = 1.25, CHEB_DELTA = 0.75;   // centre and half-width of [1/2, 2]
+
+template <int RPT, int W>
+__global__ __launch_bounds__(1024) void mass_cheb_kernel(ChebArgs A, int part0, int first, int last, int nsteps,
+                                                          double rho0, const double2 *__restrict__ y, int64_t ystride,
+                                                          double2 *__restrict__ z, int64_t zstride,
+                                                          const double2 *__restrict__ win, double2 *__restrict__ wout,
+                                                          int64_t wstride, const KrylovState *__restrict__ st)
+{
+    __shared__ double2 dsh[CHEB_LMAX];
+    const int run = blockIdx.z;
+    if (st && st[run].done) return;
+    const int p = part0 + (int)blockIdx.x, vec = blockIdx.y;
+    const int m = A.pmesh[p];
+    const int64_t off = A.base[m] + (int64_t)vec * A.nvm[m];
+    const int vb = A.vbeg[p], L = A.vbeg[p + 1] - vb;
+    const int32_t *cnt = A.cnt + (int64_t)p * (A.s + 1);
+    const int rows = cnt[A.s - 1];   // rows with entries: within s - 1 edges
+    const uint16_t *ec = A.ecol + (int64_t)A.w * vb;
+    const double *ev = A.eval + (int64_t)A.w * vb;
+    const double2 *Xi = win + run * wstride, *Ri = Xi + A.wn, *Di = Ri + A.wn;
+    const double2 *yr = y + run * ystride;
+    const int tid = threadIdx.x;
+    double xr[RPT], xi[RPT], rr[RPT], ri[RPT], dr[RPT], di[RPT], dg[RPT];
+    int cc[RPT][W];
+    double vv[RPT][W];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int l = tid + 1024 * k;
+        xr[k] = xi[k] = rr[k] = ri[k] = dr[k] = di[k] = dg[k] = 0.0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+            const bool has = l < rows && q < A.w;
+            cc[k][q] = has ? (int)ec[(int64_t)q * L + l] : 0;
+            vv[k][q] = has ? ev[(int64_t)q * L + l] : 0.0;
+        }
+        if (l < L) {
+            const int64_t g = off + A.vert[vb + l];
+            dg[k] = A.dinv[vb + l];
+            if (first) {
+                const double2 yy = yr[g];
+                rr[k] = yy.x;
+                ri[k] = yy.y;
+                dr[k] = dg[k] * yy.x / CHEB_THETA;
+                di[k] = dg[k] * yy.y / CHEB_THETA;
+            } else {
+                const double2 a = Xi[g], b = Ri[g], c = Di[g];
+                xr[k] = a.x; xi[k] = a.y; rr[k] = b.x; ri[k] = b.y; dr[k] = c.x; di[k] = c.y;
+            }
+            dsh[l] = make_double2(dr[k], di[k]);
+        }
+    }
+    const double sigma1 = CHEB_THETA / CHEB_DELTA;
+    double rho = rho0;
+    __syncthreads();
+    for (int t = 1; t <= nsteps; ++t) {
+        const int act = cnt[A.s - t];
+        double ar[RPT], ai[RPT];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            ar[k] = ai[k] = 0.0;
+            if (tid + 1024 * k < act)
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const double2 dd = dsh[cc[k][q]];
+                    ar[k] += vv[k][q] * dd.x;
+                    ai[k] += vv[k][q] * dd.y;
+                }
+        }
+        __syncthreads();
+        const double rho_new = 1.0 / (2.0 * sigma1 - rho);
+        const double c1 = rho_new * rho, c2 = 2.0 * rho_new / CHEB_DELTA;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+            const int l = tid + 1024 * k;
+            if (l < act) {
+                xr[k] += dr[k];
+                xi[k] += di[k];
+                rr[k] -= ar[k];
+                ri[k] -= ai[k];
+                dr[k] = c1 * dr[k] + c2 * dg[k] * rr[k];
+                di[k] = c1 * di[k] + c2 * dg[k] * ri[k];
+                dsh[l] = make_double2(dr[k], di[k]);
+            }
+        }
+        rho = rho_new;
+        __syncthreads();
+    }
+    const int own = cnt[0];
+    double2 *Xo = wout + run * wstride, *Ro = Xo + A.wn, *Do = Ro + A.wn;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int l = tid + 1024 * k;
+        if (l < own) {
+            const int64_t g = off + A.vert[vb + l];
+            if (last) {
+                z[run * zstride + g] = make_double2(xr[k], xi[k]);
+            } else {
+                Xo[g] = make_double2(xr[k], xi[k]);
+                Ro[g] = make_double2(rr[k], ri[k]);
+                Do[g] = make_double2(dr[k], di[k]);
+            }
+        }
+    }
 }
 
 static inline dim3 split_grid(int ne, int ni, int cwmax, int rw = 1)
@@ -1493,6 +1620,7 @@ struct Work {
 // Buffers of the multi-RHS products (one set per solve or batched mat-vec).
 struct BlockBufs {
     DevMem btv[2], btw[2], cop, btm[2], cm;
+    DevMem chw;    // sparse inverse-mass apply: two sets of (x, r, d) per run
     int64_t cop_off[2][4], cm_off[2];
 };
 
@@ -1524,7 +1652,72 @@ size_t split_part_bytes(int ne, int ni)
 {
     const int nchunk = std::max({split_nchunk(ne, MASS_CW_MAX), split_nchunk(ni, MASS_CW_MAX), sym_ntile(ne, sym_tile<double2>()),
                                  sym_ntile(ni, sym_tile<double2>())});
-    return (size_t)nchunk * (ne + ni) * sizeof(double4);
+    // the sparse inverse-mass apply of one run uses the same buffer for its two work sets (6 n complex)
+    return std::max((size_t)nchunk * (ne + ni) * sizeof(double4), (size_t)6 * (2 * ne + 2 * ni) * sizeof(double2));
+}
+
+int cheb_steps(const bem_problem *p) { return p->prec == BEM_C128 ? 36 : 24; }
+
+template <int RPT, int W>
+void launch_cheb(const bem_problem *p, dim3 grid, hipStream_t st, const ChebArgs &A, int part0, int first, int last,
+                 int nsteps, double rho, const double2 *y, int64_t ystride, double2 *z, int64_t zstride,
+                 const double2 *win, double2 *wout, int64_t wstride, const KrylovState *kst)
+{
+    KTimer kt(p->ctx, K_MASS_APPLY);
+    launch_k(kt, mass_cheb_kernel<RPT, W>, grid, dim3(1024), 0, st, A, part0, first, last, nsteps, rho, y, ystride, z,
+             zstride, win, wout, wstride, kst);
+}
+
+// z = M^-1 y by the sparse Chebyshev apply on the patches [part0, part0 + np)
+// for R runs.  Mesh m's two vectors start at base[m] in y, z and the work
+// vectors (length wn); work holds two sets of (x, r, d), 6 wn complex per
+// run, wstride apart.
+bem_status cheb_apply(const bem_problem *p, int part0, int np, int64_t base0, int64_t base1, int64_t wn,
+                      const double2 *y, int64_t ystride, double2 *z, int64_t zstride, double2 *work, int64_t wstride,
+                      int R, const KrylovState *kst)
+{
+    const ChebTables &T = p->cheb;
+    ChebArgs A;
+    A.pmesh = p->cheb_pmesh.as<int32_t>();
+    A.vbeg = p->cheb_vbeg.as<int32_t>();
+    A.cnt = p->cheb_cnt.as<int32_t>();
+    A.vert = p->cheb_vert.as<int32_t>();
+    A.ecol = p->cheb_ecol.as<uint16_t>();
+    A.dinv = p->cheb_dinv.as<double>();
+    A.eval = p->cheb_eval.as<double>();
+    A.s = T.s;
+    A.w = T.ell_w;
+    A.nvm[0] = (int)p->ext->h.nv;
+    A.nvm[1] = (int)p->inte->h.nv;
+    A.base[0] = base0;
+    A.base[1] = base1;
+    A.wn = wn;
+    const int K = cheb_steps(p), nl = (K + T.s - 1) / T.s;
+    const double sigma1 = CHEB_THETA / CHEB_DELTA;
+    double rho = 1.0 / sigma1;
+    const int rpt = (T.lmax + 1023) / 1024;
+    const dim3 grid(np, 2, R);
+    hipStream_t st = p->ctx->stream;
+    for (int j = 0; j < nl; ++j) {
+        const int steps = std::min(T.s, K - j * T.s);
+        const double2 *win = work + (j % 2) * 3 * wn;
+        double2 *wout = work + ((j + 1) % 2) * 3 * wn;
+        const int first = j == 0, last = j == nl - 1;
+#define CHEB_ARGS p, grid, st, A, part0, first, last, steps, rho, y, ystride, z, zstride, win, wout, wstride, kst
+        if (rpt <= 1) {
+            if (T.ell_w <= 8) launch_cheb<1, 8>(CHEB_ARGS);
+            else if (T.ell_w <= 12) launch_cheb<1, 12>(CHEB_ARGS);
+            else launch_cheb<1, 16>(CHEB_ARGS);
+        } else {
+            if (T.ell_w <= 8) launch_cheb<2, 8>(CHEB_ARGS);
+            else if (T.ell_w <= 12) launch_cheb<2, 12>(CHEB_ARGS);
+            else launch_cheb<2, 16>(CHEB_ARGS);
+        }
+#undef CHEB_ARGS
+        BEM_HIP(hipGetLastError());
+        for (int t = 0; t < steps; ++t) rho = 1.0 / (2.0 * sigma1 - rho);
+    }
+    return BEM_OK;
 }
 
 // z = blockdiag(M_e, M_e, M_i, M_i)^-1 y
@@ -1532,6 +1725,11 @@ bem_status apply_Minv(const bem_problem *p, const double2 *y, double2 *z, double
 {
     hipStream_t st = p->ctx->stream;
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
+    if (p->mass_sparse) {
+        const int64_t n = 2 * ne + 2 * ni;
+        return cheb_apply(p, 0, p->cheb.nparts[0] + p->cheb.nparts[1], 0, 2 * ne, n, y, 0, z, 0,
+                          reinterpret_cast<double2 *>(part), 6 * n, 1, kst);
+    }
     {
         KTimer kt(p->ctx, K_MASS_APPLY);
         if (p->prec == BEM_C128)
@@ -1632,6 +1830,11 @@ bem_status apply_Minv_mesh(const bem_problem *p, int mesh, const double2 *y, dou
 {
     hipStream_t st = p->ctx->stream;
     const int ne = mesh == 0 ? (int)p->ext->h.nv : 0, ni = mesh == 1 ? (int)p->inte->h.nv : 0;
+    if (p->mass_sparse) {   // y, z: this mesh's two vectors
+        const int64_t wn = 2 * (int64_t)(ne + ni);
+        return cheb_apply(p, mesh == 0 ? 0 : p->cheb.nparts[0], p->cheb.nparts[mesh], 0, 0, wn, y, 0, z, 0,
+                          reinterpret_cast<double2 *>(part), 6 * wn, 1, kst);
+    }
     {
         KTimer kt(p->ctx, K_MASS_APPLY);
         launch_k(kt, mass_apply_part_kernel<double, MASS_RW64>, split_grid(ne, ni, MASS_CW_MAX, MASS_RW64), dim3(256),
@@ -1881,6 +2084,8 @@ bem_status block_alloc(bem_problem *p, BlockBufs &bb)
     }
     bem_status s = dev_alloc(ctx, bb.cop, cop * sizeof(float));
     if (!s) s = dev_alloc(ctx, bb.cm, cm * sizeof(float));
+    if (!s && p->mass_sparse)
+        s = dev_alloc(ctx, bb.chw, (size_t)6 * BLOCK_RHS * (2 * nv[0] + 2 * nv[1]) * sizeof(double2));
     return s;
 }
 
@@ -2002,7 +2207,7 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
     const int nv[2] = {A.ne, A.ni};
     int nk_ops = 0, nk_mass = 0;   // (tuning, at first use, zeroes the right-hand buffers: before packing)
     bem_status s = block_tune(p, bb, 0, R, nk_ops);
-    if (!s && strong) s = block_tune(p, bb, 1, R, nk_mass);
+    if (!s && strong && !p->mass_sparse) s = block_tune(p, bb, 1, R, nk_mass);
     if (s) return s;
     for (int m = 0; m < 2; ++m) {
         const int kop = 2 * (int)op_ld(nv[m]);
@@ -2022,6 +2227,11 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
                        Y, ystride, kst);
     BEM_HIP(hipGetLastError());
     if (!strong) return BEM_OK;
+    if (p->mass_sparse) {
+        const int64_t n = 2 * A.ne + 2 * A.ni;
+        return cheb_apply(p, 0, p->cheb.nparts[0] + p->cheb.nparts[1], 0, 2 * A.ne, n, Y, ystride, Z, zstride,
+                          bb.chw.as<double2>(), 6 * n, R, kst);
+    }
     for (int m = 0; m < 2; ++m) {
         const int km = minv_ld(nv[m], true);
         hipLaunchKernelGGL(pack_mass_kernel, dim3((km + 255) / 256, 4 * BLOCK_RHS), dim3(256), 0, st, nv[m], km, R,

@@ -102,7 +102,7 @@ def test_c3_vs_golden(ctx, prec):
     _same_inputs(c, dirs, meta)
     ne, ni = meta["n_ext"], meta["n_int"]
     p, me, mi = _problem(ctx, c, prec)
-    out, st, code = p.solve(dirs, tol=TIGHT, maxit=4000)
+    out, st, code = p.solve(dirs, tol=TIGHT, maxit=3000)
     assert code == B.OK, st
     tag = "C3 FP64" if prec == B.C128 else "C3 mixed"
     print(f"{tag} at {TIGHT:g}: {st['iterations']} steps, IR {st['ir_steps']}")
