@@ -643,7 +643,8 @@ def main():
     entries = 4 * ne * ne + 4 * ni * ni
     torch.cuda.init()
     ctx = B.Context(0)
-    timed = ("regular_tiles", "mtf_dense", "mass_apply")
+    timed = ("regular_tiles", "gather_tiles", "singular_pairs", "mtf_dense", "mass_apply", "cgs_dots", "cgs_update",
+             "arnoldi_finish", "krylov_normalize")
     r = run_workload(ctx, B, c, B.C128, tol, args.steps, args.warmup, timed)
     head = summarise(c, r, args.steps, B.C128, tol, name)
     ktimes = r["ktimes"]

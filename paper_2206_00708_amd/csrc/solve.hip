@@ -1074,7 +1074,7 @@ static inline dim3 split_grid(int ne, int ni, int cwmax, int rw = 1)
 // every kernel returns at once when the state says the run has converged, so
 // steps issued ahead of the host's convergence check cost only their launch.
 
-constexpr int CGS_CHUNK = 1024;   // rows per partial dot product
+constexpr int CGS_CHUNK = 4096;   // rows per partial dot product (few partials: a short fixed-order sum)
 constexpr int UPD_ROWS = 64;      // rows per workgroup of the update sweep
 constexpr int MAXIT_CAP = 3000;   // Hessenberg column, rotations and g staged in LDS
 
@@ -1097,6 +1097,7 @@ __global__ __launch_bounds__(256) void dgs_dots_kernel(int n, int j, const doubl
     const int r0 = blockIdx.x * CGS_CHUNK, r1 = min(n, r0 + CGS_CHUNK);
     const double2 *vc = Vb + (int64_t)c * n, *u = Vb + (int64_t)j * n;
     double ur = 0, ui = 0, wr = 0, wi = 0;
+#pragma unroll 4
     for (int r = r0 + lane; r < r1; r += 64) {
         const double2 a = vc[r], x = u[r], y = w[r];
         ur += a.x * x.x + a.y * x.y;
@@ -1146,6 +1147,7 @@ __global__ __launch_bounds__(256) void dgs_hess_kernel(int j, int m, int nchunk,
     const int tid = threadIdx.x, nk = 2 * (j + 1);
     for (int k = tid; k < nk; k += 256) {
         double2 sum = make_double2(0, 0);
+#pragma unroll 8
         for (int c = 0; c < nchunk; ++c) sum = cadd(sum, partial[(int64_t)c * nk + k]);
         coef[k] = sum;
     }
@@ -1304,6 +1306,7 @@ __global__ __launch_bounds__(256) void dgs_update_kernel(int n, int j, int m, in
     const bool live = row < n;
     double ur = 0, ui = 0, wr = 0, wi = 0;
     if (live)
+#pragma unroll 4
         for (int c = wave; c < j; c += 4) {
             const double2 v = Vb[(int64_t)c * n + row], a = coef[c], b = coef[j + 1 + c];
             ur += v.x * a.x - v.y * a.y;
