@@ -425,7 +425,7 @@ def field_run(ctx, B, synth, np, reps=5):
     """Field evaluation on the C2 body: the traces of one solve, then the
     total field on a 100 x 100 grid of the plane z = 0 over [-2, 2]^2 (the
     paper's accuracy grid, 100 x 100 points over the body and a margin of
-    half its size, Sec. 6.2), regions from the exterior mesh's winding
+    half its size, Sec. 5.3), regions from the exterior mesh's winding
     number.  Reports the field call's wall time, the field kernel's device
     time (HIP events) and its FP64 rate by the operation count above."""
     import torch
@@ -556,7 +556,7 @@ def mortar_run(ctx, B, synth, np):
 
 
 def incident_run(ctx, B, synth, np):
-    """The C2 workload with the foam model's variations (Sec. 6.4) beside the
+    """The C2 workload with the foam model's variations (Sec. 5.7) beside the
     lossless plane wave: an absorbing interior (k_int + 0.5 i, the
     complex-wavenumber instantiation of the regular assembly) and a point
     source at (0, 0, 3): regular-assembly kernel time, GMRES steps and solve

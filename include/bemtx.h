@@ -147,7 +147,11 @@ bem_status bem_ctx_kernel_time(bem_ctx *ctx, const char *kernel, double *total_m
  * consistently oriented 2-manifold with positive enclosed volume, no
  * degenerate triangle and no unused vertex (BEM_E_MESH otherwise), and builds
  * the connectivity tables (adjacent-pair classes, locality blocks).  xyz and
- * tri are host arrays, copied. */
+ * tri are host arrays, copied.  Limits: at most 2^30 vertices and
+ * triangles (BEM_E_ARG); a vertex may be a corner of at most 12 of the 16
+ * triangles of one locality block (consecutive triangles in Morton order of
+ * their centroids; a valence above 12 can exceed it) and, for the sparse
+ * inverse-mass apply, have at most 15 neighbours (BEM_E_MESH otherwise). */
 bem_status bem_mesh_create(bem_ctx *ctx, const double *xyz, int64_t nv, const int32_t *tri, int64_t nt,
                            bem_mesh **out);
 void bem_mesh_destroy(bem_mesh *mesh);
@@ -263,12 +267,12 @@ bem_status bem_mtf_matvec_batch(bem_problem *p, const void *x, void *y, int32_t 
 /* Incident field of the problem's solves, right-hand sides and fields:
  * kind 0 (the default) plane waves exp(i k_ext d.x) (Sec. 5.3), whose `dirs`
  * arguments are unit directions; kind 1 point sources
- * exp(i k_ext |x - x0|) / (4 pi |x - x0|) (Sec. 6.4), whose `dirs` arguments
+ * exp(i k_ext |x - x0|) / (4 pi |x - x0|) (Sec. 5.7), whose `dirs` arguments
  * are the source positions x0 (finite; a source on or near the exterior
  * mesh makes the loads' quadrature inaccurate).  BEM_E_ARG for another kind. */
 bem_status bem_problem_set_incident(bem_problem *p, int32_t kind);
 
-/* Absorbing interior (the foam model of Sec. 6.4, whose interior wavenumber
+/* Absorbing interior (the foam model of Sec. 5.7, whose interior wavenumber
  * carries an imaginary part that grows with frequency): the interior
  * wavenumber becomes k_int + i k_int_imag, so that the interior Green's
  * function is exp(i k_int r - k_int_imag r) / (4 pi r) in the assembly of the
@@ -312,7 +316,7 @@ bem_status bem_solve(bem_problem *p, const double *dirs, int32_t nrhs, const bem
  * exterior mesh, [-K_e - hat(K_i), V_e + a hat(V_i); D_e + hat(D_i) / a,
  * T_e + hat(T_i)] [v; w] = [f; g] with hat(X) = P_ext,int M_int^-1 X
  * M_int^-1 P_int,ext and a = rho_int / rho_ext (the interior operators
- * scaled as in the single-trace Calderon system, Sec. 2.3), f, g as in
+ * scaled as in the single-trace Calderon system, Sec. 2.2), f, g as in
  * bem_mtf_rhs.  The unknowns are the traces of the total field on the
  * exterior mesh: v = p, w = dp/dn+.  Uses the operators and projection of
  * the problem (assemble both first; BEM_E_STATE otherwise).
@@ -329,7 +333,7 @@ bem_status bem_solve_pmchwt(bem_problem *p, const double *dirs, int32_t nrhs, co
                             void *traces, bem_memspace space, bem_stats *stats);
 bem_status bem_pmchwt_matvec(bem_problem *p, const void *x, void *y, int32_t strong, bem_memspace space);
 
-/* Exterior high-contrast Neumann formulation (Sec. 2.4, Eq.
+/* Exterior high-contrast Neumann formulation (Sec. 2.3, Eq.
  * "highcontrast:ext:neu", discrete form of Sec. 3.3): on the exterior mesh,
  *   [1/2 M_e - hat(T_i), -c hat(D_i) M_e^-1 V_e; M_e, 1/2 M_e - T_e] [a; b]
  *     = [c hat(D_i) M_e^-1 f; g],  c = rho_ext / rho_int,

@@ -14,7 +14,7 @@ primitives and no blocking or reordering:
   plane_wave_rhs(...)     f_j = <u_inc, phi_j>, g_j = <d_n u_inc, phi_j>
                           with u_inc = exp(i k d.x)  (plane wave, Sec. 5.3)
   point_source_rhs(...)   the same for u_inc = exp(i k r) / (4 pi r),
-                          r = |x - x0|  (point source, Sec. 6.4)
+                          r = |x - x0|  (point source, Sec. 5.7)
   mtf_system(...)         the discrete multiple-traces system as printed in
                           Sec. 3.3, with right-hand side [-f, -g, 0, 0]
   solve_mtf(...)          x = A^{-1} b by dense LU: GMRES on the mass-
@@ -26,7 +26,7 @@ primitives and no blocking or reordering:
                           place (no second copy of the matrix)
   pmchwt_system(...)      the exterior PMCHWT matrix as printed in Sec. 3.3,
                           interior operators scaled as in the single-trace
-                          Calderon system of Sec. 2.3
+                          Calderon system of Sec. 2.2
   solve_pmchwt(...)       its exact discrete solution by dense LU
   high_contrast_neumann_system(...), solve_high_contrast_neumann(...)
                           the exterior high-contrast Neumann formulation
@@ -179,7 +179,7 @@ def plane_wave_rhs(xyz, tri, k, d):
 
 def point_source_rhs(xyz, tri, k, x0):
     """f_j = <u_inc, phi_j>, g_j = <d_n u_inc, phi_j> for the point source
-    u_inc(x) = exp(i k |x - x0|) / (4 pi |x - x0|) (Sec. 6.4), with
+    u_inc(x) = exp(i k |x - x0|) / (4 pi |x - x0|) (Sec. 5.7), with
     d_n u_inc = exp(i k r)(i k r - 1)((x - x0).n) / (4 pi r^3); every
     triangle by the 6-point rule (area times the weights)."""
     xyz, tri = _mesh(xyz, tri)

@@ -152,7 +152,7 @@ def test_field_of_transparent_body(orc):
 
 
 def test_absorbing_interior_field_converges_to_mie(orc):
-    """Absorbing interior (k_int = 3 + 0.6 i, Sec. 6.4): the field off the
+    """Absorbing interior (k_int = 3 + 0.6 i, Sec. 5.7): the field off the
     surface converges at O(h^2) to the penetrable-sphere series evaluated with
     the complex wavenumber, inside (where the interior potentials carry
     exp(i k r) with the complex k) and outside."""

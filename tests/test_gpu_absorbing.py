@@ -1,4 +1,4 @@
-"""Absorbing interior (the foam model of Sec. 6.4: a complex interior
+"""Absorbing interior (the foam model of Sec. 5.7: a complex interior
 wavenumber k_int + i k_im) through the C ABI against the oracle, which
 evaluates exp(i k r) / (4 pi r) with the complex k itself: interior operators
 to 1e-12 (FP64) and to the complex64 bounds of the mixed path, the exterior

@@ -1,4 +1,4 @@
-"""Point-source incident field (Sec. 6.4) through the C ABI against the
+"""Point-source incident field (Sec. 5.7) through the C ABI against the
 oracle: loads to 1e-13 (as the plane-wave loads), the solve against the
 oracle's LU solution to 1e-5, the field to 1e-11, and argument checks."""
 import numpy as np

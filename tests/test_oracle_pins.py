@@ -542,7 +542,7 @@ def test_point_source_transparent_body(orc):
 
 def test_complex_interior_wavenumber_mie(orc):
     """An absorbing interior (k_int = 3 + 0.6 i, the power-law attenuation of
-    the foam model, Sec. 6.4): the discrete MTF solution converges at O(h^2)
+    the foam model, Sec. 5.7): the discrete MTF solution converges at O(h^2)
     to the penetrable-sphere series with the complex wavenumber, on
     conforming and nonconforming grids."""
     ke, ki, re, ri = 2.0, 3.0 + 0.6j, 1.0, 1.5
