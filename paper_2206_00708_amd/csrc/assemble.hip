@@ -60,6 +60,12 @@ __global__ void geometry_kernel(const double *__restrict__ xyz, const int32_t *_
     for (int q = 0; q < 6; ++q)
         for (int c = 0; c < 3; ++c)
             g.qp[q][c] = r6_bary(q, 0) * g.p[0][c] + r6_bary(q, 1) * g.p[1][c] + r6_bary(q, 2) * g.p[2][c];
+    for (int c = 0; c < 3; ++c) g.c[c] = (g.p[0][c] + g.p[1][c] + g.p[2][c]) / 3.0;
+    g.rho = 0.0;
+    for (int q = 0; q < 6; ++q) {
+        const double e[3] = {g.qp[q][0] - g.c[0], g.qp[q][1] - g.c[1], g.qp[q][2] - g.c[2]};
+        g.rho = fmax(g.rho, sqrt(dot3(e, e)));
+    }
     geo[t] = g;
     TriGeoF f;
     for (int c = 0; c < 3; ++c) f.c[c] = (g.p[0][c] + g.p[1][c] + g.p[2][c]) / 3.0;
@@ -151,6 +157,125 @@ __device__ inline void tile_slot_sums(int tid, int op, int ns1, int ns2, const u
         }
 }
 
+// sin and cos of a small angle t, |t| <= 1: Taylor polynomials of sin
+// through t^17 and of cos through t^18 (the first omitted terms are below
+// 1e-17 and 5e-19); the coefficients are 1/n!.
+__device__ inline void small_sincos(double t, double &s, double &c)
+{
+    const double z = t * t;
+    double ps = 2.8114572543455206e-15;            //  1/17!
+    ps = fma(ps, z, -7.647163731819816e-13);       // -1/15!
+    ps = fma(ps, z, 1.6059043836821613e-10);       //  1/13!
+    ps = fma(ps, z, -2.505210838544172e-08);       // -1/11!
+    ps = fma(ps, z, 2.7557319223985893e-06);       //  1/9!
+    ps = fma(ps, z, -0.0001984126984126984);       // -1/7!
+    ps = fma(ps, z, 0.008333333333333333);         //  1/5!
+    ps = fma(ps, z, -0.16666666666666666);         // -1/3!
+    s = fma(t * z, ps, t);
+    double pc = -1.5619206968586225e-16;           // -1/18!
+    pc = fma(pc, z, 4.779477332387385e-14);        //  1/16!
+    pc = fma(pc, z, -1.1470745597729725e-11);      // -1/14!
+    pc = fma(pc, z, 2.08767569878681e-09);         //  1/12!
+    pc = fma(pc, z, -2.755731922398589e-07);       // -1/10!
+    pc = fma(pc, z, 2.48015873015873e-05);         //  1/8!
+    pc = fma(pc, z, -0.001388888888888889);        // -1/6!
+    pc = fma(pc, z, 0.041666666666666664);         //  1/4!
+    pc = fma(pc, z, -0.5);                         // -1/2!
+    c = fma(z, pc, 1.0);
+}
+
+// 6 x 6 point pairs of one regular triangle pair (x on X, y on Y): the 3 x 3
+// element sums of V (kernel G), K (dG/dn_y), T (dG/dn_x) and the scalar sum
+// of G, unscaled (times area_X area_Y / (4 pi) later).  K uses that
+// (y - x).n_y is the same for every y on the plane of Y, so its factor is
+// applied once per test point.  BASE: phase from the per-pair base (see the
+// caller).  CK: complex wavenumber k + i kim.
+template <bool CK, bool BASE>
+__device__ inline void pair_quadrature(const TriGeo &X, const TriGeo &Y, double k, double kim, double (&vr)[9],
+                                       double (&vi)[9], double (&kr)[9], double (&ki)[9], double (&tr)[9],
+                                       double (&ti)[9], double &sr, double &si)
+{
+    const double nx0 = X.n[0], nx1 = X.n[1], nx2 = X.n[2];
+    const double ny0 = Y.n[0], ny1 = Y.n[1], ny2 = Y.n[2];
+    const double ey0 = ny0 * Y.p[0][0] + ny1 * Y.p[0][1] + ny2 * Y.p[0][2];   // n_y . (a vertex of Y)
+    double e0r = 1.0, e0i = 0.0, kr0 = 0.0;
+    if constexpr (BASE) {
+        const double c0 = X.c[0] - Y.c[0], c1 = X.c[1] - Y.c[1], c2 = X.c[2] - Y.c[2];
+        kr0 = k * sqrt(c0 * c0 + c1 * c1 + c2 * c2);
+        phase_sincos(kr0, &e0i, &e0r);
+    }
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+        const double x0 = X.qp[p][0], x1 = X.qp[p][1], x2 = X.qp[p][2];
+        const double dkp = ey0 - (ny0 * x0 + ny1 * x1 + ny2 * x2);   // (y - x).n_y
+        double hvr[3] = {0, 0, 0}, hvi[3] = {0, 0, 0}, hkr[3] = {0, 0, 0}, hki[3] = {0, 0, 0};
+        double htr[3] = {0, 0, 0}, hti[3] = {0, 0, 0}, hsr = 0.0, hsi = 0.0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double d0 = x0 - Y.qp[q][0], d1 = x1 - Y.qp[q][1], d2 = x2 - Y.qp[q][2];
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            const double rinv = rsqrt(r2);
+            const double r = r2 * rinv;
+            const double kr_ = k * r;
+            double sn, cs;
+            if constexpr (BASE) {
+                double sd, cd;
+                small_sincos(fma(k, r, -kr0), sd, cd);
+                cs = e0r * cd - e0i * sd;
+                sn = e0r * sd + e0i * cd;
+            } else {
+                phase_sincos(kr_, &sn, &cs);
+            }
+            double gr = cs * rinv, gi = sn * rinv;                 // exp(ikr)/r
+            const double rinv2 = rinv * rinv;
+            double fr, fi;                                         // exp(ikr)(ikr-1)/r^3
+            if constexpr (CK) {
+                const double dmp = exp(-kim * r), am = -1.0 - kim * r;
+                gr *= dmp; gi *= dmp;
+                fr = (gr * am - gi * kr_) * rinv2;
+                fi = (gr * kr_ + gi * am) * rinv2;
+            } else {
+                fr = (-gr - gi * kr_) * rinv2;
+                fi = (gr * kr_ - gi) * rinv2;
+            }
+            const double dt = d0 * nx0 + d1 * nx1 + d2 * nx2;     // (x-y).n_x
+            const double gtr = fr * dt, gti = fi * dt;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                const double W = r6_w(q) * r6_bary(q, b);
+                hvr[b] += W * gr; hvi[b] += W * gi;
+                hkr[b] += W * fr; hki[b] += W * fi;
+                htr[b] += W * gtr; hti[b] += W * gti;
+            }
+            hsr += r6_w(q) * gr;
+            hsi += r6_w(q) * gi;
+        }
+        const double wp = p < 3 ? kW1 : kW2;
+        const double ap = p < 3 ? kA1 : kA2;
+        const int pc = p < 3 ? p : p - 3;            // corner carrying 1 - 2a
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double W = wp * (a == pc ? 1.0 - 2.0 * ap : ap);
+            const double Wk = W * dkp;
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                vr[3 * a + b] += W * hvr[b]; vi[3 * a + b] += W * hvi[b];
+                kr[3 * a + b] += Wk * hkr[b]; ki[3 * a + b] += Wk * hki[b];
+                tr[3 * a + b] += W * htr[b]; ti[3 * a + b] += W * hti[b];
+            }
+        }
+        sr += wp * hsr;
+        si += wp * hsi;
+    }
+    const double scale = X.area * Y.area * kInv4Pi;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        vr[e] *= scale; vi[e] *= scale; kr[e] *= scale; ki[e] *= scale; tr[e] *= scale; ti[e] *= scale;
+    }
+    sr *= scale;
+    si *= scale;
+}
+
 struct TileArgsF {
     const TriGeoF *geof;
     const int32_t *tri;
@@ -215,70 +340,14 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
     if (active) {
         const TriGeo &X = gX[t1];
         const TriGeo &Y = gY[t2];
-        const double nx0 = X.n[0], nx1 = X.n[1], nx2 = X.n[2];
-        const double ny0 = Y.n[0], ny1 = Y.n[1], ny2 = Y.n[2];
-#pragma unroll 1
-        for (int p = 0; p < 6; ++p) {
-            const double x0 = X.qp[p][0], x1 = X.qp[p][1], x2 = X.qp[p][2];
-            double hvr[3] = {0, 0, 0}, hvi[3] = {0, 0, 0}, hkr[3] = {0, 0, 0}, hki[3] = {0, 0, 0};
-            double htr[3] = {0, 0, 0}, hti[3] = {0, 0, 0}, hsr = 0.0, hsi = 0.0;
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const double d0 = x0 - Y.qp[q][0], d1 = x1 - Y.qp[q][1], d2 = x2 - Y.qp[q][2];
-                const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-                const double rinv = rsqrt(r2);
-                const double r = r2 * rinv;
-                const double kr_ = k * r;
-                double sn, cs;
-                phase_sincos(kr_, &sn, &cs);
-                double gr = cs * rinv, gi = sn * rinv;                 // exp(ikr)/r
-                const double rinv2 = rinv * rinv;
-                double fr, fi;                                         // exp(ikr)(ikr-1)/r^3
-                if constexpr (CK) {
-                    const double dmp = exp(-A.kim * r), am = -1.0 - A.kim * r;
-                    gr *= dmp; gi *= dmp;
-                    fr = (gr * am - gi * kr_) * rinv2;
-                    fi = (gr * kr_ + gi * am) * rinv2;
-                } else {
-                    fr = (-gr - gi * kr_) * rinv2;
-                    fi = (gr * kr_ - gi) * rinv2;
-                }
-                const double dk = -(d0 * ny0 + d1 * ny1 + d2 * ny2);  // (y-x).n_y
-                const double dt = d0 * nx0 + d1 * nx1 + d2 * nx2;     // (x-y).n_x
-                const double gkr = fr * dk, gki = fi * dk, gtr = fr * dt, gti = fi * dt;
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    const double W = r6_w(q) * r6_bary(q, b);
-                    hvr[b] += W * gr; hvi[b] += W * gi;
-                    hkr[b] += W * gkr; hki[b] += W * gki;
-                    htr[b] += W * gtr; hti[b] += W * gti;
-                }
-                hsr += r6_w(q) * gr;
-                hsi += r6_w(q) * gi;
-            }
-            const double wp = p < 3 ? kW1 : kW2;
-            const double ap = p < 3 ? kA1 : kA2;
-            const int pc = p < 3 ? p : p - 3;            // corner carrying 1 - 2a
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double W = wp * (a == pc ? 1.0 - 2.0 * ap : ap);
-#pragma unroll
-                for (int b = 0; b < 3; ++b) {
-                    vr[3 * a + b] += W * hvr[b]; vi[3 * a + b] += W * hvi[b];
-                    kr[3 * a + b] += W * hkr[b]; ki[3 * a + b] += W * hki[b];
-                    tr[3 * a + b] += W * htr[b]; ti[3 * a + b] += W * hti[b];
-                }
-            }
-            sr += wp * hsr;
-            si += wp * hsi;
-        }
-        const double scale = X.area * Y.area * kInv4Pi;
-#pragma unroll
-        for (int e = 0; e < 9; ++e) {
-            vr[e] *= scale; vi[e] *= scale; kr[e] *= scale; ki[e] *= scale; tr[e] *= scale; ti[e] *= scale;
-        }
-        sr *= scale;
-        si *= scale;
+        // Phase by a per-pair base when k (rho_X + rho_Y) <= 1: with r0 the
+        // centroid distance, |k (r - r0)| <= 1 for every point pair, so
+        // exp(i k r) = exp(i k r0) exp(i k (r - r0)) takes one reduced
+        // sin/cos per pair and short polynomials per point pair.
+        if (!CK && k * (X.rho + Y.rho) <= 1.0)
+            pair_quadrature<CK, true>(X, Y, k, A.kim, vr, vi, kr, ki, tr, ti, sr, si);
+        else
+            pair_quadrature<CK, false>(X, Y, k, A.kim, vr, vi, kr, ki, tr, ti, sr, si);
     }
 
     // ---- per-slot reduction through LDS, one operator at a time

@@ -33,13 +33,15 @@ constexpr int NG_MAX = 16;
 // Padding columns hold zeros.
 __host__ __device__ inline int64_t op_ld(int64_t nv) { return (nv + 15) & ~int64_t(15); }
 
-// Per-triangle geometry table, built on the device (40 doubles, 320 B).
+// Per-triangle geometry table, built on the device (44 doubles, 352 B).
 struct alignas(16) TriGeo {
     double p[3][3];     // vertices in the triangle's own corner order
     double qp[6][3];    // points of the 6-point rule
     double n[3];        // unit normal (right-hand rule, outward)
     double area;
     double curl[3][3];  // surface curl of the P1 function of corner a
+    double c[3];        // centroid
+    double rho;         // largest distance from the centroid to a point of the 6-point rule
 };
 
 // Single-precision geometry for the mixed-precision regular kernel: the
