@@ -59,6 +59,24 @@ def test_operators_c1(c1, c1_oracle, mesh):
         assert _relmax(got, ref[op]) < 1e-12, op
 
 
+@pytest.mark.parametrize("k", [0.5, 4.0, 12.0])
+def test_operators_phase_paths(ctx, orc, k):
+    """The regular kernel evaluates exp(i k r) from a per-pair base phase when
+    k times the two triangles' quadrature radii is at most 1, and by the
+    reduced sin/cos otherwise: on the C1 exterior mesh (radius about 0.13)
+    k = 0.5 takes the first path for every pair, k = 12 the second, k = 4
+    mixes them.  Against the oracle at the FP64 operator tolerance."""
+    c = synth.make_config("C1")
+    me, mi = B.Mesh(ctx, *c["ext"]), B.Mesh(ctx, *c["int"])
+    p = B.Problem(ctx, me, mi, k, k, 1.0, 1.0)
+    p.assemble_operators()
+    ref = orc.assemble(*c["ext"], k)
+    for op in "VKTD":
+        got = p.operator(0, op).cpu().numpy()
+        assert _rel(got, ref[op]) < 1e-12, (k, op, _rel(got, ref[op]))
+        assert _relmax(got, ref[op]) < 1e-12, (k, op)
+
+
 @pytest.mark.parametrize("parts", [1, 2])
 def test_operator_parts_c1(ctx, orc, parts):
     """Regular-only and singular-only contributions separately."""
