@@ -337,7 +337,7 @@ def batching_compare(ctx, B, synth, np, tol=1e-7, sample=2):
     p, me, mi = setup(B.C64_MIXED)
     p.solve(dirs[:4], tol=tol, maxit=1500, batch=4)    # first use: picks the GEMM K split by timing
     torch.cuda.synchronize()
-    ctx.set_kernel_timing(("block_gemm", "mass_gemm"))
+    ctx.set_kernel_timing(("block_gemm", "mass_gemm", "mass_apply"))
     t0 = time.perf_counter()
     out, st, code = p.solve(dirs, tol=tol, maxit=1500, batch=64)
     blk = out.cpu().numpy()
@@ -345,6 +345,7 @@ def batching_compare(ctx, B, synth, np, tol=1e-7, sample=2):
     assert code == B.OK, st
     gms, gn = ctx.kernel_time("block_gemm")
     mms, mn = ctx.kernel_time("mass_gemm")
+    ams, an = ctx.kernel_time("mass_apply")
     ctx.set_kernel_timing(())
     flops = 2048.0 * (ne * ne + ni * ni)
     ach = flops / (gms / gn * 1e-3) / 1e12
@@ -354,7 +355,10 @@ def batching_compare(ctx, B, synth, np, tol=1e-7, sample=2):
     res["roofline"] = {"kernel": "block_gemm", "bound": "mfma", "achieved": round(ach, 1), "peak": FP32_MFMA_TFLOPS,
                        "unit": "TFLOP/s", "frac": round(ach / FP32_MFMA_TFLOPS, 4), "traffic": None,
                        "avg_launch_us": round(1e3 * gms / gn, 1), "flop_per_launch": flops,
-                       "mass_gemm_tflops": round(512.0 * (ne * ne + ni * ni) / (mms / mn * 1e-3) / 1e12, 1)}
+                       "inverse_mass": ({"form": "dense on the matrix cores",
+                                         "tflops": round(512.0 * (ne * ne + ni * ni) / (mms / mn * 1e-3) / 1e12, 1)}
+                                        if mn else {"form": "sparse Chebyshev", "ms_per_step": round(
+                                            ams / max(1, an) * 3, 3)})}
     t0 = time.perf_counter()
     seq, s1, c1 = p.solve(dirs[:sample], tol=tol, maxit=1500)
     seq = seq.cpu().numpy()
@@ -388,30 +392,49 @@ def batching_compare(ctx, B, synth, np, tol=1e-7, sample=2):
                                                    res["single_c64_mixed"]["solves_per_s"], 2)}
 
 
-def serving_run(B, synth, n_requests=24, slots=4, tol=1e-5, maxit=1000):
-    """The serving workload: the first `n_requests` of the seeded Poisson
-    stream (mean 20 requests/s; random ellipsoids with semi-axes in
-    [0.5, 1.5], exterior icosphere L3-L5, interior Fibonacci grid at 0.7-1.3
-    times the exterior node count, k_ext in [1, 15], k_int = k_ext x [1.2,
-    2.5], rho ratio 1.5, 1-16 plane waves) released at their arrival times
-    into a server with `slots` workers (mixed precision, all directions of a
-    request solved together, admission by device footprint).  Meshes are
-    generated before the clock starts (they are the requests' inputs)."""
+def serving_run(B, synth, n_requests=24, n_sustained=32, slots=4, tol=1e-5, maxit=1000):
+    """The serving workload: the seeded Poisson stream (random ellipsoids with
+    semi-axes in [0.5, 1.5], exterior icosphere L3-L5, interior Fibonacci grid
+    at 0.7-1.3 times the exterior node count, k_ext in [1, 15], k_int = k_ext
+    x [1.2, 2.5], rho ratio 1.5, 1-16 plane waves) through a server with
+    `slots` workers (mixed precision, all directions of a request solved
+    together, admission by device footprint with bounded out-of-order entry).
+    Two runs: the first `n_requests` released at the stream's own rate (mean
+    20 per second, far above what one device completes, so latency is
+    mostly queueing), and the first `n_sustained` at 70 % of the request rate
+    the first run completed (arrival times of the same stream, scaled), where
+    latency is mostly service.  solves/s counts only directions of requests
+    that converged.  Meshes are generated before the clock starts (they are
+    the requests' inputs)."""
     from paper_2206_00708_amd import serve
-    qs = synth.serving_stream()[:n_requests]
+    qs = synth.serving_stream()[:max(n_requests, n_sustained)]
     reqs = []
     for i, q in enumerate(qs):
         ext, inte = synth.request_meshes(q)
         reqs.append(serve.Request(i, q["t_arrival"], ext, inte, q["k_ext"], q["k_int"], q["rho_ext"], q["rho_int"],
                                   synth.request_directions(q)))
-    srv = serve.Server(slots=slots, tol=tol, maxit=maxit)
-    res, summ = srv.run(reqs, realtime=True)
-    srv.close()
-    iters = [r.stats["iterations"] for r in res.values() if r.stats]
-    summ["workload"] = (f"seeded Poisson stream, first {n_requests} requests (mean 20 req/s), random ellipsoids, "
-                        f"ext L3-L5, complex64 + FP64 refinement, tol {tol:g}, maxit {maxit}")
-    summ["iterations_median"] = int(statistics.median(iters)) if iters else 0
-    return summ
+
+    def run(rs):
+        srv = serve.Server(slots=slots, tol=tol, maxit=maxit)
+        res, summ = srv.run(rs, realtime=True)
+        srv.close()
+        iters = [r.stats["iterations"] for r in res.values() if r.stats]
+        summ["iterations_median"] = int(statistics.median(iters)) if iters else 0
+        return summ
+
+    out = {"workload": f"seeded Poisson stream of random ellipsoids, ext L3-L5, complex64 + FP64 refinement, "
+                       f"tol {tol:g}, maxit {maxit}, {slots} workers"}
+    s1 = run(reqs[:n_requests])
+    s1["offered_req_per_s"] = 20.0
+    out["stated_rate"] = s1
+    cap = max(s1["completed"] / s1["makespan_s"], 1e-3)
+    scale = n_sustained / (0.7 * cap * qs[n_sustained - 1]["t_arrival"])   # stretch of the arrival times
+    rs = [serve.Request(r.id, r.t_arrival * scale, r.ext, r.inte, r.k_ext, r.k_int, r.rho_ext, r.rho_int, r.dirs)
+          for r in reqs[:n_sustained]]
+    s2 = run(rs)
+    s2["offered_req_per_s"] = round(n_sustained / (qs[n_sustained - 1]["t_arrival"] * scale), 3)
+    out["sustained"] = s2
+    return out
 
 
 # FP64 operations per quadrature-point evaluation of the field kernel (FMA =
