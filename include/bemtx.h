@@ -379,6 +379,19 @@ bem_status bem_field(bem_problem *p, const double *dirs, int32_t nrhs, const voi
  * BEM_E_OOM, BEM_E_DEVICE. */
 bem_status bem_mesh_winding(const bem_mesh *m, const double *points, int64_t npts, double *w, bem_memspace space);
 
+/* The kernel shapes picked by timing so far (the library's tuner): one line
+ * per size class, "key value...": "gemm-ops:c<columns>:e<class>:i<class>
+ * <K split> <k per LDS stage>" for the multi-right-hand-side operator
+ * product, "gemm-mass:..." likewise for the dense inverse-mass product,
+ * "mtf-c128:..." / "mtf-c64:... <tile edge>" for the symmetric mat-vec;
+ * class = round(4 log2 N) of the exterior and interior vertex counts.  The
+ * table is shared by all contexts of the process and kept in the file
+ * $BEMTX_TUNE_FILE (else $XDG_CACHE_HOME/bemtx/tune-gfx950.txt, else
+ * $HOME/.cache/bemtx/tune-gfx950.txt), so a size class is timed once.
+ * Writes at most cap bytes (NUL-terminated) to buf when buf is not NULL;
+ * *len receives the text's length without the NUL. */
+bem_status bem_tune_table(char *buf, size_t cap, size_t *len);
+
 /* Copy one dense operator: mesh 0 = exterior, 1 = interior; op one of 'V',
  * 'K', 'T', 'D'.  dst: [N][N] in caller numbering, complex128 for BEM_C128
  * problems and complex64 for BEM_C64_MIXED (the stored values). */

@@ -66,6 +66,7 @@ SIGNATURES = {
     "bem_solve_hc_neumann": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
     "bem_hc_neumann_matvec": (c_status, [vp, vp, vp, i32, i32]),
     "bem_mesh_winding": (c_status, [vp, vp, i64, vp, i32]),
+    "bem_tune_table": (c_status, [vp, sz, ctypes.POINTER(sz)]),
     "bem_check_mesh": (c_status, [vp, i64, vp, i64]),
     "bem_host_mortar": (c_status, [vp, i64, vp, i64, vp, i64, vp, i64, vp, vp, vp, ctypes.POINTER(i64),
                                    ctypes.POINTER(f64)]),

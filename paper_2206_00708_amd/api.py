@@ -325,6 +325,21 @@ def host_mortar(int_mesh, ext_mesh):
     return rp, col, val, dfc.value
 
 
+def tune_table():
+    """bem_tune_table: {key: [values]} of the kernel shapes picked by timing."""
+    L = N.load()
+    n = ctypes.c_size_t()
+    _check(L.bem_tune_table(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(L.bem_tune_table(buf, n.value + 1, ctypes.byref(n)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        f = line.split()
+        if f:
+            out[f[0]] = [int(v) for v in f[1:]]
+    return out
+
+
 def host_gauss_legendre(n):
     x = np.zeros(n); w = np.zeros(n)
     _check(N.load().bem_host_gauss_legendre(n, x.ctypes.data, w.ctypes.data))

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbemtx.so")
-SOURCES = ["api.cpp", "mesh_prep.cpp", "mortar.cpp", "mass_cheb.cpp", "assemble.hip", "solve.hip", "gemm.hip", "field.hip", "mortar_dev.hip"]
+SOURCES = ["api.cpp", "mesh_prep.cpp", "mortar.cpp", "mass_cheb.cpp", "tune.cpp", "assemble.hip", "solve.hip", "gemm.hip", "field.hip", "mortar_dev.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -647,6 +647,19 @@ bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong
     return matvec_impl(p, x, y, strong, space);
 }
 
+bem_status bem_tune_table(char *buf, size_t cap, size_t *len)
+{
+    if (!len) return set_error(BEM_E_ARG, "len is NULL");
+    const std::string t = tune_table_text();
+    *len = t.size();
+    if (buf && cap > 0) {
+        const size_t n = std::min(cap - 1, t.size());
+        std::memcpy(buf, t.data(), n);
+        buf[n] = '\0';
+    }
+    return BEM_OK;
+}
+
 bem_status bem_mtf_matvec_noalloc(bem_problem *p, const void *x, void *y, int32_t strong)
 {
     if (!p || !x || !y) return set_error(BEM_E_ARG, "null argument");

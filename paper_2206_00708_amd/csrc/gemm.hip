@@ -30,16 +30,17 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int GT_M = 128;   // rows per tile
 constexpr int GT_N = 128;   // columns per column block of Bt and C
-constexpr int GT_K = 32;    // k per LDS stage
-constexpr int GT_LD = GT_K + 4;
 
 }  // namespace
 
 // One segment: C[kc][cb * 128 + c][row] = sum over the k of chunk kc of A[row][k] Bt[cb * 128 + c][k],
-// for the first 32 NT columns c of each 128-column block (NT = 1, 2, 4).
-template <int NT>
-__global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
+// for the first 32 NT columns c of each 128-column block (NT = 1, 2, 4); KST k
+// per LDS stage (32 or 64: a 64-k stage halves the barriers per k and fits
+// one workgroup per compute unit).
+template <int NT, int KST>
+__global__ __launch_bounds__(256, KST == 32 ? 2 : 1) void gemm_f32_kernel(GemmArgs G)
 {
+    constexpr int GT_K = KST, GT_LD = KST + 4, KH = KST / 32;   // k halves of 32 per stage
     __shared__ float As[2][GT_M * GT_LD];
     __shared__ float Bs[2][32 * NT * GT_LD];
     if (G.done) {   // every run has converged: nothing left to compute
@@ -71,41 +72,54 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
     const int lr = tid >> 3, lc = (tid & 7) * 4;
     const float *ag = SA + (int64_t)min(rt * GT_M + lr, M - 1) * lda + lc;   // rows past M: results not stored
     const float *bg = SB + (int64_t)(cb * GT_N + lr) * ldb + lc;
-    const int64_t astep = (int64_t)32 * lda, bstep = (int64_t)32 * ldb;
+    const int64_t bstep = (int64_t)32 * ldb;
     // row offsets of the other three loads (rows past M clamp to the last row)
     const int arow0 = min(rt * GT_M + lr, M - 1);
     const int64_t aoff1 = (int64_t)(min(rt * GT_M + lr + 32, M - 1) - arow0) * lda;
     const int64_t aoff2 = (int64_t)(min(rt * GT_M + lr + 64, M - 1) - arow0) * lda;
     const int64_t aoff3 = (int64_t)(min(rt * GT_M + lr + 96, M - 1) - arow0) * lda;
-    (void)astep;
-    float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-    (void)rb1; (void)rb2; (void)rb3;
+    // staged loads in named registers (arrays of float4 here went to scratch)
+    float4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;   // k 0-31 of the stage
+    float4 sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3;   // k 32-63 (KST = 64)
+    (void)rb1; (void)rb2; (void)rb3; (void)sa0; (void)sa1; (void)sa2; (void)sa3;
+    (void)sb0; (void)sb1; (void)sb2; (void)sb3;
+#define GEMM_FETCH_HALF(k, A0, A1, A2, A3, B0, B1, B2, B3)                         \
+    do {                                                                           \
+        A0 = *reinterpret_cast<const float4 *>(ag + (k));                          \
+        A1 = *reinterpret_cast<const float4 *>(ag + aoff1 + (k));                  \
+        A2 = *reinterpret_cast<const float4 *>(ag + aoff2 + (k));                  \
+        A3 = *reinterpret_cast<const float4 *>(ag + aoff3 + (k));                  \
+        B0 = *reinterpret_cast<const float4 *>(bg + (k));                          \
+        if constexpr (NT > 1) B1 = *reinterpret_cast<const float4 *>(bg + bstep + (k)); \
+        if constexpr (NT > 2) {                                                    \
+            B2 = *reinterpret_cast<const float4 *>(bg + 2 * bstep + (k));          \
+            B3 = *reinterpret_cast<const float4 *>(bg + 3 * bstep + (k));          \
+        }                                                                          \
+    } while (0)
+#define GEMM_STASH_HALF(b, h, A0, A1, A2, A3, B0, B1, B2, B3)                      \
+    do {                                                                           \
+        float *da = &As[b][lr * GT_LD + lc + 32 * (h)];                            \
+        float *db = &Bs[b][lr * GT_LD + lc + 32 * (h)];                            \
+        *reinterpret_cast<float4 *>(da) = A0;                                      \
+        *reinterpret_cast<float4 *>(da + 32 * GT_LD) = A1;                         \
+        *reinterpret_cast<float4 *>(da + 64 * GT_LD) = A2;                         \
+        *reinterpret_cast<float4 *>(da + 96 * GT_LD) = A3;                         \
+        *reinterpret_cast<float4 *>(db) = B0;                                      \
+        if constexpr (NT > 1) *reinterpret_cast<float4 *>(db + 32 * GT_LD) = B1;   \
+        if constexpr (NT > 2) {                                                    \
+            *reinterpret_cast<float4 *>(db + 64 * GT_LD) = B2;                     \
+            *reinterpret_cast<float4 *>(db + 96 * GT_LD) = B3;                     \
+        }                                                                          \
+    } while (0)
 #define GEMM_FETCH(k)                                                              \
     do {                                                                           \
-        ra0 = *reinterpret_cast<const float4 *>(ag + (k));                         \
-        ra1 = *reinterpret_cast<const float4 *>(ag + aoff1 + (k));                 \
-        ra2 = *reinterpret_cast<const float4 *>(ag + aoff2 + (k));                 \
-        ra3 = *reinterpret_cast<const float4 *>(ag + aoff3 + (k));                 \
-        rb0 = *reinterpret_cast<const float4 *>(bg + (k));                         \
-        if constexpr (NT > 1) rb1 = *reinterpret_cast<const float4 *>(bg + bstep + (k)); \
-        if constexpr (NT > 2) {                                                    \
-            rb2 = *reinterpret_cast<const float4 *>(bg + 2 * bstep + (k));         \
-            rb3 = *reinterpret_cast<const float4 *>(bg + 3 * bstep + (k));         \
-        }                                                                          \
+        GEMM_FETCH_HALF(k, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3);                \
+        if constexpr (KH > 1) GEMM_FETCH_HALF((k) + 32, sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3); \
     } while (0)
 #define GEMM_STASH(b)                                                              \
     do {                                                                           \
-        float *da = &As[b][lr * GT_LD + lc], *db = &Bs[b][lr * GT_LD + lc];        \
-        *reinterpret_cast<float4 *>(da) = ra0;                                     \
-        *reinterpret_cast<float4 *>(da + 32 * GT_LD) = ra1;                        \
-        *reinterpret_cast<float4 *>(da + 64 * GT_LD) = ra2;                        \
-        *reinterpret_cast<float4 *>(da + 96 * GT_LD) = ra3;                        \
-        *reinterpret_cast<float4 *>(db) = rb0;                                     \
-        if constexpr (NT > 1) *reinterpret_cast<float4 *>(db + 32 * GT_LD) = rb1;  \
-        if constexpr (NT > 2) {                                                    \
-            *reinterpret_cast<float4 *>(db + 64 * GT_LD) = rb2;                    \
-            *reinterpret_cast<float4 *>(db + 96 * GT_LD) = rb3;                    \
-        }                                                                          \
+        GEMM_STASH_HALF(b, 0, ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3);             \
+        if constexpr (KH > 1) GEMM_STASH_HALF(b, 1, sa0, sa1, sa2, sa3, sb0, sb1, sb2, sb3); \
     } while (0)
 
     v16f acc[NT];
@@ -148,6 +162,8 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
     }
 #undef GEMM_FETCH
 #undef GEMM_STASH
+#undef GEMM_FETCH_HALF
+#undef GEMM_STASH_HALF
 
     // accumulator v of lane l: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32 of
     // the 32 x 32 tile; the output is column-major per chunk, C[kc][c][row], so the
@@ -167,10 +183,11 @@ __global__ __launch_bounds__(256, 2) void gemm_f32_kernel(GemmArgs G)
 // multiples of 32, lda >= K, ldb >= K, and Bt zero where A has padding.
 bem_status launch_gemm_f32(bem_ctx *ctx, GemmArgs &G, hipStream_t st, int kernel_id)
 {
+    if (G.kst != 32 && G.kst != 64) return set_error(BEM_E_ARG, "internal: GEMM stage depth");
     int tiles = 0;
     for (int s = 0; s < G.nseg; ++s) {
         GemmSeg &S = G.seg[s];
-        if (S.K % GT_K || S.kchunk % GT_K || S.kchunk <= 0 || S.lda < S.K || S.ldb < S.K || S.M <= 0 || S.ncb <= 0)
+        if (S.K % G.kst || S.kchunk % G.kst || S.kchunk <= 0 || S.lda < S.K || S.ldb < S.K || S.M <= 0 || S.ncb <= 0)
             return set_error(BEM_E_ARG, "internal: GEMM segment shape");
         S.tile0 = tiles;
         const int nk = (S.K + S.kchunk - 1) / S.kchunk;
@@ -178,12 +195,15 @@ bem_status launch_gemm_f32(bem_ctx *ctx, GemmArgs &G, hipStream_t st, int kernel
     }
     if (tiles == 0) return BEM_OK;
     KTimer kt(ctx, kernel_id);
-    if (G.nt == 1)
-        launch_k(kt, gemm_f32_kernel<1>, dim3(tiles), dim3(256), 0, st, G);
-    else if (G.nt == 2)
-        launch_k(kt, gemm_f32_kernel<2>, dim3(tiles), dim3(256), 0, st, G);
-    else
-        launch_k(kt, gemm_f32_kernel<4>, dim3(tiles), dim3(256), 0, st, G);
+    if (G.kst == 32) {
+        if (G.nt == 1) launch_k(kt, gemm_f32_kernel<1, 32>, dim3(tiles), dim3(256), 0, st, G);
+        else if (G.nt == 2) launch_k(kt, gemm_f32_kernel<2, 32>, dim3(tiles), dim3(256), 0, st, G);
+        else launch_k(kt, gemm_f32_kernel<4, 32>, dim3(tiles), dim3(256), 0, st, G);
+    } else {
+        if (G.nt == 1) launch_k(kt, gemm_f32_kernel<1, 64>, dim3(tiles), dim3(256), 0, st, G);
+        else if (G.nt == 2) launch_k(kt, gemm_f32_kernel<2, 64>, dim3(tiles), dim3(256), 0, st, G);
+        else launch_k(kt, gemm_f32_kernel<4, 64>, dim3(tiles), dim3(256), 0, st, G);
+    }
     BEM_HIP(hipGetLastError());
     return BEM_OK;
 }

@@ -27,11 +27,11 @@ constexpr int SMAX = 24;
 constexpr int LMAX = 12;
 constexpr int NG_MAX = 16;
 
-// Row stride (elements) of the dense operator matrices: a multiple of 16, so
-// rows start on 128-byte boundaries and a complex64 row read as floats has a
-// length that is a multiple of 32 (the k step of the matrix-core product).
-// Padding columns hold zeros.
-__host__ __device__ inline int64_t op_ld(int64_t nv) { return (nv + 15) & ~int64_t(15); }
+// Row stride (elements) of the dense operator matrices: a multiple of 32, so
+// rows start on 256-byte boundaries and a complex64 row read as floats has a
+// length that is a multiple of 64 (the longest k stage of the matrix-core
+// product).  Padding columns hold zeros.
+__host__ __device__ inline int64_t op_ld(int64_t nv) { return (nv + 31) & ~int64_t(31); }
 
 // Per-triangle geometry table, built on the device (44 doubles, 352 B).
 struct alignas(16) TriGeo {
@@ -216,6 +216,14 @@ struct ChebTables {
     HVec<double> eval;
 };
 bem_status cheb_tables(const Csr M[2], int s, ChebTables &T);
+
+// Kernel-shape tuning table (tune.cpp): process-wide, persisted in a text
+// file.  tuned() returns the value of `key`, running `tune` once per key (other
+// callers of the same key wait for its result) and recording what it picks.
+int tune_class(int64_t n);   // size class: quarter octaves of n
+bem_status tuned(const std::string &key, std::vector<int> &value,
+                 const std::function<bem_status(std::vector<int> &)> &tune);
+std::string tune_table_text();
 void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue method
 
 }  // namespace bemtx
@@ -307,6 +315,7 @@ struct GemmSeg {
 struct GemmArgs {
     GemmSeg seg[GEMM_MAXSEG];
     int nseg;
+    int kst;            // k per LDS stage: 32 or 64
     const int *done;    // optional: nrun flags, done_stride ints apart; all set = skip
     int done_stride, nrun;
     int nt;             // columns computed per 128-column block: 32 nt (nt = 1, 2, 4)
@@ -360,4 +369,6 @@ struct bem_problem {
     // multi-RHS products: K chunks per GEMM [operators, inverse masses][tile width 32, 64, 128
     // columns], picked by timing at first use
     int gemm_nk[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    int gemm_kst[2][3] = {{0, 0, 0}, {0, 0, 0}};   // k per LDS stage of those GEMMs (32 or 64)
+    int mtf_ts = 0;                                 // tile edge of the symmetric mat-vec (64 or 128; 0: not tuned yet)
 };

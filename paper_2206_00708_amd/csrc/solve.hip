@@ -509,6 +509,7 @@ template <> struct Cx<double> { using T = double2; };
 // load).  The wider rows of the tile keep DRAM accesses in longer runs than
 // 64-column tiles do.
 template <class E> constexpr int sym_tile() { return 128; }
+constexpr int SYM_TS_MIN = 64;   // the smaller tile edge the tuner may pick (sizes the partial sums)
 __host__ __device__ inline int sym_ntile(int nv, int ts) { return (nv + ts - 1) / ts; }
 
 // task t -> tile pair (a, b), a <= b, in row-major order of the upper triangle
@@ -524,6 +525,12 @@ __device__ inline void sym_pair(int64_t t, int nt, int &a, int &b)
 }
 
 __device__ inline double2 ld_entry(const double2 *p) { return ld_stream(p); }
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ inline float2 ld_entry(const float2 *p)   // one complex64 entry, streaming
+{
+    const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f *>(p));
+    return make_float2(v.x, v.y);
+}
 __device__ inline float4 ld_entry2(const float2 *p) { return ld_stream2c(p); }   // two adjacent complex64
 
 // Sum over the 64 lanes of a wave with DPP moves (row shifts within each row
@@ -591,13 +598,13 @@ __device__ inline void ld_cols(const E *M, int64_t ld, int row, int col0, int nv
     }
 }
 
-template <class E, class R>
+template <class E, class R, int TS>
 __global__ __launch_bounds__(256) void mtf_sym_tile_kernel(MtfArgs A, const double2 *__restrict__ x,
                                                            double4 *__restrict__ part,
                                                            const KrylovState *__restrict__ st)
 {
     using C = typename Cx<R>::T;
-    constexpr int TS = sym_tile<E>(), CPL = TS / 64, RPW = TS / 4;   // tile edge, columns per lane, rows per wave
+    constexpr int CPL = TS / 64, RPW = TS / 4;   // columns per lane, rows per wave
     if (st && st->done) return;
     __shared__ C sva[TS], swa[TS], svb[TS], swb[TS];
     __shared__ C rowres[3][TS];
@@ -1640,7 +1647,7 @@ MtfArgs make_args(const bem_problem *p)
     A.c_ext_w = 0.5 * p->rho_ext / p->rho_int;
     A.c_int_v = -0.5;
     A.c_int_w = -0.5 * p->rho_int / p->rho_ext;
-    A.sym_ts = p->prec == BEM_C128 ? sym_tile<double2>() : sym_tile<float2>();
+    A.sym_ts = p->mtf_ts ? p->mtf_ts : (p->prec == BEM_C128 ? sym_tile<double2>() : sym_tile<float2>());
     A.no_mortar = 0;
     const bem_mesh *ms[2] = {p->ext, p->inte};
     for (int m = 0; m < 2; ++m) {
@@ -1653,8 +1660,8 @@ MtfArgs make_args(const bem_problem *p)
 
 size_t split_part_bytes(int ne, int ni)
 {
-    const int nchunk = std::max({split_nchunk(ne, MASS_CW_MAX), split_nchunk(ni, MASS_CW_MAX), sym_ntile(ne, sym_tile<double2>()),
-                                 sym_ntile(ni, sym_tile<double2>())});
+    const int nchunk = std::max({split_nchunk(ne, MASS_CW_MAX), split_nchunk(ni, MASS_CW_MAX), sym_ntile(ne, SYM_TS_MIN),
+                                 sym_ntile(ni, SYM_TS_MIN)});
     // the sparse inverse-mass apply of one run uses the same buffer for its two work sets (6 n complex)
     return std::max((size_t)nchunk * (ne + ni) * sizeof(double4), (size_t)6 * (2 * ne + 2 * ni) * sizeof(double2));
 }
@@ -1758,16 +1765,66 @@ bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, dou
     const dim3 g((unsigned)((int64_t)nte * (nte + 1) / 2 + (int64_t)nti * (nti + 1) / 2));
     {
         KTimer kt(p->ctx, K_MTF_DENSE);
-        if (p->prec == BEM_C128)
-            launch_k(kt, mtf_sym_tile_kernel<double2, double>, g, dim3(256), 0, st, A, x, part, kst);
-        else if (acc64)
-            launch_k(kt, mtf_sym_tile_kernel<float2, double>, g, dim3(256), 0, st, A, x, part, kst);
-        else
-            launch_k(kt, mtf_sym_tile_kernel<float2, float>, g, dim3(256), 0, st, A, x, part, kst);
+        if (A.sym_ts == 64) {
+            if (p->prec == BEM_C128)
+                launch_k(kt, mtf_sym_tile_kernel<double2, double, 64>, g, dim3(256), 0, st, A, x, part, kst);
+            else if (acc64)
+                launch_k(kt, mtf_sym_tile_kernel<float2, double, 64>, g, dim3(256), 0, st, A, x, part, kst);
+            else
+                launch_k(kt, mtf_sym_tile_kernel<float2, float, 64>, g, dim3(256), 0, st, A, x, part, kst);
+        } else {
+            if (p->prec == BEM_C128)
+                launch_k(kt, mtf_sym_tile_kernel<double2, double, 128>, g, dim3(256), 0, st, A, x, part, kst);
+            else if (acc64)
+                launch_k(kt, mtf_sym_tile_kernel<float2, double, 128>, g, dim3(256), 0, st, A, x, part, kst);
+            else
+                launch_k(kt, mtf_sym_tile_kernel<float2, float, 128>, g, dim3(256), 0, st, A, x, part, kst);
+        }
     }
     hipLaunchKernelGGL(mtf_sym_combine_kernel, dim3((rows + 15) / 16), dim3(256), 0, st, A, x, part, y, kst);
     BEM_HIP(hipGetLastError());
     if (strong) return apply_Minv(p, y, z, part, kst);
+    return BEM_OK;
+}
+
+// Tile edge of the symmetric mat-vec (64 or 128) by timing both on the
+// problem's operators once per size class and precision (tuning table).
+// x: any n-vector; y, part: work buffers.
+bem_status mtf_tune(bem_problem *p, const double2 *x, double2 *y, double4 *part)
+{
+    if (p->mtf_ts) return BEM_OK;
+    const std::string key = std::string(p->prec == BEM_C128 ? "mtf-c128" : "mtf-c64") + ":e" +
+                            std::to_string(tune_class(p->ext->h.nv)) + ":i" + std::to_string(tune_class(p->inte->h.nv));
+    hipStream_t st = p->ctx->stream;
+    std::vector<int> v;
+    bem_status s = tuned(key, v, [&](std::vector<int> &out) -> bem_status {
+        hipEvent_t e0, e1;
+        BEM_HIP(hipEventCreate(&e0));
+        BEM_HIP(hipEventCreate(&e1));
+        struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
+        float best = 1e30f;
+        int pick = 128;
+        for (int ts : {64, 128}) {
+            MtfArgs A = make_args(p);
+            A.sym_ts = ts;
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                BEM_HIP(hipEventRecord(e0, st));
+                bem_status q = apply_A(p, A, x, y, nullptr, false, nullptr, part);
+                if (q) return q;
+                BEM_HIP(hipEventRecord(e1, st));
+                BEM_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                tmin = std::min(tmin, ms);
+            }
+            if (tmin < best) { best = tmin; pick = ts; }
+        }
+        out = {pick};
+        return BEM_OK;
+    });
+    if (s) return s;
+    p->mtf_ts = v.size() == 1 && (v[0] == 64 || v[0] == 128) ? v[0] : 128;
     return BEM_OK;
 }
 
@@ -2063,7 +2120,7 @@ bem_status norm_to(const bem_problem *p, int n, const double2 *w, double *npart,
     return BEM_OK;
 }
 
-int kchunk_for(int K, int nk) { return ((K + nk - 1) / nk + 31) / 32 * 32; }
+int kchunk_for(int K, int nk, int kst = 32) { return ((K + nk - 1) / nk + kst - 1) / kst * kst; }
 int nchunks(int K, int kc) { return (K + kc - 1) / kc; }
 
 bem_status block_alloc(bem_problem *p, BlockBufs &bb)
@@ -2101,9 +2158,10 @@ void gemm_width(int cols, int &nt, int &ncb)
 }
 int nt_index(int nt) { return nt == 1 ? 0 : nt == 2 ? 1 : 2; }
 
-GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st)
+GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st, int kst = 32)
 {
     GemmArgs G{};
+    G.kst = kst;
     int nt, ncb;
     gemm_width(2 * R, nt, ncb);
     G.nt = nt;
@@ -2120,7 +2178,7 @@ GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const
             S.C = bb.cop.as<float>() + bb.cop_off[m][o];
             S.M = nv[m];
             S.K = kop;
-            S.kchunk = kchunk_for(kop, nk);
+            S.kchunk = kchunk_for(kop, nk, kst);
             S.ncb = 1;
         }
     }
@@ -2134,6 +2192,7 @@ GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const
 GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st)
 {
     GemmArgs G{};
+    G.kst = 32;
     int nt, ncb;
     gemm_width(4 * R, nt, ncb);
     G.nt = nt;
@@ -2161,42 +2220,61 @@ GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, cons
 // K chunk count of one GEMM (which = 0 operators, 1 inverse masses) for R
 // runs, chosen once per problem and tile width by timing every candidate on
 // the problem's own matrices (right-hand buffers zeroed first).
-bem_status block_tune(bem_problem *p, BlockBufs &bb, int which, int R, int &nk)
+// K split (and, for the operator product, k per LDS stage) of the block
+// GEMMs, by timing every candidate once per size class: the choice is kept
+// in the process-wide tuning table (and its file), so every problem and
+// context of the class uses the same shapes.
+bem_status block_tune(bem_problem *p, BlockBufs &bb, int which, int R, int &nk, int &kst)
 {
     int nt, ncb;
     gemm_width(which == 0 ? 2 * R : 4 * R, nt, ncb);
     int &slot = p->gemm_nk[which][nt_index(nt)];
-    if (slot > 0) { nk = slot; return BEM_OK; }
+    int &slot_kst = p->gemm_kst[which][nt_index(nt)];
+    if (slot > 0) { nk = slot; kst = slot_kst; return BEM_OK; }
     bem_ctx *ctx = p->ctx;
     hipStream_t st = ctx->stream;
-    for (int m = 0; m < 2; ++m) {
-        BEM_HIP(hipMemsetAsync(bb.btv[m].ptr, 0, bb.btv[m].bytes, st));
-        BEM_HIP(hipMemsetAsync(bb.btw[m].ptr, 0, bb.btw[m].bytes, st));
-        BEM_HIP(hipMemsetAsync(bb.btm[m].ptr, 0, bb.btm[m].bytes, st));
-    }
-    hipEvent_t e0, e1;
-    BEM_HIP(hipEventCreate(&e0));
-    BEM_HIP(hipEventCreate(&e1));
-    struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
-    const int cand[4] = {1, 2, 4, 8};
-    float best = 1e30f;
-    int pick = 4;
-    for (int c : cand) {
-        float tmin = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
-            GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c, R, nullptr) : mass_gemm_args(p, bb, c, R, nullptr);
-            BEM_HIP(hipEventRecord(e0, st));
-            bem_status s = launch_gemm_f32(ctx, G, st, which == 0 ? K_BLOCK_GEMM : K_MASS_GEMM);
-            if (s) return s;
-            BEM_HIP(hipEventRecord(e1, st));
-            BEM_HIP(hipEventSynchronize(e1));
-            float ms = 0;
-            BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-            tmin = std::min(tmin, ms);
+    const std::string key = std::string(which == 0 ? "gemm-ops" : "gemm-mass") + ":c" + std::to_string(32 * nt * ncb) +
+                            ":e" + std::to_string(tune_class(p->ext->h.nv)) + ":i" +
+                            std::to_string(tune_class(p->inte->h.nv));
+    std::vector<int> v;
+    bem_status s = tuned(key, v, [&](std::vector<int> &out) -> bem_status {
+        for (int m = 0; m < 2; ++m) {   // defined right-hand inputs for the timing runs
+            BEM_HIP(hipMemsetAsync(bb.btv[m].ptr, 0, bb.btv[m].bytes, st));
+            BEM_HIP(hipMemsetAsync(bb.btw[m].ptr, 0, bb.btw[m].bytes, st));
+            BEM_HIP(hipMemsetAsync(bb.btm[m].ptr, 0, bb.btm[m].bytes, st));
         }
-        if (tmin < best) { best = tmin; pick = c; }
-    }
-    slot = nk = pick;
+        hipEvent_t e0, e1;
+        BEM_HIP(hipEventCreate(&e0));
+        BEM_HIP(hipEventCreate(&e1));
+        struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
+        float best = 1e30f;
+        int pick_nk = 4, pick_kst = 32;
+        for (int ks : {32, 64}) {
+            if (which == 1 && ks != 32) continue;   // inverse-mass rows: multiples of 32 only
+            for (int c : {1, 2, 4, 8}) {
+                float tmin = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c, R, nullptr, ks) : mass_gemm_args(p, bb, c, R, nullptr);
+                    BEM_HIP(hipEventRecord(e0, st));
+                    bem_status q = launch_gemm_f32(ctx, G, st, which == 0 ? K_BLOCK_GEMM : K_MASS_GEMM);
+                    if (q) return q;
+                    BEM_HIP(hipEventRecord(e1, st));
+                    BEM_HIP(hipEventSynchronize(e1));
+                    float ms = 0;
+                    BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    tmin = std::min(tmin, ms);
+                }
+                if (tmin < best) { best = tmin; pick_nk = c; pick_kst = ks; }
+            }
+        }
+        out = {pick_nk, pick_kst};
+        return BEM_OK;
+    });
+    if (s) return s;
+    const bool valid = v.size() == 2 && (v[0] == 1 || v[0] == 2 || v[0] == 4 || v[0] == 8) &&
+                       (v[1] == 32 || (v[1] == 64 && which == 0));
+    slot = nk = valid ? v[0] : 4;
+    slot_kst = kst = valid ? v[1] : 32;
     return BEM_OK;
 }
 
@@ -2208,9 +2286,9 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
 {
     hipStream_t st = p->ctx->stream;
     const int nv[2] = {A.ne, A.ni};
-    int nk_ops = 0, nk_mass = 0;   // (tuning, at first use, zeroes the right-hand buffers: before packing)
-    bem_status s = block_tune(p, bb, 0, R, nk_ops);
-    if (!s && strong && !p->mass_sparse) s = block_tune(p, bb, 1, R, nk_mass);
+    int nk_ops = 0, nk_mass = 0, kst_ops = 32, kst_mass = 32;   // (tuning zeroes the right-hand buffers: before packing)
+    bem_status s = block_tune(p, bb, 0, R, nk_ops, kst_ops);
+    if (!s && strong && !p->mass_sparse) s = block_tune(p, bb, 1, R, nk_mass, kst_mass);
     if (s) return s;
     for (int m = 0; m < 2; ++m) {
         const int kop = 2 * (int)op_ld(nv[m]);
@@ -2218,7 +2296,7 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
                            kop, R, X, xstride, m == 0 ? 0 : 2 * A.ne, kst, bb.btv[m].as<float>(), bb.btw[m].as<float>());
     }
     BEM_HIP(hipGetLastError());
-    GemmArgs G = ops_gemm_args(p, bb, nk_ops, R, kst);
+    GemmArgs G = ops_gemm_args(p, bb, nk_ops, R, kst, kst_ops);
     s = launch_gemm_f32(p->ctx, G, st, K_BLOCK_GEMM);
     if (s) return s;
     BlockC bc;
@@ -2443,6 +2521,8 @@ bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_m
     const dim3 g((n + 255) / 256);
     hipLaunchKernelGGL(permute_vec_kernel, g, dim3(256), 0, st, ne, ni, p->ext->d.perm.as<int32_t>(),
                        p->inte->d.perm.as<int32_t>(), xu.as<double2>(), xi.as<double2>(), 1);
+    s = mtf_tune(p, xi.as<double2>(), yi.as<double2>(), part.as<double4>());
+    if (s) return s;
     MtfArgs A = make_args(p);
     s = apply_A(p, A, xi.as<double2>(), yi.as<double2>(), zi.as<double2>(), strong != 0, nullptr, part.as<double4>());
     if (s) return s;
@@ -2672,6 +2752,8 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     BEM_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     BEM_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     struct EvGuard { hipEvent_t *e; ~EvGuard() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); } } eguard{ev};
+    s = mtf_tune(p, W.xin.as<double2>(), W.y.as<double2>(), W.part.as<double4>());
+    if (s) return s;
     const MtfArgs A = make_args(p);
     const size_t finish_lds = (size_t)(3 * m + 1) * sizeof(double2);
     BEM_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&dgs_hess_kernel),

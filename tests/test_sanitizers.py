@@ -61,8 +61,7 @@ def test_oracle_under_asan_ubsan(meshes):
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not found")
 def test_host_code_under_asan_ubsan(meshes):
     exe = str(meshes / "host_san")
-    srcs = ["api.cpp", "mesh_prep.cpp", "mortar.cpp", "mass_cheb.cpp", "assemble.hip", "solve.hip", "gemm.hip",
-            "field.hip", "mortar_dev.hip"]
+    from paper_2206_00708_amd.build import SOURCES as srcs   # the library's own source list
     # the sanitizers instrument the host pass only; device code is built as usual and never run
     flags = ["-O1", "-g", "-std=c++17", "--offload-arch=gfx950", "-fno-omit-frame-pointer",
              "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
