@@ -97,6 +97,7 @@ typedef struct {
     double t_solve_ms;
     double t_iter_ms;         /* t_solve / iterations */
     double t_assembly_ms;     /* device span of the operator assembly of both meshes */
+    int32_t graph_steps;      /* Arnoldi steps issued through captured HIP graphs (bem_problem_set_graphs) */
 } bem_stats;
 
 typedef struct bem_ctx bem_ctx;
@@ -224,6 +225,20 @@ bem_status bem_problem_set_mass_apply(bem_problem *p, int32_t mode);
 /* The choice of the last projection set-up: *sparse = 1 for the Chebyshev
  * apply, 0 for dense inverses.  BEM_E_STATE before the projection. */
 bem_status bem_problem_mass_apply(const bem_problem *p, int32_t *sparse);
+
+/* GMRES of the solves (Sec. 5.1: no restart) in captured HIP graphs (on = 1,
+ * the default) or as individual launches (0).  With graphs, every whole
+ * batch of eight Arnoldi steps after the first goes out as one graph launch
+ * on the context's stream: the operator product (mat-vec or matrix-core
+ * block product and the inverse-mass apply) and the Gram-Schmidt and Givens
+ * kernels of each step, their step index read from device memory, so one
+ * graph serves a range of 64 step indices; graphs are captured on first use
+ * within a solve and destroyed at its end.  The kernels, their order and
+ * their arithmetic are the same in both modes, so the traces agree bit for
+ * bit.  Kernels inside graphs carry no per-kernel timing
+ * (bem_ctx_set_kernel_timing times the steps launched individually: the
+ * first batch and the last steps).  BEM_E_ARG for other values. */
+bem_status bem_problem_set_graphs(bem_problem *p, int32_t on);
 
 /* Wall-clock milliseconds of the mortar step (geometry and CSR) of the last
  * bem_assemble_projection, by the setting above.  BEM_E_STATE before the

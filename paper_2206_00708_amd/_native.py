@@ -23,7 +23,7 @@ class Stats(ctypes.Structure):
     _fields_ = [("iterations", i32), ("ir_steps", i32), ("rel_residual", f64),
                 ("t_geometry_ms", f64), ("t_regular_ms", f64), ("t_singular_ms", f64),
                 ("t_projection_ms", f64), ("t_matrix_ms", f64), ("t_solve_ms", f64), ("t_iter_ms", f64),
-                ("t_assembly_ms", f64)]
+                ("t_assembly_ms", f64), ("graph_steps", i32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -61,6 +61,7 @@ SIGNATURES = {
     "bem_problem_mortar_ms": (c_status, [vp, ctypes.POINTER(f64)]),
     "bem_problem_set_mass_apply": (c_status, [vp, i32]),
     "bem_problem_mass_apply": (c_status, [vp, ctypes.POINTER(i32)]),
+    "bem_problem_set_graphs": (c_status, [vp, i32]),
     "bem_solve_pmchwt": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
     "bem_pmchwt_matvec": (c_status, [vp, vp, vp, i32, i32]),
     "bem_solve_hc_neumann": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),

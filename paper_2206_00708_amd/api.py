@@ -215,6 +215,11 @@ class Problem:
         sparse Chebyshev apply; takes effect at the next assemble_projection."""
         _check(N.load().bem_problem_set_mass_apply(self._h, int(mode)))
 
+    def set_graphs(self, on):
+        """bem_problem_set_graphs: GMRES steps in captured HIP graphs (True, the
+        default) or launched one by one (False); the traces agree bit for bit."""
+        _check(N.load().bem_problem_set_graphs(self._h, int(bool(on))))
+
     def mass_apply_sparse(self):
         """bem_problem_mass_apply: True when the last projection set-up chose the sparse apply."""
         v = ctypes.c_int32()

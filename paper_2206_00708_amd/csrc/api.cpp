@@ -264,6 +264,7 @@ void bem_ctx_destroy(bem_ctx *ctx)
         (void)hipStreamSynchronize(ctx->aux);
         (void)hipStreamDestroy(ctx->aux);
     }
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     if (ctx->release_ev) (void)hipEventDestroy(ctx->release_ev);
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
@@ -439,6 +440,14 @@ bem_status bem_problem_set_mass_apply(bem_problem *p, int32_t mode)
     if (mode < 0 || mode > 2) return set_error(BEM_E_ARG, "mass apply mode must be 0 (by size), 1 (dense) or 2 (sparse)");
     if (mode != p->mass_mode) p->proj_ready = false;   // takes effect at the next projection set-up
     p->mass_mode = mode;
+    return BEM_OK;
+}
+
+bem_status bem_problem_set_graphs(bem_problem *p, int32_t on)
+{
+    if (!p) return set_error(BEM_E_ARG, "null problem");
+    if (on != 0 && on != 1) return set_error(BEM_E_ARG, "graphs must be 0 (off) or 1 (on)");
+    p->graphs = on;
     return BEM_OK;
 }
 

@@ -241,6 +241,9 @@ struct bem_ctx {
     // second stream (default priority) for the mass and mortar set-up, so that
     // it overlaps the operator assembly on `stream`; created at first use
     hipStream_t aux = nullptr;
+    // stream that GMRES graphs are captured on (capture records, runs nothing;
+    // the graphs are launched on `stream`, which may be the null stream)
+    hipStream_t capture = nullptr;
     size_t budget = 0;
     size_t in_use = 0;
     // per-kernel timing (HIP events around each launch on `stream`)
@@ -370,5 +373,6 @@ struct bem_problem {
     // columns], picked by timing at first use
     int gemm_nk[2][3] = {{0, 0, 0}, {0, 0, 0}};
     int gemm_kst[2][3] = {{0, 0, 0}, {0, 0, 0}};   // k per LDS stage of those GEMMs (32 or 64)
+    int graphs = 1;                                 // GMRES steps in captured HIP graphs (bem_problem_set_graphs)
     int mtf_ts = 0;                                 // tile edge of the symmetric mat-vec (64 or 128; 0: not tuned yet)
 };

@@ -1088,13 +1088,15 @@ constexpr int MAXIT_CAP = 3000;   // Hessenberg column, rotations and g staged i
 // partial[chunk][c] = sum over the chunk's rows of conj(V_c) u_j and
 // partial[chunk][j + 1 + c] = that of conj(V_c) w, for c = 0..j (slot j is
 // u_j itself: alpha and gamma).  One wave per (chunk, c); grid (nchunk,
-// ceil((j + 1) / 4), runs).
-__global__ __launch_bounds__(256) void dgs_dots_kernel(int n, int j, const double2 *__restrict__ Vb,
-                                                       const double2 *__restrict__ w, double2 *__restrict__ partial,
+// ceil((j + 1) / 4), runs), or larger (the extra waves return).
+__global__ __launch_bounds__(256) void dgs_dots_kernel(int n, int j, const int *__restrict__ jb,
+                                                       const double2 *__restrict__ Vb, const double2 *__restrict__ w,
+                                                       double2 *__restrict__ partial,
                                                        const KrylovState *__restrict__ st, KBatch B)
 {
     const int run = blockIdx.z;
     if (st[run].done) return;
+    if (jb) j += *jb;
     Vb += run * B.basis;
     w += run * B.vec;
     partial += run * B.partial;
@@ -1133,8 +1135,10 @@ __device__ inline double2 cconj_mul(double2 a, double2 b)   // conj(a) * b
 // (kept row-major in H, row stride m) and, by the first wave, its Givens rotation
 // (the earlier rotations as a scanned affine recurrence),
 // g and the residual estimate; then coef[j] = (1 / nu, nu) and coef[2j + 1] =
-// c_j for the update.  coef[2m + 3] holds beta_{j-1}.  One workgroup per run.
-__global__ __launch_bounds__(256) void dgs_hess_kernel(int j, int m, int nchunk, const double2 *__restrict__ partial,
+// c_j for the update.  coef[2m + 3] holds beta_{j-1}.  One workgroup per run;
+// dynamic LDS for at least 3 j + 1 complex values.
+__global__ __launch_bounds__(256) void dgs_hess_kernel(int j, const int *__restrict__ jb, int m, int nchunk,
+                                                       const double2 *__restrict__ partial,
                                                        double2 *__restrict__ coef, const double2 *__restrict__ hsum,
                                                        double2 *__restrict__ H, double2 *__restrict__ R,
                                                        double2 *__restrict__ g, double2 *__restrict__ cs,
@@ -1143,6 +1147,7 @@ __global__ __launch_bounds__(256) void dgs_hess_kernel(int j, int m, int nchunk,
     const int run = blockIdx.x;
     st += run;
     if (st->done) return;
+    if (jb) j += *jb;
     partial += run * B.partial;
     coef += run * B.coef;
     hsum += run * B.small;
@@ -1274,8 +1279,10 @@ __global__ __launch_bounds__(256) void dgs_hess_kernel(int j, int m, int nchunk,
 // in LDS in a fixed order); v_j = (u_j - V a) / nu into slot j, y = w - V b -
 // v_j c_j into slot j + 1, partial |y|^2 per block.  Blocks from nupd on: one
 // wave per row r <= j of the pending column, h_j[r] = ([b; c_j][r] -
-// sum over i >= r - 1 of H[r][i] a_i) / nu.  Grid (nupd + ceil((j + 1) / 4), runs).
-__global__ __launch_bounds__(256) void dgs_update_kernel(int n, int j, int m, int nupd, double2 *__restrict__ Vb,
+// sum over i >= r - 1 of H[r][i] a_i) / nu.  Grid (nupd + ceil((j + 1) / 4), runs),
+// or larger (the extra waves return).
+__global__ __launch_bounds__(256) void dgs_update_kernel(int n, int j, const int *__restrict__ jb, int m, int nupd,
+                                                         double2 *__restrict__ Vb,
                                                          const double2 *__restrict__ w, const double2 *__restrict__ coef,
                                                          const double2 *__restrict__ H, double2 *__restrict__ hsum,
                                                          double *__restrict__ npart, const KrylovState *__restrict__ st,
@@ -1283,6 +1290,7 @@ __global__ __launch_bounds__(256) void dgs_update_kernel(int n, int j, int m, in
 {
     const int run = blockIdx.y;
     if (st[run].done) return;
+    if (jb) j += *jb;
     Vb += run * B.basis;
     w += run * B.vec;
     coef += run * B.coef;
@@ -1344,15 +1352,17 @@ __global__ __launch_bounds__(256) void dgs_update_kernel(int n, int j, int m, in
 }
 
 // u_{j+1} = y / |y| in place in slot j + 1 (|y|^2 from the nupd partials, summed
-// in the same order by every block); block 0 stores beta_j = |y| / nu.
-// Grid (ceil(n / 256), runs).
-__global__ __launch_bounds__(256) void dgs_normalize_kernel(int n, int j, int m, int nupd,
+// in the same order by every block); block 0 stores beta_j = |y| / nu.  With
+// u_out, u_{j+1} also goes there (run stride B.vec): the fixed operand of the
+// next operator product.  Grid (ceil(n / 256), runs).
+__global__ __launch_bounds__(256) void dgs_normalize_kernel(int n, int j, const int *__restrict__ jb, int m, int nupd,
                                                             const double *__restrict__ npart, double2 *__restrict__ Vb,
-                                                            double2 *__restrict__ coef,
+                                                            double2 *__restrict__ coef, double2 *__restrict__ u_out,
                                                             const KrylovState *__restrict__ st, KBatch B)
 {
     const int run = blockIdx.y;
     if (st[run].done) return;
+    if (jb) j += *jb;
     npart += run * B.npart;
     Vb += run * B.basis;
     coef += run * B.coef;
@@ -1367,7 +1377,9 @@ __global__ __launch_bounds__(256) void dgs_normalize_kernel(int n, int j, int m,
     double2 *y = Vb + (int64_t)(j + 1) * n;
     if (r < n) {
         const double inv = yn > 0 ? 1.0 / yn : 0.0;
-        y[r] = make_double2(y[r].x * inv, y[r].y * inv);
+        const double2 u = make_double2(y[r].x * inv, y[r].y * inv);
+        y[r] = u;
+        if (u_out) u_out[run * B.vec + r] = u;
     }
     if (r == 0) coef[2 * m + 3] = make_double2(yn / coef[j].y, 0.0);
 }
@@ -1625,6 +1637,7 @@ namespace {
 
 struct Work {
     DevMem xin, d, y, z, b, r, Vb, partial, hsum, beta, tolv, yc, npart, R, H, coef, g, cs, sn, state, part;
+    DevMem u, jb;   // captured steps: the operand u_j of each run, and the device step base
 };
 
 // Buffers of the multi-RHS products (one set per solve or batched mat-vec).
@@ -2329,6 +2342,26 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
     return BEM_OK;
 }
 
+__global__ void set_step_kernel(int *__restrict__ jb, int j0)
+{
+    if (threadIdx.x == 0) *jb = j0;
+}
+
+// Executable graphs of one GMRES run, by step range; destroyed after the
+// stream has drained.
+struct GraphCache {
+    hipStream_t st = nullptr;
+    std::map<int, hipGraphExec_t> exec;
+    ~GraphCache()
+    {
+        if (exec.empty()) return;
+        (void)hipStreamSynchronize(st);
+        for (auto &e : exec) (void)hipGraphExecDestroy(e.second);
+    }
+};
+
+constexpr int GRAPH_SPAN = 64;   // step indices served by one captured graph (grids sized for the range's end)
+
 struct Gmres {
     bem_problem *p;
     const MtfArgs &A;
@@ -2340,6 +2373,103 @@ struct Gmres {
     KBatch B;
     double acc64_above = 0.0;   // single run, complex64: FP64 accumulation while the residual estimate exceeds this
     const PmchwtBufs *pm = nullptr;   // exterior PMCHWT system (one run, FP64) instead of the multiple-traces one
+    int graph_steps = 0;              // steps issued through captured graphs (all runs of this object)
+
+    // The launches of step j: the operator on u_j (vj, run stride vstride),
+    // then the Gram-Schmidt kernels.  With jb the kernels take their step
+    // index as j + *jb (device memory) and their grids are sized for steps up
+    // to jcap; u_out: where the normalisation also writes u_{j+1}.
+    bem_status step(int j, const int *jb, int jcap, int maxit, const double2 *vj, int64_t vstride, double2 *u_out,
+                    bool acc64)
+    {
+        bem_ctx *ctx = p->ctx;
+        hipStream_t st = ctx->stream;
+        double2 *Vb = W.Vb.as<double2>();
+        KrylovState *dst = W.state.as<KrylovState>();
+        const dim3 gv(nrow_blk, R);
+        bem_status s;
+        if (pm)
+            s = apply_ext_form(p, *pm, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
+        else if (bb)
+            s = block_apply(p, A, *bb, R, vj, vstride, W.y.as<double2>(), B.vec, W.z.as<double2>(), B.vec, true, dst);
+        else
+            s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>(), acc64);
+        if (s) return s;
+        {
+            KTimer kt(ctx, K_CGS_DOTS);
+            launch_k(kt, dgs_dots_kernel, dim3(nchunk, (jcap + 1 + 3) / 4, R), dim3(256), 0, st, n, j, jb, Vb,
+                     W.z.as<double2>(), W.partial.as<double2>(), dst, B);
+        }
+        {
+            KTimer kt(ctx, K_ARNOLDI_FINISH);
+            launch_k(kt, dgs_hess_kernel, dim3(R), dim3(256), (size_t)(3 * jcap + 1) * sizeof(double2), st, j, jb,
+                     maxit, nchunk, W.partial.as<double2>(), W.coef.as<double2>(), W.hsum.as<double2>(),
+                     W.H.as<double2>(), W.R.as<double2>(), W.g.as<double2>(), W.cs.as<double2>(), W.sn.as<double2>(),
+                     dst, B);
+        }
+        if (jb || j < maxit) {
+            {
+                KTimer kt(ctx, K_CGS_UPDATE);
+                launch_k(kt, dgs_update_kernel, dim3(nupd + (jcap + 1 + 3) / 4, R), dim3(256), 0, st, n, j, jb, maxit,
+                         nupd, Vb, W.z.as<double2>(), W.coef.as<double2>(), W.H.as<double2>(), W.hsum.as<double2>(),
+                         W.npart.as<double>(), dst, B);
+            }
+            KTimer kt(ctx, K_KRYLOV_NORM);
+            launch_k(kt, dgs_normalize_kernel, gv, dim3(256), 0, st, n, j, jb, maxit, nupd, W.npart.as<double>(), Vb,
+                     W.coef.as<double2>(), u_out, dst, B);
+        }
+        BEM_HIP(hipGetLastError());
+        return BEM_OK;
+    }
+
+    // Steps j0 .. j0 + BATCH - 1 (all below maxit) as one graph launch.  The
+    // graph of j0's range is captured on first use: BATCH steps whose kernels
+    // add the device step base W.jb to their step offset, the operator read
+    // from the fixed operand W.u.  The base is set by a one-thread kernel
+    // before each launch.  Capture runs on the context's capture stream (the
+    // library's launches follow ctx->stream, swapped for the capture), so the
+    // main stream may be the null stream.  Per-kernel event timing is off
+    // inside graphs.
+    bem_status graph_batch(GraphCache &gc, int j0, int maxit, bool acc64, int batch)
+    {
+        bem_ctx *ctx = p->ctx;
+        hipStream_t st = ctx->stream;
+        gc.st = st;
+        const int range = j0 / GRAPH_SPAN;
+        const int key = 2 * range + (acc64 ? 1 : 0);
+        auto it = gc.exec.find(key);
+        if (it == gc.exec.end()) {
+            const int jcap = std::min((range + 1) * GRAPH_SPAN - 1, maxit - 1);
+            const int64_t ustride = R > 1 ? (int64_t)n : 0;
+            if (!ctx->capture) BEM_HIP(hipStreamCreateWithFlags(&ctx->capture, hipStreamNonBlocking));
+            hipStream_t cs = ctx->capture;
+            hipGraph_t g = nullptr;
+            BEM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            bem_status s = BEM_OK;
+            ctx->stream = cs;
+            {
+                NoTiming nt;
+                for (int q = 0; q < batch && !s; ++q)
+                    s = step(q, W.jb.as<int>(), jcap, maxit, W.u.as<double2>(), ustride, W.u.as<double2>(), acc64);
+            }
+            ctx->stream = st;
+            const hipError_t e = hipStreamEndCapture(cs, &g);
+            if (s) {
+                if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+                return s;
+            }
+            BEM_HIP(e);
+            hipGraphExec_t x = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            BEM_HIP(ei);
+            it = gc.exec.emplace(key, x).first;
+        }
+        hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, st, W.jb.as<int>(), j0);
+        BEM_HIP(hipGetLastError());
+        BEM_HIP(hipGraphLaunch(it->second, st));
+        return BEM_OK;
+    }
 
     // R independent GMRES runs without restart on M^-1 A x = r0 (r0 already
     // preconditioned; run r's start vector at r0 + r r0stride), x0 = 0,
@@ -2379,43 +2509,33 @@ struct Gmres {
                 if (!k[r].done) return false;
             return true;
         };
-        // step j applies the operator to u_j and completes dimension j (j = maxit: completion only)
-        for (int j = 0; j <= maxit && !stop; ++j) {
-            const double2 *vj = Vb + (size_t)j * n;
+        // step j applies the operator to u_j and completes dimension j (j = maxit: completion only).
+        // Whole batches of BATCH full steps after the first go out as one captured HIP graph per
+        // range of GRAPH_SPAN step indices (device step base, grids sized for the range's end).
+        const bool graphs = p->graphs && maxit >= 2 * BATCH;
+        if (graphs) {
+            bem_status q = dev_alloc(ctx, W.u, (size_t)std::max(R, 1) * n * sizeof(double2));
+            if (!q) q = dev_alloc(ctx, W.jb, sizeof(int));
+            if (q) return q;
+            BEM_HIP(hipMemcpy2DAsync(W.u.ptr, (size_t)n * sizeof(double2), Vb,
+                                     (size_t)(R > 1 ? B.basis : n) * sizeof(double2), (size_t)n * sizeof(double2),
+                                     R, hipMemcpyDeviceToDevice, st));
+        }
+        GraphCache gc;
+        for (int j = 0; j <= maxit && !stop;) {
             bem_status s;
-            if (pm)
-                s = apply_ext_form(p, *pm, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>());
-            else if (bb)
-                s = block_apply(p, A, *bb, R, vj, B.basis, W.y.as<double2>(), B.vec, W.z.as<double2>(), B.vec, true,
-                                dst);
-            else
-                s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>(), acc64);
-            if (s) return s;
-            {
-                KTimer kt(ctx, K_CGS_DOTS);
-                launch_k(kt, dgs_dots_kernel, dim3(nchunk, (j + 1 + 3) / 4, R), dim3(256), 0, st, n, j, Vb,
-                         W.z.as<double2>(), W.partial.as<double2>(), dst, B);
+            if (graphs && !sync_mode && j >= BATCH && j % BATCH == 0 && j + BATCH <= maxit) {
+                s = graph_batch(gc, j, maxit, acc64, BATCH);
+                if (s) return s;
+                j += BATCH;
+                graph_steps += BATCH;
+            } else {
+                s = step(j, nullptr, j, maxit, Vb + (size_t)j * n, B.basis, graphs ? W.u.as<double2>() : nullptr,
+                         acc64);
+                if (s) return s;
+                ++j;
             }
-            {
-                KTimer kt(ctx, K_ARNOLDI_FINISH);
-                launch_k(kt, dgs_hess_kernel, dim3(R), dim3(256), (size_t)(3 * j + 1) * sizeof(double2), st, j, maxit,
-                         nchunk, W.partial.as<double2>(), W.coef.as<double2>(), W.hsum.as<double2>(),
-                         W.H.as<double2>(), W.R.as<double2>(), W.g.as<double2>(), W.cs.as<double2>(),
-                         W.sn.as<double2>(), dst, B);
-            }
-            if (j < maxit) {
-                {
-                    KTimer kt(ctx, K_CGS_UPDATE);
-                    launch_k(kt, dgs_update_kernel, dim3(nupd + (j + 1 + 3) / 4, R), dim3(256), 0, st, n, j, maxit,
-                             nupd, Vb, W.z.as<double2>(), W.coef.as<double2>(), W.H.as<double2>(),
-                             W.hsum.as<double2>(), W.npart.as<double>(), dst, B);
-                }
-                KTimer kt(ctx, K_KRYLOV_NORM);
-                launch_k(kt, dgs_normalize_kernel, gv, dim3(256), 0, st, n, j, maxit, nupd, W.npart.as<double>(), Vb,
-                         W.coef.as<double2>(), dst, B);
-            }
-            BEM_HIP(hipGetLastError());
-            const int issued = j + 1;
+            const int issued = j;
             KrylovState *hs = hstate + (size_t)slot * R;
             if (sync_mode) {
                 BEM_HIP(hipMemcpyAsync(hs, dst, sb, hipMemcpyDeviceToHost, st));
@@ -2931,6 +3051,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         stats->t_assembly_ms = p->t_assembly_ms;
         stats->t_solve_ms = t_solve;
         stats->t_iter_ms = total_it > 0 ? t_solve / total_it : 0.0;
+        stats->graph_steps = gm.graph_steps;
     }
     return all_conv ? BEM_OK : set_error(BEM_W_NOCONV, "GMRES reached maxit before the tolerance");
 }
@@ -3059,6 +3180,7 @@ bem_status ext_form_solve_impl(bem_problem *p, int form, const double *dirs, int
         stats->t_assembly_ms = p->t_assembly_ms;
         stats->t_solve_ms = t_solve;
         stats->t_iter_ms = total_it > 0 ? t_solve / total_it : 0.0;
+        stats->graph_steps = gm.graph_steps;
     }
     return all_conv ? BEM_OK : set_error(BEM_W_NOCONV, "GMRES reached maxit before the tolerance");
 }
