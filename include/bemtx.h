@@ -144,6 +144,20 @@ bem_status bem_ctx_trim(bem_ctx *ctx);
 bem_status bem_ctx_set_kernel_timing(bem_ctx *ctx, uint32_t kernel_mask);
 bem_status bem_ctx_kernel_time(bem_ctx *ctx, const char *kernel, double *total_ms, int64_t *launches);
 
+/* Size of the assembly strips of the meshes created on this context from
+ * now on, in block-pair tiles (0: the default, 65536).  The regular-pair
+ * assembly (Sec. 5.1) computes the interactions of every pair of 16-triangle
+ * blocks as tiles of per-vertex partial sums, strip by strip over
+ * consecutive rows of the block-pair triangle, and gathers each strip into
+ * the dense operators while the next strip is computed; the tile scratch
+ * holds two strips (each strip at least one row of nb tiles: 2 x 65536 x
+ * 36,864 B = 4.8 GB in FP64 at the default, half that in complex64),
+ * whatever the mesh size.  Smaller strips need less memory and take a
+ * little longer (more launches, each with its ramp and tail).  Entries fed by several strips are summed strip
+ * by strip, so the strip size changes the last bits of those entries.
+ * BEM_E_ARG for a negative count. */
+bem_status bem_ctx_set_strip_tiles(bem_ctx *ctx, int64_t tiles);
+
 /* A triangle mesh Gamma_int or Gamma_ext (Sec. 3): checks that it is a closed,
  * consistently oriented 2-manifold with positive enclosed volume, no
  * degenerate triangle and no unused vertex (BEM_E_MESH otherwise), and builds

@@ -62,6 +62,7 @@ SIGNATURES = {
     "bem_problem_set_mass_apply": (c_status, [vp, i32]),
     "bem_problem_mass_apply": (c_status, [vp, ctypes.POINTER(i32)]),
     "bem_problem_set_graphs": (c_status, [vp, i32]),
+    "bem_ctx_set_strip_tiles": (c_status, [vp, ctypes.c_int64]),
     "bem_solve_pmchwt": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),
     "bem_pmchwt_matvec": (c_status, [vp, vp, vp, i32, i32]),
     "bem_solve_hc_neumann": (c_status, [vp, vp, i32, ctypes.POINTER(SolverOpts), vp, i32, ctypes.POINTER(Stats)]),

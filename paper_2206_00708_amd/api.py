@@ -60,6 +60,11 @@ class Context:
                "cgs_dots", "cgs_update", "arnoldi_finish", "mass_inverse", "block_gemm", "mass_gemm",
                "krylov_normalize", "field", "mortar")
 
+    def set_strip_tiles(self, tiles=0):
+        """bem_ctx_set_strip_tiles: block-pair tiles per assembly strip of the
+        meshes created on this context from now on (0: the default)."""
+        _check(N.load().bem_ctx_set_strip_tiles(self._h, int(tiles)))
+
     def set_kernel_timing(self, kernels=()):
         """Time every launch of the named kernels with HIP events (empty: off)."""
         mask = 0

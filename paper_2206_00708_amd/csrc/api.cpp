@@ -265,6 +265,10 @@ void bem_ctx_destroy(bem_ctx *ctx)
         (void)hipStreamDestroy(ctx->aux);
     }
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+    if (ctx->gather) {
+        (void)hipStreamSynchronize(ctx->gather);
+        (void)hipStreamDestroy(ctx->gather);
+    }
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     if (ctx->release_ev) (void)hipEventDestroy(ctx->release_ev);
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
@@ -289,6 +293,14 @@ bem_status bem_ctx_trim(bem_ctx *ctx)
     }
     std::lock_guard<std::mutex> lk(ctx->mem_mu);
     drop_cached(ctx, 0);
+    return BEM_OK;
+}
+
+bem_status bem_ctx_set_strip_tiles(bem_ctx *ctx, int64_t tiles)
+{
+    if (!ctx) return set_error(BEM_E_ARG, "null context");
+    if (tiles < 0) return set_error(BEM_E_ARG, "strip tiles must be >= 0");
+    ctx->strip_tiles = tiles == 0 ? ASM_STRIP_TILES : tiles;
     return BEM_OK;
 }
 
@@ -331,7 +343,7 @@ bem_status bem_mesh_create(bem_ctx *ctx, const double *xyz, int64_t nv, const in
     m->h.nt = nt;
     m->h.xyz_user.assign(xyz, xyz + 3 * nv);
     m->h.tri_user.assign(tri, tri + 3 * nt);
-    bem_status s = mesh_prepare(m->h);
+    bem_status s = mesh_prepare(m->h, ctx->strip_tiles);
     if (s == BEM_OK) s = upload(ctx, m->d.perm, m->h.int_of_v);
     if (s == BEM_OK) s = upload(ctx, m->d.xyz, m->h.xyz);
     if (s == BEM_OK) s = upload(ctx, m->d.tri, m->h.tri);
@@ -341,6 +353,7 @@ bem_status bem_mesh_create(bem_ctx *ctx, const double *xyz, int64_t nv, const in
     if (s == BEM_OK) s = upload(ctx, m->d.slot_ent, m->h.slot_ent);
     if (s == BEM_OK) s = upload(ctx, m->d.memb_ptr, m->h.memb_ptr);
     if (s == BEM_OK) s = upload(ctx, m->d.memb, m->h.memb);
+    if (s == BEM_OK) s = upload(ctx, m->d.strip_rows, m->h.strip_rows);
     if (s == BEM_OK) s = upload(ctx, m->d.sing, m->h.sing);
     if (s == BEM_OK) s = upload(ctx, m->d.near_i, m->h.near_i);
     if (s == BEM_OK) s = upload(ctx, m->d.near_j, m->h.near_j);

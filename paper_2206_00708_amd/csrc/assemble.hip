@@ -91,8 +91,17 @@ struct TileArgs {
     int32_t nb;
     double k;
     double kim;            // imaginary part of the wavenumber (read by the absorbing instantiation only)
-    double2 *scratch;      // [tile][SMAX*SMAX][op]
+    double2 *scratch;      // [tile - tile_base][SMAX*SMAX][op]
+    int64_t tile_base;     // first tile of the strip the scratch holds
 };
+
+// tiles of assembly strip s: rows b in [strip_b[s], strip_b[s + 1]), nb - b each
+inline int64_t strip_tiles(const MeshData &h, int s)
+{
+    int64_t n = 0;
+    for (int b = h.strip_b[s]; b < h.strip_b[s + 1]; ++b) n += h.nb - b;
+    return n;
+}
 
 __device__ inline void tile_of(int64_t t, int nb, int &b1, int &b2)
 {
@@ -286,7 +295,8 @@ struct TileArgsF {
     int32_t nb;
     double k;
     double kim;            // imaginary part of the wavenumber (read by the absorbing instantiation only)
-    float2 *scratch;       // [tile][SMAX*SMAX][op]
+    float2 *scratch;       // [tile - tile_base][SMAX*SMAX][op]
+    int64_t tile_base;
 };
 
 // CK: complex wavenumber k + i kim (an absorbing medium), G = exp(i k r - kim r) / (4 pi r);
@@ -351,7 +361,7 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
     }
 
     // ---- per-slot reduction through LDS, one operator at a time
-    double2 *out = A.scratch + tile * (4 * SMAX * SMAX);
+    double2 *out = A.scratch + (tile - A.tile_base) * (4 * SMAX * SMAX);
 #pragma unroll 1
     for (int op = 0; op < 4; ++op) {
         if (op == 3 && active) {
@@ -525,7 +535,7 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
         sr *= scale;
         si *= scale;
     }
-    float2 *out = A.scratch + tile * (4 * SMAX * SMAX);
+    float2 *out = A.scratch + (tile - A.tile_base) * (4 * SMAX * SMAX);
 #pragma unroll 1
     for (int op = 0; op < 4; ++op) {
         if (op == 3 && active) {
@@ -559,26 +569,53 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
     }
 }
 
-// dense entry (i, j) from the tiles of the blocks that contain i and j
-template <class C2>
-__global__ __launch_bounds__(256) void gather_tiles_kernel(int nv, int nb, const int32_t *__restrict__ memb_ptr,
-                                                           const int32_t *__restrict__ memb, const C2 *__restrict__ scratch,
-                                                           C2 *__restrict__ V, C2 *__restrict__ K, C2 *__restrict__ T,
-                                                           C2 *__restrict__ D)
+// The contributions to dense entry (i, j) of the tiles of one strip (tile
+// rows [b0, b1), tile t at (t - tile_base) in the scratch): every tile
+// (min(bi, bj), max(bi, bj)) of the blocks bi, bj containing i and j whose
+// first block lies in the strip, in membership order.  The strip of the
+// smallest membership of i and j is the first to reach (i, j) and writes
+// it; later strips add their share (strips run in order on one stream).
+// ROWS: i runs over the strip's row list, j over [lo, nv) (grid (ceil((nv -
+// lo) / 256), rows)); else j over the row list and i over [lo, nv) outside
+// the list (block (64, 4), grid (ceil(rows / 64), ceil((nv - lo) / 4))).
+// Every entry a strip reaches has i or j in its row list, and j >= lo or i >= lo.
+template <class C2, bool ROWS>
+__global__ __launch_bounds__(256) void gather_strip_kernel(int nv, int nb, int b0, int b1, int64_t tile_base, int lo,
+                                                           const int32_t *__restrict__ rows, int nrows,
+                                                           const int32_t *__restrict__ memb_ptr,
+                                                           const int32_t *__restrict__ memb,
+                                                           const C2 *__restrict__ scratch, C2 *__restrict__ V,
+                                                           C2 *__restrict__ K, C2 *__restrict__ T, C2 *__restrict__ D)
 {
     using R = decltype(C2::x);
-    const int i = blockIdx.y;
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nv) return;
+    int i, j;
+    if (ROWS) {
+        i = rows[blockIdx.y];
+        j = lo + (int)blockIdx.x * 256 + (int)threadIdx.x;
+        if (j >= nv) return;
+    } else {
+        const int r = (int)blockIdx.x * 64 + (int)threadIdx.x;
+        i = lo + (int)blockIdx.y * 4 + (int)threadIdx.y;
+        if (r >= nrows || i >= nv) return;
+        j = rows[r];
+    }
     const int pi0 = memb_ptr[i], pi1 = memb_ptr[i + 1];
     const int pj0 = memb_ptr[j], pj1 = memb_ptr[j + 1];
+    if (!ROWS)   // rows of the list are the other pass's
+        for (int p = pi0; p < pi1; ++p) {
+            const int bi = memb[p] >> 8;
+            if (bi >= b0 && bi < b1) return;
+        }
     R vx = 0, vy = 0, kx = 0, ky = 0, tx = 0, ty = 0, dx = 0, dy = 0;
+    bool any = false;
     for (int p = pi0; p < pi1; ++p) {
         const int mi = memb[p], bi = mi >> 8, si = mi & 255;
         for (int q = pj0; q < pj1; ++q) {
             const int mj = memb[q], bj = mj >> 8, sj = mj & 255;
-            const int lo = bi < bj ? bi : bj, hi = bi < bj ? bj : bi;
-            const int64_t tile = (int64_t)lo * nb - (int64_t)lo * (lo - 1) / 2 + (hi - lo);
+            const int lo_b = bi < bj ? bi : bj, hi_b = bi < bj ? bj : bi;
+            if (lo_b < b0 || lo_b >= b1) continue;
+            any = true;
+            const int64_t tile = (int64_t)lo_b * nb - (int64_t)lo_b * (lo_b - 1) / 2 + (hi_b - lo_b) - tile_base;
             const C2 *tl = scratch + tile * (4 * SMAX * SMAX);
             if (bi <= bj) {
                 const int e = si * SMAX + sj;
@@ -595,11 +632,20 @@ __global__ __launch_bounds__(256) void gather_tiles_kernel(int nv, int nb, const
         }
     }
     const int64_t o = (int64_t)i * op_ld(nv) + j;
-    V[o] = C2{vx, vy};
-    K[o] = C2{kx, ky};
-    T[o] = C2{tx, ty};
-    D[o] = C2{dx, dy};
-    if (j == nv - 1)   // padding columns of the row: zero
+    const int first = min(memb[pi0] >> 8, memb[pj0] >> 8);   // smallest membership (lists ascend by block)
+    if (first >= b0) {   // this strip is the first to reach (i, j)
+        V[o] = C2{vx, vy};
+        K[o] = C2{kx, ky};
+        T[o] = C2{tx, ty};
+        D[o] = C2{dx, dy};
+    } else if (any) {
+        const C2 v = V[o], k = K[o], t = T[o], d = D[o];
+        V[o] = C2{v.x + vx, v.y + vy};
+        K[o] = C2{k.x + kx, k.y + ky};
+        T[o] = C2{t.x + tx, t.y + ty};
+        D[o] = C2{d.x + dx, d.y + dy};
+    }
+    if (ROWS && j == nv - 1 && (memb[pi0] >> 8) >= b0)   // padding columns of the row: zero, once
         for (int64_t c = 1; c < op_ld(nv) - nv + 1; ++c) {
             V[o + c] = C2{0, 0};
             K[o + c] = C2{0, 0};
@@ -792,74 +838,108 @@ bem_status launch_geometry(const bem_mesh *m, hipStream_t st)
     return BEM_OK;
 }
 
-// tile scratch of one mesh; entry size 16 B (complex128) or 8 B (complex64)
+// tile scratch of one mesh: two strips' tiles (or one when the mesh has a
+// single strip); entry size 16 B (complex128) or 8 B (complex64)
 size_t tile_scratch_bytes(const bem_mesh *m, size_t entry_bytes)
 {
-    const int64_t nb = m->h.nb;
-    return (size_t)(nb * (nb + 1) / 2) * 4 * SMAX * SMAX * entry_bytes;
+    const MeshData &h = m->h;
+    const int ns = (int)h.strip_b.size() - 1;
+    int64_t most = 0;
+    for (int s = 0; s < ns; ++s) most = std::max(most, strip_tiles(h, s));
+    return (size_t)(ns > 1 ? 2 : 1) * (size_t)most * 4 * SMAX * SMAX * entry_bytes;
 }
 
+// Regular-pair assembly strip by strip: the tiles of strip s into half s % 2
+// of the scratch on the main stream; its gather into the operators on the
+// context's gather stream, which overlaps the next strip's tiles.  The main
+// stream reuses a half once the gather of two strips before is done, and
+// waits for the last gather before returning.
 bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, void *scratch, void *ops[4], hipStream_t st)
 {
-    const int64_t nb = m->h.nb;
-    const int64_t ntiles = nb * (nb + 1) / 2;
-    const int64_t chunk = 1 << 20;
-    if (!fp32) {
-        TileArgs A;
-        A.geo = m->d.geo.as<TriGeo>();
-        A.tri = m->d.tri.as<int32_t>();
-        A.blk_start = m->d.blk_start.as<int32_t>();
-        A.blk_nslot = m->d.blk_nslot.as<int32_t>();
-        A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
-        A.slot_ent = m->d.slot_ent.as<uint8_t>();
-        A.nb = (int32_t)nb;
-        A.k = k;
-        A.kim = kim;
-        A.scratch = static_cast<double2 *>(scratch);
-        for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
-            const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
-            KTimer kt(m->ctx, K_REGULAR);
-            if (kim != 0.0)
-                launch_k(kt, regular_tiles_kernel<true>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
-            else
-                launch_k(kt, regular_tiles_kernel<false>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
-            BEM_HIP(hipGetLastError());
+    bem_ctx *ctx = m->ctx;
+    const MeshData &h = m->h;
+    const int64_t nb = h.nb;
+    const int nv = (int)h.nv;
+    const int ns = (int)h.strip_b.size() - 1;
+    const size_t eb = fp32 ? sizeof(float2) : sizeof(double2);
+    int64_t most = 0;
+    for (int s = 0; s < ns; ++s) most = std::max(most, strip_tiles(h, s));
+    const size_t half = (size_t)most * 4 * SMAX * SMAX * eb;
+    if (!ctx->gather) BEM_HIP(hipStreamCreateWithFlags(&ctx->gather, hipStreamNonBlocking));
+    hipStream_t gs = ctx->gather;
+    // events: [0] main-stream work before the assembly, [1 + b] tiles of half b done, [3 + b] its gather done
+    hipEvent_t ev[5];
+    for (int q = 0; q < 5; ++q) BEM_HIP(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
+    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int q = 0; q < 5; ++q) (void)hipEventDestroy(e[q]); } } guard{ev};
+    BEM_HIP(hipEventRecord(ev[0], st));
+    BEM_HIP(hipStreamWaitEvent(gs, ev[0], 0));   // the operator blocks may have served earlier main-stream work
+    for (int s = 0; s < ns; ++s) {
+        const int b0 = h.strip_b[s], b1 = h.strip_b[s + 1], hb = s % 2;
+        const int64_t t0 = b0 * nb - (int64_t)b0 * (b0 - 1) / 2, n = strip_tiles(h, s);
+        char *buf = static_cast<char *>(scratch) + hb * half;
+        if (s >= 2) BEM_HIP(hipStreamWaitEvent(st, ev[3 + hb], 0));
+        {
+            KTimer kt(ctx, K_REGULAR);
+            if (!fp32) {
+                TileArgs A;
+                A.geo = m->d.geo.as<TriGeo>();
+                A.tri = m->d.tri.as<int32_t>();
+                A.blk_start = m->d.blk_start.as<int32_t>();
+                A.blk_nslot = m->d.blk_nslot.as<int32_t>();
+                A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
+                A.slot_ent = m->d.slot_ent.as<uint8_t>();
+                A.nb = (int32_t)nb;
+                A.k = k;
+                A.kim = kim;
+                A.scratch = reinterpret_cast<double2 *>(buf);
+                A.tile_base = t0;
+                if (kim != 0.0)
+                    launch_k(kt, regular_tiles_kernel<true>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+                else
+                    launch_k(kt, regular_tiles_kernel<false>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+            } else {
+                TileArgsF A;
+                A.geof = m->d.geof.as<TriGeoF>();
+                A.tri = m->d.tri.as<int32_t>();
+                A.blk_start = m->d.blk_start.as<int32_t>();
+                A.blk_nslot = m->d.blk_nslot.as<int32_t>();
+                A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
+                A.slot_ent = m->d.slot_ent.as<uint8_t>();
+                A.nb = (int32_t)nb;
+                A.k = k;
+                A.kim = kim;
+                A.scratch = reinterpret_cast<float2 *>(buf);
+                A.tile_base = t0;
+                if (kim != 0.0)
+                    launch_k(kt, regular_tiles_f32_kernel<true>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+                else
+                    launch_k(kt, regular_tiles_f32_kernel<false>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
+            }
         }
-    } else {
-        TileArgsF A;
-        A.geof = m->d.geof.as<TriGeoF>();
-        A.tri = m->d.tri.as<int32_t>();
-        A.blk_start = m->d.blk_start.as<int32_t>();
-        A.blk_nslot = m->d.blk_nslot.as<int32_t>();
-        A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
-        A.slot_ent = m->d.slot_ent.as<uint8_t>();
-        A.nb = (int32_t)nb;
-        A.k = k;
-        A.kim = kim;
-        A.scratch = static_cast<float2 *>(scratch);
-        for (int64_t t0 = 0; t0 < ntiles; t0 += chunk) {
-            const int64_t n = ntiles - t0 < chunk ? ntiles - t0 : chunk;
-            KTimer kt(m->ctx, K_REGULAR);
-            if (kim != 0.0)
-                launch_k(kt, regular_tiles_f32_kernel<true>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
-            else
-                launch_k(kt, regular_tiles_f32_kernel<false>, dim3((unsigned)n), dim3(256), 0, st, A, t0);
-            BEM_HIP(hipGetLastError());
+        BEM_HIP(hipGetLastError());
+        BEM_HIP(hipEventRecord(ev[1 + hb], st));
+        BEM_HIP(hipStreamWaitEvent(gs, ev[1 + hb], 0));
+        const int r0 = h.strip_rptr[s], nr = h.strip_rptr[s + 1] - r0, lo = h.strip_lo[s];
+        const int32_t *rows = m->d.strip_rows.as<int32_t>() + r0;
+        const dim3 ga((unsigned)((nv - lo + 255) / 256), (unsigned)nr), gb((unsigned)((nr + 63) / 64),
+                                                                          (unsigned)((nv - lo + 3) / 4));
+        KTimer kt(ctx, K_GATHER);
+#define GATHER_ARGS(C2)                                                                                              \
+    nv, (int)nb, b0, b1, t0, lo, rows, nr, m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(),                    \
+        reinterpret_cast<const C2 *>(buf), static_cast<C2 *>(ops[0]), static_cast<C2 *>(ops[1]),                     \
+        static_cast<C2 *>(ops[2]), static_cast<C2 *>(ops[3])
+        if (!fp32) {
+            launch_k(kt, gather_strip_kernel<double2, true>, ga, dim3(256), 0, gs, GATHER_ARGS(double2));
+            hipLaunchKernelGGL((gather_strip_kernel<double2, false>), gb, dim3(64, 4), 0, gs, GATHER_ARGS(double2));
+        } else {
+            launch_k(kt, gather_strip_kernel<float2, true>, ga, dim3(256), 0, gs, GATHER_ARGS(float2));
+            hipLaunchKernelGGL((gather_strip_kernel<float2, false>), gb, dim3(64, 4), 0, gs, GATHER_ARGS(float2));
         }
+#undef GATHER_ARGS
+        BEM_HIP(hipGetLastError());
+        BEM_HIP(hipEventRecord(ev[3 + hb], gs));
     }
-    const int nv = (int)m->h.nv;
-    KTimer kt(m->ctx, K_GATHER);
-    if (!fp32)
-        launch_k(kt, gather_tiles_kernel<double2>, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, (int)nb,
-                 m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(), static_cast<const double2 *>(scratch),
-                 static_cast<double2 *>(ops[0]), static_cast<double2 *>(ops[1]), static_cast<double2 *>(ops[2]),
-                 static_cast<double2 *>(ops[3]));
-    else
-        launch_k(kt, gather_tiles_kernel<float2>, dim3((nv + 255) / 256, nv), dim3(256), 0, st, nv, (int)nb,
-                 m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(), static_cast<const float2 *>(scratch),
-                 static_cast<float2 *>(ops[0]), static_cast<float2 *>(ops[1]), static_cast<float2 *>(ops[2]),
-                 static_cast<float2 *>(ops[3]));
-    BEM_HIP(hipGetLastError());
+    BEM_HIP(hipStreamWaitEvent(st, ev[3 + (ns - 1) % 2], 0));   // gathers run in order: the last covers all
     return BEM_OK;
 }
 

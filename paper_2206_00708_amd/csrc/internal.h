@@ -25,6 +25,9 @@ namespace bemtx {
 constexpr int BT = 16;
 constexpr int SMAX = 24;
 constexpr int LMAX = 12;
+// block-pair tiles per assembly strip: the tile scratch holds two strips
+// (FP64: 2 x 2.4 GB) whatever the mesh size
+constexpr int64_t ASM_STRIP_TILES = 65536;
 constexpr int NG_MAX = 16;
 
 // Row stride (elements) of the dense operator matrices: a multiple of 32, so
@@ -130,6 +133,10 @@ struct MeshData {
     HVec<uint8_t> slot_ent;     // [nb][SMAX][LMAX] = tlocal*3 + corner
     HVec<int32_t> memb_ptr;     // [nv+1]
     HVec<int32_t> memb;         // block<<8 | slot
+    // assembly strips: tile rows (first block of the tile) [strip_b[s], strip_b[s+1]), at most ASM_STRIP_TILES
+    // tiles each (one block row at least); strip_rows[strip_rptr[s] ..] the vertices with a membership in the
+    // strip's blocks (ascending); strip_lo[s] the first vertex with a membership at or after strip_b[s]
+    HVec<int32_t> strip_b, strip_rptr, strip_rows, strip_lo;
     // singular pairs and near-field scatter lists
     HVec<SingPair> sing;        // sorted by kind (3, 2, 1)
     int32_t nsing_kind[4] = {0, 0, 0, 0};
@@ -144,7 +151,7 @@ struct MeshDev {
     DevMem perm;   // caller vertex -> internal vertex (int32)
     DevMem geof;   // TriGeoF table
     DevMem xyz, tri, blk_start, blk_nslot, slot_cnt, slot_ent, memb_ptr, memb, sing, near_i, near_j,
-        near_ptr, near_src, near_row, star_ptr, star_ent, geo;
+        near_ptr, near_src, near_row, star_ptr, star_ent, geo, strip_rows;
 };
 
 // CSR in internal numbering
@@ -172,7 +179,8 @@ bem_status dev_alloc(bem_ctx *ctx, DevMem &m, size_t bytes, hipStream_t use = nu
 // threads (serial below `grain` items).  Ranges are fixed by n, so results
 // that each range writes to its own slots are independent of scheduling.
 void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, int64_t)> &f);
-bem_status mesh_prepare(MeshData &m);                    // validation + tables (host)
+// validation + tables (host); assembly strips of at most strip_tiles block-pair tiles
+bem_status mesh_prepare(MeshData &m, int64_t strip_tiles = ASM_STRIP_TILES);
 void mass_csr(const MeshData &m, Csr &M);
 bem_status mortar_csr(const MeshData &mi, const MeshData &me, Csr &P, double *coverage_defect);
 // candidate search of the mortar assembly: the cones of both meshes'
@@ -244,6 +252,9 @@ struct bem_ctx {
     // stream that GMRES graphs are captured on (capture records, runs nothing;
     // the graphs are launched on `stream`, which may be the null stream)
     hipStream_t capture = nullptr;
+    // stream of the assembly's gathers, which overlap the next strip's tiles on `stream`
+    hipStream_t gather = nullptr;
+    int64_t strip_tiles = bemtx::ASM_STRIP_TILES;   // block-pair tiles per assembly strip of meshes made here
     size_t budget = 0;
     size_t in_use = 0;
     // per-kernel timing (HIP events around each launch on `stream`)

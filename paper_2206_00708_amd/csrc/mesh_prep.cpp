@@ -180,7 +180,7 @@ void parallel_for(int64_t n, int64_t grain, const std::function<void(int64_t, in
     pool.run((int)nth, [&](int part) { f(n * part / nth, n * (part + 1) / nth); });
 }
 
-bem_status mesh_prepare(MeshData &m)
+bem_status mesh_prepare(MeshData &m, int64_t strip_tiles)
 {
     const int64_t nv = m.nv, nt = m.nt;
     const double *X = m.xyz_user.data();
@@ -336,6 +336,40 @@ bem_status mesh_prepare(MeshData &m)
         std::vector<int32_t> mfill(m.memb_ptr.begin(), m.memb_ptr.end() - 1);
         for (int b = 0; b < nb; ++b)
             for (int s = 0; s < m.blk_nslot[b]; ++s) m.memb[mfill[m.blk_slots[(size_t)b * SMAX + s]]++] = b << 8 | s;
+    }
+
+    // ---- assembly strips: consecutive tile rows b (tiles (b, b2), b2 >= b: nb - b of them) up to
+    // strip_tiles tiles, the vertices each strip's tiles reach as rows, and the first vertex that
+    // can receive a contribution from the strip (its last membership at or after the strip's first block)
+    m.strip_b.assign(1, 0);
+    for (int b = 0; b < nb;) {
+        int64_t tiles = 0;
+        int e = b;
+        while (e < nb && (e == b || tiles + (nb - e) <= strip_tiles)) tiles += nb - e++;
+        m.strip_b.push_back(e);
+        b = e;
+    }
+    const int ns = (int)m.strip_b.size() - 1;
+    m.strip_rptr.assign(1, 0);
+    m.strip_rows.clear();
+    m.strip_lo.assign(ns, (int32_t)nv);
+    {
+        std::vector<int32_t> rows;
+        for (int s = 0; s < ns; ++s) {
+            rows.clear();
+            for (int b = m.strip_b[s]; b < m.strip_b[s + 1]; ++b)
+                for (int q = 0; q < m.blk_nslot[b]; ++q) rows.push_back(m.blk_slots[(size_t)b * SMAX + q]);
+            std::sort(rows.begin(), rows.end());
+            rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+            m.strip_rows.insert(m.strip_rows.end(), rows.begin(), rows.end());
+            m.strip_rptr.push_back((int32_t)m.strip_rows.size());
+        }
+        // strip_lo: strips in ascending first block, so one pass per vertex over the strips it reaches
+        for (int64_t v = 0; v < nv; ++v) {
+            const int maxb = m.memb[m.memb_ptr[v + 1] - 1] >> 8;
+            for (int s = 0; s < ns && m.strip_b[s] <= maxb; ++s)
+                if (m.strip_lo[s] > v) m.strip_lo[s] = (int32_t)v;
+        }
     }
 
     // ---- vertex stars (internal numbering)

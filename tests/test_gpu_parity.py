@@ -227,3 +227,29 @@ def test_projection_c2_sampled_rows(c2, orc):
 
 # Full-size trace parity (C2 solve against the oracle's exact discrete
 # solution) is in test_gpu_golden.py.
+
+
+@pytest.mark.parametrize("strip_tiles", [1, 37, 400])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_operators_strips(orc, strip_tiles, prec):
+    """The regular-pair assembly strip by strip: a context whose meshes take
+    tiny strips (one block row each, 37 tiles, 400 tiles) on the small
+    ellipsoid pair (642 / 700 vertices: about 80 blocks per mesh, so up to
+    80 strips, with entries fed by several strips summed strip by strip),
+    every entry of V, K, T, D of both meshes against the oracle: 1e-12 in
+    FP64, 2e-5 for the complex64 operators (the mixed form's tolerance)."""
+    ctx = B.Context(0)
+    ctx.set_strip_tiles(strip_tiles)
+    (xe, te), (xi, ti), _ = synth.make_pair(3, 3, "fib", 0.01, (1.0, 0.8, 0.6), int_n=700)
+    me, mi = B.Mesh(ctx, xe, te), B.Mesh(ctx, xi, ti)
+    p = B.Problem(ctx, me, mi, 6.0, 12.0, 1.0, 2.0, precision=B.C128 if prec == "fp64" else B.C64_MIXED)
+    p.assemble_operators()
+    bound = 1e-12 if prec == "fp64" else 2e-5
+    for mesh, (x, t, k) in enumerate(((xe, te, 6.0), (xi, ti, 12.0))):
+        ref = orc.assemble(x, t, k)
+        for op in "VKTD":
+            got = p.operator(mesh, op).cpu().numpy().astype(np.complex128)
+            e, em = _rel(got, ref[op]), _relmax(got, ref[op])
+            assert e < bound and em < bound, (strip_tiles, mesh, op, e, em)
+    del p, me, mi
+    ctx.close()
