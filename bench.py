@@ -64,15 +64,28 @@ MTF_REGIONS = {"source": "paper_2206_00708_amd/csrc/solve.hip",
                "regions": [("namespace {", "}  // namespace"),
                            ("// ---- symmetric tile form", "// y rows = sum of the tile partials")]}
 COUNTED_TRAFFIC = {
-    ("mtf_dense", "C2"): {"bytes": 2.000 * 171879.5 * 1024 + 1.000 * 2682.3 * 1024,
-                          "sha1": "332aed739a60646a5b6890a7427dea49685ce211", **MTF_REGIONS},
+    ("mtf_dense", "C3"): {"bytes": 2.000 * 2669813.6 * 1024 + 1.000 * 41682.5 * 1024,
+                          "sha1": "c5daf6dcba28df11083df99a2ef90042c1d8f7bc", **MTF_REGIONS},
 }
 
-# FP64 VALU counters of the regular-pair kernel per launch (rocprofv3 --pmc:
-# SQ_INSTS_VALU_FLOPS_FP64, SQ_INSTS_VALU_FLOPS_FP64_TRANS, SQ_INSTS_VALU,
-# SQ_ACTIVE_INST_VALU, SQ_BUSY_CYCLES), per workload, with the sha1 of
-# assemble.hip they were taken on.
-COUNTED_VALU = {}
+# FP64 VALU counters of the regular-pair kernel per launch (rocprofv3 --pmc,
+# kernels serialised by the counter collection), per workload, with the sha1
+# of assemble.hip they were taken on: FP64 flops (SQ_INSTS_VALU_FLOPS_FP64 x
+# 64 lanes), VALU instructions (SQ_INSTS_VALU), the VALU issue fraction
+# (SQ_INSTS_VALU x 4 cycles over the SIMD cycles of the launch, from
+# GRBM_GUI_ACTIVE per XCD x 1024 SIMDs) and the share of the FP64 flops in
+# the software sin/cos (the small-angle polynomials and the rotation by the
+# pair's base phase: 46 of the per-point-pair flops).
+COUNTED_VALU = {
+    ("regular_tiles", "C3"): {"flops_fp64": 1398312300.0 * 64, "valu_insts": 1114510835, "valu_busy": 0.579,
+                              "sincos_flop_share": 0.30, "isolated_launch_us": 3235.6,
+                              "source": "paper_2206_00708_amd/csrc/assemble.hip",
+                              "sha1": "64e8f72a77ba7401155739339304c59e0eb6b1fa"},
+    ("regular_tiles", "C2"): {"flops_fp64": 922141924.0 * 64, "valu_insts": 734252736, "valu_busy": 0.582,
+                              "sincos_flop_share": 0.30, "isolated_launch_us": 2288.0,
+                              "source": "paper_2206_00708_amd/csrc/assemble.hip",
+                              "sha1": "64e8f72a77ba7401155739339304c59e0eb6b1fa"},
+}
 
 
 def kernel_source_sha1(t):
@@ -103,9 +116,13 @@ def counted_valu(kernel, workload, launch_ms):
     if not t or kernel_source_sha1(t) != t["sha1"]:
         return None
     ach = t["flops_fp64"] / (launch_ms * 1e-3) / 1e12
+    iso = t["flops_fp64"] / (t["isolated_launch_us"] * 1e-6) / 1e12
     return {"flops_fp64_per_launch": t["flops_fp64"], "achieved": round(ach, 2), "peak": FP64_VEC_TFLOPS,
             "frac": round(ach / FP64_VEC_TFLOPS, 4), "valu_busy": t["valu_busy"],
-            "valu_insts_per_launch": t["valu_insts"], "sincos_flop_share": t.get("sincos_flop_share")}
+            "valu_insts_per_launch": t["valu_insts"], "sincos_flop_share": t.get("sincos_flop_share"),
+            "isolated": {"launch_us": t["isolated_launch_us"], "achieved": round(iso, 2),
+                         "frac": round(iso / FP64_VEC_TFLOPS, 4),
+                         "note": "launch duration under the counter run, kernels serialised (no gather beside it)"}}
 
 
 def golden(name):
@@ -691,18 +708,24 @@ def main():
     reg_flops = pairs * 36 * FLOP_PER_POINT_PAIR
     ms, n = ktimes["mtf_dense"]
     ach = mv_bytes / (ms / n * 1e-3) / 1e9
+    # the GMRES steps inside captured graphs carry no events: the timed launches are the steps issued one
+    # by one (the first batch and the last steps of each solve) and the residual products; the kernel's
+    # time per step is its average launch times its launches per step (one per Arnoldi step plus the
+    # final residual and the completing step)
+    mv_launches = head["gmres_iterations"] + 2
     roof_mv = {"kernel": "mtf_sym_tile", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counted_traffic("mtf_dense", name),
                "avg_launch_us": round(1e3 * ms / n, 2), "bytes_per_launch": mv_bytes,
-               "ms_per_step": round(ms / args.steps, 3)}
+               "timed_launches_per_step": round(n / args.steps, 1), "launches_per_step": mv_launches,
+               "ms_per_step": round(ms / n * mv_launches, 3)}
     ms, n = ktimes["regular_tiles"]
     ach = reg_flops / (ms / args.steps * 1e-3) / 1e12
     roof_reg = {"kernel": "regular_tiles", "bound": "alu", "achieved": round(ach, 2), "peak": FP64_VEC_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(ach / FP64_VEC_TFLOPS, 4), "traffic": None,
                 "avg_launch_us": round(1e3 * ms / n, 2), "flop_per_step_model": reg_flops,
                 "ms_per_step": round(ms / args.steps, 3), "counters": counted_valu("regular_tiles", name, ms / n)}
-    dominant = max(("mtf_dense", "regular_tiles"), key=lambda k: ktimes[k][0])
-    roof, roof_other = (roof_mv, roof_reg) if dominant == "mtf_dense" else (roof_reg, roof_mv)
+    dominant = max((roof_mv, roof_reg), key=lambda r: r["ms_per_step"])
+    roof, roof_other = (roof_mv, roof_reg) if dominant is roof_mv else (roof_reg, roof_mv)
     line = {
         "metric": "dense BEM assembly Gentries/s; solves/s vs plain FP64 at 1e-5 err; p99 latency",
         "value": round(entries * args.steps / r["total"] / 1e9, 4),
@@ -723,7 +746,9 @@ def main():
         **{k: v for k, v in head.items() if k not in ("workload", "gentries_per_s", "ms_per_step")},
         "kernel_ms_per_step": {k: round(v[0], 3) for k, v in r["breakdown"].items()},
         "kernel_launches_per_step": {k: v[1] for k, v in r["breakdown"].items()},
-        "kernel_breakdown_note": "one untimed step after the timed ones, with events on every listed kernel",
+        "kernel_breakdown_note": "one untimed step after the timed ones, with events on every listed kernel; the "
+                                 "GMRES steps inside captured graphs carry no events, so the Krylov-step kernels "
+                                 "count only the steps issued one by one",
         "tuned_shapes": {k: v for k, v in B.tune_table().items() if k.startswith("mtf-")},
     }
     if not args.no_c2 and name != "C2":
