@@ -271,13 +271,15 @@ bem_status bem_mtf_matvec(bem_problem *p, const void *x, void *y, int32_t strong
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
  * product of bem_mtf_matvec with its work buffers (the permuted input, the
  * weak and strong results and the kernels' partial sums) taken from one
- * static device array of 64 MiB per GPU instead of allocations.  x, y:
+ * static device array of 128 MiB per GPU instead of allocations.  x, y:
  * device pointers, complex128 [2 N_ext + 2 N_int] as above.  Asynchronous on
  * the context's stream: it calls no hipMalloc, hipFree or other allocating
  * routine, no synchronisation, and records no per-kernel timing.  The work
  * space needed is 3 n 16 bytes (rounded to 256) plus the partial sums,
- * 32 (N_ext + N_int) max(ceil(N_ext / 128), ceil(N_int / 128)) bytes (about
- * 49 MB for 10,242 + 8,002 vertices); a larger problem returns
+ * the larger of 32 (N_ext + N_int) max(ceil(N_ext / 64), ceil(N_int / 64))
+ * bytes (tile partials at the smaller tile edge the tuner may pick) and
+ * 96 n bytes (the two work sets of the sparse inverse-mass apply): about
+ * 96 MB for 10,242 + 8,002 vertices; a larger problem returns
  * BEM_E_UNSUPPORTED without launching anything.  All calls on one GPU share
  * that GPU's array: calls that overlap in time on one GPU (other streams or
  * contexts) race and must be ordered by the caller.  Same results as

@@ -2661,7 +2661,7 @@ bem_status matvec_impl(bem_problem *p, const void *x, void *y, int strong, bem_m
 // device is looked up once, at context creation with that device current,
 // and kept per device.
 
-constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
 static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 namespace {

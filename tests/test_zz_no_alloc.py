@@ -64,8 +64,9 @@ def test_noalloc_matches_matvec_two_calls(ctx, prec):
 
 
 def test_noalloc_rejects_oversized(ctx):
-    """12,000 + 12,000 vertices need about 74 MB of work space: rejected
-    before any launch (no assembly needed for the check)."""
+    """12,000 + 12,000 vertices need about 147 MB of work space (above the
+    128 MiB array): rejected before any launch (no assembly needed for the
+    check)."""
     xyz, tri = synth.meshes.fibonacci_sphere(12000)
     ext = inte = (xyz, synth.meshes.orient_outward(xyz, tri))
     me, mi = B.Mesh(ctx, *ext), B.Mesh(ctx, *inte)
