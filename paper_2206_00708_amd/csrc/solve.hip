@@ -1081,7 +1081,15 @@ static inline dim3 split_grid(int ne, int ni, int cwmax, int rw = 1)
 // every kernel returns at once when the state says the run has converged, so
 // steps issued ahead of the host's convergence check cost only their launch.
 
-constexpr int CGS_CHUNK = 4096;   // rows per partial dot product (few partials: a short fixed-order sum)
+// Rows per partial dot product: n / 8 rounded up to 256, between 1024 and
+// 4096 (at most about 9 partials per coefficient at large n, where the
+// Givens kernel sums them; at small n more, shorter chunks, so that more
+// waves share the sweep).
+__host__ __device__ inline int cgs_chunk(int n)
+{
+    const int c = ((n + 7) / 8 + 255) / 256 * 256;
+    return c < 1024 ? 1024 : (c > 4096 ? 4096 : c);
+}
 constexpr int UPD_ROWS = 64;      // rows per workgroup of the update sweep
 constexpr int MAXIT_CAP = 3000;   // Hessenberg column, rotations and g staged in LDS
 
@@ -1103,7 +1111,8 @@ __global__ __launch_bounds__(256) void dgs_dots_kernel(int n, int j, const int *
     const int lane = threadIdx.x & 63;
     const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (c > j) return;
-    const int r0 = blockIdx.x * CGS_CHUNK, r1 = min(n, r0 + CGS_CHUNK);
+    const int chunk = cgs_chunk(n);
+    const int r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
     const double2 *vc = Vb + (int64_t)c * n, *u = Vb + (int64_t)j * n;
     double ur = 0, ui = 0, wr = 0, wi = 0;
 #pragma unroll 4
@@ -2835,7 +2844,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     const int ir_max = opts->ir_max > 0 ? opts->ir_max : 10;
     const int R = std::min(solve_runs(p, opts), nrhs);   // runs advancing together
     const size_t vb = (size_t)n * sizeof(double2);
-    const int nchunk = (n + CGS_CHUNK - 1) / CGS_CHUNK;
+    const int nchunk = (n + cgs_chunk(n) - 1) / cgs_chunk(n);
     const int nrow_blk = (n + 255) / 256, nupd = (n + UPD_ROWS - 1) / UPD_ROWS;
     Work W;
     bem_status s = dev_alloc(ctx, W.y, R * vb);
@@ -3080,7 +3089,7 @@ bem_status ext_form_solve_impl(bem_problem *p, int form, const double *dirs, int
     const int m = opts->maxit;
     const int R = 1;
     const size_t vb = (size_t)n * sizeof(double2);
-    const int nchunk = (n + CGS_CHUNK - 1) / CGS_CHUNK;
+    const int nchunk = (n + cgs_chunk(n) - 1) / cgs_chunk(n);
     const int nrow_blk = (n + 255) / 256, nupd = (n + UPD_ROWS - 1) / UPD_ROWS;
     Work W;
     bem_status s = dev_alloc(ctx, W.y, vb);
