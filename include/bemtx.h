@@ -230,8 +230,12 @@ bem_status bem_problem_set_mortar(bem_problem *p, int32_t on_device);
  * overlapping vertex patches, O(N) memory and no size limit (a vertex may
  * have at most 15 neighbours, else BEM_E_MESH at the set-up); mode 0 (the
  * default) picks mode 2 when the dense inverses would exceed 256 MB or a mesh
- * has more than 16,384 vertices, else mode 1.  Both apply M^-1 to FP64
- * rounding in the FP64 form.  Takes effect at the next
+ * has more than 16,384 vertices, else mode 1; with mode 0, a BEM_C64_MIXED
+ * block solve of 32 or more runs (bem_solver_opts.batch) also builds the
+ * complex64-form dense inverses at its start when they take at most 1 GB
+ * and applies them to all runs as one matrix-core product (cheaper there
+ * than a Chebyshev apply per run), while single solves keep the Chebyshev
+ * apply.  Both apply M^-1 to FP64 rounding in the FP64 form.  Takes effect at the next
  * bem_assemble_projection (a changed mode marks the projection stale).
  * BEM_E_ARG for another mode. */
 bem_status bem_problem_set_mass_apply(bem_problem *p, int32_t mode);

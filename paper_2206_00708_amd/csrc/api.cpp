@@ -226,6 +226,18 @@ static double ms_since(std::chrono::steady_clock::time_point t0)
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// A block solve of R runs with the matrix cores takes the dense inverses as a
+// second matrix-core product when the choice is by size, R is at least 32
+// and the complex64 inverses take at most 1 GB: there the product of all
+// runs costs less than R Chebyshev applies (C4, 64 runs: 0.8 against 1.1 ms
+// per step).  Built at the first such solve, beside the sparse tables.
+bool block_dense_mass(const bem_problem *p, int R)
+{
+    const size_t ne = p->ext->h.nv, ni = p->inte->h.nv;
+    return p->mass_mode == 0 && p->prec == BEM_C64_MIXED && R >= 32 && std::max(ne, ni) <= 16384 &&
+           (ne * ne + ni * ni) * sizeof(float) <= (size_t(1) << 30);
+}
+
 }  // namespace bemtx
 
 using namespace bemtx;
@@ -269,6 +281,8 @@ void bem_ctx_destroy(bem_ctx *ctx)
         (void)hipStreamSynchronize(ctx->gather);
         (void)hipStreamDestroy(ctx->gather);
     }
+    for (hipEvent_t e : ctx->strip_ev)
+        if (e) (void)hipEventDestroy(e);
     for (auto &p : ctx->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     if (ctx->release_ev) (void)hipEventDestroy(ctx->release_ev);
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
@@ -481,7 +495,7 @@ bem_status bem_problem_footprint(const bem_problem *p, int32_t nrhs, int32_t max
     const bool sparse_mass = pick_mass_sparse(p);
     if (sparse_mass)   // patch tables: at most 8 patch copies of each vertex with its row (bound)
         b += 8 * (ne + ni) * (3 * sizeof(int32_t) + sizeof(double) + 14 * (sizeof(int32_t) + sizeof(double)));
-    else
+    if (!sparse_mass || block_dense_mass(p, p->prec == BEM_C64_MIXED ? std::min(nrhs, 64) : 1))
         b += (ne * ne + ni * ni) * (p->prec == BEM_C128 ? sizeof(double) : sizeof(float));   // dense inverse masses
     size_t scratch = std::max(tile_scratch_bytes(p->ext, eb), tile_scratch_bytes(p->inte, eb));
     scratch = std::max(scratch, std::max(p->ext->h.sing.size(), p->inte->h.sing.size()) * 36 * sizeof(double2));
@@ -626,6 +640,7 @@ bem_status bem_assemble_projection(bem_problem *p)
     }
     if (s) return s;
     p->mass_sparse = pick_mass_sparse(p);
+    p->mass_dense = !p->mass_sparse;
     if (p->mass_sparse) {   // patch tables of the sparse apply (host), no dense inverse
         for (int m = 0; m < 2; ++m) p->Minv[m].release();
         s = cheb_tables(p->M, CHEB_S, p->cheb);

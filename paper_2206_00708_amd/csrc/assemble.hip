@@ -867,10 +867,11 @@ bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, vo
     const size_t half = (size_t)most * 4 * SMAX * SMAX * eb;
     if (!ctx->gather) BEM_HIP(hipStreamCreateWithFlags(&ctx->gather, hipStreamNonBlocking));
     hipStream_t gs = ctx->gather;
-    // events: [0] main-stream work before the assembly, [1 + b] tiles of half b done, [3 + b] its gather done
-    hipEvent_t ev[5];
-    for (int q = 0; q < 5; ++q) BEM_HIP(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
-    struct EvGuard { hipEvent_t *e; ~EvGuard() { for (int q = 0; q < 5; ++q) (void)hipEventDestroy(e[q]); } } guard{ev};
+    // events (kept by the context, so that no event is destroyed while a wait on it is queued): [0] main-stream
+    // work before the assembly, [1 + b] tiles of half b done, [3 + b] its gather done
+    hipEvent_t *ev = ctx->strip_ev;
+    for (int q = 0; q < 5; ++q)
+        if (!ev[q]) BEM_HIP(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
     BEM_HIP(hipEventRecord(ev[0], st));
     BEM_HIP(hipStreamWaitEvent(gs, ev[0], 0));   // the operator blocks may have served earlier main-stream work
     for (int s = 0; s < ns; ++s) {

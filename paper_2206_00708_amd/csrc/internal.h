@@ -225,6 +225,9 @@ struct ChebTables {
 };
 bem_status cheb_tables(const Csr M[2], int s, ChebTables &T);
 
+// dense inverse masses for a matrix-core block solve of R runs (the choice by size; api.cpp)
+bool block_dense_mass(const bem_problem *p, int R);
+
 // Kernel-shape tuning table (tune.cpp): process-wide, persisted in a text
 // file.  tuned() returns the value of `key`, running `tune` once per key (other
 // callers of the same key wait for its result) and recording what it picks.
@@ -254,6 +257,7 @@ struct bem_ctx {
     hipStream_t capture = nullptr;
     // stream of the assembly's gathers, which overlap the next strip's tiles on `stream`
     hipStream_t gather = nullptr;
+    hipEvent_t strip_ev[5] = {};   // the strip assembly's ordering events (created at first use, kept)
     int64_t strip_tiles = bemtx::ASM_STRIP_TILES;   // block-pair tiles per assembly strip of meshes made here
     size_t budget = 0;
     size_t in_use = 0;
@@ -365,6 +369,9 @@ struct bem_problem {
     // choice of the last projection set-up
     int mass_mode = 0;
     bool mass_sparse = false;
+    // dense inverses present (the dense form, or beside the sparse tables for the matrix-core block products
+    // of many runs: built at the first such solve when the choice is by size)
+    bool mass_dense = false;
     bemtx::ChebTables cheb;
     bemtx::DevMem cheb_pmesh, cheb_vbeg, cheb_cnt, cheb_vert, cheb_dinv, cheb_ecol, cheb_eval;
     // per near entry (i, j) of each mesh: V_ij - V_ji (j < i, else 0), D_ij - D_ji (likewise),

@@ -2166,7 +2166,7 @@ bem_status block_alloc(bem_problem *p, BlockBufs &bb)
     }
     bem_status s = dev_alloc(ctx, bb.cop, cop * sizeof(float));
     if (!s) s = dev_alloc(ctx, bb.cm, cm * sizeof(float));
-    if (!s && p->mass_sparse)
+    if (!s && p->mass_sparse && !p->mass_dense)
         s = dev_alloc(ctx, bb.chw, (size_t)6 * BLOCK_RHS * (2 * nv[0] + 2 * nv[1]) * sizeof(double2));
     return s;
 }
@@ -2310,7 +2310,7 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
     const int nv[2] = {A.ne, A.ni};
     int nk_ops = 0, nk_mass = 0, kst_ops = 32, kst_mass = 32;   // (tuning zeroes the right-hand buffers: before packing)
     bem_status s = block_tune(p, bb, 0, R, nk_ops, kst_ops);
-    if (!s && strong && !p->mass_sparse) s = block_tune(p, bb, 1, R, nk_mass, kst_mass);
+    if (!s && strong && p->mass_dense) s = block_tune(p, bb, 1, R, nk_mass, kst_mass);
     if (s) return s;
     for (int m = 0; m < 2; ++m) {
         const int kop = 2 * (int)op_ld(nv[m]);
@@ -2330,7 +2330,7 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
                        Y, ystride, kst);
     BEM_HIP(hipGetLastError());
     if (!strong) return BEM_OK;
-    if (p->mass_sparse) {
+    if (!p->mass_dense) {
         const int64_t n = 2 * A.ne + 2 * A.ni;
         return cheb_apply(p, 0, p->cheb.nparts[0] + p->cheb.nparts[1], 0, 2 * A.ne, n, Y, ystride, Z, zstride,
                           bb.chw.as<double2>(), 6 * n, R, kst);
@@ -2871,6 +2871,11 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     if (s) return s;
     BlockBufs bb;
     if (R > 1) {
+        if (!p->mass_dense && p->mass_sparse && block_dense_mass(p, R)) {   // the block product's inverse masses
+            for (int m = 0; m < 2 && !s; ++m) s = launch_mass_inverse(p, m, st);
+            if (s) return s;
+            p->mass_dense = true;
+        }
         s = block_alloc(p, bb);
         if (s) return s;
     }
