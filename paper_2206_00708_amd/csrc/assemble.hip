@@ -218,7 +218,7 @@ __device__ inline void pair_quadrature(const TriGeo &X, const TriGeo &Y, double 
         const double x0 = X.qp[p][0], x1 = X.qp[p][1], x2 = X.qp[p][2];
         const double dkp = ey0 - (ny0 * x0 + ny1 * x1 + ny2 * x2);   // (y - x).n_y
         double hvr[3] = {0, 0, 0}, hvi[3] = {0, 0, 0}, hkr[3] = {0, 0, 0}, hki[3] = {0, 0, 0};
-        double htr[3] = {0, 0, 0}, hti[3] = {0, 0, 0}, hsr = 0.0, hsi = 0.0;
+        double htr[3] = {0, 0, 0}, hti[3] = {0, 0, 0};
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
             const double d0 = x0 - Y.qp[q][0], d1 = x1 - Y.qp[q][1], d2 = x2 - Y.qp[q][2];
@@ -256,8 +256,6 @@ __device__ inline void pair_quadrature(const TriGeo &X, const TriGeo &Y, double 
                 hkr[b] += W * fr; hki[b] += W * fi;
                 htr[b] += W * gtr; hti[b] += W * gti;
             }
-            hsr += r6_w(q) * gr;
-            hsi += r6_w(q) * gi;
         }
         const double wp = p < 3 ? kW1 : kW2;
         const double ap = p < 3 ? kA1 : kA2;
@@ -273,16 +271,18 @@ __device__ inline void pair_quadrature(const TriGeo &X, const TriGeo &Y, double 
                 tr[3 * a + b] += W * htr[b]; ti[3 * a + b] += W * hti[b];
             }
         }
-        sr += wp * hsr;
-        si += wp * hsi;
     }
     const double scale = X.area * Y.area * kInv4Pi;
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
         vr[e] *= scale; vi[e] *= scale; kr[e] *= scale; ki[e] *= scale; tr[e] *= scale; ti[e] *= scale;
     }
-    sr *= scale;
-    si *= scale;
+    // sum G over the point pairs: the P1 functions sum to one at every point,
+    // so the sum over a, b of the V entries is that sum
+    sr = 0.0;
+    si = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) { sr += vr[e]; si += vi[e]; }
 }
 
 struct TileArgsF {
