@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
         for (int p = 0; p < 6; ++p) {
             const float x0 = X.dq[p][0], x1 = X.dq[p][1], x2 = X.dq[p][2];
             float hvr[3] = {0, 0, 0}, hvi[3] = {0, 0, 0}, hkr[3] = {0, 0, 0}, hki[3] = {0, 0, 0};
-            float htr[3] = {0, 0, 0}, hti[3] = {0, 0, 0}, hsr = 0.f, hsi = 0.f;
+            float htr[3] = {0, 0, 0}, hti[3] = {0, 0, 0};
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 const float q0 = x0 - Y.dq[q][0], q1 = x1 - Y.dq[q][1], q2 = x2 - Y.dq[q][2];   // e
@@ -507,8 +507,6 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
                     hkr[b] += W * gkr; hki[b] += W * gki;
                     htr[b] += W * gtr; hti[b] += W * gti;
                 }
-                hsr += (float)r6_w(q) * gr;
-                hsi += (float)r6_w(q) * gi;
             }
             const float wp = p < 3 ? (float)kW1 : (float)kW2;
             const float ap = p < 3 ? (float)kA1 : (float)kA2;
@@ -524,16 +522,15 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
                     tr[3 * a + b] += W * htr[b]; ti[3 * a + b] += W * hti[b];
                 }
             }
-            sr += wp * hsr;
-            si += wp * hsi;
         }
         const float scale = X.area * Y.area * (float)kInv4Pi;
 #pragma unroll
         for (int e = 0; e < 9; ++e) {
             vr[e] *= scale; vi[e] *= scale; kr[e] *= scale; ki[e] *= scale; tr[e] *= scale; ti[e] *= scale;
         }
-        sr *= scale;
-        si *= scale;
+        // the sum of G over the point pairs is the sum of the V entries (the P1 functions sum to one)
+#pragma unroll
+        for (int e = 0; e < 9; ++e) { sr += vr[e]; si += vi[e]; }
     }
     float2 *out = A.scratch + (tile - A.tile_base) * (4 * SMAX * SMAX);
 #pragma unroll 1
