@@ -5,6 +5,7 @@
 // (mass_cheb.cpp) and the host-only C-ABI calls.  Meshes come from text
 // files "nv nt / xyz rows / tri rows"; argv: int mesh, ext mesh, a broken
 // mesh.  Exit 0 when every call behaves; any sanitizer report aborts.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <fstream>
@@ -39,6 +40,81 @@ static bool read_mesh(const char *path, Mesh &m)
         }                                                          \
     } while (0)
 
+// The assembly strips of a prepared mesh: block ranges within the tile
+// budget, the row list of each strip (the vertices with a membership in its
+// blocks), its first reachable vertex, and the gather's coverage: over all
+// strips, every dense entry (i, j) is visited where a strip holds one of its
+// tiles (rows of the list against columns from the first reachable vertex,
+// and rows outside the list from there against columns of the list),
+// receives each membership pair's tile exactly once, and is written first
+// by the strip of its smallest membership.
+static int check_strips(const MeshData &m, int64_t cap)
+{
+    const int nv = (int)m.nv, nb = m.nb, ns = (int)m.strip_b.size() - 1;
+    CHECK(ns >= 1 && m.strip_b[0] == 0 && m.strip_b[ns] == nb);
+    CHECK((int)m.strip_rptr.size() == ns + 1 && (int)m.strip_lo.size() == ns);
+    auto off = [&](int64_t b) { return b * nb - b * (b - 1) / 2; };
+    std::vector<int> minb(nv), maxb(nv);
+    for (int v = 0; v < nv; ++v) {
+        CHECK(m.memb_ptr[v + 1] > m.memb_ptr[v]);
+        minb[v] = m.memb[m.memb_ptr[v]] >> 8;
+        maxb[v] = m.memb[m.memb_ptr[v + 1] - 1] >> 8;
+    }
+    std::vector<long> count((size_t)nv * nv, 0);
+    std::vector<char> written((size_t)nv * nv, 0);
+    for (int s = 0; s < ns; ++s) {
+        const int b0 = m.strip_b[s], b1 = m.strip_b[s + 1];
+        CHECK(b1 > b0);
+        CHECK(b1 == b0 + 1 || off(b1) - off(b0) <= cap);
+        std::vector<char> in(nv, 0);
+        for (int q = m.strip_rptr[s]; q < m.strip_rptr[s + 1]; ++q) {
+            CHECK(q == m.strip_rptr[s] || m.strip_rows[q] > m.strip_rows[q - 1]);
+            in[m.strip_rows[q]] = 1;
+        }
+        int lo = nv;
+        for (int v = 0; v < nv; ++v) {
+            bool has = false;
+            for (int p = m.memb_ptr[v]; p < m.memb_ptr[v + 1]; ++p) has |= (m.memb[p] >> 8) >= b0 && (m.memb[p] >> 8) < b1;
+            CHECK(has == (in[v] != 0));
+            if (maxb[v] >= b0 && v < lo) lo = v;
+        }
+        CHECK(m.strip_lo[s] == lo);
+        auto visit = [&](int i, int j) -> bool {
+            bool any = false;
+            for (int p = m.memb_ptr[i]; p < m.memb_ptr[i + 1]; ++p)
+                for (int q = m.memb_ptr[j]; q < m.memb_ptr[j + 1]; ++q) {
+                    const int lb = std::min(m.memb[p] >> 8, m.memb[q] >> 8), hb = std::max(m.memb[p] >> 8, m.memb[q] >> 8);
+                    if (lb < b0 || lb >= b1) continue;
+                    const int64_t t = off(lb) + (hb - lb) - off(b0);
+                    if (t < 0 || t >= off(b1) - off(b0)) return false;
+                    any = true;
+                    ++count[(size_t)i * nv + j];
+                }
+            const size_t o = (size_t)i * nv + j;
+            if (std::min(minb[i], minb[j]) >= b0) {
+                if (!any || written[o]) return false;
+                written[o] = 1;
+            } else if (any && !written[o]) {
+                return false;
+            }
+            return true;
+        };
+        for (int i = 0; i < nv; ++i)
+            for (int j = lo; j < nv; ++j)
+                if (in[i]) CHECK(visit(i, j));
+        for (int i = lo; i < nv; ++i)
+            for (int j = 0; j < nv; ++j)
+                if (!in[i] && in[j]) CHECK(visit(i, j));
+    }
+    for (int i = 0; i < nv; ++i)
+        for (int j = 0; j < nv; ++j) {
+            const size_t o = (size_t)i * nv + j;
+            CHECK(written[o]);
+            CHECK(count[o] == (long)(m.memb_ptr[i + 1] - m.memb_ptr[i]) * (m.memb_ptr[j + 1] - m.memb_ptr[j]));
+        }
+    return 0;
+}
+
 int main(int argc, char **argv)
 {
     if (argc < 4) return 2;
@@ -70,6 +146,16 @@ int main(int argc, char **argv)
         md[m].xyz_user.assign(ms[m]->xyz.begin(), ms[m]->xyz.end());
         md[m].tri_user.assign(ms[m]->tri.begin(), ms[m]->tri.end());
         CHECK(mesh_prepare(md[m]) == BEM_OK);
+        CHECK(check_strips(md[m], ASM_STRIP_TILES) == 0);
+        for (int64_t cap : {1, 37, 400}) {   // small strips: many strips, entries fed by several
+            MeshData t;
+            t.nv = md[m].nv;
+            t.nt = md[m].nt;
+            t.xyz_user = md[m].xyz_user;
+            t.tri_user = md[m].tri_user;
+            CHECK(mesh_prepare(t, cap) == BEM_OK);
+            CHECK(check_strips(t, cap) == 0);
+        }
         mass_csr(md[m], M[m]);
     }
     Csr P, Pt;

@@ -1,6 +1,7 @@
 """The host code and the oracle's C part built with AddressSanitizer and
 UndefinedBehaviorSanitizer (CPU only) and run on small meshes: the mesh
-tables and their thread pool, the mass and mortar matrices, the
+tables and their thread pool (with the assembly strips checked for the
+gather's coverage at four strip sizes), the mass and mortar matrices, the
 inverse-mass patch tables and the host-only C-ABI calls of the library
 (tests/sanitize/host_driver.cpp; the host pass of every source, no device
 code), and every exported routine of the oracle
