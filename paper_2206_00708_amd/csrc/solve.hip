@@ -1446,15 +1446,78 @@ __global__ void krylov_init_kernel(int m, const double *__restrict__ beta0, cons
     }
 }
 
-// x = sum_c y[c] Vb[c]
-__global__ void combine_kernel(int n, int nvec, const double2 *__restrict__ Vb, const double2 *__restrict__ yc,
-                               double2 *__restrict__ x)
+// Back substitution R y = g of every run (k = its Arnoldi steps; R upper
+// triangular, column c at offset c (m + 1)), column by column: y_i = g_i /
+// R_ii, then g_r -= R_ri y_i for r < i.  One workgroup per run, g staged in
+// LDS (dynamic, at least k complex); y of run r at y + r (m + 1).  The next
+// column's entries are loaded before the current column's update, since
+// only y_i depends on the previous step.
+__global__ __launch_bounds__(256) void backsub_kernel(int m, const double2 *__restrict__ Rm,
+                                                      const double2 *__restrict__ g,
+                                                      const KrylovState *__restrict__ st, KBatch B,
+                                                      double2 *__restrict__ y)
 {
+    constexpr int PER = 12;   // column entries per thread held in registers (k <= 3072)
+    const int run = blockIdx.x;
+    const int k = st[run].iters;
+    Rm += run * B.hess;
+    g += run * B.small;
+    y += (int64_t)run * (m + 1);
+    extern __shared__ double2 gs[];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < k; i += 256) gs[i] = g[i];
+    double2 cur[PER];
+    if (k > 0) {
+        const double2 *col = Rm + (int64_t)(k - 1) * (m + 1);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int r = tid + 256 * q;
+            cur[q] = r < k ? col[r] : make_double2(0, 0);
+        }
+    }
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+        double2 nxt[PER];
+        if (i > 0) {
+            const double2 *col = Rm + (int64_t)(i - 1) * (m + 1);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int r = tid + 256 * q;
+                nxt[q] = r < i ? col[r] : make_double2(0, 0);
+            }
+        }
+        const double2 gi = gs[i], d = Rm[(int64_t)i * (m + 1) + i];
+        const double den = d.x * d.x + d.y * d.y;
+        const double2 yi = make_double2((gi.x * d.x + gi.y * d.y) / den, (gi.y * d.x - gi.x * d.y) / den);
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int r = tid + 256 * q;
+            if (r < i) {
+                const double2 a = cur[q];
+                gs[r] = make_double2(gs[r].x - (a.x * yi.x - a.y * yi.y), gs[r].y - (a.x * yi.y + a.y * yi.x));
+            }
+        }
+        if (tid == 0) y[i] = yi;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) cur[q] = nxt[q];
+        __syncthreads();
+    }
+}
+
+// x_r = sum_{c < k_r} y_r[c] Vb_r[c] for every run r (grid (row blocks, runs))
+__global__ void combine_kernel(int n, int m, const double2 *__restrict__ Vb, int64_t basis_stride,
+                               const double2 *__restrict__ yc, double2 *__restrict__ x, int64_t x_stride,
+                               const KrylovState *__restrict__ st)
+{
+    const int run = blockIdx.y;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
+    const int nvec = st[run].iters;
+    Vb += run * basis_stride;
+    yc += (int64_t)run * (m + 1);
     double2 acc = make_double2(0, 0);
     for (int c = 0; c < nvec; ++c) acc = cadd(acc, cmul(yc[c], Vb[(int64_t)c * n + r]));
-    x[r] = acc;
+    x[run * x_stride + r] = acc;
 }
 
 __global__ void axpy_sub_kernel(int n, const double2 *__restrict__ a, const double2 *__restrict__ b, double2 *__restrict__ out)
@@ -2585,34 +2648,13 @@ struct Gmres {
         BEM_HIP(hipMemcpyAsync(hs, dst, sb, hipMemcpyDeviceToHost, st));
         BEM_HIP(hipStreamSynchronize(st));
         for (int r = 0; r < R; ++r) fin[r] = hs[r];
-        // back substitution R y = g of every run on the host (k x k upper
-        // triangular; column c of R at offset c (maxit + 1))
-        using cd = std::complex<double>;
-        std::vector<cd> Rh, gh(maxit + 1), yv;
-        for (int r = 0; r < R; ++r) {
-            const int k = fin[r].iters;
-            Rh.assign((size_t)std::max(k, 1) * (maxit + 1), cd(0));
-            if (k > 0) {
-                BEM_HIP(hipMemcpyAsync(Rh.data(), W.R.as<double2>() + r * B.hess, (size_t)k * (maxit + 1) * sizeof(double2),
-                                       hipMemcpyDeviceToHost, st));
-                BEM_HIP(hipMemcpyAsync(gh.data(), W.g.as<double2>() + r * B.small, (size_t)(maxit + 1) * sizeof(double2),
-                                       hipMemcpyDeviceToHost, st));
-                BEM_HIP(hipStreamSynchronize(st));
-            }
-            yv.assign(std::max(k, 1), cd(0));
-            for (int i = k - 1; i >= 0; --i) {
-                cd sacc = gh[i];
-                for (int c = i + 1; c < k; ++c) sacc -= Rh[(size_t)c * (maxit + 1) + i] * yv[c];
-                yv[i] = sacc / Rh[(size_t)i * (maxit + 1) + i];
-            }
-            if (k > 0)
-                BEM_HIP(hipMemcpyAsync(W.yc.ptr, yv.data(), (size_t)k * sizeof(double2), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(combine_kernel, dim3(nrow_blk), dim3(256), 0, st, n, k, Vb + r * B.basis,
-                               W.yc.as<double2>(), x + r * B.vec);
-            BEM_HIP(hipGetLastError());
-            // yv and W.yc are reused by the next run
-            BEM_HIP(hipStreamSynchronize(st));
-        }
+        // back substitution of every run and x = V y on the device (y in W.yc, [R][maxit + 1])
+        if (maxit + 1 > 12 * 256) return set_error(BEM_E_ARG, "internal: back substitution size");
+        hipLaunchKernelGGL(backsub_kernel, dim3(R), dim3(256), (size_t)(maxit + 1) * sizeof(double2), st, maxit,
+                           W.R.as<double2>(), W.g.as<double2>(), dst, B, W.yc.as<double2>());
+        hipLaunchKernelGGL(combine_kernel, dim3(nrow_blk, R), dim3(256), 0, st, n, maxit, Vb, B.basis,
+                           W.yc.as<double2>(), x, B.vec, dst);
+        BEM_HIP(hipGetLastError());
         return BEM_OK;
     }
 };
@@ -2858,7 +2900,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
     if (!s) s = dev_alloc(ctx, W.hsum, (size_t)R * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.beta, sizeof(double) * (R + 1));
     if (!s) s = dev_alloc(ctx, W.tolv, sizeof(double) * R);
-    if (!s) s = dev_alloc(ctx, W.yc, (size_t)(m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.yc, (size_t)R * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.npart, (size_t)R * std::max(nrow_blk, nupd) * sizeof(double));
     if (!s) s = dev_alloc(ctx, W.R, (size_t)R * m * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.H, (size_t)R * m * (m + 1) * sizeof(double2));
@@ -3108,7 +3150,7 @@ bem_status ext_form_solve_impl(bem_problem *p, int form, const double *dirs, int
     if (!s) s = dev_alloc(ctx, W.hsum, (size_t)(m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.beta, sizeof(double) * (R + 1));
     if (!s) s = dev_alloc(ctx, W.tolv, sizeof(double) * R);
-    if (!s) s = dev_alloc(ctx, W.yc, (size_t)(m + 1) * sizeof(double2));
+    if (!s) s = dev_alloc(ctx, W.yc, (size_t)R * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.npart, (size_t)std::max(nrow_blk, nupd) * sizeof(double));
     if (!s) s = dev_alloc(ctx, W.R, (size_t)m * (m + 1) * sizeof(double2));
     if (!s) s = dev_alloc(ctx, W.H, (size_t)m * (m + 1) * sizeof(double2));
