@@ -77,14 +77,14 @@ COUNTED_TRAFFIC = {
 # the software sin/cos (the small-angle polynomials and the rotation by the
 # pair's base phase: 46 of the per-point-pair flops).
 COUNTED_VALU = {
-    ("regular_tiles", "C3"): {"flops_fp64": 1398312300.0 * 64, "valu_insts": 1114510835, "valu_busy": 0.579,
-                              "sincos_flop_share": 0.30, "isolated_launch_us": 3235.6,
+    ("regular_tiles", "C3"): {"flops_fp64": 1309899766.7 * 64, "valu_insts": 1097586150, "valu_busy": 0.577,
+                              "sincos_flop_share": 0.32, "isolated_launch_us": 3240.5,
                               "source": "paper_2206_00708_amd/csrc/assemble.hip",
-                              "sha1": "64e8f72a77ba7401155739339304c59e0eb6b1fa"},
-    ("regular_tiles", "C2"): {"flops_fp64": 922141924.0 * 64, "valu_insts": 734252736, "valu_busy": 0.582,
-                              "sincos_flop_share": 0.30, "isolated_launch_us": 2288.0,
+                              "sha1": "f082f069c4a3fa8f612660013e24cd8793861c04"},
+    ("regular_tiles", "C2"): {"flops_fp64": 863828424.0 * 64, "valu_insts": 723089866, "valu_busy": 0.580,
+                              "sincos_flop_share": 0.32, "isolated_launch_us": 2334.5,
                               "source": "paper_2206_00708_amd/csrc/assemble.hip",
-                              "sha1": "64e8f72a77ba7401155739339304c59e0eb6b1fa"},
+                              "sha1": "f082f069c4a3fa8f612660013e24cd8793861c04"},
 }
 
 
