@@ -1,6 +1,7 @@
 """Host-side logic of the library, no GPU: the C ABI loads and exports every
 declared symbol, mesh validation, the mortar matrix and the Gauss-Legendre
-rule against the oracle / numpy."""
+rule against the oracle / numpy, the tuning table's file, and the bench's
+one-GPU guard."""
 import glob
 import os
 import re
@@ -105,3 +106,32 @@ def test_phase_sincos_accuracy():
     assert np.abs(c - np.cos(x)).max() < 4e-16
     small = np.abs(x) < 1.0
     assert np.all(np.abs(s[small] - np.sin(x[small])) <= 2.3e-16 * np.abs(np.sin(x[small])) + 1e-300)
+
+
+def test_tuning_table_file(tmp_path):
+    """The tuning table reads $BEMTX_TUNE_FILE once per process ("key value..."
+    lines, '#' comments and malformed lines skipped); run in a child process so
+    that this process's table is not the one loaded."""
+    import subprocess
+    import sys
+    f = tmp_path / "tune.txt"
+    f.write_text("# a comment\ngemm-ops:c128:e53:i52 4 32\nmtf-c128:e53:i52 128\nbroken\n\nmtf-c64:e29:i29 64\n")
+    code = ("import sys; sys.path.insert(0, %r); import paper_2206_00708_amd as B; "
+            "t = B.tune_table(); print(sorted(t.items()))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                         env=dict(os.environ, BEMTX_TUNE_FILE=str(f)))
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == str(sorted({"gemm-ops:c128:e53:i52": [4, 32],
+                                                              "mtf-c128:e53:i52": [128],
+                                                              "mtf-c64:e29:i29": [64]}.items()))
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and says so,
+    before touching a device."""
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 2
+    assert "one GPU" in out.stderr
