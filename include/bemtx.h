@@ -416,8 +416,9 @@ bem_status bem_mesh_winding(const bem_mesh *m, const double *points, int64_t npt
 
 /* The kernel shapes picked by timing so far (the library's tuner): one line
  * per size class, "key value...": "gemm-ops:c<columns>:e<class>:i<class>
- * <K split> <k per LDS stage>" for the multi-right-hand-side operator
- * product, "gemm-mass:..." likewise for the dense inverse-mass product,
+ * <K chunks, exterior> <K chunks, interior> <k per LDS stage>" for the
+ * multi-right-hand-side operator product (an entry in another format is
+ * tuned again), "gemm-mass:..." likewise for the dense inverse-mass product,
  * "mtf-c128:..." / "mtf-c64:... <tile edge>" for the symmetric mat-vec;
  * class = round(4 log2 N) of the exterior and interior vertex counts.  The
  * table is shared by all contexts of the process and kept in the file

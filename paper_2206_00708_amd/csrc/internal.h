@@ -230,10 +230,13 @@ bool block_dense_mass(const bem_problem *p, int R);
 
 // Kernel-shape tuning table (tune.cpp): process-wide, persisted in a text
 // file.  tuned() returns the value of `key`, running `tune` once per key (other
-// callers of the same key wait for its result) and recording what it picks.
+// callers of the same key wait for its result) and recording what it picks;
+// a recorded value that `valid` (when given) rejects, such as an entry of an
+// older format, is tuned again and replaced.
 int tune_class(int64_t n);   // size class: quarter octaves of n
 bem_status tuned(const std::string &key, std::vector<int> &value,
-                 const std::function<bem_status(std::vector<int> &)> &tune);
+                 const std::function<bem_status(std::vector<int> &)> &tune,
+                 const std::function<bool(const std::vector<int> &)> &valid = nullptr);
 std::string tune_table_text();
 void gauss_legendre01(int n, double *x, double *w);      // Jacobi eigenvalue method
 
@@ -388,8 +391,8 @@ struct bem_problem {
     // the main stream waits for its end (ev_proj)
     hipEvent_t ev_pre_asm = nullptr, ev_proj = nullptr;
     // multi-RHS products: K chunks per GEMM [operators, inverse masses][tile width 32, 64, 128
-    // columns], picked by timing at first use
-    int gemm_nk[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    // columns][exterior, interior mesh], picked by timing at first use
+    int gemm_nk[2][3][2] = {};
     int gemm_kst[2][3] = {{0, 0, 0}, {0, 0, 0}};   // k per LDS stage of those GEMMs (32 or 64)
     int graphs = 1;                                 // GMRES steps in captured HIP graphs (bem_problem_set_graphs)
     int mtf_ts = 0;                                 // tile edge of the symmetric mat-vec (64 or 128; 0: not tuned yet)

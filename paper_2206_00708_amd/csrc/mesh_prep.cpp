@@ -255,7 +255,20 @@ bem_status mesh_prepare(MeshData &m, int64_t strip_tiles)
         }
         key[t] = {code, (int32_t)t};
     }
-    std::sort(key.begin(), key.end());
+    // by code, equal codes by triangle: a stable LSD radix sort of the
+    // 63-bit codes (7 passes of 9 bits) over the triangles in index order
+    {
+        std::vector<std::pair<uint64_t, int32_t>> tmp(nt);
+        std::vector<int64_t> cnt(513);
+        for (int shift = 0; shift < 63; shift += 9) {
+            std::fill(cnt.begin(), cnt.end(), 0);
+            for (int64_t t = 0; t < nt; ++t) cnt[((key[t].first >> shift) & 511) + 1]++;
+            if (cnt[1 + ((key[0].first >> shift) & 511)] == nt) continue;   // one digit value: order unchanged
+            for (int d = 0; d < 512; ++d) cnt[d + 1] += cnt[d];
+            for (int64_t t = 0; t < nt; ++t) tmp[cnt[(key[t].first >> shift) & 511]++] = key[t];
+            key.swap(tmp);
+        }
+    }
 
     // ---- blocks (<= BT triangles, <= SMAX vertices) and internal vertex numbering
     m.int_of_v.assign(nv, -1);
@@ -263,23 +276,21 @@ bem_status mesh_prepare(MeshData &m, int64_t strip_tiles)
     m.v_of_int.reserve(nv);
     m.tri.assign(3 * nt, 0);
     m.blk_start.clear();
-    int32_t cur_n = 0;
-    std::vector<int32_t> cur_verts;
+    int32_t cur_n = 0, cur_nv = 0, blk = -1;
+    std::vector<int32_t> in_blk(nv, -1);   // the last block a vertex was counted in
     for (int64_t s = 0; s < nt; ++s) {
         int32_t t = key[s].second;
-        int newv = 0;
-        for (int a = 0; a < 3; ++a) {
-            int32_t u = T[3 * t + a];
-            if (std::find(cur_verts.begin(), cur_verts.end(), u) == cur_verts.end()) ++newv;
-        }
-        if (cur_n == 0 || cur_n == BT || (int)cur_verts.size() + newv > SMAX) {
+        int newv = 0;   // vertices of t not yet in the current block (a triangle's three are distinct)
+        for (int a = 0; a < 3; ++a) newv += in_blk[T[3 * t + a]] != blk;
+        if (cur_n == 0 || cur_n == BT || cur_nv + newv > SMAX) {
             m.blk_start.push_back((int32_t)s);
             cur_n = 0;
-            cur_verts.clear();
+            cur_nv = 0;
+            ++blk;
         }
         for (int a = 0; a < 3; ++a) {
             int32_t u = T[3 * t + a];
-            if (std::find(cur_verts.begin(), cur_verts.end(), u) == cur_verts.end()) cur_verts.push_back(u);
+            if (in_blk[u] != blk) { in_blk[u] = blk; ++cur_nv; }
             if (m.int_of_v[u] < 0) {
                 m.int_of_v[u] = (int32_t)m.v_of_int.size();
                 m.v_of_int.push_back(u);
@@ -354,14 +365,19 @@ bem_status mesh_prepare(MeshData &m, int64_t strip_tiles)
     m.strip_rows.clear();
     m.strip_lo.assign(ns, (int32_t)nv);
     {
-        std::vector<int32_t> rows;
+        // each strip's rows ascending: stamp the slots of its blocks, then scan the stamped range
+        std::vector<int32_t> stamp(nv, -1);
         for (int s = 0; s < ns; ++s) {
-            rows.clear();
+            int32_t vlo = (int32_t)nv, vhi = -1;
             for (int b = m.strip_b[s]; b < m.strip_b[s + 1]; ++b)
-                for (int q = 0; q < m.blk_nslot[b]; ++q) rows.push_back(m.blk_slots[(size_t)b * SMAX + q]);
-            std::sort(rows.begin(), rows.end());
-            rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
-            m.strip_rows.insert(m.strip_rows.end(), rows.begin(), rows.end());
+                for (int q = 0; q < m.blk_nslot[b]; ++q) {
+                    const int32_t v = m.blk_slots[(size_t)b * SMAX + q];
+                    stamp[v] = s;
+                    vlo = std::min(vlo, v);
+                    vhi = std::max(vhi, v);
+                }
+            for (int32_t v = vlo; v <= vhi; ++v)
+                if (stamp[v] == s) m.strip_rows.push_back(v);
             m.strip_rptr.push_back((int32_t)m.strip_rows.size());
         }
         // strip_lo: strips in ascending first block, so one pass per vertex over the strips it reaches
@@ -451,7 +467,8 @@ bem_status mesh_prepare(MeshData &m, int64_t strip_tiles)
     // Row i collects, kind by kind and triangle by triangle of its star (the
     // global pair order restricted to the row), the 3 entries (i, j) of every
     // pair whose test triangle holds i; columns are numbered by first
-    // appearance.  Chunks of rows in parallel, concatenated in row order.
+    // appearance.  Two parallel passes over the rows: count each row's
+    // columns and contributions, then write them at their final places.
     {
         const size_t nc = m.sing.size() * 9;
         auto row_entries = [&](int64_t i, std::vector<std::pair<int32_t, int32_t>> &out) {
@@ -464,74 +481,61 @@ bem_status mesh_prepare(MeshData &m, int64_t strip_tiles)
                             out.push_back({m.tri[3 * m.sing[p].sig + b], (int32_t)(p * 9 + a * 3 + b)});
                 }
         };
-        // rows in chunks, in parallel; each chunk keeps its unique columns
-        // (with their contribution counts) and its grouped sources
-        struct RowChunk { std::vector<int32_t> row, col, cnt, src; };
-        const int64_t nchunk_r = std::min<int64_t>(nv, 128);
-        std::vector<RowChunk> rc(nchunk_r);
-        parallel_for(nchunk_r, 1, [&](int64_t c0, int64_t c1) {
-            std::vector<int32_t> mark(nv, -1), slot_of(nv, 0), ucol, ucnt, off;
+        std::vector<int64_t> src_row(nv + 1, 0);   // first contribution of each row
+        m.near_row.assign(nv + 1, 0);
+        parallel_for(nv, 256, [&](int64_t r0, int64_t r1) {
+            std::vector<int32_t> mark(nv, -1);
             std::vector<std::pair<int32_t, int32_t>> ent;
-            for (int64_t c = c0; c < c1; ++c) {
-                RowChunk &R = rc[c];
-                for (int64_t i = nv * c / nchunk_r; i < nv * (c + 1) / nchunk_r; ++i) {
-                    row_entries(i, ent);
-                    ucol.clear();
-                    ucnt.clear();
-                    for (const auto &e : ent) {
-                        const int32_t j = e.first;
-                        if (mark[j] != (int32_t)i) {
-                            mark[j] = (int32_t)i;
-                            slot_of[j] = (int32_t)ucol.size();
-                            ucol.push_back(j);
-                            ucnt.push_back(0);
-                        }
-                        ucnt[slot_of[j]]++;
-                    }
-                    off.resize(ucol.size());
-                    int32_t acc = (int32_t)R.src.size();
-                    for (size_t u = 0; u < ucol.size(); ++u) {
-                        R.row.push_back((int32_t)i);
-                        R.col.push_back(ucol[u]);
-                        R.cnt.push_back(ucnt[u]);
-                        off[u] = acc;
-                        acc += ucnt[u];
-                    }
-                    R.src.resize(acc);
-                    for (const auto &e : ent) R.src[off[slot_of[e.first]]++] = e.second;
-                }
+            for (int64_t i = r0; i < r1; ++i) {
+                row_entries(i, ent);
+                int32_t u = 0;
+                for (const auto &e : ent)
+                    if (mark[e.first] != (int32_t)i) { mark[e.first] = (int32_t)i; ++u; }
+                m.near_row[i + 1] = u;
+                src_row[i + 1] = (int64_t)ent.size();
             }
         });
-        size_t nent = 0, nsrc = 0;
-        std::vector<size_t> ent0(nchunk_r), src0(nchunk_r);
-        for (int64_t c = 0; c < nchunk_r; ++c) {
-            ent0[c] = nent;
-            src0[c] = nsrc;
-            nent += rc[c].row.size();
-            nsrc += rc[c].src.size();
+        for (int64_t v = 0; v < nv; ++v) {
+            m.near_row[v + 1] += m.near_row[v];
+            src_row[v + 1] += src_row[v];
         }
-        if (nsrc != nc) return set_error(BEM_E_MESH, "internal: singular contribution count");
+        if ((size_t)src_row[nv] != nc) return set_error(BEM_E_MESH, "internal: singular contribution count");
+        const size_t nent = (size_t)m.near_row[nv];
         m.near_i.resize(nent);
         m.near_j.resize(nent);
-        m.near_ptr.resize(nent);
+        m.near_ptr.resize(nent + 1);
         m.near_src.resize(nc);
-        parallel_for(nchunk_r, 1, [&](int64_t c0, int64_t c1) {
-            for (int64_t c = c0; c < c1; ++c) {
-                const RowChunk &R = rc[c];
-                int32_t acc = (int32_t)src0[c];
-                for (size_t u = 0; u < R.row.size(); ++u) {
-                    m.near_i[ent0[c] + u] = R.row[u];
-                    m.near_j[ent0[c] + u] = R.col[u];
-                    m.near_ptr[ent0[c] + u] = acc;
-                    acc += R.cnt[u];
+        parallel_for(nv, 256, [&](int64_t r0, int64_t r1) {
+            std::vector<int32_t> mark(nv, -1), slot_of(nv, 0), off;
+            std::vector<std::pair<int32_t, int32_t>> ent;
+            for (int64_t i = r0; i < r1; ++i) {
+                row_entries(i, ent);
+                const int64_t e0 = m.near_row[i];
+                int32_t u = 0;
+                for (const auto &e : ent) {   // columns by first appearance, with their contribution counts
+                    const int32_t j = e.first;
+                    if (mark[j] != (int32_t)i) {
+                        mark[j] = (int32_t)i;
+                        slot_of[j] = u;
+                        m.near_i[e0 + u] = (int32_t)i;
+                        m.near_j[e0 + u] = j;
+                        m.near_ptr[e0 + u] = 0;
+                        ++u;
+                    }
+                    m.near_ptr[e0 + slot_of[j]]++;
                 }
-                std::copy(R.src.begin(), R.src.end(), m.near_src.begin() + src0[c]);
+                off.resize(u);
+                int32_t acc = (int32_t)src_row[i];
+                for (int32_t q = 0; q < u; ++q) {
+                    const int32_t c = m.near_ptr[e0 + q];
+                    m.near_ptr[e0 + q] = acc;
+                    off[q] = acc;
+                    acc += c;
+                }
+                for (const auto &e : ent) m.near_src[off[slot_of[e.first]]++] = e.second;
             }
         });
-        m.near_ptr.push_back((int32_t)nc);
-        m.near_row.assign(nv + 1, 0);
-        for (size_t e = 0; e < nent; ++e) m.near_row[m.near_i[e] + 1]++;
-        for (int64_t v = 0; v < nv; ++v) m.near_row[v + 1] += m.near_row[v];
+        m.near_ptr[nent] = (int32_t)nc;
     }
     return BEM_OK;
 }

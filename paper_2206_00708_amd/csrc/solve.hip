@@ -2205,6 +2205,7 @@ bem_status norm_to(const bem_problem *p, int n, const double2 *w, double *npart,
     return BEM_OK;
 }
 
+constexpr int GEMM_MAX_SPLIT = 8;   // K chunks per GEMM segment, at most
 int kchunk_for(int K, int nk, int kst = 32) { return ((K + nk - 1) / nk + kst - 1) / kst * kst; }
 int nchunks(int K, int kc) { return (K + kc - 1) / kc; }
 
@@ -2219,13 +2220,13 @@ bem_status block_alloc(bem_problem *p, BlockBufs &bb)
         if (!s) s = dev_alloc(ctx, bb.btw[m], (size_t)2 * BLOCK_RHS * kop * sizeof(float));
         if (!s) s = dev_alloc(ctx, bb.btm[m], (size_t)4 * BLOCK_RHS * km * sizeof(float));
         if (s) return s;
-        // partial outputs sized for the largest chunk count the tuner tries (8)
+        // partial outputs sized for the largest chunk count the tuner tries
         for (int o = 0; o < 4; ++o) {
             bb.cop_off[m][o] = (int64_t)cop;
-            cop += (size_t)nchunks(kop, kchunk_for(kop, 8)) * 2 * BLOCK_RHS * nv[m];
+            cop += (size_t)nchunks(kop, kchunk_for(kop, GEMM_MAX_SPLIT)) * 2 * BLOCK_RHS * nv[m];
         }
         bb.cm_off[m] = (int64_t)cm;
-        cm += (size_t)nchunks(km, kchunk_for(km, 8)) * 4 * BLOCK_RHS * nv[m];
+        cm += (size_t)nchunks(km, kchunk_for(km, GEMM_MAX_SPLIT)) * 4 * BLOCK_RHS * nv[m];
     }
     bem_status s = dev_alloc(ctx, bb.cop, cop * sizeof(float));
     if (!s) s = dev_alloc(ctx, bb.cm, cm * sizeof(float));
@@ -2243,7 +2244,7 @@ void gemm_width(int cols, int &nt, int &ncb)
 }
 int nt_index(int nt) { return nt == 1 ? 0 : nt == 2 ? 1 : 2; }
 
-GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st, int kst = 32)
+GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, const int nk[2], int R, const KrylovState *st, int kst = 32)
 {
     GemmArgs G{};
     G.kst = kst;
@@ -2263,7 +2264,7 @@ GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const
             S.C = bb.cop.as<float>() + bb.cop_off[m][o];
             S.M = nv[m];
             S.K = kop;
-            S.kchunk = kchunk_for(kop, nk, kst);
+            S.kchunk = kchunk_for(kop, nk[m], kst);
             S.ncb = 1;
         }
     }
@@ -2274,7 +2275,7 @@ GemmArgs ops_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const
     return G;
 }
 
-GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, const KrylovState *st)
+GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, const int nk[2], int R, const KrylovState *st)
 {
     GemmArgs G{};
     G.kst = 32;
@@ -2292,7 +2293,7 @@ GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, cons
         S.C = bb.cm.as<float>() + bb.cm_off[m];
         S.M = nv[m];
         S.K = km;
-        S.kchunk = kchunk_for(km, nk);
+        S.kchunk = kchunk_for(km, nk[m]);
         S.ncb = ncb;
     }
     G.nseg = 2;
@@ -2302,25 +2303,60 @@ GemmArgs mass_gemm_args(const bem_problem *p, BlockBufs &bb, int nk, int R, cons
     return G;
 }
 
-// K chunk count of one GEMM (which = 0 operators, 1 inverse masses) for R
-// runs, chosen once per problem and tile width by timing every candidate on
-// the problem's own matrices (right-hand buffers zeroed first).
-// K split (and, for the operator product, k per LDS stage) of the block
-// GEMMs, by timing every candidate once per size class: the choice is kept
-// in the process-wide tuning table (and its file), so every problem and
-// context of the class uses the same shapes.
-bem_status block_tune(bem_problem *p, BlockBufs &bb, int which, int R, int &nk, int &kst)
+// Modelled duration of one GEMM launch, in units of 32 k: the workgroups
+// go to the 8 XCDs in turn, in launch order, and each XCD starts the next
+// of its workgroups on the first slot that frees up (slots: workgroups per
+// compute unit times compute units per XCD).  A workgroup costs its k range
+// plus a fixed share for the fill of its first stage and the store of its
+// tile.  Used to rank the K splits worth timing: with few workgroups per
+// slot the last wave of workgroups leaves most slots idle.
+double gemm_model_time(const GemmArgs &G, int slots_per_xcd)
+{
+    constexpr int kXcd = 8;
+    constexpr double kFixed = 4.0;
+    std::vector<std::vector<double>> free_at(kXcd, std::vector<double>(slots_per_xcd, 0.0));   // min-heaps
+    int64_t wg = 0;
+    double end = 0.0;
+    for (int s = 0; s < G.nseg; ++s) {
+        const GemmSeg &S = G.seg[s];
+        const int nrt = (S.M + 127) / 128, nk = nchunks(S.K, S.kchunk);
+        for (int kc = 0; kc < nk; ++kc) {   // launch order: chunk, column block, row tile
+            const double cost = (std::min(S.K, (kc + 1) * S.kchunk) - kc * S.kchunk) / 32.0 + kFixed;
+            for (int64_t c = 0; c < (int64_t)S.ncb * nrt; ++c) {
+                std::vector<double> &h = free_at[wg++ % kXcd];
+                std::pop_heap(h.begin(), h.end(), std::greater<double>());
+                h.back() += cost;
+                end = std::max(end, h.back());
+                std::push_heap(h.begin(), h.end(), std::greater<double>());
+            }
+        }
+    }
+    return end;
+}
+
+// K split of one GEMM (which = 0 operators, 1 inverse masses) for R runs:
+// chunk counts for the exterior and interior segments and, for the operator
+// product, k per LDS stage.  The splits of 1 to 8 chunks per mesh are ranked
+// by the scheduling model above; the best few of each stage depth are timed
+// on the problem's own matrices (right-hand buffers zeroed first) once per
+// size class, and the choice is kept in the process-wide tuning table (and
+// its file), so every problem and context of the class uses the same shapes.
+bem_status block_tune(bem_problem *p, BlockBufs &bb, int which, int R, int nk[2], int &kst)
 {
     int nt, ncb;
     gemm_width(which == 0 ? 2 * R : 4 * R, nt, ncb);
-    int &slot = p->gemm_nk[which][nt_index(nt)];
+    int *slot = p->gemm_nk[which][nt_index(nt)];
     int &slot_kst = p->gemm_kst[which][nt_index(nt)];
-    if (slot > 0) { nk = slot; kst = slot_kst; return BEM_OK; }
+    if (slot[0] > 0) { nk[0] = slot[0]; nk[1] = slot[1]; kst = slot_kst; return BEM_OK; }
     bem_ctx *ctx = p->ctx;
     hipStream_t st = ctx->stream;
     const std::string key = std::string(which == 0 ? "gemm-ops" : "gemm-mass") + ":c" + std::to_string(32 * nt * ncb) +
                             ":e" + std::to_string(tune_class(p->ext->h.nv)) + ":i" +
                             std::to_string(tune_class(p->inte->h.nv));
+    auto valid = [&](const std::vector<int> &v) {
+        return v.size() == 3 && v[0] >= 1 && v[0] <= GEMM_MAX_SPLIT && v[1] >= 1 && v[1] <= GEMM_MAX_SPLIT &&
+               (v[2] == 32 || (v[2] == 64 && which == 0));
+    };
     std::vector<int> v;
     bem_status s = tuned(key, v, [&](std::vector<int> &out) -> bem_status {
         for (int m = 0; m < 2; ++m) {   // defined right-hand inputs for the timing runs
@@ -2328,38 +2364,51 @@ bem_status block_tune(bem_problem *p, BlockBufs &bb, int which, int R, int &nk, 
             BEM_HIP(hipMemsetAsync(bb.btw[m].ptr, 0, bb.btw[m].bytes, st));
             BEM_HIP(hipMemsetAsync(bb.btm[m].ptr, 0, bb.btm[m].bytes, st));
         }
+        int ncu = 0;
+        BEM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        struct Cand { int nk[2], kst; double model; };
+        std::vector<Cand> timed;
+        for (int ks : {32, 64}) {
+            if (which == 1 && ks != 32) continue;   // inverse-mass rows: multiples of 32 only
+            std::vector<Cand> all;
+            for (int a = 1; a <= GEMM_MAX_SPLIT; ++a)
+                for (int b = 1; b <= GEMM_MAX_SPLIT; ++b) {
+                    const int c[2] = {a, b};
+                    GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c, R, nullptr, ks) : mass_gemm_args(p, bb, c, R, nullptr);
+                    all.push_back({{a, b}, ks, gemm_model_time(G, std::max(1, ncu / 8) * (ks == 32 ? 2 : 1))});
+                }
+            std::stable_sort(all.begin(), all.end(), [](const Cand &x, const Cand &y) { return x.model < y.model; });
+            for (size_t q = 0; q < all.size() && q < 4; ++q) timed.push_back(all[q]);
+        }
         hipEvent_t e0, e1;
         BEM_HIP(hipEventCreate(&e0));
         BEM_HIP(hipEventCreate(&e1));
         struct EvGuard { hipEvent_t a, b; ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } g{e0, e1};
         float best = 1e30f;
-        int pick_nk = 4, pick_kst = 32;
-        for (int ks : {32, 64}) {
-            if (which == 1 && ks != 32) continue;   // inverse-mass rows: multiples of 32 only
-            for (int c : {1, 2, 4, 8}) {
-                float tmin = 1e30f;
-                for (int rep = 0; rep < 2; ++rep) {
-                    GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c, R, nullptr, ks) : mass_gemm_args(p, bb, c, R, nullptr);
-                    BEM_HIP(hipEventRecord(e0, st));
-                    bem_status q = launch_gemm_f32(ctx, G, st, which == 0 ? K_BLOCK_GEMM : K_MASS_GEMM);
-                    if (q) return q;
-                    BEM_HIP(hipEventRecord(e1, st));
-                    BEM_HIP(hipEventSynchronize(e1));
-                    float ms = 0;
-                    BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    tmin = std::min(tmin, ms);
-                }
-                if (tmin < best) { best = tmin; pick_nk = c; pick_kst = ks; }
+        Cand pick = timed.front();
+        for (const Cand &c : timed) {
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c.nk, R, nullptr, c.kst) : mass_gemm_args(p, bb, c.nk, R, nullptr);
+                BEM_HIP(hipEventRecord(e0, st));
+                bem_status q = launch_gemm_f32(ctx, G, st, which == 0 ? K_BLOCK_GEMM : K_MASS_GEMM);
+                if (q) return q;
+                BEM_HIP(hipEventRecord(e1, st));
+                BEM_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                BEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                tmin = std::min(tmin, ms);
             }
+            if (tmin < best) { best = tmin; pick = c; }
         }
-        out = {pick_nk, pick_kst};
+        out = {pick.nk[0], pick.nk[1], pick.kst};
         return BEM_OK;
-    });
+    }, valid);
     if (s) return s;
-    const bool valid = v.size() == 2 && (v[0] == 1 || v[0] == 2 || v[0] == 4 || v[0] == 8) &&
-                       (v[1] == 32 || (v[1] == 64 && which == 0));
-    slot = nk = valid ? v[0] : 4;
-    slot_kst = kst = valid ? v[1] : 32;
+    const bool ok = valid(v);
+    slot[0] = nk[0] = ok ? v[0] : 4;
+    slot[1] = nk[1] = ok ? v[1] : 4;
+    slot_kst = kst = ok ? v[2] : 32;
     return BEM_OK;
 }
 
@@ -2371,7 +2420,7 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
 {
     hipStream_t st = p->ctx->stream;
     const int nv[2] = {A.ne, A.ni};
-    int nk_ops = 0, nk_mass = 0, kst_ops = 32, kst_mass = 32;   // (tuning zeroes the right-hand buffers: before packing)
+    int nk_ops[2] = {0, 0}, nk_mass[2] = {0, 0}, kst_ops = 32, kst_mass = 32;   // (tuning zeroes the right-hand buffers: before packing)
     bem_status s = block_tune(p, bb, 0, R, nk_ops, kst_ops);
     if (!s && strong && p->mass_dense) s = block_tune(p, bb, 1, R, nk_mass, kst_mass);
     if (s) return s;

@@ -105,7 +105,8 @@ int tune_class(int64_t n)
     return n <= 1 ? 0 : (int)std::lround(4.0 * std::log2((double)n));
 }
 
-bem_status tuned(const std::string &key, std::vector<int> &value, const std::function<bem_status(std::vector<int> &)> &tune)
+bem_status tuned(const std::string &key, std::vector<int> &value, const std::function<bem_status(std::vector<int> &)> &tune,
+                 const std::function<bool(const std::vector<int> &)> &valid)
 {
     Table &t = table();
     {
@@ -113,7 +114,7 @@ bem_status tuned(const std::string &key, std::vector<int> &value, const std::fun
         load_locked(t);
         for (;;) {
             auto it = t.entries.find(key);
-            if (it != t.entries.end()) {
+            if (it != t.entries.end() && (!valid || valid(it->second))) {
                 value = it->second;
                 return BEM_OK;
             }

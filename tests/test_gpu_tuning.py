@@ -1,5 +1,5 @@
 """The kernel-shape tuner: the first block solve of a size class times the
-GEMM's K split and stage depth and the first solve the mat-vec's tile edge,
+GEMM's K splits (per mesh) and stage depth and the first solve the mat-vec's tile edge,
 records them in the process-wide table (and its file), and later problems of
 the class reuse them, so that their results are bitwise equal."""
 import os
@@ -40,9 +40,9 @@ def test_shapes_recorded_and_reused(ctx):
     mtf = [k for k in t1 if k.startswith("mtf-c64:")]
     print("tuning table:", t1)
     assert gemm and mtf
-    for k in gemm:
-        nk, kst = t1[k]
-        assert nk in (1, 2, 4, 8) and kst in (32, 64)
+    for k in gemm:   # K chunks of the exterior and interior segments, k per LDS stage
+        nke, nki, kst = t1[k]
+        assert 1 <= nke <= 8 and 1 <= nki <= 8 and kst in (32, 64)
     for k in mtf:
         assert t1[k][0] in (64, 128)
     # a second problem of the same class: the recorded shapes, the same bits

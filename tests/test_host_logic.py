@@ -115,13 +115,13 @@ def test_tuning_table_file(tmp_path):
     import subprocess
     import sys
     f = tmp_path / "tune.txt"
-    f.write_text("# a comment\ngemm-ops:c128:e53:i52 4 32\nmtf-c128:e53:i52 128\nbroken\n\nmtf-c64:e29:i29 64\n")
+    f.write_text("# a comment\ngemm-ops:c128:e53:i52 3 2 32\nmtf-c128:e53:i52 128\nbroken\n\nmtf-c64:e29:i29 64\n")
     code = ("import sys; sys.path.insert(0, %r); import paper_2206_00708_amd as B; "
             "t = B.tune_table(); print(sorted(t.items()))" % ROOT)
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
                          env=dict(os.environ, BEMTX_TUNE_FILE=str(f)))
     assert out.returncode == 0, out.stderr[-2000:]
-    assert out.stdout.strip().splitlines()[-1] == str(sorted({"gemm-ops:c128:e53:i52": [4, 32],
+    assert out.stdout.strip().splitlines()[-1] == str(sorted({"gemm-ops:c128:e53:i52": [3, 2, 32],
                                                               "mtf-c128:e53:i52": [128],
                                                               "mtf-c64:e29:i29": [64]}.items()))
 
