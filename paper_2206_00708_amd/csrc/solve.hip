@@ -1109,7 +1109,7 @@ __global__ __launch_bounds__(256) void dgs_dots_kernel(int n, int j, const int *
     w += run * B.vec;
     partial += run * B.partial;
     const int lane = threadIdx.x & 63;
-    const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int c = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform column
     if (c > j) return;
     const int chunk = cgs_chunk(n);
     const int r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
@@ -1306,7 +1306,8 @@ __global__ __launch_bounds__(256) void dgs_update_kernel(int n, int j, const int
     H += run * B.hess;
     hsum += run * B.small;
     npart += run * B.npart;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the coefficients go through scalar loads
     const double inv_nu = coef[j].x;
     if ((int)blockIdx.x >= nupd) {
         const int r = ((int)blockIdx.x - nupd) * 4 + wave;
