@@ -1095,8 +1095,12 @@ constexpr int MAXIT_CAP = 3000;   // Hessenberg column, rotations and g staged i
 
 // partial[chunk][c] = sum over the chunk's rows of conj(V_c) u_j and
 // partial[chunk][j + 1 + c] = that of conj(V_c) w, for c = 0..j (slot j is
-// u_j itself: alpha and gamma).  One wave per (chunk, c); grid (nchunk,
-// ceil((j + 1) / 4), runs), or larger (the extra waves return).
+// u_j itself: alpha and gamma).  One wave per (chunk, CPW consecutive
+// columns): with CPW = 2 the wave reads the chunks of u_j and w once for
+// both columns; each column's sum runs over the same rows in the same order
+// either way.  Grid (nchunk, ceil((j + 1) / (4 CPW)), runs), or larger (the
+// extra waves return).
+template <int CPW>
 __global__ __launch_bounds__(256) void dgs_dots_kernel(int n, int j, const int *__restrict__ jb,
                                                        const double2 *__restrict__ Vb, const double2 *__restrict__ w,
                                                        double2 *__restrict__ partial,
@@ -1109,28 +1113,41 @@ __global__ __launch_bounds__(256) void dgs_dots_kernel(int n, int j, const int *
     w += run * B.vec;
     partial += run * B.partial;
     const int lane = threadIdx.x & 63;
-    const int c = blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform column
+    const int c = CPW * (blockIdx.y * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6));   // wave-uniform
     if (c > j) return;
+    const int nc = min(CPW, j + 1 - c);   // columns of this wave
     const int chunk = cgs_chunk(n);
     const int r0 = blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-    const double2 *vc = Vb + (int64_t)c * n, *u = Vb + (int64_t)j * n;
-    double ur = 0, ui = 0, wr = 0, wi = 0;
+    const double2 *u = Vb + (int64_t)j * n;
+    const double2 *vc[CPW];
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) vc[q] = Vb + (int64_t)min(c + q, j) * n;   // a missing second column repeats u_j, unused
+    double ur[CPW], ui[CPW], wr[CPW], wi[CPW];
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) ur[q] = ui[q] = wr[q] = wi[q] = 0;
 #pragma unroll 4
     for (int r = r0 + lane; r < r1; r += 64) {
-        const double2 a = vc[r], x = u[r], y = w[r];
-        ur += a.x * x.x + a.y * x.y;
-        ui += a.x * x.y - a.y * x.x;
-        wr += a.x * y.x + a.y * y.y;
-        wi += a.x * y.y - a.y * y.x;
+        double2 av[CPW];
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) av[q] = vc[q][r];
+        const double2 x = u[r], y = w[r];
+#pragma unroll
+        for (int q = 0; q < CPW; ++q) {
+            const double2 a = av[q];
+            ur[q] += a.x * x.x + a.y * x.y;
+            ui[q] += a.x * x.y - a.y * x.x;
+            wr[q] += a.x * y.x + a.y * y.y;
+            wi[q] += a.x * y.y - a.y * y.x;
+        }
     }
-    ur = wave_sum(ur);
-    ui = wave_sum(ui);
-    wr = wave_sum(wr);
-    wi = wave_sum(wi);
-    if (lane == 0) {
-        double2 *pc = partial + (int64_t)blockIdx.x * 2 * (j + 1);
-        pc[c] = make_double2(ur, ui);
-        pc[j + 1 + c] = make_double2(wr, wi);
+    double2 *pc = partial + (int64_t)blockIdx.x * 2 * (j + 1);
+#pragma unroll
+    for (int q = 0; q < CPW; ++q) {
+        const double sur = wave_sum(ur[q]), sui = wave_sum(ui[q]), swr = wave_sum(wr[q]), swi = wave_sum(wi[q]);
+        if (lane == 0 && q < nc) {
+            pc[c + q] = make_double2(sur, sui);
+            pc[j + 1 + c + q] = make_double2(swr, swi);
+        }
     }
 }
 
@@ -2519,8 +2536,14 @@ struct Gmres {
         if (s) return s;
         {
             KTimer kt(ctx, K_CGS_DOTS);
-            launch_k(kt, dgs_dots_kernel, dim3(nchunk, (jcap + 1 + 3) / 4, R), dim3(256), 0, st, n, j, jb, Vb,
-                     W.z.as<double2>(), W.partial.as<double2>(), dst, B);
+            // two columns per wave once one-column waves would exceed about two per SIMD: sharing the
+            // reads of u_j and w then pays; below that the halved wave count costs more
+            if ((int64_t)nchunk * (jcap + 1) * R >= 2048)
+                launch_k(kt, dgs_dots_kernel<2>, dim3(nchunk, (jcap + 1 + 7) / 8, R), dim3(256), 0, st, n, j, jb, Vb,
+                         W.z.as<double2>(), W.partial.as<double2>(), dst, B);
+            else
+                launch_k(kt, dgs_dots_kernel<1>, dim3(nchunk, (jcap + 1 + 3) / 4, R), dim3(256), 0, st, n, j, jb, Vb,
+                         W.z.as<double2>(), W.partial.as<double2>(), dst, B);
         }
         {
             KTimer kt(ctx, K_ARNOLDI_FINISH);
