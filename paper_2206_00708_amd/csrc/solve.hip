@@ -2355,7 +2355,8 @@ double gemm_model_time(const GemmArgs &G, int slots_per_xcd)
 // K split of one GEMM (which = 0 operators, 1 inverse masses) for R runs:
 // chunk counts for the exterior and interior segments and, for the operator
 // product, k per LDS stage.  The splits of 1 to 8 chunks per mesh are ranked
-// by the scheduling model above; the best few of each stage depth are timed
+// by the scheduling model above; the best three of each stage depth and the
+// even splits 4/4 and 8/8 are timed (best of three launches each)
 // on the problem's own matrices (right-hand buffers zeroed first) once per
 // size class, and the choice is kept in the process-wide tuning table (and
 // its file), so every problem and context of the class uses the same shapes.
@@ -2396,7 +2397,14 @@ bem_status block_tune(bem_problem *p, BlockBufs &bb, int which, int R, int nk[2]
                     all.push_back({{a, b}, ks, gemm_model_time(G, std::max(1, ncu / 8) * (ks == 32 ? 2 : 1))});
                 }
             std::stable_sort(all.begin(), all.end(), [](const Cand &x, const Cand &y) { return x.model < y.model; });
-            for (size_t q = 0; q < all.size() && q < 4; ++q) timed.push_back(all[q]);
+            // the model's best three, and the even splits 4/4 and 8/8 (the model misses part of what the
+            // hardware does: in measurements the ranked and the even splits come within a few percent)
+            for (size_t q = 0; q < all.size() && q < 3; ++q) timed.push_back(all[q]);
+            for (int e : {4, 8}) {
+                bool have = false;
+                for (const Cand &c : timed) have = have || (c.kst == ks && c.nk[0] == e && c.nk[1] == e);
+                if (!have) timed.push_back({{e, e}, ks, 0.0});
+            }
         }
         hipEvent_t e0, e1;
         BEM_HIP(hipEventCreate(&e0));
@@ -2406,7 +2414,7 @@ bem_status block_tune(bem_problem *p, BlockBufs &bb, int which, int R, int nk[2]
         Cand pick = timed.front();
         for (const Cand &c : timed) {
             float tmin = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = 0; rep < 3; ++rep) {
                 GemmArgs G = which == 0 ? ops_gemm_args(p, bb, c.nk, R, nullptr, c.kst) : mass_gemm_args(p, bb, c.nk, R, nullptr);
                 BEM_HIP(hipEventRecord(e0, st));
                 bem_status q = launch_gemm_f32(ctx, G, st, which == 0 ? K_BLOCK_GEMM : K_MASS_GEMM);

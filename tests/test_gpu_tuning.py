@@ -67,3 +67,36 @@ def test_fp64_tile_edge(ctx):
     out, st, code = p.solve(c["dirs"], tol=1e-8, maxit=500)
     assert code == B.OK
     assert any(k.startswith("mtf-c128:") for k in B.tune_table())
+
+
+def test_old_format_entry_tuned_again(tmp_path):
+    """A table file holding the operator GEMM's entry in the older two-value
+    form (one K split for both meshes): the first block solve of that class
+    times the shapes again and replaces the entry with the three-value form.
+    Run in a child process, since the table is read once per process."""
+    import math
+    import subprocess
+    import sys
+    c = synth.make_config("C1")
+    cls = lambda n: round(4 * math.log2(n))
+    key = f"gemm-ops:c32:e{cls(len(c['ext'][0]))}:i{cls(len(c['int'][0]))}"   # 4 runs: 8 real columns, 32-wide tile
+    f = tmp_path / "tune.txt"
+    f.write_text(f"{key} 4 32\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys, numpy as np; sys.path.insert(0, %r); sys.path.insert(0, %r)\n"
+        "import synth, paper_2206_00708_amd as B\n"
+        "c = synth.make_config('C1'); ctx = B.Context(0)\n"
+        "me, mi = B.Mesh(ctx, *c['ext']), B.Mesh(ctx, *c['int'])\n"
+        "p = B.Problem(ctx, me, mi, c['k_ext'], c['k_int'], c['rho_ext'], c['rho_int'], precision=B.C64_MIXED)\n"
+        "p.assemble_operators(); p.assemble_projection()\n"
+        "x, s, code = p.solve(synth.plane_wave_directions(4, np.random.default_rng(3)), tol=1e-8, maxit=500, batch=4)\n"
+        "assert code == B.OK\n"
+        "print(B.tune_table()[%r])\n" % (root, os.path.join(root, "tests"), key))
+    env = dict(os.environ, BEMTX_TUNE_FILE=str(f))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240, env=env)
+    assert out.returncode == 0, out.stderr[-2000:]
+    v = eval(out.stdout.strip().splitlines()[-1])
+    print("re-tuned entry:", key, v)
+    assert len(v) == 3 and 1 <= v[0] <= 8 and 1 <= v[1] <= 8 and v[2] in (32, 64)
+    assert f"{key} {v[0]} {v[1]} {v[2]}" in f.read_text()
