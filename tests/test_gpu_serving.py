@@ -2,8 +2,8 @@
 the same alone and in the mix, admission respects the memory budget, an
 oversized request fails alone, and a served result matches the oracle.
 Tolerances: results alone vs in the mix 1e-6 relative (the kernels are
-deterministic; only the per-problem choice of the matrix-core K split, made
-by timing, may differ between runs, which changes FP32 summation order);
+deterministic; only the matrix-core K splits, picked by timing once per size
+class, may differ between processes, which changes FP32 summation order);
 traces vs the oracle's LU solution 1e-5 (the method's target)."""
 import numpy as np
 import pytest
