@@ -363,8 +363,8 @@ bem_status bem_mesh_create(bem_ctx *ctx, const double *xyz, int64_t nv, const in
     if (s == BEM_OK) s = upload(ctx, m->d.tri, m->h.tri);
     if (s == BEM_OK) s = upload(ctx, m->d.blk_start, m->h.blk_start);
     if (s == BEM_OK) s = upload(ctx, m->d.blk_nslot, m->h.blk_nslot);
-    if (s == BEM_OK) s = upload(ctx, m->d.slot_cnt, m->h.slot_cnt);
-    if (s == BEM_OK) s = upload(ctx, m->d.slot_ent, m->h.slot_ent);
+    if (s == BEM_OK) s = upload(ctx, m->d.slot_off, m->h.slot_off);
+    if (s == BEM_OK) s = upload(ctx, m->d.slot_rank, m->h.slot_rank);
     if (s == BEM_OK) s = upload(ctx, m->d.memb_ptr, m->h.memb_ptr);
     if (s == BEM_OK) s = upload(ctx, m->d.memb, m->h.memb);
     if (s == BEM_OK) s = upload(ctx, m->d.strip_rows, m->h.strip_rows);

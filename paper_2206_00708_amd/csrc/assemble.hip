@@ -12,7 +12,8 @@
 //                     G are reduced in registers, D follows from them
 //                     (curl.curl S - k^2 n.n V).  The 9 entries of each pair
 //                     are summed per vertex slot through LDS in a fixed order
-//                     and the block-pair tile is written once.  Because the
+//                     (runs of slot-sorted corners) and the block-pair tile
+//                     is written once.  Because the
 //                     regular rule is symmetric in (x, y), the tile of
 //                     (b1, b2) also provides (b2, b1): V, D transpose to
 //                     themselves and K, T into each other.
@@ -86,8 +87,8 @@ struct TileArgs {
     const int32_t *tri;
     const int32_t *blk_start;
     const int32_t *blk_nslot;
-    const uint8_t *slot_cnt;
-    const uint8_t *slot_ent;
+    const uint8_t *slot_off;    // [nb][SLOT_OFF_LD] first slot-major rank of each slot
+    const uint8_t *slot_rank;   // [nb][3 * BT] slot-major rank of each corner
     int32_t nb;
     double k;
     double kim;            // imaginary part of the wavenumber (read by the absorbing instantiation only)
@@ -116,54 +117,77 @@ __device__ inline void tile_of(int64_t t, int nb, int &b1, int &b2)
     b2 = b + (int)(t - ((int64_t)b * nb - (int64_t)b * (b - 1) / 2));
 }
 
-// Per-slot sums of the staged 9 entries of every triangle pair of the tile:
+// Per-slot sums of the 9 entries of every triangle pair of the tile:
 // entry (q1, q2) adds the entries (a, b) of every pair whose test triangle
-// has slot q1 at corner a and trial triangle slot q2 at corner b.  The sum
-// separates over the two blocks, so it runs in two stages whose loop lengths
-// are the same on every lane of a wave:
-//   1. P[u][q2] = sum over the corners (t2, b) of trial slot q2 of the entry
-//      of test corner u = (t1, a); one lane per test corner, one trial slot
-//      per wave at a time;
-//   2. entry (q1, q2) = sum over the test corners u of slot q1 of P[u][q2];
-//      one lane per trial slot, one test slot per half-wave at a time.
-// Staged entries: st[t1 * ST_ROW + 9 t2 + 3 a + b] (the row padding keeps
-// the 16-byte reads of stage 1 on distinct LDS banks).  Fixed summation
-// order; written to out[4 * e + op] (tile layout [entry][op]).
-constexpr int ST_ROW = 9 * BT + 1;
+// has slot q1 at corner a and trial triangle slot q2 at corner b.  The
+// corners of each block are ranked in slot-major order (the order of the
+// block's slot lists, built on the host), so that the corners of a slot
+// form a run of consecutive ranks.  The sum separates over the two blocks
+// and runs in two stages, each a set of independent items spread over the
+// workgroup's threads:
+//   1. item (u, q2): P[rank1(u)][q2] = sum over the run of trial slot q2 of
+//      the staged row of test corner u = (t1, a);
+//   2. item (q1, q2): entry (q1, q2) = sum over the run of test slot q1 of
+//      the P rows, written to out[4 * e + op] (tile layout [entry][op]).
+// Both stages add in run order, i.e. in slot-list order.  Each item loads
+// the first 4 (then, for longer runs, 4 more) entries of its run at once;
+// the loads past a run's end fall in the padding or the next run and are
+// not added.  Staged entries: st[u * SROW + rank2(t2, b)].
+constexpr int SROW = 3 * BT + 1;    // staged row: one entry per trial corner (+1: distinct LDS banks per lane)
+constexpr int PROW = SMAX + 1;      // partial-sum row: one entry per trial slot (+1 likewise)
+constexpr int ST_LEN = 3 * BT * SROW + 8;
+constexpr int P_LEN = (3 * BT + 8) * PROW;
+constexpr int SLOT_IT1 = (3 * BT * SMAX + 255) / 256;   // stage-1 items per thread
+constexpr int SLOT_IT2 = (SMAX * SMAX + 255) / 256;     // stage-2 items per thread
 
+// sum of x[0 .. m) with x[v] = src[v * stride], in order; m <= LMAX
 template <class C2>
-__device__ inline void tile_slot_sums(int tid, int op, int ns1, int ns2, const uint8_t *c1, const uint8_t *c2,
-                                      const uint8_t *u1, const uint8_t *o2, const C2 *st, C2 *P, C2 *out)
+__device__ inline C2 run_sum(const C2 *src, int stride, int m)
 {
     using R = decltype(C2::x);
-    const int wave = tid >> 6, lane = tid & 63;
-    if (lane < 3 * BT) {
-        const int t = lane / 3, a = lane - 3 * t;
-        const C2 *row = st + t * ST_ROW + 3 * a;
-        for (int q2 = wave; q2 < ns2; q2 += 4) {
-            const int m2 = c2[q2];
-            R re = 0, im = 0;
-            for (int v = 0; v < m2; ++v) {
-                const C2 x = row[o2[q2 * LMAX + v]];
-                re += x.x;
-                im += x.y;
-            }
-            P[lane * SMAX + q2] = C2{re, im};
+    const C2 x0 = src[0], x1 = src[stride], x2 = src[2 * stride], x3 = src[3 * stride];
+    R re = x0.x, im = x0.y;
+    if (m > 1) { re += x1.x; im += x1.y; }
+    if (m > 2) { re += x2.x; im += x2.y; }
+    if (m > 3) { re += x3.x; im += x3.y; }
+    if (m > 4) {
+        const C2 y0 = src[4 * stride], y1 = src[5 * stride], y2 = src[6 * stride], y3 = src[7 * stride];
+        re += y0.x; im += y0.y;
+        if (m > 5) { re += y1.x; im += y1.y; }
+        if (m > 6) { re += y2.x; im += y2.y; }
+        if (m > 7) { re += y3.x; im += y3.y; }
+        for (int v = 8; v < m; ++v) { re += src[v * stride].x; im += src[v * stride].y; }
+    }
+    return C2{re, im};
+}
+
+// stage 1 (every run has at least one corner, so m >= 1)
+template <class C2>
+__device__ inline void slot_sums_trial(int tid, int nc1, int ns2, const uint8_t *o2, const uint8_t *r1, const C2 *st,
+                                       C2 *P)
+{
+#pragma unroll
+    for (int j = 0; j < SLOT_IT1; ++j) {
+        const int it = tid + 256 * j, q2 = it / (3 * BT), u = it - q2 * (3 * BT);
+        if (q2 < ns2 && u < nc1) {
+            const int s0 = o2[q2];
+            P[r1[u] * PROW + q2] = run_sum(st + u * SROW + s0, 1, o2[q2 + 1] - s0);
         }
     }
-    __syncthreads();
-    const int q2 = lane & 31;
-    if (q2 < ns2)
-        for (int q1 = wave + 4 * (lane >> 5); q1 < ns1; q1 += 8) {
-            const int m1 = c1[q1];
-            R re = 0, im = 0;
-            for (int u = 0; u < m1; ++u) {
-                const C2 x = P[u1[q1 * LMAX + u] * SMAX + q2];
-                re += x.x;
-                im += x.y;
-            }
-            out[4 * (q1 * SMAX + q2) + op] = C2{re, im};
+}
+
+// stage 2
+template <class C2>
+__device__ inline void slot_sums_test(int tid, int op, int ns1, int ns2, const uint8_t *o1, const C2 *P, C2 *out)
+{
+#pragma unroll
+    for (int j = 0; j < SLOT_IT2; ++j) {
+        const int it = tid + 256 * j, q1 = it / SMAX, q2 = it - q1 * SMAX;
+        if (q1 < ns1 && q2 < ns2) {
+            const int s0 = o1[q1];
+            out[4 * it + op] = run_sum(P + s0 * PROW + q2, PROW, o1[q1 + 1] - s0);
         }
+    }
 }
 
 // sin and cos of a small angle t, |t| <= 1: Taylor polynomials of sin
@@ -290,8 +314,8 @@ struct TileArgsF {
     const int32_t *tri;
     const int32_t *blk_start;
     const int32_t *blk_nslot;
-    const uint8_t *slot_cnt;
-    const uint8_t *slot_ent;
+    const uint8_t *slot_off;    // [nb][SLOT_OFF_LD] first slot-major rank of each slot
+    const uint8_t *slot_rank;   // [nb][3 * BT] slot-major rank of each corner
     int32_t nb;
     double k;
     double kim;            // imaginary part of the wavenumber (read by the absorbing instantiation only)
@@ -306,11 +330,10 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
 {
     __shared__ TriGeo gX[BT], gY[BT];
     __shared__ int32_t vX[BT * 3], vY[BT * 3];
-    __shared__ uint8_t c1[SMAX], c2[SMAX];
-    __shared__ uint8_t e1[SMAX * LMAX];    // slot corner (t, a) of block 1 as the test corner 3 t + a
-    __shared__ uint8_t e2[SMAX * LMAX];    // slot corner (t, b) of block 2 as the offset 9 t + b
-    __shared__ double2 st[BT * ST_ROW];   // the 9 entries of every thread's pair, one operator at a time
-    __shared__ double2 P[3 * BT * SMAX];  // test corner x trial slot partial sums
+    __shared__ uint8_t o1[SLOT_OFF_LD], o2[SLOT_OFF_LD];   // first slot-major rank of each slot
+    __shared__ uint8_t r1[3 * BT], r2[3 * BT];             // slot-major rank of each corner
+    __shared__ double2 st[ST_LEN];   // the 9 entries of every thread's pair, one operator at a time
+    __shared__ double2 P[P_LEN];     // test-corner rank x trial slot partial sums
 
     const int64_t tile = tile0 + blockIdx.x;
     int b1, b2;
@@ -328,17 +351,20 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
         for (int q = tid; q < n2 * w; q += 256) d2[q] = src2[q];
         if (tid < n1 * 3) vX[tid] = A.tri[3 * s1 + tid];
         if (tid < n2 * 3) vY[tid] = A.tri[3 * s2 + tid];
-        if (tid < SMAX) { c1[tid] = A.slot_cnt[b1 * SMAX + tid]; c2[tid] = A.slot_cnt[b2 * SMAX + tid]; }
-        for (int q = tid; q < SMAX * LMAX; q += 256) {
-            const int en1 = A.slot_ent[(size_t)b1 * SMAX * LMAX + q], en2 = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
-            e1[q] = (uint8_t)en1;
-            e2[q] = (uint8_t)((en2 / 3) * 9 + en2 % 3);
+        if (tid < SLOT_OFF_LD) {
+            o1[tid] = A.slot_off[(size_t)b1 * SLOT_OFF_LD + tid];
+            o2[tid] = A.slot_off[(size_t)b2 * SLOT_OFF_LD + tid];
+        } else if (tid >= 64 && tid < 64 + 3 * BT) {
+            r1[tid - 64] = A.slot_rank[(size_t)b1 * 3 * BT + tid - 64];
+            r2[tid - 64] = A.slot_rank[(size_t)b2 * 3 * BT + tid - 64];
         }
     }
     __syncthreads();
 
-    const int t1 = tid >> 4, t2 = tid & 15, sbase = t1 * ST_ROW + 9 * t2;
-    bool active = t1 < n1 && t2 < n2;
+    const int t1 = tid >> 4, t2 = tid & 15, sbase = 3 * t1 * SROW;
+    const bool staged = t1 < n1 && t2 < n2;   // the pair's entries have a place in the staged rows
+    const int rk0 = staged ? r2[3 * t2] : 0, rk1 = staged ? r2[3 * t2 + 1] : 0, rk2 = staged ? r2[3 * t2 + 2] : 0;
+    bool active = staged;
     if (active) {
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) active = active && (vX[3 * t1 + a] != vY[3 * t2 + b]);
@@ -360,7 +386,7 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
             pair_quadrature<CK, false>(X, Y, k, A.kim, vr, vi, kr, ki, tr, ti, sr, si);
     }
 
-    // ---- per-slot reduction through LDS, one operator at a time
+    // ---- per-slot reduction through LDS, one operator at a time (two barriers per operator)
     double2 *out = A.scratch + (tile - A.tile_base) * (4 * SMAX * SMAX);
 #pragma unroll 1
     for (int op = 0; op < 4; ++op) {
@@ -374,10 +400,10 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
                     if constexpr (CK) {   // complex k^2
                         const double k2r = k * k - A.kim * A.kim, k2i = 2.0 * k * A.kim;
                         const double v_r = vr[3 * a + b], v_i = vi[3 * a + b];
-                        st[sbase + 3 * a + b] = make_double2(cc * sr - nn * (k2r * v_r - k2i * v_i),
+                        st[sbase + a * SROW + (b == 0 ? rk0 : (b == 1 ? rk1 : rk2))] = make_double2(cc * sr - nn * (k2r * v_r - k2i * v_i),
                                                                cc * si - nn * (k2r * v_i + k2i * v_r));
                     } else {
-                        st[sbase + 3 * a + b] = make_double2(cc * sr - k * k * nn * vr[3 * a + b],
+                        st[sbase + a * SROW + (b == 0 ? rk0 : (b == 1 ? rk1 : rk2))] = make_double2(cc * sr - k * k * nn * vr[3 * a + b],
                                                                cc * si - k * k * nn * vi[3 * a + b]);
                     }
                 }
@@ -386,12 +412,15 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
             for (int e = 0; e < 9; ++e) {
                 double re = op == 0 ? vr[e] : (op == 1 ? kr[e] : (op == 2 ? tr[e] : 0.0));
                 double im = op == 0 ? vi[e] : (op == 1 ? ki[e] : (op == 2 ? ti[e] : 0.0));
-                st[sbase + e] = active ? make_double2(re, im) : make_double2(0.0, 0.0);
+                if (staged)
+                    st[sbase + (e / 3) * SROW + (e % 3 == 0 ? rk0 : (e % 3 == 1 ? rk1 : rk2))] =
+                        active ? make_double2(re, im) : make_double2(0.0, 0.0);
             }
         }
-        __syncthreads();
-        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st, P, out);
-        __syncthreads();
+        __syncthreads();   // st holds this operator; the previous operator's stage 2 is done with P
+        slot_sums_trial(tid, 3 * n1, ns2, o2, r1, st, P);
+        __syncthreads();   // P complete; st free for the next operator
+        slot_sums_test(tid, op, ns1, ns2, o1, P, out);
     }
 }
 
@@ -408,11 +437,10 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
 {
     __shared__ TriGeoF gX[BT], gY[BT];
     __shared__ int32_t vX[BT * 3], vY[BT * 3];
-    __shared__ uint8_t c1[SMAX], c2[SMAX];
-    __shared__ uint8_t e1[SMAX * LMAX];    // slot corner (t, a) of block 1 as the test corner 3 t + a
-    __shared__ uint8_t e2[SMAX * LMAX];    // slot corner (t, b) of block 2 as the offset 9 t + b
-    __shared__ float2 st[BT * ST_ROW];
-    __shared__ float2 P[3 * BT * SMAX];
+    __shared__ uint8_t o1[SLOT_OFF_LD], o2[SLOT_OFF_LD];   // first slot-major rank of each slot
+    __shared__ uint8_t r1[3 * BT], r2[3 * BT];             // slot-major rank of each corner
+    __shared__ float2 st[ST_LEN];
+    __shared__ float2 P[P_LEN];
 
     const int64_t tile = tile0 + blockIdx.x;
     int b1, b2;
@@ -430,17 +458,20 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
         for (int q = tid; q < n2 * w; q += 256) d2[q] = src2[q];
         if (tid < n1 * 3) vX[tid] = A.tri[3 * s1 + tid];
         if (tid < n2 * 3) vY[tid] = A.tri[3 * s2 + tid];
-        if (tid < SMAX) { c1[tid] = A.slot_cnt[b1 * SMAX + tid]; c2[tid] = A.slot_cnt[b2 * SMAX + tid]; }
-        for (int q = tid; q < SMAX * LMAX; q += 256) {
-            const int en1 = A.slot_ent[(size_t)b1 * SMAX * LMAX + q], en2 = A.slot_ent[(size_t)b2 * SMAX * LMAX + q];
-            e1[q] = (uint8_t)en1;
-            e2[q] = (uint8_t)((en2 / 3) * 9 + en2 % 3);
+        if (tid < SLOT_OFF_LD) {
+            o1[tid] = A.slot_off[(size_t)b1 * SLOT_OFF_LD + tid];
+            o2[tid] = A.slot_off[(size_t)b2 * SLOT_OFF_LD + tid];
+        } else if (tid >= 64 && tid < 64 + 3 * BT) {
+            r1[tid - 64] = A.slot_rank[(size_t)b1 * 3 * BT + tid - 64];
+            r2[tid - 64] = A.slot_rank[(size_t)b2 * 3 * BT + tid - 64];
         }
     }
     __syncthreads();
 
-    const int t1 = tid >> 4, t2 = tid & 15, sbase = t1 * ST_ROW + 9 * t2;
-    bool active = t1 < n1 && t2 < n2;
+    const int t1 = tid >> 4, t2 = tid & 15, sbase = 3 * t1 * SROW;
+    const bool staged = t1 < n1 && t2 < n2;   // the pair's entries have a place in the staged rows
+    const int rk0 = staged ? r2[3 * t2] : 0, rk1 = staged ? r2[3 * t2 + 1] : 0, rk2 = staged ? r2[3 * t2 + 2] : 0;
+    bool active = staged;
     if (active) {
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) active = active && (vX[3 * t1 + a] != vY[3 * t2 + b]);
@@ -545,10 +576,10 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
                     if constexpr (CK) {   // complex k^2
                         const float k2r = (float)(A.k * A.k - A.kim * A.kim), k2i = (float)(2.0 * A.k * A.kim);
                         const float v_r = vr[3 * a + b], v_i = vi[3 * a + b];
-                        st[sbase + 3 * a + b] = make_float2(cc * sr - nn * (k2r * v_r - k2i * v_i),
+                        st[sbase + a * SROW + (b == 0 ? rk0 : (b == 1 ? rk1 : rk2))] = make_float2(cc * sr - nn * (k2r * v_r - k2i * v_i),
                                                               cc * si - nn * (k2r * v_i + k2i * v_r));
                     } else {
-                        st[sbase + 3 * a + b] = make_float2(cc * sr - kf * kf * nn * vr[3 * a + b],
+                        st[sbase + a * SROW + (b == 0 ? rk0 : (b == 1 ? rk1 : rk2))] = make_float2(cc * sr - kf * kf * nn * vr[3 * a + b],
                                                               cc * si - kf * kf * nn * vi[3 * a + b]);
                     }
                 }
@@ -557,12 +588,15 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
             for (int e = 0; e < 9; ++e) {
                 float re = op == 0 ? vr[e] : (op == 1 ? kr[e] : (op == 2 ? tr[e] : 0.f));
                 float im = op == 0 ? vi[e] : (op == 1 ? ki[e] : (op == 2 ? ti[e] : 0.f));
-                st[sbase + e] = active ? make_float2(re, im) : make_float2(0.f, 0.f);
+                if (staged)
+                    st[sbase + (e / 3) * SROW + (e % 3 == 0 ? rk0 : (e % 3 == 1 ? rk1 : rk2))] =
+                        active ? make_float2(re, im) : make_float2(0.f, 0.f);
             }
         }
-        __syncthreads();
-        tile_slot_sums(tid, op, ns1, ns2, c1, c2, e1, e2, st, P, out);
-        __syncthreads();
+        __syncthreads();   // st holds this operator; the previous operator's stage 2 is done with P
+        slot_sums_trial(tid, 3 * n1, ns2, o2, r1, st, P);
+        __syncthreads();   // P complete; st free for the next operator
+        slot_sums_test(tid, op, ns1, ns2, o1, P, out);
     }
 }
 
@@ -884,8 +918,8 @@ bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, vo
                 A.tri = m->d.tri.as<int32_t>();
                 A.blk_start = m->d.blk_start.as<int32_t>();
                 A.blk_nslot = m->d.blk_nslot.as<int32_t>();
-                A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
-                A.slot_ent = m->d.slot_ent.as<uint8_t>();
+                A.slot_off = m->d.slot_off.as<uint8_t>();
+                A.slot_rank = m->d.slot_rank.as<uint8_t>();
                 A.nb = (int32_t)nb;
                 A.k = k;
                 A.kim = kim;
@@ -901,8 +935,8 @@ bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, vo
                 A.tri = m->d.tri.as<int32_t>();
                 A.blk_start = m->d.blk_start.as<int32_t>();
                 A.blk_nslot = m->d.blk_nslot.as<int32_t>();
-                A.slot_cnt = m->d.slot_cnt.as<uint8_t>();
-                A.slot_ent = m->d.slot_ent.as<uint8_t>();
+                A.slot_off = m->d.slot_off.as<uint8_t>();
+                A.slot_rank = m->d.slot_rank.as<uint8_t>();
                 A.nb = (int32_t)nb;
                 A.k = k;
                 A.kim = kim;

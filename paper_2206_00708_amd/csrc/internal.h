@@ -25,6 +25,7 @@ namespace bemtx {
 constexpr int BT = 16;
 constexpr int SMAX = 24;
 constexpr int LMAX = 12;
+constexpr int SLOT_OFF_LD = 32;   // row length of the per-block slot offsets (SMAX + 1 used)
 // block-pair tiles per assembly strip: the tile scratch holds two strips
 // (FP64: 2 x 2.4 GB) whatever the mesh size
 constexpr int64_t ASM_STRIP_TILES = 65536;
@@ -131,6 +132,10 @@ struct MeshData {
     HVec<int32_t> blk_slots;    // [nb][SMAX] internal vertex ids
     HVec<uint8_t> slot_cnt;     // [nb][SMAX]
     HVec<uint8_t> slot_ent;     // [nb][SMAX][LMAX] = tlocal*3 + corner
+    // slot-major ranks of a block's corners (the order of its slot lists): slot_off[b][q] the first rank of
+    // slot q (slot_off[b][nslot] = number of corners), slot_rank[b][tlocal * 3 + corner] the corner's rank
+    HVec<uint8_t> slot_off;     // [nb][SLOT_OFF_LD]
+    HVec<uint8_t> slot_rank;    // [nb][3 * BT]
     HVec<int32_t> memb_ptr;     // [nv+1]
     HVec<int32_t> memb;         // block<<8 | slot
     // assembly strips: tile rows (first block of the tile) [strip_b[s], strip_b[s+1]), at most ASM_STRIP_TILES
@@ -150,7 +155,7 @@ struct MeshData {
 struct MeshDev {
     DevMem perm;   // caller vertex -> internal vertex (int32)
     DevMem geof;   // TriGeoF table
-    DevMem xyz, tri, blk_start, blk_nslot, slot_cnt, slot_ent, memb_ptr, memb, sing, near_i, near_j,
+    DevMem xyz, tri, blk_start, blk_nslot, slot_off, slot_rank, memb_ptr, memb, sing, near_i, near_j,
         near_ptr, near_src, near_row, star_ptr, star_ent, geo, strip_rows;
 };
 

@@ -312,6 +312,8 @@ bem_status mesh_prepare(MeshData &m, int64_t strip_tiles)
     m.blk_slots.assign((size_t)nb * SMAX, -1);
     m.slot_cnt.assign((size_t)nb * SMAX, 0);
     m.slot_ent.assign((size_t)nb * SMAX * LMAX, 0);
+    m.slot_off.assign((size_t)nb * SLOT_OFF_LD, 0);
+    m.slot_rank.assign((size_t)nb * 3 * BT, 0);
     m.memb_ptr.assign(nv + 1, 0);
     // blocks are independent (each writes only its own slot tables): in parallel
     std::atomic<int> slot_err{0};   // 1: vertex overflow, 2: valence
@@ -334,6 +336,14 @@ bem_status mesh_prepare(MeshData &m, int64_t strip_tiles)
                     m.slot_ent[((size_t)b * SMAX + q) * LMAX + cnt] = (uint8_t)((t - m.blk_start[b]) * 3 + a);
                     ++cnt;
                 }
+            int off = 0;
+            for (int q = 0; q < nvs; ++q) {
+                m.slot_off[(size_t)b * SLOT_OFF_LD + q] = (uint8_t)off;
+                for (int v = 0; v < m.slot_cnt[(size_t)b * SMAX + q]; ++v)
+                    m.slot_rank[(size_t)b * 3 * BT + m.slot_ent[((size_t)b * SMAX + q) * LMAX + v]] = (uint8_t)(off + v);
+                off += m.slot_cnt[(size_t)b * SMAX + q];
+            }
+            m.slot_off[(size_t)b * SLOT_OFF_LD + nvs] = (uint8_t)off;
         }
     });
     if (slot_err == 1) return set_error(BEM_E_MESH, "internal: block vertex overflow");
