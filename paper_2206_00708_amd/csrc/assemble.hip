@@ -309,6 +309,15 @@ __device__ inline void pair_quadrature(const TriGeo &X, const TriGeo &Y, double 
     for (int e = 0; e < 9; ++e) { sr += vr[e]; si += vi[e]; }
 }
 
+// A triangle's table in LDS, padded to an odd number of 16-byte units (23):
+// the 16 trial triangles a wave reads at once then fall on distinct LDS banks
+// (the unpadded 22 units put triangles t and t + 8 on the same banks).
+struct alignas(16) TriGeoLds {
+    TriGeo g;
+    double pad[2];
+};
+static_assert(sizeof(TriGeoLds) % 32 == 16, "LDS stride of the triangle tables must be an odd number of 16-byte units");
+
 struct TileArgsF {
     const TriGeoF *geof;
     const int32_t *tri;
@@ -328,7 +337,7 @@ struct TileArgsF {
 template <bool CK>
 __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64_t tile0)
 {
-    __shared__ TriGeo gX[BT], gY[BT];
+    __shared__ TriGeoLds gX[BT], gY[BT];
     __shared__ int32_t vX[BT * 3], vY[BT * 3];
     __shared__ uint8_t o1[SLOT_OFF_LD], o2[SLOT_OFF_LD];   // first slot-major rank of each slot
     __shared__ uint8_t r1[3 * BT], r2[3 * BT];             // slot-major rank of each corner
@@ -346,9 +355,9 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
         const double *src1 = reinterpret_cast<const double *>(A.geo + s1);
         const double *src2 = reinterpret_cast<const double *>(A.geo + s2);
         double *d1 = reinterpret_cast<double *>(gX), *d2 = reinterpret_cast<double *>(gY);
-        const int w = sizeof(TriGeo) / sizeof(double);
-        for (int q = tid; q < n1 * w; q += 256) d1[q] = src1[q];
-        for (int q = tid; q < n2 * w; q += 256) d2[q] = src2[q];
+        constexpr int w = sizeof(TriGeo) / sizeof(double), wl = sizeof(TriGeoLds) / sizeof(double);
+        for (int q = tid; q < n1 * w; q += 256) d1[(q / w) * wl + q % w] = src1[q];
+        for (int q = tid; q < n2 * w; q += 256) d2[(q / w) * wl + q % w] = src2[q];
         if (tid < n1 * 3) vX[tid] = A.tri[3 * s1 + tid];
         if (tid < n2 * 3) vY[tid] = A.tri[3 * s2 + tid];
         if (tid < SLOT_OFF_LD) {
@@ -374,8 +383,8 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
     for (int e = 0; e < 9; ++e) { vr[e] = vi[e] = kr[e] = ki[e] = tr[e] = ti[e] = 0.0; }
     const double k = A.k;
     if (active) {
-        const TriGeo &X = gX[t1];
-        const TriGeo &Y = gY[t2];
+        const TriGeo &X = gX[t1].g;
+        const TriGeo &Y = gY[t2].g;
         // Phase by a per-pair base when k (rho_X + rho_Y) <= 1: with r0 the
         // centroid distance, |k (r - r0)| <= 1 for every point pair, so
         // exp(i k r) = exp(i k r0) exp(i k (r - r0)) takes one reduced
@@ -391,8 +400,8 @@ __global__ __launch_bounds__(256, 2) void regular_tiles_kernel(TileArgs A, int64
 #pragma unroll 1
     for (int op = 0; op < 4; ++op) {
         if (op == 3 && active) {
-            const TriGeo &X = gX[t1];
-            const TriGeo &Y = gY[t2];
+            const TriGeo &X = gX[t1].g;
+            const TriGeo &Y = gY[t2].g;
             const double nn = X.n[0] * Y.n[0] + X.n[1] * Y.n[1] + X.n[2] * Y.n[2];
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) {
