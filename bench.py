@@ -77,14 +77,14 @@ COUNTED_TRAFFIC = {
 # the software sin/cos (the small-angle polynomials and the rotation by the
 # pair's base phase: 46 of the per-point-pair flops).
 COUNTED_VALU = {
-    ("regular_tiles", "C3"): {"flops_fp64": 1309899766.7 * 64, "valu_insts": 1097586150, "valu_busy": 0.577,
-                              "sincos_flop_share": 0.32, "isolated_launch_us": 3240.5,
+    ("regular_tiles", "C3"): {"flops_fp64": 1310718788.0 * 64, "valu_insts": 1067106586, "valu_busy": 0.701,
+                              "sincos_flop_share": 0.32, "isolated_launch_us": 2715.7,
                               "source": "paper_2206_00708_amd/csrc/assemble.hip",
-                              "sha1": "f082f069c4a3fa8f612660013e24cd8793861c04"},
-    ("regular_tiles", "C2"): {"flops_fp64": 863828424.0 * 64, "valu_insts": 723089866, "valu_busy": 0.580,
-                              "sincos_flop_share": 0.32, "isolated_launch_us": 2334.5,
+                              "sha1": "91e322714d2e8c260d968b9c3593aa8005443459"},
+    ("regular_tiles", "C2"): {"flops_fp64": 864256332.0 * 64, "valu_insts": 702649931, "valu_busy": 0.704,
+                              "sincos_flop_share": 0.32, "isolated_launch_us": 1912.8,
                               "source": "paper_2206_00708_amd/csrc/assemble.hip",
-                              "sha1": "f082f069c4a3fa8f612660013e24cd8793861c04"},
+                              "sha1": "91e322714d2e8c260d968b9c3593aa8005443459"},
 }
 
 
@@ -640,6 +640,11 @@ def incident_run(ctx, B, synth, np):
     return res
 
 
+def progress(what, t0):
+    """One line on stderr per finished section (stdout carries only the JSON line)."""
+    print(f"bench: {what} done ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -698,8 +703,10 @@ def main():
     timed = ("regular_tiles", "mtf_dense")
     breakdown = ("regular_tiles", "gather_tiles", "singular_pairs", "mtf_dense", "mass_apply", "cgs_dots",
                  "cgs_update", "arnoldi_finish", "krylov_normalize")
+    t_bench = time.perf_counter()
     r = run_workload(ctx, B, c, B.C128, tol, args.steps, args.warmup, timed, breakdown)
     head = summarise(c, r, args.steps, B.C128, tol, name)
+    progress("headline " + name, t_bench)
     ktimes = r["ktimes"]
     # algorithmic work per launch
     # K in full and the upper triangles of V and D (T = K^T), complex128, both meshes
@@ -755,25 +762,34 @@ def main():
         c2 = synth.make_config("C2")
         line["c2"] = summarise(c2, run_workload(ctx, B, c2, B.C128, c2["tol"], args.steps, args.warmup), args.steps,
                                B.C128, c2["tol"], "C2")
+        progress("c2", t_bench)
     if not args.no_precision:
         line["precision"] = precision_compare(ctx, B, synth, np, {"x": r["x"], "solves_per_s": head["solves_per_s"]})
+        progress("precision", t_bench)
     ctx.trim()
     if not args.no_batching:
         line["batching"] = batching_compare(ctx, B, synth, np)
+        progress("batching", t_bench)
     if not args.no_field:
         line["field"] = field_run(ctx, B, synth, np)
+        progress("field", t_bench)
     if not args.no_pmchwt:
         line["pmchwt"] = pmchwt_run(ctx, B, synth, np)
+        progress("pmchwt", t_bench)
     if not args.no_mortar:
         line["mortar"] = mortar_run(ctx, B, synth, np)
+        progress("mortar", t_bench)
     if not args.no_incident:
         line["incident"] = incident_run(ctx, B, synth, np)
+        progress("incident", t_bench)
     if not args.no_serving:
         ctx.trim()   # the serving workers size their budget from free HBM: return this context's blocks first
         torch.cuda.empty_cache()
         line["serving"] = serving_run(B, synth)
+        progress("serving", t_bench)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_oracle_baseline(c)
+        progress("cpu_baseline", t_bench)
     print(json.dumps(line), flush=True)
 
 
