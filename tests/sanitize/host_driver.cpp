@@ -40,6 +40,32 @@ static bool read_mesh(const char *path, Mesh &m)
         }                                                          \
     } while (0)
 
+// The slot-major corner ranks of every block: the corners of a block's
+// triangles get the ranks 0 .. 3n - 1 once each; slot q holds the run
+// [off[q], off[q + 1]) of length cnt[q], its corners ranked in the order of
+// its list, and every corner of the run is at slot q's vertex.
+static int check_slot_ranks(const MeshData &m)
+{
+    for (int b = 0; b < m.nb; ++b) {
+        const int n = m.blk_start[b + 1] - m.blk_start[b], ns = m.blk_nslot[b];
+        const uint8_t *off = &m.slot_off[(size_t)b * SLOT_OFF_LD], *rank = &m.slot_rank[(size_t)b * 3 * BT];
+        CHECK(off[0] == 0 && off[ns] == 3 * n);
+        std::vector<int> seen(3 * n, 0);
+        for (int q = 0; q < ns; ++q) {
+            const int cnt = m.slot_cnt[(size_t)b * SMAX + q];
+            CHECK(cnt >= 1 && off[q + 1] - off[q] == cnt);
+            for (int v = 0; v < cnt; ++v) {
+                const int c = m.slot_ent[((size_t)b * SMAX + q) * LMAX + v];
+                CHECK(c < 3 * n && rank[c] == off[q] + v);
+                CHECK(m.tri[3 * (m.blk_start[b] + c / 3) + c % 3] == m.blk_slots[(size_t)b * SMAX + q]);
+                seen[rank[c]]++;
+            }
+        }
+        for (int r = 0; r < 3 * n; ++r) CHECK(seen[r] == 1);
+    }
+    return 0;
+}
+
 // The assembly strips of a prepared mesh: block ranges within the tile
 // budget, the row list of each strip (the vertices with a membership in its
 // blocks), its first reachable vertex, and the gather's coverage: over all
@@ -147,6 +173,7 @@ int main(int argc, char **argv)
         md[m].tri_user.assign(ms[m]->tri.begin(), ms[m]->tri.end());
         CHECK(mesh_prepare(md[m]) == BEM_OK);
         CHECK(check_strips(md[m], ASM_STRIP_TILES) == 0);
+        CHECK(check_slot_ranks(md[m]) == 0);
         for (int64_t cap : {1, 37, 400}) {   // small strips: many strips, entries fed by several
             MeshData t;
             t.nv = md[m].nv;
