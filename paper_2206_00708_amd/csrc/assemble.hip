@@ -17,8 +17,8 @@
 //                     regular rule is symmetric in (x, y), the tile of
 //                     (b1, b2) also provides (b2, b1): V, D transpose to
 //                     themselves and K, T into each other.
-//   gather_tiles      dense entry (i, j) = fixed-order sum of the tile
-//                     entries of the blocks containing i and j.
+//   gather_tiles      dense entries (i, j) and (j, i) = one fixed-order sum
+//                     of the tile entries of the blocks containing i and j.
 //   singular_pairs    ordered pairs sharing 3 / 2 / 1 vertices: Sauter-Schwab
 //                     regularising maps of [0,1]^4 with ng^4 Gauss points per
 //                     region (6 / 5 / 2 regions); 16 lanes per pair.
@@ -612,40 +612,30 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
 // The contributions to dense entry (i, j) of the tiles of one strip (tile
 // rows [b0, b1), tile t at (t - tile_base) in the scratch): every tile
 // (min(bi, bj), max(bi, bj)) of the blocks bi, bj containing i and j whose
-// first block lies in the strip, in membership order.  The strip of the
-// smallest membership of i and j is the first to reach (i, j) and writes
-// it; later strips add their share (strips run in order on one stream).
-// ROWS: i runs over the strip's row list, j over [lo, nv) (grid (ceil((nv -
-// lo) / 256), rows)); else j over the row list and i over [lo, nv) outside
-// the list (block (64, 4), grid (ceil(rows / 64), ceil((nv - lo) / 4))).
-// Every entry a strip reaches has i or j in its row list, and j >= lo or i >= lo.
-template <class C2, bool ROWS>
-__global__ __launch_bounds__(256) void gather_strip_kernel(int nv, int nb, int b0, int b1, int64_t tile_base, int lo,
-                                                           const int32_t *__restrict__ rows, int nrows,
-                                                           const int32_t *__restrict__ memb_ptr,
-                                                           const int32_t *__restrict__ memb,
-                                                           const C2 *__restrict__ scratch, C2 *__restrict__ V,
-                                                           C2 *__restrict__ K, C2 *__restrict__ T, C2 *__restrict__ D)
+// first block lies in the strip, in membership order (memberships of i,
+// then of j).  The same terms with the roles of i and j exchanged make up
+// entry (j, i): V and D are the same numbers, K and T exchange (the tile of
+// (bj, bi) read from the other side).  So one sum gives both entries, and a
+// strip reads each tile entry once.  The strip of the smallest membership
+// of i and j is the first to reach (i, j) and writes it; later strips add
+// their share (strips run in order on one stream).
+//
+// Entries a strip reaches have i or j in its row list R (the vertices with a
+// membership in its blocks) and both at or after lo (the first vertex with a
+// membership at or after b0).  Two launches cover them as unordered pairs:
+//   RR: i = R[a], j = R[b] for a <= b (16 x 16 chunks of R, chunk pairs
+//       above the diagonal exit at once);
+//   RO: i in R, j in [lo, nv) outside R (16 rows of R x 16 columns).
+// A workgroup of 256 threads holds a 16 x 16 block: it writes (i, j) along
+// rows (consecutive j), stages the sums in LDS and writes (j, i) along rows
+// j (consecutive i of R).
+template <class C2>
+__device__ inline bool strip_sum(int i, int j, int nb, int b0, int b1, int64_t tile_base, const int32_t *memb_ptr,
+                                 const int32_t *memb, const C2 *scratch, C2 (&acc)[4], bool &first)
 {
     using R = decltype(C2::x);
-    int i, j;
-    if (ROWS) {
-        i = rows[blockIdx.y];
-        j = lo + (int)blockIdx.x * 256 + (int)threadIdx.x;
-        if (j >= nv) return;
-    } else {
-        const int r = (int)blockIdx.x * 64 + (int)threadIdx.x;
-        i = lo + (int)blockIdx.y * 4 + (int)threadIdx.y;
-        if (r >= nrows || i >= nv) return;
-        j = rows[r];
-    }
     const int pi0 = memb_ptr[i], pi1 = memb_ptr[i + 1];
     const int pj0 = memb_ptr[j], pj1 = memb_ptr[j + 1];
-    if (!ROWS)   // rows of the list are the other pass's
-        for (int p = pi0; p < pi1; ++p) {
-            const int bi = memb[p] >> 8;
-            if (bi >= b0 && bi < b1) return;
-        }
     R vx = 0, vy = 0, kx = 0, ky = 0, tx = 0, ty = 0, dx = 0, dy = 0;
     bool any = false;
     for (int p = pi0; p < pi1; ++p) {
@@ -671,27 +661,91 @@ __global__ __launch_bounds__(256) void gather_strip_kernel(int nv, int nb, int b
             }
         }
     }
-    const int64_t o = (int64_t)i * op_ld(nv) + j;
-    const int first = min(memb[pi0] >> 8, memb[pj0] >> 8);   // smallest membership (lists ascend by block)
-    if (first >= b0) {   // this strip is the first to reach (i, j)
-        V[o] = C2{vx, vy};
-        K[o] = C2{kx, ky};
-        T[o] = C2{tx, ty};
-        D[o] = C2{dx, dy};
-    } else if (any) {
-        const C2 v = V[o], k = K[o], t = T[o], d = D[o];
-        V[o] = C2{v.x + vx, v.y + vy};
-        K[o] = C2{k.x + kx, k.y + ky};
-        T[o] = C2{t.x + tx, t.y + ty};
-        D[o] = C2{d.x + dx, d.y + dy};
-    }
-    if (ROWS && j == nv - 1 && (memb[pi0] >> 8) >= b0)   // padding columns of the row: zero, once
-        for (int64_t c = 1; c < op_ld(nv) - nv + 1; ++c) {
-            V[o + c] = C2{0, 0};
-            K[o + c] = C2{0, 0};
-            T[o + c] = C2{0, 0};
-            D[o + c] = C2{0, 0};
+    acc[0] = C2{vx, vy};
+    acc[1] = C2{kx, ky};
+    acc[2] = C2{tx, ty};
+    acc[3] = C2{dx, dy};
+    first = min(memb[pi0] >> 8, memb[pj0] >> 8) >= b0;   // lists ascend by block
+    return any;
+}
+
+// (i, j) of the four operators: written by the first strip to reach it, added to by later ones
+template <class C2>
+__device__ inline void strip_put(C2 *const (&op)[4], int64_t o, const C2 (&v)[4], bool first)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (first) {
+            op[k][o] = v[k];
+        } else {
+            const C2 x = op[k][o];
+            op[k][o] = C2{x.x + v[k].x, x.y + v[k].y};
         }
+    }
+}
+
+template <class C2, bool RR>
+__global__ __launch_bounds__(256) void gather_strip_kernel(int nv, int nb, int b0, int b1, int64_t tile_base, int lo,
+                                                           const int32_t *__restrict__ rows, int nrows,
+                                                           const int32_t *__restrict__ memb_ptr,
+                                                           const int32_t *__restrict__ memb,
+                                                           const C2 *__restrict__ scratch, C2 *__restrict__ V,
+                                                           C2 *__restrict__ K, C2 *__restrict__ T, C2 *__restrict__ D)
+{
+    __shared__ C2 sv[4][16][17];
+    __shared__ uint8_t sflag[16][17];   // bit 0: a contribution, bit 1: first strip to reach the entry
+    if (RR && blockIdx.x > blockIdx.y) return;
+    C2 *const op[4] = {V, K, T, D};
+    const int64_t ld = op_ld(nv);
+    const int tid = threadIdx.x, ra = tid >> 4, cb = tid & 15;
+    // (i, j): i = R[16 blockIdx.x + ra], j = R[16 blockIdx.y + cb] (RR) or lo + 16 blockIdx.y + cb (RO)
+    const int ai = 16 * (int)blockIdx.x + ra, aj = 16 * (int)blockIdx.y + cb;
+    bool ok = ai < nrows && (RR ? (aj < nrows && (blockIdx.x < blockIdx.y || ra <= cb)) : lo + aj < nv);
+    int i = 0, j = 0;
+    if (ok) {
+        i = rows[ai];
+        j = RR ? rows[aj] : lo + aj;
+        if (!RR)   // columns in R are the RR launch's
+            for (int p = memb_ptr[j]; p < memb_ptr[j + 1] && ok; ++p) {
+                const int bj = memb[p] >> 8;
+                ok = bj < b0 || bj >= b1;
+            }
+    }
+    C2 acc[4];
+    bool first = false, any = false;
+    if (ok) {
+        any = strip_sum(i, j, nb, b0, b1, tile_base, memb_ptr, memb, scratch, acc, first);
+        if (first || any) strip_put(op, (int64_t)i * ld + j, acc, first);
+    }
+    // (j, i) from the same sums, through LDS: V, D as they are, K and T exchanged
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sv[k][ra][cb] = acc[k];
+    sflag[ra][cb] = (uint8_t)((ok && any ? 1 : 0) | (ok && first && i != j ? 2 : 0) | (ok && i != j ? 4 : 0));
+    __syncthreads();
+    const int rb = tid >> 4, ca = tid & 15;   // row j of column block rb, column i of row block ca
+    const int f = sflag[ca][rb];
+    if (f & 4) {
+        const int aj2 = 16 * (int)blockIdx.y + rb, ai2 = 16 * (int)blockIdx.x + ca;
+        const int jj = RR ? rows[aj2] : lo + aj2, ii = rows[ai2];
+        if (f & 3) {
+            const C2 w[4] = {sv[0][ca][rb], sv[2][ca][rb], sv[1][ca][rb], sv[3][ca][rb]};
+            strip_put(op, (int64_t)jj * ld + ii, w, (f & 2) != 0);
+        }
+    }
+}
+
+// the padding columns [nv, op_ld(nv)) of every row of the four operators: zero
+template <class C2>
+__global__ void zero_padding_kernel(int nv, C2 *__restrict__ V, C2 *__restrict__ K, C2 *__restrict__ T, C2 *__restrict__ D)
+{
+    const int pad = (int)(op_ld(nv) - nv);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pad == 0 || t >= (int64_t)nv * pad) return;
+    const int64_t o = (t / pad) * op_ld(nv) + nv + t % pad;
+    V[o] = C2{0, 0};
+    K[o] = C2{0, 0};
+    T[o] = C2{0, 0};
+    D[o] = C2{0, 0};
 }
 
 // ----------------------------------------------------------- singular pairs
@@ -914,6 +968,17 @@ bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, vo
         if (!ev[q]) BEM_HIP(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
     BEM_HIP(hipEventRecord(ev[0], st));
     BEM_HIP(hipStreamWaitEvent(gs, ev[0], 0));   // the operator blocks may have served earlier main-stream work
+    if ((int64_t)op_ld(nv) > nv) {
+        const int64_t npad = (int64_t)nv * (op_ld(nv) - nv);
+        const dim3 gz((unsigned)((npad + 255) / 256));
+        if (!fp32)
+            hipLaunchKernelGGL(zero_padding_kernel<double2>, gz, dim3(256), 0, gs, nv, static_cast<double2 *>(ops[0]),
+                               static_cast<double2 *>(ops[1]), static_cast<double2 *>(ops[2]), static_cast<double2 *>(ops[3]));
+        else
+            hipLaunchKernelGGL(zero_padding_kernel<float2>, gz, dim3(256), 0, gs, nv, static_cast<float2 *>(ops[0]),
+                               static_cast<float2 *>(ops[1]), static_cast<float2 *>(ops[2]), static_cast<float2 *>(ops[3]));
+        BEM_HIP(hipGetLastError());
+    }
     for (int s = 0; s < ns; ++s) {
         const int b0 = h.strip_b[s], b1 = h.strip_b[s + 1], hb = s % 2;
         const int64_t t0 = b0 * nb - (int64_t)b0 * (b0 - 1) / 2, n = strip_tiles(h, s);
@@ -962,19 +1027,21 @@ bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, vo
         BEM_HIP(hipStreamWaitEvent(gs, ev[1 + hb], 0));
         const int r0 = h.strip_rptr[s], nr = h.strip_rptr[s + 1] - r0, lo = h.strip_lo[s];
         const int32_t *rows = m->d.strip_rows.as<int32_t>() + r0;
-        const dim3 ga((unsigned)((nv - lo + 255) / 256), (unsigned)nr), gb((unsigned)((nr + 63) / 64),
-                                                                          (unsigned)((nv - lo + 3) / 4));
-        KTimer kt(ctx, K_GATHER);
+        const unsigned cr = (unsigned)((nr + 15) / 16);
+        const dim3 ga(cr, cr), gb(cr, (unsigned)((nv - lo + 15) / 16));
 #define GATHER_ARGS(C2)                                                                                              \
     nv, (int)nb, b0, b1, t0, lo, rows, nr, m->d.memb_ptr.as<int32_t>(), m->d.memb.as<int32_t>(),                    \
         reinterpret_cast<const C2 *>(buf), static_cast<C2 *>(ops[0]), static_cast<C2 *>(ops[1]),                     \
         static_cast<C2 *>(ops[2]), static_cast<C2 *>(ops[3])
-        if (!fp32) {
-            launch_k(kt, gather_strip_kernel<double2, true>, ga, dim3(256), 0, gs, GATHER_ARGS(double2));
-            hipLaunchKernelGGL((gather_strip_kernel<double2, false>), gb, dim3(64, 4), 0, gs, GATHER_ARGS(double2));
-        } else {
-            launch_k(kt, gather_strip_kernel<float2, true>, ga, dim3(256), 0, gs, GATHER_ARGS(float2));
-            hipLaunchKernelGGL((gather_strip_kernel<float2, false>), gb, dim3(64, 4), 0, gs, GATHER_ARGS(float2));
+        if (nr > 0) {   // (every strip has rows: its blocks have vertices)
+            KTimer kt(ctx, K_GATHER);
+            if (!fp32) {
+                launch_k(kt, gather_strip_kernel<double2, true>, ga, dim3(256), 0, gs, GATHER_ARGS(double2));
+                hipLaunchKernelGGL((gather_strip_kernel<double2, false>), gb, dim3(256), 0, gs, GATHER_ARGS(double2));
+            } else {
+                launch_k(kt, gather_strip_kernel<float2, true>, ga, dim3(256), 0, gs, GATHER_ARGS(float2));
+                hipLaunchKernelGGL((gather_strip_kernel<float2, false>), gb, dim3(256), 0, gs, GATHER_ARGS(float2));
+            }
         }
 #undef GATHER_ARGS
         BEM_HIP(hipGetLastError());
