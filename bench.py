@@ -70,21 +70,23 @@ COUNTED_TRAFFIC = {
 
 # FP64 VALU counters of the regular-pair kernel per launch (rocprofv3 --pmc,
 # kernels serialised by the counter collection), per workload, with the sha1
-# of assemble.hip they were taken on: FP64 flops (SQ_INSTS_VALU_FLOPS_FP64 x
+# of the regular-pair region of assemble.hip they were taken on (from the
+# section's opening marker to the gather's): FP64 flops (SQ_INSTS_VALU_FLOPS_FP64 x
 # 64 lanes), VALU instructions (SQ_INSTS_VALU), the VALU issue fraction
 # (SQ_INSTS_VALU x 4 cycles over the SIMD cycles of the launch, from
 # GRBM_GUI_ACTIVE per XCD x 1024 SIMDs) and the share of the FP64 flops in
 # the software sin/cos (the small-angle polynomials and the rotation by the
 # pair's base phase: 46 of the per-point-pair flops).
+REG_REGIONS = {"source": "paper_2206_00708_amd/csrc/assemble.hip",
+               "regions": [("// ------------------------------------------------------------ regular pairs",
+                            "// The contributions to dense entry (i, j) of the tiles of one strip")]}
 COUNTED_VALU = {
     ("regular_tiles", "C3"): {"flops_fp64": 1310718788.0 * 64, "valu_insts": 1067106586, "valu_busy": 0.701,
                               "sincos_flop_share": 0.32, "isolated_launch_us": 2715.7,
-                              "source": "paper_2206_00708_amd/csrc/assemble.hip",
-                              "sha1": "91e322714d2e8c260d968b9c3593aa8005443459"},
+                              "sha1": "25fb264f3ef5797c79b384c65d0d644e4e7ed33b", **REG_REGIONS},
     ("regular_tiles", "C2"): {"flops_fp64": 864256332.0 * 64, "valu_insts": 702649931, "valu_busy": 0.704,
                               "sincos_flop_share": 0.32, "isolated_launch_us": 1912.8,
-                              "source": "paper_2206_00708_amd/csrc/assemble.hip",
-                              "sha1": "91e322714d2e8c260d968b9c3593aa8005443459"},
+                              "sha1": "25fb264f3ef5797c79b384c65d0d644e4e7ed33b", **REG_REGIONS},
 }
 
 

@@ -1037,10 +1037,12 @@ bem_status launch_regular(const bem_mesh *m, double k, double kim, bool fp32, vo
             KTimer kt(ctx, K_GATHER);
             if (!fp32) {
                 launch_k(kt, gather_strip_kernel<double2, true>, ga, dim3(256), 0, gs, GATHER_ARGS(double2));
-                hipLaunchKernelGGL((gather_strip_kernel<double2, false>), gb, dim3(256), 0, gs, GATHER_ARGS(double2));
+                KTimer kt2(ctx, K_GATHER);
+                launch_k(kt2, gather_strip_kernel<double2, false>, gb, dim3(256), 0, gs, GATHER_ARGS(double2));
             } else {
                 launch_k(kt, gather_strip_kernel<float2, true>, ga, dim3(256), 0, gs, GATHER_ARGS(float2));
-                hipLaunchKernelGGL((gather_strip_kernel<float2, false>), gb, dim3(256), 0, gs, GATHER_ARGS(float2));
+                KTimer kt2(ctx, K_GATHER);
+                launch_k(kt2, gather_strip_kernel<float2, false>, gb, dim3(256), 0, gs, GATHER_ARGS(float2));
             }
         }
 #undef GATHER_ARGS
