@@ -1769,7 +1769,18 @@ size_t split_part_bytes(int ne, int ni)
     return std::max((size_t)nchunk * (ne + ni) * sizeof(double4), (size_t)6 * (2 * ne + 2 * ni) * sizeof(double2));
 }
 
+// Chebyshev steps of the sparse inverse-mass apply: M^-1 to FP64 rounding
+// (36 steps, error 4 3^-36) in the FP64 form and to 1.4e-11 (24 steps) in the
+// mixed form, for the operator products of the C ABI and wherever M^-1 is
+// part of an operator (the exterior formulations).
 int cheb_steps(const bem_problem *p) { return p->prec == BEM_C128 ? 36 : 24; }
+// Inside GMRES on the multiple-traces system, M^-1 only preconditions: a
+// fixed number k of Chebyshev steps from zero is a fixed polynomial p(M)
+// with error 4 3^-k against M^-1 (7.5e-6 for k = 12, one launch), so
+// GMRES on p(M) A x = p(M) b converges to the solution of A x = b, with the
+// residual norms of p(M) within 1.5e-5 of those of M^-1.
+constexpr int CHEB_PRECOND_STEPS = 12;
+int cheb_precond_steps(const bem_problem *p) { return std::min(CHEB_PRECOND_STEPS, cheb_steps(p)); }
 
 template <int RPT, int W>
 void launch_cheb(const bem_problem *p, dim3 grid, hipStream_t st, const ChebArgs &A, int part0, int first, int last,
@@ -1781,13 +1792,13 @@ void launch_cheb(const bem_problem *p, dim3 grid, hipStream_t st, const ChebArgs
              zstride, win, wout, wstride, kst);
 }
 
-// z = M^-1 y by the sparse Chebyshev apply on the patches [part0, part0 + np)
-// for R runs.  Mesh m's two vectors start at base[m] in y, z and the work
+// z = M^-1 y by K steps of the sparse Chebyshev apply on the patches
+// [part0, part0 + np) for R runs.  Mesh m's two vectors start at base[m] in y, z and the work
 // vectors (length wn); work holds two sets of (x, r, d), 6 wn complex per
 // run, wstride apart.
 bem_status cheb_apply(const bem_problem *p, int part0, int np, int64_t base0, int64_t base1, int64_t wn,
                       const double2 *y, int64_t ystride, double2 *z, int64_t zstride, double2 *work, int64_t wstride,
-                      int R, const KrylovState *kst)
+                      int R, const KrylovState *kst, int K)
 {
     const ChebTables &T = p->cheb;
     ChebArgs A;
@@ -1805,7 +1816,7 @@ bem_status cheb_apply(const bem_problem *p, int part0, int np, int64_t base0, in
     A.base[0] = base0;
     A.base[1] = base1;
     A.wn = wn;
-    const int K = cheb_steps(p), nl = (K + T.s - 1) / T.s;
+    const int nl = (K + T.s - 1) / T.s;
     const double sigma1 = CHEB_THETA / CHEB_DELTA;
     double rho = 1.0 / sigma1;
     const int rpt = (T.lmax + 1023) / 1024;
@@ -1833,15 +1844,17 @@ bem_status cheb_apply(const bem_problem *p, int part0, int np, int64_t base0, in
     return BEM_OK;
 }
 
-// z = blockdiag(M_e, M_e, M_i, M_i)^-1 y
-bem_status apply_Minv(const bem_problem *p, const double2 *y, double2 *z, double4 *part, const KrylovState *kst)
+// z = blockdiag(M_e, M_e, M_i, M_i)^-1 y; K: Chebyshev steps of the sparse
+// form (0: cheb_steps)
+bem_status apply_Minv(const bem_problem *p, const double2 *y, double2 *z, double4 *part, const KrylovState *kst,
+                      int K = 0)
 {
     hipStream_t st = p->ctx->stream;
     const int ne = (int)p->ext->h.nv, ni = (int)p->inte->h.nv;
     if (p->mass_sparse) {
         const int64_t n = 2 * ne + 2 * ni;
         return cheb_apply(p, 0, p->cheb.nparts[0] + p->cheb.nparts[1], 0, 2 * ne, n, y, 0, z, 0,
-                          reinterpret_cast<double2 *>(part), 6 * n, 1, kst);
+                          reinterpret_cast<double2 *>(part), 6 * n, 1, kst, K > 0 ? K : cheb_steps(p));
     }
     {
         KTimer kt(p->ctx, K_MASS_APPLY);
@@ -1860,7 +1873,7 @@ bem_status apply_Minv(const bem_problem *p, const double2 *y, double2 *z, double
 // y = A x (weak form); z = M^-1 y when `strong`.  Complex64 operators are
 // applied with FP32 accumulation, or FP64 when `acc64` (refinement residual).
 bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, double2 *y, double2 *z, bool strong,
-                   const KrylovState *kst, double4 *part, bool acc64 = false)
+                   const KrylovState *kst, double4 *part, bool acc64 = false, int K = 0)
 {
     hipStream_t st = p->ctx->stream;
     const int rows = A.ne + A.ni;
@@ -1886,7 +1899,7 @@ bem_status apply_A(const bem_problem *p, const MtfArgs &A, const double2 *x, dou
     }
     hipLaunchKernelGGL(mtf_sym_combine_kernel, dim3((rows + 15) / 16), dim3(256), 0, st, A, x, part, y, kst);
     BEM_HIP(hipGetLastError());
-    if (strong) return apply_Minv(p, y, z, part, kst);
+    if (strong) return apply_Minv(p, y, z, part, kst, K);
     return BEM_OK;
 }
 
@@ -1996,7 +2009,7 @@ bem_status apply_Minv_mesh(const bem_problem *p, int mesh, const double2 *y, dou
     if (p->mass_sparse) {   // y, z: this mesh's two vectors
         const int64_t wn = 2 * (int64_t)(ne + ni);
         return cheb_apply(p, mesh == 0 ? 0 : p->cheb.nparts[0], p->cheb.nparts[mesh], 0, 0, wn, y, 0, z, 0,
-                          reinterpret_cast<double2 *>(part), 6 * wn, 1, kst);
+                          reinterpret_cast<double2 *>(part), 6 * wn, 1, kst, cheb_steps(p));
     }
     {
         KTimer kt(p->ctx, K_MASS_APPLY);
@@ -2471,7 +2484,7 @@ bem_status block_apply(bem_problem *p, const MtfArgs &A, BlockBufs &bb, int R, c
     if (!p->mass_dense) {
         const int64_t n = 2 * A.ne + 2 * A.ni;
         return cheb_apply(p, 0, p->cheb.nparts[0] + p->cheb.nparts[1], 0, 2 * A.ne, n, Y, ystride, Z, zstride,
-                          bb.chw.as<double2>(), 6 * n, R, kst);
+                          bb.chw.as<double2>(), 6 * n, R, kst, cheb_precond_steps(p));
     }
     for (int m = 0; m < 2; ++m) {
         const int km = minv_ld(nv[m], true);
@@ -2540,7 +2553,8 @@ struct Gmres {
         else if (bb)
             s = block_apply(p, A, *bb, R, vj, vstride, W.y.as<double2>(), B.vec, W.z.as<double2>(), B.vec, true, dst);
         else
-            s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>(), acc64);
+            s = apply_A(p, A, vj, W.y.as<double2>(), W.z.as<double2>(), true, dst, W.part.as<double4>(), acc64,
+                        cheb_precond_steps(p));
         if (s) return s;
         {
             KTimer kt(ctx, K_CGS_DOTS);
@@ -3002,6 +3016,10 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
         s = block_alloc(p, bb);
         if (s) return s;
     }
+    // M^-1 of the right-hand sides and residuals: the same operator as in the GMRES steps (the block
+    // product applies the dense inverses when they are present, else both take the preconditioner's
+    // Chebyshev steps)
+    const int kpre = R > 1 && p->mass_dense ? cheb_steps(p) : cheb_precond_steps(p);
     KrylovState *hstate = nullptr;   // two pinned snapshots of the R states
     BEM_HIP(hipHostMalloc(reinterpret_cast<void **>(&hstate), 2 * R * sizeof(KrylovState), hipHostMallocDefault));
     struct PinGuard { KrylovState *p; ~PinGuard() { if (p) (void)hipHostFree(p); } } guard{hstate};
@@ -3041,7 +3059,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
                                true);
         if (q) return q;
         hipLaunchKernelGGL(axpy_sub_kernel, gv, dim3(256), 0, st, n, W.b.as<double2>() + (size_t)r * n, yr, rr);
-        q = apply_Minv(p, rr, zr, W.part.as<double4>(), nullptr);
+        q = apply_Minv(p, rr, zr, W.part.as<double4>(), nullptr, kpre);
         if (q) return q;
         return norm_to(p, n, zr, W.npart.as<double>(), yr, beta + R);
     };
@@ -3054,7 +3072,7 @@ bem_status solve_impl(bem_problem *p, const double *dirs, int nrhs, const bem_so
             double2 *br = W.b.as<double2>() + (size_t)r * n, *rr = W.r.as<double2>() + (size_t)r * n;
             if (r < Rg) {
                 s = rhs_internal(p, dirs + 3 * (g0 + r), br);
-                if (!s) s = apply_Minv(p, br, rr, W.part.as<double4>(), nullptr);
+                if (!s) s = apply_Minv(p, br, rr, W.part.as<double4>(), nullptr, kpre);
                 if (s) return s;
             } else {
                 hipLaunchKernelGGL(zero_kernel, gv, dim3(256), 0, st, (int64_t)n, br);
