@@ -812,7 +812,7 @@ __global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__
     const double nx[3] = {X.n[0], X.n[1], X.n[2]}, ny[3] = {Y.n[0], Y.n[1], Y.n[2]};
     const int kind = sp.kind;
     const int nreg = kind == 3 ? 6 : (kind == 2 ? 5 : 2);
-    double vr[9], vi[9], kr[9], ki[9], tr[9], ti[9], sr = 0.0, si = 0.0;
+    double vr[9], vi[9], kr[9], ki[9], tr[9], ti[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) { vr[e] = vi[e] = kr[e] = ki[e] = tr[e] = ti[e] = 0.0; }
     const int ng2 = ng * ng;
@@ -848,6 +848,7 @@ __global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__
                     }
                     const double dk = -(d[0] * ny[0] + d[1] * ny[1] + d[2] * ny[2]);
                     const double dt = d[0] * nx[0] + d[1] * nx[1] + d[2] * nx[2];
+                    const double gkr = fr * dk, gki = fi * dk, gtr = fr * dt, gti = fi * dt;
                     const double phx[3] = {1.0 - xs0, xs0 - xs1, xs1}, phy[3] = {1.0 - ys0, ys0 - ys1, ys1};
 #pragma unroll
                     for (int a = 0; a < 3; ++a)
@@ -855,13 +856,16 @@ __global__ __launch_bounds__(256, 2) void singular_pairs_kernel(const TriGeo *__
                         for (int b = 0; b < 3; ++b) {
                             const double ph = phx[a] * phy[b];
                             vr[3 * a + b] += ph * gr; vi[3 * a + b] += ph * gi;
-                            kr[3 * a + b] += ph * fr * dk; ki[3 * a + b] += ph * fi * dk;
-                            tr[3 * a + b] += ph * fr * dt; ti[3 * a + b] += ph * fi * dt;
+                            kr[3 * a + b] += ph * gkr; ki[3 * a + b] += ph * gki;
+                            tr[3 * a + b] += ph * gtr; ti[3 * a + b] += ph * gti;
                         }
-                    sr += gr;
-                    si += gi;
                 }
     }
+    // the sum of G over the points: the P1 functions of each side sum to one
+    // at every point, so it is the sum of the nine V entries
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) { sr += vr[e]; si += vi[e]; }
     // reduce over the 16 lanes of the group
 #pragma unroll
     for (int off = 8; off >= 1; off >>= 1) {
