@@ -623,8 +623,8 @@ __global__ __launch_bounds__(256, 3) void regular_tiles_f32_kernel(TileArgsF A, 
 // Entries a strip reaches have i or j in its row list R (the vertices with a
 // membership in its blocks) and both at or after lo (the first vertex with a
 // membership at or after b0).  Two launches cover them as unordered pairs:
-//   RR: i = R[a], j = R[b] for a <= b (16 x 16 chunks of R, chunk pairs
-//       above the diagonal exit at once);
+//   RR: i = R[a], j = R[b] for a <= b (16 x 16 chunks of R; workgroups whose
+//       row chunk comes after their column chunk return at once);
 //   RO: i in R, j in [lo, nv) outside R (16 rows of R x 16 columns).
 // A workgroup of 256 threads holds a 16 x 16 block: it writes (i, j) along
 // rows (consecutive j), stages the sums in LDS and writes (j, i) along rows
