@@ -253,3 +253,28 @@ def test_operators_strips(orc, strip_tiles, prec):
             assert e < bound and em < bound, (strip_tiles, mesh, op, e, em)
     del p, me, mi
     ctx.close()
+
+
+@pytest.mark.parametrize("strip_tiles", [0, 37])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_regular_part_exactly_symmetric(strip_tiles, prec):
+    """The regular-pair part alone (no vertex-sharing pairs) on the small
+    ellipsoid pair, in one strip per mesh and in strips of 37 tiles: every
+    unordered vertex pair is summed once and written in both orientations,
+    so V and D equal their transposes and K equals T transposed, bitwise
+    (Sec. 2.1: V and D are symmetric and K' is the adjoint of K under the
+    Galerkin pairing)."""
+    ctx = B.Context(0)
+    ctx.set_strip_tiles(strip_tiles)
+    (xe, te), (xi, ti), _ = synth.make_pair(3, 3, "fib", 0.01, (1.0, 0.8, 0.6), int_n=700)
+    me, mi = B.Mesh(ctx, xe, te), B.Mesh(ctx, xi, ti)
+    p = B.Problem(ctx, me, mi, 6.0, 12.0, 1.0, 2.0, precision=B.C128 if prec == "fp64" else B.C64_MIXED)
+    p.assemble_operators(parts=1)
+    for mesh in (0, 1):
+        V, K, T, D = (p.operator(mesh, op).cpu().numpy() for op in "VKTD")
+        assert np.abs(V).max() > 0 and np.abs(K).max() > 0
+        assert np.array_equal(V, V.T), mesh
+        assert np.array_equal(D, D.T), mesh
+        assert np.array_equal(K, T.T), mesh
+    del p, me, mi
+    ctx.close()
