@@ -81,6 +81,26 @@ def test_sparse_solve_vs_lu(ctx, orc):
     assert max(errs) < 1e-5
 
 
+def test_preconditioner_steps_same_solution(ctx):
+    """Inside GMRES the sparse form preconditions with 12 Chebyshev steps (a
+    fixed polynomial p(M) within 7.5e-6 of M^-1, Sec. 3.3 only needs M^-1 as
+    the preconditioner of the weak-form system), while the dense form applies
+    M^-1 to FP64 rounding.  Both solve A x = b: at a tight tolerance the
+    traces of the two agree far below the preconditioner's own error, and
+    the step counts match within 2."""
+    c = _small_ellipsoid()
+    args = (c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
+    pd, a, b = _problem(ctx, *args, mode=1)
+    ps, d, e = _problem(ctx, *args, mode=2)
+    od, sd, cd = pd.solve(c["dirs"], tol=1e-11, maxit=2000)
+    os_, ss, cs = ps.solve(c["dirs"], tol=1e-11, maxit=2000)
+    assert cd == B.OK and cs == B.OK
+    err = max(_rel(os_.cpu().numpy()[r], od.cpu().numpy()[r]) for r in range(len(c["dirs"])))
+    print(f"12-step vs exact M^-1: steps {ss['iterations']} / {sd['iterations']}, trace difference {err:.2e}")
+    assert abs(sd["iterations"] - ss["iterations"]) <= 2
+    assert err < 1e-9
+
+
 @pytest.mark.parametrize("prec", [B.C128, B.C64_MIXED], ids=["fp64", "mixed"])
 def test_sparse_matches_dense_c2(ctx, prec):
     """Both forms of the apply on the C2 workload: the strong products agree
