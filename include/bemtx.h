@@ -339,7 +339,13 @@ bem_status bem_mtf_rhs(bem_problem *p, const double *dirs, int32_t nrhs, void *b
  * total field satisfies p = -v_ext, dp/dn+ = -w_ext on Gamma_ext and
  * p = -v_int, dp/dn- = -w_int on Gamma_int.  Returns BEM_W_NOCONV if a
  * right-hand side did not reach opts->tol within opts->maxit (its best
- * iterate is written).  stats may be NULL.
+ * iterate is written).  Success is decided on the true residual
+ * |M^-1 (b - A x)| / |M^-1 b|, recomputed in FP64 after the GMRES run
+ * (stats->rel_residual, the largest over the right-hand sides): when the
+ * Arnoldi estimate met the tolerance and the true residual did not, an
+ * FP64 run of one right-hand side first restarts once from the true
+ * residual with the remaining steps (the mixed form refines instead).
+ * stats may be NULL.
  * BEM_C64_MIXED: iterative refinement; each step solves the correction
  * system with GMRES (FP64 Krylov basis) to opts->ir_inner_tol (0: half the
  * remaining reduction, at least 1e-7), its products of the complex64

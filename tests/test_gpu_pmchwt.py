@@ -69,7 +69,7 @@ def test_pmchwt_solve_matches_oracle_lu(ctx, orc):
     ne = len(ext[0])
     for r in range(2):
         assert _rel(got[r][:ne], X[r][:ne]) < 1e-5 and _rel(got[r][ne:], X[r][ne:]) < 1e-5
-    assert st["rel_residual"] < 2e-9
+    assert st["rel_residual"] <= 1e-9   # success is decided on the true residual
 
 
 def test_pmchwt_c2_residual_and_mtf_agreement(ctx):
@@ -80,7 +80,7 @@ def test_pmchwt_c2_residual_and_mtf_agreement(ctx):
     p, me, mi = _problem(ctx, c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
     xp, sp, code = p.solve_pmchwt(c["dirs"], tol=1e-6, maxit=2000)
     assert code == B.OK, sp
-    assert sp["rel_residual"] < 2e-6
+    assert sp["rel_residual"] <= 1e-6
     xm, sm, code = p.solve(c["dirs"], tol=1e-6, maxit=2000)
     assert code == B.OK, sm
     ne = len(c["ext"][0])
@@ -138,7 +138,7 @@ def test_hc_neumann_solve_matches_oracle_lu(ctx, orc):
     ne = len(ext[0])
     for r in range(2):
         assert _rel(got[r][:ne], X[r][:ne]) < 1e-5 and _rel(got[r][ne:], X[r][ne:]) < 1e-5
-    assert st["rel_residual"] < 2e-9
+    assert st["rel_residual"] <= 1e-9   # success is decided on the true residual
 
 
 def test_hc_neumann_c2_agrees_with_mtf(ctx):
@@ -148,7 +148,7 @@ def test_hc_neumann_c2_agrees_with_mtf(ctx):
     p, me, mi = _problem(ctx, c["ext"], c["int"], c["k_ext"], c["k_int"], c["rho_ext"], c["rho_int"])
     xh, sh, code = p.solve_hc_neumann(c["dirs"], tol=1e-6, maxit=2000)
     assert code == B.OK, sh
-    assert sh["rel_residual"] < 2e-6
+    assert sh["rel_residual"] <= 1e-6
     xm, sm, code = p.solve(c["dirs"], tol=1e-6, maxit=2000)
     ne = len(c["ext"][0])
     assert _rel(xh.cpu().numpy()[0][:ne], -xm.cpu().numpy()[0][ne:2 * ne]) < 0.1
